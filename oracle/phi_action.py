@@ -1,0 +1,166 @@
+"""Power iteration, the Newton-Leja phi-action loop and EXPRB42 (oracle).
+
+TEST INFRASTRUCTURE ONLY (see the package header).
+
+Paper passages followed
+  * Spectral bound: Sec. 2 names power iteration for the most dominant
+    eigenvalue; Sec. 2.2 (Listing 7) then takes lambda = -1.05 * rho_hat,
+    c = lambda/2, gamma = -lambda/4.
+  * Leja loop: Sec. 2.1, Eq. (2): p_0 = d_0 y_0 with y_0 = v, then
+    y_{m+1} = ((A - c)/gamma - xi_m) y_m and p_{m+1} = p_m + d_{m+1} y_{m+1}.
+  * Stop rule: Sec. 2.2 (text with Listing 2): converged when the error
+    estimate is at most rtol * ||p|| + atol, with l2 norms divided by sqrt(N).
+  * Several outputs from one basis ("vertical" interpolation): Sec. 2.3 and
+    Listing 11 (integrator coefficients), Sec. 3 (Problem III).
+  * Nonlinear remainder N(w) = f(w) - J(u_n) w: Sec. 2.3 (EXPRB32 text).
+
+Readings (paper silent or ambiguous)
+  * Power iteration: x_{k+1} = A x_k / ||A x_k||, rho_hat = ||A x_k|| / ||x_k||,
+    a fixed number of iterations from a caller-supplied start vector.
+  * Error estimate of step m+1: |d_{m+1}| * ||y_{m+1}|| / sqrt(N), tested
+    after every iteration; iters counts operator applications.  Each output
+    freezes once it passes; the loop ends when all outputs have passed or
+    after max_iters applications (status "notconv").  A non-finite norm ends
+    the loop with status "nonfinite".
+  * EXPRB42 (named in Sec. 1, formula not printed; the published two-stage
+    fourth-order exponential Rosenbrock method with c_2 = 3/4):
+        U_2     = u + (3/4) h phi_1((3/4) h J) F(u)
+        u_{n+1} = u + h phi_1(h J) F(u) + (32/9) h phi_3(h J) [N(U_2) - N(u)]
+    with J = J(u) and N(w) = F(w) - J w.  The two phi_1 actions share one
+    Newton basis (alpha = 3/4 and 1).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+from .leja import leja_points, newton_coeffs
+from .operators import burgers_F, burgers_J
+
+
+def _rms(x) -> float:
+    """l2 norm divided by sqrt(N) (Sec. 2.2)."""
+    return float(np.linalg.norm(x.ravel()) / math.sqrt(x.size))
+
+
+# --------------------------------------------------------------------------
+# spectral bound
+# --------------------------------------------------------------------------
+
+def power_iteration(apply_A, x0, iters: int = 20):
+    """Returns (rho_hat, history) after ``iters`` applications of A."""
+    x = np.array(x0, dtype=np.float64, copy=True)
+    hist = []
+    for _ in range(iters):
+        y = apply_A(x)
+        ny = float(np.linalg.norm(y.ravel()))
+        hist.append(ny / float(np.linalg.norm(x.ravel())))
+        x = y / ny
+    return hist[-1], hist
+
+
+def shift_scale(rho_hat: float, safety: float = 1.05):
+    """lambda = -safety * rho_hat, c = lambda/2, gamma = -lambda/4
+    (Listing 7): the Leja interval [-2, 2] maps onto [lambda, 0]."""
+    lam = -safety * rho_hat
+    return lam / 2.0, -lam / 4.0
+
+
+# --------------------------------------------------------------------------
+# Newton-Leja phi actions
+# --------------------------------------------------------------------------
+
+@dataclass
+class LejaResult:
+    p: list            # one output array per requested (l, alpha, sigma)
+    iters: list        # operator applications until each output passed
+    errs: list         # error estimate of each output at its last step
+    status: str        # "ok", "notconv" or "nonfinite"
+    n_apply: int       # operator applications made in total
+
+
+def leja_phi(apply_A, v, outputs, h, c, gamma, rtol, atol, max_iters=500,
+             force_iters=None) -> LejaResult:
+    """sigma_k * phi_{l_k}(alpha_k h A) v for every (l_k, alpha_k, sigma_k) in
+    ``outputs``, by Newton interpolation at the Leja points of [-2, 2].
+
+    ``force_iters`` (int or list) replaces the stop test of an output by a
+    fixed iteration count; it exists so that a run can be compared with
+    another whose borderline stop decision went the other way.
+    """
+    v = np.asarray(v, dtype=np.float64)
+    K = len(outputs)
+    if force_iters is not None and not isinstance(force_iters, (list, tuple)):
+        force_iters = [int(force_iters)] * K
+    M = max_iters + 1
+    xi = leja_points(M)
+    d = [newton_coeffs(l, h, c, gamma, M, alpha=a, sigma=s) for (l, a, s) in outputs]
+
+    y = v.copy()
+    p = [d[k][0] * v for k in range(K)]
+    active = [True] * K
+    iters = [max_iters] * K
+    errs = [float("nan")] * K
+    status = "ok"
+    n_apply = 0
+    for m in range(max_iters):
+        y = (apply_A(y) - c * y) / gamma - xi[m] * y
+        n_apply += 1
+        ynorm = _rms(y)
+        for k in range(K):
+            if not active[k]:
+                continue
+            p[k] = p[k] + d[k][m + 1] * y
+            err = abs(d[k][m + 1]) * ynorm
+            pnorm = _rms(p[k])
+            errs[k] = err
+            if not (math.isfinite(err) and math.isfinite(pnorm)):
+                status = "nonfinite"
+                active[k] = False
+                iters[k] = m + 1
+                continue
+            if force_iters is not None:
+                done = (m + 1) >= force_iters[k]
+            else:
+                done = err <= rtol * pnorm + atol
+            if done:
+                active[k] = False
+                iters[k] = m + 1
+        if status == "nonfinite" or not any(active):
+            break
+    if status == "ok" and any(active):
+        status = "notconv"
+    return LejaResult(p=p, iters=iters, errs=errs, status=status, n_apply=n_apply)
+
+
+# --------------------------------------------------------------------------
+# EXPRB42 for Burgers
+# --------------------------------------------------------------------------
+
+@dataclass
+class StepResult:
+    u_next: np.ndarray
+    iters: list        # [pass 1 (both phi_1 outputs), pass 2 (phi_3)]
+    status: str
+    stages: dict
+
+
+def exprb42_step(u, nu, dx, dy, h, c, gamma, rtol, atol, max_iters=500) -> StepResult:
+    """One EXPRB42 step of u_t = F(u) (Burgers), Jacobian and remainder as in
+    Sec. 2.3; the phi actions use Newton-Leja interpolation."""
+    u = np.asarray(u, dtype=np.float64)
+    J = lambda w: burgers_J(u, w, nu, dx, dy)
+    F = lambda w: burgers_F(w, nu, dx, dy)
+    hF = h * F(u)
+    r1 = leja_phi(J, hF, [(1, 0.75, 0.75), (1, 1.0, 1.0)], h, c, gamma, rtol, atol, max_iters)
+    a = r1.p[0]                       # (3/4) h phi_1((3/4) h J) F(u)
+    U2 = u + a
+    Nl = lambda w: F(w) - J(w)
+    R = h * (Nl(U2) - Nl(u))
+    r2 = leja_phi(J, R, [(3, 1.0, 32.0 / 9.0)], h, c, gamma, rtol, atol, max_iters)
+    u_next = u + r1.p[1] + r2.p[0]
+    status = r1.status if r1.status != "ok" else r2.status
+    return StepResult(u_next=u_next, iters=[max(r1.iters), r2.iters[0]], status=status,
+                      stages={"a": a, "phi1": r1.p[1], "R": R, "phi3": r2.p[0]})
