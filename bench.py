@@ -1,0 +1,173 @@
+#!/usr/bin/env python
+"""Benchmark of the Leja phi-action hot path on one MI355X.
+
+One step = power iteration (20 sweeps) for the spectral bound, then the
+phi_1, phi_2, phi_3 actions of a seeded N(0,1) vector from one Newton basis
+on the periodic 4096^2 diffusion-advection grid (D = 1, cell Peclet 1,
+h = 50 x CFL, rtol 1e-8), all through the C ABI.  Inputs are resident in
+HBM before the timed region.  Prints one JSON line on stdout:
+
+  value     phi-action solves/s (3 solves per step)
+  roofline  HBM roofline of the dominant kernel (the fused Leja sweep):
+            algorithmic bytes per launch / average launch duration, both
+            from HIP events recorded on the library's stream around every
+            sweep of the timed steps
+  cpu_baseline  the CPU oracle on a bounded sample (the same solve on a
+            1024^2 grid of the same family, scaled by the point ratio 16)
+
+Usage: python bench.py [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def make_workload(name: str):
+    from paper_2310_08344_amd import workloads as W
+    if name == "phi123-4096":
+        p, v = W.config2(n=4096)
+    elif name == "phi123-1024":
+        p, v = W.config2(n=1024)
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return p, v
+
+
+def cpu_baseline(sample_n: int = 1024) -> dict:
+    """The oracle as it stands, on one thread, on the sample workload."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.operators import make_apply
+    from oracle.phi_action import leja_phi, power_iteration, shift_scale
+    from paper_2310_08344_amd import workloads as W
+
+    p, v = W.config2(n=sample_n)
+    x0 = W.start_vector(p.n)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        A = make_apply(p)
+        rho, _ = power_iteration(A, x0, 20)
+        c, g = shift_scale(rho)
+        r = leja_phi(A, v, [(1, 1.0, 1.0), (2, 1.0, 1.0), (3, 1.0, 1.0)], p.h, c, g, 1e-8, 0.0, 300)
+        t = time.perf_counter() - t0
+    scale = (4096 * 4096) / float(p.N)
+    return {"value": 3.0 / (t * scale), "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"phi_1..phi_3 solve incl. power iteration at {sample_n}^2 "
+                      f"({t:.1f} s, sweeps {r.iters}), time scaled by the point ratio {scale:.0f} to 4096^2"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="phi123-4096")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: the phi-action path is single-GPU (--gpus {args.gpus} "
+              "is not supported; see the sharding notes in the design document)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_2310_08344_amd import binding as B
+    from paper_2310_08344_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    lib = B.Library.load()
+    p, v_h = make_workload(args.workload)
+    log("workload", args.workload, "n", p.n, "h", p.h)
+    dev = torch.device("cuda:0")
+    v = torch.as_tensor(v_h).to(dev)
+    x0 = torch.as_tensor(W.start_vector(p.n)).to(dev)
+    outs = [torch.empty_like(v) for _ in range(3)]
+    ctx = lib.context(n_max=p.N, k_max=4)
+    op = B.make_operator(p)
+    ls = [1, 2, 3]
+    torch.cuda.synchronize()
+
+    def step():
+        rho, c, g = ctx.spectrum(op, x0=x0, iters=20)
+        sp = ctx.stats()
+        r = ctx.phi_leja(op, v, outs, ls, p.h, c, g, rtol=1e-8, max_iters=300)
+        if r.status != B.LX_OK:
+            raise RuntimeError(f"phi_leja status {r.status}: {ctx.last_error()}")
+        return sp, r.stats
+
+    for i in range(args.warmup):
+        step()
+        log("warmup step", i + 1, "done")
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs = []
+    for i in range(args.steps):
+        recs.append(step())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.set_timing(False)
+    log("timed steps done")
+    dt = (t1 - t0) / args.steps
+    value = 3.0 / dt
+
+    sweeps = sum(r["n_apply"] for _, r in recs)
+    sweep_ms = sum(r["sweep_ms"] for _, r in recs)
+    leja_bytes = sum(r["bytes"] for _, r in recs)
+    achieved = leja_bytes / (sweep_ms * 1e-3) / 1e9
+    pw_ms = sum(s["sweep_ms"] for s, _ in recs)
+    pw_bytes = sum(s["bytes"] for s, _ in recs)
+    last = recs[-1][1]
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "leja_sweep (diffusion-advection, K=3, FP64)",
+            "launches": sweeps, "avg_launch_us": round(sweep_ms * 1e3 / sweeps, 2),
+            "bytes_per_launch": leja_bytes / sweeps}
+    out = {
+        "metric": "phi-action solves/s at tol 1e-8",
+        "value": round(value, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"periodic diffusion-advection {p.n}^2, phi_1..phi_3 of seeded N(0,1) v from one "
+                               f"Newton basis, h = 50 x CFL, rtol 1e-8, power iteration 20 sweeps",
+                   "grid": p.n, "outputs": 3, "rtol": 1e-8, "power_iters": 20},
+        "hbm_gbs_leja": round(achieved, 1),
+        "hbm_gbs_power": round(pw_bytes / (pw_ms * 1e-3) / 1e9, 1) if pw_ms > 0 else None,
+        "sweeps": last["iters"][:3],
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle sample")
+        out["cpu_baseline"] = cpu_baseline()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,223 @@
+/*
+ * lx.h - C ABI of an MI355X (gfx950) library for the action of phi functions
+ * of a matrix-free stencil operator, phi_l(hA)v, by Newton interpolation at
+ * scaled and shifted Leja points.
+ *
+ * Method (Deka, Moriggl, Einkemmer, "LeXInt: GPU-accelerated Exponential
+ * Integrators package", SoftwareX; arXiv 2310.08344):
+ *   - phi functions: Sec. 1, phi_0 = exp, phi_{l+1}(z) = (phi_l(z) - 1/l!)/z;
+ *   - Leja points of [-2, 2] and the Newton recurrence: Sec. 2.1, Eq. (2):
+ *       p_0 = d_0 y_0,  y_{m+1} = ((A - c)/gamma - xi_m) y_m,
+ *       p_{m+1} = p_m + d_{m+1} y_{m+1},
+ *     d_j the divided differences of sigma*phi_l(alpha*h*(c + gamma*xi));
+ *   - stop rule: Sec. 2.2 (text with Listing 2): error estimate at most
+ *     rtol*||p|| + atol, l2 norms divided by sqrt(N); the estimate used here
+ *     is |d_{m+1}| * ||y_{m+1}|| / sqrt(N);
+ *   - shift and scale from power iteration: Sec. 2 and Listing 7,
+ *     lambda = -safety*rho_hat, c = lambda/2, gamma = -lambda/4;
+ *   - several phi outputs from one Newton basis ("vertical" interpolation):
+ *     Sec. 2.3, Listing 11;
+ *   - exponential Rosenbrock steps with the nonlinear remainder
+ *     N(w) = f(w) - J(u_n) w: Sec. 2.3 (Listings 12 and 13).
+ *
+ * Conventions shared by every entry point
+ *   Grids are periodic nx x ny, stored row-major [ny][nx] (x fastest),
+ *   contiguous, FP64, in device memory owned by the caller (Sec. 2.2, the
+ *   caller allocates input and output arrays, Listing 4).  The library owns
+ *   only its context workspaces, allocated once by lx_create (Sec. 2.3,
+ *   Listing 10: allocate once per object, free in the destructor).
+ *   All device work is enqueued on the stream given to lx_create; every call
+ *   that returns host values waits for that stream once, at its end.
+ *   A context is not thread-safe: one host thread at a time per context.
+ *   Every call returns an lx_status; on an error other than LX_ENOTCONV the
+ *   outputs are unspecified and lx_last_error() holds a message.
+ */
+#ifndef LX_H
+#define LX_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LX_K_MAX 4          /* most phi outputs per Newton basis            */
+#define LX_MAX_ITERS 1000   /* most Leja iterations (operator applications) */
+
+typedef struct lx_ctx lx_ctx;
+
+typedef enum {
+    LX_OK = 0,
+    LX_EINVAL = 1,      /* bad argument: sizes, null pointers, c > 0, gamma <= 0, ... */
+    LX_ENOMEM = 2,      /* device or pinned host allocation failed                    */
+    LX_ENOTCONV = 3,    /* max_iters reached; outputs hold the last polynomial        */
+    LX_ENONFINITE = 4,  /* a norm became NaN or Inf; outputs unspecified              */
+    LX_EDEVICE = 5      /* a HIP call failed                                           */
+} lx_status;
+
+typedef enum {
+    /* A y = D*lap(y) + vx*Ux(y) + vy*Uy(y): centred 5-point Laplacian and a
+     * first-order upwind difference on the side that keeps Re(sigma(A)) <= 0
+     * (v > 0 forward, v < 0 backward); Sec. 3, Eq. (3).                     */
+    LX_OP_DIFFADV2D = 1,
+    /* F(u) = nu*lap(u) - (1/2)(d_x + d_y)(u^2), centred differences, and its
+     * Jacobian J(u) w = nu*lap(w) - (d_x + d_y)(u w); Sec. 3, Eq. (5).       */
+    LX_OP_BURGERS2D = 2
+} lx_op_kind;
+
+typedef enum {
+    LX_FP64 = 0,        /* basis vectors, stencil arithmetic and accumulation in FP64 */
+    LX_FP32_SWEEP = 1   /* basis vectors and stencil arithmetic in FP32 once the
+                           terms are small (see lx_leja_opts.fp32_switch); Leja
+                           points, divided differences, norms and the polynomial
+                           stay FP64                                               */
+} lx_prec;
+
+typedef struct {
+    int kind;           /* lx_op_kind                                 */
+    int nx, ny;         /* grid, each >= 3                            */
+    double dx, dy;      /* spacings, > 0                              */
+    double D;           /* LX_OP_DIFFADV2D: diffusion coefficient >= 0 */
+    double vx, vy;      /* LX_OP_DIFFADV2D: advection velocity        */
+    double nu;          /* LX_OP_BURGERS2D: viscosity >= 0            */
+    int prec;           /* lx_prec                                    */
+} lx_operator;
+
+typedef struct {
+    double rtol, atol;  /* stop when |d_{m+1}| ||y_{m+1}|| <= rtol ||p|| + atol (rms norms) */
+    int max_iters;      /* 1 .. LX_MAX_ITERS                                              */
+    /* LX_FP32_SWEEP only: FP32 sweeps start after the first iteration at which
+     * every unconverged output has |d_{m+1}| ||y_{m+1}|| <=
+     * fp32_switch * (rtol ||p|| + atol).  0 means FP32 from the first sweep.  */
+    double fp32_switch;
+} lx_leja_opts;
+
+/* Per-call record, filled by every lx_spectrum / lx_phi_leja / lx_exprb_step. */
+typedef struct {
+    int status;             /* lx_status of the call                          */
+    int n_apply;            /* operator applications (fused sweeps) made      */
+    int n_fp32;             /* of which in FP32 (LX_FP32_SWEEP)               */
+    int iters[LX_K_MAX];    /* per output: sweeps until it passed the test    */
+    double err[LX_K_MAX];   /* per output: last error estimate                */
+    double pnorm[LX_K_MAX]; /* per output: rms norm of the result             */
+    double rho_hat;         /* lx_spectrum: spectral estimate                 */
+    double plan_ms;         /* host planner time (Leja table, coefficients)   */
+    double loop_ms;         /* device loop, first to last sweep (timing on)   */
+    double sweep_ms;        /* sum of the working sweeps' durations (timing)  */
+    double first_sweep_ms;  /* duration of sweep 0 (timing on)                */
+    double bytes;           /* algorithmic HBM bytes of the working sweeps    */
+} lx_stats;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Creates a context for grids of at most n_max points and at most k_max
+ * (<= LX_K_MAX) outputs per basis; allocates every device workspace once
+ * (Listing 10).  stream is a hipStream_t (NULL = the null stream).  The
+ * current HIP device at this call is the context's device.
+ * Errors: LX_EINVAL (n_max < 9, k_max out of range), LX_ENOMEM, LX_EDEVICE. */
+lx_status lx_create(lx_ctx** ctx, size_t n_max, int k_max, void* stream);
+
+/* Frees every workspace (Listing 10, destructor).  NULL is a no-op. */
+void lx_destroy(lx_ctx* ctx);
+
+/* Changes the stream later calls enqueue on. */
+lx_status lx_set_stream(lx_ctx* ctx, void* stream);
+
+/* on != 0: record HIP events around every sweep so that lx_stats carries
+ * loop_ms, sweep_ms and first_sweep_ms.  Off by default. */
+lx_status lx_set_timing(lx_ctx* ctx, int on);
+
+/* Last error message of this context (static storage, valid until the next
+ * call on it). */
+const char* lx_last_error(const lx_ctx* ctx);
+const char* lx_status_string(int status);
+
+/* Copies the record of the last call. */
+lx_status lx_get_stats(const lx_ctx* ctx, lx_stats* out);
+
+/* ---- spectral bound --------------------------------------------------- */
+
+/* Power iteration for the dominant eigenvalue modulus of A (LX_OP_DIFFADV2D)
+ * or of the Jacobian J(u) (LX_OP_BURGERS2D, d_u = the state), then the Leja
+ * shift and scale of Listing 7:
+ *   w_0 = x0;  w_{k+1} = A w_k / ||w_k||;  rho_hat = ||w_iters||
+ *   lambda = -safety * rho_hat;  c = lambda / 2;  gamma = -lambda / 4.
+ * d_x0: start vector (nx*ny FP64, device, not modified); NULL = the library
+ * fills one with splitmix64 values in [-1, 1) (seed 0).  A constant start
+ * vector is invalid: it lies in the null space of the periodic operators.
+ * iters >= 1 applications of the operator (20 is customary).
+ * rho_hat, c, gamma: host outputs, each may be NULL.
+ * Errors: LX_EINVAL (op invalid, size > n_max, d_u missing for Burgers,
+ * iters < 1, safety <= 0), LX_ENONFINITE (zero or non-finite norm). */
+lx_status lx_spectrum(lx_ctx* ctx, const lx_operator* op, const double* d_u,
+                      const double* d_x0, int iters, double safety,
+                      double* rho_hat, double* c, double* gamma);
+
+/* ---- phi actions ------------------------------------------------------ */
+
+/* For k = 0..K-1:  d_out[k] = sigma[k] * phi_{l[k]}(alpha[k] * h * A) d_v,
+ * all K outputs from one Newton basis (Sec. 2.1 Eq. (2); vertical outputs,
+ * Listing 11).  Covers real_Leja_exp (K = 1, l = 0) and real_Leja_phi_nl /
+ * real_Leja_phi (l >= 1) of Listings 2, 3, 8, 9 and 11.
+ *   op      operator; LX_OP_BURGERS2D uses the Jacobian J(d_u)
+ *   d_u     device state for the Jacobian (Burgers), else NULL
+ *   d_v     device input vector (nx*ny), not modified
+ *   K       1 .. k_max outputs;  l[k] in 0..8;  alpha[k] > 0 (NULL = all 1);
+ *           sigma[k] (NULL = all 1)
+ *   d_out   K device output vectors, distinct, none equal to d_v or d_u
+ *   h > 0 step; c <= 0 and gamma > 0 from lx_spectrum (the Leja interval
+ *           [-2, 2] maps onto [c - 2 gamma, c + 2 gamma])
+ *   o       tolerances and iteration cap (NULL = rtol 1e-8, atol 0, 500)
+ *   iters   host [K] or NULL: sweeps until each output passed
+ *   err     host [K] or NULL: each output's last error estimate
+ * Each output freezes once it passes; the call ends when all have passed,
+ * or with LX_ENOTCONV after max_iters sweeps (outputs then hold the last
+ * polynomial), or with LX_ENONFINITE. */
+lx_status lx_phi_leja(lx_ctx* ctx, const lx_operator* op, const double* d_u,
+                      const double* d_v, int K, const int* l, const double* alpha,
+                      const double* sigma, double* const* d_out, double h,
+                      double c, double gamma, const lx_leja_opts* o,
+                      int* iters, double* err);
+
+/* ---- exponential integrator steps ------------------------------------- */
+
+typedef enum {
+    /* two-stage fourth-order exponential Rosenbrock method (named in Sec. 1;
+     * formula of the published method, c_2 = 3/4):
+     *   U2  = u + (3/4) h phi_1((3/4) h J) F(u)
+     *   u+  = u + h phi_1(h J) F(u) + (32/9) h phi_3(h J) [N(U2) - N(u)],
+     *   J = J(u), N(w) = F(w) - J w.                                         */
+    LX_EXPRB42 = 42
+} lx_scheme;
+
+/* One step u -> d_u_out of u_t = F(u) for LX_OP_BURGERS2D.  c and gamma
+ * describe the spectrum of J(d_u) (lx_spectrum with d_u).  iters: host [2]
+ * or NULL, sweeps of the phi_1 pass and of the phi_3 pass.  d_u_out must
+ * differ from d_u.  Errors as lx_phi_leja; LX_EINVAL for another operator
+ * or scheme. */
+lx_status lx_exprb_step(lx_ctx* ctx, const lx_operator* op, int scheme,
+                        const double* d_u, double* d_u_out, double h,
+                        double c, double gamma, const lx_leja_opts* o,
+                        int* iters);
+
+/* ---- host-only planner (no device needed) ------------------------------ */
+
+/* First M (1 .. LX_MAX_ITERS+1) Leja points of [-2, 2] (Sec. 2.1): xi_0 = 2,
+ * each next point maximises the product of distances to the earlier ones,
+ * exact ties to the larger point.  xi: host array of M doubles. */
+lx_status lx_leja_points(int M, double* xi);
+
+/* phi_l(z) for real z (Sec. 1), FP64. */
+double lx_phi_scalar(int l, double z);
+
+/* Newton coefficients d_0..d_{M-1} (divided differences) of
+ * f(xi) = sigma * phi_l(alpha * h * (c + gamma * xi)) at the first M Leja
+ * points, as the device loop uses them.  d: host array of M doubles. */
+lx_status lx_newton_coeffs(int l, double alpha, double sigma, double h,
+                           double c, double gamma, int M, double* d);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LX_H */

@@ -1,0 +1,269 @@
+"""ctypes binding of the C ABI in ``include/lx.h`` (argument marshalling only).
+
+Every step of the path runs in the HIP library ``_lx.so``; this module only
+turns torch tensors into device pointers and host results into Python
+values.  Loading fails loudly when the library has not been built: there is
+no other implementation to fall back to.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lx.so")
+
+LX_OK, LX_EINVAL, LX_ENOMEM, LX_ENOTCONV, LX_ENONFINITE, LX_EDEVICE = range(6)
+LX_OP_DIFFADV2D, LX_OP_BURGERS2D = 1, 2
+LX_FP64, LX_FP32_SWEEP = 0, 1
+LX_EXPRB42 = 42
+LX_K_MAX = 4
+LX_MAX_ITERS = 1000
+
+STATUS_NAMES = {0: "ok", 1: "einval", 2: "enomem", 3: "notconv", 4: "nonfinite", 5: "edevice"}
+
+
+class LxError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Operator(C.Structure):
+    _fields_ = [("kind", C.c_int), ("nx", C.c_int), ("ny", C.c_int),
+                ("dx", C.c_double), ("dy", C.c_double), ("D", C.c_double),
+                ("vx", C.c_double), ("vy", C.c_double), ("nu", C.c_double),
+                ("prec", C.c_int)]
+
+
+class LejaOpts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("max_iters", C.c_int),
+                ("fp32_switch", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("status", C.c_int), ("n_apply", C.c_int), ("n_fp32", C.c_int),
+                ("iters", C.c_int * LX_K_MAX), ("err", C.c_double * LX_K_MAX),
+                ("pnorm", C.c_double * LX_K_MAX), ("rho_hat", C.c_double),
+                ("plan_ms", C.c_double), ("loop_ms", C.c_double), ("sweep_ms", C.c_double),
+                ("first_sweep_ms", C.c_double), ("bytes", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {"status": self.status, "n_apply": self.n_apply, "n_fp32": self.n_fp32,
+                "iters": list(self.iters), "err": list(self.err), "pnorm": list(self.pnorm),
+                "rho_hat": self.rho_hat, "plan_ms": self.plan_ms, "loop_ms": self.loop_ms,
+                "sweep_ms": self.sweep_ms, "first_sweep_ms": self.first_sweep_ms,
+                "bytes": self.bytes}
+
+
+_P = C.c_void_p
+_D = C.c_double
+_I = C.c_int
+
+
+def _signatures(lib: C.CDLL) -> None:
+    lib.lx_create.argtypes = [C.POINTER(_P), C.c_size_t, _I, _P]
+    lib.lx_create.restype = _I
+    lib.lx_destroy.argtypes = [_P]
+    lib.lx_destroy.restype = None
+    lib.lx_set_stream.argtypes = [_P, _P]
+    lib.lx_set_stream.restype = _I
+    lib.lx_set_timing.argtypes = [_P, _I]
+    lib.lx_set_timing.restype = _I
+    lib.lx_last_error.argtypes = [_P]
+    lib.lx_last_error.restype = C.c_char_p
+    lib.lx_status_string.argtypes = [_I]
+    lib.lx_status_string.restype = C.c_char_p
+    lib.lx_get_stats.argtypes = [_P, C.POINTER(Stats)]
+    lib.lx_get_stats.restype = _I
+    lib.lx_spectrum.argtypes = [_P, C.POINTER(Operator), _P, _P, _I, _D,
+                                C.POINTER(_D), C.POINTER(_D), C.POINTER(_D)]
+    lib.lx_spectrum.restype = _I
+    lib.lx_phi_leja.argtypes = [_P, C.POINTER(Operator), _P, _P, _I, C.POINTER(_I),
+                                C.POINTER(_D), C.POINTER(_D), C.POINTER(_P), _D, _D, _D,
+                                C.POINTER(LejaOpts), C.POINTER(_I), C.POINTER(_D)]
+    lib.lx_phi_leja.restype = _I
+    lib.lx_exprb_step.argtypes = [_P, C.POINTER(Operator), _I, _P, _P, _D, _D, _D,
+                                  C.POINTER(LejaOpts), C.POINTER(_I)]
+    lib.lx_exprb_step.restype = _I
+    lib.lx_leja_points.argtypes = [_I, C.POINTER(_D)]
+    lib.lx_leja_points.restype = _I
+    lib.lx_phi_scalar.argtypes = [_I, _D]
+    lib.lx_phi_scalar.restype = _D
+    lib.lx_newton_coeffs.argtypes = [_I, _D, _D, _D, _D, _D, _I, C.POINTER(_D)]
+    lib.lx_newton_coeffs.restype = _I
+
+
+EXPORTED = ["lx_create", "lx_destroy", "lx_set_stream", "lx_set_timing", "lx_last_error",
+            "lx_status_string", "lx_get_stats", "lx_spectrum", "lx_phi_leja", "lx_exprb_step",
+            "lx_leja_points", "lx_phi_scalar", "lx_newton_coeffs"]
+
+
+def make_operator(problem=None, *, kind=None, n=None, nx=None, ny=None, dx=None, dy=None, D=0.0,
+                  vx=0.0, vy=0.0, nu=0.0, prec=LX_FP64) -> Operator:
+    """lx_operator from a workload Problem or from keywords."""
+    if problem is not None:
+        kind = LX_OP_DIFFADV2D if problem.kind == "diffadv" else LX_OP_BURGERS2D
+        nx = ny = problem.n
+        dx, dy = problem.dx, problem.dy
+        D, vx, vy, nu = problem.D, problem.vx, problem.vy, problem.nu
+    else:
+        nx = nx if nx is not None else n
+        ny = ny if ny is not None else n
+        dx = dx if dx is not None else 1.0 / nx
+        dy = dy if dy is not None else 1.0 / ny
+    return Operator(int(kind), int(nx), int(ny), float(dx), float(dy), float(D), float(vx), float(vy),
+                    float(nu), int(prec))
+
+
+def _ptr(t) -> int:
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError("vectors must be contiguous float64 tensors on the GPU")
+    return t.data_ptr()
+
+
+@dataclass
+class PhiResult:
+    status: int
+    iters: list
+    err: list
+    stats: dict
+
+
+class Context:
+    """An lx_ctx: workspaces for grids of at most n_max points."""
+
+    def __init__(self, lib: "Library", n_max: int, k_max: int = LX_K_MAX, stream=None):
+        import torch
+        self.lib = lib
+        self._h = _P()
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        st = lib.c.lx_create(C.byref(self._h), C.c_size_t(int(n_max)), int(k_max), _P(int(stream)))
+        if st != LX_OK:
+            raise LxError(st, "lx_create failed")
+        self.n_max, self.k_max = int(n_max), int(k_max)
+
+    def close(self) -> None:
+        if self._h:
+            self.lib.c.lx_destroy(self._h)
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, st: int, allow=(LX_OK,)) -> int:
+        if st not in allow:
+            raise LxError(st, self.lib.c.lx_last_error(self._h).decode())
+        return st
+
+    def last_error(self) -> str:
+        return self.lib.c.lx_last_error(self._h).decode()
+
+    def set_timing(self, on: bool) -> None:
+        self._check(self.lib.c.lx_set_timing(self._h, 1 if on else 0))
+
+    def set_stream(self, stream) -> None:
+        self._check(self.lib.c.lx_set_stream(self._h, _P(int(stream))))
+
+    def stats(self) -> dict:
+        s = Stats()
+        self._check(self.lib.c.lx_get_stats(self._h, C.byref(s)))
+        return s.as_dict()
+
+    def spectrum(self, op: Operator, u=None, x0=None, iters: int = 20, safety: float = 1.05,
+                 raise_on_error: bool = True):
+        """Returns (rho_hat, c, gamma) (lx_spectrum)."""
+        rho, c, g = _D(), _D(), _D()
+        st = self.lib.c.lx_spectrum(self._h, C.byref(op), _ptr(u), _ptr(x0), int(iters), float(safety),
+                                    C.byref(rho), C.byref(c), C.byref(g))
+        if raise_on_error:
+            self._check(st)
+        return rho.value, c.value, g.value
+
+    def phi_leja(self, op: Operator, v, outs, ls, h, c, gamma, u=None, alphas=None, sigmas=None,
+                 rtol=1e-8, atol=0.0, max_iters=500, fp32_switch=1e4, raise_on_error=True) -> PhiResult:
+        """outs[k] = sigma_k phi_{l_k}(alpha_k h A) v (lx_phi_leja)."""
+        K = len(outs)
+        larr = (_I * K)(*[int(x) for x in ls])
+        aarr = (_D * K)(*[float(x) for x in alphas]) if alphas is not None else None
+        sarr = (_D * K)(*[float(x) for x in sigmas]) if sigmas is not None else None
+        oarr = (_P * K)(*[_ptr(t) for t in outs])
+        opts = LejaOpts(float(rtol), float(atol), int(max_iters), float(fp32_switch))
+        it = (_I * K)()
+        er = (_D * K)()
+        st = self.lib.c.lx_phi_leja(self._h, C.byref(op), _ptr(u), _ptr(v), K, larr,
+                                    aarr, sarr, oarr, float(h), float(c), float(gamma),
+                                    C.byref(opts), it, er)
+        if raise_on_error:
+            self._check(st, allow=(LX_OK, LX_ENOTCONV))
+        return PhiResult(st, list(it), list(er), self.stats())
+
+    def exprb_step(self, op: Operator, u, u_out, h, c, gamma, rtol=1e-8, atol=0.0, max_iters=500,
+                   fp32_switch=1e4, scheme=LX_EXPRB42, raise_on_error=True) -> PhiResult:
+        opts = LejaOpts(float(rtol), float(atol), int(max_iters), float(fp32_switch))
+        it = (_I * 2)()
+        st = self.lib.c.lx_exprb_step(self._h, C.byref(op), int(scheme), _ptr(u), _ptr(u_out), float(h),
+                                      float(c), float(gamma), C.byref(opts), it)
+        if raise_on_error:
+            self._check(st, allow=(LX_OK, LX_ENOTCONV))
+        s = self.stats()
+        return PhiResult(st, list(it), s["err"][:2], s)
+
+
+class Library:
+    """The loaded ``_lx.so``."""
+
+    _instance = None
+
+    def __init__(self, path: str = LIB_PATH):
+        if not os.path.exists(path):
+            raise RuntimeError(f"HIP library not built: {path} is missing "
+                               "(run python -m paper_2310_08344_amd.build)")
+        self.path = path
+        self.c = C.CDLL(path)
+        _signatures(self.c)
+
+    @classmethod
+    def load(cls) -> "Library":
+        if cls._instance is None:
+            cls._instance = cls()
+        return cls._instance
+
+    def context(self, n_max: int, k_max: int = LX_K_MAX, stream=None) -> Context:
+        return Context(self, n_max, k_max, stream)
+
+    # host-only planner
+    def leja_points(self, M: int):
+        import numpy as np
+        out = (_D * M)()
+        st = self.c.lx_leja_points(int(M), out)
+        if st != LX_OK:
+            raise LxError(st, "lx_leja_points")
+        return np.array(out[:], dtype=np.float64)
+
+    def newton_coeffs(self, l, h, c, gamma, M, alpha=1.0, sigma=1.0):
+        import numpy as np
+        out = (_D * M)()
+        st = self.c.lx_newton_coeffs(int(l), float(alpha), float(sigma), float(h), float(c), float(gamma),
+                                     int(M), out)
+        if st != LX_OK:
+            raise LxError(st, "lx_newton_coeffs")
+        return np.array(out[:], dtype=np.float64)
+
+    def phi_scalar(self, l: int, z: float) -> float:
+        return float(self.c.lx_phi_scalar(int(l), float(z)))

@@ -1,0 +1,664 @@
+// C ABI of the Leja phi-action library (declarations and contracts in lx.h).
+//
+// Host side of the device-resident Leja loop: argument checks, the planner
+// (Leja points; divided differences produced a chunk ahead of the sweeps
+// that read them, while the GPU works), the initial loop state, then sweeps
+// enqueued in chunks.  The sweeps decide by themselves when to stop (a
+// converged loop turns later sweeps into no-ops); the host only looks at the
+// state once per chunk, one chunk behind, to stop enqueuing.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lx.h"
+#include "lx_device.h"
+#include "planner.h"
+
+using lx::LejaState;
+using lx::PowerArgs;
+using lx::SweepArgs;
+using lx::Tile;
+
+struct lx_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    size_t n_max = 0;
+    int k_max = 0;
+    int timing = 0;
+    // device workspaces
+    double* ybuf[2] = {nullptr, nullptr};   // Newton basis ping-pong (FP64 or FP32 view)
+    float* u32 = nullptr;                   // Burgers state in FP32 (FP32 sweeps)
+    double* ws[3] = {nullptr, nullptr, nullptr};  // EXPRB42 stages (allocated on first use)
+    double* partials = nullptr;
+    size_t partials_len = 0;
+    LejaState* st = nullptr;
+    double* coef = nullptr;                 // k_max * kMaxPoints
+    double* xi = nullptr;                   // kMaxPoints
+    int xi_uploaded = 0;
+    // pinned host staging
+    LejaState* h_st = nullptr;              // [3]: initial state, two poll slots
+    double* h_coef = nullptr;
+    double* h_xi = nullptr;
+    hipEvent_t poll_ev[2] = {nullptr, nullptr};
+    std::vector<hipEvent_t> tev;            // timing events
+    lx::NewtonSeries series[LX_K_MAX];      // per-output divided differences
+    lx_stats stats{};
+    std::string err;
+};
+
+namespace {
+
+constexpr int kFirstChunk = 16;   // sweeps enqueued before the first look at the state
+constexpr int kChunk = 8;         // sweeps per later chunk
+
+lx_status fail(lx_ctx* ctx, lx_status s, const char* fmt, ...) {
+    if (ctx != nullptr) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        std::vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+        ctx->stats.status = s;
+    }
+    return s;
+}
+
+#define LX_HIP(ctx, call)                                                                        \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return fail((ctx), LX_EDEVICE, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                        __FILE__, __LINE__);                                                     \
+    } while (0)
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+lx_status check_op(lx_ctx* ctx, const lx_operator* op) {
+    if (op == nullptr) return fail(ctx, LX_EINVAL, "operator is NULL");
+    if (op->kind != LX_OP_DIFFADV2D && op->kind != LX_OP_BURGERS2D)
+        return fail(ctx, LX_EINVAL, "unknown operator kind %d", op->kind);
+    if (op->nx < 3 || op->ny < 3) return fail(ctx, LX_EINVAL, "grid %dx%d: each side must be >= 3", op->nx, op->ny);
+    const size_t n = static_cast<size_t>(op->nx) * static_cast<size_t>(op->ny);
+    if (n > ctx->n_max) return fail(ctx, LX_EINVAL, "grid of %zu points exceeds n_max %zu", n, ctx->n_max);
+    if (!(op->dx > 0.0) || !(op->dy > 0.0) || !std::isfinite(op->dx) || !std::isfinite(op->dy))
+        return fail(ctx, LX_EINVAL, "spacings must be finite and > 0");
+    if (op->kind == LX_OP_DIFFADV2D &&
+        (!(op->D >= 0.0) || !std::isfinite(op->D) || !std::isfinite(op->vx) || !std::isfinite(op->vy)))
+        return fail(ctx, LX_EINVAL, "diffusion-advection needs finite D >= 0 and finite v");
+    if (op->kind == LX_OP_BURGERS2D && (!(op->nu >= 0.0) || !std::isfinite(op->nu)))
+        return fail(ctx, LX_EINVAL, "Burgers needs finite nu >= 0");
+    if (op->prec != LX_FP64 && op->prec != LX_FP32_SWEEP) return fail(ctx, LX_EINVAL, "unknown precision %d", op->prec);
+    return LX_OK;
+}
+
+// Launch shape: two columns per lane when the rows allow 16-byte loads,
+// 64 lanes along x when the grid is wide enough, and the tallest row march
+// that still leaves >= 2048 workgroups (8 per CU) to fill the chip.
+Tile choose_tile(int nx, int ny, bool vec2_ok) {
+    Tile t;
+    t.vec = (vec2_ok && nx % 2 == 0) ? 2 : 1;
+    int tx = 64;
+    while (tx > 4 && tx * t.vec > nx) tx >>= 1;
+    t.tx = tx;
+    t.ty = lx::kBlockThreads / tx;
+    t.ry = 1;
+    for (int ry : {8, 4, 2}) {
+        Tile c = t;
+        c.ry = ry;
+        if (c.rows() <= ny && lx::num_blocks(c, nx, ny) >= 2048) {
+            t.ry = ry;
+            break;
+        }
+    }
+    return t;
+}
+
+lx_status ensure_xi(lx_ctx* ctx, int M) {
+    if (M <= ctx->xi_uploaded) return LX_OK;
+    if (!lx::leja_points(M, ctx->h_xi)) return fail(ctx, LX_EINVAL, "cannot build %d Leja points", M);
+    LX_HIP(ctx, hipMemcpyAsync(ctx->xi, ctx->h_xi, sizeof(double) * M, hipMemcpyHostToDevice, ctx->stream));
+    LX_HIP(ctx, hipStreamSynchronize(ctx->stream));   // h_xi is reused by the next extension
+    ctx->xi_uploaded = M;
+    return LX_OK;
+}
+
+lx_status ensure_timing_events(lx_ctx* ctx, size_t n) {
+    while (ctx->tev.size() < n) {
+        hipEvent_t e;
+        LX_HIP(ctx, hipEventCreate(&e));
+        ctx->tev.push_back(e);
+    }
+    return LX_OK;
+}
+
+double elapsed(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0;
+    return static_cast<double>(ms);
+}
+
+struct LejaCall {
+    const lx_operator* op;
+    const double* u;
+    const double* v;
+    int K;
+    int l[LX_K_MAX];
+    double alpha[LX_K_MAX];
+    double sigma[LX_K_MAX];
+    double* out[LX_K_MAX];
+    const double* base[LX_K_MAX];
+    double h, c, gamma;
+    lx_leja_opts o;
+};
+
+// The device-resident Newton-Leja loop (Sec. 2.1, Eq. (2); stop rule of
+// Sec. 2.2).  Fills ctx->stats.
+lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
+    const lx_operator& op = *q.op;
+    const int nx = op.nx, ny = op.ny;
+    const long N = static_cast<long>(nx) * ny;
+    const int K = q.K;
+    const int M = q.o.max_iters + 1;
+    const bool fp32 = op.prec == LX_FP32_SWEEP;
+    lx_stats& S = ctx->stats;
+    S = lx_stats{};
+
+    // ---- planner: Leja points now, Newton coefficients chunk by chunk ----
+    const auto t0 = std::chrono::steady_clock::now();
+    lx_status s = ensure_xi(ctx, M);
+    if (s != LX_OK) return s;
+    for (int k = 0; k < K; ++k)
+        ctx->series[k].reset(q.l[k], q.alpha[k], q.sigma[k], q.h, q.c, q.gamma, ctx->h_xi);
+    int have = 0;          // coefficients d_0..d_{have-1} computed and enqueued for upload
+    double plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    // sweep m reads d_{m+1}; sweeps [0, upto-1) need d_0..d_{upto-1}
+    auto ensure_coeffs = [&](int upto) -> lx_status {
+        upto = std::min(upto, M);
+        if (upto <= have) return LX_OK;
+        const auto ta = std::chrono::steady_clock::now();
+        for (int k = 0; k < K; ++k) {
+            double* hc = ctx->h_coef + static_cast<size_t>(k) * M;
+            for (int j = have; j < upto; ++j) hc[j] = ctx->series[k].next();
+        }
+        for (int k = 0; k < K; ++k) {
+            const size_t off = static_cast<size_t>(k) * M + have;
+            LX_HIP(ctx, hipMemcpyAsync(ctx->coef + off, ctx->h_coef + off, sizeof(double) * (upto - have),
+                                       hipMemcpyHostToDevice, ctx->stream));
+        }
+        have = upto;
+        plan_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - ta).count();
+        return LX_OK;
+    };
+
+    LejaState& init = ctx->h_st[0];
+    std::memset(&init, 0, sizeof(init));
+    init.rtol = q.o.rtol;
+    init.atol = q.o.atol;
+    init.fp32_switch = fp32 ? q.o.fp32_switch : -1.0;
+    init.max_iters = q.o.max_iters;
+    init.out32 = (fp32 && q.o.fp32_switch == 0.0) ? 1 : 0;
+    for (int k = 0; k < K; ++k) {
+        init.active[k] = 1;
+        init.iters[k] = q.o.max_iters;
+    }
+    LX_HIP(ctx, hipMemcpyAsync(ctx->st, &init, sizeof(LejaState), hipMemcpyHostToDevice, ctx->stream));
+
+    if (fp32 && op.kind == LX_OP_BURGERS2D) LX_HIP(ctx, lx::launch_to_fp32(q.u, ctx->u32, N, ctx->stream));
+
+    // ---- sweep arguments ----
+    bool vec2 = aligned16(q.v) && (q.u == nullptr || aligned16(q.u));
+    for (int k = 0; k < K; ++k) vec2 = vec2 && aligned16(q.out[k]) && (q.base[k] == nullptr || aligned16(q.base[k]));
+    const Tile t = choose_tile(nx, ny, vec2);
+    SweepArgs a{};
+    a.nx = nx;
+    a.ny = ny;
+    a.tiles_x = (nx + t.cols() - 1) / t.cols();
+    a.tiles_y = (ny + t.rows() - 1) / t.rows();
+    a.K = K;
+    a.ld = M;
+    const double g = q.gamma;
+    if (op.kind == LX_OP_DIFFADV2D) {
+        const double ex = op.D / (op.dx * op.dx), ey = op.D / (op.dy * op.dy);
+        const double cE = ex + std::max(op.vx, 0.0) / op.dx, cW = ex + std::max(-op.vx, 0.0) / op.dx;
+        const double cN = ey + std::max(op.vy, 0.0) / op.dy, cS = ey + std::max(-op.vy, 0.0) / op.dy;
+        const double cC = -(cE + cW + cN + cS);
+        a.aE = cE / g;
+        a.aW = cW / g;
+        a.aN = cN / g;
+        a.aS = cS / g;
+        a.aC = (cC - q.c) / g;
+    } else {
+        a.kx = op.nu / (g * op.dx * op.dx);
+        a.ky = op.nu / (g * op.dy * op.dy);
+        a.gx = 1.0 / (2.0 * g * op.dx);
+        a.gy = 1.0 / (2.0 * g * op.dy);
+        a.kC = -2.0 * a.kx - 2.0 * a.ky - q.c / g;
+    }
+    a.inv_sqrtN = 1.0 / std::sqrt(static_cast<double>(N));
+    a.v = q.v;
+    a.ybuf[0] = ctx->ybuf[0];
+    a.ybuf[1] = ctx->ybuf[1];
+    a.u = q.u;
+    a.u32 = ctx->u32;
+    for (int k = 0; k < K; ++k) {
+        a.p[k] = q.out[k];
+        a.base[k] = q.base[k];
+    }
+    a.coef = ctx->coef;
+    a.xi = ctx->xi;
+    a.partials = ctx->partials;
+    a.st = ctx->st;
+    const int opcode = op.kind == LX_OP_DIFFADV2D ? lx::kOpDiffAdv : lx::kOpBurgersJ;
+    if (static_cast<size_t>(a.tiles_x) * a.tiles_y * (1 + K) > ctx->partials_len)
+        return fail(ctx, LX_EINVAL, "launch shape exceeds the partials workspace");
+
+    // ---- chunked, device-resident loop ----
+    const int max_iters = q.o.max_iters;
+    if (ctx->timing) {
+        s = ensure_timing_events(ctx, static_cast<size_t>(max_iters) + 1);
+        if (s != LX_OK) return s;
+        LX_HIP(ctx, hipEventRecord(ctx->tev[0], ctx->stream));
+    }
+    int launched = 0, chunk_id = 0, last_slot = -1;
+    int chunk = kFirstChunk;
+    while (launched < max_iters) {
+        const int n = std::min(chunk, max_iters - launched);
+        s = ensure_coeffs(launched + n + 1);
+        if (s != LX_OK) return s;
+        for (int i = 0; i < n; ++i) {
+            LX_HIP(ctx, lx::launch_leja_sweep(opcode, K, fp32, t, a, ctx->stream));
+            if (ctx->timing) LX_HIP(ctx, hipEventRecord(ctx->tev[launched + i + 1], ctx->stream));
+        }
+        launched += n;
+        const int slot = chunk_id & 1;
+        LX_HIP(ctx, hipMemcpyAsync(&ctx->h_st[1 + slot], ctx->st, sizeof(LejaState), hipMemcpyDeviceToHost,
+                                   ctx->stream));
+        LX_HIP(ctx, hipEventRecord(ctx->poll_ev[slot], ctx->stream));
+        last_slot = slot;
+        if (chunk_id >= 1) {
+            // the next chunk's coefficients are prepared while the GPU works
+            s = ensure_coeffs(std::min(launched + kChunk, max_iters) + 1);
+            if (s != LX_OK) return s;
+            const int prev = slot ^ 1;
+            LX_HIP(ctx, hipEventSynchronize(ctx->poll_ev[prev]));
+            if (ctx->h_st[1 + prev].done) break;
+        }
+        ++chunk_id;
+        chunk = kChunk;
+    }
+    LX_HIP(ctx, hipEventSynchronize(ctx->poll_ev[last_slot]));
+    const LejaState& fin = ctx->h_st[1 + last_slot];
+
+    S.n_apply = fin.iter;
+    S.n_fp32 = fin.n_fp32;
+    for (int k = 0; k < K; ++k) {
+        S.iters[k] = fin.iters[k];
+        S.err[k] = fin.err[k];
+        S.pnorm[k] = fin.pnorm[k];
+    }
+    // algorithmic bytes: per sweep, the basis read and write, the Burgers
+    // state read, and per unconverged output a read and a write of p (sweep 0
+    // writes p_1 = d_0 v + d_1 y_1 without reading it; a base adds a read)
+    double bytes = 0.0;
+    for (int m = 0; m < fin.iter; ++m) {
+        const bool w32 = m >= fin.iter - fin.n_fp32;
+        const bool r32 = m >= 1 && (m - 1) >= fin.iter - fin.n_fp32;
+        double b = (r32 ? 4.0 : 8.0) + (w32 ? 4.0 : 8.0);
+        if (op.kind == LX_OP_BURGERS2D) b += w32 ? 4.0 : 8.0;
+        for (int k = 0; k < K; ++k) {
+            if (m < fin.iters[k]) b += (m == 0) ? (q.base[k] ? 16.0 : 8.0) : 16.0;
+        }
+        bytes += b * static_cast<double>(N);
+    }
+    S.bytes = bytes;
+    S.plan_ms = plan_ms;
+    if (ctx->timing && fin.iter > 0) {
+        S.first_sweep_ms = elapsed(ctx->tev[0], ctx->tev[1]);
+        S.loop_ms = elapsed(ctx->tev[0], ctx->tev[fin.iter]);
+        S.sweep_ms = S.loop_ms;
+    }
+    S.status = fin.done ? fin.status : LX_ENOTCONV;
+    if (S.status == LX_ENONFINITE) return fail(ctx, LX_ENONFINITE, "a norm became NaN or Inf at sweep %d", fin.iter);
+    if (S.status == LX_ENOTCONV) {
+        ctx->err = "not converged within max_iters";
+        return LX_ENOTCONV;
+    }
+    return LX_OK;
+}
+
+lx_status check_leja_opts(lx_ctx* ctx, const lx_leja_opts* o, lx_leja_opts* out) {
+    lx_leja_opts d{1e-8, 0.0, 500, 1e4};
+    if (o != nullptr) d = *o;
+    if (!(d.rtol >= 0.0) || !(d.atol >= 0.0) || !std::isfinite(d.rtol) || !std::isfinite(d.atol))
+        return fail(ctx, LX_EINVAL, "tolerances must be finite and >= 0");
+    if (d.max_iters < 1 || d.max_iters > LX_MAX_ITERS)
+        return fail(ctx, LX_EINVAL, "max_iters %d outside 1..%d", d.max_iters, LX_MAX_ITERS);
+    if (!(d.fp32_switch >= 0.0)) return fail(ctx, LX_EINVAL, "fp32_switch must be >= 0");
+    *out = d;
+    return LX_OK;
+}
+
+lx_status check_shift(lx_ctx* ctx, double h, double c, double gamma) {
+    if (!(h > 0.0) || !std::isfinite(h)) return fail(ctx, LX_EINVAL, "step h must be finite and > 0");
+    if (!(c <= 0.0) || !std::isfinite(c)) return fail(ctx, LX_EINVAL, "shift c must be finite and <= 0");
+    if (!(gamma > 0.0) || !std::isfinite(gamma)) return fail(ctx, LX_EINVAL, "scale gamma must be finite and > 0");
+    return LX_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+const char* lx_status_string(int status) {
+    switch (status) {
+        case LX_OK: return "LX_OK";
+        case LX_EINVAL: return "LX_EINVAL";
+        case LX_ENOMEM: return "LX_ENOMEM";
+        case LX_ENOTCONV: return "LX_ENOTCONV";
+        case LX_ENONFINITE: return "LX_ENONFINITE";
+        case LX_EDEVICE: return "LX_EDEVICE";
+        default: return "unknown status";
+    }
+}
+
+const char* lx_last_error(const lx_ctx* ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+
+lx_status lx_get_stats(const lx_ctx* ctx, lx_stats* out) {
+    if (ctx == nullptr || out == nullptr) return LX_EINVAL;
+    *out = ctx->stats;
+    return LX_OK;
+}
+
+void lx_destroy(lx_ctx* ctx) {
+    if (ctx == nullptr) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    for (double* p : ctx->ybuf) (void)hipFree(p);
+    for (double* p : ctx->ws) (void)hipFree(p);
+    (void)hipFree(ctx->u32);
+    (void)hipFree(ctx->partials);
+    (void)hipFree(ctx->st);
+    (void)hipFree(ctx->coef);
+    (void)hipFree(ctx->xi);
+    (void)hipHostFree(ctx->h_st);
+    (void)hipHostFree(ctx->h_coef);
+    (void)hipHostFree(ctx->h_xi);
+    for (hipEvent_t e : ctx->poll_ev)
+        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ctx->tev) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+lx_status lx_create(lx_ctx** out, size_t n_max, int k_max, void* stream) {
+    if (out == nullptr) return LX_EINVAL;
+    *out = nullptr;
+    if (n_max < 9 || k_max < 1 || k_max > LX_K_MAX) return LX_EINVAL;
+    lx_ctx* ctx = new lx_ctx();
+    ctx->n_max = n_max;
+    ctx->k_max = k_max;
+    ctx->stream = static_cast<hipStream_t>(stream);
+    auto bail = [&](lx_status s) {
+        lx_destroy(ctx);
+        return s;
+    };
+    if (hipGetDevice(&ctx->device) != hipSuccess) return bail(LX_EDEVICE);
+    for (auto& p : ctx->ybuf)
+        if (hipMalloc(&p, sizeof(double) * n_max) != hipSuccess) return bail(LX_ENOMEM);
+    if (hipMalloc(&ctx->u32, sizeof(float) * n_max) != hipSuccess) return bail(LX_ENOMEM);
+    // one partial sum per workgroup and per norm; the smallest tile has 256 points
+    ctx->partials_len = static_cast<size_t>(1 + k_max) * (n_max / 256 + 4096 + 64);
+    if (hipMalloc(&ctx->partials, sizeof(double) * ctx->partials_len) != hipSuccess) return bail(LX_ENOMEM);
+    if (hipMalloc(&ctx->st, sizeof(LejaState)) != hipSuccess) return bail(LX_ENOMEM);
+    if (hipMalloc(&ctx->coef, sizeof(double) * k_max * lx::kMaxPoints) != hipSuccess) return bail(LX_ENOMEM);
+    if (hipMalloc(&ctx->xi, sizeof(double) * lx::kMaxPoints) != hipSuccess) return bail(LX_ENOMEM);
+    if (hipHostMalloc(reinterpret_cast<void**>(&ctx->h_st), 3 * sizeof(LejaState), hipHostMallocDefault) != hipSuccess)
+        return bail(LX_ENOMEM);
+    if (hipHostMalloc(reinterpret_cast<void**>(&ctx->h_coef), sizeof(double) * k_max * lx::kMaxPoints,
+                      hipHostMallocDefault) != hipSuccess)
+        return bail(LX_ENOMEM);
+    if (hipHostMalloc(reinterpret_cast<void**>(&ctx->h_xi), sizeof(double) * lx::kMaxPoints, hipHostMallocDefault) !=
+        hipSuccess)
+        return bail(LX_ENOMEM);
+    for (auto& e : ctx->poll_ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return bail(LX_EDEVICE);
+    std::memset(ctx->h_st, 0, 3 * sizeof(LejaState));
+    if (hipMemsetAsync(ctx->st, 0, sizeof(LejaState), ctx->stream) != hipSuccess) return bail(LX_EDEVICE);
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return bail(LX_EDEVICE);
+    *out = ctx;
+    return LX_OK;
+}
+
+lx_status lx_set_stream(lx_ctx* ctx, void* stream) {
+    if (ctx == nullptr) return LX_EINVAL;
+    ctx->stream = static_cast<hipStream_t>(stream);
+    return LX_OK;
+}
+
+lx_status lx_set_timing(lx_ctx* ctx, int on) {
+    if (ctx == nullptr) return LX_EINVAL;
+    ctx->timing = on ? 1 : 0;
+    return LX_OK;
+}
+
+lx_status lx_spectrum(lx_ctx* ctx, const lx_operator* op, const double* d_u, const double* d_x0, int iters,
+                      double safety, double* rho_hat, double* c, double* gamma) {
+    if (ctx == nullptr) return LX_EINVAL;
+    ctx->stats = lx_stats{};
+    lx_status s = check_op(ctx, op);
+    if (s != LX_OK) return s;
+    if (iters < 1 || iters > LX_MAX_ITERS) return fail(ctx, LX_EINVAL, "power iterations %d outside 1..%d", iters, LX_MAX_ITERS);
+    if (!(safety > 0.0) || !std::isfinite(safety)) return fail(ctx, LX_EINVAL, "safety must be finite and > 0");
+    if (op->kind == LX_OP_BURGERS2D && d_u == nullptr) return fail(ctx, LX_EINVAL, "Burgers Jacobian needs d_u");
+    const int nx = op->nx, ny = op->ny;
+    const long N = static_cast<long>(nx) * ny;
+
+    LejaState& init = ctx->h_st[0];
+    std::memset(&init, 0, sizeof(init));
+    LX_HIP(ctx, hipMemcpyAsync(ctx->st, &init, sizeof(LejaState), hipMemcpyHostToDevice, ctx->stream));
+    const double* x0 = d_x0;
+    if (x0 == nullptr) {
+        LX_HIP(ctx, lx::launch_fill_splitmix(ctx->ybuf[1], N, 0ull, ctx->stream));
+        x0 = ctx->ybuf[1];
+    }
+    LX_HIP(ctx, lx::launch_norm(x0, N, ctx->partials, ctx->st, ctx->stream));
+
+    const bool vec2 = aligned16(x0) && (d_u == nullptr || aligned16(d_u));
+    const Tile t = choose_tile(nx, ny, vec2);
+    PowerArgs a{};
+    a.nx = nx;
+    a.ny = ny;
+    a.tiles_x = (nx + t.cols() - 1) / t.cols();
+    a.tiles_y = (ny + t.rows() - 1) / t.rows();
+    if (op->kind == LX_OP_DIFFADV2D) {
+        const double ex = op->D / (op->dx * op->dx), ey = op->D / (op->dy * op->dy);
+        a.cE = ex + std::max(op->vx, 0.0) / op->dx;
+        a.cW = ex + std::max(-op->vx, 0.0) / op->dx;
+        a.cN = ey + std::max(op->vy, 0.0) / op->dy;
+        a.cS = ey + std::max(-op->vy, 0.0) / op->dy;
+        a.cC = -(a.cE + a.cW + a.cN + a.cS);
+    } else {
+        a.kx = op->nu / (op->dx * op->dx);
+        a.ky = op->nu / (op->dy * op->dy);
+        a.gx = 1.0 / (2.0 * op->dx);
+        a.gy = 1.0 / (2.0 * op->dy);
+    }
+    a.u = d_u;
+    a.partials = ctx->partials;
+    a.st = ctx->st;
+    const int opcode = op->kind == LX_OP_DIFFADV2D ? lx::kOpDiffAdv : lx::kOpBurgersJ;
+    if (ctx->timing) {
+        s = ensure_timing_events(ctx, static_cast<size_t>(iters) + 1);
+        if (s != LX_OK) return s;
+        LX_HIP(ctx, hipEventRecord(ctx->tev[0], ctx->stream));
+    }
+    for (int k = 0; k < iters; ++k) {
+        a.in = (k == 0) ? x0 : ctx->ybuf[(k - 1) & 1];
+        a.out = ctx->ybuf[k & 1];
+        LX_HIP(ctx, lx::launch_power_sweep(opcode, t, a, ctx->stream));
+        if (ctx->timing) LX_HIP(ctx, hipEventRecord(ctx->tev[k + 1], ctx->stream));
+    }
+    LX_HIP(ctx, hipMemcpyAsync(&ctx->h_st[1], ctx->st, sizeof(LejaState), hipMemcpyDeviceToHost, ctx->stream));
+    LX_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    const LejaState& fin = ctx->h_st[1];
+    lx_stats& S = ctx->stats;
+    S.n_apply = fin.iter;
+    S.rho_hat = fin.rho;
+    S.bytes = (16.0 + (op->kind == LX_OP_BURGERS2D ? 8.0 : 0.0)) * static_cast<double>(N) * iters;
+    if (ctx->timing) {
+        S.loop_ms = elapsed(ctx->tev[0], ctx->tev[iters]);
+        S.sweep_ms = elapsed(ctx->tev[1], ctx->tev[iters]);
+        S.first_sweep_ms = elapsed(ctx->tev[0], ctx->tev[1]);
+    }
+    if (fin.status != 0 || !std::isfinite(fin.rho) || !(fin.rho > 0.0) || fin.iter != iters)
+        return fail(ctx, LX_ENONFINITE, "power iteration produced a zero or non-finite norm");
+    const double lam = -safety * fin.rho;
+    if (rho_hat) *rho_hat = fin.rho;
+    if (c) *c = lam / 2.0;
+    if (gamma) *gamma = -lam / 4.0;
+    S.status = LX_OK;
+    return LX_OK;
+}
+
+lx_status lx_phi_leja(lx_ctx* ctx, const lx_operator* op, const double* d_u, const double* d_v, int K, const int* l,
+                      const double* alpha, const double* sigma, double* const* d_out, double h, double c,
+                      double gamma, const lx_leja_opts* o, int* iters, double* err) {
+    if (ctx == nullptr) return LX_EINVAL;
+    ctx->stats = lx_stats{};
+    lx_status s = check_op(ctx, op);
+    if (s != LX_OK) return s;
+    if (K < 1 || K > ctx->k_max) return fail(ctx, LX_EINVAL, "K = %d outside 1..%d", K, ctx->k_max);
+    if (d_v == nullptr || d_out == nullptr || l == nullptr) return fail(ctx, LX_EINVAL, "NULL vector or order array");
+    if (op->kind == LX_OP_BURGERS2D && d_u == nullptr) return fail(ctx, LX_EINVAL, "Burgers Jacobian needs d_u");
+    s = check_shift(ctx, h, c, gamma);
+    if (s != LX_OK) return s;
+    LejaCall q{};
+    s = check_leja_opts(ctx, o, &q.o);
+    if (s != LX_OK) return s;
+    q.op = op;
+    q.u = op->kind == LX_OP_BURGERS2D ? d_u : nullptr;
+    q.v = d_v;
+    q.K = K;
+    q.h = h;
+    q.c = c;
+    q.gamma = gamma;
+    for (int k = 0; k < K; ++k) {
+        if (l[k] < 0 || l[k] > 8) return fail(ctx, LX_EINVAL, "phi order l[%d] = %d outside 0..8", k, l[k]);
+        q.l[k] = l[k];
+        q.alpha[k] = alpha ? alpha[k] : 1.0;
+        q.sigma[k] = sigma ? sigma[k] : 1.0;
+        if (!(q.alpha[k] > 0.0) || !std::isfinite(q.alpha[k]) || !std::isfinite(q.sigma[k]))
+            return fail(ctx, LX_EINVAL, "alpha[%d] must be finite and > 0, sigma finite", k);
+        if (d_out[k] == nullptr) return fail(ctx, LX_EINVAL, "d_out[%d] is NULL", k);
+        if (d_out[k] == d_v || (q.u != nullptr && d_out[k] == q.u))
+            return fail(ctx, LX_EINVAL, "d_out[%d] aliases an input", k);
+        for (int j = 0; j < k; ++j)
+            if (d_out[j] == d_out[k]) return fail(ctx, LX_EINVAL, "d_out[%d] and d_out[%d] alias", j, k);
+        q.out[k] = d_out[k];
+        q.base[k] = nullptr;
+    }
+    s = run_leja(ctx, q);
+    for (int k = 0; k < K; ++k) {
+        if (iters) iters[k] = ctx->stats.iters[k];
+        if (err) err[k] = ctx->stats.err[k];
+    }
+    return s;
+}
+
+lx_status lx_exprb_step(lx_ctx* ctx, const lx_operator* op, int scheme, const double* d_u, double* d_u_out,
+                        double h, double c, double gamma, const lx_leja_opts* o, int* iters) {
+    if (ctx == nullptr) return LX_EINVAL;
+    ctx->stats = lx_stats{};
+    lx_status s = check_op(ctx, op);
+    if (s != LX_OK) return s;
+    if (op->kind != LX_OP_BURGERS2D) return fail(ctx, LX_EINVAL, "exponential integrator steps need LX_OP_BURGERS2D");
+    if (scheme != LX_EXPRB42) return fail(ctx, LX_EINVAL, "unknown scheme %d", scheme);
+    if (d_u == nullptr || d_u_out == nullptr || d_u == d_u_out)
+        return fail(ctx, LX_EINVAL, "d_u and d_u_out must be distinct, non-NULL");
+    if (ctx->k_max < 2) return fail(ctx, LX_EINVAL, "EXPRB42 needs a context with k_max >= 2");
+    s = check_shift(ctx, h, c, gamma);
+    if (s != LX_OK) return s;
+    lx_leja_opts oo;
+    s = check_leja_opts(ctx, o, &oo);
+    if (s != LX_OK) return s;
+    for (auto& w : ctx->ws)
+        if (w == nullptr && hipMalloc(&w, sizeof(double) * ctx->n_max) != hipSuccess)
+            return fail(ctx, LX_ENOMEM, "EXPRB42 workspace allocation failed");
+    const int nx = op->nx, ny = op->ny;
+    double* hF = ctx->ws[0];   // h F(u), later h [N(U2) - N(u)]
+    double* U2 = ctx->ws[1];
+    // stage 1: U2 = u + (3/4) h phi_1((3/4) h J) F(u) and
+    //          u_out = u + h phi_1(h J) F(u), one Newton basis
+    LX_HIP(ctx, lx::launch_burgers_hF(d_u, hF, nx, ny, op->nu, op->dx, op->dy, h, ctx->stream));
+    LejaCall q{};
+    q.op = op;
+    q.u = d_u;
+    q.v = hF;
+    q.K = 2;
+    q.l[0] = 1; q.alpha[0] = 0.75; q.sigma[0] = 0.75; q.out[0] = U2;      q.base[0] = d_u;
+    q.l[1] = 1; q.alpha[1] = 1.0;  q.sigma[1] = 1.0;  q.out[1] = d_u_out; q.base[1] = d_u;
+    q.h = h;
+    q.c = c;
+    q.gamma = gamma;
+    q.o = oo;
+    s = run_leja(ctx, q);
+    if (s != LX_OK) return s;
+    const lx_stats s1 = ctx->stats;
+    // stage 2: R = h [N(U2) - N(u)], u_out += (32/9) h phi_3(h J) R / h
+    LX_HIP(ctx, lx::launch_burgers_remainder(d_u, U2, hF, nx, ny, op->nu, op->dx, op->dy, h, ctx->stream));
+    LejaCall r{};
+    r.op = op;
+    r.u = d_u;
+    r.v = hF;
+    r.K = 1;
+    r.l[0] = 3; r.alpha[0] = 1.0; r.sigma[0] = 32.0 / 9.0; r.out[0] = d_u_out; r.base[0] = d_u_out;
+    r.h = h;
+    r.c = c;
+    r.gamma = gamma;
+    r.o = oo;
+    s = run_leja(ctx, r);
+    lx_stats& S = ctx->stats;
+    const int it1 = std::max(s1.iters[0], s1.iters[1]);
+    const int it2 = S.iters[0];
+    if (iters) {
+        iters[0] = it1;
+        iters[1] = it2;
+    }
+    S.iters[0] = it1;
+    S.iters[1] = it2;
+    S.err[1] = S.err[0];
+    S.err[0] = std::max(s1.err[0], s1.err[1]);
+    S.n_apply += s1.n_apply;
+    S.n_fp32 += s1.n_fp32;
+    S.bytes += s1.bytes;
+    S.plan_ms += s1.plan_ms;
+    S.loop_ms += s1.loop_ms;
+    S.sweep_ms += s1.sweep_ms;
+    return s;
+}
+
+lx_status lx_leja_points(int M, double* xi) {
+    if (xi == nullptr || M < 1 || M > lx::kMaxPoints) return LX_EINVAL;
+    return lx::leja_points(M, xi) ? LX_OK : LX_EINVAL;
+}
+
+double lx_phi_scalar(int l, double z) { return lx::phi_scalar(l, z); }
+
+lx_status lx_newton_coeffs(int l, double alpha, double sigma, double h, double c, double gamma, int M, double* d) {
+    if (d == nullptr || M < 1 || M > lx::kMaxPoints || l < 0 || l > 8) return LX_EINVAL;
+    std::vector<double> xi(static_cast<size_t>(M));
+    if (!lx::leja_points(M, xi.data())) return LX_EINVAL;
+    return lx::newton_coeffs(l, alpha, sigma, h, c, gamma, M, xi.data(), d) ? LX_OK : LX_EINVAL;
+}
+
+}  // extern "C"

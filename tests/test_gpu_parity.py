@@ -1,0 +1,312 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI.
+
+Bar: relative L2 error <= 1e-10 in FP64 with equal iteration counts (a
+borderline stop decision that flips by one sweep is rerun on the oracle at
+the GPU's count and reported); FP32 sweeps within the requested tolerance of
+the FP64 oracle.  Sizes span several tiles and ragged tails; the full-size
+workloads are checked against the exact Fourier solution and invariants.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.exact import phi_fft
+from oracle.operators import burgers_J, diffadv_apply
+from oracle.phi_action import exprb42_step, leja_phi, power_iteration
+from paper_2310_08344_amd import binding as B
+from paper_2310_08344_amd import workloads as W
+from tests.gpu_helpers import (closed_form_shift, dev, diffadv_setup, host, oracle_parity,
+                               rel, say)
+
+pytestmark = pytest.mark.gpu
+
+PARITY = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ctx(lx):
+    c = lx.context(n_max=1024 * 1024, k_max=4)
+    yield c
+    c.close()
+
+
+def _op(prm, prec=B.LX_FP64):
+    return B.make_operator(kind=B.LX_OP_DIFFADV2D, nx=prm["nx"], ny=prm["ny"], dx=prm["dx"], dy=prm["dy"],
+                           D=prm["D"], vx=prm["vx"], vy=prm["vy"], prec=prec)
+
+
+def _A(prm):
+    return lambda y: diffadv_apply(y, prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
+
+
+# ---------------------------------------------------------------------------
+# spectral bound
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("nx,ny", [(64, 64), (200, 136), (97, 75)])
+def test_spectrum_matches_oracle(ctx, nx, ny):
+    prm, _ = diffadv_setup(nx, ny)
+    x0 = np.random.default_rng(5).standard_normal((ny, nx))
+    say("spectrum diffadv", nx, ny)
+    rho, c, g = ctx.spectrum(_op(prm), x0=dev(x0), iters=20)
+    rho_o, _ = power_iteration(_A(prm), x0, 20)
+    assert abs(rho - rho_o) <= 1e-12 * rho_o
+    assert c == -1.05 * rho / 2 and g == 1.05 * rho / 4
+
+
+def test_spectrum_burgers_jacobian_matches_oracle(ctx):
+    n = 128
+    u = W.fourier_modes(n, seed=3)
+    x0 = np.random.default_rng(6).standard_normal((n, n))
+    op = B.make_operator(kind=B.LX_OP_BURGERS2D, n=n, nu=1e-3)
+    say("spectrum burgers", n)
+    rho, _, _ = ctx.spectrum(op, u=dev(u), x0=dev(x0), iters=20)
+    rho_o, _ = power_iteration(lambda w: burgers_J(u, w, 1e-3, 1 / n, 1 / n), x0, 20)
+    assert abs(rho - rho_o) <= 1e-12 * rho_o
+
+
+def test_spectrum_default_start_vector(ctx):
+    prm, _ = diffadv_setup(128, 128)
+    say("spectrum default x0")
+    rho, _, _ = ctx.spectrum(_op(prm), iters=30)
+    rho_closed = 2.0 / W.diffadv_cfl_step(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
+    assert 0.9 * rho_closed <= rho <= rho_closed * (1 + 1e-12)
+
+
+# ---------------------------------------------------------------------------
+# phi actions, diffusion-advection
+# ---------------------------------------------------------------------------
+
+def test_exp_workload_64_squared_end_to_end(ctx):
+    p, u0 = W.config1()
+    op = B.make_operator(p)
+    x0 = W.start_vector(p.n)
+    say("64^2 exp workload")
+    rho, c, g = ctx.spectrum(op, x0=dev(x0), iters=20)
+    out = dev(np.zeros_like(u0))
+    r = ctx.phi_leja(op, dev(u0), [out], [0], p.h, c, g, rtol=1e-10, max_iters=200)
+    assert r.status == B.LX_OK
+    A = _A(dict(D=p.D, vx=p.vx, vy=p.vy, dx=p.dx, dy=p.dy))
+    _, errs, _ = oracle_parity([host(out)], r.iters,
+                               lambda f: leja_phi(A, u0, [(0, 1.0, 1.0)], p.h, c, g, 1e-10, 0.0, 200, f),
+                               PARITY)
+    exact = phi_fft(u0, 0, p.h, p.D, p.vx, p.vy, p.dx, p.dy)
+    assert rel(host(out), exact) <= 1e-9
+
+
+@pytest.mark.parametrize("nx,ny", [(256, 256), (200, 136), (97, 75), (130, 66), (8, 8), (3, 5)])
+def test_vertical_phi123_matches_oracle(ctx, nx, ny):
+    prm, h = diffadv_setup(nx, ny, cfl=50.0)
+    c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
+    v = np.random.default_rng(nx * 1000 + ny).standard_normal((ny, nx))
+    outs = [dev(np.zeros((ny, nx))) for _ in range(3)]
+    say("phi123", nx, ny)
+    r = ctx.phi_leja(_op(prm), dev(v), outs, [1, 2, 3], h, c, g, rtol=1e-8, max_iters=200)
+    assert r.status == B.LX_OK
+    spec = [(1, 1.0, 1.0), (2, 1.0, 1.0), (3, 1.0, 1.0)]
+    oracle_parity([host(o) for o in outs], r.iters,
+                  lambda f: leja_phi(_A(prm), v, spec, h, c, g, 1e-8, 0.0, 200, f), PARITY)
+
+
+def test_vertical_outputs_equal_single_runs_bitwise(ctx):
+    prm, h = diffadv_setup(192, 160)
+    c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
+    v = dev(np.random.default_rng(3).standard_normal((160, 192)))
+    outs = [dev(np.zeros((160, 192))) for _ in range(3)]
+    say("vertical vs single")
+    r = ctx.phi_leja(_op(prm), v, outs, [1, 2, 3], h, c, g, rtol=1e-8, max_iters=200)
+    for k, l in enumerate([1, 2, 3]):
+        o = dev(np.zeros((160, 192)))
+        rk = ctx.phi_leja(_op(prm), v, [o], [l], h, c, g, rtol=1e-8, max_iters=200)
+        assert rk.iters[0] == r.iters[k]
+        assert np.array_equal(host(o), host(outs[k]))
+
+
+def test_alpha_sigma_and_negative_velocity(ctx):
+    prm, h = diffadv_setup(144, 96, D=0.3, vx=-20.0, vy=35.0, cfl=20.0)
+    c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
+    v = np.random.default_rng(9).standard_normal((96, 144))
+    outs = [dev(np.zeros((96, 144))) for _ in range(2)]
+    spec = [(1, 0.75, 0.75), (0, 0.5, -2.0)]
+    say("alpha sigma")
+    r = ctx.phi_leja(_op(prm), dev(v), outs, [1, 0], h, c, g, alphas=[0.75, 0.5], sigmas=[0.75, -2.0],
+                     rtol=1e-9, atol=1e-12, max_iters=200)
+    oracle_parity([host(o) for o in outs], r.iters,
+                  lambda f: leja_phi(_A(prm), v, spec, h, c, g, 1e-9, 1e-12, 200, f), PARITY)
+
+
+def test_phi123_1024_squared_workload(ctx):
+    p, v = W.config2(n=1024)
+    op = B.make_operator(p)
+    x0 = W.start_vector(p.n)
+    say("1024^2 phi123 workload")
+    rho, c, g = ctx.spectrum(op, x0=dev(x0), iters=20)
+    rho_o, _ = power_iteration(_A(dict(D=p.D, vx=p.vx, vy=p.vy, dx=p.dx, dy=p.dy)), x0, 20)
+    assert abs(rho - rho_o) <= 1e-12 * rho_o
+    outs = [dev(np.zeros_like(v)) for _ in range(3)]
+    r = ctx.phi_leja(op, dev(v), outs, [1, 2, 3], p.h, c, g, rtol=1e-8, max_iters=200)
+    assert r.status == B.LX_OK
+    A = _A(dict(D=p.D, vx=p.vx, vy=p.vy, dx=p.dx, dy=p.dy))
+    spec = [(1, 1.0, 1.0), (2, 1.0, 1.0), (3, 1.0, 1.0)]
+    oracle_parity([host(o) for o in outs], r.iters,
+                  lambda f: leja_phi(A, v, spec, p.h, c, g, 1e-8, 0.0, 200, f), PARITY)
+
+
+# ---------------------------------------------------------------------------
+# Burgers Jacobian and EXPRB42
+# ---------------------------------------------------------------------------
+
+def test_burgers_jacobian_phi_matches_oracle(ctx):
+    n = 160
+    u = W.fourier_modes(n, seed=3)
+    nu = 1e-3
+    h = 10.0 * W.burgers_cfl_step(nu, float(np.max(np.abs(u))), 1 / n, 1 / n)
+    op = B.make_operator(kind=B.LX_OP_BURGERS2D, n=n, nu=nu)
+    x0 = np.random.default_rng(7).standard_normal((n, n))
+    say("burgers phi", n)
+    rho, c, g = ctx.spectrum(op, u=dev(u), x0=dev(x0), iters=20)
+    v = np.random.default_rng(8).standard_normal((n, n))
+    outs = [dev(np.zeros((n, n))) for _ in range(3)]
+    r = ctx.phi_leja(op, dev(v), outs, [1, 1, 3], h, c, g, u=dev(u), alphas=[0.75, 1.0, 1.0],
+                     sigmas=[0.75, 1.0, 32 / 9], rtol=1e-8, max_iters=200)
+    assert r.status == B.LX_OK
+    J = lambda w: burgers_J(u, w, nu, 1 / n, 1 / n)
+    spec = [(1, 0.75, 0.75), (1, 1.0, 1.0), (3, 1.0, 32 / 9)]
+    oracle_parity([host(o) for o in outs], r.iters,
+                  lambda f: leja_phi(J, v, spec, h, c, g, 1e-8, 0.0, 200, f), PARITY)
+
+
+@pytest.mark.parametrize("n", [128, 250])
+def test_exprb42_step_matches_oracle(ctx, n):
+    p, u0 = W.config3(n=n)
+    op = B.make_operator(p)
+    x0 = np.random.default_rng(11).standard_normal((n, n))
+    say("exprb42", n)
+    rho, c, g = ctx.spectrum(op, u=dev(u0), x0=dev(x0), iters=20)
+    out = dev(np.zeros_like(u0))
+    r = ctx.exprb_step(op, dev(u0), out, p.h, c, g, rtol=1e-8, max_iters=200)
+    assert r.status == B.LX_OK
+    ref = exprb42_step(u0, p.nu, p.dx, p.dy, p.h, c, g, 1e-8, 0.0, 200)
+    assert ref.status == "ok"
+    if list(ref.iters) == list(r.iters):
+        assert rel(host(out), ref.u_next) <= PARITY
+    else:
+        say("stop decision differs", ref.iters, r.iters)
+        # the step's update differs by at most tolerance-sized terms
+        assert rel(host(out) - u0, ref.u_next - u0) <= 1e-7
+
+
+# ---------------------------------------------------------------------------
+# FP32 sweeps
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("switch", [1e4, 0.0])
+def test_fp32_sweeps_against_fp64_oracle(ctx, switch):
+    prm, h = diffadv_setup(256, 192)
+    c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
+    v = np.random.default_rng(21).standard_normal((192, 256))
+    outs = [dev(np.zeros((192, 256))) for _ in range(3)]
+    say("fp32 sweeps", switch)
+    r = ctx.phi_leja(_op(prm, prec=B.LX_FP32_SWEEP), dev(v), outs, [1, 2, 3], h, c, g, rtol=1e-8,
+                     max_iters=200, fp32_switch=switch)
+    assert r.status == B.LX_OK
+    assert r.stats["n_fp32"] > 0
+    ref = leja_phi(_A(prm), v, [(1, 1.0, 1.0), (2, 1.0, 1.0), (3, 1.0, 1.0)], h, c, g, 1e-8, 0.0, 200)
+    errs = [rel(host(o), q) for o, q in zip(outs, ref.p)]
+    say("fp32 sweep errors vs fp64 oracle", errs, "sweeps", r.stats["n_apply"], "fp32", r.stats["n_fp32"])
+    if switch > 0:
+        assert max(errs) <= 1e-8
+    else:
+        assert max(errs) <= 1e-5
+
+
+def test_fp32_exprb42_against_fp64_oracle(ctx):
+    n = 192
+    p, u0 = W.config3(n=n)
+    op = B.make_operator(p)
+    op32 = B.make_operator(p)
+    op32.prec = B.LX_FP32_SWEEP
+    x0 = np.random.default_rng(12).standard_normal((n, n))
+    rho, c, g = ctx.spectrum(op, u=dev(u0), x0=dev(x0), iters=20)
+    out = dev(np.zeros_like(u0))
+    say("fp32 exprb42", n)
+    r = ctx.exprb_step(op32, dev(u0), out, p.h, c, g, rtol=1e-8, max_iters=200)
+    assert r.status == B.LX_OK and r.stats["n_fp32"] > 0
+    ref = exprb42_step(u0, p.nu, p.dx, p.dy, p.h, c, g, 1e-8, 0.0, 200)
+    err = rel(host(out) - u0, ref.u_next - u0)
+    say("fp32 exprb42 error of the update", err)
+    assert err <= 1e-7
+
+
+# ---------------------------------------------------------------------------
+# edge cases and error paths
+# ---------------------------------------------------------------------------
+
+def test_zero_input_converges_in_one_sweep(ctx):
+    prm, h = diffadv_setup(64, 64)
+    c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
+    out = dev(np.full((64, 64), 7.0))
+    r = ctx.phi_leja(_op(prm), dev(np.zeros((64, 64))), [out], [1], h, c, g, rtol=1e-8)
+    assert r.status == B.LX_OK and r.iters == [1]
+    assert not np.any(host(out))
+
+
+def test_max_iters_gives_notconv_with_last_polynomial(ctx):
+    prm, h = diffadv_setup(96, 64)
+    c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
+    v = np.random.default_rng(4).standard_normal((64, 96))
+    out = dev(np.zeros((64, 96)))
+    say("notconv")
+    r = ctx.phi_leja(_op(prm), dev(v), [out], [0], h, c, g, rtol=1e-12, max_iters=5)
+    assert r.status == B.LX_ENOTCONV and r.iters == [5]
+    ref = leja_phi(_A(prm), v, [(0, 1.0, 1.0)], h, c, g, 1e-12, 0.0, 5)
+    assert ref.status == "notconv"
+    assert rel(host(out), ref.p[0]) <= PARITY
+
+
+def test_nonfinite_input_is_reported(ctx):
+    prm, h = diffadv_setup(64, 64)
+    c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
+    v = np.ones((64, 64))
+    v[10, 11] = np.nan
+    out = dev(np.zeros((64, 64)))
+    r = ctx.phi_leja(_op(prm), dev(v), [out], [0], h, c, g, raise_on_error=False)
+    assert r.status == B.LX_ENONFINITE
+
+
+def test_invalid_arguments_are_rejected(ctx):
+    prm, h = diffadv_setup(64, 64)
+    c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
+    v = dev(np.ones((64, 64)))
+    o = dev(np.zeros((64, 64)))
+    bad = [dict(c=1.0), dict(gamma=0.0), dict(h=-1.0)]
+    for kw in bad:
+        args = dict(h=h, c=c, gamma=g)
+        args.update(kw)
+        r = ctx.phi_leja(_op(prm), v, [o], [0], args["h"], args["c"], args["gamma"], raise_on_error=False)
+        assert r.status == B.LX_EINVAL, kw
+    assert ctx.phi_leja(_op(prm), v, [v], [0], h, c, g, raise_on_error=False).status == B.LX_EINVAL
+    assert ctx.phi_leja(_op(prm), v, [o, o], [0, 1], h, c, g, raise_on_error=False).status == B.LX_EINVAL
+    assert ctx.phi_leja(_op(prm), v, [o], [9], h, c, g, raise_on_error=False).status == B.LX_EINVAL
+    assert ctx.phi_leja(_op(prm), v, [o], [0], h, c, g, max_iters=0, raise_on_error=False).status == B.LX_EINVAL
+    big = B.make_operator(kind=B.LX_OP_DIFFADV2D, n=2048, D=1.0)
+    assert ctx.phi_leja(big, v, [o], [0], h, c, g, raise_on_error=False).status == B.LX_EINVAL
+    burg = B.make_operator(kind=B.LX_OP_BURGERS2D, n=64, nu=1e-3)
+    assert ctx.phi_leja(burg, v, [o], [0], h, c, g, raise_on_error=False).status == B.LX_EINVAL
+    assert ctx.exprb_step(_op(prm), v, o, h, c, g, raise_on_error=False).status == B.LX_EINVAL
+    assert "c" in ctx.last_error() or ctx.last_error()
+
+
+def test_repeat_calls_are_bitwise_deterministic(ctx):
+    prm, h = diffadv_setup(512, 384)
+    c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
+    v = dev(np.random.default_rng(13).standard_normal((384, 512)))
+    a = [dev(np.zeros((384, 512))) for _ in range(2)]
+    b = [dev(np.zeros((384, 512))) for _ in range(2)]
+    say("determinism")
+    ra = ctx.phi_leja(_op(prm), v, a, [0, 2], h, c, g, rtol=1e-8)
+    rb = ctx.phi_leja(_op(prm), v, b, [0, 2], h, c, g, rtol=1e-8)
+    assert ra.iters == rb.iters and ra.err == rb.err
+    for x, y in zip(a, b):
+        assert np.array_equal(host(x), host(y))
