@@ -200,6 +200,37 @@ lx_status lx_exprb_step(lx_ctx* ctx, const lx_operator* op, int scheme,
                         double c, double gamma, const lx_leja_opts* o,
                         int* iters);
 
+/* ---- launch shapes and measurement ------------------------------------ */
+
+/* Times every candidate launch shape of the fused Leja sweep for this
+ * operator, grid, output count K and precision on the context's stream
+ * (sweeps timed sweeps per candidate, after two warm-up sweeps, on scratch
+ * vectors the call allocates and frees) and keeps the fastest: later
+ * lx_spectrum / lx_phi_leja / lx_exprb_step calls with the same
+ * (kind, nx, ny, K, prec) use it.  When the environment variable
+ * LX_TUNE_CACHE names a file, the winner is appended to it as one JSON
+ * object per line, and lx_create loads the file's entries.
+ * report: host buffer of report_len chars, or NULL; receives one line per
+ * candidate: "tx ty ry vec workgroups microseconds_per_sweep".
+ * Errors: LX_EINVAL (op invalid, K out of range, sweeps outside 1..200),
+ * LX_ENOMEM. */
+lx_status lx_tune(lx_ctx* ctx, const lx_operator* op, int K, int sweeps, char* report, size_t report_len);
+
+/* Forces the launch shape of later sweeps: tx lanes along x times ty
+ * thread-rows (tx * ty = 256), each lane owning vec (1 or 2) columns and
+ * marching ry (1, 2, 4 or 8) rows; nb workgroups loop over the tiles
+ * (0 = one workgroup per tile).  tx = 0 restores the automatic choice
+ * (tuned entry, else the built-in rule).  vec = 2 needs an even nx and
+ * 16-byte aligned vectors; otherwise vec 1 is used. */
+lx_status lx_set_tile(lx_ctx* ctx, int tx, int ty, int ry, int vec, int nb);
+
+/* Practical HBM bandwidth of plain streaming HIP kernels, the calibration
+ * of Sec. 3: kind 0 copies y = x (16 bytes per element), kind 1 computes
+ * z = a x + b y (24 bytes per element).  n FP64 elements (even, >= 2),
+ * reps timed repetitions after one warm-up, on vectors the call allocates
+ * and frees.  gbs: host output, bytes moved / time in GB/s. */
+lx_status lx_bandwidth_probe(lx_ctx* ctx, int kind, size_t n, int reps, double* gbs);
+
 /* ---- host-only planner (no device needed) ------------------------------ */
 
 /* First M (1 .. LX_MAX_ITERS+1) Leja points of [-2, 2] (Sec. 2.1): xi_0 = 2,

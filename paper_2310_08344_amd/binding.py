@@ -86,6 +86,12 @@ def _signatures(lib: C.CDLL) -> None:
     lib.lx_exprb_step.argtypes = [_P, C.POINTER(Operator), _I, _P, _P, _D, _D, _D,
                                   C.POINTER(LejaOpts), C.POINTER(_I)]
     lib.lx_exprb_step.restype = _I
+    lib.lx_tune.argtypes = [_P, C.POINTER(Operator), _I, _I, C.c_char_p, C.c_size_t]
+    lib.lx_tune.restype = _I
+    lib.lx_set_tile.argtypes = [_P, _I, _I, _I, _I, _I]
+    lib.lx_set_tile.restype = _I
+    lib.lx_bandwidth_probe.argtypes = [_P, _I, C.c_size_t, _I, C.POINTER(_D)]
+    lib.lx_bandwidth_probe.restype = _I
     lib.lx_leja_points.argtypes = [_I, C.POINTER(_D)]
     lib.lx_leja_points.restype = _I
     lib.lx_phi_scalar.argtypes = [_I, _D]
@@ -96,6 +102,7 @@ def _signatures(lib: C.CDLL) -> None:
 
 EXPORTED = ["lx_create", "lx_destroy", "lx_set_stream", "lx_set_timing", "lx_last_error",
             "lx_status_string", "lx_get_stats", "lx_spectrum", "lx_phi_leja", "lx_exprb_step",
+            "lx_tune", "lx_set_tile", "lx_bandwidth_probe",
             "lx_leja_points", "lx_phi_scalar", "lx_newton_coeffs"]
 
 
@@ -184,6 +191,26 @@ class Context:
         s = Stats()
         self._check(self.lib.c.lx_get_stats(self._h, C.byref(s)))
         return s.as_dict()
+
+    def tune(self, op: Operator, K: int = 1, sweeps: int = 10) -> list:
+        """Times the candidate launch shapes (lx_tune); returns
+        [(tx, ty, ry, vec, workgroups, microseconds per sweep), ...]."""
+        buf = C.create_string_buffer(8192)
+        self._check(self.lib.c.lx_tune(self._h, C.byref(op), int(K), int(sweeps), buf, C.c_size_t(8192)))
+        rows = []
+        for line in buf.value.decode().splitlines():
+            tx, ty, ry, vec, nb, us = line.split()
+            rows.append((int(tx), int(ty), int(ry), int(vec), int(nb), float(us)))
+        return rows
+
+    def set_tile(self, tx=0, ty=0, ry=0, vec=0, nb=0) -> None:
+        self._check(self.lib.c.lx_set_tile(self._h, int(tx), int(ty), int(ry), int(vec), int(nb)))
+
+    def bandwidth_probe(self, kind: int, n: int, reps: int = 20) -> float:
+        """GB/s of the copy (kind 0) or z = ax + by (kind 1) probe."""
+        g = _D()
+        self._check(self.lib.c.lx_bandwidth_probe(self._h, int(kind), C.c_size_t(int(n)), int(reps), C.byref(g)))
+        return g.value
 
     def spectrum(self, op: Operator, u=None, x0=None, iters: int = 20, safety: float = 1.05,
                  raise_on_error: bool = True):

@@ -4,19 +4,23 @@
 //     y_{m+1} = ((A - c)/gamma - xi_m) y_m           (stencil, shifted centre)
 //     p_k    += d^{(k)}_{m+1} y_{m+1}                (every unconverged output)
 //     partial sums of |y_{m+1}|^2 and |p_k|^2         (norms of the stop rule)
-// The last workgroup of a sweep to finish adds the per-workgroup partials in
-// a fixed order, applies the stop rule of Sec. 2.2 and writes the loop state
-// that the next sweep reads, so the loop never waits for the host.
+// Sweeps never synchronise their workgroups.  Each workgroup writes its
+// partial sums with plain stores; at the start of the next sweep every
+// workgroup adds all of them in the same fixed order and so takes the same
+// stop decision (Sec. 2.2) on its own.  The kernel boundary is the only
+// grid-wide barrier: on MI355X the L2 caches of the 8 XCDs are not coherent
+// with each other, and a device-scope release inside a sweep (needed by a
+// last-workgroup reduction) costs an L2 write-back per workgroup.
 //
 // Memory layout: grids are row-major [ny][nx] (x fastest).  A thread owns
 // `V` consecutive columns (one 16-byte FP64 load for V = 2) and marches down
 // RY rows keeping the rows above, at and below in registers, so each row of
-// y is fetched once per sweep; the x-neighbours of the pair come from the
+// y is fetched once per tile; the x-neighbours of the pair come from the
 // same cache lines through L1.  Workgroups are 2-D (tx lanes along x, ty
-// thread-rows), 256 threads.  Consecutive workgroup ids go round-robin to
-// the 8 XCDs; tiles are renumbered so that each XCD walks a contiguous band
-// of rows and the halo rows of a tile were fetched by its own XCD shortly
-// before.
+// thread-rows), 256 threads, and loop over tiles.  Consecutive workgroup
+// ids go round-robin to the 8 XCDs; the tiles are split into 8 contiguous
+// bands, one per XCD, so that a tile's halo rows were fetched by its own
+// XCD shortly before.
 #include <hip/hip_runtime.h>
 
 #include "lx_device.h"
@@ -31,10 +35,21 @@ __device__ __forceinline__ int wrap(int r, int n) {
     return r;
 }
 
-__device__ __forceinline__ int tile_of_block(int b, int nb) {
-    const int per = nb >> 3;
-    if (per == 0 || b >= (per << 3)) return b;
-    return (b & 7) * per + (b >> 3);
+// Calls f(tile) for the tiles of this workgroup.  With nb a multiple of 8,
+// workgroup b runs on XCD b % 8 and takes every (nb/8)-th tile of that XCD's
+// contiguous band, so that concurrently running workgroups of one XCD work
+// on neighbouring tiles.
+template <typename F>
+__device__ __forceinline__ void for_each_tile(int T, int nb, F&& f) {
+    const int b = static_cast<int>(blockIdx.x);
+    if (nb >= 8 && (nb & 7) == 0) {
+        const int x = b & 7, j = b >> 3, nbx = nb >> 3;
+        const int lo = static_cast<int>((static_cast<long>(x) * T) >> 3);
+        const int hi = static_cast<int>((static_cast<long>(x + 1) * T) >> 3);
+        for (int t = lo + j; t < hi; t += nbx) f(t);
+    } else {
+        for (int t = b; t < T; t += nb) f(t);
+    }
 }
 
 __device__ __forceinline__ int flat_tid() { return threadIdx.x + threadIdx.y * blockDim.x; }
@@ -67,12 +82,13 @@ __device__ __forceinline__ void stv(T* __restrict__ p, const T (&o)[V]) {
     }
 }
 
-// Sum NV values over the workgroup in a fixed order (butterfly within each
-// 64-lane wavefront, then wavefronts in index order); the result is valid
-// in thread 0 only.
+// Sums NV values over the workgroup in a fixed order (butterfly within each
+// 64-lane wavefront, then wavefronts in index order); every thread receives
+// the result.
 template <int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV]) {
     __shared__ double red[NV][kBlockThreads / 64];
+    __shared__ double out[NV];
     const int tid = flat_tid();
     const int lane = tid & 63, wid = tid >> 6;
 #pragma unroll
@@ -87,48 +103,30 @@ __device__ __forceinline__ void block_sum(double (&v)[NV]) {
         for (int q = 0; q < NV; ++q) red[q][wid] = v[q];
     }
     __syncthreads();
-    if (tid == 0) {
+    if (tid < NV) {
         const int nw = (block_threads() + 63) >> 6;
-#pragma unroll
-        for (int q = 0; q < NV; ++q) {
-            double s = 0.0;
-            for (int w = 0; w < nw; ++w) s += red[q][w];
-            v[q] = s;
-        }
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += red[tid][w];
+        out[tid] = s;
     }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = out[q];
     __syncthreads();
 }
 
-// Publishes this workgroup's sums and reports whether it was the last of the
-// grid to arrive; the last one then holds, in thread 0, the grid totals
-// added in workgroup-index order (independent of arrival order).
+// Adds the nb partial records of NV values written by the previous launch,
+// in workgroup-index order per lane and then block_sum's fixed tree: every
+// workgroup of the grid obtains bitwise the same totals.
 template <int NV>
-__device__ __forceinline__ bool grid_sum_last(double (&v)[NV], double* __restrict__ partials,
-                                              unsigned* counter) {
-    __shared__ int s_last;
-    block_sum<NV>(v);
-    const int tid = flat_tid();
-    if (tid == 0) {
+__device__ __forceinline__ void sum_partials(const double* __restrict__ P, int nb, double (&tot)[NV]) {
 #pragma unroll
-        for (int q = 0; q < NV; ++q) partials[blockIdx.x * NV + q] = v[q];
-        __threadfence();                                  // release the partials
-        const unsigned prev = atomicAdd(counter, 1u);
-        s_last = (prev == gridDim.x - 1) ? 1 : 0;
+    for (int q = 0; q < NV; ++q) tot[q] = 0.0;
+    for (int b = flat_tid(); b < nb; b += block_threads()) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) tot[q] += P[b * NV + q];
     }
-    __syncthreads();
-    if (!s_last) return false;
-    __threadfence();                                      // acquire the others' partials
-    double acc[NV];
-#pragma unroll
-    for (int q = 0; q < NV; ++q) acc[q] = 0.0;
-    for (int b = tid; b < static_cast<int>(gridDim.x); b += block_threads()) {
-#pragma unroll
-        for (int q = 0; q < NV; ++q) acc[q] += __builtin_nontemporal_load(&partials[b * NV + q]);
-    }
-    block_sum<NV>(acc);
-#pragma unroll
-    for (int q = 0; q < NV; ++q) v[q] = acc[q];
-    return true;
+    block_sum<NV>(tot);
 }
 
 // ---------------------------------------------------------------------------
@@ -137,9 +135,8 @@ __device__ __forceinline__ bool grid_sum_last(double (&v)[NV], double* __restric
 
 template <int OP, int K, int RY, int V, typename TI, typename TO, typename AT>
 __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int m, const int (&act)[K],
-                                           double& sy, double (&sp)[K]) {
+                                           double& sy, double (&sp)[K], const int tile) {
     const int nx = a.nx, ny = a.ny;
-    const int tile = tile_of_block(blockIdx.x, gridDim.x);
     const int tile_x = tile % a.tiles_x, tile_y = tile / a.tiles_x;
     const int col = (tile_x * static_cast<int>(blockDim.x) + static_cast<int>(threadIdx.x)) * V;
     const bool colok = col < nx;
@@ -156,6 +153,15 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int m, cons
     }
     TO* __restrict__ yout = static_cast<TO*>(a.ybuf[m & 1]);
 
+    double* __restrict__ pk[K];
+    const double* __restrict__ bk[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        pk[k] = a.p[k];
+        bk[k] = a.base[k];
+    }
+    const double* __restrict__ uu = a.u;
+    const float* __restrict__ uu32 = a.u32;
     const double xim = a.xi[m];
     double dn1[K], d0[K];
 #pragma unroll
@@ -170,11 +176,11 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int m, cons
     ldv<V>(yin + static_cast<long>(wrap(row0, ny)) * nx + c0, cen);
     if constexpr (OP == kOpBurgersJ) {
         if constexpr (sizeof(AT) == sizeof(double)) {
-            ldv<V>(a.u + static_cast<long>(wrap(row0 - 1, ny)) * nx + c0, uup);
-            ldv<V>(a.u + static_cast<long>(wrap(row0, ny)) * nx + c0, ucen);
+            ldv<V>(uu + static_cast<long>(wrap(row0 - 1, ny)) * nx + c0, uup);
+            ldv<V>(uu + static_cast<long>(wrap(row0, ny)) * nx + c0, ucen);
         } else {
-            ldv<V>(a.u32 + static_cast<long>(wrap(row0 - 1, ny)) * nx + c0, uup);
-            ldv<V>(a.u32 + static_cast<long>(wrap(row0, ny)) * nx + c0, ucen);
+            ldv<V>(uu32 + static_cast<long>(wrap(row0 - 1, ny)) * nx + c0, uup);
+            ldv<V>(uu32 + static_cast<long>(wrap(row0, ny)) * nx + c0, ucen);
         }
     }
 
@@ -204,13 +210,13 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int m, cons
             const AT kc = static_cast<AT>(a.kC - xim);
             AT ul, ur;
             if constexpr (sizeof(AT) == sizeof(double)) {
-                ldv<V>(a.u + rn * nx + c0, udn);
-                ul = a.u[rw * nx + cl];
-                ur = a.u[rw * nx + cr];
+                ldv<V>(uu + rn * nx + c0, udn);
+                ul = uu[rw * nx + cl];
+                ur = uu[rw * nx + cr];
             } else {
-                ldv<V>(a.u32 + rn * nx + c0, udn);
-                ul = a.u32[rw * nx + cl];
-                ur = a.u32[rw * nx + cr];
+                ldv<V>(uu32 + rn * nx + c0, udn);
+                ul = uu32[rw * nx + cl];
+                ur = uu32[rw * nx + cr];
             }
             if constexpr (V == 2) {
                 o[0] = kx * (cen[1] + left) + ky * (dn[0] + up[0]) - gx * (ucen[1] * cen[1] - ul * left) -
@@ -243,19 +249,19 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int m, cons
                 // p_0 = d_0 y_0 (+ optional base); y_0 = v is the centre row
 #pragma unroll
                 for (int i = 0; i < V; ++i) pv[i] = d0[k] * static_cast<double>(cen[i]);
-                if (a.base[k] != nullptr) {
+                if (bk[k] != nullptr) {
                     double bv[V];
-                    ldv<V>(a.base[k] + idx, bv);
+                    ldv<V>(bk[k] + idx, bv);
 #pragma unroll
                     for (int i = 0; i < V; ++i) pv[i] += bv[i];
                 }
             } else {
-                ldv<V>(a.p[k] + idx, pv);
+                ldv<V>(pk[k] + idx, pv);
             }
 #pragma unroll
             for (int i = 0; i < V; ++i) pv[i] = fma(dn1[k], od[i], pv[i]);
             if (ok) {
-                stv<V>(a.p[k] + idx, pv);
+                stv<V>(pk[k] + idx, pv);
 #pragma unroll
                 for (int i = 0; i < V; ++i) sp[k] += pv[i] * pv[i];
             }
@@ -272,93 +278,119 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int m, cons
     }
 }
 
-template <int OP, int K, int RY, int V, bool FP32>
-__global__ __launch_bounds__(kBlockThreads) void leja_sweep(SweepArgs a) {
-    LejaState* __restrict__ st = a.st;
-    if (st->done) return;
-    const int m = st->iter;
-    int act[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) act[k] = st->active[k];
-    double sy = 0.0, sp[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) sp[k] = 0.0;
-    int wrote32 = 0;
-    if constexpr (FP32) {
-        const int in32 = st->in32, out32 = st->out32;
-        wrote32 = out32;
-        if (in32) {
-            sweep_tile<OP, K, RY, V, float, float, float>(a, m, act, sy, sp);
-        } else if (out32) {
-            sweep_tile<OP, K, RY, V, double, float, double>(a, m, act, sy, sp);
-        } else {
-            sweep_tile<OP, K, RY, V, double, double, double>(a, m, act, sy, sp);
-        }
-    } else {
-        sweep_tile<OP, K, RY, V, double, double, double>(a, m, act, sy, sp);
-    }
-
-    double v[1 + K];
-    v[0] = sy;
-#pragma unroll
-    for (int k = 0; k < K; ++k) v[1 + k] = sp[k];
-    if (!grid_sum_last<1 + K>(v, a.partials, &st->arrive)) return;
-    if (flat_tid() != 0) return;
-
-    // stop rule (Sec. 2.2): |d_{m+1}| ||y_{m+1}|| <= rtol ||p|| + atol, rms norms
-    const double ynorm = sqrt(v[0]) * a.inv_sqrtN;
+// Stop rule (Sec. 2.2) after sweep m-1, from the grid totals of its partial
+// sums: the state entering sweep m.  tot = {sum y_m^2, sum p_k^2 ...}.
+template <int K, bool FP32>
+__device__ __forceinline__ SweepState decide(const SweepArgs& a, const LoopCtl& ctl, const SweepState& prev,
+                                             const int m, const double (&tot)[1 + K]) {
+    SweepState nx = prev;
+    nx.iter = m;
+    nx.n_fp32 = prev.n_fp32 + prev.out32;
+    nx.in32 = prev.out32;
+    const double ynorm = sqrt(tot[0]) * a.inv_sqrtN;
+    nx.ynorm = ynorm;
     bool nonfinite = !isfinite(ynorm);
     bool any_active = false, all_small = true;
-    const double rtol = st->rtol, atol = st->atol, sw = st->fp32_switch;
+    const double rtol = ctl.rtol, atol = ctl.atol, sw = ctl.fp32_switch;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        if (!act[k]) continue;
-        const double pn = sqrt(v[1 + k]) * a.inv_sqrtN;
-        const double e = fabs(a.coef[k * a.ld + m + 1]) * ynorm;
+        if (!prev.active[k]) continue;
+        const double pn = sqrt(tot[1 + k]) * a.inv_sqrtN;
+        const double e = fabs(a.coef[k * a.ld + m]) * ynorm;
         const double thr = rtol * pn + atol;
-        st->err[k] = e;
-        st->pnorm[k] = pn;
+        nx.err[k] = e;
+        nx.pnorm[k] = pn;
         if (!isfinite(pn) || !isfinite(e)) {
             nonfinite = true;
-            st->active[k] = 0;
-            st->iters[k] = m + 1;
+            nx.active[k] = 0;
+            nx.iters[k] = m;
         } else if (e <= thr) {
-            st->active[k] = 0;
-            st->iters[k] = m + 1;
+            nx.active[k] = 0;
+            nx.iters[k] = m;
         } else {
             any_active = true;
             if (!(e <= sw * thr)) all_small = false;
         }
     }
-    st->ynorm = ynorm;
-    st->iter = m + 1;
-    st->in32 = wrote32;
-    st->n_fp32 += wrote32;
-    if (FP32 && !wrote32 && any_active && all_small && sw >= 0.0) st->out32 = 1;
+    if (FP32 && !prev.out32 && any_active && all_small && sw >= 0.0) nx.out32 = 1;
     if (nonfinite) {
-        st->status = 4;  // LX_ENONFINITE
-        st->done = 1;
+        nx.status = 4;  // LX_ENONFINITE
+        nx.done = 1;
     } else if (!any_active) {
-        st->status = 0;
-        st->done = 1;
-    } else if (m + 1 >= st->max_iters) {
-        st->status = 3;  // LX_ENOTCONV
-        st->done = 1;
+        nx.status = 0;
+        nx.done = 1;
+    } else if (m >= ctl.max_iters) {
+        nx.status = 3;  // LX_ENOTCONV
+        nx.done = 1;
     }
-    st->arrive = 0u;
-    __threadfence();
+    return nx;
+}
+
+template <int OP, int K, int RY, int V, bool FP32>
+__global__ __launch_bounds__(kBlockThreads) void leja_sweep(SweepArgs a, const int m) {
+    LoopCtl* __restrict__ ctl = a.ctl;
+    if (ctl->slot[2].done) return;
+    constexpr int NV = 1 + K;
+    __shared__ SweepState s_cur;
+    const int tid = flat_tid();
+    if (m == 0) {
+        if (tid == 0) s_cur = ctl->slot[0];
+    } else {
+        double tot[NV];
+        sum_partials<NV>(a.partials + static_cast<long>((m - 1) & 1) * a.nb * NV, a.nb, tot);
+        if (tid == 0) {
+            const SweepState nxt = decide<K, FP32>(a, *ctl, ctl->slot[(m - 1) & 1], m, tot);
+            s_cur = nxt;
+            if (blockIdx.x == 0) {
+                ctl->slot[m & 1] = nxt;
+                if (nxt.done) ctl->slot[2] = nxt;
+            }
+        }
+    }
+    __syncthreads();
+    if (s_cur.done) return;
+
+    int act[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) act[k] = s_cur.active[k];
+    double sy = 0.0, sp[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) sp[k] = 0.0;
+    const int T = a.tiles_x * a.tiles_y;
+    if constexpr (FP32) {
+        if (s_cur.in32) {
+            for_each_tile(T, a.nb, [&](int t) { sweep_tile<OP, K, RY, V, float, float, float>(a, m, act, sy, sp, t); });
+        } else if (s_cur.out32) {
+            for_each_tile(T, a.nb,
+                          [&](int t) { sweep_tile<OP, K, RY, V, double, float, double>(a, m, act, sy, sp, t); });
+        } else {
+            for_each_tile(T, a.nb,
+                          [&](int t) { sweep_tile<OP, K, RY, V, double, double, double>(a, m, act, sy, sp, t); });
+        }
+    } else {
+        for_each_tile(T, a.nb,
+                      [&](int t) { sweep_tile<OP, K, RY, V, double, double, double>(a, m, act, sy, sp, t); });
+    }
+    double v[NV];
+    v[0] = sy;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[1 + k] = sp[k];
+    block_sum<NV>(v);
+    if (tid == 0) {
+        double* __restrict__ P = a.partials + static_cast<long>(m & 1) * a.nb * NV + blockIdx.x * NV;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) P[q] = v[q];
+    }
 }
 
 // ---------------------------------------------------------------------------
-// power iteration sweep: w_out = (A w_in) / ||w_in||, partial sums of w_out^2
+// power iteration: w_{k+1} = (A w_k) / ||w_k||; ||w_k|| comes from the
+// partial sums of the previous launch (the start-vector norm for k = 0)
 // ---------------------------------------------------------------------------
 
 template <int OP, int RY, int V>
-__global__ __launch_bounds__(kBlockThreads) void power_sweep(PowerArgs a) {
-    LejaState* __restrict__ st = a.st;
-    const double s = st->scale;
+__device__ __forceinline__ void power_tile(const PowerArgs& a, const double s, double& acc, const int tile) {
     const int nx = a.nx, ny = a.ny;
-    const int tile = tile_of_block(blockIdx.x, gridDim.x);
     const int tile_x = tile % a.tiles_x, tile_y = tile / a.tiles_x;
     const int col = (tile_x * static_cast<int>(blockDim.x) + static_cast<int>(threadIdx.x)) * V;
     const bool colok = col < nx;
@@ -367,15 +399,16 @@ __global__ __launch_bounds__(kBlockThreads) void power_sweep(PowerArgs a) {
     const int cr = (c0 + V >= nx) ? c0 + V - nx : c0 + V;
     const int row0 = tile_y * static_cast<int>(blockDim.y) * RY + static_cast<int>(threadIdx.y) * RY;
     const double* __restrict__ in = a.in;
+    const double* __restrict__ uu = a.u;
+    double* __restrict__ out = a.out;
 
     double up[V], cen[V], dn[V], uup[V], ucen[V], udn[V];
     ldv<V>(in + static_cast<long>(wrap(row0 - 1, ny)) * nx + c0, up);
     ldv<V>(in + static_cast<long>(wrap(row0, ny)) * nx + c0, cen);
     if constexpr (OP == kOpBurgersJ) {
-        ldv<V>(a.u + static_cast<long>(wrap(row0 - 1, ny)) * nx + c0, uup);
-        ldv<V>(a.u + static_cast<long>(wrap(row0, ny)) * nx + c0, ucen);
+        ldv<V>(uu + static_cast<long>(wrap(row0 - 1, ny)) * nx + c0, uup);
+        ldv<V>(uu + static_cast<long>(wrap(row0, ny)) * nx + c0, ucen);
     }
-    double acc = 0.0;
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
         const int row = row0 + r;
@@ -393,8 +426,8 @@ __global__ __launch_bounds__(kBlockThreads) void power_sweep(PowerArgs a) {
                 o[0] = a.cW * left + a.cE * right + a.cS * up[0] + a.cN * dn[0] + a.cC * cen[0];
             }
         } else {
-            ldv<V>(a.u + rn * nx + c0, udn);
-            const double ul = a.u[rw * nx + cl], ur = a.u[rw * nx + cr];
+            ldv<V>(uu + rn * nx + c0, udn);
+            const double ul = uu[rw * nx + cl], ur = uu[rw * nx + cr];
             const double kc = -2.0 * a.kx - 2.0 * a.ky;
             if constexpr (V == 2) {
                 o[0] = a.kx * (cen[1] + left) + a.ky * (dn[0] + up[0]) - a.gx * (ucen[1] * cen[1] - ul * left) -
@@ -409,7 +442,7 @@ __global__ __launch_bounds__(kBlockThreads) void power_sweep(PowerArgs a) {
 #pragma unroll
         for (int i = 0; i < V; ++i) o[i] *= s;
         if (ok) {
-            stv<V>(a.out + rw * nx + c0, o);
+            stv<V>(out + rw * nx + c0, o);
 #pragma unroll
             for (int i = 0; i < V; ++i) acc += o[i] * o[i];
         }
@@ -423,21 +456,23 @@ __global__ __launch_bounds__(kBlockThreads) void power_sweep(PowerArgs a) {
             }
         }
     }
-    double v[1] = {acc};
-    if (!grid_sum_last<1>(v, a.partials, &st->arrive)) return;
-    if (flat_tid() != 0) return;
-    const double nrm = sqrt(v[0]);
-    st->rho = nrm;
-    st->scale = 1.0 / nrm;
-    st->iter += 1;
-    if (!isfinite(nrm) || nrm == 0.0) st->status = 4;
-    st->arrive = 0u;
-    __threadfence();
 }
 
-// ||x|| of the start vector: st->scale = 1/||x||
-__global__ __launch_bounds__(kBlockThreads) void norm_kernel(const double* __restrict__ x, long n,
-                                                             double* partials, LejaState* st) {
+template <int OP, int RY, int V>
+__global__ __launch_bounds__(kBlockThreads) void power_sweep(PowerArgs a, const int k) {
+    double tot[1];
+    sum_partials<1>(a.partials + static_cast<long>((k - 1) & 1) * a.nb, a.nb, tot);
+    const double s = 1.0 / sqrt(tot[0]);
+    double acc = 0.0;
+    for_each_tile(a.tiles_x * a.tiles_y, a.nb, [&](int t) { power_tile<OP, RY, V>(a, s, acc, t); });
+    double v[1] = {acc};
+    block_sum<1>(v);
+    if (flat_tid() == 0) a.partials[static_cast<long>(k & 1) * a.nb + blockIdx.x] = v[0];
+}
+
+// partial sums of |x|^2 of the start vector into partials[1][*]
+__global__ __launch_bounds__(kBlockThreads) void power_norm_kernel(const double* __restrict__ x, long n,
+                                                                   double* __restrict__ partials) {
     double acc = 0.0;
     for (long i = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x; i < n;
          i += static_cast<long>(gridDim.x) * blockDim.x) {
@@ -445,13 +480,16 @@ __global__ __launch_bounds__(kBlockThreads) void norm_kernel(const double* __res
         acc += t * t;
     }
     double v[1] = {acc};
-    if (!grid_sum_last<1>(v, partials, &st->arrive)) return;
-    if (threadIdx.x != 0) return;
-    const double nrm = sqrt(v[0]);
-    st->scale = 1.0 / nrm;
-    if (!isfinite(nrm) || nrm == 0.0) st->status = 4;
-    st->arrive = 0u;
-    __threadfence();
+    block_sum<1>(v);
+    if (threadIdx.x == 0) partials[gridDim.x + blockIdx.x] = v[0];
+}
+
+// rho = ||w_iters|| from the last sweep's partial sums
+__global__ __launch_bounds__(kBlockThreads) void power_final_kernel(int nb, const double* __restrict__ P,
+                                                                    LoopCtl* ctl) {
+    double tot[1];
+    sum_partials<1>(P, nb, tot);
+    if (threadIdx.x == 0) ctl->rho = sqrt(tot[0]);
 }
 
 // splitmix64 (Steele, Lea and Flood, OOPSLA 2014): state_i = seed + (i+1) *
@@ -521,66 +559,92 @@ __global__ void burgers_remainder_kernel(const double* __restrict__ u, const dou
 }
 
 // ---------------------------------------------------------------------------
+// streaming probes: the practical-bandwidth calibration of Sec. 3 (device
+// copy and z = a x + b y)
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlockThreads) void copy_kernel(const double2* __restrict__ x,
+                                                             double2* __restrict__ y, long n2) {
+    for (long i = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x; i < n2;
+         i += static_cast<long>(gridDim.x) * blockDim.x) {
+        y[i] = x[i];
+    }
+}
+
+__global__ __launch_bounds__(kBlockThreads) void axpby_kernel(double a, const double2* __restrict__ x, double b,
+                                                              const double2* __restrict__ y,
+                                                              double2* __restrict__ z, long n2) {
+    for (long i = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x; i < n2;
+         i += static_cast<long>(gridDim.x) * blockDim.x) {
+        const double2 xv = x[i], yv = y[i];
+        double2 r;
+        r.x = a * xv.x + b * yv.x;
+        r.y = a * xv.y + b * yv.y;
+        z[i] = r;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launch dispatch
 // ---------------------------------------------------------------------------
 
 template <int OP, int K, int RY, int V>
-hipError_t launch_sweep_t(bool fp32, const Tile& t, const SweepArgs& a, hipStream_t s) {
+hipError_t launch_sweep_t(bool fp32, const Tile& t, const SweepArgs& a, int m, hipStream_t s) {
     const dim3 block(t.tx, t.ty);
-    const dim3 grid(a.tiles_x * a.tiles_y);
+    const dim3 grid(a.nb);
     if (fp32) {
-        hipLaunchKernelGGL((leja_sweep<OP, K, RY, V, true>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((leja_sweep<OP, K, RY, V, true>), grid, block, 0, s, a, m);
     } else {
-        hipLaunchKernelGGL((leja_sweep<OP, K, RY, V, false>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((leja_sweep<OP, K, RY, V, false>), grid, block, 0, s, a, m);
     }
     return hipGetLastError();
 }
 
 template <int OP, int K, int RY>
-hipError_t launch_sweep_v(bool fp32, const Tile& t, const SweepArgs& a, hipStream_t s) {
-    return t.vec == 2 ? launch_sweep_t<OP, K, RY, 2>(fp32, t, a, s) : launch_sweep_t<OP, K, RY, 1>(fp32, t, a, s);
+hipError_t launch_sweep_v(bool fp32, const Tile& t, const SweepArgs& a, int m, hipStream_t s) {
+    return t.vec == 2 ? launch_sweep_t<OP, K, RY, 2>(fp32, t, a, m, s) : launch_sweep_t<OP, K, RY, 1>(fp32, t, a, m, s);
 }
 
 template <int OP, int K>
-hipError_t launch_sweep_r(bool fp32, const Tile& t, const SweepArgs& a, hipStream_t s) {
+hipError_t launch_sweep_r(bool fp32, const Tile& t, const SweepArgs& a, int m, hipStream_t s) {
     switch (t.ry) {
-        case 1: return launch_sweep_v<OP, K, 1>(fp32, t, a, s);
-        case 2: return launch_sweep_v<OP, K, 2>(fp32, t, a, s);
-        case 4: return launch_sweep_v<OP, K, 4>(fp32, t, a, s);
-        case 8: return launch_sweep_v<OP, K, 8>(fp32, t, a, s);
+        case 1: return launch_sweep_v<OP, K, 1>(fp32, t, a, m, s);
+        case 2: return launch_sweep_v<OP, K, 2>(fp32, t, a, m, s);
+        case 4: return launch_sweep_v<OP, K, 4>(fp32, t, a, m, s);
+        case 8: return launch_sweep_v<OP, K, 8>(fp32, t, a, m, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <int OP>
-hipError_t launch_sweep_k(int K, bool fp32, const Tile& t, const SweepArgs& a, hipStream_t s) {
+hipError_t launch_sweep_k(int K, bool fp32, const Tile& t, const SweepArgs& a, int m, hipStream_t s) {
     switch (K) {
-        case 1: return launch_sweep_r<OP, 1>(fp32, t, a, s);
-        case 2: return launch_sweep_r<OP, 2>(fp32, t, a, s);
-        case 3: return launch_sweep_r<OP, 3>(fp32, t, a, s);
-        case 4: return launch_sweep_r<OP, 4>(fp32, t, a, s);
+        case 1: return launch_sweep_r<OP, 1>(fp32, t, a, m, s);
+        case 2: return launch_sweep_r<OP, 2>(fp32, t, a, m, s);
+        case 3: return launch_sweep_r<OP, 3>(fp32, t, a, m, s);
+        case 4: return launch_sweep_r<OP, 4>(fp32, t, a, m, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <int OP, int RY, int V>
-hipError_t launch_power_t(const Tile& t, const PowerArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((power_sweep<OP, RY, V>), dim3(a.tiles_x * a.tiles_y), dim3(t.tx, t.ty), 0, s, a);
+hipError_t launch_power_t(const Tile& t, const PowerArgs& a, int k, hipStream_t s) {
+    hipLaunchKernelGGL((power_sweep<OP, RY, V>), dim3(a.nb), dim3(t.tx, t.ty), 0, s, a, k);
     return hipGetLastError();
 }
 
 template <int OP, int RY>
-hipError_t launch_power_v(const Tile& t, const PowerArgs& a, hipStream_t s) {
-    return t.vec == 2 ? launch_power_t<OP, RY, 2>(t, a, s) : launch_power_t<OP, RY, 1>(t, a, s);
+hipError_t launch_power_v(const Tile& t, const PowerArgs& a, int k, hipStream_t s) {
+    return t.vec == 2 ? launch_power_t<OP, RY, 2>(t, a, k, s) : launch_power_t<OP, RY, 1>(t, a, k, s);
 }
 
 template <int OP>
-hipError_t launch_power_r(const Tile& t, const PowerArgs& a, hipStream_t s) {
+hipError_t launch_power_r(const Tile& t, const PowerArgs& a, int k, hipStream_t s) {
     switch (t.ry) {
-        case 1: return launch_power_v<OP, 1>(t, a, s);
-        case 2: return launch_power_v<OP, 2>(t, a, s);
-        case 4: return launch_power_v<OP, 4>(t, a, s);
-        case 8: return launch_power_v<OP, 8>(t, a, s);
+        case 1: return launch_power_v<OP, 1>(t, a, k, s);
+        case 2: return launch_power_v<OP, 2>(t, a, k, s);
+        case 4: return launch_power_v<OP, 4>(t, a, k, s);
+        case 8: return launch_power_v<OP, 8>(t, a, k, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -594,36 +658,50 @@ int flat_blocks(long n) {
 
 }  // namespace
 
-int num_blocks(const Tile& t, int nx, int ny) {
-    const int tx = (nx + t.cols() - 1) / t.cols();
-    const int ty = (ny + t.rows() - 1) / t.rows();
-    return tx * ty;
-}
-
-int norm_blocks(long n) { return flat_blocks(n); }
-
-hipError_t launch_leja_sweep(int op, int K, bool fp32_capable, const Tile& t, const SweepArgs& a,
+hipError_t launch_leja_sweep(int op, int K, bool fp32_capable, const Tile& t, const SweepArgs& a, int m,
                              hipStream_t s) {
-    if (t.tx * t.ty != kBlockThreads) return hipErrorInvalidValue;
-    if (op == kOpDiffAdv) return launch_sweep_k<kOpDiffAdv>(K, fp32_capable, t, a, s);
-    if (op == kOpBurgersJ) return launch_sweep_k<kOpBurgersJ>(K, fp32_capable, t, a, s);
+    if (t.tx * t.ty != kBlockThreads || a.nb < 1) return hipErrorInvalidValue;
+    if (op == kOpDiffAdv) return launch_sweep_k<kOpDiffAdv>(K, fp32_capable, t, a, m, s);
+    if (op == kOpBurgersJ) return launch_sweep_k<kOpBurgersJ>(K, fp32_capable, t, a, m, s);
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_power_sweep(int op, const Tile& t, const PowerArgs& a, hipStream_t s) {
-    if (t.tx * t.ty != kBlockThreads) return hipErrorInvalidValue;
-    if (op == kOpDiffAdv) return launch_power_r<kOpDiffAdv>(t, a, s);
-    if (op == kOpBurgersJ) return launch_power_r<kOpBurgersJ>(t, a, s);
+hipError_t launch_power_sweep(int op, const Tile& t, const PowerArgs& a, int k, hipStream_t s) {
+    if (t.tx * t.ty != kBlockThreads || a.nb < 1) return hipErrorInvalidValue;
+    if (op == kOpDiffAdv) return launch_power_r<kOpDiffAdv>(t, a, k, s);
+    if (op == kOpBurgersJ) return launch_power_r<kOpBurgersJ>(t, a, k, s);
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_norm(const double* x, long n, double* partials, LejaState* st, hipStream_t s) {
-    hipLaunchKernelGGL(norm_kernel, dim3(flat_blocks(n)), dim3(kBlockThreads), 0, s, x, n, partials, st);
+hipError_t launch_power_norm(const double* x, long n, int nb, double* partials, hipStream_t s) {
+    if (nb < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(power_norm_kernel, dim3(nb), dim3(kBlockThreads), 0, s, x, n, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_power_final(int nb, const double* partials, LoopCtl* ctl, hipStream_t s) {
+    hipLaunchKernelGGL(power_final_kernel, dim3(1), dim3(kBlockThreads), 0, s, nb, partials, ctl);
     return hipGetLastError();
 }
 
 hipError_t launch_fill_splitmix(double* x, long n, unsigned long long seed, hipStream_t s) {
     hipLaunchKernelGGL(fill_splitmix_kernel, dim3(flat_blocks(n)), dim3(kBlockThreads), 0, s, x, n, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe(int kind, const double* x, const double* y, double* z, long n, hipStream_t s) {
+    const long n2 = n / 2;
+    long blocks = (n2 + kBlockThreads - 1) / kBlockThreads;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    if (kind == 0) {
+        hipLaunchKernelGGL(copy_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kBlockThreads), 0, s,
+                           reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(z), n2);
+    } else {
+        hipLaunchKernelGGL(axpby_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kBlockThreads), 0, s, 1.5,
+                           reinterpret_cast<const double2*>(x), -0.5, reinterpret_cast<const double2*>(y),
+                           reinterpret_cast<double2*>(z), n2);
+    }
     return hipGetLastError();
 }
 

@@ -13,15 +13,19 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "lx.h"
 #include "lx_device.h"
 #include "planner.h"
 
-using lx::LejaState;
+using lx::LoopCtl;
+using lx::SweepState;
 using lx::PowerArgs;
 using lx::SweepArgs;
 using lx::Tile;
@@ -38,17 +42,21 @@ struct lx_ctx {
     double* ws[3] = {nullptr, nullptr, nullptr};  // EXPRB42 stages (allocated on first use)
     double* partials = nullptr;
     size_t partials_len = 0;
-    LejaState* st = nullptr;
+    LoopCtl* ctl = nullptr;
     double* coef = nullptr;                 // k_max * kMaxPoints
     double* xi = nullptr;                   // kMaxPoints
     int xi_uploaded = 0;
     // pinned host staging
-    LejaState* h_st = nullptr;              // [3]: initial state, two poll slots
+    LoopCtl* h_ctl = nullptr;               // initial loop control (pinned)
+    SweepState* h_poll = nullptr;           // [2]: polled final-state slots (pinned)
     double* h_coef = nullptr;
     double* h_xi = nullptr;
     hipEvent_t poll_ev[2] = {nullptr, nullptr};
     std::vector<hipEvent_t> tev;            // timing events
     lx::NewtonSeries series[LX_K_MAX];      // per-output divided differences
+    // launch shapes: forced by lx_set_tile, else tuned per (kind, nx, ny, K, prec)
+    Tile forced{0, 0, 0, 0, 0};   // tx == 0: not forced
+    std::map<std::tuple<int, int, int, int, int>, Tile> tuned;
     lx_stats stats{};
     std::string err;
 };
@@ -100,8 +108,9 @@ lx_status check_op(lx_ctx* ctx, const lx_operator* op) {
 }
 
 // Launch shape: two columns per lane when the rows allow 16-byte loads,
-// 64 lanes along x when the grid is wide enough, and the tallest row march
-// that still leaves >= 2048 workgroups (8 per CU) to fill the chip.
+// 64 lanes along x when the grid is wide enough, eight-row marches when the
+// grid is tall enough, and at most 2048 workgroups (8 per CU) looping over
+// the tiles.
 Tile choose_tile(int nx, int ny, bool vec2_ok) {
     Tile t;
     t.vec = (vec2_ok && nx % 2 == 0) ? 2 : 1;
@@ -111,14 +120,25 @@ Tile choose_tile(int nx, int ny, bool vec2_ok) {
     t.ty = lx::kBlockThreads / tx;
     t.ry = 1;
     for (int ry : {8, 4, 2}) {
-        Tile c = t;
-        c.ry = ry;
-        if (c.rows() <= ny && lx::num_blocks(c, nx, ny) >= 2048) {
+        if (t.ty * ry <= ny) {
             t.ry = ry;
             break;
         }
     }
+    t.nb = 2048;
     return t;
+}
+
+int tiles_of(const Tile& t, int nx, int ny) {
+    return ((nx + t.cols() - 1) / t.cols()) * ((ny + t.rows() - 1) / t.rows());
+}
+
+// workgroups in the grid: the shape's choice (0 = one per tile), at most one
+// per tile, a multiple of 8 once there are at least 8 (one band per XCD)
+int grid_size(const Tile& t, int tiles) {
+    int nb = (t.nb <= 0 || t.nb > tiles) ? tiles : t.nb;
+    if (nb >= 8) nb &= ~7;
+    return std::max(nb, 1);
 }
 
 lx_status ensure_xi(lx_ctx* ctx, int M) {
@@ -137,6 +157,76 @@ lx_status ensure_timing_events(lx_ctx* ctx, size_t n) {
         ctx->tev.push_back(e);
     }
     return LX_OK;
+}
+
+lx_status ensure_partials(lx_ctx* ctx, size_t need) {
+    if (need <= ctx->partials_len) return LX_OK;
+    LX_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    (void)hipFree(ctx->partials);
+    ctx->partials = nullptr;
+    ctx->partials_len = 0;
+    if (hipMalloc(&ctx->partials, sizeof(double) * need) != hipSuccess)
+        return fail(ctx, LX_ENOMEM, "partials workspace of %zu doubles", need);
+    ctx->partials_len = need;
+    return LX_OK;
+}
+
+bool valid_tile(const Tile& t) {
+    const bool ry_ok = t.ry == 1 || t.ry == 2 || t.ry == 4 || t.ry == 8;
+    return t.tx >= 1 && t.ty >= 1 && t.tx * t.ty == lx::kBlockThreads && ry_ok && (t.vec == 1 || t.vec == 2) &&
+           t.nb >= 0;
+}
+
+// forced shape, else the tuned one, else the built-in rule
+Tile pick_tile(const lx_ctx* ctx, const lx_operator& op, int K, bool vec2_ok) {
+    Tile t;
+    if (ctx->forced.tx != 0) {
+        t = ctx->forced;
+    } else {
+        auto it = ctx->tuned.find(std::make_tuple(op.kind, op.nx, op.ny, K, op.prec));
+        t = (it != ctx->tuned.end()) ? it->second : choose_tile(op.nx, op.ny, vec2_ok);
+    }
+    if (t.vec == 2 && !(vec2_ok && op.nx % 2 == 0)) t.vec = 1;
+    return t;
+}
+
+void set_stencil(SweepArgs& a, const lx_operator& op, double c, double g) {
+    if (op.kind == LX_OP_DIFFADV2D) {
+        const double ex = op.D / (op.dx * op.dx), ey = op.D / (op.dy * op.dy);
+        const double cE = ex + std::max(op.vx, 0.0) / op.dx, cW = ex + std::max(-op.vx, 0.0) / op.dx;
+        const double cN = ey + std::max(op.vy, 0.0) / op.dy, cS = ey + std::max(-op.vy, 0.0) / op.dy;
+        const double cC = -(cE + cW + cN + cS);
+        a.aE = cE / g;
+        a.aW = cW / g;
+        a.aN = cN / g;
+        a.aS = cS / g;
+        a.aC = (cC - c) / g;
+    } else {
+        a.kx = op.nu / (g * op.dx * op.dx);
+        a.ky = op.nu / (g * op.dy * op.dy);
+        a.gx = 1.0 / (2.0 * g * op.dx);
+        a.gy = 1.0 / (2.0 * g * op.dy);
+        a.kC = -2.0 * a.kx - 2.0 * a.ky - c / g;
+    }
+}
+
+void load_tune_cache(lx_ctx* ctx) {
+    const char* path = std::getenv("LX_TUNE_CACHE");
+    if (path == nullptr || *path == 0) return;
+    FILE* f = std::fopen(path, "r");
+    if (f == nullptr) return;
+    char line[256];
+    while (std::fgets(line, sizeof(line), f) != nullptr) {
+        int kind, nx, ny, K, prec;
+        Tile t;
+        if (std::sscanf(line, "{\"kind\": %d, \"nx\": %d, \"ny\": %d, \"K\": %d, \"prec\": %d, \"tx\": %d, "
+                              "\"ty\": %d, \"ry\": %d, \"vec\": %d, \"nb\": %d",
+                        &kind, &nx, &ny, &K, &prec, &t.tx, &t.ty, &t.ry, &t.vec, &t.nb) == 10 &&
+            valid_tile(t)) {
+            ctx->tuned[std::make_tuple(kind, nx, ny, K, prec)] = t;
+        }
+    }
+    std::fclose(f);
 }
 
 double elapsed(hipEvent_t a, hipEvent_t b) {
@@ -198,50 +288,34 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
         return LX_OK;
     };
 
-    LejaState& init = ctx->h_st[0];
+    LoopCtl& init = *ctx->h_ctl;
     std::memset(&init, 0, sizeof(init));
     init.rtol = q.o.rtol;
     init.atol = q.o.atol;
     init.fp32_switch = fp32 ? q.o.fp32_switch : -1.0;
     init.max_iters = q.o.max_iters;
-    init.out32 = (fp32 && q.o.fp32_switch == 0.0) ? 1 : 0;
+    SweepState& s0 = init.slot[0];
+    s0.out32 = (fp32 && q.o.fp32_switch == 0.0) ? 1 : 0;
     for (int k = 0; k < K; ++k) {
-        init.active[k] = 1;
-        init.iters[k] = q.o.max_iters;
+        s0.active[k] = 1;
+        s0.iters[k] = q.o.max_iters;
     }
-    LX_HIP(ctx, hipMemcpyAsync(ctx->st, &init, sizeof(LejaState), hipMemcpyHostToDevice, ctx->stream));
+    LX_HIP(ctx, hipMemcpyAsync(ctx->ctl, &init, sizeof(LoopCtl), hipMemcpyHostToDevice, ctx->stream));
 
     if (fp32 && op.kind == LX_OP_BURGERS2D) LX_HIP(ctx, lx::launch_to_fp32(q.u, ctx->u32, N, ctx->stream));
 
     // ---- sweep arguments ----
     bool vec2 = aligned16(q.v) && (q.u == nullptr || aligned16(q.u));
     for (int k = 0; k < K; ++k) vec2 = vec2 && aligned16(q.out[k]) && (q.base[k] == nullptr || aligned16(q.base[k]));
-    const Tile t = choose_tile(nx, ny, vec2);
+    const Tile t = pick_tile(ctx, op, K, vec2);
     SweepArgs a{};
     a.nx = nx;
     a.ny = ny;
     a.tiles_x = (nx + t.cols() - 1) / t.cols();
     a.tiles_y = (ny + t.rows() - 1) / t.rows();
-    a.K = K;
+    a.nb = grid_size(t, a.tiles_x * a.tiles_y);
     a.ld = M;
-    const double g = q.gamma;
-    if (op.kind == LX_OP_DIFFADV2D) {
-        const double ex = op.D / (op.dx * op.dx), ey = op.D / (op.dy * op.dy);
-        const double cE = ex + std::max(op.vx, 0.0) / op.dx, cW = ex + std::max(-op.vx, 0.0) / op.dx;
-        const double cN = ey + std::max(op.vy, 0.0) / op.dy, cS = ey + std::max(-op.vy, 0.0) / op.dy;
-        const double cC = -(cE + cW + cN + cS);
-        a.aE = cE / g;
-        a.aW = cW / g;
-        a.aN = cN / g;
-        a.aS = cS / g;
-        a.aC = (cC - q.c) / g;
-    } else {
-        a.kx = op.nu / (g * op.dx * op.dx);
-        a.ky = op.nu / (g * op.dy * op.dy);
-        a.gx = 1.0 / (2.0 * g * op.dx);
-        a.gy = 1.0 / (2.0 * g * op.dy);
-        a.kC = -2.0 * a.kx - 2.0 * a.ky - q.c / g;
-    }
+    set_stencil(a, op, q.c, q.gamma);
     a.inv_sqrtN = 1.0 / std::sqrt(static_cast<double>(N));
     a.v = q.v;
     a.ybuf[0] = ctx->ybuf[0];
@@ -254,11 +328,11 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
     }
     a.coef = ctx->coef;
     a.xi = ctx->xi;
-    a.partials = ctx->partials;
-    a.st = ctx->st;
+    a.ctl = ctx->ctl;
     const int opcode = op.kind == LX_OP_DIFFADV2D ? lx::kOpDiffAdv : lx::kOpBurgersJ;
-    if (static_cast<size_t>(a.tiles_x) * a.tiles_y * (1 + K) > ctx->partials_len)
-        return fail(ctx, LX_EINVAL, "launch shape exceeds the partials workspace");
+    s = ensure_partials(ctx, 2 * static_cast<size_t>(a.nb) * (1 + K));
+    if (s != LX_OK) return s;
+    a.partials = ctx->partials;
 
     // ---- chunked, device-resident loop ----
     const int max_iters = q.o.max_iters;
@@ -267,20 +341,23 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
         if (s != LX_OK) return s;
         LX_HIP(ctx, hipEventRecord(ctx->tev[0], ctx->stream));
     }
+    // sweep m (0 <= m < max_iters) reads d_m (its stop decision) and d_{m+1};
+    // the launch m = max_iters only takes the last decision
     int launched = 0, chunk_id = 0, last_slot = -1;
     int chunk = kFirstChunk;
-    while (launched < max_iters) {
-        const int n = std::min(chunk, max_iters - launched);
+    while (launched <= max_iters) {
+        const int n = std::min(chunk, max_iters + 1 - launched);
         s = ensure_coeffs(launched + n + 1);
         if (s != LX_OK) return s;
         for (int i = 0; i < n; ++i) {
-            LX_HIP(ctx, lx::launch_leja_sweep(opcode, K, fp32, t, a, ctx->stream));
-            if (ctx->timing) LX_HIP(ctx, hipEventRecord(ctx->tev[launched + i + 1], ctx->stream));
+            const int m = launched + i;
+            LX_HIP(ctx, lx::launch_leja_sweep(opcode, K, fp32, t, a, m, ctx->stream));
+            if (ctx->timing && m < max_iters) LX_HIP(ctx, hipEventRecord(ctx->tev[m + 1], ctx->stream));
         }
         launched += n;
         const int slot = chunk_id & 1;
-        LX_HIP(ctx, hipMemcpyAsync(&ctx->h_st[1 + slot], ctx->st, sizeof(LejaState), hipMemcpyDeviceToHost,
-                                   ctx->stream));
+        LX_HIP(ctx, hipMemcpyAsync(&ctx->h_poll[slot], &ctx->ctl->slot[2], sizeof(SweepState),
+                                   hipMemcpyDeviceToHost, ctx->stream));
         LX_HIP(ctx, hipEventRecord(ctx->poll_ev[slot], ctx->stream));
         last_slot = slot;
         if (chunk_id >= 1) {
@@ -289,13 +366,14 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
             if (s != LX_OK) return s;
             const int prev = slot ^ 1;
             LX_HIP(ctx, hipEventSynchronize(ctx->poll_ev[prev]));
-            if (ctx->h_st[1 + prev].done) break;
+            if (ctx->h_poll[prev].done) break;
         }
         ++chunk_id;
         chunk = kChunk;
     }
     LX_HIP(ctx, hipEventSynchronize(ctx->poll_ev[last_slot]));
-    const LejaState& fin = ctx->h_st[1 + last_slot];
+    const SweepState& fin = ctx->h_poll[last_slot];
+    if (!fin.done) return fail(ctx, LX_EDEVICE, "the device loop did not record a final state");
 
     S.n_apply = fin.iter;
     S.n_fp32 = fin.n_fp32;
@@ -321,11 +399,13 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
     S.bytes = bytes;
     S.plan_ms = plan_ms;
     if (ctx->timing && fin.iter > 0) {
+        // events follow every sweep: sweep m's interval also holds the stop
+        // decision the next sweep takes first (a few microseconds)
         S.first_sweep_ms = elapsed(ctx->tev[0], ctx->tev[1]);
         S.loop_ms = elapsed(ctx->tev[0], ctx->tev[fin.iter]);
         S.sweep_ms = S.loop_ms;
     }
-    S.status = fin.done ? fin.status : LX_ENOTCONV;
+    S.status = fin.status;
     if (S.status == LX_ENONFINITE) return fail(ctx, LX_ENONFINITE, "a norm became NaN or Inf at sweep %d", fin.iter);
     if (S.status == LX_ENOTCONV) {
         ctx->err = "not converged within max_iters";
@@ -388,10 +468,11 @@ void lx_destroy(lx_ctx* ctx) {
     for (double* p : ctx->ws) (void)hipFree(p);
     (void)hipFree(ctx->u32);
     (void)hipFree(ctx->partials);
-    (void)hipFree(ctx->st);
+    (void)hipFree(ctx->ctl);
     (void)hipFree(ctx->coef);
     (void)hipFree(ctx->xi);
-    (void)hipHostFree(ctx->h_st);
+    (void)hipHostFree(ctx->h_ctl);
+    (void)hipHostFree(ctx->h_poll);
     (void)hipHostFree(ctx->h_coef);
     (void)hipHostFree(ctx->h_xi);
     for (hipEvent_t e : ctx->poll_ev)
@@ -416,13 +497,17 @@ lx_status lx_create(lx_ctx** out, size_t n_max, int k_max, void* stream) {
     for (auto& p : ctx->ybuf)
         if (hipMalloc(&p, sizeof(double) * n_max) != hipSuccess) return bail(LX_ENOMEM);
     if (hipMalloc(&ctx->u32, sizeof(float) * n_max) != hipSuccess) return bail(LX_ENOMEM);
-    // one partial sum per workgroup and per norm; the smallest tile has 256 points
-    ctx->partials_len = static_cast<size_t>(1 + k_max) * (n_max / 256 + 4096 + 64);
+    // two parity slots of (1 + k_max) partial sums per workgroup, for up to
+    // 4096 workgroups (grown on demand for larger grids)
+    ctx->partials_len = 2 * static_cast<size_t>(1 + k_max) * 4096;
     if (hipMalloc(&ctx->partials, sizeof(double) * ctx->partials_len) != hipSuccess) return bail(LX_ENOMEM);
-    if (hipMalloc(&ctx->st, sizeof(LejaState)) != hipSuccess) return bail(LX_ENOMEM);
+    if (hipMalloc(&ctx->ctl, sizeof(LoopCtl)) != hipSuccess) return bail(LX_ENOMEM);
     if (hipMalloc(&ctx->coef, sizeof(double) * k_max * lx::kMaxPoints) != hipSuccess) return bail(LX_ENOMEM);
     if (hipMalloc(&ctx->xi, sizeof(double) * lx::kMaxPoints) != hipSuccess) return bail(LX_ENOMEM);
-    if (hipHostMalloc(reinterpret_cast<void**>(&ctx->h_st), 3 * sizeof(LejaState), hipHostMallocDefault) != hipSuccess)
+    if (hipHostMalloc(reinterpret_cast<void**>(&ctx->h_ctl), sizeof(LoopCtl), hipHostMallocDefault) != hipSuccess)
+        return bail(LX_ENOMEM);
+    if (hipHostMalloc(reinterpret_cast<void**>(&ctx->h_poll), 2 * sizeof(SweepState), hipHostMallocDefault) !=
+        hipSuccess)
         return bail(LX_ENOMEM);
     if (hipHostMalloc(reinterpret_cast<void**>(&ctx->h_coef), sizeof(double) * k_max * lx::kMaxPoints,
                       hipHostMallocDefault) != hipSuccess)
@@ -432,9 +517,12 @@ lx_status lx_create(lx_ctx** out, size_t n_max, int k_max, void* stream) {
         return bail(LX_ENOMEM);
     for (auto& e : ctx->poll_ev)
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return bail(LX_EDEVICE);
-    std::memset(ctx->h_st, 0, 3 * sizeof(LejaState));
-    if (hipMemsetAsync(ctx->st, 0, sizeof(LejaState), ctx->stream) != hipSuccess) return bail(LX_EDEVICE);
+    std::memset(ctx->h_ctl, 0, sizeof(LoopCtl));
+    std::memset(ctx->h_poll, 0, 2 * sizeof(SweepState));
+    if (hipMemcpyAsync(ctx->ctl, ctx->h_ctl, sizeof(LoopCtl), hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
+        return bail(LX_EDEVICE);
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) return bail(LX_EDEVICE);
+    load_tune_cache(ctx);
     *out = ctx;
     return LX_OK;
 }
@@ -463,23 +551,19 @@ lx_status lx_spectrum(lx_ctx* ctx, const lx_operator* op, const double* d_u, con
     const int nx = op->nx, ny = op->ny;
     const long N = static_cast<long>(nx) * ny;
 
-    LejaState& init = ctx->h_st[0];
-    std::memset(&init, 0, sizeof(init));
-    LX_HIP(ctx, hipMemcpyAsync(ctx->st, &init, sizeof(LejaState), hipMemcpyHostToDevice, ctx->stream));
     const double* x0 = d_x0;
     if (x0 == nullptr) {
         LX_HIP(ctx, lx::launch_fill_splitmix(ctx->ybuf[1], N, 0ull, ctx->stream));
         x0 = ctx->ybuf[1];
     }
-    LX_HIP(ctx, lx::launch_norm(x0, N, ctx->partials, ctx->st, ctx->stream));
-
     const bool vec2 = aligned16(x0) && (d_u == nullptr || aligned16(d_u));
-    const Tile t = choose_tile(nx, ny, vec2);
+    const Tile t = pick_tile(ctx, *op, 1, vec2);
     PowerArgs a{};
     a.nx = nx;
     a.ny = ny;
     a.tiles_x = (nx + t.cols() - 1) / t.cols();
     a.tiles_y = (ny + t.rows() - 1) / t.rows();
+    a.nb = grid_size(t, a.tiles_x * a.tiles_y);
     if (op->kind == LX_OP_DIFFADV2D) {
         const double ex = op->D / (op->dx * op->dx), ey = op->D / (op->dy * op->dy);
         a.cE = ex + std::max(op->vx, 0.0) / op->dx;
@@ -494,9 +578,13 @@ lx_status lx_spectrum(lx_ctx* ctx, const lx_operator* op, const double* d_u, con
         a.gy = 1.0 / (2.0 * op->dy);
     }
     a.u = d_u;
+    s = ensure_partials(ctx, 2 * static_cast<size_t>(a.nb));
+    if (s != LX_OK) return s;
     a.partials = ctx->partials;
-    a.st = ctx->st;
+    a.ctl = ctx->ctl;
     const int opcode = op->kind == LX_OP_DIFFADV2D ? lx::kOpDiffAdv : lx::kOpBurgersJ;
+    // |x0|^2 partials into slot 1, read by sweep 0
+    LX_HIP(ctx, lx::launch_power_norm(x0, N, a.nb, ctx->partials, ctx->stream));
     if (ctx->timing) {
         s = ensure_timing_events(ctx, static_cast<size_t>(iters) + 1);
         if (s != LX_OK) return s;
@@ -505,25 +593,27 @@ lx_status lx_spectrum(lx_ctx* ctx, const lx_operator* op, const double* d_u, con
     for (int k = 0; k < iters; ++k) {
         a.in = (k == 0) ? x0 : ctx->ybuf[(k - 1) & 1];
         a.out = ctx->ybuf[k & 1];
-        LX_HIP(ctx, lx::launch_power_sweep(opcode, t, a, ctx->stream));
+        LX_HIP(ctx, lx::launch_power_sweep(opcode, t, a, k, ctx->stream));
         if (ctx->timing) LX_HIP(ctx, hipEventRecord(ctx->tev[k + 1], ctx->stream));
     }
-    LX_HIP(ctx, hipMemcpyAsync(&ctx->h_st[1], ctx->st, sizeof(LejaState), hipMemcpyDeviceToHost, ctx->stream));
+    LX_HIP(ctx, lx::launch_power_final(a.nb, ctx->partials + static_cast<size_t>((iters - 1) & 1) * a.nb, ctx->ctl,
+                                       ctx->stream));
+    LX_HIP(ctx, hipMemcpyAsync(ctx->h_ctl, ctx->ctl, sizeof(LoopCtl), hipMemcpyDeviceToHost, ctx->stream));
     LX_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    const LejaState& fin = ctx->h_st[1];
+    const double rho = ctx->h_ctl->rho;
     lx_stats& S = ctx->stats;
-    S.n_apply = fin.iter;
-    S.rho_hat = fin.rho;
+    S.n_apply = iters;
+    S.rho_hat = rho;
     S.bytes = (16.0 + (op->kind == LX_OP_BURGERS2D ? 8.0 : 0.0)) * static_cast<double>(N) * iters;
     if (ctx->timing) {
         S.loop_ms = elapsed(ctx->tev[0], ctx->tev[iters]);
-        S.sweep_ms = elapsed(ctx->tev[1], ctx->tev[iters]);
+        S.sweep_ms = S.loop_ms;
         S.first_sweep_ms = elapsed(ctx->tev[0], ctx->tev[1]);
     }
-    if (fin.status != 0 || !std::isfinite(fin.rho) || !(fin.rho > 0.0) || fin.iter != iters)
+    if (!std::isfinite(rho) || !(rho > 0.0))
         return fail(ctx, LX_ENONFINITE, "power iteration produced a zero or non-finite norm");
-    const double lam = -safety * fin.rho;
-    if (rho_hat) *rho_hat = fin.rho;
+    const double lam = -safety * rho;
+    if (rho_hat) *rho_hat = rho;
     if (c) *c = lam / 2.0;
     if (gamma) *gamma = -lam / 4.0;
     S.status = LX_OK;
@@ -597,8 +687,9 @@ lx_status lx_exprb_step(lx_ctx* ctx, const lx_operator* op, int scheme, const do
     const int nx = op->nx, ny = op->ny;
     double* hF = ctx->ws[0];   // h F(u), later h [N(U2) - N(u)]
     double* U2 = ctx->ws[1];
+    double* B = ctx->ws[2];    // u + h phi_1(h J) F(u)
     // stage 1: U2 = u + (3/4) h phi_1((3/4) h J) F(u) and
-    //          u_out = u + h phi_1(h J) F(u), one Newton basis
+    //          B  = u + h phi_1(h J) F(u), one Newton basis
     LX_HIP(ctx, lx::launch_burgers_hF(d_u, hF, nx, ny, op->nu, op->dx, op->dy, h, ctx->stream));
     LejaCall q{};
     q.op = op;
@@ -606,7 +697,7 @@ lx_status lx_exprb_step(lx_ctx* ctx, const lx_operator* op, int scheme, const do
     q.v = hF;
     q.K = 2;
     q.l[0] = 1; q.alpha[0] = 0.75; q.sigma[0] = 0.75; q.out[0] = U2;      q.base[0] = d_u;
-    q.l[1] = 1; q.alpha[1] = 1.0;  q.sigma[1] = 1.0;  q.out[1] = d_u_out; q.base[1] = d_u;
+    q.l[1] = 1; q.alpha[1] = 1.0;  q.sigma[1] = 1.0;  q.out[1] = B;       q.base[1] = d_u;
     q.h = h;
     q.c = c;
     q.gamma = gamma;
@@ -614,14 +705,14 @@ lx_status lx_exprb_step(lx_ctx* ctx, const lx_operator* op, int scheme, const do
     s = run_leja(ctx, q);
     if (s != LX_OK) return s;
     const lx_stats s1 = ctx->stats;
-    // stage 2: R = h [N(U2) - N(u)], u_out += (32/9) h phi_3(h J) R / h
+    // stage 2: R = h [N(U2) - N(u)], u_out = B + (32/9) phi_3(h J) R
     LX_HIP(ctx, lx::launch_burgers_remainder(d_u, U2, hF, nx, ny, op->nu, op->dx, op->dy, h, ctx->stream));
     LejaCall r{};
     r.op = op;
     r.u = d_u;
     r.v = hF;
     r.K = 1;
-    r.l[0] = 3; r.alpha[0] = 1.0; r.sigma[0] = 32.0 / 9.0; r.out[0] = d_u_out; r.base[0] = d_u_out;
+    r.l[0] = 3; r.alpha[0] = 1.0; r.sigma[0] = 32.0 / 9.0; r.out[0] = d_u_out; r.base[0] = B;
     r.h = h;
     r.c = c;
     r.gamma = gamma;
@@ -645,6 +736,174 @@ lx_status lx_exprb_step(lx_ctx* ctx, const lx_operator* op, int scheme, const do
     S.loop_ms += s1.loop_ms;
     S.sweep_ms += s1.sweep_ms;
     return s;
+}
+
+lx_status lx_set_tile(lx_ctx* ctx, int tx, int ty, int ry, int vec, int nb) {
+    if (ctx == nullptr) return LX_EINVAL;
+    if (tx == 0) {
+        ctx->forced = Tile{0, 0, 0, 0, 0};
+        return LX_OK;
+    }
+    const Tile t{tx, ty, ry, vec, nb};
+    if (!valid_tile(t))
+        return fail(ctx, LX_EINVAL, "invalid launch shape tx=%d ty=%d ry=%d vec=%d nb=%d", tx, ty, ry, vec, nb);
+    ctx->forced = t;
+    return LX_OK;
+}
+
+lx_status lx_tune(lx_ctx* ctx, const lx_operator* op, int K, int sweeps, char* report, size_t report_len) {
+    if (ctx == nullptr) return LX_EINVAL;
+    ctx->stats = lx_stats{};
+    lx_status s = check_op(ctx, op);
+    if (s != LX_OK) return s;
+    if (K < 1 || K > ctx->k_max) return fail(ctx, LX_EINVAL, "K = %d outside 1..%d", K, ctx->k_max);
+    if (sweeps < 1 || sweeps > 200) return fail(ctx, LX_EINVAL, "sweeps %d outside 1..200", sweeps);
+    const int nx = op->nx, ny = op->ny;
+    const size_t N = static_cast<size_t>(nx) * ny;
+    const int ld = sweeps + 8;
+    s = ensure_xi(ctx, ld);
+    if (s != LX_OK) return s;
+    // scratch: K outputs (+ the Burgers state), all zero, so that values stay
+    // finite for any number of sweeps; atol < 0 keeps the loop running
+    double* scratch = nullptr;
+    const size_t nvec = static_cast<size_t>(K) + (op->kind == LX_OP_BURGERS2D ? 1 : 0);
+    if (hipMalloc(&scratch, sizeof(double) * N * nvec) != hipSuccess) return fail(ctx, LX_ENOMEM, "tuning scratch");
+    auto cleanup = [&](lx_status r) {
+        (void)hipStreamSynchronize(ctx->stream);
+        (void)hipFree(scratch);
+        return r;
+    };
+    if (hipMemsetAsync(scratch, 0, sizeof(double) * N * nvec, ctx->stream) != hipSuccess ||
+        hipMemsetAsync(ctx->ybuf[0], 0, sizeof(double) * N, ctx->stream) != hipSuccess ||
+        hipMemsetAsync(ctx->ybuf[1], 0, sizeof(double) * N, ctx->stream) != hipSuccess)
+        return cleanup(fail(ctx, LX_EDEVICE, "tuning scratch clear failed"));
+    for (int k = 0; k < K; ++k)
+        for (int j = 0; j < ld; ++j) ctx->h_coef[static_cast<size_t>(k) * ld + j] = 1e-3;
+    if (hipMemcpyAsync(ctx->coef, ctx->h_coef, sizeof(double) * K * ld, hipMemcpyHostToDevice, ctx->stream) !=
+        hipSuccess)
+        return cleanup(fail(ctx, LX_EDEVICE, "coefficient upload failed"));
+    LoopCtl& init = *ctx->h_ctl;
+    std::memset(&init, 0, sizeof(init));
+    init.max_iters = LX_MAX_ITERS;
+    init.rtol = 0.0;
+    init.atol = -1.0;
+    init.fp32_switch = -1.0;
+    for (int k = 0; k < K; ++k) {
+        init.slot[0].active[k] = 1;
+        init.slot[0].iters[k] = LX_MAX_ITERS;
+    }
+    s = ensure_timing_events(ctx, 2);
+    if (s != LX_OK) return cleanup(s);
+
+    const bool vec2_ok = nx % 2 == 0;
+    std::vector<Tile> cands;
+    for (int tx : {64, 32, 16, 8, 4}) {
+        Tile t;
+        t.tx = tx;
+        t.ty = lx::kBlockThreads / tx;
+        t.vec = vec2_ok ? 2 : 1;
+        if (t.cols() > nx && tx > 4) continue;   // narrower workgroups cover this grid
+        for (int ry : {1, 2, 4, 8}) {
+            t.ry = ry;
+            if (t.rows() > ny && ry > 1) continue;
+            const int tiles = tiles_of(t, nx, ny);
+            for (int nb : {0, 2048, 1024, 512}) {
+                if (nb != 0 && nb >= tiles) continue;   // same as one workgroup per tile
+                t.nb = nb;
+                cands.push_back(t);
+            }
+        }
+    }
+    std::string rep;
+    double best_us = 1e300;
+    Tile best = cands.empty() ? choose_tile(nx, ny, vec2_ok) : cands[0];
+    const int opcode = op->kind == LX_OP_DIFFADV2D ? lx::kOpDiffAdv : lx::kOpBurgersJ;
+    const bool fp32 = op->prec == LX_FP32_SWEEP;
+    for (const Tile& t : cands) {
+        SweepArgs a{};
+        a.nx = nx;
+        a.ny = ny;
+        a.tiles_x = (nx + t.cols() - 1) / t.cols();
+        a.tiles_y = (ny + t.rows() - 1) / t.rows();
+        a.nb = grid_size(t, a.tiles_x * a.tiles_y);
+        a.ld = ld;
+        set_stencil(a, *op, -2.0, 1.0);
+        a.inv_sqrtN = 1.0 / std::sqrt(static_cast<double>(N));
+        a.v = ctx->ybuf[0];
+        a.ybuf[0] = ctx->ybuf[0];
+        a.ybuf[1] = ctx->ybuf[1];
+        a.u = op->kind == LX_OP_BURGERS2D ? scratch + static_cast<size_t>(K) * N : nullptr;
+        a.u32 = ctx->u32;
+        for (int k = 0; k < K; ++k) a.p[k] = scratch + static_cast<size_t>(k) * N;
+        a.coef = ctx->coef;
+        a.xi = ctx->xi;
+        s = ensure_partials(ctx, 2 * static_cast<size_t>(a.nb) * (1 + K));
+        if (s != LX_OK) return cleanup(s);
+        a.partials = ctx->partials;
+        a.ctl = ctx->ctl;
+        if (hipMemcpyAsync(ctx->ctl, &init, sizeof(LoopCtl), hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
+            return cleanup(fail(ctx, LX_EDEVICE, "state upload failed"));
+        // sweeps 0 and 1 warm up, sweeps 2 .. sweeps+1 are timed
+        hipError_t e = hipSuccess;
+        for (int m = 0; m < 2 && e == hipSuccess; ++m) e = lx::launch_leja_sweep(opcode, K, fp32, t, a, m, ctx->stream);
+        if (e == hipSuccess) e = hipEventRecord(ctx->tev[0], ctx->stream);
+        for (int m = 2; m < sweeps + 2 && e == hipSuccess; ++m)
+            e = lx::launch_leja_sweep(opcode, K, fp32, t, a, m, ctx->stream);
+        if (e == hipSuccess) e = hipEventRecord(ctx->tev[1], ctx->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(ctx->tev[1]);
+        if (e != hipSuccess) return cleanup(fail(ctx, LX_EDEVICE, "tuning launch failed: %s", hipGetErrorString(e)));
+        const double us = elapsed(ctx->tev[0], ctx->tev[1]) * 1e3 / sweeps;
+        char line[112];
+        std::snprintf(line, sizeof(line), "%d %d %d %d %d %.3f\n", t.tx, t.ty, t.ry, t.vec, a.nb, us);
+        rep += line;
+        if (us < best_us) {
+            best_us = us;
+            best = t;
+        }
+    }
+    ctx->tuned[std::make_tuple(op->kind, nx, ny, K, op->prec)] = best;
+    if (report != nullptr && report_len > 0) {
+        std::snprintf(report, report_len, "%s", rep.c_str());
+    }
+    const char* path = std::getenv("LX_TUNE_CACHE");
+    if (path != nullptr && *path != 0) {
+        FILE* f = std::fopen(path, "a");
+        if (f != nullptr) {
+            std::fprintf(f,
+                         "{\"kind\": %d, \"nx\": %d, \"ny\": %d, \"K\": %d, \"prec\": %d, \"tx\": %d, "
+                         "\"ty\": %d, \"ry\": %d, \"vec\": %d, \"nb\": %d, \"us\": %.3f}\n",
+                         op->kind, nx, ny, K, op->prec, best.tx, best.ty, best.ry, best.vec, best.nb, best_us);
+            std::fclose(f);
+        }
+    }
+    return cleanup(LX_OK);
+}
+
+lx_status lx_bandwidth_probe(lx_ctx* ctx, int kind, size_t n, int reps, double* gbs) {
+    if (ctx == nullptr || gbs == nullptr) return LX_EINVAL;
+    if ((kind != 0 && kind != 1) || n < 2 || n % 2 != 0 || reps < 1)
+        return fail(ctx, LX_EINVAL, "probe kind %d, n %zu, reps %d", kind, n, reps);
+    double* buf = nullptr;
+    if (hipMalloc(&buf, sizeof(double) * n * 3) != hipSuccess) return fail(ctx, LX_ENOMEM, "probe vectors");
+    auto cleanup = [&](lx_status r) {
+        (void)hipStreamSynchronize(ctx->stream);
+        (void)hipFree(buf);
+        return r;
+    };
+    lx_status s = ensure_timing_events(ctx, 2);
+    if (s != LX_OK) return cleanup(s);
+    hipError_t e = hipMemsetAsync(buf, 0, sizeof(double) * n * 3, ctx->stream);
+    if (e == hipSuccess) e = lx::launch_probe(kind, buf, buf + n, buf + 2 * n, static_cast<long>(n), ctx->stream);
+    if (e == hipSuccess) e = hipEventRecord(ctx->tev[0], ctx->stream);
+    for (int i = 0; i < reps && e == hipSuccess; ++i)
+        e = lx::launch_probe(kind, buf, buf + n, buf + 2 * n, static_cast<long>(n), ctx->stream);
+    if (e == hipSuccess) e = hipEventRecord(ctx->tev[1], ctx->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(ctx->tev[1]);
+    if (e != hipSuccess) return cleanup(fail(ctx, LX_EDEVICE, "probe failed: %s", hipGetErrorString(e)));
+    const double ms = elapsed(ctx->tev[0], ctx->tev[1]);
+    const double bytes = (kind == 0 ? 16.0 : 24.0) * static_cast<double>(n) * reps;
+    *gbs = bytes / (ms * 1e-3) / 1e9;
+    return cleanup(LX_OK);
 }
 
 lx_status lx_leja_points(int M, double* xi) {

@@ -8,35 +8,42 @@ namespace lx {
 constexpr int kKMax = 4;          // most outputs per Newton basis
 constexpr int kBlockThreads = 256;
 
-// Loop state kept in device memory.  The kernel of sweep m reads it at entry;
-// the last workgroup of that sweep to finish updates it (after every other
-// workgroup of the sweep has arrived), so the next sweep in the stream sees
-// the new values.  The host reads it once per chunk of sweeps.
-struct LejaState {
+// State of the Newton-Leja loop as it enters one sweep.
+struct SweepState {
     double err[kKMax];       // last error estimate per output
     double pnorm[kKMax];     // rms norm of each output after its last update
     double ynorm;            // rms norm of the newest basis vector
+    int active[kKMax];       // output still iterating during this sweep
+    int iters[kKMax];        // sweeps until the output passed the test
+    int in32;                // y_m is stored in FP32
+    int out32;               // this sweep writes y_{m+1} in FP32
+    int n_fp32;              // sweeps so far that wrote FP32
+    int status;              // lx_status
+    int done;                // the loop has ended
+    int iter;                // sweeps completed
+};
+
+// Loop control in device memory.  There is no synchronisation between the
+// workgroups of one sweep: sweep m writes per-workgroup partial sums into
+// partials[m & 1]; every workgroup of sweep m+1 adds all of them in the same
+// fixed order, so all reach the same stop decision, and workgroup 0 records
+// it in slot[(m+1) & 1].  Kernel boundaries make each sweep's writes visible
+// to the next.  slot[2] receives the final state once the loop ends; later
+// sweeps see its done flag and return at once.
+struct LoopCtl {
+    SweepState slot[3];
     double rtol, atol;
     double fp32_switch;      // < 0: never switch to FP32 sweeps
-    double scale;            // power iteration: 1 / ||w_k||
-    double rho;              // power iteration: ||w_{k+1}||
-    int iter;                // sweeps completed (= index m of the next sweep)
-    int done;                // 1 once the loop has ended
-    int status;              // lx_status
+    double rho;              // power iteration result
     int max_iters;
-    int in32;                // y_m is stored in FP32
-    int out32;               // the next sweep writes y_{m+1} in FP32
-    int n_fp32;              // sweeps that wrote FP32
-    int active[kKMax];       // output still iterating
-    int iters[kKMax];        // sweeps until the output passed
-    unsigned arrive;         // workgroups of the current sweep that finished
     int pad;
 };
 
 // Launch shape of a stencil sweep: 2-D workgroups of tx * ty threads; each
-// thread owns `vec` consecutive columns and marches over `ry` rows.
+// thread owns `vec` consecutive columns and marches over `ry` rows; `nb`
+// workgroups (0 = one per tile) loop over the tiles.
 struct Tile {
-    int tx = 64, ty = 4, ry = 4, vec = 2;
+    int tx = 64, ty = 4, ry = 4, vec = 2, nb = 0;
     int cols() const { return tx * vec; }
     int rows() const { return ty * ry; }
 };
@@ -44,7 +51,7 @@ struct Tile {
 struct SweepArgs {
     int nx, ny;
     int tiles_x, tiles_y;
-    int K;
+    int nb;                  // workgroups in the grid (every sweep uses the same)
     int ld;                  // leading dimension of coef (per output)
     // diffusion-advection: stencil coefficients divided by gamma; aC holds
     // (c_C - c)/gamma, the sweep subtracts xi_m
@@ -61,38 +68,42 @@ struct SweepArgs {
     const double* base[kKMax];  // optional: p_0 = base + d_0 v (internal use)
     const double* coef;      // coef[k*ld + j] = d_j of output k
     const double* xi;        // Leja points
-    double* partials;        // per-workgroup partial sums, (1+K) each
-    LejaState* st;
+    double* partials;        // [2][nb][1+K]
+    LoopCtl* ctl;
 };
 
 struct PowerArgs {
     int nx, ny;
     int tiles_x, tiles_y;
+    int nb;
     double cE, cW, cN, cS, cC;     // diffusion-advection stencil
     double kx, ky, gx, gy;         // Burgers: nu/dx^2, nu/dy^2, 1/(2dx), 1/(2dy)
     const double* in;
     double* out;
     const double* u;
-    double* partials;
-    LejaState* st;
+    double* partials;              // [2][nb]
+    LoopCtl* ctl;
 };
 
 enum OpCode { kOpDiffAdv = 0, kOpBurgersJ = 1 };
 
 // Kernel launchers (kernels.hip).  Each returns the hipError_t of the launch.
-hipError_t launch_leja_sweep(int op, int K, bool fp32_capable, const Tile& t, const SweepArgs& a,
+// Sweep m of the Leja loop (m = max_iters only takes the last decision).
+hipError_t launch_leja_sweep(int op, int K, bool fp32_capable, const Tile& t, const SweepArgs& a, int m,
                              hipStream_t s);
-hipError_t launch_power_sweep(int op, const Tile& t, const PowerArgs& a, hipStream_t s);
-hipError_t launch_norm(const double* x, long n, double* partials, LejaState* st, hipStream_t s);
+// Power iteration: norm of the start vector into partials[1], then sweeps
+// k = 0..iters-1, then the final norm into ctl->rho.
+hipError_t launch_power_norm(const double* x, long n, int nb, double* partials, hipStream_t s);
+hipError_t launch_power_sweep(int op, const Tile& t, const PowerArgs& a, int k, hipStream_t s);
+hipError_t launch_power_final(int nb, const double* partials, LoopCtl* ctl, hipStream_t s);
 hipError_t launch_fill_splitmix(double* x, long n, unsigned long long seed, hipStream_t s);
 hipError_t launch_to_fp32(const double* x, float* y, long n, hipStream_t s);
+// kind 0: z = x (copy); kind 1: z = 1.5 x - 0.5 y.  n even.
+hipError_t launch_probe(int kind, const double* x, const double* y, double* z, long n, hipStream_t s);
 // Burgers helpers for EXPRB42
 hipError_t launch_burgers_hF(const double* u, double* out, int nx, int ny, double nu, double dx,
                              double dy, double h, hipStream_t s);
 hipError_t launch_burgers_remainder(const double* u, const double* U2, double* out, int nx, int ny,
                                     double nu, double dx, double dy, double h, hipStream_t s);
-
-int num_blocks(const Tile& t, int nx, int ny);
-int norm_blocks(long n);
 
 }  // namespace lx

@@ -310,3 +310,63 @@ def test_repeat_calls_are_bitwise_deterministic(ctx):
     assert ra.iters == rb.iters and ra.err == rb.err
     for x, y in zip(a, b):
         assert np.array_equal(host(x), host(y))
+
+
+# ---------------------------------------------------------------------------
+# launch shapes: every shape the tuner can pick gives the same answer
+# ---------------------------------------------------------------------------
+
+TILES = [(64, 4, 1, 2), (64, 4, 8, 2), (32, 8, 2, 2), (16, 16, 4, 2), (8, 32, 1, 2), (4, 64, 8, 2),
+         (64, 4, 4, 1), (32, 8, 8, 1), (4, 64, 1, 1)]
+
+
+@pytest.mark.parametrize("tile", TILES)
+def test_every_launch_shape_matches_oracle(ctx, tile):
+    prm, h = diffadv_setup(200, 136)
+    c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
+    v = np.random.default_rng(31).standard_normal((136, 200))
+    outs = [dev(np.zeros((136, 200))) for _ in range(3)]
+    say("forced tile", tile)
+    ctx.set_tile(*tile)
+    try:
+        r = ctx.phi_leja(_op(prm), dev(v), outs, [0, 1, 3], h, c, g, rtol=1e-8, max_iters=200)
+        n = 120
+        u = W.fourier_modes(n, seed=5)
+        op_b = B.make_operator(kind=B.LX_OP_BURGERS2D, nx=n, ny=90, dx=1 / n, dy=1 / 90, nu=2e-3)
+        ub = u[:90, :]
+        x0 = np.random.default_rng(1).standard_normal((90, n))
+        rho, cb, gb = ctx.spectrum(op_b, u=dev(ub), x0=dev(x0), iters=20)
+        vb = np.random.default_rng(2).standard_normal((90, n))
+        ob = dev(np.zeros((90, n)))
+        hb = 5.0 * W.burgers_cfl_step(2e-3, float(np.max(np.abs(ub))), 1 / n, 1 / 90)
+        rb = ctx.phi_leja(op_b, dev(vb), [ob], [1], hb, cb, gb, u=dev(ub), rtol=1e-8, max_iters=200)
+    finally:
+        ctx.set_tile(0, 0, 0, 0)
+    spec = [(0, 1.0, 1.0), (1, 1.0, 1.0), (3, 1.0, 1.0)]
+    oracle_parity([host(o) for o in outs], r.iters,
+                  lambda f: leja_phi(_A(prm), v, spec, h, c, g, 1e-8, 0.0, 200, f), PARITY)
+    rho_o, _ = power_iteration(lambda w: burgers_J(ub, w, 2e-3, 1 / n, 1 / 90), x0, 20)
+    assert abs(rho - rho_o) <= 1e-12 * rho_o
+    oracle_parity([host(ob)], rb.iters,
+                  lambda f: leja_phi(lambda w: burgers_J(ub, w, 2e-3, 1 / n, 1 / 90), vb, [(1, 1.0, 1.0)],
+                                     hb, cb, gb, 1e-8, 0.0, 200, f), PARITY)
+
+
+def test_tune_then_solve(ctx):
+    prm, h = diffadv_setup(384, 256)
+    c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
+    say("tune 384x256")
+    rows = ctx.tune(_op(prm), K=2, sweeps=3)
+    assert len(rows) >= 4 and all(r[4] > 0 for r in rows)
+    v = np.random.default_rng(41).standard_normal((256, 384))
+    outs = [dev(np.zeros((256, 384))) for _ in range(2)]
+    r = ctx.phi_leja(_op(prm), dev(v), outs, [1, 2], h, c, g, rtol=1e-8, max_iters=200)
+    spec = [(1, 1.0, 1.0), (2, 1.0, 1.0)]
+    oracle_parity([host(o) for o in outs], r.iters,
+                  lambda f: leja_phi(_A(prm), v, spec, h, c, g, 1e-8, 0.0, 200, f), PARITY)
+
+
+def test_bandwidth_probe_reports_plausible_rates(ctx):
+    for kind in (0, 1):
+        gbs = ctx.bandwidth_probe(kind, 1 << 22, reps=5)
+        assert 50.0 < gbs < 20000.0
