@@ -5,51 +5,65 @@ One step = power iteration (20 sweeps) for the spectral bound, then the
 phi_1, phi_2, phi_3 actions of a seeded N(0,1) vector from one Newton basis
 on the periodic 4096^2 diffusion-advection grid (D = 1, cell Peclet 1,
 h = 50 x CFL, rtol 1e-8), all through the C ABI.  Inputs are resident in
-HBM before the timed region.  Prints one JSON line on stdout:
+HBM before the timed region.  Before it, the launch shapes of this grid are
+autotuned (lx_tune) and the practical bandwidth is calibrated with plain
+copy and z = a x + b y kernels on vectors larger than the Infinity Cache.
 
-  value     phi-action solves/s (3 solves per step)
-  roofline  HBM roofline of the dominant kernel (the fused Leja sweep):
-            algorithmic bytes per launch / average launch duration, both
-            from HIP events recorded on the library's stream around every
-            sweep of the timed steps
+Prints one JSON line on stdout:
+  value         phi-action solves/s (3 solves per step)
+  roofline      HBM roofline of the dominant kernel (the fused Leja sweep):
+                algorithmic bytes per launch / average launch duration, both
+                from HIP events recorded on the library's stream around
+                every sweep of the timed steps; traffic from the committed
+                rocprofv3 counter summary when it was taken on the current
+                kernel source, else null
   cpu_baseline  the CPU oracle on a bounded sample (the same solve on a
-            1024^2 grid of the same family, scaled by the point ratio 16)
+                2048^2 grid of the same family, scaled by the point ratio 4)
 
-Usage: python bench.py [--steps K] [--warmup W] [--workload NAME]
+Usage: python bench.py [--steps K] [--warmup W] [--no-tune] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
 import time
-
-import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_2310_08344_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "leja_sweep_phi123_4096_traffic.json")
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def make_workload(name: str):
-    from paper_2310_08344_amd import workloads as W
-    if name == "phi123-4096":
-        p, v = W.config2(n=4096)
-    elif name == "phi123-1024":
-        p, v = W.config2(n=1024)
-    else:
-        raise SystemExit(f"unknown workload {name}")
-    return p, v
+def kernel_source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
 
 
-def cpu_baseline(sample_n: int = 1024) -> dict:
+def committed_traffic(launch_bytes: float):
+    """HBM bytes per launch of the sweep from the committed counter summary,
+    if it was taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return {"bytes_per_launch": t["hbm_bytes_per_launch"], "ratio_to_algorithmic":
+            round(t["hbm_bytes_per_launch"] / launch_bytes, 4) if launch_bytes else None}
+
+
+def cpu_baseline(sample_n: int = 2048) -> dict:
     """The oracle as it stands, on one thread, on the sample workload."""
     from threadpoolctl import threadpool_limits
 
@@ -57,7 +71,7 @@ def cpu_baseline(sample_n: int = 1024) -> dict:
     from oracle.phi_action import leja_phi, power_iteration, shift_scale
     from paper_2310_08344_amd import workloads as W
 
-    p, v = W.config2(n=sample_n)
+    p, v = W.config2(n=sample_n, seed=2)
     x0 = W.start_vector(p.n)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
@@ -69,7 +83,8 @@ def cpu_baseline(sample_n: int = 1024) -> dict:
     scale = (4096 * 4096) / float(p.N)
     return {"value": 3.0 / (t * scale), "unit": "solves/s", "cores": 1, "kind": "oracle",
             "sample": f"phi_1..phi_3 solve incl. power iteration at {sample_n}^2 "
-                      f"({t:.1f} s, sweeps {r.iters}), time scaled by the point ratio {scale:.0f} to 4096^2"}
+                      f"({t:.1f} s on 1 thread, sweeps {r.iters}), time scaled by the point ratio "
+                      f"{scale:.0f} to 4096^2"}
 
 
 def main() -> int:
@@ -77,12 +92,14 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="phi123-4096")
+    ap.add_argument("--n", type=int, default=4096, help="grid side of the phi_1..phi_3 workload")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-calibrate", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the phi-action path is single-GPU (--gpus {args.gpus} "
-              "is not supported; see the sharding notes in the design document)", file=sys.stderr)
+              "is not supported; the design notes describe how it would shard)", file=sys.stderr)
         return 2
 
     import torch
@@ -93,16 +110,28 @@ def main() -> int:
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     lib = B.Library.load()
-    p, v_h = make_workload(args.workload)
-    log("workload", args.workload, "n", p.n, "h", p.h)
+    p, v_h = W.config2(n=args.n)
+    log("workload n", p.n, "h", p.h)
     dev = torch.device("cuda:0")
     v = torch.as_tensor(v_h).to(dev)
     x0 = torch.as_tensor(W.start_vector(p.n)).to(dev)
     outs = [torch.empty_like(v) for _ in range(3)]
-    ctx = lib.context(n_max=p.N, k_max=4)
+    ctx = lib.context(n_max=max(p.N, 1 << 22), k_max=4)
     op = B.make_operator(p)
     ls = [1, 2, 3]
     torch.cuda.synchronize()
+
+    extra = {}
+    if not args.no_calibrate:
+        n_cal = 1 << 26   # 512 MiB per vector: beyond the 256 MB Infinity Cache
+        extra["practical_copy_gbs"] = round(ctx.bandwidth_probe(0, n_cal, 10), 1)
+        extra["practical_axpby_gbs"] = round(ctx.bandwidth_probe(1, n_cal, 10), 1)
+        log("calibration copy", extra["practical_copy_gbs"], "axpby", extra["practical_axpby_gbs"], "GB/s")
+    if not args.no_tune:
+        for K in (3, 2, 1):
+            best = min(ctx.tune(op, K=K, sweeps=8), key=lambda r: r[5])
+            log(f"tuned K={K}: tx {best[0]} ty {best[1]} ry {best[2]} vec {best[3]} workgroups {best[4]} "
+                f"{best[5]:.1f} us")
 
     def step():
         rho, c, g = ctx.spectrum(op, x0=x0, iters=20)
@@ -135,11 +164,16 @@ def main() -> int:
     pw_ms = sum(s["sweep_ms"] for s, _ in recs)
     pw_bytes = sum(s["bytes"] for s, _ in recs)
     last = recs[-1][1]
+    per_launch = leja_bytes / sweeps
+    traffic = committed_traffic(per_launch)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic["bytes_per_launch"] if traffic else None,
             "kernel": "leja_sweep (diffusion-advection, K=3, FP64)",
             "launches": sweeps, "avg_launch_us": round(sweep_ms * 1e3 / sweeps, 2),
-            "bytes_per_launch": leja_bytes / sweeps}
+            "bytes_per_launch": per_launch}
+    if traffic:
+        roof["traffic_ratio_to_algorithmic"] = traffic["ratio_to_algorithmic"]
     out = {
         "metric": "phi-action solves/s at tol 1e-8",
         "value": round(value, 3),
@@ -159,8 +193,10 @@ def main() -> int:
         "hbm_gbs_leja": round(achieved, 1),
         "hbm_gbs_power": round(pw_bytes / (pw_ms * 1e-3) / 1e9, 1) if pw_ms > 0 else None,
         "sweeps": last["iters"][:3],
+        "plan_ms": round(last["plan_ms"], 3),
         "roofline": roof,
     }
+    out.update({k: v for k, v in extra.items() if v is not None})
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline()

@@ -107,11 +107,12 @@ lx_status check_op(lx_ctx* ctx, const lx_operator* op) {
     return LX_OK;
 }
 
-// Launch shape: two columns per lane when the rows allow 16-byte loads,
-// 64 lanes along x when the grid is wide enough, eight-row marches when the
-// grid is tall enough, and at most 2048 workgroups (8 per CU) looping over
-// the tiles.
+// Default launch shape (measured on MI355X with lx_tune at 1024^2..4096^2):
+// two columns per lane when the rows allow 16-byte loads, 64 lanes along x
+// when the grid is wide enough, one row per thread per tile, and 1024
+// workgroups (4 per CU) looping over the tiles.
 Tile choose_tile(int nx, int ny, bool vec2_ok) {
+    (void)ny;
     Tile t;
     t.vec = (vec2_ok && nx % 2 == 0) ? 2 : 1;
     int tx = 64;
@@ -119,13 +120,7 @@ Tile choose_tile(int nx, int ny, bool vec2_ok) {
     t.tx = tx;
     t.ty = lx::kBlockThreads / tx;
     t.ry = 1;
-    for (int ry : {8, 4, 2}) {
-        if (t.ty * ry <= ny) {
-            t.ry = ry;
-            break;
-        }
-    }
-    t.nb = 2048;
+    t.nb = 1024;
     return t;
 }
 
