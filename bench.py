@@ -17,10 +17,12 @@ Prints one JSON line on stdout:
                 every sweep of the timed steps; traffic from the committed
                 rocprofv3 counter summary when it was taken on the current
                 kernel source, else null
+  batched_256   256 uneven instances in one batched call against the plain
+                per-instance path (both with power iteration)
   cpu_baseline  the CPU oracle on a bounded sample (the same solve on a
                 2048^2 grid of the same family, scaled by the point ratio 4)
 
-Usage: python bench.py [--steps K] [--warmup W] [--no-tune] [--no-cpu-baseline]
+Usage: python bench.py [--steps K] [--warmup W] [--no-tune] [--no-batched] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -87,6 +89,59 @@ def cpu_baseline(sample_n: int = 2048) -> dict:
                       f"{scale:.0f} to 4096^2"}
 
 
+def bench_batched(lib, repeats: int = 3) -> dict:
+    """256 uneven diffusion-advection instances (sides 64..512), exp action
+    at rtol 1e-8 with 20 power-iteration sweeps each: one batched call
+    against the plain path (lx_spectrum + lx_phi_leja per instance)."""
+    import torch
+
+    from paper_2310_08344_amd import binding as B
+    from paper_2310_08344_amd import workloads as W
+
+    items = W.batched_instances()
+    dev = torch.device("cuda:0")
+    vs = [torch.as_tensor(u0).to(dev) for _, u0 in items]
+    outs = [torch.empty_like(v) for v in vs]
+    ops = [B.make_operator(p) for p, _ in items]
+    ctx = lib.context(n_max=max(p.N for p, _ in items), k_max=1)
+    args = [dict(op=op, v=v, out=o, l=0, h=p.h) for op, v, o, (p, _) in zip(ops, vs, outs, items)]
+
+    def plain():
+        for op, v, o, (p, _) in zip(ops, vs, outs, items):
+            _, c, g = ctx.spectrum(op, iters=20)
+            ctx.phi_leja(op, v, [o], [0], p.h, c, g, rtol=1e-8, max_iters=300)
+
+    def batched():
+        st, res = ctx.phi_leja_batched(args, power_iters=20, rtol=1e-8, max_iters=300)
+        if st != B.LX_OK:
+            raise RuntimeError(f"batched status {st}")
+        return res
+
+    plain()
+    res = batched()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(repeats):
+        plain()
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / repeats
+    t0 = time.perf_counter()
+    for _ in range(repeats):
+        batched()
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / repeats
+    ctx.close()
+    iters = sorted(r["iters"] for r in res)
+    return {"workload": "256 diffusion-advection instances, sides uniform in {64,128,256,512}, D ~ LogU(0.1,10), "
+                        "|v| ~ U(0,5), h = s x CFL with s ~ LogU(1,50), exp action, rtol 1e-8, 20 power sweeps",
+            "points": int(sum(p.N for p, _ in items)),
+            "batched_solves_per_s": round(len(items) / t_batch, 1),
+            "plain_solves_per_s": round(len(items) / t_plain, 1),
+            "batched_ms": round(t_batch * 1e3, 3), "plain_ms": round(t_plain * 1e3, 3),
+            "speedup_batched_vs_plain": round(t_plain / t_batch, 2),
+            "sweeps_min_median_max": [iters[0], iters[len(iters) // 2], iters[-1]]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +151,7 @@ def main() -> int:
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-calibrate", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the phi-action path is single-GPU (--gpus {args.gpus} "
@@ -197,10 +253,13 @@ def main() -> int:
         "roofline": roof,
     }
     out.update({k: v for k, v in extra.items() if v is not None})
+    ctx.close()
+    if not args.no_batched:
+        log("batched 256-instance comparison")
+        out["batched_256"] = bench_batched(lib)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline()
-    ctx.close()
     print(json.dumps(out), flush=True)
     return 0
 

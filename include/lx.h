@@ -200,6 +200,50 @@ lx_status lx_exprb_step(lx_ctx* ctx, const lx_operator* op, int scheme,
                         double c, double gamma, const lx_leja_opts* o,
                         int* iters);
 
+/* ---- batches of independent problems ---------------------------------- */
+
+/* One problem of a batch: out = phi_l(h A) v for its own operator and data
+ * (Sec. 2.1, Eq. (2); one output per instance). */
+typedef struct {
+    lx_operator op;         /* grid and operator (prec must be LX_FP64)            */
+    const double* d_u;      /* Burgers state, else NULL                             */
+    const double* d_v;      /* input vector (device, op.nx*op.ny), not modified     */
+    double* d_out;          /* output vector (device), distinct from d_v            */
+    const double* d_x0;     /* power-iteration start vector, or NULL: the library's
+                               splitmix64 vector seeded by the instance index        */
+    int l;                  /* phi order 0..8                                       */
+    double h;               /* step > 0                                             */
+    double c, gamma;        /* shift and scale when the batch runs no power
+                               iteration (c <= 0, gamma > 0); ignored otherwise       */
+    int budget;             /* most sweeps for this instance, 1..max_iters;
+                               0 = the batch's max_iters                             */
+} lx_instance;
+
+typedef struct {
+    int status;             /* LX_OK, LX_ENOTCONV (budget reached), LX_ENONFINITE   */
+    int iters;              /* sweeps until the stop rule passed                    */
+    double err;             /* last error estimate                                  */
+    double pnorm;           /* rms norm of the output                               */
+    double rho_hat;         /* power-iteration estimate (0 when none ran)           */
+    double c, gamma;        /* shift and scale that were used                       */
+} lx_instance_result;
+
+/* Computes every instance of a batch with one launch per sweep for the whole
+ * batch: all instances advance together, each with its own stop decision
+ * and budget, and finished instances cost nothing more.  With
+ * power_iters > 0, each instance's spectral bound first comes from
+ * power_iters power-iteration sweeps, and c, gamma follow from safety as in
+ * lx_spectrum (Listing 7); otherwise the instances' c and gamma are used.
+ * The Newton coefficients are computed on the device.  Instances may have
+ * different sizes, operators, data, orders and steps; the caller owns all
+ * vectors.  n: 1..65536 instances.  res: host array of n results.
+ * Returns LX_OK when every instance converged, LX_ENOTCONV when at least
+ * one reached its budget (its output holds the last polynomial),
+ * LX_ENONFINITE when one became non-finite; LX_EINVAL for a bad argument
+ * (naming the instance), LX_ENOMEM when workspaces cannot grow. */
+lx_status lx_phi_leja_batched(lx_ctx* ctx, int n, const lx_instance* inst, int power_iters, double safety,
+                              const lx_leja_opts* o, lx_instance_result* res);
+
 /* ---- launch shapes and measurement ------------------------------------ */
 
 /* Times every candidate launch shape of the fused Leja sweep for this

@@ -56,6 +56,21 @@ class Stats(C.Structure):
                 "bytes": self.bytes}
 
 
+class Instance(C.Structure):
+    _fields_ = [("op", Operator), ("d_u", C.c_void_p), ("d_v", C.c_void_p), ("d_out", C.c_void_p),
+                ("d_x0", C.c_void_p), ("l", C.c_int), ("h", C.c_double), ("c", C.c_double),
+                ("gamma", C.c_double), ("budget", C.c_int)]
+
+
+class InstanceResult(C.Structure):
+    _fields_ = [("status", C.c_int), ("iters", C.c_int), ("err", C.c_double), ("pnorm", C.c_double),
+                ("rho_hat", C.c_double), ("c", C.c_double), ("gamma", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {"status": self.status, "iters": self.iters, "err": self.err, "pnorm": self.pnorm,
+                "rho_hat": self.rho_hat, "c": self.c, "gamma": self.gamma}
+
+
 _P = C.c_void_p
 _D = C.c_double
 _I = C.c_int
@@ -86,6 +101,9 @@ def _signatures(lib: C.CDLL) -> None:
     lib.lx_exprb_step.argtypes = [_P, C.POINTER(Operator), _I, _P, _P, _D, _D, _D,
                                   C.POINTER(LejaOpts), C.POINTER(_I)]
     lib.lx_exprb_step.restype = _I
+    lib.lx_phi_leja_batched.argtypes = [_P, _I, C.POINTER(Instance), _I, _D, C.POINTER(LejaOpts),
+                                        C.POINTER(InstanceResult)]
+    lib.lx_phi_leja_batched.restype = _I
     lib.lx_tune.argtypes = [_P, C.POINTER(Operator), _I, _I, C.c_char_p, C.c_size_t]
     lib.lx_tune.restype = _I
     lib.lx_set_tile.argtypes = [_P, _I, _I, _I, _I, _I]
@@ -102,7 +120,7 @@ def _signatures(lib: C.CDLL) -> None:
 
 EXPORTED = ["lx_create", "lx_destroy", "lx_set_stream", "lx_set_timing", "lx_last_error",
             "lx_status_string", "lx_get_stats", "lx_spectrum", "lx_phi_leja", "lx_exprb_step",
-            "lx_tune", "lx_set_tile", "lx_bandwidth_probe",
+            "lx_phi_leja_batched", "lx_tune", "lx_set_tile", "lx_bandwidth_probe",
             "lx_leja_points", "lx_phi_scalar", "lx_newton_coeffs"]
 
 
@@ -239,6 +257,33 @@ class Context:
         if raise_on_error:
             self._check(st, allow=(LX_OK, LX_ENOTCONV))
         return PhiResult(st, list(it), list(er), self.stats())
+
+    def phi_leja_batched(self, instances, power_iters=0, safety=1.05, rtol=1e-8, atol=0.0, max_iters=500,
+                         raise_on_error=True):
+        """Batched phi actions (lx_phi_leja_batched).  instances: list of
+        dicts with keys op, v, out and optionally u, x0, l (0), h, c, gamma,
+        budget (0).  Returns (status, [result dict per instance])."""
+        n = len(instances)
+        arr = (Instance * n)()
+        keep = []
+        for i, q in enumerate(instances):
+            arr[i].op = q["op"]
+            arr[i].d_u = _ptr(q.get("u"))
+            arr[i].d_v = _ptr(q["v"])
+            arr[i].d_out = _ptr(q["out"])
+            arr[i].d_x0 = _ptr(q.get("x0"))
+            arr[i].l = int(q.get("l", 0))
+            arr[i].h = float(q["h"])
+            arr[i].c = float(q.get("c", 0.0))
+            arr[i].gamma = float(q.get("gamma", 0.0))
+            arr[i].budget = int(q.get("budget", 0))
+            keep.append(q)
+        res = (InstanceResult * n)()
+        opts = LejaOpts(float(rtol), float(atol), int(max_iters), 1e4)
+        st = self.lib.c.lx_phi_leja_batched(self._h, n, arr, int(power_iters), float(safety), C.byref(opts), res)
+        if raise_on_error:
+            self._check(st, allow=(LX_OK, LX_ENOTCONV))
+        return st, [r.as_dict() for r in res]
 
     def exprb_step(self, op: Operator, u, u_out, h, c, gamma, rtol=1e-8, atol=0.0, max_iters=500,
                    fp32_switch=1e4, scheme=LX_EXPRB42, raise_on_error=True) -> PhiResult:

@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "lx.h"
+#include "lx_ctx.h"
 #include "lx_device.h"
 #include "planner.h"
 
@@ -29,37 +30,6 @@ using lx::SweepState;
 using lx::PowerArgs;
 using lx::SweepArgs;
 using lx::Tile;
-
-struct lx_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    size_t n_max = 0;
-    int k_max = 0;
-    int timing = 0;
-    // device workspaces
-    double* ybuf[2] = {nullptr, nullptr};   // Newton basis ping-pong (FP64 or FP32 view)
-    float* u32 = nullptr;                   // Burgers state in FP32 (FP32 sweeps)
-    double* ws[3] = {nullptr, nullptr, nullptr};  // EXPRB42 stages (allocated on first use)
-    double* partials = nullptr;
-    size_t partials_len = 0;
-    LoopCtl* ctl = nullptr;
-    double* coef = nullptr;                 // k_max * kMaxPoints
-    double* xi = nullptr;                   // kMaxPoints
-    int xi_uploaded = 0;
-    // pinned host staging
-    LoopCtl* h_ctl = nullptr;               // initial loop control (pinned)
-    SweepState* h_poll = nullptr;           // [2]: polled final-state slots (pinned)
-    double* h_coef = nullptr;
-    double* h_xi = nullptr;
-    hipEvent_t poll_ev[2] = {nullptr, nullptr};
-    std::vector<hipEvent_t> tev;            // timing events
-    lx::NewtonSeries series[LX_K_MAX];      // per-output divided differences
-    // launch shapes: forced by lx_set_tile, else tuned per (kind, nx, ny, K, prec)
-    Tile forced{0, 0, 0, 0, 0};   // tx == 0: not forced
-    std::map<std::tuple<int, int, int, int, int>, Tile> tuned;
-    lx_stats stats{};
-    std::string err;
-};
 
 namespace {
 
@@ -430,6 +400,25 @@ lx_status check_shift(lx_ctx* ctx, double h, double c, double gamma) {
 
 }  // namespace
 
+lx_status lx_internal_fail(lx_ctx* ctx, lx_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    return fail(ctx, s, "%s", buf);
+}
+lx_status lx_internal_check_op(lx_ctx* ctx, const lx_operator* op, size_t n_limit) {
+    const size_t keep = ctx->n_max;
+    ctx->n_max = n_limit;
+    const lx_status s = check_op(ctx, op);
+    ctx->n_max = keep;
+    return s;
+}
+lx_status lx_internal_ensure_xi(lx_ctx* ctx, int M) { return ensure_xi(ctx, M); }
+lx_status lx_internal_ensure_timing_events(lx_ctx* ctx, size_t n) { return ensure_timing_events(ctx, n); }
+double lx_internal_elapsed(hipEvent_t a, hipEvent_t b) { return elapsed(a, b); }
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -473,6 +462,7 @@ void lx_destroy(lx_ctx* ctx) {
     for (hipEvent_t e : ctx->poll_ev)
         if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->tev) (void)hipEventDestroy(e);
+    lx_internal_free_batch(ctx);
     delete ctx;
 }
 

@@ -87,6 +87,29 @@ struct PowerArgs {
 
 enum OpCode { kOpDiffAdv = 0, kOpBurgersJ = 1 };
 
+// One instance of a batch: its operator, vectors and its share of the
+// workgroups of every batched launch.  c, gamma and rho are written by the
+// batched power iteration when it runs.
+struct BatchInst {
+    int kind;                // OpCode
+    int nx, ny;
+    int vec;                 // columns per lane (2 when nx is even and rows are 16-byte aligned)
+    int l;                   // phi order
+    int tiles_x, tiles_y;
+    int wg_begin, nb;        // workgroups [wg_begin, wg_begin + nb) of each launch
+    int has_x0;              // x0 given; else a splitmix64 vector in y[1]
+    long part_off;           // offset of its partial sums: [2][nb][2]
+    double dx, dy, D, vx, vy, nu;
+    double h, c, gamma, rho;
+    const double* u;
+    const double* v;
+    double* out;
+    const double* x0;
+    double* y[2];            // basis (and power iteration) buffers
+};
+
+constexpr int kBatchTx = 32, kBatchTy = 8;   // workgroup shape of the batched sweeps
+
 // Kernel launchers (kernels.hip).  Each returns the hipError_t of the launch.
 // Sweep m of the Leja loop (m = max_iters only takes the last decision).
 hipError_t launch_leja_sweep(int op, int K, bool fp32_capable, const Tile& t, const SweepArgs& a, int m,
@@ -105,5 +128,19 @@ hipError_t launch_burgers_hF(const double* u, double* out, int nx, int ny, doubl
                              double dy, double h, hipStream_t s);
 hipError_t launch_burgers_remainder(const double* u, const double* U2, double* out, int nx, int ny,
                                     double nu, double dx, double dy, double h, hipStream_t s);
+
+// Batched launches: every workgroup serves the instance block_inst[b].
+hipError_t launch_batch_fill_x0(BatchInst* insts, const int* block_inst, int nblocks, hipStream_t s);
+hipError_t launch_batch_power_norm(const BatchInst* insts, const int* block_inst, int nblocks, double* partials,
+                                   hipStream_t s);
+hipError_t launch_batch_power_sweep(const BatchInst* insts, const int* block_inst, int nblocks, double* partials,
+                                    int k, hipStream_t s);
+hipError_t launch_batch_power_final(BatchInst* insts, int n_inst, const double* partials, int k_last,
+                                    double safety, hipStream_t s);
+hipError_t launch_batch_coeffs(const BatchInst* insts, int n_inst, const double* xi, double* coef, int ld,
+                               hipStream_t s);
+hipError_t launch_batch_sweep(const BatchInst* insts, LoopCtl* ctls, const int* block_inst, int nblocks,
+                              double* partials, const double* coef, int ld, const double* xi, unsigned* done,
+                              int m, hipStream_t s);
 
 }  // namespace lx

@@ -2,6 +2,8 @@
 // differences (Sec. 1 and Sec. 2.1 of arXiv 2310.08344).  Plain C++, no HIP.
 #include "planner.h"
 
+#include "dd_math.h"
+
 #include <algorithm>
 #include <cmath>
 #include <limits>
@@ -181,136 +183,6 @@ bool leja_points(int M, double* out) {
 }
 
 // ---------------------------------------------------------------------------
-// Double-double arithmetic (a value is hi + lo with |lo| <= ulp(hi)/2), from
-// the error-free transformations of Knuth (TwoSum) and Dekker (TwoProduct,
-// here with an FMA) and the double-double algorithms of Hida, Li and Bailey
-// ("Algorithms for quad-double precision floating point arithmetic", 2001).
-// About 32 significant digits.
-// ---------------------------------------------------------------------------
-namespace {
-
-struct dd {
-    double hi, lo;
-};
-
-inline dd two_sum(double a, double b) {
-    const double s = a + b;
-    const double bb = s - a;
-    return {s, (a - (s - bb)) + (b - bb)};
-}
-
-inline dd quick_two_sum(double a, double b) {
-    const double s = a + b;
-    return {s, b - (s - a)};
-}
-
-inline dd two_prod(double a, double b) {
-    const double p = a * b;
-    return {p, std::fma(a, b, -p)};
-}
-
-inline dd dd_add(dd x, dd y) {
-    dd s = two_sum(x.hi, y.hi);
-    dd t = two_sum(x.lo, y.lo);
-    s.lo += t.hi;
-    s = quick_two_sum(s.hi, s.lo);
-    s.lo += t.lo;
-    return quick_two_sum(s.hi, s.lo);
-}
-
-inline dd dd_neg(dd x) { return {-x.hi, -x.lo}; }
-inline dd dd_sub(dd x, dd y) { return dd_add(x, dd_neg(y)); }
-
-inline dd dd_mul(dd x, dd y) {
-    dd p = two_prod(x.hi, y.hi);
-    p.lo += x.hi * y.lo + x.lo * y.hi;
-    return quick_two_sum(p.hi, p.lo);
-}
-
-inline dd dd_mul_d(dd x, double b) {
-    dd p = two_prod(x.hi, b);
-    p.lo += x.lo * b;
-    return quick_two_sum(p.hi, p.lo);
-}
-
-inline dd dd_div(dd x, dd y) {
-    const double q1 = x.hi / y.hi;
-    dd r = dd_sub(x, dd_mul_d(y, q1));
-    const double q2 = r.hi / y.hi;
-    r = dd_sub(r, dd_mul_d(y, q2));
-    const double q3 = r.hi / y.hi;
-    dd q = quick_two_sum(q1, q2);
-    return dd_add(q, dd{q3, 0.0});
-}
-
-inline dd dd_div_d(dd x, double b) { return dd_div(x, dd{b, 0.0}); }
-inline dd dd_ldexp(dd x, int e) { return {std::ldexp(x.hi, e), std::ldexp(x.lo, e)}; }
-
-// ln 2 = kLn2Hi + kLn2Lo to double-double accuracy
-constexpr double kLn2Hi = 6.931471805599452862e-01;
-constexpr double kLn2Lo = 2.319046813846299558e-17;
-
-// e^a - 1 and the power of two it was reduced by: with a = k ln2 + r,
-// |r| <= ln2/2, returns s = e^r - 1 (r scaled by 2^-10, Taylor series to
-// order 12, then ten doublings e^{2x} - 1 = 2(e^x - 1) + (e^x - 1)^2) and k.
-dd expm1_reduced(dd a, int* k_out) {
-    const double k = std::nearbyint(a.hi / kLn2Hi);
-    dd r = dd_sub(a, dd_add(two_prod(k, kLn2Hi), two_prod(k, kLn2Lo)));
-    r = dd_ldexp(r, -10);
-    dd term = r, s = r;
-    for (int n = 2; n <= 12; ++n) {
-        term = dd_div_d(dd_mul(term, r), static_cast<double>(n));
-        s = dd_add(s, term);
-    }
-    for (int i = 0; i < 10; ++i) s = dd_add(dd_mul_d(s, 2.0), dd_mul(s, s));
-    *k_out = static_cast<int>(k);
-    return s;
-}
-
-dd dd_exp(dd a) {
-    if (a.hi < -1000.0) return {0.0, 0.0};
-    int k = 0;
-    const dd s = expm1_reduced(a, &k);
-    return dd_ldexp(dd_add(s, dd{1.0, 0.0}), k);
-}
-
-dd dd_expm1(dd a) {
-    if (a.hi < -1000.0) return {-1.0, 0.0};
-    int k = 0;
-    const dd s = expm1_reduced(a, &k);
-    if (k == 0) return s;
-    return dd_sub(dd_ldexp(dd_add(s, dd{1.0, 0.0}), k), dd{1.0, 0.0});
-}
-
-// phi_l(z) in double-double (Sec. 1): the Taylor series sum_k z^k/(k+l)!
-// while its terms decrease monotonically (|z| < max(1.5, l)), otherwise
-// phi_1 = expm1(z)/z and the recursion phi_{k+1} = (phi_k - 1/k!)/z.
-dd dd_phi(int l, dd z) {
-    dd inv_fact_l{1.0, 0.0};
-    for (int k = 2; k <= l; ++k) inv_fact_l = dd_div_d(inv_fact_l, static_cast<double>(k));
-    if (z.hi == 0.0) return inv_fact_l;
-    if (std::fabs(z.hi) < std::max(1.5, static_cast<double>(l))) {
-        constexpr int kTerms = 60;
-        dd coef[kTerms + 1];
-        coef[0] = inv_fact_l;
-        for (int k = 1; k <= kTerms; ++k) coef[k] = dd_div_d(coef[k - 1], static_cast<double>(k + l));
-        dd acc{0.0, 0.0};
-        for (int k = kTerms; k >= 0; --k) acc = dd_add(dd_mul(acc, z), coef[k]);
-        return acc;
-    }
-    if (l == 0) return dd_exp(z);
-    dd val = dd_div(dd_expm1(z), z);          // phi_1
-    dd inv_fact{1.0, 0.0};                    // 1/k! for k = 1
-    for (int k = 1; k < l; ++k) {
-        val = dd_div(dd_sub(val, inv_fact), z);
-        inv_fact = dd_div_d(inv_fact, static_cast<double>(k + 1));
-    }
-    return val;
-}
-
-}  // namespace
-
-// ---------------------------------------------------------------------------
 // Newton coefficients (Sec. 2.1, Eq. (2)): the divided differences
 // d_j = f[xi_0, ..., xi_j] of f(xi) = sigma * phi_l(alpha*h*(c + gamma*xi)).
 // The Newton basis at Leja points can grow by many orders of magnitude while
@@ -322,9 +194,7 @@ dd dd_phi(int l, dd z) {
 // ---------------------------------------------------------------------------
 struct NewtonSeries::Impl {
     std::vector<dd> row;
-    dd ah{0.0, 0.0};
-    dd sigma{1.0, 0.0};
-    double c = 0.0, gamma = 0.0;
+    double alpha = 1.0, h = 0.0, sigma = 1.0, c = 0.0, gamma = 0.0;
     int l = 0;
 };
 
@@ -333,8 +203,9 @@ NewtonSeries::~NewtonSeries() { delete impl_; }
 
 void NewtonSeries::reset(int l, double alpha, double sigma, double h, double c, double gamma, const double* xi) {
     impl_->row.clear();
-    impl_->ah = two_prod(alpha, h);
-    impl_->sigma = dd{sigma, 0.0};
+    impl_->alpha = alpha;
+    impl_->h = h;
+    impl_->sigma = sigma;
     impl_->c = c;
     impl_->gamma = gamma;
     impl_->l = l;
@@ -346,10 +217,7 @@ double NewtonSeries::next() {
     Impl& s = *impl_;
     const int J = count_;
     const double x = xi_[J];
-    // z = alpha h (c + gamma xi_J) in double-double
-    const dd t = dd_add(dd{s.c, 0.0}, two_prod(s.gamma, x));
-    const dd f = dd_mul(s.sigma, dd_phi(s.l, dd_mul(s.ah, t)));
-    s.row.push_back(f);
+    s.row.push_back(dd_phi_at(s.l, s.alpha, s.sigma, s.h, s.c, s.gamma, x));
     for (int i = J - 1; i >= 0; --i) {
         const dd diff = two_sum(x, -xi_[i]);   // exact
         s.row[i] = dd_div(dd_sub(s.row[i + 1], s.row[i]), diff);

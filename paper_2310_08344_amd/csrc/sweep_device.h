@@ -1,0 +1,387 @@
+// Device building blocks of the Leja sweeps, shared by the single-grid
+// kernels (kernels.hip) and the batched kernels (batch.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lx_device.h"
+
+namespace lx {
+namespace dev {
+
+
+__device__ __forceinline__ int wrap(int r, int n) {
+    if (r < 0) r += n;
+    else if (r >= n) r -= n;
+    if (r >= n) r %= n;      // only when a tile is taller than the grid
+    return r;
+}
+
+// Calls f(tile) for the tiles of this workgroup.  With nb a multiple of 8,
+// workgroup b runs on XCD b % 8 and takes every (nb/8)-th tile of that XCD's
+// contiguous band, so that concurrently running workgroups of one XCD work
+// on neighbouring tiles.
+template <typename F>
+__device__ __forceinline__ void for_each_tile(int T, int nb, F&& f) {
+    const int b = static_cast<int>(blockIdx.x);
+    if (nb >= 8 && (nb & 7) == 0) {
+        const int x = b & 7, j = b >> 3, nbx = nb >> 3;
+        const int lo = static_cast<int>((static_cast<long>(x) * T) >> 3);
+        const int hi = static_cast<int>((static_cast<long>(x + 1) * T) >> 3);
+        for (int t = lo + j; t < hi; t += nbx) f(t);
+    } else {
+        for (int t = b; t < T; t += nb) f(t);
+    }
+}
+
+__device__ __forceinline__ int flat_tid() { return threadIdx.x + threadIdx.y * blockDim.x; }
+__device__ __forceinline__ int block_threads() { return blockDim.x * blockDim.y; }
+
+template <typename T> struct Pair;
+template <> struct Pair<double> { using type = double2; };
+template <> struct Pair<float> { using type = float2; };
+
+template <int V, typename T, typename A>
+__device__ __forceinline__ void ldv(const T* __restrict__ p, A (&o)[V]) {
+    if constexpr (V == 2) {
+        const auto t = *reinterpret_cast<const typename Pair<T>::type*>(p);
+        o[0] = static_cast<A>(t.x);
+        o[1] = static_cast<A>(t.y);
+    } else {
+        o[0] = static_cast<A>(p[0]);
+    }
+}
+
+template <int V, typename T>
+__device__ __forceinline__ void stv(T* __restrict__ p, const T (&o)[V]) {
+    if constexpr (V == 2) {
+        typename Pair<T>::type t;
+        t.x = o[0];
+        t.y = o[1];
+        *reinterpret_cast<typename Pair<T>::type*>(p) = t;
+    } else {
+        p[0] = o[0];
+    }
+}
+
+// Sums NV values over the workgroup in a fixed order (butterfly within each
+// 64-lane wavefront, then wavefronts in index order); every thread receives
+// the result.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV]) {
+    __shared__ double red[NV][kBlockThreads / 64];
+    __shared__ double out[NV];
+    const int tid = flat_tid();
+    const int lane = tid & 63, wid = tid >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double x = v[q];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+        v[q] = x;
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) red[q][wid] = v[q];
+    }
+    __syncthreads();
+    if (tid < NV) {
+        const int nw = (block_threads() + 63) >> 6;
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += red[tid][w];
+        out[tid] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = out[q];
+    __syncthreads();
+}
+
+// Adds the nb partial records of NV values written by the previous launch,
+// in workgroup-index order per lane and then block_sum's fixed tree: every
+// workgroup of the grid obtains bitwise the same totals.
+template <int NV>
+__device__ __forceinline__ void sum_partials(const double* __restrict__ P, int nb, double (&tot)[NV]) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) tot[q] = 0.0;
+    for (int b = flat_tid(); b < nb; b += block_threads()) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) tot[q] += P[b * NV + q];
+    }
+    block_sum<NV>(tot);
+}
+
+// ---------------------------------------------------------------------------
+// Leja sweep
+// ---------------------------------------------------------------------------
+
+template <int OP, int K, int RY, int V, typename TI, typename TO, typename AT>
+__device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int m, const int (&act)[K],
+                                           double& sy, double (&sp)[K], const int tile) {
+    const int nx = a.nx, ny = a.ny;
+    const int tile_x = tile % a.tiles_x, tile_y = tile / a.tiles_x;
+    const int col = (tile_x * static_cast<int>(blockDim.x) + static_cast<int>(threadIdx.x)) * V;
+    const bool colok = col < nx;
+    const int c0 = colok ? col : 0;
+    const int cl = (c0 == 0) ? nx - 1 : c0 - 1;
+    const int cr = (c0 + V >= nx) ? c0 + V - nx : c0 + V;
+    const int row0 = tile_y * static_cast<int>(blockDim.y) * RY + static_cast<int>(threadIdx.y) * RY;
+
+    const TI* __restrict__ yin;
+    if constexpr (sizeof(TI) == sizeof(double)) {
+        yin = (m == 0) ? reinterpret_cast<const TI*>(a.v) : static_cast<const TI*>(a.ybuf[(m - 1) & 1]);
+    } else {
+        yin = static_cast<const TI*>(a.ybuf[(m - 1) & 1]);
+    }
+    TO* __restrict__ yout = static_cast<TO*>(a.ybuf[m & 1]);
+
+    double* __restrict__ pk[K];
+    const double* __restrict__ bk[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        pk[k] = a.p[k];
+        bk[k] = a.base[k];
+    }
+    const double* __restrict__ uu = a.u;
+    const float* __restrict__ uu32 = a.u32;
+    const double xim = a.xi[m];
+    double dn1[K], d0[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        dn1[k] = a.coef[k * a.ld + m + 1];
+        d0[k] = a.coef[k * a.ld];
+    }
+
+    AT up[V], cen[V], dn[V];
+    AT uup[V], ucen[V], udn[V];
+    ldv<V>(yin + static_cast<long>(wrap(row0 - 1, ny)) * nx + c0, up);
+    ldv<V>(yin + static_cast<long>(wrap(row0, ny)) * nx + c0, cen);
+    if constexpr (OP == kOpBurgersJ) {
+        if constexpr (sizeof(AT) == sizeof(double)) {
+            ldv<V>(uu + static_cast<long>(wrap(row0 - 1, ny)) * nx + c0, uup);
+            ldv<V>(uu + static_cast<long>(wrap(row0, ny)) * nx + c0, ucen);
+        } else {
+            ldv<V>(uu32 + static_cast<long>(wrap(row0 - 1, ny)) * nx + c0, uup);
+            ldv<V>(uu32 + static_cast<long>(wrap(row0, ny)) * nx + c0, ucen);
+        }
+    }
+
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        const int row = row0 + r;
+        const bool ok = colok && row < ny;
+        const long rw = wrap(row, ny);
+        const long rn = wrap(row + 1, ny);
+        ldv<V>(yin + rn * nx + c0, dn);
+        const AT left = static_cast<AT>(yin[rw * nx + cl]);
+        const AT right = static_cast<AT>(yin[rw * nx + cr]);
+        AT o[V];
+        if constexpr (OP == kOpDiffAdv) {
+            const AT aE = static_cast<AT>(a.aE), aW = static_cast<AT>(a.aW);
+            const AT aN = static_cast<AT>(a.aN), aS = static_cast<AT>(a.aS);
+            const AT ac = static_cast<AT>(a.aC - xim);
+            if constexpr (V == 2) {
+                o[0] = aW * left + aE * cen[1] + aS * up[0] + aN * dn[0] + ac * cen[0];
+                o[1] = aW * cen[0] + aE * right + aS * up[1] + aN * dn[1] + ac * cen[1];
+            } else {
+                o[0] = aW * left + aE * right + aS * up[0] + aN * dn[0] + ac * cen[0];
+            }
+        } else {
+            const AT kx = static_cast<AT>(a.kx), ky = static_cast<AT>(a.ky);
+            const AT gx = static_cast<AT>(a.gx), gy = static_cast<AT>(a.gy);
+            const AT kc = static_cast<AT>(a.kC - xim);
+            AT ul, ur;
+            if constexpr (sizeof(AT) == sizeof(double)) {
+                ldv<V>(uu + rn * nx + c0, udn);
+                ul = uu[rw * nx + cl];
+                ur = uu[rw * nx + cr];
+            } else {
+                ldv<V>(uu32 + rn * nx + c0, udn);
+                ul = uu32[rw * nx + cl];
+                ur = uu32[rw * nx + cr];
+            }
+            if constexpr (V == 2) {
+                o[0] = kx * (cen[1] + left) + ky * (dn[0] + up[0]) - gx * (ucen[1] * cen[1] - ul * left) -
+                       gy * (udn[0] * dn[0] - uup[0] * up[0]) + kc * cen[0];
+                o[1] = kx * (right + cen[0]) + ky * (dn[1] + up[1]) - gx * (ur * right - ucen[0] * cen[0]) -
+                       gy * (udn[1] * dn[1] - uup[1] * up[1]) + kc * cen[1];
+            } else {
+                o[0] = kx * (right + left) + ky * (dn[0] + up[0]) - gx * (ur * right - ul * left) -
+                       gy * (udn[0] * dn[0] - uup[0] * up[0]) + kc * cen[0];
+            }
+        }
+        TO ot[V];
+        double od[V];
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            ot[i] = static_cast<TO>(o[i]);
+            od[i] = static_cast<double>(ot[i]);
+        }
+        const long idx = rw * nx + c0;
+        if (ok) {
+            stv<V>(yout + idx, ot);
+#pragma unroll
+            for (int i = 0; i < V; ++i) sy += od[i] * od[i];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (!act[k]) continue;
+            double pv[V];
+            if (m == 0) {
+                // p_0 = d_0 y_0 (+ optional base); y_0 = v is the centre row
+#pragma unroll
+                for (int i = 0; i < V; ++i) pv[i] = d0[k] * static_cast<double>(cen[i]);
+                if (bk[k] != nullptr) {
+                    double bv[V];
+                    ldv<V>(bk[k] + idx, bv);
+#pragma unroll
+                    for (int i = 0; i < V; ++i) pv[i] += bv[i];
+                }
+            } else {
+                ldv<V>(pk[k] + idx, pv);
+            }
+#pragma unroll
+            for (int i = 0; i < V; ++i) pv[i] = fma(dn1[k], od[i], pv[i]);
+            if (ok) {
+                stv<V>(pk[k] + idx, pv);
+#pragma unroll
+                for (int i = 0; i < V; ++i) sp[k] += pv[i] * pv[i];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            up[i] = cen[i];
+            cen[i] = dn[i];
+            if constexpr (OP == kOpBurgersJ) {
+                uup[i] = ucen[i];
+                ucen[i] = udn[i];
+            }
+        }
+    }
+}
+
+// Stop rule (Sec. 2.2) after sweep m-1, from the grid totals of its partial
+// sums: the state entering sweep m.  tot = {sum y_m^2, sum p_k^2 ...}.
+template <int K, bool FP32>
+__device__ __forceinline__ SweepState decide(const SweepArgs& a, const LoopCtl& ctl, const SweepState& prev,
+                                             const int m, const double (&tot)[1 + K]) {
+    SweepState nx = prev;
+    nx.iter = m;
+    nx.n_fp32 = prev.n_fp32 + prev.out32;
+    nx.in32 = prev.out32;
+    const double ynorm = sqrt(tot[0]) * a.inv_sqrtN;
+    nx.ynorm = ynorm;
+    bool nonfinite = !isfinite(ynorm);
+    bool any_active = false, all_small = true;
+    const double rtol = ctl.rtol, atol = ctl.atol, sw = ctl.fp32_switch;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (!prev.active[k]) continue;
+        const double pn = sqrt(tot[1 + k]) * a.inv_sqrtN;
+        const double e = fabs(a.coef[k * a.ld + m]) * ynorm;
+        const double thr = rtol * pn + atol;
+        nx.err[k] = e;
+        nx.pnorm[k] = pn;
+        if (!isfinite(pn) || !isfinite(e)) {
+            nonfinite = true;
+            nx.active[k] = 0;
+            nx.iters[k] = m;
+        } else if (e <= thr) {
+            nx.active[k] = 0;
+            nx.iters[k] = m;
+        } else {
+            any_active = true;
+            if (!(e <= sw * thr)) all_small = false;
+        }
+    }
+    if (FP32 && !prev.out32 && any_active && all_small && sw >= 0.0) nx.out32 = 1;
+    if (nonfinite) {
+        nx.status = 4;  // LX_ENONFINITE
+        nx.done = 1;
+    } else if (!any_active) {
+        nx.status = 0;
+        nx.done = 1;
+    } else if (m >= ctl.max_iters) {
+        nx.status = 3;  // LX_ENOTCONV
+        nx.done = 1;
+    }
+    return nx;
+}
+
+// ---------------------------------------------------------------------------
+// power iteration: w_{k+1} = (A w_k) / ||w_k||; ||w_k|| comes from the
+// partial sums of the previous launch (the start-vector norm for k = 0)
+// ---------------------------------------------------------------------------
+
+template <int OP, int RY, int V>
+__device__ __forceinline__ void power_tile(const PowerArgs& a, const double s, double& acc, const int tile) {
+    const int nx = a.nx, ny = a.ny;
+    const int tile_x = tile % a.tiles_x, tile_y = tile / a.tiles_x;
+    const int col = (tile_x * static_cast<int>(blockDim.x) + static_cast<int>(threadIdx.x)) * V;
+    const bool colok = col < nx;
+    const int c0 = colok ? col : 0;
+    const int cl = (c0 == 0) ? nx - 1 : c0 - 1;
+    const int cr = (c0 + V >= nx) ? c0 + V - nx : c0 + V;
+    const int row0 = tile_y * static_cast<int>(blockDim.y) * RY + static_cast<int>(threadIdx.y) * RY;
+    const double* __restrict__ in = a.in;
+    const double* __restrict__ uu = a.u;
+    double* __restrict__ out = a.out;
+
+    double up[V], cen[V], dn[V], uup[V], ucen[V], udn[V];
+    ldv<V>(in + static_cast<long>(wrap(row0 - 1, ny)) * nx + c0, up);
+    ldv<V>(in + static_cast<long>(wrap(row0, ny)) * nx + c0, cen);
+    if constexpr (OP == kOpBurgersJ) {
+        ldv<V>(uu + static_cast<long>(wrap(row0 - 1, ny)) * nx + c0, uup);
+        ldv<V>(uu + static_cast<long>(wrap(row0, ny)) * nx + c0, ucen);
+    }
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        const int row = row0 + r;
+        const bool ok = colok && row < ny;
+        const long rw = wrap(row, ny);
+        const long rn = wrap(row + 1, ny);
+        ldv<V>(in + rn * nx + c0, dn);
+        const double left = in[rw * nx + cl], right = in[rw * nx + cr];
+        double o[V];
+        if constexpr (OP == kOpDiffAdv) {
+            if constexpr (V == 2) {
+                o[0] = a.cW * left + a.cE * cen[1] + a.cS * up[0] + a.cN * dn[0] + a.cC * cen[0];
+                o[1] = a.cW * cen[0] + a.cE * right + a.cS * up[1] + a.cN * dn[1] + a.cC * cen[1];
+            } else {
+                o[0] = a.cW * left + a.cE * right + a.cS * up[0] + a.cN * dn[0] + a.cC * cen[0];
+            }
+        } else {
+            ldv<V>(uu + rn * nx + c0, udn);
+            const double ul = uu[rw * nx + cl], ur = uu[rw * nx + cr];
+            const double kc = -2.0 * a.kx - 2.0 * a.ky;
+            if constexpr (V == 2) {
+                o[0] = a.kx * (cen[1] + left) + a.ky * (dn[0] + up[0]) - a.gx * (ucen[1] * cen[1] - ul * left) -
+                       a.gy * (udn[0] * dn[0] - uup[0] * up[0]) + kc * cen[0];
+                o[1] = a.kx * (right + cen[0]) + a.ky * (dn[1] + up[1]) - a.gx * (ur * right - ucen[0] * cen[0]) -
+                       a.gy * (udn[1] * dn[1] - uup[1] * up[1]) + kc * cen[1];
+            } else {
+                o[0] = a.kx * (right + left) + a.ky * (dn[0] + up[0]) - a.gx * (ur * right - ul * left) -
+                       a.gy * (udn[0] * dn[0] - uup[0] * up[0]) + kc * cen[0];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < V; ++i) o[i] *= s;
+        if (ok) {
+            stv<V>(out + rw * nx + c0, o);
+#pragma unroll
+            for (int i = 0; i < V; ++i) acc += o[i] * o[i];
+        }
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            up[i] = cen[i];
+            cen[i] = dn[i];
+            if constexpr (OP == kOpBurgersJ) {
+                uup[i] = ucen[i];
+                ucen[i] = udn[i];
+            }
+        }
+    }
+}
+
+}  // namespace dev
+}  // namespace lx

@@ -1,0 +1,189 @@
+"""GPU parity of batched phi actions (lx_phi_leja_batched) against the
+oracle, instance by instance, through the C ABI.
+
+Each instance of a batch must match a separate oracle run on its own data
+(relative L2 <= 1e-10, equal sweep counts up to a borderline stop
+decision).  Batches mix grid sizes (including odd and ragged ones),
+operators, phi orders and steps; the full 256-instance workload is checked
+on a sample against the oracle and on every instance through the sum
+invariant.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.operators import burgers_J, diffadv_apply
+from oracle.phi_action import leja_phi, power_iteration, shift_scale
+from paper_2310_08344_amd import binding as B
+from paper_2310_08344_amd import workloads as W
+from tests.gpu_helpers import dev, host, oracle_parity, rel, say
+
+pytestmark = pytest.mark.gpu
+
+PARITY = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ctx(lx):
+    c = lx.context(n_max=1 << 16, k_max=4)
+    yield c
+    c.close()
+
+
+def splitmix_vector(seed, n):
+    """splitmix64 (Steele, Lea and Flood 2014) at positions 0..n-1 of a
+    stream with the given seed, mapped to [-1, 1) as the library does."""
+    t = np.arange(n, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (t + np.uint64(1)) * np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return (z >> np.uint64(11)).astype(np.float64) * 2.0**-52 - 1.0
+
+
+def _mixed_batch(seed=0):
+    rng = np.random.default_rng(seed)
+    specs = [(64, 64, "da"), (96, 40, "da"), (33, 17, "da"), (128, 128, "bu"), (130, 66, "da"),
+             (8, 8, "da"), (200, 136, "bu"), (75, 97, "da"), (256, 256, "da"), (50, 50, "bu")]
+    inst = []
+    for i, (nx, ny, kind) in enumerate(specs):
+        dx, dy = 1.0 / nx, 1.0 / ny
+        v = rng.standard_normal((ny, nx))
+        if kind == "da":
+            D = float(np.exp(rng.uniform(np.log(0.1), np.log(10.0))))
+            sp, ang = rng.uniform(0, 5), rng.uniform(0, 2 * np.pi)
+            vx, vy = sp * np.cos(ang), sp * np.sin(ang)
+            op = B.make_operator(kind=B.LX_OP_DIFFADV2D, nx=nx, ny=ny, dx=dx, dy=dy, D=D, vx=vx, vy=vy)
+            rho = 2.0 / W.diffadv_cfl_step(D, vx, vy, dx, dy)
+            A = (lambda D, vx, vy, dx, dy: (lambda y: diffadv_apply(y, D, vx, vy, dx, dy)))(D, vx, vy, dx, dy)
+            u = None
+        else:
+            nu = 2e-3
+            u = W.fourier_modes(max(nx, ny), seed=10 + i)[:ny, :nx] + 0.2
+            op = B.make_operator(kind=B.LX_OP_BURGERS2D, nx=nx, ny=ny, dx=dx, dy=dy, nu=nu)
+            rho = 2.0 / W.burgers_cfl_step(nu, float(np.max(np.abs(u))), dx, dy)
+            A = (lambda u, nu, dx, dy: (lambda w: burgers_J(u, w, nu, dx, dy)))(u, nu, dx, dy)
+        # advection-dominated Burgers Jacobians have strongly imaginary
+        # spectra, where interpolation on the real interval needs many more
+        # sweeps: their steps stay at most 10 x CFL
+        s = float(np.exp(rng.uniform(0.0, np.log(40.0 if kind == "da" else 10.0))))
+        h = 2.0 * s / rho
+        c, g = shift_scale(rho)
+        inst.append(dict(nx=nx, ny=ny, op=op, A=A, u=u, v=v, l=int(rng.integers(0, 4)), h=h, c=c, gamma=g))
+    return inst
+
+
+def _run(ctx, inst, power_iters=0, x0s=None, budgets=None, **kw):
+    outs = [dev(np.zeros((q["ny"], q["nx"]))) for q in inst]
+    args = []
+    for i, q in enumerate(inst):
+        a = dict(op=q["op"], v=dev(q["v"]), out=outs[i], l=q["l"], h=q["h"], c=q["c"], gamma=q["gamma"])
+        if q["u"] is not None:
+            a["u"] = dev(q["u"])
+        if x0s is not None and x0s[i] is not None:
+            a["x0"] = dev(x0s[i])
+        if budgets is not None:
+            a["budget"] = budgets[i]
+        args.append(a)
+    st, res = ctx.phi_leja_batched(args, power_iters=power_iters, **kw)
+    return st, res, [host(o) for o in outs]
+
+
+def test_mixed_batch_matches_oracle_per_instance(ctx):
+    inst = _mixed_batch(0)
+    say("mixed batch", len(inst))
+    st, res, outs = _run(ctx, inst, rtol=1e-8, max_iters=200)
+    assert st == B.LX_OK
+    for q, r, o in zip(inst, res, outs):
+        assert r["status"] == B.LX_OK
+        oracle_parity([o], [r["iters"]],
+                      lambda f, q=q: leja_phi(q["A"], q["v"], [(q["l"], 1.0, 1.0)], q["h"], q["c"], q["gamma"],
+                                              1e-8, 0.0, 200, f), PARITY)
+
+
+def test_batched_power_iteration_matches_oracle(ctx):
+    inst = _mixed_batch(1)
+    rng = np.random.default_rng(5)
+    x0s = [rng.standard_normal((q["ny"], q["nx"])) if i % 2 == 0 else None for i, q in enumerate(inst)]
+    say("batched power iteration")
+    st, res, outs = _run(ctx, inst, power_iters=20, x0s=x0s, rtol=1e-8, max_iters=250)
+    assert st == B.LX_OK
+    for i, (q, r, o) in enumerate(zip(inst, res, outs)):
+        x0 = x0s[i] if x0s[i] is not None else splitmix_vector(i, q["nx"] * q["ny"]).reshape(q["ny"], q["nx"])
+        rho_o, _ = power_iteration(q["A"], x0, 20)
+        assert abs(r["rho_hat"] - rho_o) <= 1e-12 * rho_o, (i, r["rho_hat"], rho_o)
+        c, g = shift_scale(r["rho_hat"])
+        assert r["c"] == c and r["gamma"] == g
+        oracle_parity([o], [r["iters"]],
+                      lambda f, q=q, c=c, g=g: leja_phi(q["A"], q["v"], [(q["l"], 1.0, 1.0)], q["h"], c, g,
+                                                        1e-8, 0.0, 250, f), PARITY)
+
+
+def test_budgets_stop_instances_with_notconv(ctx):
+    inst = _mixed_batch(2)[:5]
+    budgets = [3, 0, 2, 0, 1]
+    say("budgets")
+    st, res, outs = _run(ctx, inst, budgets=budgets, rtol=1e-10, max_iters=200)
+    assert st == B.LX_ENOTCONV
+    for q, b, r, o in zip(inst, budgets, res, outs):
+        if b == 0:
+            assert r["status"] == B.LX_OK
+            continue
+        assert r["status"] == B.LX_ENOTCONV and r["iters"] == b
+        ref = leja_phi(q["A"], q["v"], [(q["l"], 1.0, 1.0)], q["h"], q["c"], q["gamma"], 1e-10, 0.0, b)
+        assert rel(o, ref.p[0]) <= PARITY
+
+
+def test_batch_equals_single_instance_path(ctx):
+    inst = _mixed_batch(3)[:4]
+    st, res, outs = _run(ctx, inst, rtol=1e-9, max_iters=200)
+    for q, r, o in zip(inst, res, outs):
+        out = dev(np.zeros((q["ny"], q["nx"])))
+        kw = {"u": dev(q["u"])} if q["u"] is not None else {}
+        rs = ctx.phi_leja(q["op"], dev(q["v"]), [out], [q["l"]], q["h"], q["c"], q["gamma"], rtol=1e-9,
+                          max_iters=200, **kw)
+        assert rs.iters[0] == r["iters"]
+        assert rel(o, host(out)) <= 1e-12
+
+
+def test_batch_rejects_bad_instances(ctx):
+    inst = _mixed_batch(4)[:2]
+    bad = dict(inst[0])
+    bad["h"] = -1.0
+    st, _, _ = _run(ctx, [inst[1], bad], raise_on_error=False)
+    assert st == B.LX_EINVAL
+    assert "instance 1" in ctx.last_error()
+
+
+def test_full_256_instance_workload(lx):
+    items = W.batched_instances()
+    n_tot = sum(p.N for p, _ in items)
+    say("256-instance workload", n_tot, "points")
+    with lx.context(n_max=1 << 16, k_max=1) as ctx:
+        args, outs, vs = [], [], []
+        for i, (p, u0) in enumerate(items):
+            rho = 2.0 / W.diffadv_cfl_step(p.D, p.vx, p.vy, p.dx, p.dy)
+            c, g = shift_scale(rho)
+            o = dev(np.zeros_like(u0))
+            vs.append(u0)
+            outs.append(o)
+            args.append(dict(op=B.make_operator(p), v=dev(u0), out=o, l=0, h=p.h, c=c, gamma=g))
+        st, res = ctx.phi_leja_batched(args, rtol=1e-8, max_iters=300)
+    assert st == B.LX_OK
+    iters = [r["iters"] for r in res]
+    say("sweeps min/median/max", min(iters), int(np.median(iters)), max(iters))
+    # every instance: the sum invariant of the exp action (the periodic
+    # stencil conserves the sum and xi_0 = 2 is a node)
+    for v, o in zip(vs, outs):
+        ho = host(o)
+        assert abs(ho.sum() - v.sum()) <= 1e-12 * np.abs(v).sum()
+    # a sample against the oracle
+    for i in range(0, 256, 37):
+        p, u0 = items[i]
+        A = lambda y, p=p: diffadv_apply(y, p.D, p.vx, p.vy, p.dx, p.dy)
+        c, g = res[i]["c"], res[i]["gamma"]
+        oracle_parity([host(outs[i])], [res[i]["iters"]],
+                      lambda f, A=A, u0=u0, p=p, c=c, g=g: leja_phi(A, u0, [(0, 1.0, 1.0)], p.h, c, g, 1e-8, 0.0,
+                                                                    300, f), PARITY)
