@@ -244,6 +244,68 @@ typedef struct {
 lx_status lx_phi_leja_batched(lx_ctx* ctx, int n, const lx_instance* inst, int power_iters, double safety,
                               const lx_leja_opts* o, lx_instance_result* res);
 
+/* ---- learned spectral bound and sweep budget ------------------------- */
+
+/* A small MLP (8 -> 64 -> 64 -> 2, ReLU, float32 weights, bfloat16 hidden
+ * activations) predicting, from 8 features of an instance, the scaled
+ * spectral bound log(safety * rho_hat) and the sweep count log(iters) of the
+ * plain method.  Trained on records the plain method produces (power
+ * iteration and batched Leja runs); a prediction is accepted only when the
+ * Leja loop converges within the predicted budget, and power iteration is
+ * the fallback.  The paper has no learned component.
+ * Features (lx_instance_features): log D, log(|v| + 1e-3), atan2(vy, vx),
+ * log dx, log h, log rms(u), log max|u|, l, where u is the input vector of a
+ * diffusion-advection instance and the state of a Burgers instance, for
+ * which D := nu, |v| := sqrt(2) max|u| and the angle is pi/4.
+ * State vector (get/set/save/load): parameters W1[64][8], b1[64],
+ * W2[64][64], b2[64], W3[2][64], b3[2], then the Adam moments m and v in
+ * the same layout, the standardisation (mean_x[8], std_x[8], mean_y[2],
+ * std_y[2]) and the Adam step count: LX_MLP_STATE floats. */
+#define LX_MLP_PARAMS 4866
+#define LX_MLP_STATE (3 * LX_MLP_PARAMS + 21)
+
+typedef struct lx_predictor lx_predictor;
+
+/* Creates a predictor on the context's device and stream: He-uniform weights
+ * from a splitmix64 stream of the given seed, zero biases and moments,
+ * identity standardisation. */
+lx_status lx_predictor_create(lx_ctx* ctx, unsigned long long seed, lx_predictor** out);
+void lx_predictor_destroy(lx_predictor* p);
+int lx_predictor_state_size(void);
+
+/* Input and target standardisation, x_std = (x - mean)/std (host arrays of
+ * 8, 8, 2, 2 floats; std > 0). */
+lx_status lx_predictor_set_scaling(lx_predictor* p, const float* mean_x, const float* std_x,
+                                   const float* mean_y, const float* std_y);
+
+/* Host copies of the whole state, and the same as a binary file (an 8-byte
+ * tag, the float count, the floats): checkpoint and resume. */
+lx_status lx_predictor_get_state(const lx_predictor* p, float* state);
+lx_status lx_predictor_set_state(lx_predictor* p, const float* state);
+lx_status lx_predictor_save(const lx_predictor* p, const char* path);
+lx_status lx_predictor_load(lx_predictor* p, const char* path);
+
+/* Mean squared error over n samples and both outputs of the standardised
+ * targets, and its gradient (host, LX_MLP_PARAMS floats; NULL to skip).
+ * d_x: device [n][8] raw features, d_y: device [n][2] raw targets. */
+lx_status lx_predictor_gradient(lx_predictor* p, const float* d_x, const float* d_y, int n, float* grad,
+                                double* loss);
+
+/* steps Adam steps (learning rate lr, beta 0.9/0.999, eps 1e-8) on
+ * minibatches of `batch` samples: the host array order (steps * batch
+ * indices) when given, else epochs of a splitmix64-driven shuffle of seed.
+ * final_loss: the last minibatch's loss (host, may be NULL). */
+lx_status lx_predictor_train(lx_predictor* p, const float* d_x, const float* d_y, int n, int steps, int batch,
+                             float lr, unsigned long long seed, const int* order, double* final_loss);
+
+/* d_y[n][2] = raw predictions for the raw features d_x[n][8] (device),
+ * enqueued on the context's stream. */
+lx_status lx_predictor_infer(lx_predictor* p, const float* d_x, int n, float* d_y);
+
+/* The 8 features of each instance into d_x[n][8] (device), enqueued on the
+ * context's stream. */
+lx_status lx_instance_features(lx_ctx* ctx, int n, const lx_instance* inst, float* d_x);
+
 /* ---- launch shapes and measurement ------------------------------------ */
 
 /* Times every candidate launch shape of the fused Leja sweep for this

@@ -104,6 +104,32 @@ def _signatures(lib: C.CDLL) -> None:
     lib.lx_phi_leja_batched.argtypes = [_P, _I, C.POINTER(Instance), _I, _D, C.POINTER(LejaOpts),
                                         C.POINTER(InstanceResult)]
     lib.lx_phi_leja_batched.restype = _I
+    lib.lx_predictor_create.argtypes = [_P, C.c_ulonglong, C.POINTER(_P)]
+    lib.lx_predictor_create.restype = _I
+    lib.lx_predictor_destroy.argtypes = [_P]
+    lib.lx_predictor_destroy.restype = None
+    lib.lx_predictor_state_size.argtypes = []
+    lib.lx_predictor_state_size.restype = _I
+    lib.lx_predictor_set_scaling.argtypes = [_P, C.POINTER(C.c_float), C.POINTER(C.c_float),
+                                             C.POINTER(C.c_float), C.POINTER(C.c_float)]
+    lib.lx_predictor_set_scaling.restype = _I
+    lib.lx_predictor_get_state.argtypes = [_P, C.POINTER(C.c_float)]
+    lib.lx_predictor_get_state.restype = _I
+    lib.lx_predictor_set_state.argtypes = [_P, C.POINTER(C.c_float)]
+    lib.lx_predictor_set_state.restype = _I
+    lib.lx_predictor_save.argtypes = [_P, C.c_char_p]
+    lib.lx_predictor_save.restype = _I
+    lib.lx_predictor_load.argtypes = [_P, C.c_char_p]
+    lib.lx_predictor_load.restype = _I
+    lib.lx_predictor_gradient.argtypes = [_P, _P, _P, _I, C.POINTER(C.c_float), C.POINTER(_D)]
+    lib.lx_predictor_gradient.restype = _I
+    lib.lx_predictor_train.argtypes = [_P, _P, _P, _I, _I, _I, C.c_float, C.c_ulonglong, C.POINTER(_I),
+                                       C.POINTER(_D)]
+    lib.lx_predictor_train.restype = _I
+    lib.lx_predictor_infer.argtypes = [_P, _P, _I, _P]
+    lib.lx_predictor_infer.restype = _I
+    lib.lx_instance_features.argtypes = [_P, _I, C.POINTER(Instance), _P]
+    lib.lx_instance_features.restype = _I
     lib.lx_tune.argtypes = [_P, C.POINTER(Operator), _I, _I, C.c_char_p, C.c_size_t]
     lib.lx_tune.restype = _I
     lib.lx_set_tile.argtypes = [_P, _I, _I, _I, _I, _I]
@@ -121,6 +147,9 @@ def _signatures(lib: C.CDLL) -> None:
 EXPORTED = ["lx_create", "lx_destroy", "lx_set_stream", "lx_set_timing", "lx_last_error",
             "lx_status_string", "lx_get_stats", "lx_spectrum", "lx_phi_leja", "lx_exprb_step",
             "lx_phi_leja_batched", "lx_tune", "lx_set_tile", "lx_bandwidth_probe",
+            "lx_predictor_create", "lx_predictor_destroy", "lx_predictor_state_size", "lx_predictor_set_scaling",
+            "lx_predictor_get_state", "lx_predictor_set_state", "lx_predictor_save", "lx_predictor_load",
+            "lx_predictor_gradient", "lx_predictor_train", "lx_predictor_infer", "lx_instance_features",
             "lx_leja_points", "lx_phi_scalar", "lx_newton_coeffs"]
 
 
@@ -258,32 +287,48 @@ class Context:
             self._check(st, allow=(LX_OK, LX_ENOTCONV))
         return PhiResult(st, list(it), list(er), self.stats())
 
-    def phi_leja_batched(self, instances, power_iters=0, safety=1.05, rtol=1e-8, atol=0.0, max_iters=500,
-                         raise_on_error=True):
-        """Batched phi actions (lx_phi_leja_batched).  instances: list of
-        dicts with keys op, v, out and optionally u, x0, l (0), h, c, gamma,
-        budget (0).  Returns (status, [result dict per instance])."""
+    @staticmethod
+    def _instances(instances):
         n = len(instances)
         arr = (Instance * n)()
-        keep = []
         for i, q in enumerate(instances):
             arr[i].op = q["op"]
             arr[i].d_u = _ptr(q.get("u"))
             arr[i].d_v = _ptr(q["v"])
-            arr[i].d_out = _ptr(q["out"])
+            arr[i].d_out = _ptr(q["out"]) if q.get("out") is not None else None
             arr[i].d_x0 = _ptr(q.get("x0"))
             arr[i].l = int(q.get("l", 0))
             arr[i].h = float(q["h"])
             arr[i].c = float(q.get("c", 0.0))
             arr[i].gamma = float(q.get("gamma", 0.0))
             arr[i].budget = int(q.get("budget", 0))
-            keep.append(q)
+        return arr
+
+    def phi_leja_batched(self, instances, power_iters=0, safety=1.05, rtol=1e-8, atol=0.0, max_iters=500,
+                         raise_on_error=True):
+        """Batched phi actions (lx_phi_leja_batched).  instances: list of
+        dicts with keys op, v, out and optionally u, x0, l (0), h, c, gamma,
+        budget (0).  Returns (status, [result dict per instance])."""
+        n = len(instances)
+        arr = self._instances(instances)
         res = (InstanceResult * n)()
         opts = LejaOpts(float(rtol), float(atol), int(max_iters), 1e4)
         st = self.lib.c.lx_phi_leja_batched(self._h, n, arr, int(power_iters), float(safety), C.byref(opts), res)
         if raise_on_error:
             self._check(st, allow=(LX_OK, LX_ENOTCONV))
         return st, [r.as_dict() for r in res]
+
+    def features(self, instances, out):
+        """lx_instance_features: out is a float32 CUDA tensor [n, 8]."""
+        import torch
+        n = len(instances)
+        if out.dtype != torch.float32 or not out.is_cuda or tuple(out.shape) != (n, 8) or not out.is_contiguous():
+            raise ValueError("features need a contiguous float32 CUDA tensor of shape [n, 8]")
+        self._check(self.lib.c.lx_instance_features(self._h, n, self._instances(instances), out.data_ptr()))
+        return out
+
+    def predictor(self, seed: int = 0) -> "Predictor":
+        return Predictor(self, seed)
 
     def exprb_step(self, op: Operator, u, u_out, h, c, gamma, rtol=1e-8, atol=0.0, max_iters=500,
                    fp32_switch=1e4, scheme=LX_EXPRB42, raise_on_error=True) -> PhiResult:
@@ -295,6 +340,85 @@ class Context:
             self._check(st, allow=(LX_OK, LX_ENOTCONV))
         s = self.stats()
         return PhiResult(st, list(it), s["err"][:2], s)
+
+
+def _fptr(t, cols):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() \
+            or t.dim() != 2 or t.shape[1] != cols:
+        raise ValueError(f"expected a contiguous float32 CUDA tensor of shape [n, {cols}]")
+    return t.data_ptr()
+
+
+class Predictor:
+    """lx_predictor: the spectral/budget MLP on a context's device."""
+
+    def __init__(self, ctx: Context, seed: int = 0):
+        self.ctx = ctx
+        self.c = ctx.lib.c
+        self._h = _P()
+        ctx._check(self.c.lx_predictor_create(ctx._h, C.c_ulonglong(int(seed)), C.byref(self._h)))
+        self.state_size = int(self.c.lx_predictor_state_size())
+
+    def close(self):
+        if self._h:
+            self.c.lx_predictor_destroy(self._h)
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_scaling(self, mean_x, std_x, mean_y, std_y):
+        f = lambda a, n: (C.c_float * n)(*[float(x) for x in a])
+        self.ctx._check(self.c.lx_predictor_set_scaling(self._h, f(mean_x, 8), f(std_x, 8), f(mean_y, 2),
+                                                        f(std_y, 2)))
+
+    def get_state(self):
+        import numpy as np
+        buf = (C.c_float * self.state_size)()
+        self.ctx._check(self.c.lx_predictor_get_state(self._h, buf))
+        return np.frombuffer(buf, dtype=np.float32).copy()
+
+    def set_state(self, state):
+        import numpy as np
+        a = np.ascontiguousarray(state, dtype=np.float32)
+        if a.size != self.state_size:
+            raise ValueError("state size mismatch")
+        self.ctx._check(self.c.lx_predictor_set_state(self._h, a.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def save(self, path):
+        self.ctx._check(self.c.lx_predictor_save(self._h, str(path).encode()))
+
+    def load(self, path):
+        self.ctx._check(self.c.lx_predictor_load(self._h, str(path).encode()))
+
+    def gradient(self, X, Y):
+        import numpy as np
+        n = X.shape[0]
+        g = (C.c_float * LX_MLP_PARAMS)()
+        loss = _D()
+        self.ctx._check(self.c.lx_predictor_gradient(self._h, _fptr(X, 8), _fptr(Y, 2), n, g, C.byref(loss)))
+        return loss.value, np.frombuffer(g, dtype=np.float32).copy()
+
+    def train(self, X, Y, steps, batch, lr, seed=0, order=None):
+        n = X.shape[0]
+        o = None
+        if order is not None:
+            o = (_I * len(order))(*[int(x) for x in order])
+        loss = _D()
+        self.ctx._check(self.c.lx_predictor_train(self._h, _fptr(X, 8), _fptr(Y, 2), n, int(steps), int(batch),
+                                                  float(lr), C.c_ulonglong(int(seed)), o, C.byref(loss)))
+        return loss.value
+
+    def infer(self, X, out):
+        self.ctx._check(self.c.lx_predictor_infer(self._h, _fptr(X, 8), X.shape[0], _fptr(out, 2)))
+        return out
+
+
+LX_MLP_PARAMS = 4866
 
 
 class Library:

@@ -24,8 +24,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "_lx.so")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["kernels.hip", "batch.hip"]
-CXX_SOURCES = ["lx_api.cpp", "lx_batch.cpp", "planner.cpp"]
+HIP_SOURCES = ["kernels.hip", "batch.hip", "mlp.hip"]
+CXX_SOURCES = ["lx_api.cpp", "lx_batch.cpp", "lx_predictor.cpp", "planner.cpp"]
 
 
 def _hipcc() -> str:

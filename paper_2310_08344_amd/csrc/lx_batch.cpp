@@ -83,6 +83,8 @@ void lx_internal_free_batch(lx_ctx* ctx) {
     (void)hipHostFree(b.h_ctl);
     (void)hipHostFree(b.h_block_inst);
     (void)hipHostFree(b.h_done);
+    (void)hipFree(b.d_feat);
+    (void)hipHostFree(b.h_feat);
     b = lx_batch_ws{};
 }
 

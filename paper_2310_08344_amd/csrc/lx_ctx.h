@@ -25,8 +25,10 @@ struct lx_batch_ws {
     void* h_ctl = nullptr;
     int* h_block_inst = nullptr;
     unsigned* h_done = nullptr;  // [2] polled counters
+    void* d_feat = nullptr;      // feature descriptors (lx_instance_features)
+    void* h_feat = nullptr;
     size_t cap_d_inst = 0, cap_d_ctl = 0, cap_d_blk = 0, cap_coef = 0, cap_partials = 0, cap_basis = 0,
-           cap_done = 0, cap_h_inst = 0, cap_h_ctl = 0, cap_h_blk = 0, cap_h_done = 0;
+           cap_done = 0, cap_h_inst = 0, cap_h_ctl = 0, cap_h_blk = 0, cap_h_done = 0, cap_feat = 0;
 };
 
 struct lx_ctx {

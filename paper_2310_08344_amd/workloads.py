@@ -187,3 +187,36 @@ def batched_instances(count: int = 256, seed: int = 4,
                           "speed": speed, "angle": ang})
         out.append((p, gaussian(n, float(cx), float(cy))))
     return out
+
+
+def learned_instance(index: int, seed0: int, sizes=(64, 128, 256)):
+    """One instance of the predictor's training/evaluation distribution,
+    drawn from its own seed (seed0 + index).  Even indices: diffusion-
+    advection as in ``batched_instances`` (Gaussian input); odd indices:
+    Burgers with nu ~ LogU(1e-4, 1e-2) and a four-mode Fourier state u,
+    whose Jacobian acts on v = u.  Steps h = s x CFL with s ~ LogU(1, 100)
+    for diffusion-advection and s ~ LogU(1, 10) for Burgers (reading: the
+    advection-dominated Burgers Jacobians have nearly imaginary spectra,
+    where larger steps need hundreds of sweeps); phi order l ~ U{0..3}.
+    Returns (Problem, u or None, v)."""
+    rng = np.random.default_rng(seed0 + index)
+    n = int(rng.choice(sizes))
+    dx = 1.0 / n
+    l = int(rng.integers(0, 4))
+    if index % 2 == 0:
+        D = float(math.exp(rng.uniform(math.log(0.1), math.log(10.0))))
+        speed = float(rng.uniform(0.0, 5.0))
+        ang = float(rng.uniform(0.0, 2.0 * math.pi))
+        cx, cy = rng.uniform(0.0, 1.0, size=2)
+        s = float(math.exp(rng.uniform(0.0, math.log(100.0))))
+        vx, vy = speed * math.cos(ang), speed * math.sin(ang)
+        h = s * diffadv_cfl_step(D, vx, vy, dx, dx)
+        p = Problem(DIFFADV, n, D=D, vx=vx, vy=vy, h=h, cfl_multiple=s, seed=seed0 + index,
+                    meta={"l": l, "index": index})
+        return p, None, gaussian(n, float(cx), float(cy))
+    nu = float(math.exp(rng.uniform(math.log(1e-4), math.log(1e-2))))
+    s = float(math.exp(rng.uniform(0.0, math.log(10.0))))
+    u = fourier_modes(n, int(rng.integers(0, 2**31 - 1)))
+    h = s * burgers_cfl_step(nu, float(np.max(np.abs(u))), dx, dx)
+    p = Problem(BURGERS, n, nu=nu, h=h, cfl_multiple=s, seed=seed0 + index, meta={"l": l, "index": index})
+    return p, u, u.copy()
