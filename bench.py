@@ -27,7 +27,6 @@ Usage: python bench.py [--steps K] [--warmup W] [--no-tune] [--no-batched] [--no
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -38,17 +37,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_2310_08344_amd", "csrc", "kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "leja_sweep_phi123_4096_traffic.json")
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
-
-
-def kernel_source_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
 
 
 def committed_traffic(launch_bytes: float):
@@ -59,7 +52,8 @@ def committed_traffic(launch_bytes: float):
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha256") != kernel_source_hash():
+    from paper_2310_08344_amd.profsummary import sweep_source_hash
+    if t.get("sweep_source_sha256") != sweep_source_hash():
         return None
     return {"bytes_per_launch": t["hbm_bytes_per_launch"], "ratio_to_algorithmic":
             round(t["hbm_bytes_per_launch"] / launch_bytes, 4) if launch_bytes else None}
@@ -185,9 +179,9 @@ def main() -> int:
         log("calibration copy", extra["practical_copy_gbs"], "axpby", extra["practical_axpby_gbs"], "GB/s")
     if not args.no_tune:
         for K in (3, 2, 1):
-            best = min(ctx.tune(op, K=K, sweeps=8), key=lambda r: r[5])
-            log(f"tuned K={K}: tx {best[0]} ty {best[1]} ry {best[2]} vec {best[3]} workgroups {best[4]} "
-                f"{best[5]:.1f} us")
+            best = min(ctx.tune(op, K=K, sweeps=8), key=lambda r: r[6])
+            log(f"tuned K={K}: depth {best[0]} tx {best[1]} ty {best[2]} rows {best[3]} vec {best[4]} "
+                f"workgroups {best[5]} {best[6]:.1f} us per iteration")
 
     def step():
         rho, c, g = ctx.spectrum(op, x0=x0, iters=20)
@@ -213,20 +207,22 @@ def main() -> int:
     dt = (t1 - t0) / args.steps
     value = 3.0 / dt
 
-    sweeps = sum(r["n_apply"] for _, r in recs)
+    launches = sum(r["n_launch"] for _, r in recs)
     sweep_ms = sum(r["sweep_ms"] for _, r in recs)
     leja_bytes = sum(r["bytes"] for _, r in recs)
     achieved = leja_bytes / (sweep_ms * 1e-3) / 1e9
     pw_ms = sum(s["sweep_ms"] for s, _ in recs)
     pw_bytes = sum(s["bytes"] for s, _ in recs)
     last = recs[-1][1]
-    per_launch = leja_bytes / sweeps
+    per_launch = leja_bytes / launches
+    depth = last["depth"]
     traffic = committed_traffic(per_launch)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic["bytes_per_launch"] if traffic else None,
-            "kernel": "leja_sweep (diffusion-advection, K=3, FP64)",
-            "launches": sweeps, "avg_launch_us": round(sweep_ms * 1e3 / sweeps, 2),
+            "kernel": ("leja_pair (diffusion-advection, K=3, FP64, two iterations per launch)" if depth == 2
+                       else "leja_sweep (diffusion-advection, K=3, FP64)"),
+            "launches": launches, "avg_launch_us": round(sweep_ms * 1e3 / launches, 2),
             "bytes_per_launch": per_launch}
     if traffic:
         roof["traffic_ratio_to_algorithmic"] = traffic["ratio_to_algorithmic"]

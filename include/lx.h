@@ -95,7 +95,7 @@ typedef struct {
 /* Per-call record, filled by every lx_spectrum / lx_phi_leja / lx_exprb_step. */
 typedef struct {
     int status;             /* lx_status of the call                          */
-    int n_apply;            /* operator applications (fused sweeps) made      */
+    int n_apply;            /* operator applications made                     */
     int n_fp32;             /* of which in FP32 (LX_FP32_SWEEP)               */
     int iters[LX_K_MAX];    /* per output: sweeps until it passed the test    */
     double err[LX_K_MAX];   /* per output: last error estimate                */
@@ -106,6 +106,8 @@ typedef struct {
     double sweep_ms;        /* sum of the working sweeps' durations (timing)  */
     double first_sweep_ms;  /* duration of sweep 0 (timing on)                */
     double bytes;           /* algorithmic HBM bytes of the working sweeps    */
+    int n_launch;           /* Leja-loop launches that did work               */
+    int depth;              /* Leja iterations per launch (1 or 2)            */
 } lx_stats;
 
 /* ---- context ---------------------------------------------------------- */
@@ -308,16 +310,21 @@ lx_status lx_instance_features(lx_ctx* ctx, int n, const lx_instance* inst, floa
 
 /* ---- launch shapes and measurement ------------------------------------ */
 
-/* Times every candidate launch shape of the fused Leja sweep for this
- * operator, grid, output count K and precision on the context's stream
- * (sweeps timed sweeps per candidate, after two warm-up sweeps, on scratch
- * vectors the call allocates and frees) and keeps the fastest: later
- * lx_spectrum / lx_phi_leja / lx_exprb_step calls with the same
- * (kind, nx, ny, K, prec) use it.  When the environment variable
- * LX_TUNE_CACHE names a file, the winner is appended to it as one JSON
- * object per line, and lx_create loads the file's entries.
+/* Times every candidate launch shape of the Leja loop for this operator,
+ * grid, output count K and precision on the context's stream (about
+ * `sweeps` timed iterations per candidate, after two warm-up launches, on
+ * scratch vectors the call allocates and frees): the one-sweep shapes
+ * (tx, ty, ry, vec, workgroups) and, for FP64 with even nx, the
+ * two-iteration shapes (tile rows th, workgroups).  It keeps the fastest
+ * one-sweep shape (used by lx_spectrum and by depth-1 loops), the fastest
+ * two-iteration shape, and the depth with the lower time per iteration:
+ * later calls with the same (kind, nx, ny, K, prec) use them.  When the
+ * environment variable LX_TUNE_CACHE names a file, the winners are
+ * appended to it as one JSON object per line, and lx_create loads the
+ * file's entries.
  * report: host buffer of report_len chars, or NULL; receives one line per
- * candidate: "tx ty ry vec workgroups microseconds_per_sweep".
+ * candidate: "depth tx ty rows vec workgroups microseconds_per_iteration",
+ * rows being ry for depth 1 and th for depth 2 (whose workgroups are 64 x 4).
  * Errors: LX_EINVAL (op invalid, K out of range, sweeps outside 1..200),
  * LX_ENOMEM. */
 lx_status lx_tune(lx_ctx* ctx, const lx_operator* op, int K, int sweeps, char* report, size_t report_len);
@@ -329,6 +336,18 @@ lx_status lx_tune(lx_ctx* ctx, const lx_operator* op, int K, int sweeps, char* r
  * (tuned entry, else the built-in rule).  vec = 2 needs an even nx and
  * 16-byte aligned vectors; otherwise vec 1 is used. */
 lx_status lx_set_tile(lx_ctx* ctx, int tx, int ty, int ry, int vec, int nb);
+
+/* Leja iterations per launch of later lx_phi_leja / lx_exprb_step loops:
+ * depth 1 runs one fused sweep per launch (the shape of lx_set_tile);
+ * depth 2 runs two iterations per launch on LDS-resident tiles of 128
+ * columns by th (8, 16 or 32) rows with nb workgroups (0 = automatic),
+ * reading the basis once per two iterations; depth 0 restores the automatic
+ * choice (the tuned entry, else 2).  Depth 2 applies to FP64 sweeps on
+ * grids with even nx and 16-byte aligned vectors; other calls use depth 1.
+ * Results agree with depth 1 to rounding (the outputs take the same terms
+ * in the same order; only the order of the norm reductions differs).
+ * Errors: LX_EINVAL (depth outside 0..2, th not 0, 8, 16 or 32, nb < 0). */
+lx_status lx_set_depth(lx_ctx* ctx, int depth, int th, int nb);
 
 /* Practical HBM bandwidth of plain streaming HIP kernels, the calibration
  * of Sec. 3: kind 0 copies y = x (16 bytes per element), kind 1 computes

@@ -46,14 +46,15 @@ class Stats(C.Structure):
                 ("iters", C.c_int * LX_K_MAX), ("err", C.c_double * LX_K_MAX),
                 ("pnorm", C.c_double * LX_K_MAX), ("rho_hat", C.c_double),
                 ("plan_ms", C.c_double), ("loop_ms", C.c_double), ("sweep_ms", C.c_double),
-                ("first_sweep_ms", C.c_double), ("bytes", C.c_double)]
+                ("first_sweep_ms", C.c_double), ("bytes", C.c_double), ("n_launch", C.c_int),
+                ("depth", C.c_int)]
 
     def as_dict(self) -> dict:
         return {"status": self.status, "n_apply": self.n_apply, "n_fp32": self.n_fp32,
                 "iters": list(self.iters), "err": list(self.err), "pnorm": list(self.pnorm),
                 "rho_hat": self.rho_hat, "plan_ms": self.plan_ms, "loop_ms": self.loop_ms,
                 "sweep_ms": self.sweep_ms, "first_sweep_ms": self.first_sweep_ms,
-                "bytes": self.bytes}
+                "bytes": self.bytes, "n_launch": self.n_launch, "depth": self.depth}
 
 
 class Instance(C.Structure):
@@ -134,6 +135,8 @@ def _signatures(lib: C.CDLL) -> None:
     lib.lx_tune.restype = _I
     lib.lx_set_tile.argtypes = [_P, _I, _I, _I, _I, _I]
     lib.lx_set_tile.restype = _I
+    lib.lx_set_depth.argtypes = [_P, _I, _I, _I]
+    lib.lx_set_depth.restype = _I
     lib.lx_bandwidth_probe.argtypes = [_P, _I, C.c_size_t, _I, C.POINTER(_D)]
     lib.lx_bandwidth_probe.restype = _I
     lib.lx_leja_points.argtypes = [_I, C.POINTER(_D)]
@@ -146,7 +149,7 @@ def _signatures(lib: C.CDLL) -> None:
 
 EXPORTED = ["lx_create", "lx_destroy", "lx_set_stream", "lx_set_timing", "lx_last_error",
             "lx_status_string", "lx_get_stats", "lx_spectrum", "lx_phi_leja", "lx_exprb_step",
-            "lx_phi_leja_batched", "lx_tune", "lx_set_tile", "lx_bandwidth_probe",
+            "lx_phi_leja_batched", "lx_tune", "lx_set_tile", "lx_set_depth", "lx_bandwidth_probe",
             "lx_predictor_create", "lx_predictor_destroy", "lx_predictor_state_size", "lx_predictor_set_scaling",
             "lx_predictor_get_state", "lx_predictor_set_state", "lx_predictor_save", "lx_predictor_load",
             "lx_predictor_gradient", "lx_predictor_train", "lx_predictor_infer", "lx_instance_features",
@@ -241,17 +244,22 @@ class Context:
 
     def tune(self, op: Operator, K: int = 1, sweeps: int = 10) -> list:
         """Times the candidate launch shapes (lx_tune); returns
-        [(tx, ty, ry, vec, workgroups, microseconds per sweep), ...]."""
+        [(depth, tx, ty, rows, vec, workgroups, microseconds per iteration), ...]
+        with rows = ry (depth 1) or tile rows th (depth 2)."""
         buf = C.create_string_buffer(8192)
         self._check(self.lib.c.lx_tune(self._h, C.byref(op), int(K), int(sweeps), buf, C.c_size_t(8192)))
         rows = []
         for line in buf.value.decode().splitlines():
-            tx, ty, ry, vec, nb, us = line.split()
-            rows.append((int(tx), int(ty), int(ry), int(vec), int(nb), float(us)))
+            d, tx, ty, ry, vec, nb, us = line.split()
+            rows.append((int(d), int(tx), int(ty), int(ry), int(vec), int(nb), float(us)))
         return rows
 
     def set_tile(self, tx=0, ty=0, ry=0, vec=0, nb=0) -> None:
         self._check(self.lib.c.lx_set_tile(self._h, int(tx), int(ty), int(ry), int(vec), int(nb)))
+
+    def set_depth(self, depth=0, th=0, nb=0) -> None:
+        """Leja iterations per launch (lx_set_depth): 0 automatic, 1 or 2."""
+        self._check(self.lib.c.lx_set_depth(self._h, int(depth), int(th), int(nb)))
 
     def bandwidth_probe(self, kind: int, n: int, reps: int = 20) -> float:
         """GB/s of the copy (kind 0) or z = ax + by (kind 1) probe."""

@@ -185,9 +185,12 @@ void load_tune_cache(lx_ctx* ctx) {
         int kind, nx, ny, K, prec;
         Tile t;
         if (std::sscanf(line, "{\"kind\": %d, \"nx\": %d, \"ny\": %d, \"K\": %d, \"prec\": %d, \"tx\": %d, "
-                              "\"ty\": %d, \"ry\": %d, \"vec\": %d, \"nb\": %d",
-                        &kind, &nx, &ny, &K, &prec, &t.tx, &t.ty, &t.ry, &t.vec, &t.nb) == 10 &&
-            valid_tile(t)) {
+                              "\"ty\": %d, \"ry\": %d, \"vec\": %d, \"nb\": %d, \"depth\": %d, \"th\": %d, "
+                              "\"pnb\": %d",
+                        &kind, &nx, &ny, &K, &prec, &t.tx, &t.ty, &t.ry, &t.vec, &t.nb, &t.depth, &t.th,
+                        &t.pnb) == 13 &&
+            valid_tile(t) && (t.depth == 1 || t.depth == 2) && (t.th == 8 || t.th == 16 || t.th == 32) &&
+            t.pnb >= 0) {
             ctx->tuned[std::make_tuple(kind, nx, ny, K, prec)] = t;
         }
     }
@@ -214,8 +217,36 @@ struct LejaCall {
     lx_leja_opts o;
 };
 
+// Iterations per launch for this call: forced by lx_set_depth, else the
+// tuned entry's, else two.  Two needs FP64 sweeps and 16-byte pairs.
+void choose_depth(const lx_ctx* ctx, const lx_operator& op, int K, bool vec2_ok, Tile& t) {
+    const bool pair_ok = op.prec == LX_FP64 && vec2_ok && op.nx % 2 == 0;
+    auto it = ctx->tuned.find(std::make_tuple(op.kind, op.nx, op.ny, K, op.prec));
+    int depth = 2;
+    if (ctx->depth_forced != 0) depth = ctx->depth_forced;
+    else if (it != ctx->tuned.end()) depth = it->second.depth;
+    t.depth = (depth == 2 && pair_ok) ? 2 : 1;
+    if (it != ctx->tuned.end() && it->second.depth == 2) {
+        t.th = it->second.th;
+        t.pnb = it->second.pnb;
+    } else {
+        t.th = 16;
+        t.pnb = 1024;
+    }
+    if (ctx->pair_th != 0) t.th = ctx->pair_th;
+    if (ctx->pair_nb != 0) t.pnb = ctx->pair_nb;
+}
+
+// workgroups of a leja_pair grid: at most one per tile, a multiple of 8 once
+// there are at least 8
+int pair_grid(int pnb, int tiles) {
+    int nb = (pnb <= 0 || pnb > tiles) ? tiles : pnb;
+    if (nb >= 8) nb &= ~7;
+    return std::max(nb, 1);
+}
+
 // The device-resident Newton-Leja loop (Sec. 2.1, Eq. (2); stop rule of
-// Sec. 2.2).  Fills ctx->stats.
+// Sec. 2.2), one or two iterations per launch.  Fills ctx->stats.
 lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
     const lx_operator& op = *q.op;
     const int nx = op.nx, ny = op.ny;
@@ -226,25 +257,33 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
     lx_stats& S = ctx->stats;
     S = lx_stats{};
 
+    bool vec2 = aligned16(q.v) && (q.u == nullptr || aligned16(q.u));
+    for (int k = 0; k < K; ++k) vec2 = vec2 && aligned16(q.out[k]) && (q.base[k] == nullptr || aligned16(q.base[k]));
+    Tile t = pick_tile(ctx, op, K, vec2);
+    choose_depth(ctx, op, K, vec2, t);
+    const bool pair = t.depth == 2;
+    // coefficients the loop may read: d_0..d_{NC-1} (a two-iteration launch
+    // also forms the norm its last, deferred term would give)
+    const int NC = pair ? M + 1 : M;
+
     // ---- planner: Leja points now, Newton coefficients chunk by chunk ----
     const auto t0 = std::chrono::steady_clock::now();
-    lx_status s = ensure_xi(ctx, M);
+    lx_status s = ensure_xi(ctx, NC);
     if (s != LX_OK) return s;
     for (int k = 0; k < K; ++k)
         ctx->series[k].reset(q.l[k], q.alpha[k], q.sigma[k], q.h, q.c, q.gamma, ctx->h_xi);
     int have = 0;          // coefficients d_0..d_{have-1} computed and enqueued for upload
     double plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    // sweep m reads d_{m+1}; sweeps [0, upto-1) need d_0..d_{upto-1}
     auto ensure_coeffs = [&](int upto) -> lx_status {
-        upto = std::min(upto, M);
+        upto = std::min(upto, NC);
         if (upto <= have) return LX_OK;
         const auto ta = std::chrono::steady_clock::now();
         for (int k = 0; k < K; ++k) {
-            double* hc = ctx->h_coef + static_cast<size_t>(k) * M;
+            double* hc = ctx->h_coef + static_cast<size_t>(k) * NC;
             for (int j = have; j < upto; ++j) hc[j] = ctx->series[k].next();
         }
         for (int k = 0; k < K; ++k) {
-            const size_t off = static_cast<size_t>(k) * M + have;
+            const size_t off = static_cast<size_t>(k) * NC + have;
             LX_HIP(ctx, hipMemcpyAsync(ctx->coef + off, ctx->h_coef + off, sizeof(double) * (upto - have),
                                        hipMemcpyHostToDevice, ctx->stream));
         }
@@ -270,16 +309,19 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
     if (fp32 && op.kind == LX_OP_BURGERS2D) LX_HIP(ctx, lx::launch_to_fp32(q.u, ctx->u32, N, ctx->stream));
 
     // ---- sweep arguments ----
-    bool vec2 = aligned16(q.v) && (q.u == nullptr || aligned16(q.u));
-    for (int k = 0; k < K; ++k) vec2 = vec2 && aligned16(q.out[k]) && (q.base[k] == nullptr || aligned16(q.base[k]));
-    const Tile t = pick_tile(ctx, op, K, vec2);
     SweepArgs a{};
     a.nx = nx;
     a.ny = ny;
-    a.tiles_x = (nx + t.cols() - 1) / t.cols();
-    a.tiles_y = (ny + t.rows() - 1) / t.rows();
-    a.nb = grid_size(t, a.tiles_x * a.tiles_y);
-    a.ld = M;
+    if (pair) {
+        a.tiles_x = (nx + 127) / 128;
+        a.tiles_y = (ny + t.th - 1) / t.th;
+        a.nb = pair_grid(t.pnb, a.tiles_x * a.tiles_y);
+    } else {
+        a.tiles_x = (nx + t.cols() - 1) / t.cols();
+        a.tiles_y = (ny + t.rows() - 1) / t.rows();
+        a.nb = grid_size(t, a.tiles_x * a.tiles_y);
+    }
+    a.ld = NC;
     set_stencil(a, op, q.c, q.gamma);
     a.inv_sqrtN = 1.0 / std::sqrt(static_cast<double>(N));
     a.v = q.v;
@@ -295,29 +337,36 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
     a.xi = ctx->xi;
     a.ctl = ctx->ctl;
     const int opcode = op.kind == LX_OP_DIFFADV2D ? lx::kOpDiffAdv : lx::kOpBurgersJ;
-    s = ensure_partials(ctx, 2 * static_cast<size_t>(a.nb) * (1 + K));
+    s = ensure_partials(ctx, 2 * static_cast<size_t>(a.nb) * (1 + K) * (pair ? 2 : 1));
     if (s != LX_OK) return s;
     a.partials = ctx->partials;
 
     // ---- chunked, device-resident loop ----
+    // single: launch m (0 <= m < max_iters) is sweep m, which reads d_m (its
+    // stop decision) and d_{m+1}; launch max_iters only takes the last
+    // decision.  pair: launch L takes the decisions at terms 2L-1 and 2L and
+    // then sweeps 2L and 2L+1; by launch ceil(max_iters/2) the loop has
+    // ended, and the launch after it publishes a flush's final state.
     const int max_iters = q.o.max_iters;
+    const int last = pair ? (max_iters + 1) / 2 + 1 : max_iters;   // last launch index
+    const int per = pair ? 2 : 1;                                   // iterations per launch
     if (ctx->timing) {
-        s = ensure_timing_events(ctx, static_cast<size_t>(max_iters) + 1);
+        s = ensure_timing_events(ctx, static_cast<size_t>(last) + 2);
         if (s != LX_OK) return s;
         LX_HIP(ctx, hipEventRecord(ctx->tev[0], ctx->stream));
     }
-    // sweep m (0 <= m < max_iters) reads d_m (its stop decision) and d_{m+1};
-    // the launch m = max_iters only takes the last decision
+    auto coeffs_for = [&](int launches) { return per * launches + 1; };   // d_0 .. d_{per*launches}
     int launched = 0, chunk_id = 0, last_slot = -1;
-    int chunk = kFirstChunk;
-    while (launched <= max_iters) {
-        const int n = std::min(chunk, max_iters + 1 - launched);
-        s = ensure_coeffs(launched + n + 1);
+    int chunk = kFirstChunk / per;
+    while (launched <= last) {
+        const int n = std::min(chunk, last + 1 - launched);
+        s = ensure_coeffs(coeffs_for(launched + n));
         if (s != LX_OK) return s;
         for (int i = 0; i < n; ++i) {
-            const int m = launched + i;
-            LX_HIP(ctx, lx::launch_leja_sweep(opcode, K, fp32, t, a, m, ctx->stream));
-            if (ctx->timing && m < max_iters) LX_HIP(ctx, hipEventRecord(ctx->tev[m + 1], ctx->stream));
+            const int L = launched + i;
+            if (pair) LX_HIP(ctx, lx::launch_leja_pair(opcode, K, t.th, a, L, ctx->stream));
+            else LX_HIP(ctx, lx::launch_leja_sweep(opcode, K, fp32, t, a, L, ctx->stream));
+            if (ctx->timing && L < last) LX_HIP(ctx, hipEventRecord(ctx->tev[L + 1], ctx->stream));
         }
         launched += n;
         const int slot = chunk_id & 1;
@@ -327,47 +376,78 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
         last_slot = slot;
         if (chunk_id >= 1) {
             // the next chunk's coefficients are prepared while the GPU works
-            s = ensure_coeffs(std::min(launched + kChunk, max_iters) + 1);
+            s = ensure_coeffs(coeffs_for(std::min(launched + kChunk / per, last)));
             if (s != LX_OK) return s;
             const int prev = slot ^ 1;
             LX_HIP(ctx, hipEventSynchronize(ctx->poll_ev[prev]));
             if (ctx->h_poll[prev].done) break;
         }
         ++chunk_id;
-        chunk = kChunk;
+        chunk = kChunk / per;
     }
     LX_HIP(ctx, hipEventSynchronize(ctx->poll_ev[last_slot]));
     const SweepState& fin = ctx->h_poll[last_slot];
     if (!fin.done) return fail(ctx, LX_EDEVICE, "the device loop did not record a final state");
 
-    S.n_apply = fin.iter;
     S.n_fp32 = fin.n_fp32;
     for (int k = 0; k < K; ++k) {
         S.iters[k] = fin.iters[k];
         S.err[k] = fin.err[k];
         S.pnorm[k] = fin.pnorm[k];
     }
-    // algorithmic bytes: per sweep, the basis read and write, the Burgers
-    // state read, and per unconverged output a read and a write of p (sweep 0
-    // writes p_1 = d_0 v + d_1 y_1 without reading it; a base adds a read)
+    // algorithmic bytes of the launches that did work
     double bytes = 0.0;
-    for (int m = 0; m < fin.iter; ++m) {
-        const bool w32 = m >= fin.iter - fin.n_fp32;
-        const bool r32 = m >= 1 && (m - 1) >= fin.iter - fin.n_fp32;
-        double b = (r32 ? 4.0 : 8.0) + (w32 ? 4.0 : 8.0);
-        if (op.kind == LX_OP_BURGERS2D) b += w32 ? 4.0 : 8.0;
-        for (int k = 0; k < K; ++k) {
-            if (m < fin.iters[k]) b += (m == 0) ? (q.base[k] ? 16.0 : 8.0) : 16.0;
+    const double ub = op.kind == LX_OP_BURGERS2D ? 8.0 : 0.0;
+    if (!pair) {
+        // per sweep: the basis read and write, the Burgers state read, and per
+        // unconverged output a read and a write of p (sweep 0 writes
+        // p_1 = d_0 v + d_1 y_1 without reading it; a base adds a read)
+        S.n_apply = fin.iter;
+        S.n_launch = fin.iter;
+        for (int m = 0; m < fin.iter; ++m) {
+            const bool w32 = m >= fin.iter - fin.n_fp32;
+            const bool r32 = m >= 1 && (m - 1) >= fin.iter - fin.n_fp32;
+            double b = (r32 ? 4.0 : 8.0) + (w32 ? 4.0 : 8.0);
+            if (op.kind == LX_OP_BURGERS2D) b += w32 ? 4.0 : 8.0;
+            for (int k = 0; k < K; ++k) {
+                if (m < fin.iters[k]) b += (m == 0) ? (q.base[k] ? 16.0 : 8.0) : 16.0;
+            }
+            bytes += b * static_cast<double>(N);
         }
-        bytes += b * static_cast<double>(N);
+    } else {
+        // the loop ended at the test of term T: launches 0..F-1 ran both
+        // sweeps, and an even T left a deferred term for one more launch.
+        // Per two-sweep launch: y_m in, y_{m+2} out, the Burgers state, and
+        // per output still taking terms a read and a write of p (launch 0
+        // writes p without reading it; a base adds a read).
+        const int T = fin.iter;
+        const int F = (T + 1) / 2;
+        const bool flush = T % 2 == 0;
+        S.n_apply = 2 * F;
+        S.n_launch = F + (flush ? 1 : 0);
+        for (int L = 0; L < F; ++L) {
+            double b = 16.0 + ub;
+            for (int k = 0; k < K; ++k) {
+                if (L == 0) b += q.base[k] ? 16.0 : 8.0;
+                else if (fin.iters[k] >= 2 * L) b += 16.0;
+            }
+            bytes += b * static_cast<double>(N);
+        }
+        if (flush) {
+            double b = 8.0;
+            for (int k = 0; k < K; ++k)
+                if (fin.iters[k] >= T) b += 16.0;
+            bytes += b * static_cast<double>(N);
+        }
     }
+    S.depth = per;
     S.bytes = bytes;
     S.plan_ms = plan_ms;
-    if (ctx->timing && fin.iter > 0) {
-        // events follow every sweep: sweep m's interval also holds the stop
-        // decision the next sweep takes first (a few microseconds)
+    if (ctx->timing && S.n_launch > 0) {
+        // events follow every launch: a launch's interval also holds the stop
+        // decision the next one takes first (a few microseconds)
         S.first_sweep_ms = elapsed(ctx->tev[0], ctx->tev[1]);
-        S.loop_ms = elapsed(ctx->tev[0], ctx->tev[fin.iter]);
+        S.loop_ms = elapsed(ctx->tev[0], ctx->tev[S.n_launch]);
         S.sweep_ms = S.loop_ms;
     }
     S.status = fin.status;
@@ -723,6 +803,16 @@ lx_status lx_exprb_step(lx_ctx* ctx, const lx_operator* op, int scheme, const do
     return s;
 }
 
+lx_status lx_set_depth(lx_ctx* ctx, int depth, int th, int nb) {
+    if (ctx == nullptr) return LX_EINVAL;
+    if (depth < 0 || depth > 2 || !(th == 0 || th == 8 || th == 16 || th == 32) || nb < 0)
+        return fail(ctx, LX_EINVAL, "depth %d, th %d, nb %d: need depth 0..2, th 0/8/16/32, nb >= 0", depth, th, nb);
+    ctx->depth_forced = depth;
+    ctx->pair_th = th;
+    ctx->pair_nb = nb;
+    return LX_OK;
+}
+
 lx_status lx_set_tile(lx_ctx* ctx, int tx, int ty, int ry, int vec, int nb) {
     if (ctx == nullptr) return LX_EINVAL;
     if (tx == 0) {
@@ -839,13 +929,69 @@ lx_status lx_tune(lx_ctx* ctx, const lx_operator* op, int K, int sweeps, char* r
         if (e != hipSuccess) return cleanup(fail(ctx, LX_EDEVICE, "tuning launch failed: %s", hipGetErrorString(e)));
         const double us = elapsed(ctx->tev[0], ctx->tev[1]) * 1e3 / sweeps;
         char line[112];
-        std::snprintf(line, sizeof(line), "%d %d %d %d %d %.3f\n", t.tx, t.ty, t.ry, t.vec, a.nb, us);
+        std::snprintf(line, sizeof(line), "1 %d %d %d %d %d %.3f\n", t.tx, t.ty, t.ry, t.vec, a.nb, us);
         rep += line;
         if (us < best_us) {
             best_us = us;
             best = t;
         }
     }
+    // two iterations per launch (FP64, even nx): tile rows x workgroups
+    best.depth = 1;
+    double best_pair_us = 1e300;
+    if (op->prec == LX_FP64 && nx % 2 == 0) {
+        const int tiles_x = (nx + 127) / 128;
+        for (int th : {8, 16, 32}) {
+            const int tiles = tiles_x * ((ny + th - 1) / th);
+            for (int pnb : {0, 2048, 1024, 512}) {
+                if (pnb != 0 && pnb >= tiles) continue;
+                SweepArgs a{};
+                a.nx = nx;
+                a.ny = ny;
+                a.tiles_x = tiles_x;
+                a.tiles_y = (ny + th - 1) / th;
+                a.nb = pair_grid(pnb, tiles);
+                a.ld = ld;
+                set_stencil(a, *op, -2.0, 1.0);
+                a.inv_sqrtN = 1.0 / std::sqrt(static_cast<double>(N));
+                a.v = ctx->ybuf[0];
+                a.ybuf[0] = ctx->ybuf[0];
+                a.ybuf[1] = ctx->ybuf[1];
+                a.u = op->kind == LX_OP_BURGERS2D ? scratch + static_cast<size_t>(K) * N : nullptr;
+                for (int k = 0; k < K; ++k) a.p[k] = scratch + static_cast<size_t>(k) * N;
+                a.coef = ctx->coef;
+                a.xi = ctx->xi;
+                s = ensure_partials(ctx, 4 * static_cast<size_t>(a.nb) * (1 + K));
+                if (s != LX_OK) return cleanup(s);
+                a.partials = ctx->partials;
+                a.ctl = ctx->ctl;
+                if (hipMemcpyAsync(ctx->ctl, &init, sizeof(LoopCtl), hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
+                    return cleanup(fail(ctx, LX_EDEVICE, "state upload failed"));
+                // launches 0 and 1 warm up; launches 2 .. n+1 (2n iterations) are timed
+                const int n = std::max(1, sweeps / 2);
+                hipError_t e = hipSuccess;
+                for (int L = 0; L < 2 && e == hipSuccess; ++L) e = lx::launch_leja_pair(opcode, K, th, a, L, ctx->stream);
+                if (e == hipSuccess) e = hipEventRecord(ctx->tev[0], ctx->stream);
+                for (int L = 2; L < n + 2 && e == hipSuccess; ++L)
+                    e = lx::launch_leja_pair(opcode, K, th, a, L, ctx->stream);
+                if (e == hipSuccess) e = hipEventRecord(ctx->tev[1], ctx->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(ctx->tev[1]);
+                if (e != hipSuccess)
+                    return cleanup(fail(ctx, LX_EDEVICE, "tuning launch failed: %s", hipGetErrorString(e)));
+                const double us = elapsed(ctx->tev[0], ctx->tev[1]) * 1e3 / (2.0 * n);
+                char line[112];
+                std::snprintf(line, sizeof(line), "2 64 4 %d 2 %d %.3f\n", th, a.nb, us);
+                rep += line;
+                if (us < best_pair_us) {
+                    best_pair_us = us;
+                    best.th = th;
+                    best.pnb = pnb;
+                }
+            }
+        }
+        if (best_pair_us < best_us) best.depth = 2;
+    }
+    const double best_iter_us = std::min(best_us, best_pair_us);
     ctx->tuned[std::make_tuple(op->kind, nx, ny, K, op->prec)] = best;
     if (report != nullptr && report_len > 0) {
         std::snprintf(report, report_len, "%s", rep.c_str());
@@ -856,8 +1002,10 @@ lx_status lx_tune(lx_ctx* ctx, const lx_operator* op, int K, int sweeps, char* r
         if (f != nullptr) {
             std::fprintf(f,
                          "{\"kind\": %d, \"nx\": %d, \"ny\": %d, \"K\": %d, \"prec\": %d, \"tx\": %d, "
-                         "\"ty\": %d, \"ry\": %d, \"vec\": %d, \"nb\": %d, \"us\": %.3f}\n",
-                         op->kind, nx, ny, K, op->prec, best.tx, best.ty, best.ry, best.vec, best.nb, best_us);
+                         "\"ty\": %d, \"ry\": %d, \"vec\": %d, \"nb\": %d, \"depth\": %d, \"th\": %d, "
+                         "\"pnb\": %d, \"us\": %.3f}\n",
+                         op->kind, nx, ny, K, op->prec, best.tx, best.ty, best.ry, best.vec, best.nb, best.depth,
+                         best.th, best.pnb, best_iter_us);
             std::fclose(f);
         }
     }
@@ -892,14 +1040,14 @@ lx_status lx_bandwidth_probe(lx_ctx* ctx, int kind, size_t n, int reps, double* 
 }
 
 lx_status lx_leja_points(int M, double* xi) {
-    if (xi == nullptr || M < 1 || M > lx::kMaxPoints) return LX_EINVAL;
+    if (xi == nullptr || M < 1 || M > LX_MAX_ITERS + 1) return LX_EINVAL;
     return lx::leja_points(M, xi) ? LX_OK : LX_EINVAL;
 }
 
 double lx_phi_scalar(int l, double z) { return lx::phi_scalar(l, z); }
 
 lx_status lx_newton_coeffs(int l, double alpha, double sigma, double h, double c, double gamma, int M, double* d) {
-    if (d == nullptr || M < 1 || M > lx::kMaxPoints || l < 0 || l > 8) return LX_EINVAL;
+    if (d == nullptr || M < 1 || M > LX_MAX_ITERS + 1 || l < 0 || l > 8) return LX_EINVAL;
     std::vector<double> xi(static_cast<size_t>(M));
     if (!lx::leja_points(M, xi.data())) return LX_EINVAL;
     return lx::newton_coeffs(l, alpha, sigma, h, c, gamma, M, xi.data(), d) ? LX_OK : LX_EINVAL;

@@ -57,6 +57,8 @@ struct lx_ctx {
     lx::NewtonSeries series[LX_K_MAX];      // per-output divided differences
     // launch shapes: forced by lx_set_tile, else tuned per (kind, nx, ny, K, prec)
     lx::Tile forced{0, 0, 0, 0, 0};         // tx == 0: not forced
+    int depth_forced = 0;                   // lx_set_depth: 0 automatic, 1 or 2 iterations per launch
+    int pair_th = 0, pair_nb = 0;           // lx_set_depth: forced leja_pair shape (0: automatic)
     std::map<std::tuple<int, int, int, int, int>, lx::Tile> tuned;
     lx_batch_ws batch;
     lx_stats stats{};

@@ -44,6 +44,9 @@ struct LoopCtl {
 // workgroups (0 = one per tile) loop over the tiles.
 struct Tile {
     int tx = 64, ty = 4, ry = 4, vec = 2, nb = 0;
+    int depth = 1;           // Leja iterations per launch: 1 (leja_sweep) or 2 (leja_pair)
+    int th = 16;             // tile rows of leja_pair (its tiles are 128 columns wide)
+    int pnb = 1024;          // workgroups of leja_pair
     int cols() const { return tx * vec; }
     int rows() const { return ty * ry; }
 };
@@ -114,6 +117,9 @@ constexpr int kBatchTx = 32, kBatchTy = 8;   // workgroup shape of the batched s
 // Sweep m of the Leja loop (m = max_iters only takes the last decision).
 hipError_t launch_leja_sweep(int op, int K, bool fp32_capable, const Tile& t, const SweepArgs& a, int m,
                              hipStream_t s);
+// Launch L of the two-iterations-per-launch loop (pair.hip): sweeps 2L and
+// 2L+1 on tiles of 128 x th points (th in {8, 16, 32}); FP64, nx even.
+hipError_t launch_leja_pair(int op, int K, int th, const SweepArgs& a, int L, hipStream_t s);
 // Power iteration: norm of the start vector into partials[1], then sweeps
 // k = 0..iters-1, then the final norm into ctl->rho.
 hipError_t launch_power_norm(const double* x, long n, int nb, double* partials, hipStream_t s);

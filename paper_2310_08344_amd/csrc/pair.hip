@@ -1,0 +1,415 @@
+// Two Leja iterations per launch (gfx950), FP64.
+//
+// The single-sweep kernel moves (16 + 16K) bytes per point for every
+// iteration: the basis vector in and out and each unconverged output in and
+// out.  Here one launch advances the Newton recurrence (Sec. 2.1, Eq. (2))
+// by two steps on LDS-resident tiles:
+//
+//     y_{m+1} = ((A - c)/gamma - xi_m) y_m        on the tile plus a 1-cell halo
+//     y_{m+2} = ((A - c)/gamma - xi_{m+1}) y_{m+1}  on the tile
+//
+// so y_m is read once (with a 2-cell halo, mostly from L2) and only y_{m+2}
+// is written: the same bytes as one sweep buy two iterations.
+//
+// The stop rule (Sec. 2.2) for term m+1 needs norms that only exist after
+// the launch, so the second term is deferred: launch L (m = 2L) adds
+// d_m y_m (its own input, the term deferred by launch L-1) and
+// d_{m+1} y_{m+1}, and records the sums of squares of y_{m+1}, of the
+// outputs after that update, of y_{m+2}, and of the outputs as they would
+// be with d_{m+2} y_{m+2} added.  At the next launch every workgroup adds
+// the partial sums in the same fixed order and applies the stop rule at
+// terms m+1 and m+2 in turn; an output that passed at m+1 takes no further
+// term, one that passes at m+2 takes only the deferred d_{m+2} y_{m+2}.
+// The arithmetic on every output is the single-sweep kernel's, term by term
+// in the same order, so the results and iteration counts are those of
+// one-iteration launches up to the order of the norm reductions.
+//
+// When the rule ends the loop with a deferred term still owed, the launch
+// only adds it (a "flush"), records the final state in its parity slot, and
+// the following launch publishes it to slot[2]: slot[2] must not announce
+// the end while workgroups of the flushing launch may still be starting.
+//
+// Tiles are 128 columns (64 lanes x 2) by TH rows; a workgroup is four
+// wavefronts.  LDS holds y_m on rows -2..TH+1 and columns -2..129 of the
+// tile (and the Burgers state u on the same cells) and y_{m+1} on rows
+// -1..TH and columns -1..128.  Global indices wrap periodically, so cells
+// of a tile past the grid's edge hold the wrapped values and the halo of the
+// last real column is exactly the periodic neighbour; such cells are
+// computed but never stored or counted.  Requires nx even (16-byte pairs).
+#include <hip/hip_runtime.h>
+
+#include "lx_device.h"
+#include "sweep_device.h"
+
+namespace lx {
+namespace {
+
+using namespace dev;
+
+constexpr int kPairTW = 128;                // tile columns
+constexpr int kPairPitch = kPairTW + 4;     // LDS row pitch in doubles (16-byte multiple)
+constexpr int kPairWaves = kBlockThreads / 64;
+
+template <int OP, int TH>
+struct PairLds {
+    double ym[TH + 4][kPairPitch];          // y_m: row r at [r + 2], column c at [c + 2]
+    double y1[TH + 2][kPairPitch];          // y_{m+1}: row r at [r + 1], column c at [c + 2]
+    double u[TH + 4][kPairPitch];           // Burgers state, laid out as ym
+};
+template <int TH>
+struct PairLds<kOpDiffAdv, TH> {
+    double ym[TH + 4][kPairPitch];
+    double y1[TH + 2][kPairPitch];
+};
+
+// The shifted operator at one point from its four neighbours (W, E, S, N),
+// its centre C and, for Burgers, u at the same cells: the stencils of the
+// single-sweep kernel, so both compute the same bits.
+template <int OP>
+__device__ __forceinline__ double shifted_at(const SweepArgs& a, const double shift, double W, double E, double S,
+                                             double N, double C, double uW, double uE, double uS, double uN) {
+    if constexpr (OP == kOpDiffAdv) {
+        return stencil_da(a.aW, a.aE, a.aS, a.aN, a.aC - shift, W, E, S, N, C);
+    } else {
+        return stencil_bu(a.kx, a.ky, a.gx, a.gy, a.kC - shift, W, E, S, N, C, uW, uE, uS, uN);
+    }
+}
+
+// the operator on LDS row `ce` (rows `up`, `dn` above and below) at the
+// column pair j, j+1 (j even)
+template <int OP>
+__device__ __forceinline__ void shifted_pair(const SweepArgs& a, const double shift, const double* up,
+                                             const double* ce, const double* dn, const double* uup,
+                                             const double* uce, const double* udn, const int j, double (&o)[2]) {
+    const double2 c2 = *reinterpret_cast<const double2*>(ce + j);
+    const double2 u2 = *reinterpret_cast<const double2*>(up + j);
+    const double2 d2 = *reinterpret_cast<const double2*>(dn + j);
+    const double l = ce[j - 1], r = ce[j + 2];
+    if constexpr (OP == kOpDiffAdv) {
+        o[0] = shifted_at<OP>(a, shift, l, c2.y, u2.x, d2.x, c2.x, 0, 0, 0, 0);
+        o[1] = shifted_at<OP>(a, shift, c2.x, r, u2.y, d2.y, c2.y, 0, 0, 0, 0);
+    } else {
+        const double2 uc = *reinterpret_cast<const double2*>(uce + j);
+        const double2 uu = *reinterpret_cast<const double2*>(uup + j);
+        const double2 ud = *reinterpret_cast<const double2*>(udn + j);
+        const double ul = uce[j - 1], ur = uce[j + 2];
+        o[0] = shifted_at<OP>(a, shift, l, c2.y, u2.x, d2.x, c2.x, ul, uc.y, uu.x, ud.x);
+        o[1] = shifted_at<OP>(a, shift, c2.x, r, u2.y, d2.y, c2.y, uc.x, ur, uu.y, ud.y);
+    }
+}
+
+template <int OP>
+__device__ __forceinline__ double shifted_one(const SweepArgs& a, const double shift, const double* up,
+                                              const double* ce, const double* dn, const double* uup,
+                                              const double* uce, const double* udn, const int j) {
+    if constexpr (OP == kOpDiffAdv) {
+        return shifted_at<OP>(a, shift, ce[j - 1], ce[j + 1], up[j], dn[j], ce[j], 0, 0, 0, 0);
+    } else {
+        return shifted_at<OP>(a, shift, ce[j - 1], ce[j + 1], up[j], dn[j], ce[j], uce[j - 1], uce[j + 1], uup[j],
+                              udn[j]);
+    }
+}
+
+template <int OP, int K, int TH>
+__device__ __forceinline__ void pair_tile(const SweepArgs& a, PairLds<OP, TH>& S, const double* __restrict__ yin,
+                                          double* __restrict__ yout, const int m, const bool first,
+                                          const int (&add0)[K], const int (&add1)[K], double& sy1, double& sy2,
+                                          double (&sp1)[K], double (&sp2)[K], const int tile) {
+    constexpr int RW = TH / kPairWaves;           // tile rows per wavefront
+    const int nx = a.nx, ny = a.ny;
+    const int x0 = (tile % a.tiles_x) * kPairTW, y0 = (tile / a.tiles_x) * TH;
+    const int tid = flat_tid(), lane = tid & 63, w = tid >> 6;
+    const double* __restrict__ uu = a.u;
+    const int j = 2 + 2 * lane;                   // LDS column of this lane's pair
+    const int gcol = x0 + 2 * lane;
+    const int gc = wrap(gcol, nx);                // even: nx and x0 are even
+    const double xm = a.xi[m], xm1 = a.xi[m + 1];
+
+    // ---- y_m (and u) on rows -2..TH+1, columns -2..129; the outputs ----
+    static_assert(TH % kPairWaves == 0, "tile rows must be a multiple of the wavefronts");
+    constexpr int RM = (TH + 4) / kPairWaves;     // staged rows of y_m per wavefront
+    double2 yv[RM];
+#pragma unroll
+    for (int i = 0; i < RM; ++i) {
+        const long g = wrap(y0 - 2 + w + i * kPairWaves, ny) * static_cast<long>(nx) + gc;
+        yv[i] = *reinterpret_cast<const double2*>(yin + g);
+    }
+    double edge = 0.0, uedge = 0.0;
+    int er = 0, ec = 0;
+    const bool has_edge = tid < (TH + 4) * 4;
+    if (has_edge) {
+        er = tid >> 2;
+        const int q = tid & 3;
+        ec = (q < 2) ? q : kPairTW + q;           // LDS columns 0, 1, 130, 131
+        const long g = wrap(y0 - 2 + er, ny) * static_cast<long>(nx) + wrap(x0 + ec - 2, nx);
+        edge = yin[g];
+        if constexpr (OP == kOpBurgersJ) uedge = uu[g];
+    }
+    // outputs of this thread's rows, fetched while the tile is staged
+    double2 pv[K][RW];
+    if (!first) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (!(add0[k] | add1[k])) continue;
+            const double* __restrict__ pk = a.p[k];
+#pragma unroll
+            for (int i = 0; i < RW; ++i) {
+                const int grow = y0 + w + i * kPairWaves;
+                if (gcol < nx && grow < ny)
+                    pv[k][i] = *reinterpret_cast<const double2*>(pk + static_cast<long>(grow) * nx + gcol);
+            }
+        }
+    }
+    if constexpr (OP == kOpBurgersJ) {
+#pragma unroll
+        for (int i = 0; i < RM; ++i) {
+            const int r = w + i * kPairWaves;
+            const long g = wrap(y0 - 2 + r, ny) * static_cast<long>(nx) + gc;
+            *reinterpret_cast<double2*>(&S.u[r][j]) = *reinterpret_cast<const double2*>(uu + g);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < RM; ++i) {
+        const int r = w + i * kPairWaves;
+        *reinterpret_cast<double2*>(&S.ym[r][j]) = yv[i];
+    }
+    if (has_edge) {
+        S.ym[er][ec] = edge;
+        if constexpr (OP == kOpBurgersJ) S.u[er][ec] = uedge;
+    }
+    __syncthreads();
+
+    // ---- y_{m+1} on rows -1..TH, columns -1..128 ----
+#pragma unroll
+    for (int i = 0; i < (TH + 2 + kPairWaves - 1) / kPairWaves; ++i) {
+        const int r = w + i * kPairWaves;
+        if (r >= TH + 2) break;
+        double o[2];
+        if constexpr (OP == kOpBurgersJ) {
+            shifted_pair<OP>(a, xm, S.ym[r], S.ym[r + 1], S.ym[r + 2], S.u[r], S.u[r + 1], S.u[r + 2], j, o);
+        } else {
+            shifted_pair<OP>(a, xm, S.ym[r], S.ym[r + 1], S.ym[r + 2], nullptr, nullptr, nullptr, j, o);
+        }
+        double2 t;
+        t.x = o[0];
+        t.y = o[1];
+        *reinterpret_cast<double2*>(&S.y1[r][j]) = t;
+    }
+    if (tid < (TH + 2) * 2) {
+        const int r = tid >> 1;
+        const int lc = (tid & 1) ? kPairTW + 2 : 1;   // columns 128 and -1
+        if constexpr (OP == kOpBurgersJ) {
+            S.y1[r][lc] = shifted_one<OP>(a, xm, S.ym[r], S.ym[r + 1], S.ym[r + 2], S.u[r], S.u[r + 1], S.u[r + 2], lc);
+        } else {
+            S.y1[r][lc] = shifted_one<OP>(a, xm, S.ym[r], S.ym[r + 1], S.ym[r + 2], nullptr, nullptr, nullptr, lc);
+        }
+    }
+    __syncthreads();
+
+    // ---- y_{m+2} on the tile; outputs; sums of squares ----
+#pragma unroll
+    for (int i = 0; i < RW; ++i) {
+        const int r = w + i * kPairWaves;
+        const int grow = y0 + r;
+        double o[2];
+        if constexpr (OP == kOpBurgersJ) {
+            shifted_pair<OP>(a, xm1, S.y1[r], S.y1[r + 1], S.y1[r + 2], S.u[r + 1], S.u[r + 2], S.u[r + 3], j, o);
+        } else {
+            shifted_pair<OP>(a, xm1, S.y1[r], S.y1[r + 1], S.y1[r + 2], nullptr, nullptr, nullptr, j, o);
+        }
+        if (gcol < nx && grow < ny) {
+            const long idx = static_cast<long>(grow) * nx + gcol;
+            const double2 c1 = *reinterpret_cast<const double2*>(&S.y1[r + 1][j]);
+            const double2 c0 = *reinterpret_cast<const double2*>(&S.ym[r + 2][j]);
+            double2 t;
+            t.x = o[0];
+            t.y = o[1];
+            *reinterpret_cast<double2*>(yout + idx) = t;
+            sy1 += c1.x * c1.x + c1.y * c1.y;
+            sy2 += o[0] * o[0] + o[1] * o[1];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (!(add0[k] | add1[k])) continue;
+                const double dm = a.coef[k * a.ld + m], dm1 = a.coef[k * a.ld + m + 1];
+                const double dm2 = a.coef[k * a.ld + m + 2];
+                double2 p;
+                if (first) {
+                    // p_0 = d_0 y_0 (+ optional base); y_0 = v is the centre
+                    p.x = dm * c0.x;
+                    p.y = dm * c0.y;
+                    if (a.base[k] != nullptr) {
+                        const double2 b = *reinterpret_cast<const double2*>(a.base[k] + idx);
+                        p.x += b.x;
+                        p.y += b.y;
+                    }
+                } else {
+                    p = pv[k][i];
+                    if (add0[k]) {
+                        p.x = fma(dm, c0.x, p.x);
+                        p.y = fma(dm, c0.y, p.y);
+                    }
+                }
+                if (add1[k]) {
+                    p.x = fma(dm1, c1.x, p.x);
+                    p.y = fma(dm1, c1.y, p.y);
+                }
+                *reinterpret_cast<double2*>(a.p[k] + idx) = p;
+                sp1[k] += p.x * p.x + p.y * p.y;
+                const double qx = fma(dm2, o[0], p.x), qy = fma(dm2, o[1], p.y);
+                sp2[k] += qx * qx + qy * qy;
+            }
+        }
+    }
+    __syncthreads();   // the next tile overwrites LDS
+}
+
+template <int OP, int K, int TH>
+__global__ __launch_bounds__(kBlockThreads) void leja_pair(SweepArgs a, const int L) {
+    LoopCtl* __restrict__ ctl = a.ctl;
+    if (ctl->slot[2].done) return;
+    constexpr int NV = 2 * (1 + K);
+    __shared__ int s_mode;   // 0: both terms, 1: deferred term only, 2: nothing
+    __shared__ int s_add0[K], s_add1[K];
+    const int tid = flat_tid();
+    const int m = 2 * L;
+    if (L == 0) {
+        if (tid == 0) {
+            s_mode = 0;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                s_add0[k] = 1;
+                s_add1[k] = ctl->slot[0].active[k];
+            }
+        }
+    } else {
+        double tot[NV];
+        sum_partials<NV>(a.partials + static_cast<long>((L - 1) & 1) * a.nb * NV, a.nb, tot);
+        if (tid == 0) {
+            const SweepState prev = ctl->slot[(L - 1) & 1];
+            const bool pub = blockIdx.x == 0;
+            if (prev.done) {
+                // the previous launch flushed the last deferred term
+                s_mode = 2;
+                if (pub) ctl->slot[2] = prev;
+            } else {
+                double t1[1 + K], t2[1 + K];
+                t1[0] = tot[0];
+                t2[0] = tot[1 + K];
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    t1[1 + k] = tot[1 + k];
+                    t2[1 + k] = tot[2 + K + k];
+                }
+                const SweepState s1 = decide<K, false>(a, *ctl, prev, m - 1, t1);
+                if (s1.done) {
+                    s_mode = 2;
+                    if (pub) {
+                        ctl->slot[L & 1] = s1;
+                        ctl->slot[2] = s1;
+                    }
+                } else {
+                    const SweepState s2 = decide<K, false>(a, *ctl, s1, m, t2);
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        s_add0[k] = s1.active[k];
+                        s_add1[k] = s2.done ? 0 : s2.active[k];
+                    }
+                    s_mode = s2.done ? 1 : 0;
+                    if (pub) ctl->slot[L & 1] = s2;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const int mode = s_mode;
+    if (mode == 2) return;
+    int add0[K], add1[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        add0[k] = s_add0[k];
+        add1[k] = s_add1[k];
+    }
+    const double* __restrict__ yin = (L == 0) ? a.v : static_cast<const double*>(a.ybuf[(L - 1) & 1]);
+
+    if (mode == 1) {
+        // p_k += d_m y_m for the outputs that passed the stop rule at term m
+        const long n2 = static_cast<long>(a.nx) * a.ny / 2;
+        for (long i = static_cast<long>(blockIdx.x) * kBlockThreads + tid; i < n2;
+             i += static_cast<long>(a.nb) * kBlockThreads) {
+            const double2 y = reinterpret_cast<const double2*>(yin)[i];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (!add0[k]) continue;
+                const double dm = a.coef[k * a.ld + m];
+                double2 p = reinterpret_cast<const double2*>(a.p[k])[i];
+                p.x = fma(dm, y.x, p.x);
+                p.y = fma(dm, y.y, p.y);
+                reinterpret_cast<double2*>(a.p[k])[i] = p;
+            }
+        }
+        return;
+    }
+
+    __shared__ PairLds<OP, TH> S;
+    double* __restrict__ yout = static_cast<double*>(a.ybuf[L & 1]);
+    double sy1 = 0.0, sy2 = 0.0, sp1[K], sp2[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        sp1[k] = 0.0;
+        sp2[k] = 0.0;
+    }
+    const int T = a.tiles_x * a.tiles_y;
+    for_each_tile(T, a.nb, [&](int t) {
+        pair_tile<OP, K, TH>(a, S, yin, yout, m, L == 0, add0, add1, sy1, sy2, sp1, sp2, t);
+    });
+    double v[NV];
+    v[0] = sy1;
+    v[1 + K] = sy2;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        v[1 + k] = sp1[k];
+        v[2 + K + k] = sp2[k];
+    }
+    block_sum<NV>(v);
+    if (tid == 0) {
+        double* __restrict__ P = a.partials + static_cast<long>(L & 1) * a.nb * NV + blockIdx.x * NV;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) P[q] = v[q];
+    }
+}
+
+template <int OP, int K>
+hipError_t launch_pair_th(int th, const SweepArgs& a, int L, hipStream_t s) {
+    const dim3 block(64, kPairWaves), grid(a.nb);
+    switch (th) {
+        case 8: hipLaunchKernelGGL((leja_pair<OP, K, 8>), grid, block, 0, s, a, L); break;
+        case 16: hipLaunchKernelGGL((leja_pair<OP, K, 16>), grid, block, 0, s, a, L); break;
+        case 32: hipLaunchKernelGGL((leja_pair<OP, K, 32>), grid, block, 0, s, a, L); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int OP>
+hipError_t launch_pair_k(int K, int th, const SweepArgs& a, int L, hipStream_t s) {
+    switch (K) {
+        case 1: return launch_pair_th<OP, 1>(th, a, L, s);
+        case 2: return launch_pair_th<OP, 2>(th, a, L, s);
+        case 3: return launch_pair_th<OP, 3>(th, a, L, s);
+        case 4: return launch_pair_th<OP, 4>(th, a, L, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_leja_pair(int op, int K, int th, const SweepArgs& a, int L, hipStream_t s) {
+    if (a.nb < 1 || a.nx % 2 != 0 || a.nx < 2 || a.ny < 2) return hipErrorInvalidValue;
+    if (a.tiles_x != (a.nx + kPairTW - 1) / kPairTW || a.tiles_y != (a.ny + th - 1) / th)
+        return hipErrorInvalidValue;
+    if (op == kOpDiffAdv) return launch_pair_k<kOpDiffAdv>(K, th, a, L, s);
+    if (op == kOpBurgersJ) return launch_pair_k<kOpBurgersJ>(K, th, a, L, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace lx

@@ -112,6 +112,33 @@ __device__ __forceinline__ void sum_partials(const double* __restrict__ P, int n
 }
 
 // ---------------------------------------------------------------------------
+// the stencils, with every product and sum in a fixed order (explicit FMAs,
+// no contraction left to the compiler), so that all kernels compute the
+// same bits from the same inputs
+// ---------------------------------------------------------------------------
+
+// diffusion-advection: cW W + cE E + cS S + cN N + cC C
+template <typename T>
+__device__ __forceinline__ T stencil_da(T cW, T cE, T cS, T cN, T cC, T W, T E, T S, T N, T C) {
+#pragma clang fp contract(off)
+    return fma(cN, N, fma(cS, S, fma(cE, E, fma(cW, W, cC * C))));
+}
+
+// Burgers Jacobian: kx (E + W) + ky (N + S) - gx (uE E - uW W) - gy (uN N - uS S) + kc C
+template <typename T>
+__device__ __forceinline__ T stencil_bu(T kx, T ky, T gx, T gy, T kc, T W, T E, T S, T N, T C, T uW, T uE, T uS,
+                                        T uN) {
+#pragma clang fp contract(off)
+    const T ax = fma(uE, E, -(uW * W));
+    const T ay = fma(uN, N, -(uS * S));
+    T r = kc * C;
+    r = fma(kx, E + W, r);
+    r = fma(ky, N + S, r);
+    r = fma(-gx, ax, r);
+    return fma(-gy, ay, r);
+}
+
+// ---------------------------------------------------------------------------
 // Leja sweep
 // ---------------------------------------------------------------------------
 
@@ -181,10 +208,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int m, cons
             const AT aN = static_cast<AT>(a.aN), aS = static_cast<AT>(a.aS);
             const AT ac = static_cast<AT>(a.aC - xim);
             if constexpr (V == 2) {
-                o[0] = aW * left + aE * cen[1] + aS * up[0] + aN * dn[0] + ac * cen[0];
-                o[1] = aW * cen[0] + aE * right + aS * up[1] + aN * dn[1] + ac * cen[1];
+                o[0] = stencil_da(aW, aE, aS, aN, ac, left, cen[1], up[0], dn[0], cen[0]);
+                o[1] = stencil_da(aW, aE, aS, aN, ac, cen[0], right, up[1], dn[1], cen[1]);
             } else {
-                o[0] = aW * left + aE * right + aS * up[0] + aN * dn[0] + ac * cen[0];
+                o[0] = stencil_da(aW, aE, aS, aN, ac, left, right, up[0], dn[0], cen[0]);
             }
         } else {
             const AT kx = static_cast<AT>(a.kx), ky = static_cast<AT>(a.ky);
@@ -201,13 +228,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int m, cons
                 ur = uu32[rw * nx + cr];
             }
             if constexpr (V == 2) {
-                o[0] = kx * (cen[1] + left) + ky * (dn[0] + up[0]) - gx * (ucen[1] * cen[1] - ul * left) -
-                       gy * (udn[0] * dn[0] - uup[0] * up[0]) + kc * cen[0];
-                o[1] = kx * (right + cen[0]) + ky * (dn[1] + up[1]) - gx * (ur * right - ucen[0] * cen[0]) -
-                       gy * (udn[1] * dn[1] - uup[1] * up[1]) + kc * cen[1];
+                o[0] = stencil_bu(kx, ky, gx, gy, kc, left, cen[1], up[0], dn[0], cen[0], ul, ucen[1], uup[0], udn[0]);
+                o[1] = stencil_bu(kx, ky, gx, gy, kc, cen[0], right, up[1], dn[1], cen[1], ucen[0], ur, uup[1], udn[1]);
             } else {
-                o[0] = kx * (right + left) + ky * (dn[0] + up[0]) - gx * (ur * right - ul * left) -
-                       gy * (udn[0] * dn[0] - uup[0] * up[0]) + kc * cen[0];
+                o[0] = stencil_bu(kx, ky, gx, gy, kc, left, right, up[0], dn[0], cen[0], ul, ur, uup[0], udn[0]);
             }
         }
         TO ot[V];
@@ -345,23 +369,22 @@ __device__ __forceinline__ void power_tile(const PowerArgs& a, const double s, d
         double o[V];
         if constexpr (OP == kOpDiffAdv) {
             if constexpr (V == 2) {
-                o[0] = a.cW * left + a.cE * cen[1] + a.cS * up[0] + a.cN * dn[0] + a.cC * cen[0];
-                o[1] = a.cW * cen[0] + a.cE * right + a.cS * up[1] + a.cN * dn[1] + a.cC * cen[1];
+                o[0] = stencil_da(a.cW, a.cE, a.cS, a.cN, a.cC, left, cen[1], up[0], dn[0], cen[0]);
+                o[1] = stencil_da(a.cW, a.cE, a.cS, a.cN, a.cC, cen[0], right, up[1], dn[1], cen[1]);
             } else {
-                o[0] = a.cW * left + a.cE * right + a.cS * up[0] + a.cN * dn[0] + a.cC * cen[0];
+                o[0] = stencil_da(a.cW, a.cE, a.cS, a.cN, a.cC, left, right, up[0], dn[0], cen[0]);
             }
         } else {
             ldv<V>(uu + rn * nx + c0, udn);
             const double ul = uu[rw * nx + cl], ur = uu[rw * nx + cr];
             const double kc = -2.0 * a.kx - 2.0 * a.ky;
             if constexpr (V == 2) {
-                o[0] = a.kx * (cen[1] + left) + a.ky * (dn[0] + up[0]) - a.gx * (ucen[1] * cen[1] - ul * left) -
-                       a.gy * (udn[0] * dn[0] - uup[0] * up[0]) + kc * cen[0];
-                o[1] = a.kx * (right + cen[0]) + a.ky * (dn[1] + up[1]) - a.gx * (ur * right - ucen[0] * cen[0]) -
-                       a.gy * (udn[1] * dn[1] - uup[1] * up[1]) + kc * cen[1];
+                o[0] = stencil_bu(a.kx, a.ky, a.gx, a.gy, kc, left, cen[1], up[0], dn[0], cen[0], ul, ucen[1], uup[0],
+                                  udn[0]);
+                o[1] = stencil_bu(a.kx, a.ky, a.gx, a.gy, kc, cen[0], right, up[1], dn[1], cen[1], ucen[0], ur, uup[1],
+                                  udn[1]);
             } else {
-                o[0] = a.kx * (right + left) + a.ky * (dn[0] + up[0]) - a.gx * (ur * right - ul * left) -
-                       a.gy * (udn[0] * dn[0] - uup[0] * up[0]) + kc * cen[0];
+                o[0] = stencil_bu(a.kx, a.ky, a.gx, a.gy, kc, left, right, up[0], dn[0], cen[0], ul, ur, uup[0], udn[0]);
             }
         }
 #pragma unroll

@@ -39,11 +39,33 @@ def test_binding_covers_the_header(lib):
     assert sorted(EXPORTED) == _declared_functions()
 
 
-def test_struct_layouts_match_the_header(lib):
-    from paper_2310_08344_amd.binding import LejaOpts, Operator, Stats
-    assert ctypes.sizeof(Operator) == 4 * 3 + 4 + 8 * 6 + 4 + 4   # ints, padding, doubles, int, tail pad
-    assert ctypes.sizeof(LejaOpts) == 8 + 8 + 8 + 8
-    assert ctypes.sizeof(Stats) == 4 * 3 + 4 * 4 + 4 + 8 * 4 * 2 + 8 * 6
+def test_struct_layouts_match_the_header(lib, tmp_path):
+    """Sizes and field offsets of the binding's ctypes structures against a C
+    compiler's reading of include/lx.h."""
+    import shutil
+    import subprocess
+    from paper_2310_08344_amd.binding import Instance, InstanceResult, LejaOpts, Operator, Stats
+    structs = {"lx_operator": Operator, "lx_leja_opts": LejaOpts, "lx_stats": Stats, "lx_instance": Instance,
+               "lx_instance_result": InstanceResult}
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lx.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(ln.split()[:2]): int(ln.split()[2]) for ln in out if ln}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
 
 
 def test_leja_points_agree_with_oracle(lib):

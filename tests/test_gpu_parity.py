@@ -328,6 +328,7 @@ def test_every_launch_shape_matches_oracle(ctx, tile):
     outs = [dev(np.zeros((136, 200))) for _ in range(3)]
     say("forced tile", tile)
     ctx.set_tile(*tile)
+    ctx.set_depth(1)
     try:
         r = ctx.phi_leja(_op(prm), dev(v), outs, [0, 1, 3], h, c, g, rtol=1e-8, max_iters=200)
         n = 120
@@ -342,6 +343,8 @@ def test_every_launch_shape_matches_oracle(ctx, tile):
         rb = ctx.phi_leja(op_b, dev(vb), [ob], [1], hb, cb, gb, u=dev(ub), rtol=1e-8, max_iters=200)
     finally:
         ctx.set_tile(0, 0, 0, 0)
+        ctx.set_depth(0)
+    assert r.stats["depth"] == 1 and rb.stats["depth"] == 1
     spec = [(0, 1.0, 1.0), (1, 1.0, 1.0), (3, 1.0, 1.0)]
     oracle_parity([host(o) for o in outs], r.iters,
                   lambda f: leja_phi(_A(prm), v, spec, h, c, g, 1e-8, 0.0, 200, f), PARITY)
@@ -352,12 +355,121 @@ def test_every_launch_shape_matches_oracle(ctx, tile):
                                      hb, cb, gb, 1e-8, 0.0, 200, f), PARITY)
 
 
+# ---------------------------------------------------------------------------
+# two iterations per launch: the oracle, and one iteration per launch
+# ---------------------------------------------------------------------------
+
+PAIR_SHAPES = [(8, 0), (16, 0), (32, 0), (16, 8), (8, 24), (32, 16)]
+
+
+def _solve_depth(ctx, depth, th, nb, op, v, ls, h, c, g, u=None, **kw):
+    outs = [dev(np.zeros(v.shape)) for _ in ls]
+    ctx.set_depth(depth, th, nb)
+    try:
+        r = ctx.phi_leja(op, dev(v), outs, ls, h, c, g, u=None if u is None else dev(u), **kw)
+    finally:
+        ctx.set_depth(0)
+    return r, [host(o) for o in outs]
+
+
+@pytest.mark.parametrize("th,nb", PAIR_SHAPES)
+def test_two_iteration_launches_match_oracle(ctx, th, nb):
+    """Ragged tiles in both directions (200 = 128 + 72 columns, 136 rows),
+    phi_0, phi_1, phi_3 from one basis; a Burgers Jacobian with u staged
+    beside y; against the oracle and against one iteration per launch."""
+    prm, h = diffadv_setup(200, 136)
+    c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
+    v = np.random.default_rng(31).standard_normal((136, 200))
+    say("pair shape", th, nb)
+    r2, o2 = _solve_depth(ctx, 2, th, nb, _op(prm), v, [0, 1, 3], h, c, g, rtol=1e-8, max_iters=200)
+    r1, o1 = _solve_depth(ctx, 1, 0, 0, _op(prm), v, [0, 1, 3], h, c, g, rtol=1e-8, max_iters=200)
+    assert r2.stats["depth"] == 2 and r1.stats["depth"] == 1
+    spec = [(0, 1.0, 1.0), (1, 1.0, 1.0), (3, 1.0, 1.0)]
+    oracle_parity(o2, r2.iters, lambda f: leja_phi(_A(prm), v, spec, h, c, g, 1e-8, 0.0, 200, f), PARITY)
+    if r2.iters == r1.iters:
+        assert max(rel(a, b) for a, b in zip(o2, o1)) <= 1e-13
+    n = 120
+    ub = W.fourier_modes(n, seed=5)[:90, :]
+    op_b = B.make_operator(kind=B.LX_OP_BURGERS2D, nx=n, ny=90, dx=1 / n, dy=1 / 90, nu=2e-3)
+    vb = np.random.default_rng(2).standard_normal((90, n))
+    hb = 5.0 * W.burgers_cfl_step(2e-3, float(np.max(np.abs(ub))), 1 / n, 1 / 90)
+    rho = 2.0 / W.burgers_cfl_step(2e-3, float(np.max(np.abs(ub))), 1 / n, 1 / 90)
+    cb, gb = -1.05 * rho / 2.0, 1.05 * rho / 4.0
+    rb, ob = _solve_depth(ctx, 2, th, nb, op_b, vb, [1, 2], hb, cb, gb, u=ub, rtol=1e-8, max_iters=200)
+    assert rb.stats["depth"] == 2
+    Ab = lambda w: burgers_J(ub, w, 2e-3, 1 / n, 1 / 90)
+    oracle_parity(ob, rb.iters, lambda f: leja_phi(Ab, vb, [(1, 1.0, 1.0), (2, 1.0, 1.0)], hb, cb, gb, 1e-8, 0.0,
+                                                    200, f), PARITY)
+
+
+@pytest.mark.parametrize("nx,ny", [(6, 5), (4, 3), (130, 7), (256, 40)])
+def test_two_iteration_launches_small_and_odd_grids(ctx, nx, ny):
+    """Grids narrower than a tile (indices wrap several times), an odd
+    number of rows, a single partial tile row."""
+    prm, h = diffadv_setup(nx, ny, cfl=20.0)
+    c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
+    v = np.random.default_rng(nx * 100 + ny).standard_normal((ny, nx))
+    say("pair small grid", nx, ny)
+    r, o = _solve_depth(ctx, 2, 16, 0, _op(prm), v, [0, 2, 1, 3], h, c, g, rtol=1e-9, max_iters=300)
+    assert r.stats["depth"] == 2
+    spec = [(0, 1.0, 1.0), (2, 1.0, 1.0), (1, 1.0, 1.0), (3, 1.0, 1.0)]
+    oracle_parity(o, r.iters, lambda f: leja_phi(_A(prm), v, spec, h, c, g, 1e-9, 0.0, 300, f), PARITY)
+
+
+@pytest.mark.parametrize("max_iters", [1, 2, 5, 6])
+def test_two_iteration_launches_at_max_iters(ctx, max_iters):
+    """An odd and an even budget end on the first and on the second test of
+    a launch (the even one with a deferred last term)."""
+    prm, h = diffadv_setup(96, 64)
+    c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
+    v = np.random.default_rng(4).standard_normal((64, 96))
+    say("pair notconv", max_iters)
+    r, o = _solve_depth(ctx, 2, 16, 0, _op(prm), v, [0], h, c, g, rtol=1e-12, max_iters=max_iters,
+                        raise_on_error=False)
+    assert r.status == B.LX_ENOTCONV and r.iters == [max_iters]
+    ref = leja_phi(_A(prm), v, [(0, 1.0, 1.0)], h, c, g, 1e-12, 0.0, max_iters)
+    assert rel(o[0], ref.p[0]) <= PARITY
+    F = (max_iters + 1) // 2
+    assert r.stats["n_launch"] == F + (1 if max_iters % 2 == 0 else 0)
+    assert r.stats["n_apply"] == 2 * F
+
+
+def test_two_iteration_exprb42_matches_one_iteration(ctx):
+    n = 128
+    u0 = W.fourier_modes(n, seed=9)
+    nu = 1e-3
+    op = B.make_operator(kind=B.LX_OP_BURGERS2D, n=n, nu=nu)
+    h = 10.0 * W.burgers_cfl_step(nu, float(np.max(np.abs(u0))), 1 / n, 1 / n)
+    rho, c, g = ctx.spectrum(op, u=dev(u0), iters=20)
+    outs = {}
+    for depth in (2, 1):
+        o = dev(np.zeros((n, n)))
+        ctx.set_depth(depth)
+        try:
+            say("exprb42 depth", depth)
+            r = ctx.exprb_step(op, dev(u0), o, h, c, g, rtol=1e-8, max_iters=300)
+        finally:
+            ctx.set_depth(0)
+        assert r.status == B.LX_OK and r.stats["depth"] == depth
+        outs[depth] = (host(o), r.iters)
+    ref = exprb42_step(u0, nu, 1 / n, 1 / n, h, c, g, 1e-8, 0.0, 300)
+    assert ref.status == "ok"
+    if list(ref.iters) == list(outs[2][1]):
+        assert rel(outs[2][0], ref.u_next) <= PARITY
+    else:
+        say("stop decision differs", ref.iters, outs[2][1])
+        assert rel(outs[2][0] - u0, ref.u_next - u0) <= 1e-7
+    if outs[2][1] == outs[1][1]:
+        assert rel(outs[2][0] - u0, outs[1][0] - u0) <= 1e-12
+
+
 def test_tune_then_solve(ctx):
     prm, h = diffadv_setup(384, 256)
     c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
     say("tune 384x256")
     rows = ctx.tune(_op(prm), K=2, sweeps=3)
-    assert len(rows) >= 4 and all(r[4] > 0 for r in rows)
+    assert len(rows) >= 4 and all(r[5] > 0 for r in rows)
+    assert {r[0] for r in rows} == {1, 2}
     v = np.random.default_rng(41).standard_normal((256, 384))
     outs = [dev(np.zeros((256, 384))) for _ in range(2)]
     r = ctx.phi_leja(_op(prm), dev(v), outs, [1, 2], h, c, g, rtol=1e-8, max_iters=200)
