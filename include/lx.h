@@ -119,7 +119,9 @@ typedef struct {
  * Errors: LX_EINVAL (n_max < 9, k_max out of range), LX_ENOMEM, LX_EDEVICE. */
 lx_status lx_create(lx_ctx** ctx, size_t n_max, int k_max, void* stream);
 
-/* Frees every workspace (Listing 10, destructor).  NULL is a no-op. */
+/* Frees every workspace (Listing 10, destructor) and destroys the
+ * predictors created on this context, whose handles become invalid.
+ * NULL is a no-op. */
 void lx_destroy(lx_ctx* ctx);
 
 /* Changes the stream later calls enqueue on. */
@@ -272,6 +274,8 @@ typedef struct lx_predictor lx_predictor;
  * from a splitmix64 stream of the given seed, zero biases and moments,
  * identity standardisation. */
 lx_status lx_predictor_create(lx_ctx* ctx, unsigned long long seed, lx_predictor** out);
+/* Frees a predictor; call it before lx_destroy of its context, or not at
+ * all (lx_destroy frees the context's remaining predictors). */
 void lx_predictor_destroy(lx_predictor* p);
 int lx_predictor_state_size(void);
 

@@ -205,9 +205,14 @@ class Context:
         if st != LX_OK:
             raise LxError(st, "lx_create failed")
         self.n_max, self.k_max = int(n_max), int(k_max)
+        import weakref
+        self._predictors = weakref.WeakSet()
 
     def close(self) -> None:
         if self._h:
+            # lx_destroy frees the context's predictors: their handles go first
+            for p in list(self._predictors):
+                p._h = _P()
             self.lib.c.lx_destroy(self._h)
             self._h = _P()
 
@@ -367,6 +372,7 @@ class Predictor:
         self._h = _P()
         ctx._check(self.c.lx_predictor_create(ctx._h, C.c_ulonglong(int(seed)), C.byref(self._h)))
         self.state_size = int(self.c.lx_predictor_state_size())
+        ctx._predictors.add(self)
 
     def close(self):
         if self._h:

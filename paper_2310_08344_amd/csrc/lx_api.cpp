@@ -527,6 +527,7 @@ lx_status lx_get_stats(const lx_ctx* ctx, lx_stats* out) {
 
 void lx_destroy(lx_ctx* ctx) {
     if (ctx == nullptr) return;
+    while (!ctx->predictors.empty()) lx_predictor_destroy(ctx->predictors.back());
     (void)hipStreamSynchronize(ctx->stream);
     for (double* p : ctx->ybuf) (void)hipFree(p);
     for (double* p : ctx->ws) (void)hipFree(p);

@@ -61,6 +61,7 @@ struct lx_ctx {
     int pair_th = 0, pair_nb = 0;           // lx_set_depth: forced leja_pair shape (0: automatic)
     std::map<std::tuple<int, int, int, int, int>, lx::Tile> tuned;
     lx_batch_ws batch;
+    std::vector<lx_predictor*> predictors;  // live predictors; lx_destroy frees them
     lx_stats stats{};
     std::string err;
 };

@@ -1,6 +1,7 @@
 // C ABI of the spectral/budget predictor (declarations and contracts in lx.h).
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -102,13 +103,18 @@ lx_status lx_predictor_create(lx_ctx* ctx, unsigned long long seed, lx_predictor
         return bail(LX_EDEVICE);
     for (int j = 0; j < lx::kMlpIn; ++j) p->sc.std_x[j] = 1.0f;
     for (int o = 0; o < lx::kMlpOut; ++o) p->sc.std_y[o] = 1.0f;
+    ctx->predictors.push_back(p);
     *out = p;
     return LX_OK;
 }
 
 void lx_predictor_destroy(lx_predictor* p) {
     if (p == nullptr) return;
-    if (p->ctx) (void)hipStreamSynchronize(p->ctx->stream);
+    if (p->ctx) {
+        auto& v = p->ctx->predictors;
+        v.erase(std::remove(v.begin(), v.end(), p), v.end());
+        (void)hipStreamSynchronize(p->ctx->stream);
+    }
     (void)hipFree(p->theta);
     (void)hipFree(p->grad);
     (void)hipFree(p->d_loss);

@@ -192,12 +192,16 @@ def batched_instances(count: int = 256, seed: int = 4,
 def learned_instance(index: int, seed0: int, sizes=(64, 128, 256)):
     """One instance of the predictor's training/evaluation distribution,
     drawn from its own seed (seed0 + index).  Even indices: diffusion-
-    advection as in ``batched_instances`` (Gaussian input); odd indices:
-    Burgers with nu ~ LogU(1e-4, 1e-2) and a four-mode Fourier state u,
-    whose Jacobian acts on v = u.  Steps h = s x CFL with s ~ LogU(1, 100)
-    for diffusion-advection and s ~ LogU(1, 10) for Burgers (reading: the
-    advection-dominated Burgers Jacobians have nearly imaginary spectra,
-    where larger steps need hundreds of sweeps); phi order l ~ U{0..3}.
+    advection as in ``batched_instances`` (Gaussian input), h = s x CFL with
+    s ~ LogU(1, 100); odd indices: Burgers with a four-mode Fourier state u,
+    whose Jacobian acts on v = u, viscosity from the cell Peclet number
+    Pe = max|u| dx / nu ~ LogU(1/4, 4) and h = s x CFL with s ~ LogU(1, 10);
+    phi order l ~ U{0..3}.  (Reading: interpolation at real Leja points needs
+    the Jacobian's spectrum close to the negative real axis; at cell Peclet
+    numbers well above 2 the centred Burgers Jacobian is advection-dominated,
+    its spectrum nearly imaginary, and the plain method diverges, so the
+    distribution keeps to the diffusion-dominated regime of the Burgers
+    workload at 2048^2, where Pe is about 2.)
     Returns (Problem, u or None, v)."""
     rng = np.random.default_rng(seed0 + index)
     n = int(rng.choice(sizes))
@@ -214,9 +218,11 @@ def learned_instance(index: int, seed0: int, sizes=(64, 128, 256)):
         p = Problem(DIFFADV, n, D=D, vx=vx, vy=vy, h=h, cfl_multiple=s, seed=seed0 + index,
                     meta={"l": l, "index": index})
         return p, None, gaussian(n, float(cx), float(cy))
-    nu = float(math.exp(rng.uniform(math.log(1e-4), math.log(1e-2))))
+    pe = float(math.exp(rng.uniform(math.log(0.25), math.log(4.0))))
     s = float(math.exp(rng.uniform(0.0, math.log(10.0))))
     u = fourier_modes(n, int(rng.integers(0, 2**31 - 1)))
-    h = s * burgers_cfl_step(nu, float(np.max(np.abs(u))), dx, dx)
+    umax = float(np.max(np.abs(u)))
+    nu = umax * dx / pe
+    h = s * burgers_cfl_step(nu, umax, dx, dx)
     p = Problem(BURGERS, n, nu=nu, h=h, cfl_multiple=s, seed=seed0 + index, meta={"l": l, "index": index})
     return p, u, u.copy()
