@@ -230,6 +230,7 @@ typedef struct {
     double pnorm;           /* rms norm of the output                               */
     double rho_hat;         /* power-iteration estimate (0 when none ran)           */
     double c, gamma;        /* shift and scale that were used                       */
+    int fallback;           /* lx_phi_leja_learned: solved again by the plain method */
 } lx_instance_result;
 
 /* Computes every instance of a batch with one launch per sweep for the whole
@@ -311,6 +312,23 @@ lx_status lx_predictor_infer(lx_predictor* p, const float* d_x, int n, float* d_
 /* The 8 features of each instance into d_x[n][8] (device), enqueued on the
  * context's stream. */
 lx_status lx_instance_features(lx_ctx* ctx, int n, const lx_instance* inst, float* d_x);
+
+/* The learned form of lx_phi_leja_batched.  The predictor maps each
+ * instance's features to (a, b) ~ (log(safety * rho_hat), log(sweeps)); the
+ * instance then runs without power iteration, with lambda = -exp(a +
+ * margin_log_rho), c = lambda/2, gamma = -lambda/4 and a budget of
+ * ceil(exp(b + margin_log_sweeps)) + 1 sweeps (at most o->max_iters; the
+ * instance's own c, gamma and budget fields are ignored).  The prediction
+ * is accepted when the Leja loop converges within that budget; every other
+ * instance (and any with a non-finite prediction) is solved again by the
+ * plain method: power_iters (>= 1) power-iteration sweeps with the given
+ * safety factor, then the loop with o->max_iters.  res[i].fallback says
+ * which; res[i].rho_hat is 0 for accepted instances.  The predictor must
+ * belong to ctx.  fallbacks (host, may be NULL) receives their number.
+ * Statuses as for lx_phi_leja_batched, after the fallback. */
+lx_status lx_phi_leja_learned(lx_ctx* ctx, lx_predictor* p, int n, const lx_instance* inst, double margin_log_rho,
+                              double margin_log_sweeps, int power_iters, double safety, const lx_leja_opts* o,
+                              lx_instance_result* res, int* fallbacks);
 
 /* ---- launch shapes and measurement ------------------------------------ */
 

@@ -65,11 +65,11 @@ class Instance(C.Structure):
 
 class InstanceResult(C.Structure):
     _fields_ = [("status", C.c_int), ("iters", C.c_int), ("err", C.c_double), ("pnorm", C.c_double),
-                ("rho_hat", C.c_double), ("c", C.c_double), ("gamma", C.c_double)]
+                ("rho_hat", C.c_double), ("c", C.c_double), ("gamma", C.c_double), ("fallback", C.c_int)]
 
     def as_dict(self) -> dict:
         return {"status": self.status, "iters": self.iters, "err": self.err, "pnorm": self.pnorm,
-                "rho_hat": self.rho_hat, "c": self.c, "gamma": self.gamma}
+                "rho_hat": self.rho_hat, "c": self.c, "gamma": self.gamma, "fallback": bool(self.fallback)}
 
 
 _P = C.c_void_p
@@ -131,6 +131,9 @@ def _signatures(lib: C.CDLL) -> None:
     lib.lx_predictor_infer.restype = _I
     lib.lx_instance_features.argtypes = [_P, _I, C.POINTER(Instance), _P]
     lib.lx_instance_features.restype = _I
+    lib.lx_phi_leja_learned.argtypes = [_P, _P, _I, C.POINTER(Instance), _D, _D, _I, _D, C.POINTER(LejaOpts),
+                                        C.POINTER(InstanceResult), C.POINTER(_I)]
+    lib.lx_phi_leja_learned.restype = _I
     lib.lx_tune.argtypes = [_P, C.POINTER(Operator), _I, _I, C.c_char_p, C.c_size_t]
     lib.lx_tune.restype = _I
     lib.lx_set_tile.argtypes = [_P, _I, _I, _I, _I, _I]
@@ -153,6 +156,7 @@ EXPORTED = ["lx_create", "lx_destroy", "lx_set_stream", "lx_set_timing", "lx_las
             "lx_predictor_create", "lx_predictor_destroy", "lx_predictor_state_size", "lx_predictor_set_scaling",
             "lx_predictor_get_state", "lx_predictor_set_state", "lx_predictor_save", "lx_predictor_load",
             "lx_predictor_gradient", "lx_predictor_train", "lx_predictor_infer", "lx_instance_features",
+            "lx_phi_leja_learned",
             "lx_leja_points", "lx_phi_scalar", "lx_newton_coeffs"]
 
 
@@ -190,6 +194,18 @@ class PhiResult:
     iters: list
     err: list
     stats: dict
+
+
+class Batch:
+    """A prepared lx_instance array (Context.prepare) and the instance dicts
+    whose tensors it points to."""
+
+    def __init__(self, array, keep):
+        self.array = array
+        self.keep = keep
+
+    def __len__(self):
+        return len(self.keep)
 
 
 class Context:
@@ -300,8 +316,15 @@ class Context:
             self._check(st, allow=(LX_OK, LX_ENOTCONV))
         return PhiResult(st, list(it), list(er), self.stats())
 
+    def prepare(self, instances) -> "Batch":
+        """The lx_instance array of a batch, built once and reusable: the
+        dicts' tensors are kept alive with it."""
+        return Batch(self._instances(instances), list(instances))
+
     @staticmethod
     def _instances(instances):
+        if isinstance(instances, Batch):
+            return instances.array
         n = len(instances)
         arr = (Instance * n)()
         for i, q in enumerate(instances):
@@ -330,6 +353,22 @@ class Context:
         if raise_on_error:
             self._check(st, allow=(LX_OK, LX_ENOTCONV))
         return st, [r.as_dict() for r in res]
+
+    def phi_leja_learned(self, instances, predictor, margin_log_rho, margin_log_sweeps, power_iters=20, safety=1.05,
+                         rtol=1e-8, atol=0.0, max_iters=500, raise_on_error=True):
+        """lx_phi_leja_learned: the predictor's bound and budget, plain-method
+        fallback.  Returns (status, [result dict per instance], fallbacks)."""
+        n = len(instances)
+        arr = self._instances(instances)
+        res = (InstanceResult * n)()
+        opts = LejaOpts(float(rtol), float(atol), int(max_iters), 1e4)
+        nf = _I()
+        st = self.lib.c.lx_phi_leja_learned(self._h, predictor._h, n, arr, float(margin_log_rho),
+                                            float(margin_log_sweeps), int(power_iters), float(safety),
+                                            C.byref(opts), res, C.byref(nf))
+        if raise_on_error:
+            self._check(st, allow=(LX_OK, LX_ENOTCONV))
+        return st, [r.as_dict() for r in res], nf.value
 
     def features(self, instances, out):
         """lx_instance_features: out is a float32 CUDA tensor [n, 8]."""
@@ -445,6 +484,10 @@ class Library:
             raise RuntimeError(f"HIP library not built: {path} is missing "
                                "(run python -m paper_2310_08344_amd.build)")
         self.path = path
+        # PyTorch ships its own HIP runtime under the same soname as the one
+        # the library links; loading torch first makes both use that single
+        # runtime (a second one would not know torch's streams)
+        import torch  # noqa: F401
         self.c = C.CDLL(path)
         _signatures(self.c)
 

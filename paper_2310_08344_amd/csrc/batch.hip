@@ -14,6 +14,7 @@
 
 #include "dd_math.h"
 #include "lx_device.h"
+#include "stencil_coeffs.h"
 #include "sweep_device.h"
 
 namespace lx {
@@ -22,7 +23,7 @@ namespace {
 using namespace dev;
 
 constexpr int kCoefThreads = 64;
-constexpr int kMaxCoef = 1001;
+constexpr int kMaxCoef = 1002;   // coefficients per instance: max_iters + 2 (two-iteration launches)
 
 struct Who {
     int i;   // instance
@@ -76,17 +77,16 @@ __global__ __launch_bounds__(kBlockThreads) void batch_power_norm_kernel(const B
 
 __device__ __forceinline__ void power_coeffs(const BatchInst& I, PowerArgs& a) {
     if (I.kind == kOpDiffAdv) {
-        const double ex = I.D / (I.dx * I.dx), ey = I.D / (I.dy * I.dy);
-        a.cE = ex + fmax(I.vx, 0.0) / I.dx;
-        a.cW = ex + fmax(-I.vx, 0.0) / I.dx;
-        a.cN = ey + fmax(I.vy, 0.0) / I.dy;
-        a.cS = ey + fmax(-I.vy, 0.0) / I.dy;
-        a.cC = -(a.cE + a.cW + a.cN + a.cS);
+        a.cE = I.pw[0];
+        a.cW = I.pw[1];
+        a.cN = I.pw[2];
+        a.cS = I.pw[3];
+        a.cC = I.pw[4];
     } else {
-        a.kx = I.nu / (I.dx * I.dx);
-        a.ky = I.nu / (I.dy * I.dy);
-        a.gx = 1.0 / (2.0 * I.dx);
-        a.gy = 1.0 / (2.0 * I.dy);
+        a.kx = I.pw[0];
+        a.ky = I.pw[1];
+        a.gx = I.pw[2];
+        a.gy = I.pw[3];
     }
 }
 
@@ -99,19 +99,25 @@ __global__ __launch_bounds__(kBlockThreads) void batch_power_sweep_kernel(const 
     double tot[1];
     sum_partials<1>(P + static_cast<long>((k - 1) & 1) * I.nb, I.nb, tot);
     const double s = 1.0 / sqrt(tot[0]);
-    PowerArgs a{};
-    a.nx = I.nx;
-    a.ny = I.ny;
-    a.tiles_x = I.tiles_x;
-    a.tiles_y = I.tiles_y;
-    a.nb = I.nb;
-    power_coeffs(I, a);
-    a.in = (k == 0) ? (I.has_x0 ? I.x0 : I.y[1]) : I.y[(k - 1) & 1];
-    a.out = I.y[k & 1];
-    a.u = I.u;
+    // the arguments live in LDS: a per-lane copy selected by the parity of
+    // k would spill to scratch
+    __shared__ PowerArgs a;
+    if (flat_tid() == 0) {
+        a = PowerArgs{};
+        a.nx = I.nx;
+        a.ny = I.ny;
+        a.tiles_x = I.ptiles_x;
+        a.tiles_y = I.ptiles_y;
+        a.nb = I.nb;
+        power_coeffs(I, a);
+        a.in = (k == 0) ? (I.has_x0 ? I.x0 : I.y[1]) : I.y[(k - 1) & 1];
+        a.out = I.y[k & 1];
+        a.u = I.u;
+    }
+    __syncthreads();
     double acc = 0.0;
-    const int T = I.tiles_x * I.tiles_y;
-    for (int t = w.j; t < T; t += I.nb) {
+    const int T = I.ptiles_x * I.ptiles_y;
+    for_tile_band(T, I.nb, w.j, [&](int t) {
         if (I.kind == kOpDiffAdv) {
             if (I.vec == 2) power_tile<kOpDiffAdv, 1, 2>(a, s, acc, t);
             else power_tile<kOpDiffAdv, 1, 1>(a, s, acc, t);
@@ -119,7 +125,7 @@ __global__ __launch_bounds__(kBlockThreads) void batch_power_sweep_kernel(const 
             if (I.vec == 2) power_tile<kOpBurgersJ, 1, 2>(a, s, acc, t);
             else power_tile<kOpBurgersJ, 1, 1>(a, s, acc, t);
         }
-    }
+    });
     double v[1] = {acc};
     block_sum<1>(v);
     if (flat_tid() == 0) P[static_cast<long>(k & 1) * I.nb + w.j] = v[0];
@@ -139,6 +145,7 @@ __global__ __launch_bounds__(kBlockThreads) void batch_power_final_kernel(BatchI
         I.rho = rho;
         I.c = lam / 2.0;
         I.gamma = -lam / 4.0;
+        stencil_coeffs(I.kind == kOpDiffAdv ? 0 : 1, I.dx, I.dy, I.D, I.vx, I.vy, I.nu, I.c, I.gamma, I.st);
     }
 }
 
@@ -181,23 +188,18 @@ __global__ __launch_bounds__(kCoefThreads) void batch_coeffs_kernel(const BatchI
 }
 
 __device__ __forceinline__ void sweep_coeffs(const BatchInst& I, SweepArgs& a) {
-    const double g = I.gamma, c = I.c;
     if (I.kind == kOpDiffAdv) {
-        const double ex = I.D / (I.dx * I.dx), ey = I.D / (I.dy * I.dy);
-        const double cE = ex + fmax(I.vx, 0.0) / I.dx, cW = ex + fmax(-I.vx, 0.0) / I.dx;
-        const double cN = ey + fmax(I.vy, 0.0) / I.dy, cS = ey + fmax(-I.vy, 0.0) / I.dy;
-        const double cC = -(cE + cW + cN + cS);
-        a.aE = cE / g;
-        a.aW = cW / g;
-        a.aN = cN / g;
-        a.aS = cS / g;
-        a.aC = (cC - c) / g;
+        a.aE = I.st[0];
+        a.aW = I.st[1];
+        a.aN = I.st[2];
+        a.aS = I.st[3];
+        a.aC = I.st[4];
     } else {
-        a.kx = I.nu / (g * I.dx * I.dx);
-        a.ky = I.nu / (g * I.dy * I.dy);
-        a.gx = 1.0 / (2.0 * g * I.dx);
-        a.gy = 1.0 / (2.0 * g * I.dy);
-        a.kC = -2.0 * a.kx - 2.0 * a.ky - c / g;
+        a.kx = I.st[0];
+        a.ky = I.st[1];
+        a.gx = I.st[2];
+        a.gy = I.st[3];
+        a.kC = I.st[4];
     }
 }
 
@@ -209,30 +211,36 @@ __global__ __launch_bounds__(kBlockThreads) void batch_sweep_kernel(const BatchI
     const Who w = who(insts, block_inst);
     const BatchInst& I = insts[w.i];
     LoopCtl* __restrict__ ctl = ctls + w.i;
-    if (ctl->slot[2].done) return;
-    SweepArgs a{};
-    a.nx = I.nx;
-    a.ny = I.ny;
-    a.tiles_x = I.tiles_x;
-    a.tiles_y = I.tiles_y;
-    a.nb = I.nb;
-    a.ld = ld;
-    sweep_coeffs(I, a);
-    a.inv_sqrtN = 1.0 / sqrt(static_cast<double>(I.nx) * I.ny);
-    a.v = I.v;
-    a.ybuf[0] = I.y[0];
-    a.ybuf[1] = I.y[1];
-    a.u = I.u;
-    a.u32 = nullptr;
-    a.p[0] = I.out;
-    a.base[0] = nullptr;
-    a.coef = coef + static_cast<long>(w.i) * ld;
-    a.xi = xi;
-    a.partials = partials + I.part_off;
-    a.ctl = ctl;
+    if (loop_ended(ctl)) return;
+    // the instance's arguments live in LDS: a per-lane copy would be indexed
+    // dynamically (the basis parity) and spill to scratch
+    __shared__ SweepArgs a;
+    const int tid = flat_tid();
+    if (tid == 0) {
+        a = SweepArgs{};
+        a.nx = I.nx;
+        a.ny = I.ny;
+        a.tiles_x = I.tiles_x;
+        a.tiles_y = I.tiles_y;
+        a.nb = I.nb;
+        a.ld = ld;
+        sweep_coeffs(I, a);
+        a.inv_sqrtN = 1.0 / sqrt(static_cast<double>(I.nx) * I.ny);
+        a.v = I.v;
+        a.ybuf[0] = I.y[0];
+        a.ybuf[1] = I.y[1];
+        a.u = I.u;
+        a.u32 = nullptr;
+        a.p[0] = I.out;
+        a.base[0] = nullptr;
+        a.coef = coef + static_cast<long>(w.i) * ld;
+        a.xi = xi;
+        a.partials = partials + I.part_off;
+        a.ctl = ctl;
+    }
+    __syncthreads();
 
     __shared__ SweepState s_cur;
-    const int tid = flat_tid();
     if (m == 0) {
         if (tid == 0) s_cur = ctl->slot[0];
     } else {
@@ -256,7 +264,7 @@ __global__ __launch_bounds__(kBlockThreads) void batch_sweep_kernel(const BatchI
     int act[1] = {s_cur.active[0]};
     double sy = 0.0, sp[1] = {0.0};
     const int T = I.tiles_x * I.tiles_y;
-    for (int t = w.j; t < T; t += I.nb) {
+    for_tile_band(T, I.nb, w.j, [&](int t) {
         if (I.kind == kOpDiffAdv) {
             if (I.vec == 2) sweep_tile<kOpDiffAdv, 1, 1, 2, double, double, double>(a, m, act, sy, sp, t);
             else sweep_tile<kOpDiffAdv, 1, 1, 1, double, double, double>(a, m, act, sy, sp, t);
@@ -264,7 +272,8 @@ __global__ __launch_bounds__(kBlockThreads) void batch_sweep_kernel(const BatchI
             if (I.vec == 2) sweep_tile<kOpBurgersJ, 1, 1, 2, double, double, double>(a, m, act, sy, sp, t);
             else sweep_tile<kOpBurgersJ, 1, 1, 1, double, double, double>(a, m, act, sy, sp, t);
         }
-    }
+    });
+
     double v[2] = {sy, sp[0]};
     block_sum<2>(v);
     if (tid == 0) {

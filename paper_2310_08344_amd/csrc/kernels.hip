@@ -34,7 +34,7 @@ using namespace dev;
 template <int OP, int K, int RY, int V, bool FP32>
 __global__ __launch_bounds__(kBlockThreads) void leja_sweep(SweepArgs a, const int m) {
     LoopCtl* __restrict__ ctl = a.ctl;
-    if (ctl->slot[2].done) return;
+    if (loop_ended(ctl)) return;
     constexpr int NV = 1 + K;
     __shared__ SweepState s_cur;
     const int tid = flat_tid();

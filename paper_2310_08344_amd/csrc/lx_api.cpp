@@ -24,6 +24,7 @@
 #include "lx_ctx.h"
 #include "lx_device.h"
 #include "planner.h"
+#include "stencil_coeffs.h"
 
 using lx::LoopCtl;
 using lx::SweepState;
@@ -156,22 +157,20 @@ Tile pick_tile(const lx_ctx* ctx, const lx_operator& op, int K, bool vec2_ok) {
 }
 
 void set_stencil(SweepArgs& a, const lx_operator& op, double c, double g) {
+    double k[5];
+    lx::stencil_coeffs(op.kind == LX_OP_DIFFADV2D ? 0 : 1, op.dx, op.dy, op.D, op.vx, op.vy, op.nu, c, g, k);
     if (op.kind == LX_OP_DIFFADV2D) {
-        const double ex = op.D / (op.dx * op.dx), ey = op.D / (op.dy * op.dy);
-        const double cE = ex + std::max(op.vx, 0.0) / op.dx, cW = ex + std::max(-op.vx, 0.0) / op.dx;
-        const double cN = ey + std::max(op.vy, 0.0) / op.dy, cS = ey + std::max(-op.vy, 0.0) / op.dy;
-        const double cC = -(cE + cW + cN + cS);
-        a.aE = cE / g;
-        a.aW = cW / g;
-        a.aN = cN / g;
-        a.aS = cS / g;
-        a.aC = (cC - c) / g;
+        a.aE = k[0];
+        a.aW = k[1];
+        a.aN = k[2];
+        a.aS = k[3];
+        a.aC = k[4];
     } else {
-        a.kx = op.nu / (g * op.dx * op.dx);
-        a.ky = op.nu / (g * op.dy * op.dy);
-        a.gx = 1.0 / (2.0 * g * op.dx);
-        a.gy = 1.0 / (2.0 * g * op.dy);
-        a.kC = -2.0 * a.kx - 2.0 * a.ky - c / g;
+        a.kx = k[0];
+        a.ky = k[1];
+        a.gx = k[2];
+        a.gy = k[3];
+        a.kC = k[4];
     }
 }
 
@@ -630,18 +629,20 @@ lx_status lx_spectrum(lx_ctx* ctx, const lx_operator* op, const double* d_u, con
     a.tiles_x = (nx + t.cols() - 1) / t.cols();
     a.tiles_y = (ny + t.rows() - 1) / t.rows();
     a.nb = grid_size(t, a.tiles_x * a.tiles_y);
+    double pk[5];
+    lx::stencil_coeffs(op->kind == LX_OP_DIFFADV2D ? 0 : 1, op->dx, op->dy, op->D, op->vx, op->vy, op->nu, 0.0, 1.0,
+                       pk);
     if (op->kind == LX_OP_DIFFADV2D) {
-        const double ex = op->D / (op->dx * op->dx), ey = op->D / (op->dy * op->dy);
-        a.cE = ex + std::max(op->vx, 0.0) / op->dx;
-        a.cW = ex + std::max(-op->vx, 0.0) / op->dx;
-        a.cN = ey + std::max(op->vy, 0.0) / op->dy;
-        a.cS = ey + std::max(-op->vy, 0.0) / op->dy;
-        a.cC = -(a.cE + a.cW + a.cN + a.cS);
+        a.cE = pk[0];
+        a.cW = pk[1];
+        a.cN = pk[2];
+        a.cS = pk[3];
+        a.cC = pk[4];
     } else {
-        a.kx = op->nu / (op->dx * op->dx);
-        a.ky = op->nu / (op->dy * op->dy);
-        a.gx = 1.0 / (2.0 * op->dx);
-        a.gy = 1.0 / (2.0 * op->dy);
+        a.kx = pk[0];
+        a.ky = pk[1];
+        a.gx = pk[2];
+        a.gy = pk[3];
     }
     a.u = d_u;
     s = ensure_partials(ctx, 2 * static_cast<size_t>(a.nb));

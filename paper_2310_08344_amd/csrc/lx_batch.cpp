@@ -17,13 +17,14 @@
 #include "lx_ctx.h"
 #include "lx_device.h"
 #include "planner.h"
+#include "stencil_coeffs.h"
 
 using lx::BatchInst;
 using lx::LoopCtl;
 
 namespace {
 
-constexpr int kTilesPerWorkgroup = 4;
+constexpr long kPointsPerWorkgroup = 16384;   // an instance's share of a launch, per workgroup
 constexpr int kMaxWorkgroupsPerInstance = 1024;
 constexpr int kFirstChunk = 16;
 constexpr int kChunk = 8;
@@ -106,6 +107,18 @@ extern "C" lx_status lx_phi_leja_batched(lx_ctx* ctx, int n, const lx_instance* 
         return lx_internal_fail(ctx, LX_EINVAL, "max_iters %d outside 1..%d", opt.max_iters, LX_MAX_ITERS);
 
     // ---- layout ----
+    // two iterations per launch when every instance allows 16-byte pairs
+    bool pair = ctx->depth_forced != 1;
+    bool any_burgers = false;
+    for (int i = 0; i < n; ++i) {
+        const lx_instance& q = inst[i];
+        any_burgers = any_burgers || q.op.kind == LX_OP_BURGERS2D;
+        pair = pair && q.op.nx % 2 == 0 && aligned16(q.d_v) && aligned16(q.d_out) &&
+               (q.d_u == nullptr || aligned16(q.d_u)) && (q.d_x0 == nullptr || aligned16(q.d_x0));
+    }
+    // tile rows: 16 (40 KB of LDS, 4 workgroups per CU) unless the Burgers
+    // state needs room too, then 8 (36 KB)
+    const int th = (ctx->pair_th == 8 || ctx->pair_th == 16) ? ctx->pair_th : (any_burgers ? 8 : 16);
     std::vector<BatchInst> hi(static_cast<size_t>(n));
     std::vector<int> budget(static_cast<size_t>(n));
     int total_blocks = 0, max_budget = 1;
@@ -135,14 +148,25 @@ extern "C" lx_status lx_phi_leja_batched(lx_ctx* ctx, int n, const lx_instance* 
                         (q.d_x0 == nullptr || aligned16(q.d_x0));
         b.vec = (al && b.nx % 2 == 0) ? 2 : 1;
         b.l = q.l;
-        b.tiles_x = (b.nx + lx::kBatchTx * b.vec - 1) / (lx::kBatchTx * b.vec);
-        b.tiles_y = (b.ny + lx::kBatchTy - 1) / lx::kBatchTy;
+        long tile_points;
+        if (pair) {
+            b.tiles_x = (b.nx + 127) / 128;
+            b.tiles_y = (b.ny + th - 1) / th;
+            tile_points = 128L * th;
+        } else {
+            b.tiles_x = (b.nx + lx::kBatchTx * b.vec - 1) / (lx::kBatchTx * b.vec);
+            b.tiles_y = (b.ny + lx::kBatchTy - 1) / lx::kBatchTy;
+            tile_points = static_cast<long>(lx::kBatchTx) * b.vec * lx::kBatchTy;
+        }
+        b.ptiles_x = (b.nx + lx::kBatchTx * b.vec - 1) / (lx::kBatchTx * b.vec);
+        b.ptiles_y = (b.ny + lx::kBatchTy - 1) / lx::kBatchTy;
         const int T = b.tiles_x * b.tiles_y;
-        b.nb = std::min(std::max((T + kTilesPerWorkgroup - 1) / kTilesPerWorkgroup, 1), kMaxWorkgroupsPerInstance);
+        const int tpw = static_cast<int>(std::max(1L, kPointsPerWorkgroup / tile_points));
+        b.nb = std::min(std::max((T + tpw - 1) / tpw, 1), kMaxWorkgroupsPerInstance);
         b.wg_begin = total_blocks;
         total_blocks += b.nb;
         b.part_off = part_total;
-        part_total += 4L * b.nb;
+        part_total += (pair ? 8L : 4L) * b.nb;   // [2][nb][NV] partial sums
         b.has_x0 = q.d_x0 != nullptr;
         b.dx = q.op.dx;
         b.dy = q.op.dy;
@@ -153,6 +177,9 @@ extern "C" lx_status lx_phi_leja_batched(lx_ctx* ctx, int n, const lx_instance* 
         b.h = q.h;
         b.c = q.c;
         b.gamma = q.gamma;
+        const int sk = b.kind == lx::kOpDiffAdv ? 0 : 1;
+        lx::stencil_coeffs(sk, b.dx, b.dy, b.D, b.vx, b.vy, b.nu, 0.0, 1.0, b.pw);
+        if (power_iters == 0) lx::stencil_coeffs(sk, b.dx, b.dy, b.D, b.vx, b.vy, b.nu, b.c, b.gamma, b.st);
         b.u = q.op.kind == LX_OP_BURGERS2D ? q.d_u : nullptr;
         b.v = q.d_v;
         b.out = q.d_out;
@@ -162,7 +189,7 @@ extern "C" lx_status lx_phi_leja_batched(lx_ctx* ctx, int n, const lx_instance* 
         max_budget = std::max(max_budget, budget[static_cast<size_t>(i)]);
     }
     if (total_blocks > (1 << 30)) return lx_internal_fail(ctx, LX_EINVAL, "batch too large");
-    const int ld = max_budget + 1;
+    const int ld = max_budget + (pair ? 2 : 1);   // Newton coefficients per instance
 
     // ---- workspaces ----
     lx_batch_ws& W = ctx->batch;
@@ -231,14 +258,22 @@ extern "C" lx_status lx_phi_leja_batched(lx_ctx* ctx, int n, const lx_instance* 
     LXB_HIP(ctx, lx::launch_batch_coeffs(d_inst, n, ctx->xi, W.d_coef, ld, st));
     if (timing) LXB_HIP(ctx, hipEventRecord(ctx->tev[1], st));
 
-    // ---- batched sweeps ----
+    // ---- batched sweeps (one or two iterations per launch) ----
+    const int last = pair ? (max_budget + 1) / 2 + 1 : max_budget;   // last launch index
+    const int per = pair ? 2 : 1;
     int launched = 0, chunk_id = 0, last_slot = 0;
-    int chunk = kFirstChunk;
-    while (launched <= max_budget) {
-        const int cnt = std::min(chunk, max_budget + 1 - launched);
-        for (int i = 0; i < cnt; ++i)
-            LXB_HIP(ctx, lx::launch_batch_sweep(d_inst, d_ctl, W.d_block_inst, total_blocks, W.d_partials, W.d_coef,
-                                                ld, ctx->xi, W.d_done, launched + i, st));
+    int chunk = kFirstChunk / per;
+    while (launched <= last) {
+        const int cnt = std::min(chunk, last + 1 - launched);
+        for (int i = 0; i < cnt; ++i) {
+            if (pair) {
+                LXB_HIP(ctx, lx::launch_batch_pair(d_inst, d_ctl, W.d_block_inst, total_blocks, any_burgers, th,
+                                                   W.d_partials, W.d_coef, ld, ctx->xi, W.d_done, launched + i, st));
+            } else {
+                LXB_HIP(ctx, lx::launch_batch_sweep(d_inst, d_ctl, W.d_block_inst, total_blocks, W.d_partials,
+                                                    W.d_coef, ld, ctx->xi, W.d_done, launched + i, st));
+            }
+        }
         launched += cnt;
         const int slot = chunk_id & 1;
         LXB_HIP(ctx, hipMemcpyAsync(&W.h_done[slot], W.d_done, sizeof(unsigned), hipMemcpyDeviceToHost, st));
@@ -250,7 +285,7 @@ extern "C" lx_status lx_phi_leja_batched(lx_ctx* ctx, int n, const lx_instance* 
             if (W.h_done[prev] >= static_cast<unsigned>(n)) break;
         }
         ++chunk_id;
-        chunk = kChunk;
+        chunk = kChunk / per;
     }
     if (timing) LXB_HIP(ctx, hipEventRecord(ctx->tev[2], st));
     LXB_HIP(ctx, hipEventSynchronize(ctx->poll_ev[last_slot]));
@@ -268,6 +303,7 @@ extern "C" lx_status lx_phi_leja_batched(lx_ctx* ctx, int n, const lx_instance* 
         lx_instance_result& r = res[i];
         const BatchInst& b = h_inst[i];
         r.status = f.done ? f.status : LX_EDEVICE;
+        r.fallback = 0;
         r.iters = f.iters[0];
         r.err = f.err[0];
         r.pnorm = f.pnorm[0];
@@ -277,12 +313,24 @@ extern "C" lx_status lx_phi_leja_batched(lx_ctx* ctx, int n, const lx_instance* 
         if (r.status == LX_ENONFINITE || r.status == LX_EDEVICE) worst = static_cast<lx_status>(r.status);
         else if (r.status == LX_ENOTCONV && worst == LX_OK) worst = LX_ENOTCONV;
         const double N = static_cast<double>(b.nx) * b.ny;
-        // sweep 0 reads v, writes y_1 and p; later sweeps read y and p, write both
-        bytes += N * (24.0 + 32.0 * std::max(f.iter - 1, 0));
-        bytes += N * 16.0 * power_iters;
-        max_iter = std::max(max_iter, f.iter);
+        const double ub = b.kind == lx::kOpBurgersJ ? 8.0 : 0.0;
+        if (pair) {
+            // launches 0..F-1 ran both sweeps (launch 0 writes p without
+            // reading it), an even final test added a flush of the deferred term
+            const int F = (f.iter + 1) / 2;
+            bytes += N * (24.0 + ub);
+            for (int L = 1; L < F; ++L) bytes += N * (16.0 + ub + (f.iters[0] >= 2 * L ? 16.0 : 0.0));
+            if (f.iter % 2 == 0) bytes += N * 24.0;
+            max_iter = std::max(max_iter, 2 * F);
+        } else {
+            // sweep 0 reads v, writes y_1 and p; later sweeps read y and p, write both
+            bytes += N * ((24.0 + ub) + (32.0 + ub) * std::max(f.iter - 1, 0));
+            max_iter = std::max(max_iter, f.iter);
+        }
+        bytes += N * (16.0 + ub) * power_iters;
     }
     S.n_apply = max_iter;
+    S.depth = per;
     S.bytes = bytes;
     if (timing) {
         S.plan_ms = lx_internal_elapsed(ctx->tev[0], ctx->tev[1]);

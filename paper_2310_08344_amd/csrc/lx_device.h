@@ -98,12 +98,15 @@ struct BatchInst {
     int nx, ny;
     int vec;                 // columns per lane (2 when nx is even and rows are 16-byte aligned)
     int l;                   // phi order
-    int tiles_x, tiles_y;
+    int tiles_x, tiles_y;    // tiles of the Leja kernel in use (one- or two-iteration layout)
+    int ptiles_x, ptiles_y;  // tiles of the power-iteration sweeps (kBatchTx * vec x kBatchTy)
     int wg_begin, nb;        // workgroups [wg_begin, wg_begin + nb) of each launch
     int has_x0;              // x0 given; else a splitmix64 vector in y[1]
     long part_off;           // offset of its partial sums: [2][nb][2]
     double dx, dy, D, vx, vy, nu;
     double h, c, gamma, rho;
+    double pw[5];            // stencil of A (power iteration), from the host
+    double st[5];            // stencil of (A - c)/gamma (Leja sweeps), host or batched power iteration
     const double* u;
     const double* v;
     double* out;
@@ -145,6 +148,12 @@ hipError_t launch_batch_power_final(BatchInst* insts, int n_inst, const double* 
                                     double safety, hipStream_t s);
 hipError_t launch_batch_coeffs(const BatchInst* insts, int n_inst, const double* xi, double* coef, int ld,
                                hipStream_t s);
+// Batched two-iteration launch L (pair.hip; one output per instance, every
+// instance with nx even and 16-byte aligned vectors); th in {8, 16};
+// burgers: the batch holds a Burgers instance (sizes the LDS for its u tile).
+hipError_t launch_batch_pair(const BatchInst* insts, LoopCtl* ctls, const int* block_inst, int nblocks, bool burgers,
+                             int th, double* partials, const double* coef, int ld, const double* xi, unsigned* done,
+                             int L, hipStream_t s);
 hipError_t launch_batch_sweep(const BatchInst* insts, LoopCtl* ctls, const int* block_inst, int nblocks,
                               double* partials, const double* coef, int ld, const double* xi, unsigned* done,
                               int m, hipStream_t s);

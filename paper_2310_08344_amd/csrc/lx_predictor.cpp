@@ -22,6 +22,10 @@ struct lx_predictor {
     int* d_idx = nullptr;
     size_t idx_cap = 0;
     double* h_loss = nullptr;    // pinned
+    float* d_x = nullptr;        // lx_phi_leja_learned: features [n][8]
+    float* d_y = nullptr;        // and predictions [n][2] (device) ...
+    float* h_y = nullptr;        // ... copied to pinned host memory
+    size_t xy_cap = 0;
     lx::MlpScaling sc{};
     int t = 0;                   // Adam steps taken
 };
@@ -121,6 +125,9 @@ void lx_predictor_destroy(lx_predictor* p) {
     (void)hipFree(p->scratch);
     (void)hipFree(p->d_idx);
     (void)hipHostFree(p->h_loss);
+    (void)hipFree(p->d_x);
+    (void)hipFree(p->d_y);
+    (void)hipHostFree(p->h_y);
     delete p;
 }
 
@@ -303,6 +310,116 @@ lx_status lx_instance_features(lx_ctx* ctx, int n, const lx_instance* inst, floa
     std::memcpy(W.h_feat, f.data(), bytes);
     LXP_HIP(ctx, hipMemcpyAsync(W.d_feat, W.h_feat, bytes, hipMemcpyHostToDevice, ctx->stream));
     LXP_HIP(ctx, lx::launch_features(static_cast<const lx::FeatureInst*>(W.d_feat), n, d_x, ctx->stream));
+    return LX_OK;
+}
+
+lx_status lx_phi_leja_learned(lx_ctx* ctx, lx_predictor* p, int n, const lx_instance* inst, double margin_log_rho,
+                              double margin_log_sweeps, int power_iters, double safety, const lx_leja_opts* o,
+                              lx_instance_result* res, int* fallbacks) {
+    if (ctx == nullptr) return LX_EINVAL;
+    ctx->stats = lx_stats{};
+    if (p == nullptr || p->ctx != ctx) return lx_internal_fail(ctx, LX_EINVAL, "the predictor belongs to another context");
+    if (n < 1 || n > 65536 || inst == nullptr || res == nullptr)
+        return lx_internal_fail(ctx, LX_EINVAL, "batch of %d instances (1..65536) with inputs and results", n);
+    if (!std::isfinite(margin_log_rho) || !std::isfinite(margin_log_sweeps) || margin_log_rho < 0.0 ||
+        margin_log_sweeps < 0.0)
+        return lx_internal_fail(ctx, LX_EINVAL, "margins must be finite and >= 0");
+    if (power_iters < 1 || power_iters > LX_MAX_ITERS || !(safety > 0.0) || !std::isfinite(safety))
+        return lx_internal_fail(ctx, LX_EINVAL, "the fallback needs 1..%d power iterations and a safety > 0",
+                                LX_MAX_ITERS);
+    lx_leja_opts opt{1e-8, 0.0, 500, 1e4};
+    if (o != nullptr) opt = *o;
+    if (opt.max_iters < 1 || opt.max_iters > LX_MAX_ITERS)
+        return lx_internal_fail(ctx, LX_EINVAL, "max_iters %d outside 1..%d", opt.max_iters, LX_MAX_ITERS);
+
+    // ---- predictions ----
+    const size_t nn = static_cast<size_t>(n);
+    if (nn > p->xy_cap) {
+        LXP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        (void)hipFree(p->d_x);
+        (void)hipFree(p->d_y);
+        (void)hipHostFree(p->h_y);
+        p->d_x = p->d_y = p->h_y = nullptr;
+        p->xy_cap = 0;
+        if (hipMalloc(&p->d_x, sizeof(float) * 8 * nn) != hipSuccess ||
+            hipMalloc(&p->d_y, sizeof(float) * 2 * nn) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void**>(&p->h_y), sizeof(float) * 2 * nn, hipHostMallocDefault) != hipSuccess)
+            return lx_internal_fail(ctx, LX_ENOMEM, "prediction buffers for %d instances", n);
+        p->xy_cap = nn;
+    }
+    lx_status s = lx_instance_features(ctx, n, inst, p->d_x);
+    if (s != LX_OK) return s;
+    s = lx_predictor_infer(p, p->d_x, n, p->d_y);
+    if (s != LX_OK) return s;
+    LXP_HIP(ctx, hipMemcpyAsync(p->h_y, p->d_y, sizeof(float) * 2 * nn, hipMemcpyDeviceToHost, ctx->stream));
+    LXP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+
+    // ---- the learned batch: predicted shift, scale and budget ----
+    std::vector<lx_instance> q;
+    std::vector<int> idx, fb;
+    q.reserve(nn);
+    idx.reserve(nn);
+    for (int i = 0; i < n; ++i) {
+        const double a = p->h_y[2 * i], b = p->h_y[2 * i + 1];
+        const double lam = -std::exp(a + margin_log_rho);
+        const double sweeps = std::ceil(std::exp(b + margin_log_sweeps)) + 1.0;
+        res[i] = lx_instance_result{};
+        if (!std::isfinite(lam) || !(lam < 0.0) || !std::isfinite(sweeps)) {
+            fb.push_back(i);
+            continue;
+        }
+        lx_instance r = inst[i];
+        r.c = lam / 2.0;
+        r.gamma = -lam / 4.0;
+        r.budget = static_cast<int>(std::min(static_cast<double>(opt.max_iters), std::max(1.0, sweeps)));
+        q.push_back(r);
+        idx.push_back(i);
+    }
+    lx_stats acc{};
+    if (!q.empty()) {
+        std::vector<lx_instance_result> r(q.size());
+        s = lx_phi_leja_batched(ctx, static_cast<int>(q.size()), q.data(), 0, 1.0, &opt, r.data());
+        if (s != LX_OK && s != LX_ENOTCONV && s != LX_ENONFINITE) return s;
+        acc = ctx->stats;
+        for (size_t k = 0; k < q.size(); ++k) {
+            res[idx[k]] = r[k];
+            if (r[k].status != LX_OK) fb.push_back(idx[k]);
+        }
+    }
+    // ---- the plain method for the rest ----
+    lx_status worst = LX_OK;
+    if (!fb.empty()) {
+        std::sort(fb.begin(), fb.end());
+        std::vector<lx_instance> qf;
+        qf.reserve(fb.size());
+        for (int i : fb) {
+            lx_instance r = inst[i];
+            r.budget = 0;
+            qf.push_back(r);
+        }
+        std::vector<lx_instance_result> r(fb.size());
+        s = lx_phi_leja_batched(ctx, static_cast<int>(fb.size()), qf.data(), power_iters, safety, &opt, r.data());
+        if (s != LX_OK && s != LX_ENOTCONV && s != LX_ENONFINITE) return s;
+        for (size_t k = 0; k < fb.size(); ++k) {
+            res[fb[k]] = r[k];
+            res[fb[k]].fallback = 1;
+        }
+        const lx_stats& f = ctx->stats;
+        acc.n_apply = std::max(acc.n_apply, f.n_apply);
+        acc.bytes += f.bytes;
+        acc.plan_ms += f.plan_ms;
+        acc.loop_ms += f.loop_ms;
+        acc.sweep_ms += f.sweep_ms;
+        acc.depth = f.depth;
+    }
+    for (int i = 0; i < n; ++i) {
+        if (res[i].status == LX_ENONFINITE || res[i].status == LX_EDEVICE) worst = static_cast<lx_status>(res[i].status);
+        else if (res[i].status == LX_ENOTCONV && worst == LX_OK) worst = LX_ENOTCONV;
+    }
+    acc.status = worst;
+    ctx->stats = acc;
+    if (fallbacks != nullptr) *fallbacks = static_cast<int>(fb.size());
+    if (worst != LX_OK) return lx_internal_fail(ctx, worst, "at least one instance failed after its fallback");
     return LX_OK;
 }
 

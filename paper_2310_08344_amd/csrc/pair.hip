@@ -62,23 +62,66 @@ struct PairLds<kOpDiffAdv, TH> {
     double y1[TH + 2][kPairPitch];
 };
 
+// The stencil of (A - c)/gamma: aW, aE, aS, aN, aC (diffusion-advection) or
+// kx, ky, gx, gy, kC (Burgers).
+struct Sten {
+    double c0, c1, c2, c3, c4;
+};
+
+// What the tile code reads of the launch arguments, held in registers for
+// the whole launch (the batched kernel keeps its SweepArgs in LDS, where a
+// read after any LDS store would be issued again).
+template <int K>
+struct TileArgs {
+    int nx, ny, tiles_x, ld;
+    Sten st;
+    const double* u;
+    const double* coef;
+    const double* xi;
+    double* p[K];
+    const double* base[K];
+};
+
+template <int OP, int K>
+__device__ __forceinline__ TileArgs<K> tile_args(const SweepArgs& a) {
+    TileArgs<K> t;
+    t.nx = a.nx;
+    t.ny = a.ny;
+    t.tiles_x = a.tiles_x;
+    t.ld = a.ld;
+    if constexpr (OP == kOpDiffAdv) {
+        t.st = Sten{a.aW, a.aE, a.aS, a.aN, a.aC};
+    } else {
+        t.st = Sten{a.kx, a.ky, a.gx, a.gy, a.kC};
+    }
+    t.u = a.u;
+    t.coef = a.coef;
+    t.xi = a.xi;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        t.p[k] = a.p[k];
+        t.base[k] = a.base[k];
+    }
+    return t;
+}
+
 // The shifted operator at one point from its four neighbours (W, E, S, N),
 // its centre C and, for Burgers, u at the same cells: the stencils of the
 // single-sweep kernel, so both compute the same bits.
 template <int OP>
-__device__ __forceinline__ double shifted_at(const SweepArgs& a, const double shift, double W, double E, double S,
+__device__ __forceinline__ double shifted_at(const Sten& k, const double shift, double W, double E, double S,
                                              double N, double C, double uW, double uE, double uS, double uN) {
     if constexpr (OP == kOpDiffAdv) {
-        return stencil_da(a.aW, a.aE, a.aS, a.aN, a.aC - shift, W, E, S, N, C);
+        return stencil_da(k.c0, k.c1, k.c2, k.c3, k.c4 - shift, W, E, S, N, C);
     } else {
-        return stencil_bu(a.kx, a.ky, a.gx, a.gy, a.kC - shift, W, E, S, N, C, uW, uE, uS, uN);
+        return stencil_bu(k.c0, k.c1, k.c2, k.c3, k.c4 - shift, W, E, S, N, C, uW, uE, uS, uN);
     }
 }
 
 // the operator on LDS row `ce` (rows `up`, `dn` above and below) at the
 // column pair j, j+1 (j even)
 template <int OP>
-__device__ __forceinline__ void shifted_pair(const SweepArgs& a, const double shift, const double* up,
+__device__ __forceinline__ void shifted_pair(const Sten& a, const double shift, const double* up,
                                              const double* ce, const double* dn, const double* uup,
                                              const double* uce, const double* udn, const int j, double (&o)[2]) {
     const double2 c2 = *reinterpret_cast<const double2*>(ce + j);
@@ -99,7 +142,7 @@ __device__ __forceinline__ void shifted_pair(const SweepArgs& a, const double sh
 }
 
 template <int OP>
-__device__ __forceinline__ double shifted_one(const SweepArgs& a, const double shift, const double* up,
+__device__ __forceinline__ double shifted_one(const Sten& a, const double shift, const double* up,
                                               const double* ce, const double* dn, const double* uup,
                                               const double* uce, const double* udn, const int j) {
     if constexpr (OP == kOpDiffAdv) {
@@ -111,7 +154,7 @@ __device__ __forceinline__ double shifted_one(const SweepArgs& a, const double s
 }
 
 template <int OP, int K, int TH>
-__device__ __forceinline__ void pair_tile(const SweepArgs& a, PairLds<OP, TH>& S, const double* __restrict__ yin,
+__device__ __forceinline__ void pair_tile(const TileArgs<K>& a, PairLds<OP, TH>& S, const double* __restrict__ yin,
                                           double* __restrict__ yout, const int m, const bool first,
                                           const int (&add0)[K], const int (&add1)[K], double& sy1, double& sy2,
                                           double (&sp1)[K], double (&sp2)[K], const int tile) {
@@ -186,9 +229,9 @@ __device__ __forceinline__ void pair_tile(const SweepArgs& a, PairLds<OP, TH>& S
         if (r >= TH + 2) break;
         double o[2];
         if constexpr (OP == kOpBurgersJ) {
-            shifted_pair<OP>(a, xm, S.ym[r], S.ym[r + 1], S.ym[r + 2], S.u[r], S.u[r + 1], S.u[r + 2], j, o);
+            shifted_pair<OP>(a.st, xm, S.ym[r], S.ym[r + 1], S.ym[r + 2], S.u[r], S.u[r + 1], S.u[r + 2], j, o);
         } else {
-            shifted_pair<OP>(a, xm, S.ym[r], S.ym[r + 1], S.ym[r + 2], nullptr, nullptr, nullptr, j, o);
+            shifted_pair<OP>(a.st, xm, S.ym[r], S.ym[r + 1], S.ym[r + 2], nullptr, nullptr, nullptr, j, o);
         }
         double2 t;
         t.x = o[0];
@@ -199,9 +242,9 @@ __device__ __forceinline__ void pair_tile(const SweepArgs& a, PairLds<OP, TH>& S
         const int r = tid >> 1;
         const int lc = (tid & 1) ? kPairTW + 2 : 1;   // columns 128 and -1
         if constexpr (OP == kOpBurgersJ) {
-            S.y1[r][lc] = shifted_one<OP>(a, xm, S.ym[r], S.ym[r + 1], S.ym[r + 2], S.u[r], S.u[r + 1], S.u[r + 2], lc);
+            S.y1[r][lc] = shifted_one<OP>(a.st, xm, S.ym[r], S.ym[r + 1], S.ym[r + 2], S.u[r], S.u[r + 1], S.u[r + 2], lc);
         } else {
-            S.y1[r][lc] = shifted_one<OP>(a, xm, S.ym[r], S.ym[r + 1], S.ym[r + 2], nullptr, nullptr, nullptr, lc);
+            S.y1[r][lc] = shifted_one<OP>(a.st, xm, S.ym[r], S.ym[r + 1], S.ym[r + 2], nullptr, nullptr, nullptr, lc);
         }
     }
     __syncthreads();
@@ -213,9 +256,9 @@ __device__ __forceinline__ void pair_tile(const SweepArgs& a, PairLds<OP, TH>& S
         const int grow = y0 + r;
         double o[2];
         if constexpr (OP == kOpBurgersJ) {
-            shifted_pair<OP>(a, xm1, S.y1[r], S.y1[r + 1], S.y1[r + 2], S.u[r + 1], S.u[r + 2], S.u[r + 3], j, o);
+            shifted_pair<OP>(a.st, xm1, S.y1[r], S.y1[r + 1], S.y1[r + 2], S.u[r + 1], S.u[r + 2], S.u[r + 3], j, o);
         } else {
-            shifted_pair<OP>(a, xm1, S.y1[r], S.y1[r + 1], S.y1[r + 2], nullptr, nullptr, nullptr, j, o);
+            shifted_pair<OP>(a.st, xm1, S.y1[r], S.y1[r + 1], S.y1[r + 2], nullptr, nullptr, nullptr, j, o);
         }
         if (gcol < nx && grow < ny) {
             const long idx = static_cast<long>(grow) * nx + gcol;
@@ -263,10 +306,16 @@ __device__ __forceinline__ void pair_tile(const SweepArgs& a, PairLds<OP, TH>& S
     __syncthreads();   // the next tile overwrites LDS
 }
 
+// One launch L of the two-iteration loop, as workgroup `wg` of the `a.nb`
+// that serve this grid: the stop decisions at terms 2L-1 and 2L from the
+// previous launch's partial sums, then the flush or the two sweeps.
+// Workgroup 0 records the state; when the loop has ended it also publishes
+// slot[2] and, if `done` is given, counts the grid as finished.  `banded`
+// selects the XCD-banded tile order (whole-device grids).
 template <int OP, int K, int TH>
-__global__ __launch_bounds__(kBlockThreads) void leja_pair(SweepArgs a, const int L) {
+__device__ __forceinline__ void pair_launch(const SweepArgs& a, const int L, const int wg, const bool banded,
+                                            PairLds<OP, TH>& S, unsigned* done) {
     LoopCtl* __restrict__ ctl = a.ctl;
-    if (ctl->slot[2].done) return;
     constexpr int NV = 2 * (1 + K);
     __shared__ int s_mode;   // 0: both terms, 1: deferred term only, 2: nothing
     __shared__ int s_add0[K], s_add1[K];
@@ -286,11 +335,14 @@ __global__ __launch_bounds__(kBlockThreads) void leja_pair(SweepArgs a, const in
         sum_partials<NV>(a.partials + static_cast<long>((L - 1) & 1) * a.nb * NV, a.nb, tot);
         if (tid == 0) {
             const SweepState prev = ctl->slot[(L - 1) & 1];
-            const bool pub = blockIdx.x == 0;
+            const bool pub = wg == 0;
             if (prev.done) {
                 // the previous launch flushed the last deferred term
                 s_mode = 2;
-                if (pub) ctl->slot[2] = prev;
+                if (pub) {
+                    ctl->slot[2] = prev;
+                    if (done != nullptr) atomicAdd(done, 1u);
+                }
             } else {
                 double t1[1 + K], t2[1 + K];
                 t1[0] = tot[0];
@@ -306,6 +358,7 @@ __global__ __launch_bounds__(kBlockThreads) void leja_pair(SweepArgs a, const in
                     if (pub) {
                         ctl->slot[L & 1] = s1;
                         ctl->slot[2] = s1;
+                        if (done != nullptr) atomicAdd(done, 1u);
                     }
                 } else {
                     const SweepState s2 = decide<K, false>(a, *ctl, s1, m, t2);
@@ -334,8 +387,7 @@ __global__ __launch_bounds__(kBlockThreads) void leja_pair(SweepArgs a, const in
     if (mode == 1) {
         // p_k += d_m y_m for the outputs that passed the stop rule at term m
         const long n2 = static_cast<long>(a.nx) * a.ny / 2;
-        for (long i = static_cast<long>(blockIdx.x) * kBlockThreads + tid; i < n2;
-             i += static_cast<long>(a.nb) * kBlockThreads) {
+        for (long i = static_cast<long>(wg) * kBlockThreads + tid; i < n2; i += static_cast<long>(a.nb) * kBlockThreads) {
             const double2 y = reinterpret_cast<const double2*>(yin)[i];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
@@ -350,7 +402,6 @@ __global__ __launch_bounds__(kBlockThreads) void leja_pair(SweepArgs a, const in
         return;
     }
 
-    __shared__ PairLds<OP, TH> S;
     double* __restrict__ yout = static_cast<double*>(a.ybuf[L & 1]);
     double sy1 = 0.0, sy2 = 0.0, sp1[K], sp2[K];
 #pragma unroll
@@ -359,9 +410,13 @@ __global__ __launch_bounds__(kBlockThreads) void leja_pair(SweepArgs a, const in
         sp2[k] = 0.0;
     }
     const int T = a.tiles_x * a.tiles_y;
-    for_each_tile(T, a.nb, [&](int t) {
-        pair_tile<OP, K, TH>(a, S, yin, yout, m, L == 0, add0, add1, sy1, sy2, sp1, sp2, t);
-    });
+    const TileArgs<K> ta = tile_args<OP, K>(a);
+    auto body = [&](int t) { pair_tile<OP, K, TH>(ta, S, yin, yout, m, L == 0, add0, add1, sy1, sy2, sp1, sp2, t); };
+    if (banded) {
+        for_each_tile(T, a.nb, body);
+    } else {
+        for_tile_band(T, a.nb, wg, body);
+    }
     double v[NV];
     v[0] = sy1;
     v[1 + K] = sy2;
@@ -372,9 +427,74 @@ __global__ __launch_bounds__(kBlockThreads) void leja_pair(SweepArgs a, const in
     }
     block_sum<NV>(v);
     if (tid == 0) {
-        double* __restrict__ P = a.partials + static_cast<long>(L & 1) * a.nb * NV + blockIdx.x * NV;
+        double* __restrict__ P = a.partials + static_cast<long>(L & 1) * a.nb * NV + static_cast<long>(wg) * NV;
 #pragma unroll
         for (int q = 0; q < NV; ++q) P[q] = v[q];
+    }
+}
+
+template <int OP, int K, int TH>
+__global__ __launch_bounds__(kBlockThreads) void leja_pair(SweepArgs a, const int L) {
+    if (loop_ended(a.ctl)) return;
+    __shared__ PairLds<OP, TH> S;
+    pair_launch<OP, K, TH>(a, L, static_cast<int>(blockIdx.x), true, S, nullptr);
+}
+
+// Batched: every workgroup serves the instance block_inst[blockIdx.x], one
+// output per instance; LDS is sized by the launch for the largest tile
+// layout in the batch.
+template <int TH>
+__global__ __launch_bounds__(kBlockThreads) void batch_pair_kernel(const BatchInst* insts, LoopCtl* ctls,
+                                                                   const int* block_inst, double* partials,
+                                                                   const double* coef, const int ld,
+                                                                   const double* xi, unsigned* done, const int L) {
+    extern __shared__ double lds_dyn[];
+    // the instance's arguments live in LDS: a per-lane copy would be indexed
+    // dynamically (the basis parity) and spill to scratch
+    __shared__ SweepArgs a;
+    const int i = block_inst[blockIdx.x];
+    const BatchInst& I = insts[i];
+    LoopCtl* __restrict__ ctl = ctls + i;
+    if (loop_ended(ctl)) return;
+    if (flat_tid() == 0) {
+        a = SweepArgs{};
+        a.nx = I.nx;
+        a.ny = I.ny;
+        a.tiles_x = I.tiles_x;
+        a.tiles_y = I.tiles_y;
+        a.nb = I.nb;
+        a.ld = ld;
+        if (I.kind == kOpDiffAdv) {
+            a.aE = I.st[0];
+            a.aW = I.st[1];
+            a.aN = I.st[2];
+            a.aS = I.st[3];
+            a.aC = I.st[4];
+        } else {
+            a.kx = I.st[0];
+            a.ky = I.st[1];
+            a.gx = I.st[2];
+            a.gy = I.st[3];
+            a.kC = I.st[4];
+        }
+        a.inv_sqrtN = 1.0 / sqrt(static_cast<double>(I.nx) * I.ny);
+        a.v = I.v;
+        a.ybuf[0] = I.y[0];
+        a.ybuf[1] = I.y[1];
+        a.u = I.u;
+        a.p[0] = I.out;
+        a.base[0] = nullptr;
+        a.coef = coef + static_cast<long>(i) * ld;
+        a.xi = xi;
+        a.partials = partials + I.part_off;
+        a.ctl = ctl;
+    }
+    __syncthreads();
+    const int wg = static_cast<int>(blockIdx.x) - I.wg_begin;
+    if (I.kind == kOpDiffAdv) {
+        pair_launch<kOpDiffAdv, 1, TH>(a, L, wg, false, *reinterpret_cast<PairLds<kOpDiffAdv, TH>*>(lds_dyn), done);
+    } else {
+        pair_launch<kOpBurgersJ, 1, TH>(a, L, wg, false, *reinterpret_cast<PairLds<kOpBurgersJ, TH>*>(lds_dyn), done);
     }
 }
 
@@ -402,6 +522,29 @@ hipError_t launch_pair_k(int K, int th, const SweepArgs& a, int L, hipStream_t s
 }
 
 }  // namespace
+
+hipError_t launch_batch_pair(const BatchInst* insts, LoopCtl* ctls, const int* block_inst, int nblocks, bool burgers,
+                             int th, double* partials, const double* coef, int ld, const double* xi, unsigned* done,
+                             int L, hipStream_t s) {
+    if (nblocks < 1) return hipErrorInvalidValue;
+    const dim3 block(64, kPairWaves), grid(nblocks);
+    switch (th) {
+        case 8: {
+            const size_t lds = burgers ? sizeof(PairLds<kOpBurgersJ, 8>) : sizeof(PairLds<kOpDiffAdv, 8>);
+            hipLaunchKernelGGL(batch_pair_kernel<8>, grid, block, lds, s, insts, ctls, block_inst, partials, coef, ld, xi,
+                               done, L);
+            break;
+        }
+        case 16: {
+            const size_t lds = burgers ? sizeof(PairLds<kOpBurgersJ, 16>) : sizeof(PairLds<kOpDiffAdv, 16>);
+            hipLaunchKernelGGL(batch_pair_kernel<16>, grid, block, lds, s, insts, ctls, block_inst, partials, coef, ld,
+                               xi, done, L);
+            break;
+        }
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_leja_pair(int op, int K, int th, const SweepArgs& a, int L, hipStream_t s) {
     if (a.nb < 1 || a.nx % 2 != 0 || a.nx < 2 || a.ny < 2) return hipErrorInvalidValue;

@@ -35,6 +35,16 @@ __device__ __forceinline__ void for_each_tile(int T, int nb, F&& f) {
 }
 
 __device__ __forceinline__ int flat_tid() { return threadIdx.x + threadIdx.y * blockDim.x; }
+
+// Workgroup j of nb takes the contiguous tiles [T j / nb, T (j+1) / nb):
+// consecutive tiles are neighbours, so the halo rows a tile reads were
+// fetched by the same workgroup (and its XCD's L2) just before.
+template <typename F>
+__device__ __forceinline__ void for_tile_band(int T, int nb, int j, F&& f) {
+    const int lo = static_cast<int>((static_cast<long>(j) * T) / nb);
+    const int hi = static_cast<int>((static_cast<long>(j + 1) * T) / nb);
+    for (int t = lo; t < hi; ++t) f(t);
+}
 __device__ __forceinline__ int block_threads() { return blockDim.x * blockDim.y; }
 
 template <typename T> struct Pair;
@@ -95,6 +105,17 @@ __device__ __forceinline__ void block_sum(double (&v)[NV]) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) v[q] = out[q];
     __syncthreads();
+}
+
+// Whether the loop behind `ctl` has ended, read by one lane for the whole
+// workgroup: workgroup 0 of the same launch may publish the flag while this
+// workgroup starts, and all its wavefronts must take the same branch since
+// they meet at barriers later.
+__device__ __forceinline__ bool loop_ended(const LoopCtl* ctl) {
+    __shared__ int s_end;
+    if (flat_tid() == 0) s_end = ctl->slot[2].done;
+    __syncthreads();
+    return s_end != 0;
 }
 
 // Adds the nb partial records of NV values written by the previous launch,

@@ -43,10 +43,15 @@ def splitmix_vector(seed, n):
     return (z >> np.uint64(11)).astype(np.float64) * 2.0**-52 - 1.0
 
 
-def _mixed_batch(seed=0):
+MIXED = [(64, 64, "da"), (96, 40, "da"), (33, 17, "da"), (128, 128, "bu"), (130, 66, "da"),
+         (8, 8, "da"), (200, 136, "bu"), (75, 97, "da"), (256, 256, "da"), (50, 50, "bu")]
+# every side even: the batch runs two iterations per launch
+EVEN = [(64, 64, "da"), (96, 40, "da"), (130, 66, "da"), (128, 128, "bu"), (8, 8, "da"), (200, 136, "bu"),
+        (256, 256, "da"), (50, 50, "bu"), (6, 10, "da"), (258, 34, "bu")]
+
+
+def _mixed_batch(seed=0, specs=MIXED):
     rng = np.random.default_rng(seed)
-    specs = [(64, 64, "da"), (96, 40, "da"), (33, 17, "da"), (128, 128, "bu"), (130, 66, "da"),
-             (8, 8, "da"), (200, 136, "bu"), (75, 97, "da"), (256, 256, "da"), (50, 50, "bu")]
     inst = []
     for i, (nx, ny, kind) in enumerate(specs):
         dx, dy = 1.0 / nx, 1.0 / ny
@@ -60,14 +65,15 @@ def _mixed_batch(seed=0):
             A = (lambda D, vx, vy, dx, dy: (lambda y: diffadv_apply(y, D, vx, vy, dx, dy)))(D, vx, vy, dx, dy)
             u = None
         else:
-            nu = 2e-3
+            # cell Peclet number 2: the diffusion-dominated regime where the
+            # real-interval Leja interpolation is stable (advection-dominated
+            # Jacobians amplify rounding along the Newton basis)
             u = W.fourier_modes(max(nx, ny), seed=10 + i)[:ny, :nx] + 0.2
+            nu = float(np.max(np.abs(u))) * max(dx, dy) / 2.0
             op = B.make_operator(kind=B.LX_OP_BURGERS2D, nx=nx, ny=ny, dx=dx, dy=dy, nu=nu)
             rho = 2.0 / W.burgers_cfl_step(nu, float(np.max(np.abs(u))), dx, dy)
             A = (lambda u, nu, dx, dy: (lambda w: burgers_J(u, w, nu, dx, dy)))(u, nu, dx, dy)
-        # advection-dominated Burgers Jacobians have strongly imaginary
-        # spectra, where interpolation on the real interval needs many more
-        # sweeps: their steps stay at most 10 x CFL
+        # Burgers steps stay at most 10 x CFL
         s = float(np.exp(rng.uniform(0.0, np.log(40.0 if kind == "da" else 10.0))))
         h = 2.0 * s / rho
         c, g = shift_scale(rho)
@@ -146,6 +152,71 @@ def test_batch_equals_single_instance_path(ctx):
                           max_iters=200, **kw)
         assert rs.iters[0] == r["iters"]
         assert rel(o, host(out)) <= 1e-12
+
+
+@pytest.mark.parametrize("th", [8, 16])
+def test_two_iteration_batch_matches_oracle(ctx, th):
+    """Even sides (ragged against the 128-column tiles), both operators in
+    one launch, against the oracle instance by instance."""
+    inst = _mixed_batch(5, EVEN)
+    say("two-iteration batch", th)
+    ctx.set_depth(0, th, 0)
+    try:
+        st, res, outs = _run(ctx, inst, rtol=1e-8, max_iters=200)
+        assert ctx.stats()["depth"] == 2
+    finally:
+        ctx.set_depth(0)
+    assert st == B.LX_OK
+    for q, r, o in zip(inst, res, outs):
+        assert r["status"] == B.LX_OK
+        oracle_parity([o], [r["iters"]],
+                      lambda f, q=q: leja_phi(q["A"], q["v"], [(q["l"], 1.0, 1.0)], q["h"], q["c"], q["gamma"],
+                                              1e-8, 0.0, 200, f), PARITY)
+
+
+def test_two_iteration_batch_budgets_and_power_iteration(ctx):
+    """Odd and even budgets end on either test of a launch; the batched
+    power iteration feeds the two-iteration loop."""
+    inst = _mixed_batch(6, EVEN)[:6]
+    budgets = [3, 0, 2, 0, 1, 4]
+    say("two-iteration budgets")
+    st, res, outs = _run(ctx, inst, budgets=budgets, rtol=1e-10, max_iters=200)
+    assert ctx.stats()["depth"] == 2 and st == B.LX_ENOTCONV
+    for q, b, r, o in zip(inst, budgets, res, outs):
+        if b == 0:
+            assert r["status"] == B.LX_OK
+            continue
+        assert r["status"] == B.LX_ENOTCONV and r["iters"] == b
+        ref = leja_phi(q["A"], q["v"], [(q["l"], 1.0, 1.0)], q["h"], q["c"], q["gamma"], 1e-10, 0.0, b)
+        assert rel(o, ref.p[0]) <= PARITY
+    inst = _mixed_batch(7, EVEN)
+    st, res, outs = _run(ctx, inst, power_iters=20, rtol=1e-8, max_iters=250)
+    assert ctx.stats()["depth"] == 2 and st == B.LX_OK
+    for i, (q, r, o) in enumerate(zip(inst, res, outs)):
+        x0 = splitmix_vector(i, q["nx"] * q["ny"]).reshape(q["ny"], q["nx"])
+        rho_o, _ = power_iteration(q["A"], x0, 20)
+        assert abs(r["rho_hat"] - rho_o) <= 1e-12 * rho_o
+        c, g = shift_scale(r["rho_hat"])
+        oracle_parity([o], [r["iters"]],
+                      lambda f, q=q, c=c, g=g: leja_phi(q["A"], q["v"], [(q["l"], 1.0, 1.0)], q["h"], c, g,
+                                                        1e-8, 0.0, 250, f), PARITY)
+
+
+def test_two_iteration_batch_equals_one_iteration_batch(ctx):
+    inst = _mixed_batch(8, EVEN)
+    st2, res2, outs2 = _run(ctx, inst, rtol=1e-9, max_iters=200)
+    ctx.set_depth(1)
+    try:
+        st1, res1, outs1 = _run(ctx, inst, rtol=1e-9, max_iters=200)
+        assert ctx.stats()["depth"] == 1
+    finally:
+        ctx.set_depth(0)
+    for r2, r1, o2, o1 in zip(res2, res1, outs2, outs1):
+        if r2["iters"] == r1["iters"]:
+            assert np.array_equal(o2, o1)
+        else:
+            say("borderline stop decision", r2["iters"], r1["iters"])
+            assert abs(r2["iters"] - r1["iters"]) <= 1 and rel(o2, o1) <= 1e-9
 
 
 def test_batch_rejects_bad_instances(ctx):

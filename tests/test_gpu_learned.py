@@ -41,6 +41,9 @@ def test_small_trained_predictor_agrees_with_plain(ctx):
     say("learned: train 400 steps")
     p, summary = L.train_predictor(ctx, X, Y, steps=400, batch=64, lr=3e-3)
     assert np.isfinite(summary["val_rmse_log_rho"])
+    say("learned: calibrate on 64")
+    margin_s, cal = L.calibrate_budget(ctx, p, summary["margin_log_rho"], count=64, sizes=(64,))
+    assert np.isfinite(margin_s) and cal["calibration_instances"] == 64
     items = _items(24, 700000)
     args, keep = L._instance_args(items, "cuda:0")
     import torch
@@ -48,7 +51,7 @@ def test_small_trained_predictor_agrees_with_plain(ctx):
     say("learned: plain batched 24")
     res_p = L.solve_plain(ctx, [dict(a, out=o) for a, o in zip(args, plain_out)])
     say("learned: learned batched 24")
-    res_l, fb = L.solve_learned(ctx, p, args, summary["margin_log_rho"], summary["margin_log_sweeps"])
+    res_l, fb = L.solve_learned(ctx, p, args, summary["margin_log_rho"], margin_s)
     say("accepted", 24 - len(fb), "fallbacks", len(fb))
     for i, (a, o, rp, rl) in enumerate(zip(args, plain_out, res_p, res_l)):
         assert rp["status"] == B.LX_OK and rl["status"] == B.LX_OK, (i, rp, rl)
