@@ -37,7 +37,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "leja_sweep_phi123_4096_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "leja_pair_phi123_4096_traffic.json")
 
 
 def log(*a):
@@ -134,6 +134,22 @@ def bench_batched(lib, repeats: int = 3) -> dict:
             "batched_ms": round(t_batch * 1e3, 3), "plain_ms": round(t_plain * 1e3, 3),
             "speedup_batched_vs_plain": round(t_plain / t_batch, 2),
             "sweeps_min_median_max": [iters[0], iters[len(iters) // 2], iters[-1]]}
+
+
+def bench_learned(lib, count: int = 1024) -> dict:
+    """The learned + batched form against the plain batched and plain
+    single-instance paths on 1024 instances at 256^2 (half
+    diffusion-advection, half Burgers), with the committed predictor."""
+    from paper_2310_08344_amd import learned as L
+
+    ctx = lib.context(n_max=1 << 16, k_max=1)
+    p, margins, meta = L.load_predictor(ctx)
+    res = L.evaluate(ctx, p, margins, count=count)
+    ctx.close()
+    res["predictor"] = {"records": meta.get("records"), "val_rmse_log_rho": meta.get("val_rmse_log_rho"),
+                        "val_rmse_log_sweeps": meta.get("val_rmse_log_sweeps"),
+                        "margins": [round(margins[0], 4), round(margins[1], 4)]}
+    return res
 
 
 def main() -> int:
@@ -253,6 +269,8 @@ def main() -> int:
     if not args.no_batched:
         log("batched 256-instance comparison")
         out["batched_256"] = bench_batched(lib)
+        log("learned + batched on 1024 instances at 256^2")
+        out["learned_1024"] = bench_learned(lib)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline()
