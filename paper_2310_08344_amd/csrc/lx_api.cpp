@@ -945,7 +945,7 @@ lx_status lx_tune(lx_ctx* ctx, const lx_operator* op, int K, int sweeps, char* r
         const int tiles_x = (nx + 127) / 128;
         for (int th : {8, 16, 32}) {
             const int tiles = tiles_x * ((ny + th - 1) / th);
-            for (int pnb : {0, 2048, 1024, 512}) {
+            for (int pnb : {0, 2048, 1536, 1024, 768, 512, 256}) {
                 if (pnb != 0 && pnb >= tiles) continue;
                 SweepArgs a{};
                 a.nx = nx;

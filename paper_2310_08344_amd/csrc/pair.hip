@@ -153,11 +153,48 @@ __device__ __forceinline__ double shifted_one(const Sten& a, const double shift,
     }
 }
 
+// y_m of one tile as this thread stages it (rows -2..TH+1 of its column
+// pair, and one halo value), loaded a tile ahead of its LDS staging so that
+// the loads overlap the previous tile's arithmetic
+template <int TH>
+struct TileY {
+    // the two columns of each staged row, kept as two scalar arrays (an
+    // array of double2 this long is not promoted to registers)
+    double x[(TH + 4) / kPairWaves], y[(TH + 4) / kPairWaves];
+    double edge;
+};
+
+template <int K, int TH>
+__device__ __forceinline__ TileY<TH> load_tile_y(const TileArgs<K>& a, const double* __restrict__ yin,
+                                                 const int tile) {
+    TileY<TH> r;
+    r.edge = 0.0;
+    static_assert(TH % kPairWaves == 0, "tile rows must be a multiple of the wavefronts");
+    const int nx = a.nx, ny = a.ny;
+    const int x0 = (tile % a.tiles_x) * kPairTW, y0 = (tile / a.tiles_x) * TH;
+    const int tid = flat_tid(), lane = tid & 63, w = tid >> 6;
+    const int gc = wrap(x0 + 2 * lane, nx);       // even: nx and x0 are even
+#pragma unroll
+    for (int i = 0; i < (TH + 4) / kPairWaves; ++i) {
+        const long g = wrap(y0 - 2 + w + i * kPairWaves, ny) * static_cast<long>(nx) + gc;
+        const double2 t = *reinterpret_cast<const double2*>(yin + g);
+        r.x[i] = t.x;
+        r.y[i] = t.y;
+    }
+    if (tid < (TH + 4) * 4) {
+        const int q = tid & 3;
+        const int ec = (q < 2) ? q : kPairTW + q;
+        r.edge = yin[wrap(y0 - 2 + (tid >> 2), ny) * static_cast<long>(nx) + wrap(x0 + ec - 2, nx)];
+    }
+    return r;
+}
+
 template <int OP, int K, int TH>
 __device__ __forceinline__ void pair_tile(const TileArgs<K>& a, PairLds<OP, TH>& S, const double* __restrict__ yin,
                                           double* __restrict__ yout, const int m, const bool first,
                                           const int (&add0)[K], const int (&add1)[K], double& sy1, double& sy2,
-                                          double (&sp1)[K], double (&sp2)[K], const int tile) {
+                                          double (&sp1)[K], double (&sp2)[K], const int tile, TileY<TH>& ty,
+                                          const int next) {
     constexpr int RW = TH / kPairWaves;           // tile rows per wavefront
     const int nx = a.nx, ny = a.ny;
     const int x0 = (tile % a.tiles_x) * kPairTW, y0 = (tile / a.tiles_x) * TH;
@@ -169,24 +206,16 @@ __device__ __forceinline__ void pair_tile(const TileArgs<K>& a, PairLds<OP, TH>&
     const double xm = a.xi[m], xm1 = a.xi[m + 1];
 
     // ---- y_m (and u) on rows -2..TH+1, columns -2..129; the outputs ----
-    static_assert(TH % kPairWaves == 0, "tile rows must be a multiple of the wavefronts");
     constexpr int RM = (TH + 4) / kPairWaves;     // staged rows of y_m per wavefront
-    double2 yv[RM];
-#pragma unroll
-    for (int i = 0; i < RM; ++i) {
-        const long g = wrap(y0 - 2 + w + i * kPairWaves, ny) * static_cast<long>(nx) + gc;
-        yv[i] = *reinterpret_cast<const double2*>(yin + g);
-    }
-    double edge = 0.0, uedge = 0.0;
+    double uedge = 0.0;
     int er = 0, ec = 0;
     const bool has_edge = tid < (TH + 4) * 4;
     if (has_edge) {
         er = tid >> 2;
         const int q = tid & 3;
         ec = (q < 2) ? q : kPairTW + q;           // LDS columns 0, 1, 130, 131
-        const long g = wrap(y0 - 2 + er, ny) * static_cast<long>(nx) + wrap(x0 + ec - 2, nx);
-        edge = yin[g];
-        if constexpr (OP == kOpBurgersJ) uedge = uu[g];
+        if constexpr (OP == kOpBurgersJ)
+            uedge = uu[wrap(y0 - 2 + er, ny) * static_cast<long>(nx) + wrap(x0 + ec - 2, nx)];
     }
     // outputs of this thread's rows, fetched while the tile is staged
     double2 pv[K][RW];
@@ -214,13 +243,17 @@ __device__ __forceinline__ void pair_tile(const TileArgs<K>& a, PairLds<OP, TH>&
 #pragma unroll
     for (int i = 0; i < RM; ++i) {
         const int r = w + i * kPairWaves;
-        *reinterpret_cast<double2*>(&S.ym[r][j]) = yv[i];
+        double2 t;
+        t.x = ty.x[i];
+        t.y = ty.y[i];
+        *reinterpret_cast<double2*>(&S.ym[r][j]) = t;
     }
     if (has_edge) {
-        S.ym[er][ec] = edge;
+        S.ym[er][ec] = ty.edge;
         if constexpr (OP == kOpBurgersJ) S.u[er][ec] = uedge;
     }
     __syncthreads();
+    ty = load_tile_y<K, TH>(a, yin, next);   // the next tile's y_m, in flight during this one
 
     // ---- y_{m+1} on rows -1..TH, columns -1..128 ----
 #pragma unroll
@@ -411,11 +444,30 @@ __device__ __forceinline__ void pair_launch(const SweepArgs& a, const int L, con
     }
     const int T = a.tiles_x * a.tiles_y;
     const TileArgs<K> ta = tile_args<OP, K>(a);
-    auto body = [&](int t) { pair_tile<OP, K, TH>(ta, S, yin, yout, m, L == 0, add0, add1, sy1, sy2, sp1, sp2, t); };
-    if (banded) {
-        for_each_tile(T, a.nb, body);
+    // this workgroup's tiles: first, first + step, ... < end (an XCD's band
+    // for whole-device grids, a contiguous run for a batch instance)
+    int first, step, end;
+    if (banded && a.nb >= 8 && (a.nb & 7) == 0) {
+        const int x = wg & 7, nbx = a.nb >> 3;
+        first = static_cast<int>((static_cast<long>(x) * T) >> 3) + (wg >> 3);
+        step = nbx;
+        end = static_cast<int>((static_cast<long>(x + 1) * T) >> 3);
+    } else if (banded) {
+        first = wg;
+        step = a.nb;
+        end = T;
     } else {
-        for_tile_band(T, a.nb, wg, body);
+        first = static_cast<int>((static_cast<long>(wg) * T) / a.nb);
+        step = 1;
+        end = static_cast<int>((static_cast<long>(wg + 1) * T) / a.nb);
+    }
+    TileY<TH> ty;
+    if (first < end) ty = load_tile_y<K, TH>(ta, yin, first);
+    for (int t = first; t < end; t += step) {
+        // after the last tile, reload it (from L2) rather than branch: the
+        // registers then stay registers
+        const int next = (t + step < end) ? t + step : t;
+        pair_tile<OP, K, TH>(ta, S, yin, yout, m, L == 0, add0, add1, sy1, sy2, sp1, sp2, t, ty, next);
     }
     double v[NV];
     v[0] = sy1;
