@@ -50,6 +50,21 @@ constexpr int kPairTW = 128;                // tile columns
 constexpr int kPairPitch = kPairTW + 4;     // LDS row pitch in doubles (16-byte multiple)
 constexpr int kPairWaves = kBlockThreads / 64;
 
+// the outputs are read and written once per launch: streaming
+// (nontemporal) accesses that leave the caches to the basis vector
+__device__ __forceinline__ double2 ld_stream(const double* p) {
+    double v[2];
+    ldv_nt<2>(p, v);
+    double2 r;
+    r.x = v[0];
+    r.y = v[1];
+    return r;
+}
+__device__ __forceinline__ void st_stream(double* p, const double2 t) {
+    const double v[2] = {t.x, t.y};
+    stv_nt<2>(p, v);
+}
+
 template <int OP, int TH>
 struct PairLds {
     double ym[TH + 4][kPairPitch];          // y_m: row r at [r + 2], column c at [c + 2]
@@ -228,7 +243,7 @@ __device__ __forceinline__ void pair_tile(const TileArgs<K>& a, PairLds<OP, TH>&
             for (int i = 0; i < RW; ++i) {
                 const int grow = y0 + w + i * kPairWaves;
                 if (gcol < nx && grow < ny)
-                    pv[k][i] = *reinterpret_cast<const double2*>(pk + static_cast<long>(grow) * nx + gcol);
+                    pv[k][i] = ld_stream(pk + static_cast<long>(grow) * nx + gcol);
             }
         }
     }
@@ -329,7 +344,7 @@ __device__ __forceinline__ void pair_tile(const TileArgs<K>& a, PairLds<OP, TH>&
                     p.x = fma(dm1, c1.x, p.x);
                     p.y = fma(dm1, c1.y, p.y);
                 }
-                *reinterpret_cast<double2*>(a.p[k] + idx) = p;
+                st_stream(a.p[k] + idx, p);
                 sp1[k] += p.x * p.x + p.y * p.y;
                 const double qx = fma(dm2, o[0], p.x), qy = fma(dm2, o[1], p.y);
                 sp2[k] += qx * qx + qy * qy;

@@ -74,6 +74,40 @@ __device__ __forceinline__ void stv(T* __restrict__ p, const T (&o)[V]) {
     }
 }
 
+// Streaming (nontemporal) variants for the outputs p_k, which each launch
+// reads and writes once.  The hint keeps them from displacing the basis
+// vector in the caches: on MI355X the basis vector of a 4096^2 grid
+// (134 MB) then stays in the 256 MB Infinity Cache from the launch that
+// writes it to the launch that reads it.  Measured at 4096^2 with three
+// outputs: 105 us per iteration without hints, 92 with hints on p and the
+// basis vector, 79 with hints on p only.
+template <typename T> struct Vec2;
+template <> struct Vec2<double> { typedef double type __attribute__((ext_vector_type(2))); };
+template <> struct Vec2<float> { typedef float type __attribute__((ext_vector_type(2))); };
+
+template <int V, typename T, typename A>
+__device__ __forceinline__ void ldv_nt(const T* __restrict__ p, A (&o)[V]) {
+    if constexpr (V == 2) {
+        const auto t = __builtin_nontemporal_load(reinterpret_cast<const typename Vec2<T>::type*>(p));
+        o[0] = static_cast<A>(t.x);
+        o[1] = static_cast<A>(t.y);
+    } else {
+        o[0] = static_cast<A>(__builtin_nontemporal_load(p));
+    }
+}
+
+template <int V, typename T>
+__device__ __forceinline__ void stv_nt(T* __restrict__ p, const T (&o)[V]) {
+    if constexpr (V == 2) {
+        typename Vec2<T>::type t;
+        t.x = o[0];
+        t.y = o[1];
+        __builtin_nontemporal_store(t, reinterpret_cast<typename Vec2<T>::type*>(p));
+    } else {
+        __builtin_nontemporal_store(o[0], p);
+    }
+}
+
 // Sums NV values over the workgroup in a fixed order (butterfly within each
 // 64-lane wavefront, then wavefronts in index order); every thread receives
 // the result.
@@ -283,12 +317,12 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int m, cons
                     for (int i = 0; i < V; ++i) pv[i] += bv[i];
                 }
             } else {
-                ldv<V>(pk[k] + idx, pv);
+                ldv_nt<V>(pk[k] + idx, pv);
             }
 #pragma unroll
             for (int i = 0; i < V; ++i) pv[i] = fma(dn1[k], od[i], pv[i]);
             if (ok) {
-                stv<V>(pk[k] + idx, pv);
+                stv_nt<V>(pk[k] + idx, pv);
 #pragma unroll
                 for (int i = 0; i < V; ++i) sp[k] += pv[i] * pv[i];
             }
