@@ -108,6 +108,7 @@ typedef struct {
     double bytes;           /* algorithmic HBM bytes of the working sweeps    */
     int n_launch;           /* Leja-loop launches that did work               */
     int depth;              /* Leja iterations per launch (1 or 2)            */
+    double step_err;        /* lx_exprb_step with LX_EXPRB32: embedded error  */
 } lx_stats;
 
 /* ---- context ---------------------------------------------------------- */
@@ -185,20 +186,34 @@ lx_status lx_phi_leja(lx_ctx* ctx, const lx_operator* op, const double* d_u,
 
 /* ---- exponential integrator steps ------------------------------------- */
 
+/* In all three, J = J(u) and N(w) = F(w) - J w (Sec. 2.3); every phi
+ * action is a Leja pass of its own, whose stop rule measures that action
+ * alone, and the stages are summed afterwards. */
 typedef enum {
+    /* exponential Rosenbrock-Euler, second order (Sec. 2.3):
+     *   u+ = u + h phi_1(h J) F(u)                                            */
+    LX_ROS_EULER = 2,
+    /* EXPRB32, third order with an embedded second-order solution (Sec. 2.3):
+     *   a  = u + h phi_1(h J) F(u)
+     *   u+ = a + 2 h phi_3(h J) [N(a) - N(u)];
+     * lx_stats.step_err receives the rms norm (l2 / sqrt(N)) of the
+     * correction u+ - a, the embedded error estimate.                        */
+    LX_EXPRB32 = 32,
     /* two-stage fourth-order exponential Rosenbrock method (named in Sec. 1;
      * formula of the published method, c_2 = 3/4):
      *   U2  = u + (3/4) h phi_1((3/4) h J) F(u)
-     *   u+  = u + h phi_1(h J) F(u) + (32/9) h phi_3(h J) [N(U2) - N(u)],
-     *   J = J(u), N(w) = F(w) - J w.                                         */
+     *   u+  = u + h phi_1(h J) F(u) + (32/9) h phi_3(h J) [N(U2) - N(u)];
+     * both phi_1 actions come from one Newton basis.                         */
     LX_EXPRB42 = 42
 } lx_scheme;
 
 /* One step u -> d_u_out of u_t = F(u) for LX_OP_BURGERS2D.  c and gamma
  * describe the spectrum of J(d_u) (lx_spectrum with d_u).  iters: host [2]
- * or NULL, sweeps of the phi_1 pass and of the phi_3 pass.  d_u_out must
- * differ from d_u.  Errors as lx_phi_leja; LX_EINVAL for another operator
- * or scheme. */
+ * or NULL, iterations of the first (phi_1) pass and of the phi_3 pass (0 for
+ * LX_ROS_EULER).  d_u_out must differ from d_u.  Three workspace vectors of
+ * the context's n_max are allocated on the first call.  Errors as
+ * lx_phi_leja; LX_EINVAL for another operator or scheme, or LX_EXPRB42 on a
+ * context with k_max < 2. */
 lx_status lx_exprb_step(lx_ctx* ctx, const lx_operator* op, int scheme,
                         const double* d_u, double* d_u_out, double h,
                         double c, double gamma, const lx_leja_opts* o,

@@ -147,6 +147,36 @@ class StepResult:
     stages: dict
 
 
+def ros_euler_step(u, nu, dx, dy, h, c, gamma, rtol, atol, max_iters=500) -> StepResult:
+    """One exponential Rosenbrock-Euler step (Sec. 2.3): the phi_1 action of
+    the Jacobian at u on h F(u), added to u."""
+    u = np.asarray(u, dtype=np.float64)
+    J = lambda w: burgers_J(u, w, nu, dx, dy)
+    hF = h * burgers_F(u, nu, dx, dy)
+    r = leja_phi(J, hF, [(1, 1.0, 1.0)], h, c, gamma, rtol, atol, max_iters)
+    return StepResult(u_next=u + r.p[0], iters=[r.iters[0], 0], status=r.status, stages={"phi1": r.p[0]})
+
+
+def exprb32_step(u, nu, dx, dy, h, c, gamma, rtol, atol, max_iters=500) -> StepResult:
+    """One EXPRB32 step (Sec. 2.3): the Rosenbrock-Euler stage a, then the
+    third-order correction 2 phi_3(hJ) h [N(a) - N(u)] with N(w) = F(w) - J w;
+    stages["error"] is the rms norm of the correction (the embedded estimate)."""
+    u = np.asarray(u, dtype=np.float64)
+    J = lambda w: burgers_J(u, w, nu, dx, dy)
+    F = lambda w: burgers_F(w, nu, dx, dy)
+    hF = h * F(u)
+    r1 = leja_phi(J, hF, [(1, 1.0, 1.0)], h, c, gamma, rtol, atol, max_iters)
+    a = u + r1.p[0]
+    Nl = lambda w: F(w) - J(w)
+    R = h * (Nl(a) - Nl(u))
+    r2 = leja_phi(J, R, [(3, 1.0, 2.0)], h, c, gamma, rtol, atol, max_iters)
+    corr = r2.p[0]
+    status = r1.status if r1.status != "ok" else r2.status
+    return StepResult(u_next=a + corr, iters=[r1.iters[0], r2.iters[0]], status=status,
+                      stages={"a": a, "R": R, "correction": corr,
+                              "error": float(np.linalg.norm(corr) / math.sqrt(corr.size))})
+
+
 def exprb42_step(u, nu, dx, dy, h, c, gamma, rtol, atol, max_iters=500) -> StepResult:
     """One EXPRB42 step of u_t = F(u) (Burgers), Jacobian and remainder as in
     Sec. 2.3; the phi actions use Newton-Leja interpolation."""

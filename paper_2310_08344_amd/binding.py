@@ -16,6 +16,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lx.so")
 LX_OK, LX_EINVAL, LX_ENOMEM, LX_ENOTCONV, LX_ENONFINITE, LX_EDEVICE = range(6)
 LX_OP_DIFFADV2D, LX_OP_BURGERS2D = 1, 2
 LX_FP64, LX_FP32_SWEEP = 0, 1
+LX_ROS_EULER = 2
+LX_EXPRB32 = 32
 LX_EXPRB42 = 42
 LX_K_MAX = 4
 LX_MAX_ITERS = 1000
@@ -47,14 +49,15 @@ class Stats(C.Structure):
                 ("pnorm", C.c_double * LX_K_MAX), ("rho_hat", C.c_double),
                 ("plan_ms", C.c_double), ("loop_ms", C.c_double), ("sweep_ms", C.c_double),
                 ("first_sweep_ms", C.c_double), ("bytes", C.c_double), ("n_launch", C.c_int),
-                ("depth", C.c_int)]
+                ("depth", C.c_int), ("step_err", C.c_double)]
 
     def as_dict(self) -> dict:
         return {"status": self.status, "n_apply": self.n_apply, "n_fp32": self.n_fp32,
                 "iters": list(self.iters), "err": list(self.err), "pnorm": list(self.pnorm),
                 "rho_hat": self.rho_hat, "plan_ms": self.plan_ms, "loop_ms": self.loop_ms,
                 "sweep_ms": self.sweep_ms, "first_sweep_ms": self.first_sweep_ms,
-                "bytes": self.bytes, "n_launch": self.n_launch, "depth": self.depth}
+                "bytes": self.bytes, "n_launch": self.n_launch, "depth": self.depth,
+                "step_err": self.step_err}
 
 
 class Instance(C.Structure):

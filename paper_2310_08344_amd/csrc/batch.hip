@@ -232,7 +232,6 @@ __global__ __launch_bounds__(kBlockThreads) void batch_sweep_kernel(const BatchI
         a.u = I.u;
         a.u32 = nullptr;
         a.p[0] = I.out;
-        a.base[0] = nullptr;
         a.coef = coef + static_cast<long>(w.i) * ld;
         a.xi = xi;
         a.partials = partials + I.part_off;

@@ -165,9 +165,10 @@ __global__ void burgers_hF_kernel(const double* __restrict__ u, double* __restri
     }
 }
 
-// R = h [N(U2) - N(u)] with N(w) = F(w) - J(u) w, i.e.
-// h [F(U2) - F(u) - J(u)(U2 - u)]
-__global__ void burgers_remainder_kernel(const double* __restrict__ u, const double* __restrict__ U2,
+// R = h [N(u + a) - N(u)] with N(w) = F(w) - J(u) w, i.e.
+// h [F(w) - F(u) - J(u) a] for the stage w = u + a (formed here, as the
+// stage vector of the integrator)
+__global__ void burgers_remainder_kernel(const double* __restrict__ u, const double* __restrict__ a,
                                          double* __restrict__ out, int nx, int ny, double nu, double dx,
                                          double dy, double h) {
     const long n = static_cast<long>(nx) * ny;
@@ -178,13 +179,24 @@ __global__ void burgers_remainder_kernel(const double* __restrict__ u, const dou
         const int jn = (j + 1 == ny) ? 0 : j + 1, js = (j == 0) ? ny - 1 : j - 1;
         const long ce = static_cast<long>(j) * nx + ie, cw = static_cast<long>(j) * nx + iw;
         const long cn = static_cast<long>(jn) * nx + i, cs = static_cast<long>(js) * nx + i;
-        const double ae = U2[ce] - u[ce], aw = U2[cw] - u[cw], an = U2[cn] - u[cn], as = U2[cs] - u[cs];
-        const double ac = U2[t] - u[t];
-        const double lap = (ae - 2.0 * ac + aw) / (dx * dx) + (an - 2.0 * ac + as) / (dy * dy);
-        const double Ja = nu * lap - ((u[ce] * ae - u[cw] * aw) / (2.0 * dx) + (u[cn] * an - u[cs] * as) / (2.0 * dy));
-        const double FU2 = burgers_F_at(U2, i, j, nx, ny, nu, dx, dy);
+        const double ac = a[t], ae = a[ce], aw = a[cw], an = a[cn], as = a[cs];
+        const double wc = u[t] + ac, we = u[ce] + ae, ww = u[cw] + aw, wn = u[cn] + an, ws = u[cs] + as;
+        const double lapw = (we - 2.0 * wc + ww) / (dx * dx) + (wn - 2.0 * wc + ws) / (dy * dy);
+        const double Fw = nu * lapw - 0.5 * ((we * we - ww * ww) / (2.0 * dx) + (wn * wn - ws * ws) / (2.0 * dy));
+        const double lapa = (ae - 2.0 * ac + aw) / (dx * dx) + (an - 2.0 * ac + as) / (dy * dy);
+        const double Ja = nu * lapa - ((u[ce] * ae - u[cw] * aw) / (2.0 * dx) + (u[cn] * an - u[cs] * as) / (2.0 * dy));
         const double Fu = burgers_F_at(u, i, j, nx, ny, nu, dx, dy);
-        out[t] = h * (FU2 - Fu - Ja);
+        out[t] = h * (Fw - Fu - Ja);
+    }
+}
+
+// out = (x + y) + z, z optional (the stages of the integrators)
+__global__ void combine_kernel(const double* __restrict__ x, const double* __restrict__ y,
+                               const double* __restrict__ z, double* __restrict__ out, long n) {
+    for (long t = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x; t < n;
+         t += static_cast<long>(gridDim.x) * blockDim.x) {
+        const double s = x[t] + y[t];
+        out[t] = (z != nullptr) ? s + z[t] : s;
     }
 }
 
@@ -347,10 +359,15 @@ hipError_t launch_burgers_hF(const double* u, double* out, int nx, int ny, doubl
     return hipGetLastError();
 }
 
-hipError_t launch_burgers_remainder(const double* u, const double* U2, double* out, int nx, int ny, double nu,
+hipError_t launch_burgers_remainder(const double* u, const double* a, double* out, int nx, int ny, double nu,
                                     double dx, double dy, double h, hipStream_t s) {
     hipLaunchKernelGGL(burgers_remainder_kernel, dim3(flat_blocks(static_cast<long>(nx) * ny)),
-                       dim3(kBlockThreads), 0, s, u, U2, out, nx, ny, nu, dx, dy, h);
+                       dim3(kBlockThreads), 0, s, u, a, out, nx, ny, nu, dx, dy, h);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(const double* x, const double* y, const double* z, double* out, long n, hipStream_t s) {
+    hipLaunchKernelGGL(combine_kernel, dim3(flat_blocks(n)), dim3(kBlockThreads), 0, s, x, y, z, out, n);
     return hipGetLastError();
 }
 

@@ -211,7 +211,6 @@ struct LejaCall {
     double alpha[LX_K_MAX];
     double sigma[LX_K_MAX];
     double* out[LX_K_MAX];
-    const double* base[LX_K_MAX];
     double h, c, gamma;
     lx_leja_opts o;
 };
@@ -257,7 +256,7 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
     S = lx_stats{};
 
     bool vec2 = aligned16(q.v) && (q.u == nullptr || aligned16(q.u));
-    for (int k = 0; k < K; ++k) vec2 = vec2 && aligned16(q.out[k]) && (q.base[k] == nullptr || aligned16(q.base[k]));
+    for (int k = 0; k < K; ++k) vec2 = vec2 && aligned16(q.out[k]);
     Tile t = pick_tile(ctx, op, K, vec2);
     choose_depth(ctx, op, K, vec2, t);
     const bool pair = t.depth == 2;
@@ -328,10 +327,7 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
     a.ybuf[1] = ctx->ybuf[1];
     a.u = q.u;
     a.u32 = ctx->u32;
-    for (int k = 0; k < K; ++k) {
-        a.p[k] = q.out[k];
-        a.base[k] = q.base[k];
-    }
+    for (int k = 0; k < K; ++k) a.p[k] = q.out[k];
     a.coef = ctx->coef;
     a.xi = ctx->xi;
     a.ctl = ctx->ctl;
@@ -400,7 +396,7 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
     if (!pair) {
         // per sweep: the basis read and write, the Burgers state read, and per
         // unconverged output a read and a write of p (sweep 0 writes
-        // p_1 = d_0 v + d_1 y_1 without reading it; a base adds a read)
+        // p_1 = d_0 v + d_1 y_1 without reading it)
         S.n_apply = fin.iter;
         S.n_launch = fin.iter;
         for (int m = 0; m < fin.iter; ++m) {
@@ -409,7 +405,7 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
             double b = (r32 ? 4.0 : 8.0) + (w32 ? 4.0 : 8.0);
             if (op.kind == LX_OP_BURGERS2D) b += w32 ? 4.0 : 8.0;
             for (int k = 0; k < K; ++k) {
-                if (m < fin.iters[k]) b += (m == 0) ? (q.base[k] ? 16.0 : 8.0) : 16.0;
+                if (m < fin.iters[k]) b += (m == 0) ? 8.0 : 16.0;
             }
             bytes += b * static_cast<double>(N);
         }
@@ -427,7 +423,7 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
         for (int L = 0; L < F; ++L) {
             double b = 16.0 + ub;
             for (int k = 0; k < K; ++k) {
-                if (L == 0) b += q.base[k] ? 16.0 : 8.0;
+                if (L == 0) b += 8.0;
                 else if (fin.iters[k] >= 2 * L) b += 16.0;
             }
             bytes += b * static_cast<double>(N);
@@ -722,7 +718,6 @@ lx_status lx_phi_leja(lx_ctx* ctx, const lx_operator* op, const double* d_u, con
         for (int j = 0; j < k; ++j)
             if (d_out[j] == d_out[k]) return fail(ctx, LX_EINVAL, "d_out[%d] and d_out[%d] alias", j, k);
         q.out[k] = d_out[k];
-        q.base[k] = nullptr;
     }
     s = run_leja(ctx, q);
     for (int k = 0; k < K; ++k) {
@@ -739,10 +734,11 @@ lx_status lx_exprb_step(lx_ctx* ctx, const lx_operator* op, int scheme, const do
     lx_status s = check_op(ctx, op);
     if (s != LX_OK) return s;
     if (op->kind != LX_OP_BURGERS2D) return fail(ctx, LX_EINVAL, "exponential integrator steps need LX_OP_BURGERS2D");
-    if (scheme != LX_EXPRB42) return fail(ctx, LX_EINVAL, "unknown scheme %d", scheme);
+    if (scheme != LX_ROS_EULER && scheme != LX_EXPRB32 && scheme != LX_EXPRB42)
+        return fail(ctx, LX_EINVAL, "unknown scheme %d", scheme);
     if (d_u == nullptr || d_u_out == nullptr || d_u == d_u_out)
         return fail(ctx, LX_EINVAL, "d_u and d_u_out must be distinct, non-NULL");
-    if (ctx->k_max < 2) return fail(ctx, LX_EINVAL, "EXPRB42 needs a context with k_max >= 2");
+    if (scheme == LX_EXPRB42 && ctx->k_max < 2) return fail(ctx, LX_EINVAL, "EXPRB42 needs a context with k_max >= 2");
     s = check_shift(ctx, h, c, gamma);
     if (s != LX_OK) return s;
     lx_leja_opts oo;
@@ -750,59 +746,121 @@ lx_status lx_exprb_step(lx_ctx* ctx, const lx_operator* op, int scheme, const do
     if (s != LX_OK) return s;
     for (auto& w : ctx->ws)
         if (w == nullptr && hipMalloc(&w, sizeof(double) * ctx->n_max) != hipSuccess)
-            return fail(ctx, LX_ENOMEM, "EXPRB42 workspace allocation failed");
+            return fail(ctx, LX_ENOMEM, "integrator workspace allocation failed");
     const int nx = op->nx, ny = op->ny;
-    double* hF = ctx->ws[0];   // h F(u), later h [N(U2) - N(u)]
-    double* U2 = ctx->ws[1];
-    double* B = ctx->ws[2];    // u + h phi_1(h J) F(u)
-    // stage 1: U2 = u + (3/4) h phi_1((3/4) h J) F(u) and
-    //          B  = u + h phi_1(h J) F(u), one Newton basis
+    const long N = static_cast<long>(nx) * ny;
+    double* hF = ctx->ws[0];   // h F(u), later the remainder h [N(u + a) - N(u)]
+    auto pass = [&](int K, const int* l, const double* alpha, const double* sigma, double* const* out,
+                    const double* v) -> lx_status {
+        LejaCall q{};
+        q.op = op;
+        q.u = d_u;
+        q.v = v;
+        q.K = K;
+        for (int k = 0; k < K; ++k) {
+            q.l[k] = l[k];
+            q.alpha[k] = alpha[k];
+            q.sigma[k] = sigma[k];
+            q.out[k] = out[k];
+        }
+        q.h = h;
+        q.c = c;
+        q.gamma = gamma;
+        q.o = oo;
+        return run_leja(ctx, q);
+    };
+    auto merge = [](lx_stats& acc, const lx_stats& t) {
+        acc.n_apply += t.n_apply;
+        acc.n_fp32 += t.n_fp32;
+        acc.n_launch += t.n_launch;
+        acc.plan_ms += t.plan_ms;
+        acc.loop_ms += t.loop_ms;
+        acc.sweep_ms += t.sweep_ms;
+        acc.bytes += t.bytes;
+        acc.depth = t.depth;
+    };
     LX_HIP(ctx, lx::launch_burgers_hF(d_u, hF, nx, ny, op->nu, op->dx, op->dy, h, ctx->stream));
-    LejaCall q{};
-    q.op = op;
-    q.u = d_u;
-    q.v = hF;
-    q.K = 2;
-    q.l[0] = 1; q.alpha[0] = 0.75; q.sigma[0] = 0.75; q.out[0] = U2;      q.base[0] = d_u;
-    q.l[1] = 1; q.alpha[1] = 1.0;  q.sigma[1] = 1.0;  q.out[1] = B;       q.base[1] = d_u;
-    q.h = h;
-    q.c = c;
-    q.gamma = gamma;
-    q.o = oo;
-    s = run_leja(ctx, q);
-    if (s != LX_OK) return s;
-    const lx_stats s1 = ctx->stats;
-    // stage 2: R = h [N(U2) - N(u)], u_out = B + (32/9) phi_3(h J) R
-    LX_HIP(ctx, lx::launch_burgers_remainder(d_u, U2, hF, nx, ny, op->nu, op->dx, op->dy, h, ctx->stream));
-    LejaCall r{};
-    r.op = op;
-    r.u = d_u;
-    r.v = hF;
-    r.K = 1;
-    r.l[0] = 3; r.alpha[0] = 1.0; r.sigma[0] = 32.0 / 9.0; r.out[0] = d_u_out; r.base[0] = B;
-    r.h = h;
-    r.c = c;
-    r.gamma = gamma;
-    r.o = oo;
-    s = run_leja(ctx, r);
-    lx_stats& S = ctx->stats;
-    const int it1 = std::max(s1.iters[0], s1.iters[1]);
-    const int it2 = S.iters[0];
+    lx_stats acc{};
+    int it1 = 0, it2 = 0;
+    double e1 = 0.0, e2 = 0.0, step_err = 0.0;
+    if (scheme == LX_ROS_EULER) {
+        // u+ = u + phi_1(h J) h F(u)
+        const int l[1] = {1};
+        const double one[1] = {1.0};
+        double* out[1] = {d_u_out};
+        s = pass(1, l, one, one, out, hF);
+        if (s != LX_OK) return s;
+        acc = ctx->stats;
+        it1 = acc.iters[0];
+        e1 = acc.err[0];
+        LX_HIP(ctx, lx::launch_combine(d_u, d_u_out, nullptr, d_u_out, N, ctx->stream));
+    } else if (scheme == LX_EXPRB32) {
+        // a = u + phi_1(h J) h F(u);  u+ = a + 2 phi_3(h J) h [N(a) - N(u)];
+        // the embedded estimate is the rms norm of the correction
+        double* p1 = ctx->ws[1];
+        double* a = ctx->ws[2];
+        const int l1[1] = {1}, l3[1] = {3};
+        const double one[1] = {1.0}, two[1] = {2.0};
+        double* out1[1] = {p1};
+        s = pass(1, l1, one, one, out1, hF);
+        if (s != LX_OK) return s;
+        acc = ctx->stats;
+        it1 = acc.iters[0];
+        e1 = acc.err[0];
+        LX_HIP(ctx, lx::launch_combine(d_u, p1, nullptr, a, N, ctx->stream));
+        LX_HIP(ctx, lx::launch_burgers_remainder(d_u, p1, hF, nx, ny, op->nu, op->dx, op->dy, h, ctx->stream));
+        double* out2[1] = {d_u_out};
+        s = pass(1, l3, one, two, out2, hF);
+        const lx_stats t = ctx->stats;
+        merge(acc, t);
+        it2 = t.iters[0];
+        e2 = t.err[0];
+        step_err = t.pnorm[0];
+        if (s != LX_OK) {
+            ctx->stats = acc;
+            return s;
+        }
+        LX_HIP(ctx, lx::launch_combine(a, d_u_out, nullptr, d_u_out, N, ctx->stream));
+    } else {
+        // one Newton basis for (3/4) h phi_1((3/4) h J) F(u) and h phi_1(h J) F(u);
+        // U2 = u + the first; u+ = u + the second + (32/9) h phi_3(h J) [N(U2) - N(u)]
+        double* a = ctx->ws[1];
+        double* p1 = ctx->ws[2];
+        const int l1[2] = {1, 1}, l3[1] = {3};
+        const double alpha1[2] = {0.75, 1.0}, sigma1[2] = {0.75, 1.0};
+        const double one[1] = {1.0}, s3[1] = {32.0 / 9.0};
+        double* out1[2] = {a, p1};
+        s = pass(2, l1, alpha1, sigma1, out1, hF);
+        if (s != LX_OK) return s;
+        acc = ctx->stats;
+        it1 = std::max(acc.iters[0], acc.iters[1]);
+        e1 = std::max(acc.err[0], acc.err[1]);
+        LX_HIP(ctx, lx::launch_burgers_remainder(d_u, a, hF, nx, ny, op->nu, op->dx, op->dy, h, ctx->stream));
+        double* out2[1] = {d_u_out};
+        s = pass(1, l3, one, s3, out2, hF);
+        const lx_stats t = ctx->stats;
+        merge(acc, t);
+        it2 = t.iters[0];
+        e2 = t.err[0];
+        if (s != LX_OK) {
+            ctx->stats = acc;
+            return s;
+        }
+        LX_HIP(ctx, lx::launch_combine(d_u, p1, d_u_out, d_u_out, N, ctx->stream));
+    }
     if (iters) {
         iters[0] = it1;
         iters[1] = it2;
     }
-    S.iters[0] = it1;
-    S.iters[1] = it2;
-    S.err[1] = S.err[0];
-    S.err[0] = std::max(s1.err[0], s1.err[1]);
-    S.n_apply += s1.n_apply;
-    S.n_fp32 += s1.n_fp32;
-    S.bytes += s1.bytes;
-    S.plan_ms += s1.plan_ms;
-    S.loop_ms += s1.loop_ms;
-    S.sweep_ms += s1.sweep_ms;
-    return s;
+    acc.iters[0] = it1;
+    acc.iters[1] = it2;
+    acc.iters[2] = acc.iters[3] = 0;
+    acc.err[0] = e1;
+    acc.err[1] = e2;
+    acc.step_err = step_err;
+    acc.status = LX_OK;
+    ctx->stats = acc;
+    return LX_OK;
 }
 
 lx_status lx_set_depth(lx_ctx* ctx, int depth, int th, int nb) {

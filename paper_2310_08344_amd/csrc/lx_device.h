@@ -68,7 +68,6 @@ struct SweepArgs {
     const double* u;         // Burgers state
     const float* u32;        // Burgers state rounded to FP32 (FP32 sweeps)
     double* p[kKMax];        // outputs (the polynomials)
-    const double* base[kKMax];  // optional: p_0 = base + d_0 v (internal use)
     const double* coef;      // coef[k*ld + j] = d_j of output k
     const double* xi;        // Leja points
     double* partials;        // [2][nb][1+K]
@@ -135,8 +134,11 @@ hipError_t launch_probe(int kind, const double* x, const double* y, double* z, l
 // Burgers helpers for EXPRB42
 hipError_t launch_burgers_hF(const double* u, double* out, int nx, int ny, double nu, double dx,
                              double dy, double h, hipStream_t s);
-hipError_t launch_burgers_remainder(const double* u, const double* U2, double* out, int nx, int ny,
+// h [N(u + a) - N(u)], N(w) = F(w) - J(u) w
+hipError_t launch_burgers_remainder(const double* u, const double* a, double* out, int nx, int ny,
                                     double nu, double dx, double dy, double h, hipStream_t s);
+// out = (x + y) + z (z may be NULL)
+hipError_t launch_combine(const double* x, const double* y, const double* z, double* out, long n, hipStream_t s);
 
 // Batched launches: every workgroup serves the instance block_inst[b].
 hipError_t launch_batch_fill_x0(BatchInst* insts, const int* block_inst, int nblocks, hipStream_t s);

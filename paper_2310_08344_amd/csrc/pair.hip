@@ -94,7 +94,6 @@ struct TileArgs {
     const double* coef;
     const double* xi;
     double* p[K];
-    const double* base[K];
 };
 
 template <int OP, int K>
@@ -115,7 +114,6 @@ __device__ __forceinline__ TileArgs<K> tile_args(const SweepArgs& a) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         t.p[k] = a.p[k];
-        t.base[k] = a.base[k];
     }
     return t;
 }
@@ -325,14 +323,9 @@ __device__ __forceinline__ void pair_tile(const TileArgs<K>& a, PairLds<OP, TH>&
                 const double dm2 = a.coef[k * a.ld + m + 2];
                 double2 p;
                 if (first) {
-                    // p_0 = d_0 y_0 (+ optional base); y_0 = v is the centre
+                    // p_0 = d_0 y_0; y_0 = v is the centre
                     p.x = dm * c0.x;
                     p.y = dm * c0.y;
-                    if (a.base[k] != nullptr) {
-                        const double2 b = *reinterpret_cast<const double2*>(a.base[k] + idx);
-                        p.x += b.x;
-                        p.y += b.y;
-                    }
                 } else {
                     p = pv[k][i];
                     if (add0[k]) {
@@ -550,7 +543,6 @@ __global__ __launch_bounds__(kBlockThreads) void batch_pair_kernel(const BatchIn
         a.ybuf[1] = I.y[1];
         a.u = I.u;
         a.p[0] = I.out;
-        a.base[0] = nullptr;
         a.coef = coef + static_cast<long>(i) * ld;
         a.xi = xi;
         a.partials = partials + I.part_off;

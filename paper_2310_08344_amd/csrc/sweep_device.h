@@ -218,12 +218,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int m, cons
     TO* __restrict__ yout = static_cast<TO*>(a.ybuf[m & 1]);
 
     double* __restrict__ pk[K];
-    const double* __restrict__ bk[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        pk[k] = a.p[k];
-        bk[k] = a.base[k];
-    }
+    for (int k = 0; k < K; ++k) pk[k] = a.p[k];
     const double* __restrict__ uu = a.u;
     const float* __restrict__ uu32 = a.u32;
     const double xim = a.xi[m];
@@ -307,15 +303,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int m, cons
             if (!act[k]) continue;
             double pv[V];
             if (m == 0) {
-                // p_0 = d_0 y_0 (+ optional base); y_0 = v is the centre row
+                // p_0 = d_0 y_0; y_0 = v is the centre row
 #pragma unroll
                 for (int i = 0; i < V; ++i) pv[i] = d0[k] * static_cast<double>(cen[i]);
-                if (bk[k] != nullptr) {
-                    double bv[V];
-                    ldv<V>(bk[k] + idx, bv);
-#pragma unroll
-                    for (int i = 0; i < V; ++i) pv[i] += bv[i];
-                }
             } else {
                 ldv_nt<V>(pk[k] + idx, pv);
             }

@@ -13,7 +13,7 @@ import pytest
 
 from oracle.exact import phi_fft
 from oracle.operators import burgers_J, diffadv_apply
-from oracle.phi_action import exprb42_step, leja_phi, power_iteration
+from oracle.phi_action import exprb32_step, exprb42_step, leja_phi, power_iteration, ros_euler_step
 from paper_2310_08344_amd import binding as B
 from paper_2310_08344_amd import workloads as W
 from tests.gpu_helpers import (closed_form_shift, dev, diffadv_setup, host, oracle_parity,
@@ -194,6 +194,44 @@ def test_exprb42_step_matches_oracle(ctx, n):
     else:
         say("stop decision differs", ref.iters, r.iters)
         # the step's update differs by at most tolerance-sized terms
+        assert rel(host(out) - u0, ref.u_next - u0) <= 1e-7
+
+
+STEPS = {"ros_euler": (B.LX_ROS_EULER, ros_euler_step), "exprb32": (B.LX_EXPRB32, exprb32_step),
+         "exprb42": (B.LX_EXPRB42, exprb42_step)}
+
+
+@pytest.mark.parametrize("depth", [2, 1])
+@pytest.mark.parametrize("scheme", sorted(STEPS))
+@pytest.mark.parametrize("n", [128, 250])
+def test_integrator_steps_match_oracle(ctx, scheme, n, depth):
+    """Each scheme's step, one or two Leja iterations per launch, against the
+    oracle's step (the stages, the sum order and the stop rule of every phi
+    pass as in the oracle), at cell Peclet number 2 and h = 10 x CFL."""
+    code, oracle_step = STEPS[scheme]
+    u0 = W.fourier_modes(n, seed=3)
+    nu = float(np.max(np.abs(u0))) / n / 2.0
+    h = 10.0 * W.burgers_cfl_step(nu, float(np.max(np.abs(u0))), 1 / n, 1 / n)
+    op = B.make_operator(kind=B.LX_OP_BURGERS2D, n=n, nu=nu)
+    x0 = np.random.default_rng(11).standard_normal((n, n))
+    say("integrator", scheme, n, "depth", depth)
+    rho, c, g = ctx.spectrum(op, u=dev(u0), x0=dev(x0), iters=20)
+    out = dev(np.zeros_like(u0))
+    ctx.set_depth(depth)
+    try:
+        r = ctx.exprb_step(op, dev(u0), out, h, c, g, rtol=1e-8, max_iters=200, scheme=code)
+    finally:
+        ctx.set_depth(0)
+    assert r.status == B.LX_OK and r.stats["depth"] == depth
+    ref = oracle_step(u0, nu, 1 / n, 1 / n, h, c, g, 1e-8, 0.0, 200)
+    assert ref.status == "ok"
+    if list(ref.iters) == list(r.iters):
+        assert rel(host(out), ref.u_next) <= PARITY
+        if scheme == "exprb32":
+            assert abs(r.stats["step_err"] - ref.stages["error"]) <= 1e-9 * ref.stages["error"]
+    else:
+        say("stop decision differs", ref.iters, r.iters)
+        assert max(abs(a - b) for a, b in zip(ref.iters, r.iters)) <= 1
         assert rel(host(out) - u0, ref.u_next - u0) <= 1e-7
 
 

@@ -23,7 +23,7 @@ from scipy.integrate import solve_ivp
 
 from oracle.exact import dense_matrix, phi_dense, phi_fft
 from oracle.operators import burgers_F, burgers_J, diffadv_apply, make_apply
-from oracle.phi_action import (exprb42_step, leja_phi, power_iteration,
+from oracle.phi_action import (exprb32_step, exprb42_step, leja_phi, power_iteration, ros_euler_step,
                                shift_scale)
 from paper_2310_08344_amd import workloads as W
 
@@ -194,6 +194,47 @@ def test_zero_vector_converges_in_one_step():
     n, h, A_apply, c, g = _small_problem()
     r = leja_phi(A_apply, np.zeros((n, n)), [(1, 1.0, 1.0)], h, c, g, 1e-8, 0.0, max_iters=50)
     assert r.status == "ok" and r.iters == [1] and not np.any(r.p[0])
+
+
+def _burgers_orders(step, steps_list, n=16, nu=0.05, T=0.02):
+    """Errors of `step` against DOP853 on a smooth Burgers problem, and the
+    observed convergence rates when the step is halved."""
+    u0 = 1.0 + 0.5 * W.fourier_modes(n, seed=21, n_modes=2, kmax=1)
+    dx = 1.0 / n
+    sol = solve_ivp(lambda t, y: burgers_F(y.reshape(n, n), nu, dx, dx).ravel(), (0.0, T),
+                    u0.ravel(), method="DOP853", rtol=1e-13, atol=1e-13)
+    ref = sol.y[:, -1].reshape(n, n)
+    errs, ests = [], []
+    for steps in steps_list:
+        h = T / steps
+        u = u0.copy()
+        for _ in range(steps):
+            J = lambda w, u=u: burgers_J(u, w, nu, dx, dx)
+            x0 = np.random.default_rng(1).standard_normal((n, n))
+            rho, _ = power_iteration(J, x0, 30)
+            c, g = shift_scale(rho)
+            r = step(u, nu, dx, dx, h, c, g, 1e-14, 0.0, max_iters=300)
+            if len(ests) < len(errs) + 1 and "error" in r.stages:
+                ests.append(r.stages["error"])     # the first step's embedded estimate
+            u = r.u_next
+        errs.append(np.linalg.norm(u - ref) / np.linalg.norm(ref))
+    rates = [math.log2(a / b) for a, b in zip(errs, errs[1:])]
+    return errs, rates, ests
+
+
+@pytest.mark.slow
+def test_ros_euler_is_second_order():
+    errs, rates, _ = _burgers_orders(ros_euler_step, (4, 8, 16))
+    assert min(rates) > 1.8 and max(rates) < 2.3, (errs, rates)
+
+
+@pytest.mark.slow
+def test_exprb32_is_third_order_and_its_estimate_local_third_order():
+    errs, rates, ests = _burgers_orders(exprb32_step, (4, 8, 16))
+    assert min(rates) > 2.7 and max(rates) < 3.4, (errs, rates)
+    # the estimate is the local error of the embedded second-order solution: O(h^3)
+    est_rates = [math.log2(a / b) for a, b in zip(ests, ests[1:])]
+    assert min(est_rates) > 2.6, (ests, est_rates)
 
 
 @pytest.mark.slow
