@@ -69,6 +69,36 @@ def diffadv_symbol(ny: int, nx: int, D, vx, vy, dx, dy) -> np.ndarray:
     return lam
 
 
+def diffadv3_symbol(ny: int, nx: int, D, vx, vy, dx, dy) -> np.ndarray:
+    """Eigenvalues of the stencil with the third-order upwind gradient, in the
+    numpy.fft.fft2 layout: the Laplacian's symbol plus, per axis with
+    t = 2 pi k / n,
+        v >= 0:  v (-e^{2it} + 6 e^{it} - 3 - 2 e^{-it}) / (6 d)
+        v <  0:  v (2 e^{it} + 3 - 6 e^{-it} + e^{-2it}) / (6 d)."""
+    tx = 2.0 * np.pi * np.fft.fftfreq(nx)[None, :]
+    ty = 2.0 * np.pi * np.fft.fftfreq(ny)[:, None]
+    lam = D * (2.0 * np.cos(tx) - 2.0) / dx**2 + D * (2.0 * np.cos(ty) - 2.0) / dy**2
+
+    def g(t, v, d):
+        e = np.exp(1j * t)
+        if v >= 0:
+            return v * (-e * e + 6.0 * e - 3.0 - 2.0 / e) / (6.0 * d)
+        return v * (2.0 * e + 3.0 - 6.0 / e + 1.0 / (e * e)) / (6.0 * d)
+
+    return lam + g(tx, vx, dx) + g(ty, vy, dy)
+
+
+def linear_step_fft(u: np.ndarray, S, h: float, lam: np.ndarray) -> np.ndarray:
+    """Exact solution after a time h of u_t = A u + S (S constant in time, or
+    None) for a stencil diagonalised by the 2-D DFT with symbol lam:
+    mode by mode, e^{h lam} u_hat + h phi_1(h lam) S_hat."""
+    uh = np.fft.fft2(np.asarray(u, dtype=np.float64))
+    out = np.exp(h * lam) * uh
+    if S is not None:
+        out = out + h * phi_complex(1, h * lam) * np.fft.fft2(np.asarray(S, dtype=np.float64))
+    return np.fft.ifft2(out).real
+
+
 def phi_fft(v: np.ndarray, l: int, h: float, D, vx, vy, dx, dy) -> np.ndarray:
     """phi_l(hA) v for the periodic diffusion-advection stencil, via FFT."""
     v = np.asarray(v, dtype=np.float64)

@@ -13,6 +13,9 @@ Paper passages followed
   * Several outputs from one basis ("vertical" interpolation): Sec. 2.3 and
     Listing 11 (integrator coefficients), Sec. 3 (Problem III).
   * Nonlinear remainder N(w) = f(w) - J(u_n) w: Sec. 2.3 (EXPRB32 text).
+  * Linear problems (Sec. 3, Problems I and II): u_{n+1} = exp(h A) u_n
+    without a source; with a time-independent source S,
+    u_{n+1} = u_n + phi_1(h A) h (A u_n + S).
 
 Readings (paper silent or ambiguous)
   * Power iteration: x_{k+1} = A x_k / ||A x_k||, rho_hat = ||A x_k|| / ||x_k||,
@@ -22,6 +25,8 @@ Readings (paper silent or ambiguous)
     freezes once it passes; the loop ends when all outputs have passed or
     after max_iters applications (status "notconv").  A non-finite norm ends
     the loop with status "nonfinite".
+  * Problem II's update is printed without the factor h in front of
+    phi_1; the exact solution of u_t = A u + S over a step h has it.
   * EXPRB42 (named in Sec. 1, formula not printed; the published two-stage
     fourth-order exponential Rosenbrock method with c_2 = 3/4):
         U_2     = u + (3/4) h phi_1((3/4) h J) F(u)
@@ -133,6 +138,23 @@ def leja_phi(apply_A, v, outputs, h, c, gamma, rtol, atol, max_iters=500,
     if status == "ok" and any(active):
         status = "notconv"
     return LejaResult(p=p, iters=iters, errs=errs, status=status, n_apply=n_apply)
+
+
+# --------------------------------------------------------------------------
+# linear problems (Problems I and II)
+# --------------------------------------------------------------------------
+
+def linear_step(apply_A, u, S, h, c, gamma, rtol, atol, max_iters=500) -> "StepResult":
+    """One step of u_t = A u (+ S): the exp action of u when S is None
+    (Problem I), else u + phi_1(h A) h (A u + S) (Problem II)."""
+    u = np.asarray(u, dtype=np.float64)
+    if S is None:
+        r = leja_phi(apply_A, u, [(0, 1.0, 1.0)], h, c, gamma, rtol, atol, max_iters)
+        return StepResult(u_next=r.p[0], iters=[r.iters[0], 0], status=r.status, stages={})
+    w = h * (apply_A(u) + np.asarray(S, dtype=np.float64))
+    r = leja_phi(apply_A, w, [(1, 1.0, 1.0)], h, c, gamma, rtol, atol, max_iters)
+    return StepResult(u_next=u + r.p[0], iters=[r.iters[0], 0], status=r.status,
+                      stages={"rhs": w, "phi1": r.p[0]})
 
 
 # --------------------------------------------------------------------------

@@ -8,7 +8,8 @@ HIP path and the CPU oracle can take their inputs from it.
 Conventions shared by every workload:
 
 * the domain is the periodic unit square [0, 1)^2 with ``n x n`` cells,
-  ``dx = dy = 1/n`` and grid points ``x_i = i*dx``;
+  ``dx = dy = 1/n`` and grid points ``x_i = i*dx`` (the paper-shaped linear
+  problems use [-1, 1)^2: ``dx = 2/n``, ``x_i = -1 + i*dx``);
 * arrays are row-major ``[ny][nx]``: the x index is the fast one;
 * the step size is a multiple ``s`` of the explicit CFL step, read as
   ``2 / rho`` where ``rho`` bounds the modulus of the discrete operator's
@@ -23,6 +24,7 @@ from dataclasses import dataclass, field, asdict
 import numpy as np
 
 DIFFADV = "diffadv"
+DIFFADV3 = "diffadv3"   # diffusion + third-order upwind advection
 BURGERS = "burgers"
 
 
@@ -40,14 +42,15 @@ class Problem:
     cfl_multiple: float = 0.0
     seed: int = 0
     meta: dict = field(default_factory=dict)
+    length: float = 1.0     # side of the periodic square
 
     @property
     def dx(self) -> float:
-        return 1.0 / self.n
+        return self.length / self.n
 
     @property
     def dy(self) -> float:
-        return 1.0 / self.n
+        return self.length / self.n
 
     @property
     def N(self) -> int:
@@ -68,6 +71,17 @@ def diffadv_cfl_step(D: float, vx: float, vy: float, dx: float, dy: float) -> fl
     """Explicit CFL step 2/rho of the periodic diffusion + first-order upwind
     stencil, rho = 4D/dx^2 + 4D/dy^2 + 2|vx|/dx + 2|vy|/dy."""
     rho = 4.0 * D / dx**2 + 4.0 * D / dy**2 + 2.0 * abs(vx) / dx + 2.0 * abs(vy) / dy
+    return 2.0 / rho
+
+
+def diffadv3_cfl_step(D: float, vx: float, vy: float, dx: float, dy: float) -> float:
+    """Explicit CFL step 2/rho with rho the Gershgorin bound (row sum of
+    moduli) of the periodic diffusion + third-order upwind stencil: per axis
+    with spacing d and speed |v|, the centre 2D/d^2 + |v|/(2d) and the
+    neighbours |D/d^2 - |v|/(3d)|, D/d^2 + |v|/d and |v|/(6d)."""
+    rho = 0.0
+    for v, d in ((abs(vx), dx), (abs(vy), dy)):
+        rho += 2.0 * D / d**2 + v / (2.0 * d) + abs(D / d**2 - v / (3.0 * d)) + D / d**2 + v / d + v / (6.0 * d)
     return 2.0 / rho
 
 
@@ -187,6 +201,31 @@ def batched_instances(count: int = 256, seed: int = 4,
                           "speed": speed, "angle": ang})
         out.append((p, gaussian(n, float(cx), float(cy))))
     return out
+
+
+def paper_linear(n: int = 8192, cfl_multiple: float = 1.0, source: bool = False,
+                 rtol: float = 1e-12) -> tuple[Problem, np.ndarray, np.ndarray | None]:
+    """The paper's linear test problems (Sec. 3, Problems I and II) on the
+    periodic square [-1, 1)^2 with n x n cells: u_t = lap(u) + nu (u_x + u_y)
+    with nu = 10, the Laplacian centred and the gradient third-order upwind;
+    u0 = 1 + exp(-((x + 0.5)^2 + (y + 0.5)^2)/0.01).  With ``source`` the
+    time-independent source S = exp(-((x + 0.4)^2 + (y - 0.6)^2)/0.05)
+    + exp(-((x - 0.25)^2 + (y + 0.1)^2)/0.04) is added (Problem II).
+    h = cfl_multiple x CFL; tolerance 1e-12 as in every run of the paper.
+    Returns (problem, u0, S or None)."""
+    L = 2.0
+    dx = L / n
+    nu = 10.0
+    x = -1.0 + np.arange(n, dtype=np.float64) * dx
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    u0 = 1.0 + np.exp(-((X + 0.5) ** 2 + (Y + 0.5) ** 2) / 0.01)
+    S = None
+    if source:
+        S = np.exp(-((X + 0.4) ** 2 + (Y - 0.6) ** 2) / 0.05) + np.exp(-((X - 0.25) ** 2 + (Y + 0.1) ** 2) / 0.04)
+    h = cfl_multiple * diffadv3_cfl_step(1.0, nu, nu, dx, dx)
+    p = Problem(DIFFADV3, n, D=1.0, vx=nu, vy=nu, h=h, cfl_multiple=cfl_multiple, length=L,
+                meta={"rtol": rtol, "atol": 0.0, "power_iters": 20, "problem": "II" if source else "I"})
+    return p, u0, S
 
 
 def learned_instance(index: int, seed0: int, sizes=(64, 128, 256)):

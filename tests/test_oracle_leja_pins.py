@@ -14,6 +14,9 @@ references that do not use Leja interpolation, and against invariants.
 * Power iteration: for a normal matrix the norm ratio never exceeds the
   spectral radius and never decreases.
 * EXPRB42: fourth order against an independent ODE solution (scipy DOP853).
+* Linear problems I and II (Sec. 3) with the third-order upwind gradient:
+  one step equals the exact solution of u_t = A u (+ S) over h, computed mode
+  by mode as e^{h lam} u_hat + h phi_1(h lam) S_hat.
 """
 import math
 
@@ -261,3 +264,16 @@ def test_exprb42_is_fourth_order():
     rates = [math.log2(a / b) for a, b in zip(errs, errs[1:])]
     assert errs[-1] < 1e-7
     assert min(rates) > 3.5, (errs, rates)
+
+
+@pytest.mark.parametrize("n,cfl,source", [(64, 10.0, False), (64, 10.0, True), (50, 100.0, True), (48, 1.0, True)])
+def test_linear_step_matches_exact_solution(n, cfl, source):
+    from oracle.exact import diffadv3_symbol, linear_step_fft
+    from oracle.phi_action import linear_step
+    p, u, S = W.paper_linear(n, cfl, source)
+    A = make_apply(p)
+    c, g = _bounds(A, u.shape)
+    r = linear_step(A, u, S, p.h, c, g, 1e-12, 0.0, max_iters=200)
+    assert r.status == "ok"
+    lam = diffadv3_symbol(n, n, p.D, p.vx, p.vy, p.dx, p.dy)
+    assert _rel(r.u_next, linear_step_fft(u, S, p.h, lam)) <= 1e-11
