@@ -62,7 +62,14 @@ typedef enum {
     LX_OP_DIFFADV2D = 1,
     /* F(u) = nu*lap(u) - (1/2)(d_x + d_y)(u^2), centred differences, and its
      * Jacobian J(u) w = nu*lap(w) - (d_x + d_y)(u w); Sec. 3, Eq. (5).       */
-    LX_OP_BURGERS2D = 2
+    LX_OP_BURGERS2D = 2,
+    /* A y = D*lap(y) + vx*Dx(y) + vy*Dy(y) with the paper's third-order
+     * upwind gradient (Sec. 3): per axis the four-point upwind-biased
+     * difference, exact for cubics, on points i-1..i+2 for v >= 0,
+     *   Dx y = (-y_{i+2} + 6 y_{i+1} - 3 y_i - 2 y_{i-1}) / (6 dx),
+     * and mirrored (points i-2..i+1) for v < 0; a radius-2 stencil.  Grids
+     * need sides >= 4.  Not accepted by the batched and learned calls.     */
+    LX_OP_DIFFADV2D_UP3 = 3
 } lx_op_kind;
 
 typedef enum {
@@ -218,6 +225,23 @@ lx_status lx_exprb_step(lx_ctx* ctx, const lx_operator* op, int scheme,
                         const double* d_u, double* d_u_out, double h,
                         double c, double gamma, const lx_leja_opts* o,
                         int* iters);
+
+/* One step of the linear problem u_t = A u + S (Sec. 3, Problems I and
+ * II) for LX_OP_DIFFADV2D or LX_OP_DIFFADV2D_UP3:
+ *   d_src == NULL:  u+ = exp(h A) u                       (Problem I)
+ *   otherwise:      u+ = u + h phi_1(h A) (A u + S)       (Problem II)
+ * d_src: device, nx*ny, the time-independent source, or NULL.  c and gamma
+ * describe the spectrum of A (lx_spectrum).  The phi action's stop rule
+ * measures that action alone (Problem II) or exp(h A) u (Problem I).
+ * iters: host, or NULL: iterations taken.  d_u_out must differ from d_u
+ * and d_src.  The first call with a source allocates one workspace vector
+ * of the context's n_max.  Errors as lx_phi_leja (after LX_ENOTCONV,
+ * d_u_out holds the step taken with the last polynomial); LX_EINVAL for
+ * another operator kind. */
+lx_status lx_linear_step(lx_ctx* ctx, const lx_operator* op, const double* d_u,
+                         const double* d_src, double* d_u_out, double h,
+                         double c, double gamma, const lx_leja_opts* o,
+                         int* iters);
 
 /* ---- batches of independent problems ---------------------------------- */
 

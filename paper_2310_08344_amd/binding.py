@@ -14,7 +14,7 @@ from dataclasses import dataclass
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lx.so")
 
 LX_OK, LX_EINVAL, LX_ENOMEM, LX_ENOTCONV, LX_ENONFINITE, LX_EDEVICE = range(6)
-LX_OP_DIFFADV2D, LX_OP_BURGERS2D = 1, 2
+LX_OP_DIFFADV2D, LX_OP_BURGERS2D, LX_OP_DIFFADV2D_UP3 = 1, 2, 3
 LX_FP64, LX_FP32_SWEEP = 0, 1
 LX_ROS_EULER = 2
 LX_EXPRB32 = 32
@@ -105,6 +105,9 @@ def _signatures(lib: C.CDLL) -> None:
     lib.lx_exprb_step.argtypes = [_P, C.POINTER(Operator), _I, _P, _P, _D, _D, _D,
                                   C.POINTER(LejaOpts), C.POINTER(_I)]
     lib.lx_exprb_step.restype = _I
+    lib.lx_linear_step.argtypes = [_P, C.POINTER(Operator), _P, _P, _P, _D, _D, _D, C.POINTER(LejaOpts),
+                                   C.POINTER(_I)]
+    lib.lx_linear_step.restype = _I
     lib.lx_phi_leja_batched.argtypes = [_P, _I, C.POINTER(Instance), _I, _D, C.POINTER(LejaOpts),
                                         C.POINTER(InstanceResult)]
     lib.lx_phi_leja_batched.restype = _I
@@ -154,7 +157,7 @@ def _signatures(lib: C.CDLL) -> None:
 
 
 EXPORTED = ["lx_create", "lx_destroy", "lx_set_stream", "lx_set_timing", "lx_last_error",
-            "lx_status_string", "lx_get_stats", "lx_spectrum", "lx_phi_leja", "lx_exprb_step",
+            "lx_status_string", "lx_get_stats", "lx_spectrum", "lx_phi_leja", "lx_exprb_step", "lx_linear_step",
             "lx_phi_leja_batched", "lx_tune", "lx_set_tile", "lx_set_depth", "lx_bandwidth_probe",
             "lx_predictor_create", "lx_predictor_destroy", "lx_predictor_state_size", "lx_predictor_set_scaling",
             "lx_predictor_get_state", "lx_predictor_set_state", "lx_predictor_save", "lx_predictor_load",
@@ -167,7 +170,8 @@ def make_operator(problem=None, *, kind=None, n=None, nx=None, ny=None, dx=None,
                   vx=0.0, vy=0.0, nu=0.0, prec=LX_FP64) -> Operator:
     """lx_operator from a workload Problem or from keywords."""
     if problem is not None:
-        kind = LX_OP_DIFFADV2D if problem.kind == "diffadv" else LX_OP_BURGERS2D
+        kind = {"diffadv": LX_OP_DIFFADV2D, "diffadv3": LX_OP_DIFFADV2D_UP3,
+                "burgers": LX_OP_BURGERS2D}[problem.kind]
         nx = ny = problem.n
         dx, dy = problem.dx, problem.dy
         D, vx, vy, nu = problem.D, problem.vx, problem.vy, problem.nu
@@ -395,6 +399,19 @@ class Context:
             self._check(st, allow=(LX_OK, LX_ENOTCONV))
         s = self.stats()
         return PhiResult(st, list(it), s["err"][:2], s)
+
+
+    def linear_step(self, op: Operator, u, u_out, h, c, gamma, source=None, rtol=1e-12, atol=0.0,
+                    max_iters=500, fp32_switch=1e4, raise_on_error=True) -> PhiResult:
+        """lx_linear_step: exp(hA)u, or u + h phi_1(hA)(Au + S) with a source."""
+        opts = LejaOpts(float(rtol), float(atol), int(max_iters), float(fp32_switch))
+        it = _I(0)
+        st = self.lib.c.lx_linear_step(self._h, C.byref(op), _ptr(u), _ptr(source) if source is not None else None,
+                                       _ptr(u_out), float(h), float(c), float(gamma), C.byref(opts), C.byref(it))
+        if raise_on_error:
+            self._check(st, allow=(LX_OK, LX_ENOTCONV))
+        s = self.stats()
+        return PhiResult(st, [it.value], s["err"][:1], s)
 
 
 def _fptr(t, cols):

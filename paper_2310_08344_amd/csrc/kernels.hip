@@ -190,6 +190,26 @@ __global__ void burgers_remainder_kernel(const double* __restrict__ u, const dou
     }
 }
 
+// out = h (A u + S), S optional: the vector whose phi_1 action advances the
+// linear problem with a source (Sec. 3, Problem II).  st is the stencil of
+// A with the radius-2 neighbours (zero for the five-point operator).
+__global__ void linear_rhs_kernel(const double* __restrict__ u, const double* __restrict__ S,
+                                  double* __restrict__ out, int nx, int ny, double cE, double cW, double cN,
+                                  double cS, double cC, double cE2, double cW2, double cN2, double cS2, double h) {
+    const long n = static_cast<long>(nx) * ny;
+    for (long t = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x; t < n;
+         t += static_cast<long>(gridDim.x) * blockDim.x) {
+        const int i = static_cast<int>(t % nx), j = static_cast<int>(t / nx);
+        const long r = static_cast<long>(j) * nx;
+        const long rs = static_cast<long>(wrap(j - 1, ny)) * nx, rn = static_cast<long>(wrap(j + 1, ny)) * nx;
+        const long rs2 = static_cast<long>(wrap(j - 2, ny)) * nx, rn2 = static_cast<long>(wrap(j + 2, ny)) * nx;
+        const int iw = wrap(i - 1, nx), ie = wrap(i + 1, nx), iw2 = wrap(i - 2, nx), ie2 = wrap(i + 2, nx);
+        const double Au = stencil_d3(cW, cE, cS, cN, cC, cW2, cE2, cS2, cN2, u[r + iw], u[r + ie], u[rs + i],
+                                     u[rn + i], u[r + i], u[r + iw2], u[r + ie2], u[rs2 + i], u[rn2 + i]);
+        out[t] = h * ((S != nullptr) ? Au + S[t] : Au);
+    }
+}
+
 // out = (x + y) + z, z optional (the stages of the integrators)
 __global__ void combine_kernel(const double* __restrict__ x, const double* __restrict__ y,
                                const double* __restrict__ z, double* __restrict__ out, long n) {
@@ -305,6 +325,7 @@ hipError_t launch_leja_sweep(int op, int K, bool fp32_capable, const Tile& t, co
     if (t.tx * t.ty != kBlockThreads || a.nb < 1) return hipErrorInvalidValue;
     if (op == kOpDiffAdv) return launch_sweep_k<kOpDiffAdv>(K, fp32_capable, t, a, m, s);
     if (op == kOpBurgersJ) return launch_sweep_k<kOpBurgersJ>(K, fp32_capable, t, a, m, s);
+    if (op == kOpDiffAdv3) return launch_sweep_k<kOpDiffAdv3>(K, fp32_capable, t, a, m, s);
     return hipErrorInvalidValue;
 }
 
@@ -312,6 +333,7 @@ hipError_t launch_power_sweep(int op, const Tile& t, const PowerArgs& a, int k, 
     if (t.tx * t.ty != kBlockThreads || a.nb < 1) return hipErrorInvalidValue;
     if (op == kOpDiffAdv) return launch_power_r<kOpDiffAdv>(t, a, k, s);
     if (op == kOpBurgersJ) return launch_power_r<kOpBurgersJ>(t, a, k, s);
+    if (op == kOpDiffAdv3) return launch_power_r<kOpDiffAdv3>(t, a, k, s);
     return hipErrorInvalidValue;
 }
 
@@ -363,6 +385,14 @@ hipError_t launch_burgers_remainder(const double* u, const double* a, double* ou
                                     double dx, double dy, double h, hipStream_t s) {
     hipLaunchKernelGGL(burgers_remainder_kernel, dim3(flat_blocks(static_cast<long>(nx) * ny)),
                        dim3(kBlockThreads), 0, s, u, a, out, nx, ny, nu, dx, dy, h);
+    return hipGetLastError();
+}
+
+hipError_t launch_linear_rhs(int op, const double* u, const double* S, double* out, int nx, int ny,
+                             const double (&st)[9], double h, hipStream_t s) {
+    if ((op != kOpDiffAdv && op != kOpDiffAdv3) || nx < 3 || ny < 3) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(linear_rhs_kernel, dim3(flat_blocks(static_cast<long>(nx) * ny)), dim3(kBlockThreads), 0, s,
+                       u, S, out, nx, ny, st[0], st[1], st[2], st[3], st[4], st[5], st[6], st[7], st[8], h);
     return hipGetLastError();
 }
 

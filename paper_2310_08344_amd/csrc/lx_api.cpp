@@ -60,16 +60,39 @@ lx_status fail(lx_ctx* ctx, lx_status s, const char* fmt, ...) {
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
+bool is_diffadv(int kind) { return kind == LX_OP_DIFFADV2D || kind == LX_OP_DIFFADV2D_UP3; }
+
+// the device kernels' operator code of an lx_op_kind
+int opcode_of(int kind) {
+    if (kind == LX_OP_DIFFADV2D) return lx::kOpDiffAdv;
+    if (kind == LX_OP_DIFFADV2D_UP3) return lx::kOpDiffAdv3;
+    return lx::kOpBurgersJ;
+}
+
+// the stencil of (A - c)/g as {E, W, N, S, C, E2, W2, N2, S2} for the
+// diffusion-advection operators (second neighbours 0 for the five-point one)
+void diffadv_stencil9(const lx_operator& op, double c, double g, double (&k9)[9]) {
+    if (op.kind == LX_OP_DIFFADV2D_UP3) {
+        lx::stencil_coeffs_up3(op.dx, op.dy, op.D, op.vx, op.vy, c, g, k9);
+    } else {
+        double k[5];
+        lx::stencil_coeffs(0, op.dx, op.dy, op.D, op.vx, op.vy, op.nu, c, g, k);
+        for (int i = 0; i < 9; ++i) k9[i] = i < 5 ? k[i] : 0.0;
+    }
+}
+
 lx_status check_op(lx_ctx* ctx, const lx_operator* op) {
     if (op == nullptr) return fail(ctx, LX_EINVAL, "operator is NULL");
-    if (op->kind != LX_OP_DIFFADV2D && op->kind != LX_OP_BURGERS2D)
+    if (op->kind != LX_OP_DIFFADV2D && op->kind != LX_OP_BURGERS2D && op->kind != LX_OP_DIFFADV2D_UP3)
         return fail(ctx, LX_EINVAL, "unknown operator kind %d", op->kind);
     if (op->nx < 3 || op->ny < 3) return fail(ctx, LX_EINVAL, "grid %dx%d: each side must be >= 3", op->nx, op->ny);
+    if (op->kind == LX_OP_DIFFADV2D_UP3 && (op->nx < 4 || op->ny < 4))
+        return fail(ctx, LX_EINVAL, "grid %dx%d: the third-order upwind operator needs sides >= 4", op->nx, op->ny);
     const size_t n = static_cast<size_t>(op->nx) * static_cast<size_t>(op->ny);
     if (n > ctx->n_max) return fail(ctx, LX_EINVAL, "grid of %zu points exceeds n_max %zu", n, ctx->n_max);
     if (!(op->dx > 0.0) || !(op->dy > 0.0) || !std::isfinite(op->dx) || !std::isfinite(op->dy))
         return fail(ctx, LX_EINVAL, "spacings must be finite and > 0");
-    if (op->kind == LX_OP_DIFFADV2D &&
+    if (is_diffadv(op->kind) &&
         (!(op->D >= 0.0) || !std::isfinite(op->D) || !std::isfinite(op->vx) || !std::isfinite(op->vy)))
         return fail(ctx, LX_EINVAL, "diffusion-advection needs finite D >= 0 and finite v");
     if (op->kind == LX_OP_BURGERS2D && (!(op->nu >= 0.0) || !std::isfinite(op->nu)))
@@ -157,15 +180,21 @@ Tile pick_tile(const lx_ctx* ctx, const lx_operator& op, int K, bool vec2_ok) {
 }
 
 void set_stencil(SweepArgs& a, const lx_operator& op, double c, double g) {
-    double k[5];
-    lx::stencil_coeffs(op.kind == LX_OP_DIFFADV2D ? 0 : 1, op.dx, op.dy, op.D, op.vx, op.vy, op.nu, c, g, k);
-    if (op.kind == LX_OP_DIFFADV2D) {
+    if (is_diffadv(op.kind)) {
+        double k[9];
+        diffadv_stencil9(op, c, g, k);
         a.aE = k[0];
         a.aW = k[1];
         a.aN = k[2];
         a.aS = k[3];
         a.aC = k[4];
+        a.aE2 = k[5];
+        a.aW2 = k[6];
+        a.aN2 = k[7];
+        a.aS2 = k[8];
     } else {
+        double k[5];
+        lx::stencil_coeffs(1, op.dx, op.dy, op.D, op.vx, op.vy, op.nu, c, g, k);
         a.kx = k[0];
         a.ky = k[1];
         a.gx = k[2];
@@ -233,6 +262,8 @@ void choose_depth(const lx_ctx* ctx, const lx_operator& op, int K, bool vec2_ok,
     }
     if (ctx->pair_th != 0) t.th = ctx->pair_th;
     if (ctx->pair_nb != 0) t.pnb = ctx->pair_nb;
+    // a radius-2 stencil stages 8 edge cells per row: tiles of at most 16 rows
+    if (op.kind == LX_OP_DIFFADV2D_UP3 && t.th > 16) t.th = 16;
 }
 
 // workgroups of a leja_pair grid: at most one per tile, a multiple of 8 once
@@ -331,7 +362,7 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
     a.coef = ctx->coef;
     a.xi = ctx->xi;
     a.ctl = ctx->ctl;
-    const int opcode = op.kind == LX_OP_DIFFADV2D ? lx::kOpDiffAdv : lx::kOpBurgersJ;
+    const int opcode = opcode_of(op.kind);
     s = ensure_partials(ctx, 2 * static_cast<size_t>(a.nb) * (1 + K) * (pair ? 2 : 1));
     if (s != LX_OK) return s;
     a.partials = ctx->partials;
@@ -414,7 +445,7 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
         // sweeps, and an even T left a deferred term for one more launch.
         // Per two-sweep launch: y_m in, y_{m+2} out, the Burgers state, and
         // per output still taking terms a read and a write of p (launch 0
-        // writes p without reading it; a base adds a read).
+        // writes p without reading it).
         const int T = fin.iter;
         const int F = (T + 1) / 2;
         const bool flush = T % 2 == 0;
@@ -625,16 +656,21 @@ lx_status lx_spectrum(lx_ctx* ctx, const lx_operator* op, const double* d_u, con
     a.tiles_x = (nx + t.cols() - 1) / t.cols();
     a.tiles_y = (ny + t.rows() - 1) / t.rows();
     a.nb = grid_size(t, a.tiles_x * a.tiles_y);
-    double pk[5];
-    lx::stencil_coeffs(op->kind == LX_OP_DIFFADV2D ? 0 : 1, op->dx, op->dy, op->D, op->vx, op->vy, op->nu, 0.0, 1.0,
-                       pk);
-    if (op->kind == LX_OP_DIFFADV2D) {
+    if (is_diffadv(op->kind)) {
+        double pk[9];
+        diffadv_stencil9(*op, 0.0, 1.0, pk);
         a.cE = pk[0];
         a.cW = pk[1];
         a.cN = pk[2];
         a.cS = pk[3];
         a.cC = pk[4];
+        a.cE2 = pk[5];
+        a.cW2 = pk[6];
+        a.cN2 = pk[7];
+        a.cS2 = pk[8];
     } else {
+        double pk[5];
+        lx::stencil_coeffs(1, op->dx, op->dy, op->D, op->vx, op->vy, op->nu, 0.0, 1.0, pk);
         a.kx = pk[0];
         a.ky = pk[1];
         a.gx = pk[2];
@@ -645,7 +681,7 @@ lx_status lx_spectrum(lx_ctx* ctx, const lx_operator* op, const double* d_u, con
     if (s != LX_OK) return s;
     a.partials = ctx->partials;
     a.ctl = ctx->ctl;
-    const int opcode = op->kind == LX_OP_DIFFADV2D ? lx::kOpDiffAdv : lx::kOpBurgersJ;
+    const int opcode = opcode_of(op->kind);
     // |x0|^2 partials into slot 1, read by sweep 0
     LX_HIP(ctx, lx::launch_power_norm(x0, N, a.nb, ctx->partials, ctx->stream));
     if (ctx->timing) {
@@ -724,6 +760,58 @@ lx_status lx_phi_leja(lx_ctx* ctx, const lx_operator* op, const double* d_u, con
         if (iters) iters[k] = ctx->stats.iters[k];
         if (err) err[k] = ctx->stats.err[k];
     }
+    return s;
+}
+
+lx_status lx_linear_step(lx_ctx* ctx, const lx_operator* op, const double* d_u, const double* d_src,
+                         double* d_u_out, double h, double c, double gamma, const lx_leja_opts* o, int* iters) {
+    if (ctx == nullptr) return LX_EINVAL;
+    ctx->stats = lx_stats{};
+    lx_status s = check_op(ctx, op);
+    if (s != LX_OK) return s;
+    if (!is_diffadv(op->kind)) return fail(ctx, LX_EINVAL, "linear steps need a diffusion-advection operator");
+    if (d_u == nullptr || d_u_out == nullptr || d_u == d_u_out || d_src == d_u_out)
+        return fail(ctx, LX_EINVAL, "d_u and d_u_out must be distinct, non-NULL, and d_u_out must differ from d_src");
+    s = check_shift(ctx, h, c, gamma);
+    if (s != LX_OK) return s;
+    lx_leja_opts oo;
+    s = check_leja_opts(ctx, o, &oo);
+    if (s != LX_OK) return s;
+    const int nx = op->nx, ny = op->ny;
+    const long N = static_cast<long>(nx) * ny;
+    LejaCall q{};
+    q.op = op;
+    q.u = nullptr;
+    q.K = 1;
+    q.alpha[0] = 1.0;
+    q.sigma[0] = 1.0;
+    q.out[0] = d_u_out;
+    q.h = h;
+    q.c = c;
+    q.gamma = gamma;
+    q.o = oo;
+    if (d_src == nullptr) {
+        // Problem I: the exp action of u
+        q.l[0] = 0;
+        q.v = d_u;
+        s = run_leja(ctx, q);
+    } else {
+        // Problem II: u + phi_1(h A) h (A u + S)
+        if (ctx->ws[0] == nullptr && hipMalloc(&ctx->ws[0], sizeof(double) * ctx->n_max) != hipSuccess)
+            return fail(ctx, LX_ENOMEM, "linear-step workspace allocation failed");
+        double k9[9];
+        diffadv_stencil9(*op, 0.0, 1.0, k9);
+        LX_HIP(ctx, lx::launch_linear_rhs(opcode_of(op->kind), d_u, d_src, ctx->ws[0], nx, ny, k9, h, ctx->stream));
+        q.l[0] = 1;
+        q.v = ctx->ws[0];
+        s = run_leja(ctx, q);
+        if (s == LX_OK || s == LX_ENOTCONV) {
+            // after LX_ENOTCONV too: u plus the last polynomial
+            LX_HIP(ctx, lx::launch_combine(d_u, d_u_out, nullptr, d_u_out, N, ctx->stream));
+            LX_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        }
+    }
+    if (iters) *iters = ctx->stats.iters[0];
     return s;
 }
 
@@ -952,7 +1040,7 @@ lx_status lx_tune(lx_ctx* ctx, const lx_operator* op, int K, int sweeps, char* r
     std::string rep;
     double best_us = 1e300;
     Tile best = cands.empty() ? choose_tile(nx, ny, vec2_ok) : cands[0];
-    const int opcode = op->kind == LX_OP_DIFFADV2D ? lx::kOpDiffAdv : lx::kOpBurgersJ;
+    const int opcode = opcode_of(op->kind);
     const bool fp32 = op->prec == LX_FP32_SWEEP;
     for (const Tile& t : cands) {
         SweepArgs a{};
@@ -1002,6 +1090,7 @@ lx_status lx_tune(lx_ctx* ctx, const lx_operator* op, int K, int sweeps, char* r
     if (op->prec == LX_FP64 && nx % 2 == 0) {
         const int tiles_x = (nx + 127) / 128;
         for (int th : {8, 16, 32}) {
+            if (th > 16 && op->kind == LX_OP_DIFFADV2D_UP3) continue;   // radius 2: at most 16 rows
             const int tiles = tiles_x * ((ny + th - 1) / th);
             for (int pnb : {0, 2048, 1536, 1024, 768, 512, 256}) {
                 if (pnb != 0 && pnb >= tiles) continue;

@@ -129,6 +129,8 @@ extern "C" lx_status lx_phi_leja_batched(lx_ctx* ctx, int n, const lx_instance* 
         lx_status s = lx_internal_check_op(ctx, &q.op, static_cast<size_t>(1) << 40);
         if (s != LX_OK) return lx_internal_fail(ctx, s, "instance %d: %s", i, lx_last_error(ctx));
         if (q.op.prec != LX_FP64) return lx_internal_fail(ctx, LX_EINVAL, "instance %d: batches run in FP64", i);
+        if (q.op.kind != LX_OP_DIFFADV2D && q.op.kind != LX_OP_BURGERS2D)
+            return lx_internal_fail(ctx, LX_EINVAL, "instance %d: batches take the five-point operators", i);
         if (q.d_v == nullptr || q.d_out == nullptr || q.d_out == q.d_v)
             return lx_internal_fail(ctx, LX_EINVAL, "instance %d: needs distinct d_v and d_out", i);
         if (q.op.kind == LX_OP_BURGERS2D && q.d_u == nullptr)

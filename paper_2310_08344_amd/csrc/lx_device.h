@@ -59,6 +59,8 @@ struct SweepArgs {
     // diffusion-advection: stencil coefficients divided by gamma; aC holds
     // (c_C - c)/gamma, the sweep subtracts xi_m
     double aE, aW, aN, aS, aC;
+    // third-order upwind advection: the second neighbours (one of each pair is 0)
+    double aE2, aW2, aN2, aS2;
     // Burgers Jacobian: nu/(gamma dx^2), nu/(gamma dy^2), 1/(2 gamma dx),
     // 1/(2 gamma dy), and the centre (-2 kx - 2 ky - c/gamma)
     double kx, ky, gx, gy, kC;
@@ -79,6 +81,7 @@ struct PowerArgs {
     int tiles_x, tiles_y;
     int nb;
     double cE, cW, cN, cS, cC;     // diffusion-advection stencil
+    double cE2, cW2, cN2, cS2;     // its second neighbours (third-order upwind)
     double kx, ky, gx, gy;         // Burgers: nu/dx^2, nu/dy^2, 1/(2dx), 1/(2dy)
     const double* in;
     double* out;
@@ -87,7 +90,9 @@ struct PowerArgs {
     LoopCtl* ctl;
 };
 
-enum OpCode { kOpDiffAdv = 0, kOpBurgersJ = 1 };
+// kOpDiffAdv3: diffusion with third-order upwind advection, a radius-2 cross
+// stencil (the others have radius 1)
+enum OpCode { kOpDiffAdv = 0, kOpBurgersJ = 1, kOpDiffAdv3 = 2 };
 
 // One instance of a batch: its operator, vectors and its share of the
 // workgroups of every batched launch.  c, gamma and rho are written by the
@@ -137,6 +142,11 @@ hipError_t launch_burgers_hF(const double* u, double* out, int nx, int ny, doubl
 // h [N(u + a) - N(u)], N(w) = F(w) - J(u) w
 hipError_t launch_burgers_remainder(const double* u, const double* a, double* out, int nx, int ny,
                                     double nu, double dx, double dy, double h, hipStream_t s);
+// out = h (A u + S) for the linear operators (S may be NULL); st holds the
+// stencil of A as {cE, cW, cN, cS, cC, cE2, cW2, cN2, cS2} (the last four 0
+// for kOpDiffAdv)
+hipError_t launch_linear_rhs(int op, const double* u, const double* S, double* out, int nx, int ny,
+                             const double (&st)[9], double h, hipStream_t s);
 // out = (x + y) + z (z may be NULL)
 hipError_t launch_combine(const double* x, const double* y, const double* z, double* out, long n, hipStream_t s);
 

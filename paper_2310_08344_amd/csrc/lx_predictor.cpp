@@ -278,7 +278,8 @@ lx_status lx_instance_features(lx_ctx* ctx, int n, const lx_instance* inst, floa
     std::vector<lx::FeatureInst> f(static_cast<size_t>(n));
     for (int i = 0; i < n; ++i) {
         const lx_instance& q = inst[i];
-        if (q.op.nx < 1 || q.op.ny < 1 || !(q.op.dx > 0.0) || !(q.h > 0.0) || q.d_v == nullptr ||
+        if ((q.op.kind != LX_OP_DIFFADV2D && q.op.kind != LX_OP_BURGERS2D) || q.op.nx < 1 || q.op.ny < 1 ||
+            !(q.op.dx > 0.0) || !(q.h > 0.0) || q.d_v == nullptr ||
             (q.op.kind == LX_OP_BURGERS2D && (q.d_u == nullptr || !(q.op.nu > 0.0))) ||
             (q.op.kind == LX_OP_DIFFADV2D && !(q.op.D > 0.0)))
             return lx_internal_fail(ctx, LX_EINVAL, "features: instance %d", i);

@@ -30,12 +30,14 @@
 // the end while workgroups of the flushing launch may still be starting.
 //
 // Tiles are 128 columns (64 lanes x 2) by TH rows; a workgroup is four
-// wavefronts.  LDS holds y_m on rows -2..TH+1 and columns -2..129 of the
-// tile (and the Burgers state u on the same cells) and y_{m+1} on rows
-// -1..TH and columns -1..128.  Global indices wrap periodically, so cells
-// of a tile past the grid's edge hold the wrapped values and the halo of the
-// last real column is exactly the periodic neighbour; such cells are
-// computed but never stored or counted.  Requires nx even (16-byte pairs).
+// wavefronts.  For a stencil of radius R (1 for the five-point operators, 2
+// for third-order upwind advection) LDS holds y_m on rows -2R..TH+2R-1 and
+// columns -2R..127+2R of the tile (and the Burgers state u on the same
+// cells) and y_{m+1} on rows -R..TH+R-1 and columns -R..127+R.  Global
+// indices wrap periodically, so cells of a tile past the grid's edge hold
+// the wrapped values and the halo of the last real column is exactly the
+// periodic neighbour; such cells are computed but never stored or counted.
+// Requires nx even (16-byte pairs).
 #include <hip/hip_runtime.h>
 
 #include "lx_device.h"
@@ -47,8 +49,18 @@ namespace {
 using namespace dev;
 
 constexpr int kPairTW = 128;                // tile columns
-constexpr int kPairPitch = kPairTW + 4;     // LDS row pitch in doubles (16-byte multiple)
 constexpr int kPairWaves = kBlockThreads / 64;
+
+template <int OP>
+constexpr int radius() {
+    return OP == kOpDiffAdv3 ? 2 : 1;
+}
+// LDS row pitch in doubles: the tile and a 2R halo on each side (a 16-byte
+// multiple)
+template <int R>
+constexpr int pitch() {
+    return kPairTW + 4 * R;
+}
 
 // the outputs are read and written once per launch: streaming
 // (nontemporal) accesses that leave the caches to the basis vector
@@ -67,20 +79,28 @@ __device__ __forceinline__ void st_stream(double* p, const double2 t) {
 
 template <int OP, int TH>
 struct PairLds {
-    double ym[TH + 4][kPairPitch];          // y_m: row r at [r + 2], column c at [c + 2]
-    double y1[TH + 2][kPairPitch];          // y_{m+1}: row r at [r + 1], column c at [c + 2]
-    double u[TH + 4][kPairPitch];           // Burgers state, laid out as ym
+    static constexpr int R = radius<OP>();
+    double ym[TH + 4 * R][pitch<R>()];      // y_m: row r at [r + 2R], column c at [c + 2R]
+    double y1[TH + 2 * R][pitch<R>()];      // y_{m+1}: row r at [r + R], column c at [c + 2R]
+    double u[TH + 4 * R][pitch<R>()];       // Burgers state, laid out as ym
 };
 template <int TH>
 struct PairLds<kOpDiffAdv, TH> {
-    double ym[TH + 4][kPairPitch];
-    double y1[TH + 2][kPairPitch];
+    double ym[TH + 4][pitch<1>()];
+    double y1[TH + 2][pitch<1>()];
+};
+template <int TH>
+struct PairLds<kOpDiffAdv3, TH> {
+    double ym[TH + 8][pitch<2>()];
+    double y1[TH + 4][pitch<2>()];
 };
 
-// The stencil of (A - c)/gamma: aW, aE, aS, aN, aC (diffusion-advection) or
-// kx, ky, gx, gy, kC (Burgers).
+// The stencil of (A - c)/gamma: aW, aE, aS, aN, aC (diffusion-advection;
+// third-order upwind adds aW2, aE2, aS2, aN2 in e0..e3) or kx, ky, gx, gy, kC
+// (Burgers).
 struct Sten {
     double c0, c1, c2, c3, c4;
+    double e0, e1, e2, e3;
 };
 
 // What the tile code reads of the launch arguments, held in registers for
@@ -104,9 +124,11 @@ __device__ __forceinline__ TileArgs<K> tile_args(const SweepArgs& a) {
     t.tiles_x = a.tiles_x;
     t.ld = a.ld;
     if constexpr (OP == kOpDiffAdv) {
-        t.st = Sten{a.aW, a.aE, a.aS, a.aN, a.aC};
+        t.st = Sten{a.aW, a.aE, a.aS, a.aN, a.aC, 0.0, 0.0, 0.0, 0.0};
+    } else if constexpr (OP == kOpDiffAdv3) {
+        t.st = Sten{a.aW, a.aE, a.aS, a.aN, a.aC, a.aW2, a.aE2, a.aS2, a.aN2};
     } else {
-        t.st = Sten{a.kx, a.ky, a.gx, a.gy, a.kC};
+        t.st = Sten{a.kx, a.ky, a.gx, a.gy, a.kC, 0.0, 0.0, 0.0, 0.0};
     }
     t.u = a.u;
     t.coef = a.coef;
@@ -166,38 +188,70 @@ __device__ __forceinline__ double shifted_one(const Sten& a, const double shift,
     }
 }
 
+// the radius-2 operator on LDS row ce (rows u2, u1 below and d1, d2 above)
+// at the column pair j, j+1 (j even), and at the single column j
+__device__ __forceinline__ void shifted_pair3(const Sten& a, const double shift, const double* u2, const double* u1,
+                                              const double* ce, const double* d1, const double* d2, const int j,
+                                              double (&o)[2]) {
+    const double2 c2 = *reinterpret_cast<const double2*>(ce + j);
+    const double2 s1 = *reinterpret_cast<const double2*>(u1 + j);
+    const double2 s2 = *reinterpret_cast<const double2*>(u2 + j);
+    const double2 n1 = *reinterpret_cast<const double2*>(d1 + j);
+    const double2 n2 = *reinterpret_cast<const double2*>(d2 + j);
+    const double l1 = ce[j - 1], l2 = ce[j - 2], r1 = ce[j + 2], r2 = ce[j + 3];
+    const double cc = a.c4 - shift;
+    o[0] = stencil_d3(a.c0, a.c1, a.c2, a.c3, cc, a.e0, a.e1, a.e2, a.e3, l1, c2.y, s1.x, n1.x, c2.x, l2, r1, s2.x,
+                      n2.x);
+    o[1] = stencil_d3(a.c0, a.c1, a.c2, a.c3, cc, a.e0, a.e1, a.e2, a.e3, c2.x, r1, s1.y, n1.y, c2.y, l1, r2, s2.y,
+                      n2.y);
+}
+
+__device__ __forceinline__ double shifted_one3(const Sten& a, const double shift, const double* u2, const double* u1,
+                                               const double* ce, const double* d1, const double* d2, const int j) {
+    return stencil_d3(a.c0, a.c1, a.c2, a.c3, a.c4 - shift, a.e0, a.e1, a.e2, a.e3, ce[j - 1], ce[j + 1], u1[j], d1[j],
+                      ce[j], ce[j - 2], ce[j + 2], u2[j], d2[j]);
+}
+
 // y_m of one tile as this thread stages it (rows -2..TH+1 of its column
 // pair, and one halo value), loaded a tile ahead of its LDS staging so that
 // the loads overlap the previous tile's arithmetic
-template <int TH>
+template <int TH, int R>
 struct TileY {
     // the two columns of each staged row, kept as two scalar arrays (an
     // array of double2 this long is not promoted to registers)
-    double x[(TH + 4) / kPairWaves], y[(TH + 4) / kPairWaves];
+    double x[(TH + 4 * R) / kPairWaves], y[(TH + 4 * R) / kPairWaves];
     double edge;
 };
 
-template <int K, int TH>
-__device__ __forceinline__ TileY<TH> load_tile_y(const TileArgs<K>& a, const double* __restrict__ yin,
-                                                 const int tile) {
-    TileY<TH> r;
+// Edge cells of y_m: 4R per staged row (LDS columns 0..2R-1 and
+// 128+2R..127+4R), one per thread; thread e covers row e / 4R.
+template <int TH, int R>
+constexpr bool edges_fit() {
+    return (TH + 4 * R) * 4 * R <= kBlockThreads;
+}
+
+template <int K, int TH, int R>
+__device__ __forceinline__ TileY<TH, R> load_tile_y(const TileArgs<K>& a, const double* __restrict__ yin,
+                                                    const int tile) {
+    TileY<TH, R> r;
     r.edge = 0.0;
     static_assert(TH % kPairWaves == 0, "tile rows must be a multiple of the wavefronts");
+    static_assert(edges_fit<TH, R>(), "one edge cell per thread");
     const int nx = a.nx, ny = a.ny;
     const int x0 = (tile % a.tiles_x) * kPairTW, y0 = (tile / a.tiles_x) * TH;
     const int tid = flat_tid(), lane = tid & 63, w = tid >> 6;
     const int gc = wrap(x0 + 2 * lane, nx);       // even: nx and x0 are even
 #pragma unroll
-    for (int i = 0; i < (TH + 4) / kPairWaves; ++i) {
-        const long g = wrap(y0 - 2 + w + i * kPairWaves, ny) * static_cast<long>(nx) + gc;
+    for (int i = 0; i < (TH + 4 * R) / kPairWaves; ++i) {
+        const long g = wrap(y0 - 2 * R + w + i * kPairWaves, ny) * static_cast<long>(nx) + gc;
         const double2 t = *reinterpret_cast<const double2*>(yin + g);
         r.x[i] = t.x;
         r.y[i] = t.y;
     }
-    if (tid < (TH + 4) * 4) {
-        const int q = tid & 3;
-        const int ec = (q < 2) ? q : kPairTW + q;
-        r.edge = yin[wrap(y0 - 2 + (tid >> 2), ny) * static_cast<long>(nx) + wrap(x0 + ec - 2, nx)];
+    if (tid < (TH + 4 * R) * 4 * R) {
+        const int q = tid % (4 * R);
+        const int ec = (q < 2 * R) ? q : kPairTW + q;
+        r.edge = yin[wrap(y0 - 2 * R + tid / (4 * R), ny) * static_cast<long>(nx) + wrap(x0 + ec - 2 * R, nx)];
     }
     return r;
 }
@@ -206,29 +260,30 @@ template <int OP, int K, int TH>
 __device__ __forceinline__ void pair_tile(const TileArgs<K>& a, PairLds<OP, TH>& S, const double* __restrict__ yin,
                                           double* __restrict__ yout, const int m, const bool first,
                                           const int (&add0)[K], const int (&add1)[K], double& sy1, double& sy2,
-                                          double (&sp1)[K], double (&sp2)[K], const int tile, TileY<TH>& ty,
-                                          const int next) {
+                                          double (&sp1)[K], double (&sp2)[K], const int tile,
+                                          TileY<TH, radius<OP>()>& ty, const int next) {
+    constexpr int R = radius<OP>();
     constexpr int RW = TH / kPairWaves;           // tile rows per wavefront
     const int nx = a.nx, ny = a.ny;
     const int x0 = (tile % a.tiles_x) * kPairTW, y0 = (tile / a.tiles_x) * TH;
     const int tid = flat_tid(), lane = tid & 63, w = tid >> 6;
     const double* __restrict__ uu = a.u;
-    const int j = 2 + 2 * lane;                   // LDS column of this lane's pair
+    const int j = 2 * R + 2 * lane;               // LDS column of this lane's pair
     const int gcol = x0 + 2 * lane;
     const int gc = wrap(gcol, nx);                // even: nx and x0 are even
     const double xm = a.xi[m], xm1 = a.xi[m + 1];
 
-    // ---- y_m (and u) on rows -2..TH+1, columns -2..129; the outputs ----
-    constexpr int RM = (TH + 4) / kPairWaves;     // staged rows of y_m per wavefront
+    // ---- y_m (and u) on rows -2R..TH+2R-1, columns -2R..127+2R; the outputs ----
+    constexpr int RM = (TH + 4 * R) / kPairWaves; // staged rows of y_m per wavefront
     double uedge = 0.0;
     int er = 0, ec = 0;
-    const bool has_edge = tid < (TH + 4) * 4;
+    const bool has_edge = tid < (TH + 4 * R) * 4 * R;
     if (has_edge) {
-        er = tid >> 2;
-        const int q = tid & 3;
-        ec = (q < 2) ? q : kPairTW + q;           // LDS columns 0, 1, 130, 131
+        er = tid / (4 * R);
+        const int q = tid % (4 * R);
+        ec = (q < 2 * R) ? q : kPairTW + q;       // LDS columns 0..2R-1, 128+2R..127+4R
         if constexpr (OP == kOpBurgersJ)
-            uedge = uu[wrap(y0 - 2 + er, ny) * static_cast<long>(nx) + wrap(x0 + ec - 2, nx)];
+            uedge = uu[wrap(y0 - 2 * R + er, ny) * static_cast<long>(nx) + wrap(x0 + ec - 2 * R, nx)];
     }
     // outputs of this thread's rows, fetched while the tile is staged
     double2 pv[K][RW];
@@ -249,7 +304,7 @@ __device__ __forceinline__ void pair_tile(const TileArgs<K>& a, PairLds<OP, TH>&
 #pragma unroll
         for (int i = 0; i < RM; ++i) {
             const int r = w + i * kPairWaves;
-            const long g = wrap(y0 - 2 + r, ny) * static_cast<long>(nx) + gc;
+            const long g = wrap(y0 - 2 * R + r, ny) * static_cast<long>(nx) + gc;
             *reinterpret_cast<double2*>(&S.u[r][j]) = *reinterpret_cast<const double2*>(uu + g);
         }
     }
@@ -266,15 +321,18 @@ __device__ __forceinline__ void pair_tile(const TileArgs<K>& a, PairLds<OP, TH>&
         if constexpr (OP == kOpBurgersJ) S.u[er][ec] = uedge;
     }
     __syncthreads();
-    ty = load_tile_y<K, TH>(a, yin, next);   // the next tile's y_m, in flight during this one
+    ty = load_tile_y<K, TH, R>(a, yin, next);   // the next tile's y_m, in flight during this one
 
-    // ---- y_{m+1} on rows -1..TH, columns -1..128 ----
+    // ---- y_{m+1} on rows -R..TH+R-1, columns -R..127+R: LDS row r of y1
+    // is centred on LDS row r + R of ym ----
 #pragma unroll
-    for (int i = 0; i < (TH + 2 + kPairWaves - 1) / kPairWaves; ++i) {
+    for (int i = 0; i < (TH + 2 * R + kPairWaves - 1) / kPairWaves; ++i) {
         const int r = w + i * kPairWaves;
-        if (r >= TH + 2) break;
+        if (r >= TH + 2 * R) break;
         double o[2];
-        if constexpr (OP == kOpBurgersJ) {
+        if constexpr (OP == kOpDiffAdv3) {
+            shifted_pair3(a.st, xm, S.ym[r], S.ym[r + 1], S.ym[r + 2], S.ym[r + 3], S.ym[r + 4], j, o);
+        } else if constexpr (OP == kOpBurgersJ) {
             shifted_pair<OP>(a.st, xm, S.ym[r], S.ym[r + 1], S.ym[r + 2], S.u[r], S.u[r + 1], S.u[r + 2], j, o);
         } else {
             shifted_pair<OP>(a.st, xm, S.ym[r], S.ym[r + 1], S.ym[r + 2], nullptr, nullptr, nullptr, j, o);
@@ -284,10 +342,14 @@ __device__ __forceinline__ void pair_tile(const TileArgs<K>& a, PairLds<OP, TH>&
         t.y = o[1];
         *reinterpret_cast<double2*>(&S.y1[r][j]) = t;
     }
-    if (tid < (TH + 2) * 2) {
-        const int r = tid >> 1;
-        const int lc = (tid & 1) ? kPairTW + 2 : 1;   // columns 128 and -1
-        if constexpr (OP == kOpBurgersJ) {
+    // the R columns on each side of the tile: LDS columns R..2R-1 and
+    // 128+2R..127+3R
+    if (tid < (TH + 2 * R) * 2 * R) {
+        const int r = tid / (2 * R), q = tid % (2 * R);
+        const int lc = (q < R) ? R + q : kPairTW + R + q;
+        if constexpr (OP == kOpDiffAdv3) {
+            S.y1[r][lc] = shifted_one3(a.st, xm, S.ym[r], S.ym[r + 1], S.ym[r + 2], S.ym[r + 3], S.ym[r + 4], lc);
+        } else if constexpr (OP == kOpBurgersJ) {
             S.y1[r][lc] = shifted_one<OP>(a.st, xm, S.ym[r], S.ym[r + 1], S.ym[r + 2], S.u[r], S.u[r + 1], S.u[r + 2], lc);
         } else {
             S.y1[r][lc] = shifted_one<OP>(a.st, xm, S.ym[r], S.ym[r + 1], S.ym[r + 2], nullptr, nullptr, nullptr, lc);
@@ -301,15 +363,17 @@ __device__ __forceinline__ void pair_tile(const TileArgs<K>& a, PairLds<OP, TH>&
         const int r = w + i * kPairWaves;
         const int grow = y0 + r;
         double o[2];
-        if constexpr (OP == kOpBurgersJ) {
+        if constexpr (OP == kOpDiffAdv3) {
+            shifted_pair3(a.st, xm1, S.y1[r], S.y1[r + 1], S.y1[r + 2], S.y1[r + 3], S.y1[r + 4], j, o);
+        } else if constexpr (OP == kOpBurgersJ) {
             shifted_pair<OP>(a.st, xm1, S.y1[r], S.y1[r + 1], S.y1[r + 2], S.u[r + 1], S.u[r + 2], S.u[r + 3], j, o);
         } else {
             shifted_pair<OP>(a.st, xm1, S.y1[r], S.y1[r + 1], S.y1[r + 2], nullptr, nullptr, nullptr, j, o);
         }
         if (gcol < nx && grow < ny) {
             const long idx = static_cast<long>(grow) * nx + gcol;
-            const double2 c1 = *reinterpret_cast<const double2*>(&S.y1[r + 1][j]);
-            const double2 c0 = *reinterpret_cast<const double2*>(&S.ym[r + 2][j]);
+            const double2 c1 = *reinterpret_cast<const double2*>(&S.y1[r + R][j]);
+            const double2 c0 = *reinterpret_cast<const double2*>(&S.ym[r + 2 * R][j]);
             double2 t;
             t.x = o[0];
             t.y = o[1];
@@ -469,8 +533,8 @@ __device__ __forceinline__ void pair_launch(const SweepArgs& a, const int L, con
         step = 1;
         end = static_cast<int>((static_cast<long>(wg + 1) * T) / a.nb);
     }
-    TileY<TH> ty;
-    if (first < end) ty = load_tile_y<K, TH>(ta, yin, first);
+    TileY<TH, radius<OP>()> ty;
+    if (first < end) ty = load_tile_y<K, TH, radius<OP>()>(ta, yin, first);
     for (int t = first; t < end; t += step) {
         // after the last tile, reload it (from L2) rather than branch: the
         // registers then stay registers
@@ -563,7 +627,13 @@ hipError_t launch_pair_th(int th, const SweepArgs& a, int L, hipStream_t s) {
     switch (th) {
         case 8: hipLaunchKernelGGL((leja_pair<OP, K, 8>), grid, block, 0, s, a, L); break;
         case 16: hipLaunchKernelGGL((leja_pair<OP, K, 16>), grid, block, 0, s, a, L); break;
-        case 32: hipLaunchKernelGGL((leja_pair<OP, K, 32>), grid, block, 0, s, a, L); break;
+        case 32:
+            if constexpr (edges_fit<32, radius<OP>()>()) {
+                hipLaunchKernelGGL((leja_pair<OP, K, 32>), grid, block, 0, s, a, L);
+            } else {
+                return hipErrorInvalidValue;
+            }
+            break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -611,6 +681,10 @@ hipError_t launch_leja_pair(int op, int K, int th, const SweepArgs& a, int L, hi
         return hipErrorInvalidValue;
     if (op == kOpDiffAdv) return launch_pair_k<kOpDiffAdv>(K, th, a, L, s);
     if (op == kOpBurgersJ) return launch_pair_k<kOpBurgersJ>(K, th, a, L, s);
+    if (op == kOpDiffAdv3) {
+        if (a.nx < 4 || a.ny < 4) return hipErrorInvalidValue;   // wrap() reaches back 2R = 4 cells
+        return launch_pair_k<kOpDiffAdv3>(K, th, a, L, s);
+    }
     return hipErrorInvalidValue;
 }
 

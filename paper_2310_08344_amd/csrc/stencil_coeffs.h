@@ -1,4 +1,4 @@
-// Coefficients of the two periodic five-point operators, shared by the host
+// Coefficients of the periodic stencil operators, shared by the host
 // and by device code that derives them from a shift computed on the device.
 //
 // Diffusion-advection (second-order diffusion, first-order upwind
@@ -39,6 +39,46 @@ LX_SHD void stencil_coeffs(int kind, double dx, double dy, double D, double vx, 
         out[3] = 1.0 / (2.0 * g * dy);
         out[4] = -2.0 * out[0] - 2.0 * out[1] - c / g;
     }
+}
+
+// Diffusion with third-order upwind advection (the gradient of Sec. 3):
+// per axis with spacing d, speed v and Dd = D/d^2, the four-point
+// upwind-biased first difference (exact for cubics) gives the upwind
+// neighbour Dd + |v|/d, the downwind one Dd - |v|/(3d), the second upwind
+// neighbour -|v|/(6d), the second downwind one 0 and the centre
+// -2 Dd - |v|/(2d); "upwind" is the forward side for v >= 0.
+//     out = {cE, cW, cN, cS, cC, cE2, cW2, cN2, cS2} of (A - c)/g.
+LX_SHD void stencil_coeffs_up3(double dx, double dy, double D, double vx, double vy, double c, double g,
+                               double (&out)[9]) {
+    double ax[4], ay[4];   // {E, W, E2, W2} along x, {N, S, N2, S2} along y
+    const double sp[2] = {vx, vy}, dd[2] = {dx, dy};
+    for (int t = 0; t < 2; ++t) {
+        double* o = t == 0 ? ax : ay;
+        const double d = dd[t], a = sp[t] < 0.0 ? -sp[t] : sp[t], Dd = D / (d * d);
+        const double up = Dd + a / d, down = Dd - a / (3.0 * d), up2 = -a / (6.0 * d);
+        if (sp[t] >= 0.0) {
+            o[0] = up;
+            o[1] = down;
+            o[2] = up2;
+            o[3] = 0.0;
+        } else {
+            o[0] = down;
+            o[1] = up;
+            o[2] = 0.0;
+            o[3] = up2;
+        }
+    }
+    const double cC = -(2.0 * D / (dx * dx) + 2.0 * D / (dy * dy)) -
+                      ((vx < 0.0 ? -vx : vx) / (2.0 * dx) + (vy < 0.0 ? -vy : vy) / (2.0 * dy));
+    out[0] = ax[0] / g;
+    out[1] = ax[1] / g;
+    out[2] = ay[0] / g;
+    out[3] = ay[1] / g;
+    out[4] = (cC - c) / g;
+    out[5] = ax[2] / g;
+    out[6] = ax[3] / g;
+    out[7] = ay[2] / g;
+    out[8] = ay[3] / g;
 }
 
 }  // namespace lx

@@ -179,6 +179,19 @@ __device__ __forceinline__ T stencil_da(T cW, T cE, T cS, T cN, T cC, T W, T E, 
     return fma(cN, N, fma(cS, S, fma(cE, E, fma(cW, W, cC * C))));
 }
 
+// radius-2 cross stencil (diffusion + third-order upwind advection): the
+// five-point part, then the second neighbours W2, E2, S2, N2
+template <typename T>
+__device__ __forceinline__ T stencil_d3(T cW, T cE, T cS, T cN, T cC, T cW2, T cE2, T cS2, T cN2, T W, T E, T S, T N,
+                                        T C, T W2, T E2, T S2, T N2) {
+#pragma clang fp contract(off)
+    T r = fma(cN, N, fma(cS, S, fma(cE, E, fma(cW, W, cC * C))));
+    r = fma(cW2, W2, r);
+    r = fma(cE2, E2, r);
+    r = fma(cS2, S2, r);
+    return fma(cN2, N2, r);
+}
+
 // Burgers Jacobian: kx (E + W) + ky (N + S) - gx (uE E - uW W) - gy (uN N - uS S) + kc C
 template <typename T>
 __device__ __forceinline__ T stencil_bu(T kx, T ky, T gx, T gy, T kc, T W, T E, T S, T N, T C, T uW, T uE, T uS,
@@ -207,6 +220,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int m, cons
     const int c0 = colok ? col : 0;
     const int cl = (c0 == 0) ? nx - 1 : c0 - 1;
     const int cr = (c0 + V >= nx) ? c0 + V - nx : c0 + V;
+    // second neighbours of the radius-2 stencil (nx >= 4)
+    const int cl2 = wrap(c0 - 2, nx), cr2 = wrap(c0 + V + 1, nx);
     const int row0 = tile_y * static_cast<int>(blockDim.y) * RY + static_cast<int>(threadIdx.y) * RY;
 
     const TI* __restrict__ yin;
@@ -232,8 +247,13 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int m, cons
 
     AT up[V], cen[V], dn[V];
     AT uup[V], ucen[V], udn[V];
+    AT up2[V], dn2[V];       // radius-2 stencil: rows two below and two above
     ldv<V>(yin + static_cast<long>(wrap(row0 - 1, ny)) * nx + c0, up);
     ldv<V>(yin + static_cast<long>(wrap(row0, ny)) * nx + c0, cen);
+    if constexpr (OP == kOpDiffAdv3) {
+        ldv<V>(yin + static_cast<long>(wrap(row0 - 2, ny)) * nx + c0, up2);
+        ldv<V>(yin + static_cast<long>(wrap(row0 + 1, ny)) * nx + c0, dn);
+    }
     if constexpr (OP == kOpBurgersJ) {
         if constexpr (sizeof(AT) == sizeof(double)) {
             ldv<V>(uu + static_cast<long>(wrap(row0 - 1, ny)) * nx + c0, uup);
@@ -250,11 +270,32 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int m, cons
         const bool ok = colok && row < ny;
         const long rw = wrap(row, ny);
         const long rn = wrap(row + 1, ny);
-        ldv<V>(yin + rn * nx + c0, dn);
+        if constexpr (OP == kOpDiffAdv3) {
+            ldv<V>(yin + static_cast<long>(wrap(row + 2, ny)) * nx + c0, dn2);
+        } else {
+            ldv<V>(yin + rn * nx + c0, dn);
+        }
         const AT left = static_cast<AT>(yin[rw * nx + cl]);
         const AT right = static_cast<AT>(yin[rw * nx + cr]);
         AT o[V];
-        if constexpr (OP == kOpDiffAdv) {
+        if constexpr (OP == kOpDiffAdv3) {
+            const AT left2 = static_cast<AT>(yin[rw * nx + cl2]);
+            const AT right2 = static_cast<AT>(yin[rw * nx + cr2]);
+            const AT aE = static_cast<AT>(a.aE), aW = static_cast<AT>(a.aW);
+            const AT aN = static_cast<AT>(a.aN), aS = static_cast<AT>(a.aS);
+            const AT aE2 = static_cast<AT>(a.aE2), aW2 = static_cast<AT>(a.aW2);
+            const AT aN2 = static_cast<AT>(a.aN2), aS2 = static_cast<AT>(a.aS2);
+            const AT ac = static_cast<AT>(a.aC - xim);
+            if constexpr (V == 2) {
+                o[0] = stencil_d3(aW, aE, aS, aN, ac, aW2, aE2, aS2, aN2, left, cen[1], up[0], dn[0], cen[0], left2,
+                                  right, up2[0], dn2[0]);
+                o[1] = stencil_d3(aW, aE, aS, aN, ac, aW2, aE2, aS2, aN2, cen[0], right, up[1], dn[1], cen[1], left,
+                                  right2, up2[1], dn2[1]);
+            } else {
+                o[0] = stencil_d3(aW, aE, aS, aN, ac, aW2, aE2, aS2, aN2, left, right, up[0], dn[0], cen[0], left2,
+                                  right2, up2[0], dn2[0]);
+            }
+        } else if constexpr (OP == kOpDiffAdv) {
             const AT aE = static_cast<AT>(a.aE), aW = static_cast<AT>(a.aW);
             const AT aN = static_cast<AT>(a.aN), aS = static_cast<AT>(a.aS);
             const AT ac = static_cast<AT>(a.aC - xim);
@@ -319,8 +360,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int m, cons
         }
 #pragma unroll
         for (int i = 0; i < V; ++i) {
+            if constexpr (OP == kOpDiffAdv3) up2[i] = up[i];
             up[i] = cen[i];
             cen[i] = dn[i];
+            if constexpr (OP == kOpDiffAdv3) dn[i] = dn2[i];
             if constexpr (OP == kOpBurgersJ) {
                 uup[i] = ucen[i];
                 ucen[i] = udn[i];
@@ -391,14 +434,20 @@ __device__ __forceinline__ void power_tile(const PowerArgs& a, const double s, d
     const int c0 = colok ? col : 0;
     const int cl = (c0 == 0) ? nx - 1 : c0 - 1;
     const int cr = (c0 + V >= nx) ? c0 + V - nx : c0 + V;
+    // second neighbours of the radius-2 stencil (nx >= 4)
+    const int cl2 = wrap(c0 - 2, nx), cr2 = wrap(c0 + V + 1, nx);
     const int row0 = tile_y * static_cast<int>(blockDim.y) * RY + static_cast<int>(threadIdx.y) * RY;
     const double* __restrict__ in = a.in;
     const double* __restrict__ uu = a.u;
     double* __restrict__ out = a.out;
 
-    double up[V], cen[V], dn[V], uup[V], ucen[V], udn[V];
+    double up[V], cen[V], dn[V], uup[V], ucen[V], udn[V], up2[V], dn2[V];
     ldv<V>(in + static_cast<long>(wrap(row0 - 1, ny)) * nx + c0, up);
     ldv<V>(in + static_cast<long>(wrap(row0, ny)) * nx + c0, cen);
+    if constexpr (OP == kOpDiffAdv3) {
+        ldv<V>(in + static_cast<long>(wrap(row0 - 2, ny)) * nx + c0, up2);
+        ldv<V>(in + static_cast<long>(wrap(row0 + 1, ny)) * nx + c0, dn);
+    }
     if constexpr (OP == kOpBurgersJ) {
         ldv<V>(uu + static_cast<long>(wrap(row0 - 1, ny)) * nx + c0, uup);
         ldv<V>(uu + static_cast<long>(wrap(row0, ny)) * nx + c0, ucen);
@@ -409,10 +458,25 @@ __device__ __forceinline__ void power_tile(const PowerArgs& a, const double s, d
         const bool ok = colok && row < ny;
         const long rw = wrap(row, ny);
         const long rn = wrap(row + 1, ny);
-        ldv<V>(in + rn * nx + c0, dn);
+        if constexpr (OP == kOpDiffAdv3) {
+            ldv<V>(in + static_cast<long>(wrap(row + 2, ny)) * nx + c0, dn2);
+        } else {
+            ldv<V>(in + rn * nx + c0, dn);
+        }
         const double left = in[rw * nx + cl], right = in[rw * nx + cr];
         double o[V];
-        if constexpr (OP == kOpDiffAdv) {
+        if constexpr (OP == kOpDiffAdv3) {
+            const double left2 = in[rw * nx + cl2], right2 = in[rw * nx + cr2];
+            if constexpr (V == 2) {
+                o[0] = stencil_d3(a.cW, a.cE, a.cS, a.cN, a.cC, a.cW2, a.cE2, a.cS2, a.cN2, left, cen[1], up[0], dn[0],
+                                  cen[0], left2, right, up2[0], dn2[0]);
+                o[1] = stencil_d3(a.cW, a.cE, a.cS, a.cN, a.cC, a.cW2, a.cE2, a.cS2, a.cN2, cen[0], right, up[1], dn[1],
+                                  cen[1], left, right2, up2[1], dn2[1]);
+            } else {
+                o[0] = stencil_d3(a.cW, a.cE, a.cS, a.cN, a.cC, a.cW2, a.cE2, a.cS2, a.cN2, left, right, up[0], dn[0],
+                                  cen[0], left2, right2, up2[0], dn2[0]);
+            }
+        } else if constexpr (OP == kOpDiffAdv) {
             if constexpr (V == 2) {
                 o[0] = stencil_da(a.cW, a.cE, a.cS, a.cN, a.cC, left, cen[1], up[0], dn[0], cen[0]);
                 o[1] = stencil_da(a.cW, a.cE, a.cS, a.cN, a.cC, cen[0], right, up[1], dn[1], cen[1]);
@@ -441,8 +505,10 @@ __device__ __forceinline__ void power_tile(const PowerArgs& a, const double s, d
         }
 #pragma unroll
         for (int i = 0; i < V; ++i) {
+            if constexpr (OP == kOpDiffAdv3) up2[i] = up[i];
             up[i] = cen[i];
             cen[i] = dn[i];
+            if constexpr (OP == kOpDiffAdv3) dn[i] = dn2[i];
             if constexpr (OP == kOpBurgersJ) {
                 uup[i] = ucen[i];
                 ucen[i] = udn[i];
