@@ -19,10 +19,18 @@ Prints one JSON line on stdout:
                 kernel source, else null
   batched_256   256 uneven instances in one batched call against the plain
                 per-instance path (both with power iteration)
+  learned_1024  the learned + batched form against plain batched and plain
+                per-instance solves on 1024 instances at 256^2
+  paper_problems_8192
+                the paper's linear test problems (Sec. 3, Problems I and II:
+                nu = 10, third-order upwind gradient, tolerance 1e-12) at
+                8192^2 for h = 1, 10, 100 x CFL to the paper's final times,
+                with the algorithmic bandwidth over the whole time loop as a
+                fraction of the practical peak measured in the same run
   cpu_baseline  the CPU oracle on a bounded sample (the same solve on a
                 2048^2 grid of the same family, scaled by the point ratio 4)
 
-Usage: python bench.py [--steps K] [--warmup W] [--no-tune] [--no-batched] [--no-cpu-baseline]
+Usage: python bench.py [--steps K] [--warmup W] [--no-tune] [--no-batched] [--no-paper] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -152,6 +160,79 @@ def bench_learned(lib, count: int = 1024) -> dict:
     return res
 
 
+# final times of the paper's 2^13 runs for h = 1, 10, 100 x CFL (Sec. 3,
+# table of Problems I and II)
+PAPER_RUNS_8192 = ((1.0, 2e-7), (10.0, 2e-6), (100.0, 2e-5))
+
+
+def bench_paper_problems(lib, n: int = 8192, axpby_gbs=None, tune: bool = True) -> dict:
+    """Problems I (exp action) and II (phi_1 with a source) on n^2 with the
+    third-order upwind operator: for each step size, power iteration once
+    (A is constant), then the time loop to the paper's final time, timed as
+    a whole.  Bytes are the kernels' algorithmic bytes: the spectrum
+    (16 B/pt per sweep), the Leja loops (lx_stats.bytes), and for Problem II
+    the right-hand side h (A u + S) (24 B/pt) and the sum u + phi (24 B/pt)."""
+    import torch
+
+    from paper_2310_08344_amd import binding as B
+    from paper_2310_08344_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    ctx = lib.context(n_max=n * n, k_max=1)
+    res = {"grid": n, "tolerance": 1e-12, "runs": []}
+    try:
+        p0, u0_h, S_h = W.paper_linear(n, 1.0, True)
+        op = B.make_operator(p0)
+        if tune:
+            best = min(ctx.tune(op, K=1, sweeps=8), key=lambda r: r[6])
+            res["tuned"] = {"depth": best[0], "rows": best[3], "workgroups": best[5],
+                            "us_per_iteration": round(best[6], 2)}
+        u0 = torch.as_tensor(u0_h).to(dev)
+        S = torch.as_tensor(S_h).to(dev)
+        del u0_h, S_h
+        x0 = torch.as_tensor(W.start_vector(n)).to(dev)
+        ua, ub = torch.empty_like(u0), torch.empty_like(u0)
+        N = float(n * n)
+        for source in (False, True):
+            for cfl, t_final in PAPER_RUNS_8192:
+                h = cfl * p0.h   # p0.h is one CFL step
+                steps = max(1, round(t_final / h))
+                # untimed warm-up step (planner tables, code paths)
+                _, c, g = ctx.spectrum(op, x0=x0, iters=20)
+                ctx.linear_step(op, u0, ua, h, c, g, source=S if source else None, rtol=1e-12, max_iters=1000)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, c, g = ctx.spectrum(op, x0=x0, iters=20)
+                nbytes = 16.0 * N * 20
+                iters = []
+                cur, nxt = u0, ua
+                for k in range(steps):
+                    r = ctx.linear_step(op, cur, nxt, h, c, g, source=S if source else None, rtol=1e-12,
+                                        max_iters=1000)
+                    if r.status != B.LX_OK:
+                        raise RuntimeError(f"linear_step status {r.status}: {ctx.last_error()}")
+                    iters.append(r.iters[0])
+                    nbytes += r.stats["bytes"] + (48.0 * N if source else 0.0)
+                    cur, nxt = nxt, (ub if nxt is ua else ua)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                gbs = nbytes / dt / 1e9
+                run = {"problem": "II" if source else "I", "h_cfl": cfl, "t_final": t_final, "steps": steps,
+                       "iters_first_last": [iters[0], iters[-1]], "seconds": round(dt, 4),
+                       "ms_per_step": round(dt * 1e3 / steps, 3), "gbs": round(gbs, 1),
+                       "frac_of_8tbs": round(gbs / HBM_PEAK_GBS, 4)}
+                if axpby_gbs:
+                    run["frac_of_practical_axpby"] = round(gbs / axpby_gbs, 4)
+                res["runs"].append(run)
+                log("paper problem", run)
+    finally:
+        ctx.close()
+    res["note"] = ("bytes are this library's algorithmic bytes (two Leja iterations per launch read and write "
+                   "the outputs once); the paper's A100 figures (0.87-0.92 of its practical z = ax + by "
+                   "bandwidth at 2^13, Sec. 3) count its own kernels' reads and writes: context only")
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -162,6 +243,7 @@ def main() -> int:
     ap.add_argument("--no-calibrate", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-paper", action="store_true", help="skip the paper-shaped 8192^2 problems")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the phi-action path is single-GPU (--gpus {args.gpus} "
@@ -274,6 +356,10 @@ def main() -> int:
         out["batched_256"] = bench_batched(lib)
         log("learned + batched on 1024 instances at 256^2")
         out["learned_1024"] = bench_learned(lib)
+    if not args.no_paper:
+        log("paper-shaped problems I and II at 8192^2")
+        out["paper_problems_8192"] = bench_paper_problems(lib, axpby_gbs=extra.get("practical_axpby_gbs"),
+                                                          tune=not args.no_tune)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline()
