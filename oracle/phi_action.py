@@ -25,6 +25,15 @@ Readings (paper silent or ambiguous)
     freezes once it passes; the loop ends when all outputs have passed or
     after max_iters applications (status "notconv").  A non-finite norm ends
     the loop with status "nonfinite".
+  * Substeps (not in the paper; the Leja loop of Sec. 2.1 loses accuracy
+    once alpha*h*gamma is large): with s substeps of tau = alpha*h/s,
+    exp(alpha h A) v = exp(tau A)^s v, and for l >= 1 the function
+    u(t) = t^l phi_l(tA) v solves u' = A u + t^(l-1)/(l-1)! v, u(0) = 0, so
+    by the variation-of-constants formula
+        u(t + tau) = e^(tau A) u(t) + sum_{i=1..l} tau^i t^(l-i)/(l-i)! phi_i(tau A) v
+    (phi-function time stepping, Niesen and Wright 2012) and
+    phi_l(alpha h A) v = u(alpha h) / (alpha h)^l.  phi_1..phi_l(tau A) v come
+    from one Newton basis; every substep takes one exp action.
   * Problem II's update is printed without the factor h in front of
     phi_1; the exact solution of u_t = A u + S over a step h has it.
   * EXPRB42 (named in Sec. 1, formula not printed; the published two-stage
@@ -138,6 +147,58 @@ def leja_phi(apply_A, v, outputs, h, c, gamma, rtol, atol, max_iters=500,
     if status == "ok" and any(active):
         status = "notconv"
     return LejaResult(p=p, iters=iters, errs=errs, status=status, n_apply=n_apply)
+
+
+def substep_count(outputs, h, gamma, hg_max: float = 300.0) -> int:
+    """Automatic substep count: the largest alpha*h*gamma split into pieces
+    of at most hg_max (reading: 300, half the largest alpha*h*gamma at which
+    the plain loop was still seen to converge)."""
+    hg = max(a for (_, a, _) in outputs) * h * gamma
+    return max(1, math.ceil(hg / hg_max))
+
+
+def leja_phi_substeps(apply_A, v, outputs, h, c, gamma, rtol, atol, substeps, max_iters=500):
+    """sigma_k phi_{l_k}(alpha_k h A) v by ``substeps`` substeps (see the
+    module header); every Leja call has its own stop rule.  Returns
+    (outputs, iterations per output: the phi_l call it used plus its exp
+    calls, status)."""
+    v = np.asarray(v, dtype=np.float64)
+    s = int(substeps)
+    outs, iters, status = [], [], "ok"
+
+    def worst(st):
+        nonlocal status
+        if st != "ok" and status != "nonfinite":
+            status = st
+
+    for (l, a, sg) in outputs:
+        H = a * h
+        tau = H / s
+        if l == 0:
+            u, it = v, 0
+            for j in range(s):
+                r = leja_phi(apply_A, u, [(0, 1.0, sg if j == s - 1 else 1.0)], tau, c, gamma, rtol, atol,
+                             max_iters)
+                worst(r.status)
+                u, it = r.p[0], it + r.iters[0]
+            outs.append(u)
+            iters.append(it)
+            continue
+        P = leja_phi(apply_A, v, [(i, 1.0, 1.0) for i in range(1, l + 1)], tau, c, gamma, rtol, atol, max_iters)
+        worst(P.status)
+        it = P.iters[l - 1]
+        u = tau**l * P.p[l - 1]                       # u(tau): t = 0 leaves only i = l
+        for j in range(1, s):
+            t = j * tau
+            r = leja_phi(apply_A, u, [(0, 1.0, 1.0)], tau, c, gamma, rtol, atol, max_iters)
+            worst(r.status)
+            it += r.iters[0]
+            u = r.p[0]
+            for i in range(1, l + 1):
+                u = u + (tau**i * t ** (l - i) / math.factorial(l - i)) * P.p[i - 1]
+        outs.append(sg * u / H**l)
+        iters.append(it)
+    return outs, iters, status
 
 
 # --------------------------------------------------------------------------

@@ -277,3 +277,46 @@ def test_linear_step_matches_exact_solution(n, cfl, source):
     assert r.status == "ok"
     lam = diffadv3_symbol(n, n, p.D, p.vx, p.vy, p.dx, p.dy)
     assert _rel(r.u_next, linear_step_fft(u, S, p.h, lam)) <= 1e-11
+
+
+# ---- substeps (phi-function time stepping) --------------------------------
+
+def _paper_fft(n, hg, ls):
+    from oracle.exact import diffadv3_symbol
+    from oracle.leja import phi_complex
+    p, u, _ = W.paper_linear(n, 1.0, False)
+    A = make_apply(p)
+    c, g = _bounds(A, u.shape)
+    h = hg / g
+    lam = diffadv3_symbol(n, n, p.D, p.vx, p.vy, p.dx, p.dy)
+    ex = [np.fft.ifft2(phi_complex(l, a * h * lam) * np.fft.fft2(u)).real * sg for (l, a, sg) in ls]
+    return A, u, h, c, g, ex
+
+
+@pytest.mark.parametrize("n", [32, 30])
+def test_substeps_recover_large_steps(n):
+    """At alpha h gamma = 1200 the plain loop diverges; eight substeps give
+    the exact Fourier solution for exp and phi_1..phi_3, with alpha and sigma."""
+    from oracle.phi_action import leja_phi_substeps, substep_count
+    ls = [(0, 1.0, 1.0), (1, 1.0, 1.0), (3, 0.75, 2.0), (2, 1.0, -0.5)]
+    A, u, h, c, g, ex = _paper_fft(n, 1200.0, ls)
+    plain = leja_phi(A, u, [(0, 1.0, 1.0)], h, c, g, 1e-12, 0.0, 1000)
+    assert plain.status != "ok" or _rel(plain.p[0], ex[0]) > 1e-3
+    assert substep_count(ls, h, g) == 4
+    outs, iters, status = leja_phi_substeps(A, u, ls, h, c, g, 1e-12, 0.0, 8, 500)
+    assert status == "ok"
+    for o, e in zip(outs, ex):
+        assert _rel(o, e) <= 1e-10
+
+
+def test_one_substep_is_the_plain_loop():
+    from oracle.phi_action import leja_phi_substeps
+    ls = [(0, 1.0, 1.0), (2, 0.5, 3.0)]
+    A, u, h, c, g, ex = _paper_fft(24, 80.0, ls)
+    outs, iters, status = leja_phi_substeps(A, u, ls, h, c, g, 1e-12, 0.0, 1, 500)
+    r0 = leja_phi(A, u, [ls[0]], h, c, g, 1e-12, 0.0, 500)
+    assert np.array_equal(outs[0], r0.p[0]) and iters[0] == r0.iters[0]
+    r2 = leja_phi(A, u, [(1, 0.5, 1.0), (2, 0.5, 1.0)], h, c, g, 1e-12, 0.0, 500)
+    assert _rel(outs[1], 3.0 * r2.p[1]) <= 1e-14
+    for o, e in zip(outs, ex):
+        assert _rel(o, e) <= 1e-10
