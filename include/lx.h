@@ -97,7 +97,21 @@ typedef struct {
      * every unconverged output has |d_{m+1}| ||y_{m+1}|| <=
      * fp32_switch * (rtol ||p|| + atol).  0 means FP32 from the first sweep.  */
     double fp32_switch;
+    /* Substeps s (not in the paper): the Leja loop loses accuracy once
+     * alpha*h*gamma is large (it diverges near 800 on the diffusion-
+     * advection operators), so each output may be computed over s substeps
+     * of tau = alpha*h/s: exp(alpha h A) v = exp(tau A)^s v, and for l >= 1
+     * by phi-function time stepping (Niesen and Wright 2012): with
+     * u(t) = t^l phi_l(tA) v,
+     *   u(t + tau) = e^{tau A} u(t) + sum_{i=1..l} tau^i t^{l-i}/(l-i)! phi_i(tau A) v,
+     * phi_1..phi_l(tau A) v from one Newton basis, one exp action per
+     * substep, each call with its own stop rule.
+     * 0: automatic, s = ceil(max_k alpha_k * h * gamma / 300);
+     * 1 .. LX_MAX_SUBSTEPS: that many.  Batched calls ignore it.            */
+    int substeps;
 } lx_leja_opts;
+
+#define LX_MAX_SUBSTEPS 1000
 
 /* Per-call record, filled by every lx_spectrum / lx_phi_leja / lx_exprb_step. */
 typedef struct {
@@ -116,6 +130,7 @@ typedef struct {
     int n_launch;           /* Leja-loop launches that did work               */
     int depth;              /* Leja iterations per launch (1 or 2)            */
     double step_err;        /* lx_exprb_step with LX_EXPRB32: embedded error  */
+    int substeps;           /* substeps taken (lx_leja_opts.substeps)         */
 } lx_stats;
 
 /* ---- context ---------------------------------------------------------- */
@@ -179,12 +194,16 @@ lx_status lx_spectrum(lx_ctx* ctx, const lx_operator* op, const double* d_u,
  *   d_out   K device output vectors, distinct, none equal to d_v or d_u
  *   h > 0 step; c <= 0 and gamma > 0 from lx_spectrum (the Leja interval
  *           [-2, 2] maps onto [c - 2 gamma, c + 2 gamma])
- *   o       tolerances and iteration cap (NULL = rtol 1e-8, atol 0, 500)
- *   iters   host [K] or NULL: sweeps until each output passed
+ *   o       tolerances, iteration cap and substeps (NULL = rtol 1e-8,
+ *           atol 0, 500, automatic substeps)
+ *   iters   host [K] or NULL: sweeps until each output passed (with
+ *           substeps: the sweeps of its phi_l call plus its exp calls)
  *   err     host [K] or NULL: each output's last error estimate
  * Each output freezes once it passes; the call ends when all have passed,
  * or with LX_ENOTCONV after max_iters sweeps (outputs then hold the last
- * polynomial), or with LX_ENONFINITE. */
+ * polynomial; with substeps, of the call that did not converge), or with
+ * LX_ENONFINITE.  With more than one substep the call allocates, on first
+ * use, up to 10 workspace vectors of the context's n_max. */
 lx_status lx_phi_leja(lx_ctx* ctx, const lx_operator* op, const double* d_u,
                       const double* d_v, int K, const int* l, const double* alpha,
                       const double* sigma, double* const* d_out, double h,

@@ -40,7 +40,7 @@ class Operator(C.Structure):
 
 class LejaOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("max_iters", C.c_int),
-                ("fp32_switch", C.c_double)]
+                ("fp32_switch", C.c_double), ("substeps", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -49,7 +49,7 @@ class Stats(C.Structure):
                 ("pnorm", C.c_double * LX_K_MAX), ("rho_hat", C.c_double),
                 ("plan_ms", C.c_double), ("loop_ms", C.c_double), ("sweep_ms", C.c_double),
                 ("first_sweep_ms", C.c_double), ("bytes", C.c_double), ("n_launch", C.c_int),
-                ("depth", C.c_int), ("step_err", C.c_double)]
+                ("depth", C.c_int), ("step_err", C.c_double), ("substeps", C.c_int)]
 
     def as_dict(self) -> dict:
         return {"status": self.status, "n_apply": self.n_apply, "n_fp32": self.n_fp32,
@@ -57,7 +57,7 @@ class Stats(C.Structure):
                 "rho_hat": self.rho_hat, "plan_ms": self.plan_ms, "loop_ms": self.loop_ms,
                 "sweep_ms": self.sweep_ms, "first_sweep_ms": self.first_sweep_ms,
                 "bytes": self.bytes, "n_launch": self.n_launch, "depth": self.depth,
-                "step_err": self.step_err}
+                "step_err": self.step_err, "substeps": self.substeps}
 
 
 class Instance(C.Structure):
@@ -306,14 +306,15 @@ class Context:
         return rho.value, c.value, g.value
 
     def phi_leja(self, op: Operator, v, outs, ls, h, c, gamma, u=None, alphas=None, sigmas=None,
-                 rtol=1e-8, atol=0.0, max_iters=500, fp32_switch=1e4, raise_on_error=True) -> PhiResult:
-        """outs[k] = sigma_k phi_{l_k}(alpha_k h A) v (lx_phi_leja)."""
+                 rtol=1e-8, atol=0.0, max_iters=500, fp32_switch=1e4, raise_on_error=True,
+                 substeps=0) -> PhiResult:
+        """outs[k] = sigma_k phi_{l_k}(alpha_k h A) v (lx_phi_leja); substeps 0 = automatic."""
         K = len(outs)
         larr = (_I * K)(*[int(x) for x in ls])
         aarr = (_D * K)(*[float(x) for x in alphas]) if alphas is not None else None
         sarr = (_D * K)(*[float(x) for x in sigmas]) if sigmas is not None else None
         oarr = (_P * K)(*[_ptr(t) for t in outs])
-        opts = LejaOpts(float(rtol), float(atol), int(max_iters), float(fp32_switch))
+        opts = LejaOpts(float(rtol), float(atol), int(max_iters), float(fp32_switch), int(substeps))
         it = (_I * K)()
         er = (_D * K)()
         st = self.lib.c.lx_phi_leja(self._h, C.byref(op), _ptr(u), _ptr(v), K, larr,
@@ -390,8 +391,8 @@ class Context:
         return Predictor(self, seed)
 
     def exprb_step(self, op: Operator, u, u_out, h, c, gamma, rtol=1e-8, atol=0.0, max_iters=500,
-                   fp32_switch=1e4, scheme=LX_EXPRB42, raise_on_error=True) -> PhiResult:
-        opts = LejaOpts(float(rtol), float(atol), int(max_iters), float(fp32_switch))
+                   fp32_switch=1e4, scheme=LX_EXPRB42, raise_on_error=True, substeps=0) -> PhiResult:
+        opts = LejaOpts(float(rtol), float(atol), int(max_iters), float(fp32_switch), int(substeps))
         it = (_I * 2)()
         st = self.lib.c.lx_exprb_step(self._h, C.byref(op), int(scheme), _ptr(u), _ptr(u_out), float(h),
                                       float(c), float(gamma), C.byref(opts), it)
@@ -402,9 +403,9 @@ class Context:
 
 
     def linear_step(self, op: Operator, u, u_out, h, c, gamma, source=None, rtol=1e-12, atol=0.0,
-                    max_iters=500, fp32_switch=1e4, raise_on_error=True) -> PhiResult:
+                    max_iters=500, fp32_switch=1e4, raise_on_error=True, substeps=0) -> PhiResult:
         """lx_linear_step: exp(hA)u, or u + h phi_1(hA)(Au + S) with a source."""
-        opts = LejaOpts(float(rtol), float(atol), int(max_iters), float(fp32_switch))
+        opts = LejaOpts(float(rtol), float(atol), int(max_iters), float(fp32_switch), int(substeps))
         it = _I(0)
         st = self.lib.c.lx_linear_step(self._h, C.byref(op), _ptr(u), _ptr(source) if source is not None else None,
                                        _ptr(u_out), float(h), float(c), float(gamma), C.byref(opts), C.byref(it))

@@ -210,6 +210,18 @@ __global__ void linear_rhs_kernel(const double* __restrict__ u, const double* __
     }
 }
 
+// out = b base + sum_i a_i x_i, base optional: the substep updates of
+// phi-function time stepping
+__global__ void lincomb_kernel(double* __restrict__ out, const double* __restrict__ base, double b, LinComb t,
+                               long n) {
+    for (long i = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<long>(gridDim.x) * blockDim.x) {
+        double r = (base != nullptr) ? b * base[i] : 0.0;
+        for (int k = 0; k < t.n_terms; ++k) r = fma(t.a[k], t.x[k][i], r);
+        out[i] = r;
+    }
+}
+
 // out = (x + y) + z, z optional (the stages of the integrators)
 __global__ void combine_kernel(const double* __restrict__ x, const double* __restrict__ y,
                                const double* __restrict__ z, double* __restrict__ out, long n) {
@@ -393,6 +405,12 @@ hipError_t launch_linear_rhs(int op, const double* u, const double* S, double* o
     if ((op != kOpDiffAdv && op != kOpDiffAdv3) || nx < 3 || ny < 3) return hipErrorInvalidValue;
     hipLaunchKernelGGL(linear_rhs_kernel, dim3(flat_blocks(static_cast<long>(nx) * ny)), dim3(kBlockThreads), 0, s,
                        u, S, out, nx, ny, st[0], st[1], st[2], st[3], st[4], st[5], st[6], st[7], st[8], h);
+    return hipGetLastError();
+}
+
+hipError_t launch_lincomb(double* out, const double* base, double b, const LinComb& t, long n, hipStream_t s) {
+    if (t.n_terms < 0 || t.n_terms > 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(lincomb_kernel, dim3(flat_blocks(n)), dim3(kBlockThreads), 0, s, out, base, b, t, n);
     return hipGetLastError();
 }
 

@@ -486,13 +486,15 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
 }
 
 lx_status check_leja_opts(lx_ctx* ctx, const lx_leja_opts* o, lx_leja_opts* out) {
-    lx_leja_opts d{1e-8, 0.0, 500, 1e4};
+    lx_leja_opts d{1e-8, 0.0, 500, 1e4, 0};
     if (o != nullptr) d = *o;
     if (!(d.rtol >= 0.0) || !(d.atol >= 0.0) || !std::isfinite(d.rtol) || !std::isfinite(d.atol))
         return fail(ctx, LX_EINVAL, "tolerances must be finite and >= 0");
     if (d.max_iters < 1 || d.max_iters > LX_MAX_ITERS)
         return fail(ctx, LX_EINVAL, "max_iters %d outside 1..%d", d.max_iters, LX_MAX_ITERS);
     if (!(d.fp32_switch >= 0.0)) return fail(ctx, LX_EINVAL, "fp32_switch must be >= 0");
+    if (d.substeps < 0 || d.substeps > LX_MAX_SUBSTEPS)
+        return fail(ctx, LX_EINVAL, "substeps %d outside 0..%d", d.substeps, LX_MAX_SUBSTEPS);
     *out = d;
     return LX_OK;
 }
@@ -502,6 +504,178 @@ lx_status check_shift(lx_ctx* ctx, double h, double c, double gamma) {
     if (!(c <= 0.0) || !std::isfinite(c)) return fail(ctx, LX_EINVAL, "shift c must be finite and <= 0");
     if (!(gamma > 0.0) || !std::isfinite(gamma)) return fail(ctx, LX_EINVAL, "scale gamma must be finite and > 0");
     return LX_OK;
+}
+
+// Largest alpha*h*gamma of one Leja call under automatic substeps: half of
+// the largest value at which the plain loop was still seen to converge.
+constexpr double kSubstepHGamma = 300.0;
+
+// rms norm (l2 / sqrt(N)) of a device vector: per-workgroup sums of squares
+// (the power iteration's norm kernel), added on the host in workgroup order
+lx_status rms_norm(lx_ctx* ctx, const double* x, long N, double* out) {
+    constexpr int nb = 256;
+    lx_status s = ensure_partials(ctx, 2 * nb);
+    if (s != LX_OK) return s;
+    double h[nb];
+    LX_HIP(ctx, lx::launch_power_norm(x, N, nb, ctx->partials, ctx->stream));
+    LX_HIP(ctx, hipMemcpyAsync(h, ctx->partials + nb, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    LX_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    double t = 0.0;
+    for (double v : h) t += v;
+    *out = std::sqrt(t / static_cast<double>(N));
+    return LX_OK;
+}
+
+lx_status ensure_sub_ws(lx_ctx* ctx, size_t count) {
+    while (ctx->sub_ws.size() < count) {
+        double* p = nullptr;
+        if (hipMalloc(&p, sizeof(double) * ctx->n_max) != hipSuccess)
+            return fail(ctx, LX_ENOMEM, "substep workspace allocation failed");
+        ctx->sub_ws.push_back(p);
+    }
+    return LX_OK;
+}
+
+// The Leja call with substeps (lx_leja_opts.substeps): every output over s
+// substeps of tau = alpha h / s.  exp: s exp actions in a row, sigma on the
+// last.  l >= 1: phi-function time stepping on u(t) = t^l phi_l(tA) v,
+//   u(tau) = tau^l phi_l(tau A) v,
+//   u(t + tau) = e^{tau A} u(t) + sum_{i=1..l} tau^i t^{l-i}/(l-i)! phi_i(tau A) v,
+//   out = sigma u(alpha h) / (alpha h)^l,
+// with phi_1..phi_L(tau A) v for all outputs of one alpha from vertical
+// calls of at most k_max outputs.  Fills ctx->stats with the sums.
+lx_status run_leja_sub(lx_ctx* ctx, const LejaCall& q) {
+    double amax = 0.0;
+    for (int k = 0; k < q.K; ++k) amax = std::max(amax, q.alpha[k]);
+    int s = q.o.substeps;
+    if (s == 0) {
+        const double want = std::ceil(amax * q.h * q.gamma / kSubstepHGamma);
+        s = static_cast<int>(std::min<double>(std::max(1.0, want), LX_MAX_SUBSTEPS));
+    }
+    if (s <= 1) {
+        const lx_status st = run_leja(ctx, q);
+        ctx->stats.substeps = 1;
+        return st;
+    }
+    const long N = static_cast<long>(q.op->nx) * q.op->ny;
+    lx_stats acc{};
+    int iters[LX_K_MAX] = {0, 0, 0, 0};
+    double errs[LX_K_MAX] = {0, 0, 0, 0};
+    lx_status worst = LX_OK;
+    // one Leja call, its statistics added; LX_ENOTCONV is remembered
+    auto call = [&](const LejaCall& c) -> lx_status {
+        const lx_status st = run_leja(ctx, c);
+        const lx_stats& t = ctx->stats;
+        acc.n_apply += t.n_apply;
+        acc.n_fp32 += t.n_fp32;
+        acc.n_launch += t.n_launch;
+        acc.plan_ms += t.plan_ms;
+        acc.loop_ms += t.loop_ms;
+        acc.sweep_ms += t.sweep_ms;
+        acc.bytes += t.bytes;
+        acc.depth = t.depth;
+        if (st == LX_ENOTCONV) {
+            worst = LX_ENOTCONV;
+            return LX_OK;
+        }
+        return st;
+    };
+    auto single = [&](const double* v, double* out, int l, double tau, double sigma) {
+        LejaCall c = q;
+        c.v = v;
+        c.K = 1;
+        c.l[0] = l;
+        c.alpha[0] = 1.0;
+        c.sigma[0] = sigma;
+        c.out[0] = out;
+        c.h = tau;
+        return c;
+    };
+    bool done[LX_K_MAX] = {false, false, false, false};
+    for (int k0 = 0; k0 < q.K; ++k0) {
+        if (done[k0]) continue;
+        const double alpha = q.alpha[k0];
+        const double H = alpha * q.h, tau = H / s;
+        int L = 0;
+        for (int k = k0; k < q.K; ++k)
+            if (q.alpha[k] == alpha) L = std::max(L, q.l[k]);
+        lx_status st = ensure_sub_ws(ctx, static_cast<size_t>(L) + 2);
+        if (st != LX_OK) return st;
+        double* const* P = ctx->sub_ws.data();            // P[i-1] = phi_i(tau A) v
+        double* A = ctx->sub_ws[L];
+        double* B = ctx->sub_ws[L + 1];
+        int piters[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int i0 = 1; i0 <= L; i0 += ctx->k_max) {
+            LejaCall c = q;
+            c.K = std::min(ctx->k_max, L - i0 + 1);
+            c.h = tau;
+            for (int j = 0; j < c.K; ++j) {
+                c.l[j] = i0 + j;
+                c.alpha[j] = 1.0;
+                c.sigma[j] = 1.0;
+                c.out[j] = P[i0 + j - 1];
+            }
+            st = call(c);
+            if (st != LX_OK) return st;
+            for (int j = 0; j < c.K; ++j) piters[i0 + j - 1] = ctx->stats.iters[j];
+        }
+        for (int k = k0; k < q.K; ++k) {
+            if (q.alpha[k] != alpha) continue;
+            done[k] = true;
+            const int l = q.l[k];
+            if (l == 0) {
+                const double* cur = q.v;
+                for (int j = 0; j < s; ++j) {
+                    double* dst = (j == s - 1) ? q.out[k] : ((j & 1) ? B : A);
+                    st = call(single(cur, dst, 0, tau, j == s - 1 ? q.sigma[k] : 1.0));
+                    if (st != LX_OK) return st;
+                    iters[k] += ctx->stats.iters[0];
+                    errs[k] = ctx->stats.err[0];
+                    cur = dst;
+                }
+                continue;
+            }
+            iters[k] = piters[l - 1];
+            // u(tau) = tau^l phi_l(tau A) v into A
+            lx::LinComb lc{};
+            lc.n_terms = 1;
+            lc.x[0] = P[l - 1];
+            lc.a[0] = std::pow(tau, l);
+            LX_HIP(ctx, lx::launch_lincomb(A, nullptr, 0.0, lc, N, ctx->stream));
+            const double fin = q.sigma[k] / std::pow(H, l);
+            for (int j = 1; j < s; ++j) {
+                const double t = j * tau;
+                st = call(single(A, B, 0, tau, 1.0));   // B = e^{tau A} u(t)
+                if (st != LX_OK) return st;
+                iters[k] += ctx->stats.iters[0];
+                errs[k] = ctx->stats.err[0];
+                const bool last = j == s - 1;
+                const double sc = last ? fin : 1.0;
+                lx::LinComb u{};
+                u.n_terms = l;
+                double fact = 1.0;   // (l - i)!, from i = l down
+                for (int i = l; i >= 1; --i) {
+                    if (i < l) fact *= static_cast<double>(l - i);
+                    u.x[i - 1] = P[i - 1];
+                    u.a[i - 1] = sc * std::pow(tau, i) * std::pow(t, l - i) / fact;
+                }
+                double* dst = last ? q.out[k] : A;
+                LX_HIP(ctx, lx::launch_lincomb(dst, B, sc, u, N, ctx->stream));
+            }
+        }
+    }
+    LX_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    for (int k = 0; k < q.K; ++k) {
+        acc.iters[k] = iters[k];
+        acc.err[k] = errs[k];
+        const lx_status st = rms_norm(ctx, q.out[k], N, &acc.pnorm[k]);
+        if (st != LX_OK) return st;
+    }
+    acc.substeps = s;
+    acc.status = worst;
+    ctx->stats = acc;
+    if (worst == LX_ENOTCONV) ctx->err = "not converged within max_iters (a substep call)";
+    return worst;
 }
 
 }  // namespace
@@ -557,6 +731,7 @@ void lx_destroy(lx_ctx* ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     for (double* p : ctx->ybuf) (void)hipFree(p);
     for (double* p : ctx->ws) (void)hipFree(p);
+    for (double* p : ctx->sub_ws) (void)hipFree(p);
     (void)hipFree(ctx->u32);
     (void)hipFree(ctx->partials);
     (void)hipFree(ctx->ctl);
@@ -755,7 +930,7 @@ lx_status lx_phi_leja(lx_ctx* ctx, const lx_operator* op, const double* d_u, con
             if (d_out[j] == d_out[k]) return fail(ctx, LX_EINVAL, "d_out[%d] and d_out[%d] alias", j, k);
         q.out[k] = d_out[k];
     }
-    s = run_leja(ctx, q);
+    s = run_leja_sub(ctx, q);
     for (int k = 0; k < K; ++k) {
         if (iters) iters[k] = ctx->stats.iters[k];
         if (err) err[k] = ctx->stats.err[k];
@@ -794,7 +969,7 @@ lx_status lx_linear_step(lx_ctx* ctx, const lx_operator* op, const double* d_u, 
         // Problem I: the exp action of u
         q.l[0] = 0;
         q.v = d_u;
-        s = run_leja(ctx, q);
+        s = run_leja_sub(ctx, q);
     } else {
         // Problem II: u + phi_1(h A) h (A u + S)
         if (ctx->ws[0] == nullptr && hipMalloc(&ctx->ws[0], sizeof(double) * ctx->n_max) != hipSuccess)
@@ -804,7 +979,7 @@ lx_status lx_linear_step(lx_ctx* ctx, const lx_operator* op, const double* d_u, 
         LX_HIP(ctx, lx::launch_linear_rhs(opcode_of(op->kind), d_u, d_src, ctx->ws[0], nx, ny, k9, h, ctx->stream));
         q.l[0] = 1;
         q.v = ctx->ws[0];
-        s = run_leja(ctx, q);
+        s = run_leja_sub(ctx, q);
         if (s == LX_OK || s == LX_ENOTCONV) {
             // after LX_ENOTCONV too: u plus the last polynomial
             LX_HIP(ctx, lx::launch_combine(d_u, d_u_out, nullptr, d_u_out, N, ctx->stream));
@@ -855,7 +1030,7 @@ lx_status lx_exprb_step(lx_ctx* ctx, const lx_operator* op, int scheme, const do
         q.c = c;
         q.gamma = gamma;
         q.o = oo;
-        return run_leja(ctx, q);
+        return run_leja_sub(ctx, q);
     };
     auto merge = [](lx_stats& acc, const lx_stats& t) {
         acc.n_apply += t.n_apply;

@@ -40,7 +40,8 @@ struct lx_ctx {
     // device workspaces
     double* ybuf[2] = {nullptr, nullptr};   // Newton basis ping-pong (FP64 or FP32 view)
     float* u32 = nullptr;                   // Burgers state in FP32 (FP32 sweeps)
-    double* ws[3] = {nullptr, nullptr, nullptr};  // EXPRB42 stages (allocated on first use)
+    double* ws[3] = {nullptr, nullptr, nullptr};  // integrator stages (allocated on first use)
+    std::vector<double*> sub_ws;            // substep workspaces (phi_i(tau A) v, two states)
     double* partials = nullptr;
     size_t partials_len = 0;
     lx::LoopCtl* ctl = nullptr;

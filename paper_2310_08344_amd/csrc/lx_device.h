@@ -147,6 +147,13 @@ hipError_t launch_burgers_remainder(const double* u, const double* a, double* ou
 // for kOpDiffAdv)
 hipError_t launch_linear_rhs(int op, const double* u, const double* S, double* out, int nx, int ny,
                              const double (&st)[9], double h, hipStream_t s);
+// out = b * base + sum_i a[i] * x[i] (base may be NULL; at most 8 terms)
+struct LinComb {
+    const double* x[8];
+    double a[8];
+    int n_terms;
+};
+hipError_t launch_lincomb(double* out, const double* base, double b, const LinComb& t, long n, hipStream_t s);
 // out = (x + y) + z (z may be NULL)
 hipError_t launch_combine(const double* x, const double* y, const double* z, double* out, long n, hipStream_t s);
 
