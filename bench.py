@@ -318,8 +318,10 @@ def main() -> int:
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic["bytes_per_launch"] if traffic else None,
-            "kernel": ("leja_pair (diffusion-advection, K=3, FP64, two iterations per launch)" if depth == 2
-                       else "leja_sweep (diffusion-advection, K=3, FP64)"),
+            "kernel": ({2: "leja_pair (diffusion-advection, K=3, FP64, two iterations per launch)",
+                        3: "leja_block (diffusion-advection, K=3, FP64, windows of three iterations)",
+                        4: "leja_block (diffusion-advection, K=3, FP64, windows of four iterations)"}.get(
+                           depth, "leja_sweep (diffusion-advection, K=3, FP64)")),
             "launches": launches, "avg_launch_us": round(sweep_ms * 1e3 / launches, 2),
             "cache_note": "the outputs stream with nontemporal hints and the basis vector (8 of the 64 bytes per point "
                           "and launch) is mostly read back from the 256 MB Infinity Cache; the L2 traffic counters "

@@ -421,12 +421,17 @@ lx_status lx_set_tile(lx_ctx* ctx, int tx, int ty, int ry, int vec, int nb);
  * depth 1 runs one fused sweep per launch (the shape of lx_set_tile);
  * depth 2 runs two iterations per launch on LDS-resident tiles of 128
  * columns by th (8, 16 or 32) rows with nb workgroups (0 = automatic),
- * reading the basis once per two iterations; depth 0 restores the automatic
- * choice (the tuned entry, else 2).  Depth 2 applies to FP64 sweeps on
- * grids with even nx and 16-byte aligned vectors; other calls use depth 1.
- * Results agree with depth 1 to rounding (the outputs take the same terms
- * in the same order; only the order of the norm reductions differs).
- * Errors: LX_EINVAL (depth outside 0..2, th not 0, 8, 16 or 32, nb < 0). */
+ * reading the basis once per two iterations; depths 3 and 4 run windows of
+ * that many iterations (th 8 or 16; larger th is taken as 16) whose terms
+ * are added speculatively, and re-execute a window in which an output
+ * stopped (they also use one more buffer per output, allocated on first
+ * use); depth 0 restores the automatic choice (the tuned entry, else 2).
+ * Depths 2..4 apply to FP64 sweeps on grids with even nx and 16-byte aligned
+ * vectors, depths 3 and 4 to LX_OP_DIFFADV2D only (others use 2); other
+ * calls use depth 1.  Results agree with depth 1 to rounding (the outputs
+ * take the same terms in the same order; only the order of the norm
+ * reductions differs).
+ * Errors: LX_EINVAL (depth outside 0..4, th not 0, 8, 16 or 32, nb < 0). */
 lx_status lx_set_depth(lx_ctx* ctx, int depth, int th, int nb);
 
 /* Practical HBM bandwidth of plain streaming HIP kernels, the calibration

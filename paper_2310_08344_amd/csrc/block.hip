@@ -1,0 +1,477 @@
+// D Leja iterations per launch (D = 3 or 4) on LDS-resident tiles (gfx950),
+// FP64, with speculative windows.
+//
+// Launch w of the plain loop advances the Newton recurrence (Sec. 2.1,
+// Eq. (2)) from y_m (m = wD) through y_{m+1} .. y_{m+D} on a tile staged
+// once with a D-cell halo (D R cells for a stencil of radius R), so the
+// basis vector is read and written once and every output once per D
+// iterations.  The stop rule (Sec. 2.2) for term m+j needs norms of
+// y_{m+j} and of p_{m+j} over the whole grid, which exist only after the
+// launch; the window therefore adds all D terms speculatively to every
+// output still iterating and records, for every j, the sums of squares of
+// y_{m+j} and of each output as it stands after term m+j.  The outputs of a
+// window go to a second buffer, so its inputs survive it.
+//
+// The next launch adds the partial sums (the same fixed order in every
+// workgroup) and applies the stop rule at m+1, .., m+D in turn.  If no output
+// stopped inside the window, the speculation was exact and the loop goes on
+// from y_{m+D}.  If some did, the launch re-executes the window from the same
+// inputs with the terms each output really takes (up to its stopping term),
+// writing stopped outputs to their final buffer; y_{m+D} and the outputs
+// that go on come out bitwise as before (explicit-FMA stencils, the same
+// terms in the same order).  Every output therefore takes exactly the terms
+// of the one-iteration loop, in the same order, and the iteration counts are
+// those of one-iteration launches up to the order of the norm reductions.
+//
+// Buffers: window w reads y_m from v (w = 0) or ybuf[(w-1) & 1] and writes
+// y_{m+D} to ybuf[w & 1]; it reads the outputs from p (w even) or p2 (w odd)
+// and writes them to the other; a re-execution writes stopped outputs to p,
+// the caller's buffer, so every final result lands there.
+//
+// Tiles are 128 columns by TH rows, four wavefronts; LDS holds two levels
+// (ping-pong) of ROWS = TH + 2H rows and 128 + 2H (rounded up to even)
+// columns, H = D R: level j
+// is valid on the tile plus an (D - j) R halo, and level D is formed in
+// registers on the tile only.
+#include <hip/hip_runtime.h>
+
+#include "lx_device.h"
+#include "sweep_device.h"
+#include "tile_device.h"
+
+namespace lx {
+namespace {
+
+using namespace dev;
+
+template <int OP, int TH, int D>
+struct BlockLds {
+    static constexpr int R = radius<OP>();
+    static constexpr int H = D * R;              // halo of level 0
+    static constexpr int CO = (H + 1) & ~1;      // column offset: even, so column pairs are 16-byte aligned
+    static constexpr int ROWS = TH + 2 * H;
+    static constexpr int P = kPairTW + 2 * CO;   // row pitch in doubles
+    double a[ROWS][P];                           // levels 0, 2, ...: LDS row r = tile row r - H,
+    double b[ROWS][P];                           // levels 1, 3, ...: LDS column c = tile column c - CO
+};
+
+// y_m of one tile as this thread stages it, loaded a tile ahead
+template <int TH, int D, int R>
+struct BlockY {
+    static constexpr int H = D * R, ROWS = TH + 2 * H;
+    static constexpr int RM = (ROWS + kPairWaves - 1) / kPairWaves;   // rows per wavefront
+    static constexpr int E = ROWS * 2 * H;                             // edge cells
+    static constexpr int EQ = (E + kBlockThreads - 1) / kBlockThreads; // edge cells per thread
+    double x[RM], y[RM];
+    double edge[EQ];
+};
+
+template <int K, int TH, int D, int R>
+__device__ __forceinline__ BlockY<TH, D, R> load_block_y(const TileArgs<K>& a, const double* __restrict__ yin,
+                                                         const int tile) {
+    using Y = BlockY<TH, D, R>;
+    constexpr int H = Y::H;
+    Y r;
+    const int nx = a.nx, ny = a.ny;
+    const int x0 = (tile % a.tiles_x) * kPairTW, y0 = (tile / a.tiles_x) * TH;
+    const int tid = flat_tid(), lane = tid & 63, w = tid >> 6;
+    const int gc = wrap(x0 + 2 * lane, nx);       // even: nx and x0 are even
+#pragma unroll
+    for (int i = 0; i < Y::RM; ++i) {
+        const int row = w + i * kPairWaves;
+        r.x[i] = 0.0;
+        r.y[i] = 0.0;
+        if (row < Y::ROWS) {
+            const long g = wrap(y0 - H + row, ny) * static_cast<long>(nx) + gc;
+            const double2 t = *reinterpret_cast<const double2*>(yin + g);
+            r.x[i] = t.x;
+            r.y[i] = t.y;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < Y::EQ; ++q) {
+        const int e = tid + q * kBlockThreads;
+        r.edge[q] = 0.0;
+        if (e < Y::E) {
+            // tile column -H .. -1 (qq < H) or 128 .. 127+H
+            const int row = e / (2 * H), qq = e % (2 * H);
+            const int tc = (qq < H) ? qq - H : kPairTW + (qq - H);
+            r.edge[q] = yin[wrap(y0 - H + row, ny) * static_cast<long>(nx) + wrap(x0 + tc, nx)];
+        }
+    }
+    return r;
+}
+
+// the shifted operator at the column pair j, j+1 of LDS row r of `src`
+template <int OP, int P>
+__device__ __forceinline__ void level_pair(const Sten& st, const double shift, const double (*src)[P], const int r,
+                                           const int j, double (&o)[2]) {
+    if constexpr (radius<OP>() == 2) {
+        shifted_pair3(st, shift, src[r - 2], src[r - 1], src[r], src[r + 1], src[r + 2], j, o);
+    } else {
+        shifted_pair<OP>(st, shift, src[r - 1], src[r], src[r + 1], nullptr, nullptr, nullptr, j, o);
+    }
+}
+
+template <int OP, int P>
+__device__ __forceinline__ double level_one(const Sten& st, const double shift, const double (*src)[P], const int r,
+                                            const int j) {
+    if constexpr (radius<OP>() == 2) {
+        return shifted_one3(st, shift, src[r - 2], src[r - 1], src[r], src[r + 1], src[r + 2], j);
+    } else {
+        return shifted_one<OP>(st, shift, src[r - 1], src[r], src[r + 1], nullptr, nullptr, nullptr, j);
+    }
+}
+
+template <int OP, int K, int TH, int D>
+__device__ __forceinline__ void block_tile(const TileArgs<K>& a, BlockLds<OP, TH, D>& S,
+                                           const double* __restrict__ yin, double* __restrict__ yout,
+                                           const double* const (&pin)[K], double* const (&pout)[K], const int m,
+                                           const bool first, const int (&nt)[K], double (&sy)[D],
+                                           double (&sp)[K][D], const int tile, BlockY<TH, D, radius<OP>()>& ty,
+                                           const int next) {
+    using L = BlockLds<OP, TH, D>;
+    using Y = BlockY<TH, D, radius<OP>()>;
+    constexpr int R = L::R, H = L::H, CO = L::CO, ROWS = L::ROWS, P = L::P;
+    constexpr int RW = TH / kPairWaves;           // tile rows per wavefront
+    const int nx = a.nx, ny = a.ny;
+    const int x0 = (tile % a.tiles_x) * kPairTW, y0 = (tile / a.tiles_x) * TH;
+    const int tid = flat_tid(), lane = tid & 63, w = tid >> 6;
+    const int j0 = CO + 2 * lane;                 // LDS column of this lane's pair
+    const int gcol = x0 + 2 * lane;
+
+    // ---- the outputs of this thread's rows, fetched while the tile is staged ----
+    double2 pv[K][RW];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+        for (int i = 0; i < RW; ++i) pv[k][i] = double2{0.0, 0.0};
+        if (first || nt[k] == 0) continue;
+#pragma unroll
+        for (int i = 0; i < RW; ++i) {
+            const int grow = y0 + w + i * kPairWaves;
+            if (gcol < nx && grow < ny) pv[k][i] = ld_stream(pin[k] + static_cast<long>(grow) * nx + gcol);
+        }
+    }
+    // ---- level 0: y_m on rows -H..TH+H-1, columns -H..127+H ----
+#pragma unroll
+    for (int i = 0; i < Y::RM; ++i) {
+        const int r = w + i * kPairWaves;
+        if (r < ROWS) {
+            double2 t;
+            t.x = ty.x[i];
+            t.y = ty.y[i];
+            *reinterpret_cast<double2*>(&S.a[r][j0]) = t;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < Y::EQ; ++q) {
+        const int e = tid + q * kBlockThreads;
+        if (e < Y::E) {
+            const int row = e / (2 * H), qq = e % (2 * H);
+            const int tc = (qq < H) ? qq - H : kPairTW + (qq - H);
+            S.a[row][CO + tc] = ty.edge[q];
+        }
+    }
+    __syncthreads();
+    ty = load_block_y<K, TH, D, R>(a, yin, next);   // the next tile's y_m, in flight during this one
+    if (first) {
+        // p_0 = d_0 y_0
+#pragma unroll
+        for (int i = 0; i < RW; ++i) {
+            const double2 c0 = *reinterpret_cast<const double2*>(&S.a[H + w + i * kPairWaves][j0]);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const double d0 = a.coef[k * a.ld];
+                pv[k][i].x = d0 * c0.x;
+                pv[k][i].y = d0 * c0.y;
+            }
+        }
+    }
+
+    // ---- levels 1 .. D-1 in LDS, each followed by the terms it gives ----
+#pragma unroll
+    for (int j = 1; j < D; ++j) {
+        const double (*src)[P] = ((j - 1) & 1) ? S.b : S.a;
+        double (*dst)[P] = (j & 1) ? S.b : S.a;
+        const double shift = a.xi[m + j - 1];
+        const int r_lo = j * R, r_hi = ROWS - j * R;    // level j on LDS rows [r_lo, r_hi)
+#pragma unroll
+        for (int i = 0; i < (ROWS + kPairWaves - 1) / kPairWaves; ++i) {
+            const int r = r_lo + w + i * kPairWaves;
+            if (r < r_hi) {
+                double o[2];
+                level_pair<OP, P>(a.st, shift, src, r, j0, o);
+                double2 t;
+                t.x = o[0];
+                t.y = o[1];
+                *reinterpret_cast<double2*>(&dst[r][j0]) = t;
+            }
+        }
+        // the (D - j) R columns on each side of the tile
+        const int side = H - j * R;
+        const int ne = (r_hi - r_lo) * 2 * side;
+        for (int e = tid; e < ne; e += kBlockThreads) {
+            const int r = r_lo + e / (2 * side), qq = e % (2 * side);
+            const int tc = (qq < side) ? qq - side : kPairTW + (qq - side);
+            dst[r][CO + tc] = level_one<OP, P>(a.st, shift, src, r, CO + tc);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < RW; ++i) {
+            const int grow = y0 + w + i * kPairWaves;
+            if (gcol < nx && grow < ny) {
+                const double2 y = *reinterpret_cast<const double2*>(&dst[H + w + i * kPairWaves][j0]);
+                sy[j - 1] += y.x * y.x + y.y * y.y;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    if (nt[k] < j) continue;
+                    const double dj = a.coef[k * a.ld + m + j];
+                    pv[k][i].x = fma(dj, y.x, pv[k][i].x);
+                    pv[k][i].y = fma(dj, y.y, pv[k][i].y);
+                    sp[k][j - 1] += pv[k][i].x * pv[k][i].x + pv[k][i].y * pv[k][i].y;
+                }
+            }
+        }
+    }
+
+    // ---- level D on the tile: y_{m+D}, the last term, the outputs ----
+    {
+        const double (*src)[P] = ((D - 1) & 1) ? S.b : S.a;
+        const double shift = a.xi[m + D - 1];
+#pragma unroll
+        for (int i = 0; i < RW; ++i) {
+            const int r = H + w + i * kPairWaves;
+            const int grow = y0 + w + i * kPairWaves;
+            double o[2];
+            level_pair<OP, P>(a.st, shift, src, r, j0, o);
+            if (gcol < nx && grow < ny) {
+                const long idx = static_cast<long>(grow) * nx + gcol;
+                double2 t;
+                t.x = o[0];
+                t.y = o[1];
+                *reinterpret_cast<double2*>(yout + idx) = t;
+                sy[D - 1] += o[0] * o[0] + o[1] * o[1];
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    if (nt[k] == 0) continue;
+                    if (nt[k] >= D) {
+                        const double dD = a.coef[k * a.ld + m + D];
+                        pv[k][i].x = fma(dD, o[0], pv[k][i].x);
+                        pv[k][i].y = fma(dD, o[1], pv[k][i].y);
+                        sp[k][D - 1] += pv[k][i].x * pv[k][i].x + pv[k][i].y * pv[k][i].y;
+                    }
+                    st_stream(pout[k] + idx, pv[k][i]);
+                }
+            }
+        }
+    }
+    __syncthreads();   // the next tile overwrites LDS
+}
+
+// The state entering a launch from the state of the previous launch and its
+// partial sums tot[(j-1)(1+K) + q], q = 0: |y_{m+j}|^2, q = 1+k: |p_k|^2
+// after term m+j (j = 1..D).
+template <int K, int D>
+__device__ __forceinline__ SweepState block_decide(const SweepArgs& a, const LoopCtl& ctl, const SweepState& prev,
+                                                   const double (&tot)[D * (1 + K)]) {
+    SweepState nx = prev;
+    if (prev.blk_mode == 1) {
+        // the window was re-executed with its stops: the outputs that took all
+        // D terms go on from y_{m+D}
+        nx.blk_mode = 0;
+        nx.iter = prev.iter + D;
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            nx.active[k] = (prev.active[k] && prev.nt[k] == D) ? 1 : 0;
+            nx.nt[k] = nx.active[k] ? D : 0;
+            any = any || nx.active[k];
+        }
+        if (!any) nx.done = 1;
+        return nx;
+    }
+    const int m = prev.iter;
+    bool stopped = false, nonfinite = false, notconv = false;
+    int nt[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) nt[k] = prev.active[k] ? D : 0;
+    for (int j = 1; j <= D; ++j) {
+        const double ynorm = sqrt(tot[(j - 1) * (1 + K)]) * a.inv_sqrtN;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (nt[k] != D) continue;   // inactive, or stopped earlier in this window
+            const double pn = sqrt(tot[(j - 1) * (1 + K) + 1 + k]) * a.inv_sqrtN;
+            const double e = fabs(a.coef[k * a.ld + m + j]) * ynorm;
+            const double thr = ctl.rtol * pn + ctl.atol;
+            nx.err[k] = e;
+            nx.pnorm[k] = pn;
+            nx.ynorm = ynorm;
+            if (!isfinite(pn) || !isfinite(e)) {
+                nonfinite = true;
+            } else if (e <= thr) {
+                nt[k] = -j;   // stopped after term m+j (also when j = D)
+                nx.iters[k] = m + j;
+                stopped = true;
+            } else if (m + j >= ctl.max_iters) {
+                nt[k] = -j;
+                nx.iters[k] = m + j;
+                stopped = true;
+                notconv = true;
+            }
+        }
+    }
+    if (nonfinite) {
+        nx.status = 4;   // LX_ENONFINITE
+        nx.done = 1;
+        return nx;
+    }
+    if (stopped) {
+        // re-execute the window with the stops: nt[k] = -j for an output
+        // that stopped after term m+j, D for one that goes on, 0 otherwise
+        nx.blk_mode = 1;
+#pragma unroll
+        for (int k = 0; k < K; ++k) nx.nt[k] = nt[k];
+        if (notconv) nx.status = 3;   // LX_ENOTCONV
+    } else {
+        nx.iter = m + D;
+    }
+    return nx;
+}
+
+template <int OP, int K, int TH, int D>
+__global__ __launch_bounds__(kBlockThreads) void leja_block(SweepArgs a, const int L) {
+    LoopCtl* __restrict__ ctl = a.ctl;
+    if (loop_ended(ctl)) return;
+    constexpr int NV = D * (1 + K);
+    __shared__ BlockLds<OP, TH, D> S;
+    __shared__ SweepState s_cur;
+    const int tid = flat_tid();
+    const int wg = static_cast<int>(blockIdx.x);
+    if (L == 0) {
+        if (tid == 0) {
+            SweepState st = ctl->slot[0];
+            st.blk_mode = 0;
+            st.iter = 0;
+            for (int k = 0; k < kKMax; ++k) st.nt[k] = (k < K && st.active[k]) ? D : 0;
+            st.n_work = 1;
+            double b = 16.0;
+            for (int k = 0; k < K; ++k) b += st.nt[k] ? 8.0 : 0.0;
+            st.bytes_pp = b;
+            s_cur = st;
+            if (wg == 0) ctl->slot[0] = st;
+        }
+    } else {
+        double tot[NV];
+        sum_partials<NV>(a.partials + static_cast<long>((L - 1) & 1) * a.nb * NV, a.nb, tot);
+        if (tid == 0) {
+            SweepState st = block_decide<K, D>(a, *ctl, ctl->slot[(L - 1) & 1], tot);
+            if (!st.done) {
+                st.n_work += 1;
+                double b = 16.0;
+                for (int k = 0; k < K; ++k) b += st.nt[k] ? (st.iter == 0 ? 8.0 : 16.0) : 0.0;
+                st.bytes_pp += b;
+            }
+            s_cur = st;
+            if (wg == 0) {
+                ctl->slot[L & 1] = st;
+                if (st.done) ctl->slot[2] = st;   // this launch does no work
+            }
+        }
+    }
+    __syncthreads();
+    if (s_cur.done) return;
+    const int m = s_cur.iter;
+    const int win = m / D;
+    const bool redo = s_cur.blk_mode == 1;
+    int nt[K];   // terms each output takes in this launch
+    const double* pin[K];
+    double* pout[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int q = s_cur.nt[k];
+        nt[k] = q < 0 ? -q : q;
+        pin[k] = (win & 1) ? a.p2[k] : a.p[k];
+        double* nxt = (win & 1) ? a.p[k] : a.p2[k];
+        pout[k] = (redo && q < 0) ? a.p[k] : nxt;   // a stopped output's final buffer
+    }
+    const double* __restrict__ yin = (win == 0) ? a.v : static_cast<const double*>(a.ybuf[(win - 1) & 1]);
+    double* __restrict__ yout = static_cast<double*>(a.ybuf[win & 1]);
+
+    double sy[D], sp[K][D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        sy[j] = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) sp[k][j] = 0.0;
+    }
+    const int T = a.tiles_x * a.tiles_y;
+    const TileArgs<K> ta = tile_args<OP, K>(a);
+    // this workgroup's tiles: a band of its XCD, as in the two-iteration kernel
+    int first, step, end;
+    if (a.nb >= 8 && (a.nb & 7) == 0) {
+        const int x = wg & 7, nbx = a.nb >> 3;
+        first = static_cast<int>((static_cast<long>(x) * T) >> 3) + (wg >> 3);
+        step = nbx;
+        end = static_cast<int>((static_cast<long>(x + 1) * T) >> 3);
+    } else {
+        first = wg;
+        step = a.nb;
+        end = T;
+    }
+    BlockY<TH, D, radius<OP>()> ty;
+    if (first < end) ty = load_block_y<K, TH, D, radius<OP>()>(ta, yin, first);
+    for (int t = first; t < end; t += step) {
+        const int next = (t + step < end) ? t + step : t;
+        block_tile<OP, K, TH, D>(ta, S, yin, yout, pin, pout, m, win == 0, nt, sy, sp, t, ty, next);
+    }
+    double v[NV];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        v[j * (1 + K)] = sy[j];
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[j * (1 + K) + 1 + k] = sp[k][j];
+    }
+    block_sum<NV>(v);
+    if (tid == 0) {
+        double* __restrict__ Pp = a.partials + static_cast<long>(L & 1) * a.nb * NV + static_cast<long>(wg) * NV;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) Pp[q] = v[q];
+    }
+}
+
+template <int OP, int K, int D>
+hipError_t launch_block_th(int th, const SweepArgs& a, int L, hipStream_t s) {
+    const dim3 block(64, kPairWaves), grid(a.nb);
+    switch (th) {
+        case 8: hipLaunchKernelGGL((leja_block<OP, K, 8, D>), grid, block, 0, s, a, L); break;
+        case 16: hipLaunchKernelGGL((leja_block<OP, K, 16, D>), grid, block, 0, s, a, L); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int OP, int D>
+hipError_t launch_block_k(int K, int th, const SweepArgs& a, int L, hipStream_t s) {
+    switch (K) {
+        case 1: return launch_block_th<OP, 1, D>(th, a, L, s);
+        case 2: return launch_block_th<OP, 2, D>(th, a, L, s);
+        case 3: return launch_block_th<OP, 3, D>(th, a, L, s);
+        case 4: return launch_block_th<OP, 4, D>(th, a, L, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_leja_block(int op, int K, int th, int depth, const SweepArgs& a, int L, hipStream_t s) {
+    if (a.nb < 1 || a.nx % 2 != 0 || a.nx < 2 || a.ny < 2) return hipErrorInvalidValue;
+    if (a.tiles_x != (a.nx + kPairTW - 1) / kPairTW || a.tiles_y != (a.ny + th - 1) / th)
+        return hipErrorInvalidValue;
+    if (op != kOpDiffAdv || a.nx < depth || a.ny < depth) return hipErrorInvalidValue;   // halo reach
+    if (depth == 3) return launch_block_k<kOpDiffAdv, 3>(K, th, a, L, s);
+    if (depth == 4) return launch_block_k<kOpDiffAdv, 4>(K, th, a, L, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace lx

@@ -245,15 +245,20 @@ struct LejaCall {
 };
 
 // Iterations per launch for this call: forced by lx_set_depth, else the
-// tuned entry's, else two.  Two needs FP64 sweeps and 16-byte pairs.
+// tuned entry's, else two.  Two or more need FP64 sweeps and 16-byte pairs;
+// three and four (speculative windows) the five-point diffusion-advection
+// operator, else two are used.
 void choose_depth(const lx_ctx* ctx, const lx_operator& op, int K, bool vec2_ok, Tile& t) {
     const bool pair_ok = op.prec == LX_FP64 && vec2_ok && op.nx % 2 == 0;
     auto it = ctx->tuned.find(std::make_tuple(op.kind, op.nx, op.ny, K, op.prec));
     int depth = 2;
     if (ctx->depth_forced != 0) depth = ctx->depth_forced;
     else if (it != ctx->tuned.end()) depth = it->second.depth;
-    t.depth = (depth == 2 && pair_ok) ? 2 : 1;
-    if (it != ctx->tuned.end() && it->second.depth == 2) {
+    // windows stage a halo of `depth` cells, which the periodic index wrap
+    // allows only on sides of at least that many cells
+    if (depth >= 3 && (op.kind != LX_OP_DIFFADV2D || op.nx < depth || op.ny < depth)) depth = 2;
+    t.depth = (depth >= 2 && pair_ok) ? depth : 1;
+    if (it != ctx->tuned.end() && it->second.depth >= 2 && it->second.depth == t.depth) {
         t.th = it->second.th;
         t.pnb = it->second.pnb;
     } else {
@@ -262,8 +267,19 @@ void choose_depth(const lx_ctx* ctx, const lx_operator& op, int K, bool vec2_ok,
     }
     if (ctx->pair_th != 0) t.th = ctx->pair_th;
     if (ctx->pair_nb != 0) t.pnb = ctx->pair_nb;
-    // a radius-2 stencil stages 8 edge cells per row: tiles of at most 16 rows
-    if (op.kind == LX_OP_DIFFADV2D_UP3 && t.th > 16) t.th = 16;
+    // a radius-2 stencil stages 8 edge cells per row, and three or four
+    // iterations per launch hold two levels in LDS: tiles of at most 16 rows
+    if ((op.kind == LX_OP_DIFFADV2D_UP3 || t.depth >= 3) && t.th > 16) t.th = 16;
+}
+
+lx_status ensure_blk_ws(lx_ctx* ctx, int K) {
+    while (static_cast<int>(ctx->blk_ws.size()) < K) {
+        double* p = nullptr;
+        if (hipMalloc(&p, sizeof(double) * ctx->n_max) != hipSuccess)
+            return fail(ctx, LX_ENOMEM, "second output buffers of the multi-iteration loop");
+        ctx->blk_ws.push_back(p);
+    }
+    return LX_OK;
 }
 
 // workgroups of a leja_pair grid: at most one per tile, a multiple of 8 once
@@ -291,9 +307,12 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
     Tile t = pick_tile(ctx, op, K, vec2);
     choose_depth(ctx, op, K, vec2, t);
     const bool pair = t.depth == 2;
+    const bool blk = t.depth >= 3;          // speculative windows of D iterations
+    const int D = t.depth;
     // coefficients the loop may read: d_0..d_{NC-1} (a two-iteration launch
-    // also forms the norm its last, deferred term would give)
-    const int NC = pair ? M + 1 : M;
+    // also forms the norm its last, deferred term would give; a window that
+    // starts below max_iters reads up to D terms on)
+    const int NC = blk ? M + D : (pair ? M + 1 : M);
 
     // ---- planner: Leja points now, Newton coefficients chunk by chunk ----
     const auto t0 = std::chrono::steady_clock::now();
@@ -341,7 +360,7 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
     SweepArgs a{};
     a.nx = nx;
     a.ny = ny;
-    if (pair) {
+    if (pair || blk) {
         a.tiles_x = (nx + 127) / 128;
         a.tiles_y = (ny + t.th - 1) / t.th;
         a.nb = pair_grid(t.pnb, a.tiles_x * a.tiles_y);
@@ -359,11 +378,16 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
     a.u = q.u;
     a.u32 = ctx->u32;
     for (int k = 0; k < K; ++k) a.p[k] = q.out[k];
+    if (blk) {
+        s = ensure_blk_ws(ctx, K);
+        if (s != LX_OK) return s;
+        for (int k = 0; k < K; ++k) a.p2[k] = ctx->blk_ws[k];
+    }
     a.coef = ctx->coef;
     a.xi = ctx->xi;
     a.ctl = ctx->ctl;
     const int opcode = opcode_of(op.kind);
-    s = ensure_partials(ctx, 2 * static_cast<size_t>(a.nb) * (1 + K) * (pair ? 2 : 1));
+    s = ensure_partials(ctx, 2 * static_cast<size_t>(a.nb) * (1 + K) * (blk ? D : (pair ? 2 : 1)));
     if (s != LX_OK) return s;
     a.partials = ctx->partials;
 
@@ -373,9 +397,13 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
     // decision.  pair: launch L takes the decisions at terms 2L-1 and 2L and
     // then sweeps 2L and 2L+1; by launch ceil(max_iters/2) the loop has
     // ended, and the launch after it publishes a flush's final state.
+    // blk: windows start below max_iters (at most ceil(max_iters/D) of
+    // them), each stop event re-executes one (at most K), and one launch
+    // after the last publishes the final state.
     const int max_iters = q.o.max_iters;
-    const int last = pair ? (max_iters + 1) / 2 + 1 : max_iters;   // last launch index
-    const int per = pair ? 2 : 1;                                   // iterations per launch
+    const int last = blk ? (max_iters + D - 1) / D + K + 2
+                         : (pair ? (max_iters + 1) / 2 + 1 : max_iters);   // last launch index
+    const int per = blk ? D : (pair ? 2 : 1);                               // iterations per launch
     if (ctx->timing) {
         s = ensure_timing_events(ctx, static_cast<size_t>(last) + 2);
         if (s != LX_OK) return s;
@@ -390,7 +418,8 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
         if (s != LX_OK) return s;
         for (int i = 0; i < n; ++i) {
             const int L = launched + i;
-            if (pair) LX_HIP(ctx, lx::launch_leja_pair(opcode, K, t.th, a, L, ctx->stream));
+            if (blk) LX_HIP(ctx, lx::launch_leja_block(opcode, K, t.th, D, a, L, ctx->stream));
+            else if (pair) LX_HIP(ctx, lx::launch_leja_pair(opcode, K, t.th, a, L, ctx->stream));
             else LX_HIP(ctx, lx::launch_leja_sweep(opcode, K, fp32, t, a, L, ctx->stream));
             if (ctx->timing && L < last) LX_HIP(ctx, hipEventRecord(ctx->tev[L + 1], ctx->stream));
         }
@@ -424,7 +453,14 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
     // algorithmic bytes of the launches that did work
     double bytes = 0.0;
     const double ub = op.kind == LX_OP_BURGERS2D ? 8.0 : 0.0;
-    if (!pair) {
+    if (blk) {
+        // counted on the device by the launches that did work (windows and
+        // their re-executions): y in and out, and per output taking terms a
+        // read and a write of p (the first window writes p without reading it)
+        S.n_launch = fin.n_work;
+        S.n_apply = D * fin.n_work;
+        bytes = fin.bytes_pp * static_cast<double>(N);
+    } else if (!pair) {
         // per sweep: the basis read and write, the Burgers state read, and per
         // unconverged output a read and a write of p (sweep 0 writes
         // p_1 = d_0 v + d_1 y_1 without reading it)
@@ -732,6 +768,7 @@ void lx_destroy(lx_ctx* ctx) {
     for (double* p : ctx->ybuf) (void)hipFree(p);
     for (double* p : ctx->ws) (void)hipFree(p);
     for (double* p : ctx->sub_ws) (void)hipFree(p);
+    for (double* p : ctx->blk_ws) (void)hipFree(p);
     (void)hipFree(ctx->u32);
     (void)hipFree(ctx->partials);
     (void)hipFree(ctx->ctl);
@@ -1128,8 +1165,8 @@ lx_status lx_exprb_step(lx_ctx* ctx, const lx_operator* op, int scheme, const do
 
 lx_status lx_set_depth(lx_ctx* ctx, int depth, int th, int nb) {
     if (ctx == nullptr) return LX_EINVAL;
-    if (depth < 0 || depth > 2 || !(th == 0 || th == 8 || th == 16 || th == 32) || nb < 0)
-        return fail(ctx, LX_EINVAL, "depth %d, th %d, nb %d: need depth 0..2, th 0/8/16/32, nb >= 0", depth, th, nb);
+    if (depth < 0 || depth > 4 || !(th == 0 || th == 8 || th == 16 || th == 32) || nb < 0)
+        return fail(ctx, LX_EINVAL, "depth %d, th %d, nb %d: need depth 0..4, th 0/8/16/32, nb >= 0", depth, th, nb);
     ctx->depth_forced = depth;
     ctx->pair_th = th;
     ctx->pair_nb = nb;
@@ -1158,7 +1195,7 @@ lx_status lx_tune(lx_ctx* ctx, const lx_operator* op, int K, int sweeps, char* r
     if (sweeps < 1 || sweeps > 200) return fail(ctx, LX_EINVAL, "sweeps %d outside 1..200", sweeps);
     const int nx = op->nx, ny = op->ny;
     const size_t N = static_cast<size_t>(nx) * ny;
-    const int ld = sweeps + 8;
+    const int ld = sweeps + 16;   // windows read up to 2 depths past the timed sweeps
     s = ensure_xi(ctx, ld);
     if (s != LX_OK) return s;
     // scratch: K outputs (+ the Burgers state), all zero, so that values stay
@@ -1259,61 +1296,79 @@ lx_status lx_tune(lx_ctx* ctx, const lx_operator* op, int K, int sweeps, char* r
             best = t;
         }
     }
-    // two iterations per launch (FP64, even nx): tile rows x workgroups
+    // several iterations per launch (FP64, even nx): depth x tile rows x
+    // workgroups; depths 3 and 4 (speculative windows) for the five-point
+    // diffusion-advection operator only
     best.depth = 1;
     double best_pair_us = 1e300;
     if (op->prec == LX_FP64 && nx % 2 == 0) {
         const int tiles_x = (nx + 127) / 128;
-        for (int th : {8, 16, 32}) {
-            if (th > 16 && op->kind == LX_OP_DIFFADV2D_UP3) continue;   // radius 2: at most 16 rows
-            const int tiles = tiles_x * ((ny + th - 1) / th);
-            for (int pnb : {0, 2048, 1536, 1024, 768, 512, 256}) {
-                if (pnb != 0 && pnb >= tiles) continue;
-                SweepArgs a{};
-                a.nx = nx;
-                a.ny = ny;
-                a.tiles_x = tiles_x;
-                a.tiles_y = (ny + th - 1) / th;
-                a.nb = pair_grid(pnb, tiles);
-                a.ld = ld;
-                set_stencil(a, *op, -2.0, 1.0);
-                a.inv_sqrtN = 1.0 / std::sqrt(static_cast<double>(N));
-                a.v = ctx->ybuf[0];
-                a.ybuf[0] = ctx->ybuf[0];
-                a.ybuf[1] = ctx->ybuf[1];
-                a.u = op->kind == LX_OP_BURGERS2D ? scratch + static_cast<size_t>(K) * N : nullptr;
-                for (int k = 0; k < K; ++k) a.p[k] = scratch + static_cast<size_t>(k) * N;
-                a.coef = ctx->coef;
-                a.xi = ctx->xi;
-                s = ensure_partials(ctx, 4 * static_cast<size_t>(a.nb) * (1 + K));
+        for (int depth : {2, 3, 4}) {
+            if (depth >= 3 && (op->kind != LX_OP_DIFFADV2D || nx < depth || ny < depth)) continue;
+            if (depth >= 3) {
+                s = ensure_blk_ws(ctx, K);
                 if (s != LX_OK) return cleanup(s);
-                a.partials = ctx->partials;
-                a.ctl = ctx->ctl;
-                if (hipMemcpyAsync(ctx->ctl, &init, sizeof(LoopCtl), hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
-                    return cleanup(fail(ctx, LX_EDEVICE, "state upload failed"));
-                // launches 0 and 1 warm up; launches 2 .. n+1 (2n iterations) are timed
-                const int n = std::max(1, sweeps / 2);
-                hipError_t e = hipSuccess;
-                for (int L = 0; L < 2 && e == hipSuccess; ++L) e = lx::launch_leja_pair(opcode, K, th, a, L, ctx->stream);
-                if (e == hipSuccess) e = hipEventRecord(ctx->tev[0], ctx->stream);
-                for (int L = 2; L < n + 2 && e == hipSuccess; ++L)
-                    e = lx::launch_leja_pair(opcode, K, th, a, L, ctx->stream);
-                if (e == hipSuccess) e = hipEventRecord(ctx->tev[1], ctx->stream);
-                if (e == hipSuccess) e = hipEventSynchronize(ctx->tev[1]);
-                if (e != hipSuccess)
-                    return cleanup(fail(ctx, LX_EDEVICE, "tuning launch failed: %s", hipGetErrorString(e)));
-                const double us = elapsed(ctx->tev[0], ctx->tev[1]) * 1e3 / (2.0 * n);
-                char line[112];
-                std::snprintf(line, sizeof(line), "2 64 4 %d 2 %d %.3f\n", th, a.nb, us);
-                rep += line;
-                if (us < best_pair_us) {
-                    best_pair_us = us;
-                    best.th = th;
-                    best.pnb = pnb;
+            }
+            for (int th : {8, 16, 32}) {
+                // radius 2, and two LDS levels of windows: at most 16 rows
+                if (th > 16 && (op->kind == LX_OP_DIFFADV2D_UP3 || depth >= 3)) continue;
+                const int tiles = tiles_x * ((ny + th - 1) / th);
+                for (int pnb : {0, 2048, 1536, 1024, 768, 512, 256}) {
+                    if (pnb != 0 && pnb >= tiles) continue;
+                    if (depth >= 3 && pnb > 1024) continue;
+                    SweepArgs a{};
+                    a.nx = nx;
+                    a.ny = ny;
+                    a.tiles_x = tiles_x;
+                    a.tiles_y = (ny + th - 1) / th;
+                    a.nb = pair_grid(pnb, tiles);
+                    a.ld = ld;
+                    set_stencil(a, *op, -2.0, 1.0);
+                    a.inv_sqrtN = 1.0 / std::sqrt(static_cast<double>(N));
+                    a.v = ctx->ybuf[0];
+                    a.ybuf[0] = ctx->ybuf[0];
+                    a.ybuf[1] = ctx->ybuf[1];
+                    a.u = op->kind == LX_OP_BURGERS2D ? scratch + static_cast<size_t>(K) * N : nullptr;
+                    for (int k = 0; k < K; ++k) a.p[k] = scratch + static_cast<size_t>(k) * N;
+                    if (depth >= 3)
+                        for (int k = 0; k < K; ++k) a.p2[k] = ctx->blk_ws[k];
+                    a.coef = ctx->coef;
+                    a.xi = ctx->xi;
+                    s = ensure_partials(ctx, 2 * static_cast<size_t>(depth) * a.nb * (1 + K));
+                    if (s != LX_OK) return cleanup(s);
+                    a.partials = ctx->partials;
+                    a.ctl = ctx->ctl;
+                    if (hipMemcpyAsync(ctx->ctl, &init, sizeof(LoopCtl), hipMemcpyHostToDevice, ctx->stream) !=
+                        hipSuccess)
+                        return cleanup(fail(ctx, LX_EDEVICE, "state upload failed"));
+                    auto go = [&](int L) {
+                        return depth >= 3 ? lx::launch_leja_block(opcode, K, th, depth, a, L, ctx->stream)
+                                          : lx::launch_leja_pair(opcode, K, th, a, L, ctx->stream);
+                    };
+                    // launches 0 and 1 warm up; launches 2 .. n+1 (depth * n iterations) are timed
+                    const int n = std::max(1, sweeps / depth);
+                    hipError_t e = hipSuccess;
+                    for (int L = 0; L < 2 && e == hipSuccess; ++L) e = go(L);
+                    if (e == hipSuccess) e = hipEventRecord(ctx->tev[0], ctx->stream);
+                    for (int L = 2; L < n + 2 && e == hipSuccess; ++L) e = go(L);
+                    if (e == hipSuccess) e = hipEventRecord(ctx->tev[1], ctx->stream);
+                    if (e == hipSuccess) e = hipEventSynchronize(ctx->tev[1]);
+                    if (e != hipSuccess)
+                        return cleanup(fail(ctx, LX_EDEVICE, "tuning launch failed: %s", hipGetErrorString(e)));
+                    const double us = elapsed(ctx->tev[0], ctx->tev[1]) * 1e3 / (static_cast<double>(depth) * n);
+                    char line[112];
+                    std::snprintf(line, sizeof(line), "%d 64 4 %d 2 %d %.3f\n", depth, th, a.nb, us);
+                    rep += line;
+                    if (us < best_pair_us) {
+                        best_pair_us = us;
+                        best.th = th;
+                        best.pnb = pnb;
+                        best.depth = depth;
+                    }
                 }
             }
         }
-        if (best_pair_us < best_us) best.depth = 2;
+        if (!(best_pair_us < best_us)) best.depth = 1;
     }
     const double best_iter_us = std::min(best_us, best_pair_us);
     ctx->tuned[std::make_tuple(op->kind, nx, ny, K, op->prec)] = best;

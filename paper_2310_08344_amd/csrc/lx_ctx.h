@@ -42,6 +42,7 @@ struct lx_ctx {
     float* u32 = nullptr;                   // Burgers state in FP32 (FP32 sweeps)
     double* ws[3] = {nullptr, nullptr, nullptr};  // integrator stages (allocated on first use)
     std::vector<double*> sub_ws;            // substep workspaces (phi_i(tau A) v, two states)
+    std::vector<double*> blk_ws;            // second buffer per output of speculative windows
     double* partials = nullptr;
     size_t partials_len = 0;
     lx::LoopCtl* ctl = nullptr;

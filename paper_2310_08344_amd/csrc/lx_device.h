@@ -20,7 +20,12 @@ struct SweepState {
     int n_fp32;              // sweeps so far that wrote FP32
     int status;              // lx_status
     int done;                // the loop has ended
-    int iter;                // sweeps completed
+    int iter;                // sweeps completed (leja_block: the window's first term index m)
+    // leja_block (several iterations per launch, speculative windows):
+    int blk_mode;            // 0: a window whose terms are added speculatively; 1: its re-execution
+    int nt[kKMax];           // terms each output takes in this launch (0..depth; -j: stops after j)
+    int n_work;              // launches that did work so far
+    double bytes_pp;         // their algorithmic bytes per grid point
 };
 
 // Loop control in device memory.  There is no synchronisation between the
@@ -70,6 +75,7 @@ struct SweepArgs {
     const double* u;         // Burgers state
     const float* u32;        // Burgers state rounded to FP32 (FP32 sweeps)
     double* p[kKMax];        // outputs (the polynomials)
+    double* p2[kKMax];       // leja_block: second buffer of each output (windows alternate)
     const double* coef;      // coef[k*ld + j] = d_j of output k
     const double* xi;        // Leja points
     double* partials;        // [2][nb][1+K]
@@ -127,6 +133,11 @@ hipError_t launch_leja_sweep(int op, int K, bool fp32_capable, const Tile& t, co
 // Launch L of the two-iterations-per-launch loop (pair.hip): sweeps 2L and
 // 2L+1 on tiles of 128 x th points (th in {8, 16, 32}); FP64, nx even.
 hipError_t launch_leja_pair(int op, int K, int th, const SweepArgs& a, int L, hipStream_t s);
+// Launch L of the loop with `depth` (3 or 4) iterations per launch
+// (block.hip): speculative windows re-executed when an output stops inside
+// one; tiles of 128 x th points (th in {8, 16}); FP64, nx even; the
+// five-point diffusion-advection operator.
+hipError_t launch_leja_block(int op, int K, int th, int depth, const SweepArgs& a, int L, hipStream_t s);
 // Power iteration: norm of the start vector into partials[1], then sweeps
 // k = 0..iters-1, then the final norm into ctl->rho.
 hipError_t launch_power_norm(const double* x, long n, int nb, double* partials, hipStream_t s);

@@ -27,8 +27,8 @@ import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2310_08344_amd", "csrc")
-# the sources the FP64 Leja kernels (one and two iterations per launch) are compiled from
-SWEEP_SOURCES = ("kernels.hip", "pair.hip", "sweep_device.h", "lx_device.h")
+# the sources the FP64 Leja kernels (one, two and more iterations per launch) are compiled from
+SWEEP_SOURCES = ("kernels.hip", "pair.hip", "block.hip", "tile_device.h", "sweep_device.h", "lx_device.h")
 COPY_ELEMS = 1 << 26
 
 

@@ -1,0 +1,162 @@
+"""GPU parity of the speculative-window kernel (three and four Leja
+iterations per launch, `leja_block`) against the CPU oracle and against one
+iteration per launch, through the C ABI.
+
+Each output must take exactly the terms of the one-iteration loop: the
+oracle comparison at 1e-10 with equal iteration counts (a borderline stop
+decision flipped by the order of the norm reductions is rerun at the GPU's
+count and reported), 1e-13 against depth 1 when the counts agree, stops at
+every position inside a window (max_iters 1..9), outputs that stop in
+different windows, ragged and tiny grids.
+"""
+import numpy as np
+import pytest
+
+from oracle.exact import phi_fft
+from oracle.operators import burgers_J, diffadv_apply
+from oracle.phi_action import leja_phi, power_iteration
+from paper_2310_08344_amd import binding as B
+from paper_2310_08344_amd import workloads as W
+from tests.gpu_helpers import closed_form_shift, dev, diffadv_setup, host, oracle_parity, rel, say
+
+pytestmark = pytest.mark.gpu
+
+PARITY = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ctx(lx):
+    c = lx.context(n_max=1024 * 1024, k_max=4)
+    yield c
+    c.close()
+
+
+def _op(prm):
+    return B.make_operator(kind=B.LX_OP_DIFFADV2D, nx=prm["nx"], ny=prm["ny"], dx=prm["dx"], dy=prm["dy"],
+                           D=prm["D"], vx=prm["vx"], vy=prm["vy"])
+
+
+def _A(prm):
+    return lambda y: diffadv_apply(y, prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
+
+
+def _solve(ctx, depth, th, nb, op, v, ls, h, c, g, **kw):
+    outs = [dev(np.zeros(v.shape)) for _ in ls]
+    ctx.set_depth(depth, th, nb)
+    try:
+        r = ctx.phi_leja(op, dev(v), outs, ls, h, c, g, **kw)
+    finally:
+        ctx.set_depth(0)
+    return r, [host(o) for o in outs]
+
+
+@pytest.mark.parametrize("depth,th,nb", [(3, 8, 0), (3, 16, 0), (4, 8, 0), (4, 16, 0), (4, 16, 8), (3, 8, 24)])
+def test_windows_match_oracle_and_one_iteration(ctx, depth, th, nb):
+    """Ragged tiles both ways (200 = 128 + 72 columns, 136 rows); phi_0,
+    phi_1 and phi_3 stop in different windows."""
+    prm, h = diffadv_setup(200, 136)
+    c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
+    v = np.random.default_rng(31).standard_normal((136, 200))
+    say("window", depth, th, nb)
+    rb, ob = _solve(ctx, depth, th, nb, _op(prm), v, [0, 1, 3], h, c, g, rtol=1e-8, max_iters=200)
+    r1, o1 = _solve(ctx, 1, 0, 0, _op(prm), v, [0, 1, 3], h, c, g, rtol=1e-8, max_iters=200)
+    assert rb.status == B.LX_OK and rb.stats["depth"] == depth and r1.stats["depth"] == 1
+    spec = [(0, 1.0, 1.0), (1, 1.0, 1.0), (3, 1.0, 1.0)]
+    oracle_parity(ob, rb.iters, lambda f: leja_phi(_A(prm), v, spec, h, c, g, 1e-8, 0.0, 200, f), PARITY)
+    if rb.iters == r1.iters:
+        assert max(rel(a, b) for a, b in zip(ob, o1)) <= 1e-13
+    # windows: ceil(max iters / depth), plus one re-execution per window in
+    # which an output stopped
+    its = rb.iters
+    windows = (max(its) + depth - 1) // depth
+    stops = len({(i - 1) // depth for i in its})
+    assert rb.stats["n_launch"] == windows + stops
+    assert rb.stats["n_apply"] == depth * rb.stats["n_launch"]
+
+
+@pytest.mark.parametrize("depth", [3, 4])
+@pytest.mark.parametrize("nx,ny", [(6, 5), (4, 3), (130, 7), (256, 40)])
+def test_windows_small_and_odd_grids(ctx, depth, nx, ny):
+    """Grids narrower than a tile and than the halo (indices wrap several
+    times), an odd number of rows, a single partial tile row; four outputs."""
+    prm, h = diffadv_setup(nx, ny, cfl=20.0)
+    c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
+    v = np.random.default_rng(nx * 100 + ny).standard_normal((ny, nx))
+    say("window small grid", depth, nx, ny)
+    r, o = _solve(ctx, depth, 16, 0, _op(prm), v, [0, 2, 1, 3], h, c, g, rtol=1e-9, max_iters=300)
+    # sides shorter than the window's halo run two iterations per launch
+    assert r.status == B.LX_OK and r.stats["depth"] == (depth if min(nx, ny) >= depth else 2)
+    spec = [(0, 1.0, 1.0), (2, 1.0, 1.0), (1, 1.0, 1.0), (3, 1.0, 1.0)]
+    oracle_parity(o, r.iters, lambda f: leja_phi(_A(prm), v, spec, h, c, g, 1e-9, 0.0, 300, f), PARITY)
+
+
+@pytest.mark.parametrize("depth", [3, 4])
+@pytest.mark.parametrize("max_iters", [1, 2, 3, 4, 5, 7, 9])
+def test_windows_at_max_iters(ctx, depth, max_iters):
+    """The budget ends at every position inside a window: LX_ENOTCONV with
+    exactly max_iters terms."""
+    prm, h = diffadv_setup(96, 64)
+    c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
+    v = np.random.default_rng(4).standard_normal((64, 96))
+    say("window notconv", depth, max_iters)
+    r, o = _solve(ctx, depth, 16, 0, _op(prm), v, [0, 2], h, c, g, rtol=1e-12, max_iters=max_iters,
+                  raise_on_error=False)
+    assert r.status == B.LX_ENOTCONV and r.iters == [max_iters, max_iters]
+    ref = leja_phi(_A(prm), v, [(0, 1.0, 1.0), (2, 1.0, 1.0)], h, c, g, 1e-12, 0.0, max_iters)
+    assert max(rel(a, b) for a, b in zip(o, ref.p)) <= PARITY
+
+
+@pytest.mark.parametrize("depth", [3, 4])
+def test_windows_edge_inputs(ctx, depth):
+    prm, h = diffadv_setup(64, 64)
+    c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
+    say("window zero / nan", depth)
+    r, o = _solve(ctx, depth, 16, 0, _op(prm), np.zeros((64, 64)), [1], h, c, g, rtol=1e-8)
+    assert r.status == B.LX_OK and r.iters == [1] and not np.any(o[0])
+    v = np.ones((64, 64))
+    v[10, 11] = np.nan
+    r, o = _solve(ctx, depth, 16, 0, _op(prm), v, [0], h, c, g, raise_on_error=False)
+    assert r.status == B.LX_ENONFINITE
+
+
+@pytest.mark.parametrize("depth", [3, 4])
+def test_windows_1024_squared_workload(ctx, depth):
+    p, v = W.config2(n=1024)
+    op = B.make_operator(p)
+    x0 = W.start_vector(p.n)
+    say("1024^2 phi123 windows", depth)
+    rho, c, g = ctx.spectrum(op, x0=dev(x0), iters=20)
+    r, o = _solve(ctx, depth, 16, 0, op, v, [1, 2, 3], p.h, c, g, rtol=1e-8, max_iters=200)
+    assert r.status == B.LX_OK and r.stats["depth"] == depth
+    A = _A(dict(D=p.D, vx=p.vx, vy=p.vy, dx=p.dx, dy=p.dy))
+    spec = [(1, 1.0, 1.0), (2, 1.0, 1.0), (3, 1.0, 1.0)]
+    oracle_parity(o, r.iters, lambda f: leja_phi(A, v, spec, p.h, c, g, 1e-8, 0.0, 200, f), PARITY)
+    for l, ob in zip([1, 2, 3], o):
+        ex = phi_fft(v, l, p.h, p.D, p.vx, p.vy, p.dx, p.dy)
+        assert rel(ob, ex) <= 1e-7
+
+
+def test_windows_repeat_bitwise_and_other_operators_fall_back(ctx):
+    prm, h = diffadv_setup(192, 160)
+    c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
+    v = np.random.default_rng(3).standard_normal((160, 192))
+    say("window determinism")
+    r1, o1 = _solve(ctx, 4, 16, 0, _op(prm), v, [1, 2, 3], h, c, g, rtol=1e-8, max_iters=200)
+    r2, o2 = _solve(ctx, 4, 16, 0, _op(prm), v, [1, 2, 3], h, c, g, rtol=1e-8, max_iters=200)
+    assert r1.iters == r2.iters and all(np.array_equal(a, b) for a, b in zip(o1, o2))
+    # the Burgers Jacobian runs two iterations per launch when four are asked
+    n = 64
+    ub = W.fourier_modes(n, seed=5)
+    opb = B.make_operator(kind=B.LX_OP_BURGERS2D, n=n, nu=2e-2)
+    hb = 2.0 * W.burgers_cfl_step(2e-2, float(np.max(np.abs(ub))), 1 / n, 1 / n)
+    rho = 2.0 / W.burgers_cfl_step(2e-2, float(np.max(np.abs(ub))), 1 / n, 1 / n)
+    out = dev(np.zeros((n, n)))
+    ctx.set_depth(4)
+    try:
+        rb = ctx.phi_leja(opb, dev(ub), [out], [1], hb, -1.05 * rho / 2, 1.05 * rho / 4, u=dev(ub), rtol=1e-8)
+    finally:
+        ctx.set_depth(0)
+    assert rb.status == B.LX_OK and rb.stats["depth"] == 2
+    ref = leja_phi(lambda w: burgers_J(ub, w, 2e-2, 1 / n, 1 / n), ub, [(1, 1.0, 1.0)], hb, -1.05 * rho / 2,
+                   1.05 * rho / 4, 1e-8, 0.0, 500)
+    assert rel(host(out), ref.p[0]) <= 1e-9
