@@ -127,7 +127,8 @@ template <int OP, int K, int TH, int D>
 __device__ __forceinline__ void block_tile(const TileArgs<K>& a, BlockLds<OP, TH, D>& S,
                                            const double* __restrict__ yin, double* __restrict__ yout,
                                            const double* const (&pin)[K], double* const (&pout)[K], const int m,
-                                           const bool first, const int (&nt)[K], double (&sy)[D],
+                                           const bool first, const int (&nt)[K], const int jmax,
+                                           const bool store_y, double (&sy)[D],
                                            double (&sp)[K][D], const int tile, BlockY<TH, D, radius<OP>()>& ty,
                                            const int next) {
     using L = BlockLds<OP, TH, D>;
@@ -189,9 +190,11 @@ __device__ __forceinline__ void block_tile(const TileArgs<K>& a, BlockLds<OP, TH
         }
     }
 
-    // ---- levels 1 .. D-1 in LDS, each followed by the terms it gives ----
+    // ---- levels 1 .. D-1 in LDS, each followed by the terms it gives
+    // (up to level jmax, the same in every thread) ----
 #pragma unroll
     for (int j = 1; j < D; ++j) {
+        if (j > jmax) break;
         const double (*src)[P] = ((j - 1) & 1) ? S.b : S.a;
         double (*dst)[P] = (j & 1) ? S.b : S.a;
         const double shift = a.xi[m + j - 1];
@@ -235,8 +238,8 @@ __device__ __forceinline__ void block_tile(const TileArgs<K>& a, BlockLds<OP, TH
         }
     }
 
-    // ---- level D on the tile: y_{m+D}, the last term, the outputs ----
-    {
+    // ---- level D on the tile: y_{m+D} and the last term ----
+    if (jmax >= D) {
         const double (*src)[P] = ((D - 1) & 1) ? S.b : S.a;
         const double shift = a.xi[m + D - 1];
 #pragma unroll
@@ -247,23 +250,33 @@ __device__ __forceinline__ void block_tile(const TileArgs<K>& a, BlockLds<OP, TH
             level_pair<OP, P>(a.st, shift, src, r, j0, o);
             if (gcol < nx && grow < ny) {
                 const long idx = static_cast<long>(grow) * nx + gcol;
-                double2 t;
-                t.x = o[0];
-                t.y = o[1];
-                *reinterpret_cast<double2*>(yout + idx) = t;
+                if (store_y) {
+                    double2 t;
+                    t.x = o[0];
+                    t.y = o[1];
+                    *reinterpret_cast<double2*>(yout + idx) = t;
+                }
                 sy[D - 1] += o[0] * o[0] + o[1] * o[1];
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    if (nt[k] == 0) continue;
-                    if (nt[k] >= D) {
-                        const double dD = a.coef[k * a.ld + m + D];
-                        pv[k][i].x = fma(dD, o[0], pv[k][i].x);
-                        pv[k][i].y = fma(dD, o[1], pv[k][i].y);
-                        sp[k][D - 1] += pv[k][i].x * pv[k][i].x + pv[k][i].y * pv[k][i].y;
-                    }
-                    st_stream(pout[k] + idx, pv[k][i]);
+                    if (nt[k] < D) continue;
+                    const double dD = a.coef[k * a.ld + m + D];
+                    pv[k][i].x = fma(dD, o[0], pv[k][i].x);
+                    pv[k][i].y = fma(dD, o[1], pv[k][i].y);
+                    sp[k][D - 1] += pv[k][i].x * pv[k][i].x + pv[k][i].y * pv[k][i].y;
                 }
             }
+        }
+    }
+    // ---- the outputs ----
+#pragma unroll
+    for (int i = 0; i < RW; ++i) {
+        const int grow = y0 + w + i * kPairWaves;
+        if (gcol < nx && grow < ny) {
+            const long idx = static_cast<long>(grow) * nx + gcol;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (nt[k] > 0) st_stream(pout[k] + idx, pv[k][i]);
         }
     }
     __syncthreads();   // the next tile overwrites LDS
@@ -355,6 +368,7 @@ __global__ __launch_bounds__(kBlockThreads) void leja_block(SweepArgs a, const i
             st.iter = 0;
             for (int k = 0; k < kKMax; ++k) st.nt[k] = (k < K && st.active[k]) ? D : 0;
             st.n_work = 1;
+            st.n_levels = D;
             double b = 16.0;
             for (int k = 0; k < K; ++k) b += st.nt[k] ? 8.0 : 0.0;
             st.bytes_pp = b;
@@ -367,10 +381,20 @@ __global__ __launch_bounds__(kBlockThreads) void leja_block(SweepArgs a, const i
         if (tid == 0) {
             SweepState st = block_decide<K, D>(a, *ctl, ctl->slot[(L - 1) & 1], tot);
             if (!st.done) {
+                // algorithmic bytes per point: y in (and out, unless a
+                // re-execution), and per output written p (in and out; the
+                // first window only writes it)
+                const bool rd = st.blk_mode == 1;
                 st.n_work += 1;
-                double b = 16.0;
-                for (int k = 0; k < K; ++k) b += st.nt[k] ? (st.iter == 0 ? 8.0 : 16.0) : 0.0;
+                double b = rd ? 8.0 : 16.0;
+                int lev = rd ? 0 : D;
+                for (int k = 0; k < K; ++k) {
+                    const bool w_k = rd ? st.nt[k] < 0 : st.nt[k] != 0;
+                    if (w_k) b += st.iter == 0 ? 8.0 : 16.0;
+                    if (rd && -st.nt[k] > lev) lev = -st.nt[k];
+                }
                 st.bytes_pp += b;
+                st.n_levels += lev;
             }
             s_cur = st;
             if (wg == 0) {
@@ -384,16 +408,19 @@ __global__ __launch_bounds__(kBlockThreads) void leja_block(SweepArgs a, const i
     const int m = s_cur.iter;
     const int win = m / D;
     const bool redo = s_cur.blk_mode == 1;
-    int nt[K];   // terms each output takes in this launch
+    // terms each output takes in this launch.  A re-execution recomputes
+    // only the outputs that stopped (their final buffer is p); the others,
+    // and y_{m+D}, the window already wrote exactly.
+    int nt[K], jmax = redo ? 0 : D;
     const double* pin[K];
     double* pout[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int q = s_cur.nt[k];
-        nt[k] = q < 0 ? -q : q;
+        nt[k] = redo ? (q < 0 ? -q : 0) : q;
+        if (nt[k] > jmax) jmax = nt[k];
         pin[k] = (win & 1) ? a.p2[k] : a.p[k];
-        double* nxt = (win & 1) ? a.p[k] : a.p2[k];
-        pout[k] = (redo && q < 0) ? a.p[k] : nxt;   // a stopped output's final buffer
+        pout[k] = redo ? a.p[k] : ((win & 1) ? a.p[k] : a.p2[k]);
     }
     const double* __restrict__ yin = (win == 0) ? a.v : static_cast<const double*>(a.ybuf[(win - 1) & 1]);
     double* __restrict__ yout = static_cast<double*>(a.ybuf[win & 1]);
@@ -423,7 +450,7 @@ __global__ __launch_bounds__(kBlockThreads) void leja_block(SweepArgs a, const i
     if (first < end) ty = load_block_y<K, TH, D, radius<OP>()>(ta, yin, first);
     for (int t = first; t < end; t += step) {
         const int next = (t + step < end) ? t + step : t;
-        block_tile<OP, K, TH, D>(ta, S, yin, yout, pin, pout, m, win == 0, nt, sy, sp, t, ty, next);
+        block_tile<OP, K, TH, D>(ta, S, yin, yout, pin, pout, m, win == 0, nt, jmax, !redo, sy, sp, t, ty, next);
     }
     double v[NV];
 #pragma unroll
@@ -437,6 +464,175 @@ __global__ __launch_bounds__(kBlockThreads) void leja_block(SweepArgs a, const i
         double* __restrict__ Pp = a.partials + static_cast<long>(L & 1) * a.nb * NV + static_cast<long>(wg) * NV;
 #pragma unroll
         for (int q = 0; q < NV; ++q) Pp[q] = v[q];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// power iteration, D sweeps per launch: level j = A^j (x / ||x||) on the tile
+// (levels 1..nlev-1 in LDS, the last in registers), the sums of squares of
+// every level recorded; the next launch scales by the last level's norm.
+// The directions are those of the normalised iteration x_{k+1} = A x_k /
+// ||A x_k||; rho_hat = ||level nlev|| / ||level nlev-1|| (level 0 has norm
+// 1).  Unnormalised levels grow like rho_hat^j, far from overflow for any
+// stencil of practical size.
+// ---------------------------------------------------------------------------
+
+template <int TH, int D>
+__device__ __forceinline__ void power_block_tile(const TileArgs<1>& ta, const Sten& st, BlockLds<kOpDiffAdv, TH, D>& S,
+                                                 const double* __restrict__ in, double* __restrict__ out,
+                                                 const double s, const int nlev, double (&sy)[D], const int tile,
+                                                 BlockY<TH, D, 1>& ty, const int next) {
+    using L = BlockLds<kOpDiffAdv, TH, D>;
+    using Y = BlockY<TH, D, 1>;
+    constexpr int R = 1, H = L::H, CO = L::CO, ROWS = L::ROWS, P = L::P;
+    constexpr int RW = TH / kPairWaves;
+    const int nx = ta.nx, ny = ta.ny;
+    const int x0 = (tile % ta.tiles_x) * kPairTW, y0 = (tile / ta.tiles_x) * TH;
+    const int tid = flat_tid(), lane = tid & 63, w = tid >> 6;
+    const int j0 = CO + 2 * lane;
+    const int gcol = x0 + 2 * lane;
+#pragma unroll
+    for (int i = 0; i < Y::RM; ++i) {
+        const int r = w + i * kPairWaves;
+        if (r < ROWS) {
+            double2 t;
+            t.x = s * ty.x[i];
+            t.y = s * ty.y[i];
+            *reinterpret_cast<double2*>(&S.a[r][j0]) = t;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < Y::EQ; ++q) {
+        const int e = tid + q * kBlockThreads;
+        if (e < Y::E) {
+            const int row = e / (2 * H), qq = e % (2 * H);
+            const int tc = (qq < H) ? qq - H : kPairTW + (qq - H);
+            S.a[row][CO + tc] = s * ty.edge[q];
+        }
+    }
+    __syncthreads();
+    ty = load_block_y<1, TH, D, 1>(ta, in, next);
+#pragma unroll
+    for (int j = 1; j < D; ++j) {
+        if (j >= nlev) break;
+        const double (*src)[P] = ((j - 1) & 1) ? S.b : S.a;
+        double (*dst)[P] = (j & 1) ? S.b : S.a;
+        const int r_lo = j * R, r_hi = ROWS - j * R;
+#pragma unroll
+        for (int i = 0; i < (ROWS + kPairWaves - 1) / kPairWaves; ++i) {
+            const int r = r_lo + w + i * kPairWaves;
+            if (r < r_hi) {
+                double o[2];
+                level_pair<kOpDiffAdv, P>(st, 0.0, src, r, j0, o);
+                double2 t;
+                t.x = o[0];
+                t.y = o[1];
+                *reinterpret_cast<double2*>(&dst[r][j0]) = t;
+            }
+        }
+        const int side = H - j * R;
+        const int ne = (r_hi - r_lo) * 2 * side;
+        for (int e = tid; e < ne; e += kBlockThreads) {
+            const int r = r_lo + e / (2 * side), qq = e % (2 * side);
+            const int tc = (qq < side) ? qq - side : kPairTW + (qq - side);
+            dst[r][CO + tc] = level_one<kOpDiffAdv, P>(st, 0.0, src, r, CO + tc);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < RW; ++i) {
+            const int grow = y0 + w + i * kPairWaves;
+            if (gcol < nx && grow < ny) {
+                const double2 y = *reinterpret_cast<const double2*>(&dst[H + w + i * kPairWaves][j0]);
+                sy[j - 1] += y.x * y.x + y.y * y.y;
+            }
+        }
+    }
+    {
+        const double (*src)[P] = ((nlev - 1) & 1) ? S.b : S.a;
+#pragma unroll
+        for (int i = 0; i < RW; ++i) {
+            const int grow = y0 + w + i * kPairWaves;
+            double o[2];
+            level_pair<kOpDiffAdv, P>(st, 0.0, src, H + w + i * kPairWaves, j0, o);
+            if (gcol < nx && grow < ny) {
+                double2 t;
+                t.x = o[0];
+                t.y = o[1];
+                *reinterpret_cast<double2*>(out + static_cast<long>(grow) * nx + gcol) = t;
+#pragma unroll
+                for (int j = 0; j < D; ++j)
+                    if (j == nlev - 1) sy[j] += o[0] * o[0] + o[1] * o[1];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Partial sums: the start vector's (power_norm_kernel) at partials[nb + i];
+// launch b's at partials[2 nb + (b & 1) nb D + i D + j].
+template <int TH, int D>
+__global__ __launch_bounds__(kBlockThreads) void power_block(PowerArgs a, const double* in, double* out, const int b,
+                                                             const int nlev) {
+    __shared__ BlockLds<kOpDiffAdv, TH, D> S;
+    const int tid = flat_tid();
+    const int wg = static_cast<int>(blockIdx.x);
+    double scale;
+    if (b == 0) {
+        double tot[1];
+        sum_partials<1>(a.partials + a.nb, a.nb, tot);
+        scale = 1.0 / sqrt(tot[0]);
+    } else {
+        double tot[D];
+        sum_partials<D>(a.partials + 2L * a.nb + static_cast<long>((b - 1) & 1) * a.nb * D, a.nb, tot);
+        scale = 1.0 / sqrt(tot[D - 1]);   // every launch but the last makes D levels
+    }
+    TileArgs<1> ta{};
+    ta.nx = a.nx;
+    ta.ny = a.ny;
+    ta.tiles_x = a.tiles_x;
+    const Sten st{a.cW, a.cE, a.cS, a.cN, a.cC, 0.0, 0.0, 0.0, 0.0};
+    double sy[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) sy[j] = 0.0;
+    const int T = a.tiles_x * a.tiles_y;
+    int first, step, end;
+    if (a.nb >= 8 && (a.nb & 7) == 0) {
+        const int x = wg & 7, nbx = a.nb >> 3;
+        first = static_cast<int>((static_cast<long>(x) * T) >> 3) + (wg >> 3);
+        step = nbx;
+        end = static_cast<int>((static_cast<long>(x + 1) * T) >> 3);
+    } else {
+        first = wg;
+        step = a.nb;
+        end = T;
+    }
+    BlockY<TH, D, 1> ty;
+    if (first < end) ty = load_block_y<1, TH, D, 1>(ta, in, first);
+    for (int t = first; t < end; t += step) {
+        const int next = (t + step < end) ? t + step : t;
+        power_block_tile<TH, D>(ta, st, S, in, out, scale, nlev, sy, t, ty, next);
+    }
+    block_sum<D>(sy);
+    if (tid == 0) {
+        double* __restrict__ Pp = a.partials + 2L * a.nb + static_cast<long>(b & 1) * a.nb * D + static_cast<long>(wg) * D;
+#pragma unroll
+        for (int j = 0; j < D; ++j) Pp[j] = sy[j];
+    }
+}
+
+// rho_hat = ||level nlev|| / ||level nlev-1|| of the last launch b
+template <int D>
+__global__ __launch_bounds__(kBlockThreads) void power_block_final(PowerArgs a, const int b, const int nlev) {
+    double tot[D];
+    sum_partials<D>(a.partials + 2L * a.nb + static_cast<long>(b & 1) * a.nb * D, a.nb, tot);
+    if (flat_tid() == 0) {
+        double last = 0.0, prev = 1.0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            if (j == nlev - 1) last = tot[j];
+            if (j == nlev - 2) prev = tot[j];
+        }
+        a.ctl->rho = sqrt(last / prev);
     }
 }
 
@@ -463,6 +659,19 @@ hipError_t launch_block_k(int K, int th, const SweepArgs& a, int L, hipStream_t 
 }
 
 }  // namespace
+
+hipError_t launch_power_block(const PowerArgs& a, const double* in, double* out, int b, int nlev, hipStream_t s) {
+    constexpr int D = kPowerBlockDepth, TH = 16;
+    if (a.nb < 1 || a.nx % 2 != 0 || a.nx < D || a.ny < D || nlev < 1 || nlev > D) return hipErrorInvalidValue;
+    if (a.tiles_x != (a.nx + kPairTW - 1) / kPairTW || a.tiles_y != (a.ny + TH - 1) / TH) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((power_block<TH, D>), dim3(a.nb), dim3(64, kPairWaves), 0, s, a, in, out, b, nlev);
+    return hipGetLastError();
+}
+
+hipError_t launch_power_block_final(const PowerArgs& a, int b, int nlev, hipStream_t s) {
+    hipLaunchKernelGGL((power_block_final<kPowerBlockDepth>), dim3(1), dim3(kBlockThreads), 0, s, a, b, nlev);
+    return hipGetLastError();
+}
 
 hipError_t launch_leja_block(int op, int K, int th, int depth, const SweepArgs& a, int L, hipStream_t s) {
     if (a.nb < 1 || a.nx % 2 != 0 || a.nx < 2 || a.ny < 2) return hipErrorInvalidValue;

@@ -458,7 +458,7 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
         // their re-executions): y in and out, and per output taking terms a
         // read and a write of p (the first window writes p without reading it)
         S.n_launch = fin.n_work;
-        S.n_apply = D * fin.n_work;
+        S.n_apply = fin.n_levels;
         bytes = fin.bytes_pp * static_cast<double>(N);
     } else if (!pair) {
         // per sweep: the basis read and write, the Burgers state read, and per
@@ -861,6 +861,66 @@ lx_status lx_spectrum(lx_ctx* ctx, const lx_operator* op, const double* d_u, con
         x0 = ctx->ybuf[1];
     }
     const bool vec2 = aligned16(x0) && (d_u == nullptr || aligned16(d_u));
+    // the five-point diffusion-advection operator takes kPowerBlockDepth
+    // sweeps per launch on LDS tiles (the basis read and written once per
+    // launch); the others one sweep per launch
+    constexpr int PD = lx::kPowerBlockDepth;
+    if (op->kind == LX_OP_DIFFADV2D && vec2 && nx % 2 == 0 && nx >= PD && ny >= PD) {
+        PowerArgs a{};
+        a.nx = nx;
+        a.ny = ny;
+        a.tiles_x = (nx + 127) / 128;
+        a.tiles_y = (ny + 15) / 16;
+        a.nb = pair_grid(1024, a.tiles_x * a.tiles_y);
+        double pk[9];
+        diffadv_stencil9(*op, 0.0, 1.0, pk);
+        a.cE = pk[0];
+        a.cW = pk[1];
+        a.cN = pk[2];
+        a.cS = pk[3];
+        a.cC = pk[4];
+        s = ensure_partials(ctx, 2 * static_cast<size_t>(a.nb) * (1 + PD));
+        if (s != LX_OK) return s;
+        a.partials = ctx->partials;
+        a.ctl = ctx->ctl;
+        const int nblk = (iters + PD - 1) / PD;
+        LX_HIP(ctx, lx::launch_power_norm(x0, N, a.nb, ctx->partials, ctx->stream));
+        if (ctx->timing) {
+            s = ensure_timing_events(ctx, static_cast<size_t>(nblk) + 1);
+            if (s != LX_OK) return s;
+            LX_HIP(ctx, hipEventRecord(ctx->tev[0], ctx->stream));
+        }
+        int nlev = PD;
+        for (int b = 0; b < nblk; ++b) {
+            nlev = (b == nblk - 1) ? iters - PD * (nblk - 1) : PD;
+            const double* in = (b == 0) ? x0 : ctx->ybuf[(b - 1) & 1];
+            LX_HIP(ctx, lx::launch_power_block(a, in, ctx->ybuf[b & 1], b, nlev, ctx->stream));
+            if (ctx->timing) LX_HIP(ctx, hipEventRecord(ctx->tev[b + 1], ctx->stream));
+        }
+        LX_HIP(ctx, lx::launch_power_block_final(a, nblk - 1, nlev, ctx->stream));
+        LX_HIP(ctx, hipMemcpyAsync(ctx->h_ctl, ctx->ctl, sizeof(LoopCtl), hipMemcpyDeviceToHost, ctx->stream));
+        LX_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        const double rho = ctx->h_ctl->rho;
+        lx_stats& S = ctx->stats;
+        S.n_apply = iters;
+        S.n_launch = nblk;
+        S.depth = PD;
+        S.rho_hat = rho;
+        S.bytes = 16.0 * static_cast<double>(N) * nblk;
+        if (ctx->timing) {
+            S.loop_ms = elapsed(ctx->tev[0], ctx->tev[nblk]);
+            S.sweep_ms = S.loop_ms;
+            S.first_sweep_ms = elapsed(ctx->tev[0], ctx->tev[1]);
+        }
+        if (!std::isfinite(rho) || !(rho > 0.0))
+            return fail(ctx, LX_ENONFINITE, "power iteration produced a zero or non-finite norm");
+        const double lam = -safety * rho;
+        if (rho_hat) *rho_hat = rho;
+        if (c) *c = lam / 2.0;
+        if (gamma) *gamma = -lam / 4.0;
+        S.status = LX_OK;
+        return LX_OK;
+    }
     const Tile t = pick_tile(ctx, *op, 1, vec2);
     PowerArgs a{};
     a.nx = nx;
