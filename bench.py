@@ -45,7 +45,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "leja_pair_phi123_4096_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "leja_block_phi123_4096_traffic.json")
 
 
 def log(*a):

@@ -217,7 +217,7 @@ void load_tune_cache(lx_ctx* ctx) {
                               "\"pnb\": %d",
                         &kind, &nx, &ny, &K, &prec, &t.tx, &t.ty, &t.ry, &t.vec, &t.nb, &t.depth, &t.th,
                         &t.pnb) == 13 &&
-            valid_tile(t) && (t.depth == 1 || t.depth == 2) && (t.th == 8 || t.th == 16 || t.th == 32) &&
+            valid_tile(t) && t.depth >= 1 && t.depth <= 4 && (t.th == 8 || t.th == 16 || t.th == 32) &&
             t.pnb >= 0) {
             ctx->tuned[std::make_tuple(kind, nx, ny, K, prec)] = t;
         }
