@@ -165,7 +165,13 @@ def bench_learned(lib, count: int = 1024) -> dict:
 PAPER_RUNS_8192 = ((1.0, 2e-7), (10.0, 2e-6), (100.0, 2e-5))
 
 
-def bench_paper_problems(lib, n: int = 8192, axpby_gbs=None, tune: bool = True) -> dict:
+# the paper's time-to-solution runs on one A100 (Sec. 3, table of speedups):
+# 2^14 grid, T_f = 2e-6, h = 100 x CFL; its GPU seconds for Problems I and II
+PAPER_RUNS_16384 = ((100.0, 2e-6),)
+PAPER_A100_SECONDS_16384 = {"I": 4.76, "II": 4.14}
+
+
+def bench_paper_problems(lib, n: int = 8192, axpby_gbs=None, tune: bool = True, runs=PAPER_RUNS_8192) -> dict:
     """Problems I (exp action) and II (phi_1 with a source) on n^2 with the
     third-order upwind operator: for each step size, power iteration once
     (A is constant), then the time loop to the paper's final time, timed as
@@ -194,7 +200,7 @@ def bench_paper_problems(lib, n: int = 8192, axpby_gbs=None, tune: bool = True) 
         ua, ub = torch.empty_like(u0), torch.empty_like(u0)
         N = float(n * n)
         for source in (False, True):
-            for cfl, t_final in PAPER_RUNS_8192:
+            for cfl, t_final in runs:
                 h = cfl * p0.h   # p0.h is one CFL step
                 steps = max(1, round(t_final / h))
                 # untimed warm-up step (planner tables, code paths)
@@ -204,6 +210,7 @@ def bench_paper_problems(lib, n: int = 8192, axpby_gbs=None, tune: bool = True) 
                 t0 = time.perf_counter()
                 _, c, g = ctx.spectrum(op, x0=x0, iters=20)
                 nbytes = 16.0 * N * 20
+                nbytes1 = 16.0 * N * 20   # the same iterations one per launch
                 iters = []
                 cur, nxt = u0, ua
                 for k in range(steps):
@@ -213,6 +220,7 @@ def bench_paper_problems(lib, n: int = 8192, axpby_gbs=None, tune: bool = True) 
                         raise RuntimeError(f"linear_step status {r.status}: {ctx.last_error()}")
                     iters.append(r.iters[0])
                     nbytes += r.stats["bytes"] + (48.0 * N if source else 0.0)
+                    nbytes1 += N * (24.0 + 32.0 * (r.iters[0] - 1)) + (48.0 * N if source else 0.0)
                     cur, nxt = nxt, (ub if nxt is ua else ua)
                 torch.cuda.synchronize()
                 dt = time.perf_counter() - t0
@@ -220,16 +228,22 @@ def bench_paper_problems(lib, n: int = 8192, axpby_gbs=None, tune: bool = True) 
                 run = {"problem": "II" if source else "I", "h_cfl": cfl, "t_final": t_final, "steps": steps,
                        "iters_first_last": [iters[0], iters[-1]], "seconds": round(dt, 4),
                        "ms_per_step": round(dt * 1e3 / steps, 3), "gbs": round(gbs, 1),
-                       "frac_of_8tbs": round(gbs / HBM_PEAK_GBS, 4)}
+                       "frac_of_8tbs": round(gbs / HBM_PEAK_GBS, 4),
+                       "gbs_one_iteration_bytes": round(nbytes1 / dt / 1e9, 1)}
                 if axpby_gbs:
                     run["frac_of_practical_axpby"] = round(gbs / axpby_gbs, 4)
+                    run["one_iteration_bytes_frac_of_practical_axpby"] = round(nbytes1 / dt / 1e9 / axpby_gbs, 4)
+                if n == 16384 and cfl == 100.0:
+                    run["paper_a100_seconds"] = PAPER_A100_SECONDS_16384[run["problem"]]
                 res["runs"].append(run)
                 log("paper problem", run)
     finally:
         ctx.close()
-    res["note"] = ("bytes are this library's algorithmic bytes (two Leja iterations per launch read and write "
-                   "the outputs once); the paper's A100 figures (0.87-0.92 of its practical z = ax + by "
-                   "bandwidth at 2^13, Sec. 3) count its own kernels' reads and writes: context only")
+    res["note"] = ("gbs: this library's algorithmic bytes (several Leja iterations per launch read and write the "
+                   "basis and the output once) over the wall time of the whole loop; gbs_one_iteration_bytes: the "
+                   "bytes the same iterations move one per launch (32 B/pt each), over the same time; the paper's "
+                   "A100 figures (0.87-0.92 of its practical z = ax + by bandwidth at 2^13, and its seconds at "
+                   "2^14, Sec. 3) are context, not a like-for-like ratio")
     return res
 
 
@@ -362,6 +376,9 @@ def main() -> int:
         log("paper-shaped problems I and II at 8192^2")
         out["paper_problems_8192"] = bench_paper_problems(lib, axpby_gbs=extra.get("practical_axpby_gbs"),
                                                           tune=not args.no_tune)
+        log("paper-shaped problems I and II at 16384^2 (time to solution)")
+        out["paper_problems_16384"] = bench_paper_problems(lib, n=16384, axpby_gbs=extra.get("practical_axpby_gbs"),
+                                                           tune=not args.no_tune, runs=PAPER_RUNS_16384)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline()

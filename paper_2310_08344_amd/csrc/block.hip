@@ -477,14 +477,14 @@ __global__ __launch_bounds__(kBlockThreads) void leja_block(SweepArgs a, const i
 // stencil of practical size.
 // ---------------------------------------------------------------------------
 
-template <int TH, int D>
-__device__ __forceinline__ void power_block_tile(const TileArgs<1>& ta, const Sten& st, BlockLds<kOpDiffAdv, TH, D>& S,
+template <int OP, int TH, int D>
+__device__ __forceinline__ void power_block_tile(const TileArgs<1>& ta, const Sten& st, BlockLds<OP, TH, D>& S,
                                                  const double* __restrict__ in, double* __restrict__ out,
                                                  const double s, const int nlev, double (&sy)[D], const int tile,
-                                                 BlockY<TH, D, 1>& ty, const int next) {
-    using L = BlockLds<kOpDiffAdv, TH, D>;
-    using Y = BlockY<TH, D, 1>;
-    constexpr int R = 1, H = L::H, CO = L::CO, ROWS = L::ROWS, P = L::P;
+                                                 BlockY<TH, D, radius<OP>()>& ty, const int next) {
+    using L = BlockLds<OP, TH, D>;
+    using Y = BlockY<TH, D, radius<OP>()>;
+    constexpr int R = L::R, H = L::H, CO = L::CO, ROWS = L::ROWS, P = L::P;
     constexpr int RW = TH / kPairWaves;
     const int nx = ta.nx, ny = ta.ny;
     const int x0 = (tile % ta.tiles_x) * kPairTW, y0 = (tile / ta.tiles_x) * TH;
@@ -511,7 +511,7 @@ __device__ __forceinline__ void power_block_tile(const TileArgs<1>& ta, const St
         }
     }
     __syncthreads();
-    ty = load_block_y<1, TH, D, 1>(ta, in, next);
+    ty = load_block_y<1, TH, D, R>(ta, in, next);
 #pragma unroll
     for (int j = 1; j < D; ++j) {
         if (j >= nlev) break;
@@ -523,7 +523,7 @@ __device__ __forceinline__ void power_block_tile(const TileArgs<1>& ta, const St
             const int r = r_lo + w + i * kPairWaves;
             if (r < r_hi) {
                 double o[2];
-                level_pair<kOpDiffAdv, P>(st, 0.0, src, r, j0, o);
+                level_pair<OP, P>(st, 0.0, src, r, j0, o);
                 double2 t;
                 t.x = o[0];
                 t.y = o[1];
@@ -535,7 +535,7 @@ __device__ __forceinline__ void power_block_tile(const TileArgs<1>& ta, const St
         for (int e = tid; e < ne; e += kBlockThreads) {
             const int r = r_lo + e / (2 * side), qq = e % (2 * side);
             const int tc = (qq < side) ? qq - side : kPairTW + (qq - side);
-            dst[r][CO + tc] = level_one<kOpDiffAdv, P>(st, 0.0, src, r, CO + tc);
+            dst[r][CO + tc] = level_one<OP, P>(st, 0.0, src, r, CO + tc);
         }
         __syncthreads();
 #pragma unroll
@@ -553,7 +553,7 @@ __device__ __forceinline__ void power_block_tile(const TileArgs<1>& ta, const St
         for (int i = 0; i < RW; ++i) {
             const int grow = y0 + w + i * kPairWaves;
             double o[2];
-            level_pair<kOpDiffAdv, P>(st, 0.0, src, H + w + i * kPairWaves, j0, o);
+            level_pair<OP, P>(st, 0.0, src, H + w + i * kPairWaves, j0, o);
             if (gcol < nx && grow < ny) {
                 double2 t;
                 t.x = o[0];
@@ -570,10 +570,11 @@ __device__ __forceinline__ void power_block_tile(const TileArgs<1>& ta, const St
 
 // Partial sums: the start vector's (power_norm_kernel) at partials[nb + i];
 // launch b's at partials[2 nb + (b & 1) nb D + i D + j].
-template <int TH, int D>
+template <int OP, int TH, int D>
 __global__ __launch_bounds__(kBlockThreads) void power_block(PowerArgs a, const double* in, double* out, const int b,
                                                              const int nlev) {
-    __shared__ BlockLds<kOpDiffAdv, TH, D> S;
+    constexpr int R = radius<OP>();
+    __shared__ BlockLds<OP, TH, D> S;
     const int tid = flat_tid();
     const int wg = static_cast<int>(blockIdx.x);
     double scale;
@@ -590,7 +591,7 @@ __global__ __launch_bounds__(kBlockThreads) void power_block(PowerArgs a, const 
     ta.nx = a.nx;
     ta.ny = a.ny;
     ta.tiles_x = a.tiles_x;
-    const Sten st{a.cW, a.cE, a.cS, a.cN, a.cC, 0.0, 0.0, 0.0, 0.0};
+    const Sten st{a.cW, a.cE, a.cS, a.cN, a.cC, a.cW2, a.cE2, a.cS2, a.cN2};
     double sy[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) sy[j] = 0.0;
@@ -606,11 +607,11 @@ __global__ __launch_bounds__(kBlockThreads) void power_block(PowerArgs a, const 
         step = a.nb;
         end = T;
     }
-    BlockY<TH, D, 1> ty;
-    if (first < end) ty = load_block_y<1, TH, D, 1>(ta, in, first);
+    BlockY<TH, D, R> ty;
+    if (first < end) ty = load_block_y<1, TH, D, R>(ta, in, first);
     for (int t = first; t < end; t += step) {
         const int next = (t + step < end) ? t + step : t;
-        power_block_tile<TH, D>(ta, st, S, in, out, scale, nlev, sy, t, ty, next);
+        power_block_tile<OP, TH, D>(ta, st, S, in, out, scale, nlev, sy, t, ty, next);
     }
     block_sum<D>(sy);
     if (tid == 0) {
@@ -636,12 +637,24 @@ __global__ __launch_bounds__(kBlockThreads) void power_block_final(PowerArgs a, 
     }
 }
 
+// at most 64 KB of static LDS per workgroup
+template <int OP, int TH, int D>
+constexpr bool block_fits() {
+    return sizeof(BlockLds<OP, TH, D>) <= 63 * 1024;
+}
+
 template <int OP, int K, int D>
 hipError_t launch_block_th(int th, const SweepArgs& a, int L, hipStream_t s) {
     const dim3 block(64, kPairWaves), grid(a.nb);
     switch (th) {
         case 8: hipLaunchKernelGGL((leja_block<OP, K, 8, D>), grid, block, 0, s, a, L); break;
-        case 16: hipLaunchKernelGGL((leja_block<OP, K, 16, D>), grid, block, 0, s, a, L); break;
+        case 16:
+            if constexpr (block_fits<OP, 16, D>()) {
+                hipLaunchKernelGGL((leja_block<OP, K, 16, D>), grid, block, 0, s, a, L);
+            } else {
+                return hipErrorInvalidValue;
+            }
+            break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -660,11 +673,22 @@ hipError_t launch_block_k(int K, int th, const SweepArgs& a, int L, hipStream_t 
 
 }  // namespace
 
-hipError_t launch_power_block(const PowerArgs& a, const double* in, double* out, int b, int nlev, hipStream_t s) {
-    constexpr int D = kPowerBlockDepth, TH = 16;
-    if (a.nb < 1 || a.nx % 2 != 0 || a.nx < D || a.ny < D || nlev < 1 || nlev > D) return hipErrorInvalidValue;
+int power_block_rows(int op) { return op == kOpDiffAdv3 ? 8 : 16; }
+
+hipError_t launch_power_block(int op, const PowerArgs& a, const double* in, double* out, int b, int nlev,
+                              hipStream_t s) {
+    constexpr int D = kPowerBlockDepth;
+    if (op != kOpDiffAdv && op != kOpDiffAdv3) return hipErrorInvalidValue;
+    const int TH = power_block_rows(op), H = D * (op == kOpDiffAdv3 ? 2 : 1);
+    if (a.nb < 1 || a.nx % 2 != 0 || a.nx < H || a.ny < H || nlev < 1 || nlev > D) return hipErrorInvalidValue;
     if (a.tiles_x != (a.nx + kPairTW - 1) / kPairTW || a.tiles_y != (a.ny + TH - 1) / TH) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((power_block<TH, D>), dim3(a.nb), dim3(64, kPairWaves), 0, s, a, in, out, b, nlev);
+    if (op == kOpDiffAdv) {
+        hipLaunchKernelGGL((power_block<kOpDiffAdv, 16, D>), dim3(a.nb), dim3(64, kPairWaves), 0, s, a, in, out, b,
+                           nlev);
+    } else {
+        hipLaunchKernelGGL((power_block<kOpDiffAdv3, 8, D>), dim3(a.nb), dim3(64, kPairWaves), 0, s, a, in, out, b,
+                           nlev);
+    }
     return hipGetLastError();
 }
 
@@ -677,9 +701,15 @@ hipError_t launch_leja_block(int op, int K, int th, int depth, const SweepArgs& 
     if (a.nb < 1 || a.nx % 2 != 0 || a.nx < 2 || a.ny < 2) return hipErrorInvalidValue;
     if (a.tiles_x != (a.nx + kPairTW - 1) / kPairTW || a.tiles_y != (a.ny + th - 1) / th)
         return hipErrorInvalidValue;
-    if (op != kOpDiffAdv || a.nx < depth || a.ny < depth) return hipErrorInvalidValue;   // halo reach
-    if (depth == 3) return launch_block_k<kOpDiffAdv, 3>(K, th, a, L, s);
-    if (depth == 4) return launch_block_k<kOpDiffAdv, 4>(K, th, a, L, s);
+    const int H = depth * (op == kOpDiffAdv3 ? 2 : 1);
+    if ((op != kOpDiffAdv && op != kOpDiffAdv3) || a.nx < H || a.ny < H) return hipErrorInvalidValue;   // halo reach
+    if (op == kOpDiffAdv) {
+        if (depth == 3) return launch_block_k<kOpDiffAdv, 3>(K, th, a, L, s);
+        if (depth == 4) return launch_block_k<kOpDiffAdv, 4>(K, th, a, L, s);
+    } else {
+        if (depth == 3) return launch_block_k<kOpDiffAdv3, 3>(K, th, a, L, s);
+        if (depth == 4) return launch_block_k<kOpDiffAdv3, 4>(K, th, a, L, s);
+    }
     return hipErrorInvalidValue;
 }
 

@@ -254,9 +254,10 @@ void choose_depth(const lx_ctx* ctx, const lx_operator& op, int K, bool vec2_ok,
     int depth = 2;
     if (ctx->depth_forced != 0) depth = ctx->depth_forced;
     else if (it != ctx->tuned.end()) depth = it->second.depth;
-    // windows stage a halo of `depth` cells, which the periodic index wrap
-    // allows only on sides of at least that many cells
-    if (depth >= 3 && (op.kind != LX_OP_DIFFADV2D || op.nx < depth || op.ny < depth)) depth = 2;
+    // windows stage a halo of depth * radius cells, which the periodic index
+    // wrap allows only on sides of at least that many cells
+    const int halo = depth * (op.kind == LX_OP_DIFFADV2D_UP3 ? 2 : 1);
+    if (depth >= 3 && (!is_diffadv(op.kind) || op.nx < halo || op.ny < halo)) depth = 2;
     t.depth = (depth >= 2 && pair_ok) ? depth : 1;
     if (it != ctx->tuned.end() && it->second.depth >= 2 && it->second.depth == t.depth) {
         t.th = it->second.th;
@@ -270,6 +271,8 @@ void choose_depth(const lx_ctx* ctx, const lx_operator& op, int K, bool vec2_ok,
     // a radius-2 stencil stages 8 edge cells per row, and three or four
     // iterations per launch hold two levels in LDS: tiles of at most 16 rows
     if ((op.kind == LX_OP_DIFFADV2D_UP3 || t.depth >= 3) && t.th > 16) t.th = 16;
+    // the radius-2 window of four holds 8-row tiles in 64 KB of LDS
+    if (op.kind == LX_OP_DIFFADV2D_UP3 && t.depth == 4) t.th = 8;
 }
 
 lx_status ensure_blk_ws(lx_ctx* ctx, int K) {
@@ -861,16 +864,19 @@ lx_status lx_spectrum(lx_ctx* ctx, const lx_operator* op, const double* d_u, con
         x0 = ctx->ybuf[1];
     }
     const bool vec2 = aligned16(x0) && (d_u == nullptr || aligned16(d_u));
-    // the five-point diffusion-advection operator takes kPowerBlockDepth
-    // sweeps per launch on LDS tiles (the basis read and written once per
-    // launch); the others one sweep per launch
+    // the diffusion-advection operators take kPowerBlockDepth sweeps per
+    // launch on LDS tiles (the basis read and written once per launch); the
+    // Burgers Jacobian one sweep per launch
     constexpr int PD = lx::kPowerBlockDepth;
-    if (op->kind == LX_OP_DIFFADV2D && vec2 && nx % 2 == 0 && nx >= PD && ny >= PD) {
+    const int pcode = opcode_of(op->kind);
+    const int ph = PD * (op->kind == LX_OP_DIFFADV2D_UP3 ? 2 : 1);   // halo of a power launch
+    if (is_diffadv(op->kind) && vec2 && nx % 2 == 0 && nx >= ph && ny >= ph) {
+        const int prow = lx::power_block_rows(pcode);
         PowerArgs a{};
         a.nx = nx;
         a.ny = ny;
         a.tiles_x = (nx + 127) / 128;
-        a.tiles_y = (ny + 15) / 16;
+        a.tiles_y = (ny + prow - 1) / prow;
         a.nb = pair_grid(1024, a.tiles_x * a.tiles_y);
         double pk[9];
         diffadv_stencil9(*op, 0.0, 1.0, pk);
@@ -879,6 +885,10 @@ lx_status lx_spectrum(lx_ctx* ctx, const lx_operator* op, const double* d_u, con
         a.cN = pk[2];
         a.cS = pk[3];
         a.cC = pk[4];
+        a.cE2 = pk[5];
+        a.cW2 = pk[6];
+        a.cN2 = pk[7];
+        a.cS2 = pk[8];
         s = ensure_partials(ctx, 2 * static_cast<size_t>(a.nb) * (1 + PD));
         if (s != LX_OK) return s;
         a.partials = ctx->partials;
@@ -894,7 +904,7 @@ lx_status lx_spectrum(lx_ctx* ctx, const lx_operator* op, const double* d_u, con
         for (int b = 0; b < nblk; ++b) {
             nlev = (b == nblk - 1) ? iters - PD * (nblk - 1) : PD;
             const double* in = (b == 0) ? x0 : ctx->ybuf[(b - 1) & 1];
-            LX_HIP(ctx, lx::launch_power_block(a, in, ctx->ybuf[b & 1], b, nlev, ctx->stream));
+            LX_HIP(ctx, lx::launch_power_block(pcode, a, in, ctx->ybuf[b & 1], b, nlev, ctx->stream));
             if (ctx->timing) LX_HIP(ctx, hipEventRecord(ctx->tev[b + 1], ctx->stream));
         }
         LX_HIP(ctx, lx::launch_power_block_final(a, nblk - 1, nlev, ctx->stream));
@@ -1364,7 +1374,8 @@ lx_status lx_tune(lx_ctx* ctx, const lx_operator* op, int K, int sweeps, char* r
     if (op->prec == LX_FP64 && nx % 2 == 0) {
         const int tiles_x = (nx + 127) / 128;
         for (int depth : {2, 3, 4}) {
-            if (depth >= 3 && (op->kind != LX_OP_DIFFADV2D || nx < depth || ny < depth)) continue;
+            const int halo = depth * (op->kind == LX_OP_DIFFADV2D_UP3 ? 2 : 1);
+            if (depth >= 3 && (!is_diffadv(op->kind) || nx < halo || ny < halo)) continue;
             if (depth >= 3) {
                 s = ensure_blk_ws(ctx, K);
                 if (s != LX_OK) return cleanup(s);
@@ -1372,6 +1383,7 @@ lx_status lx_tune(lx_ctx* ctx, const lx_operator* op, int K, int sweeps, char* r
             for (int th : {8, 16, 32}) {
                 // radius 2, and two LDS levels of windows: at most 16 rows
                 if (th > 16 && (op->kind == LX_OP_DIFFADV2D_UP3 || depth >= 3)) continue;
+                if (th > 8 && op->kind == LX_OP_DIFFADV2D_UP3 && depth == 4) continue;   // 64 KB of LDS
                 const int tiles = tiles_x * ((ny + th - 1) / th);
                 for (int pnb : {0, 2048, 1536, 1024, 768, 512, 256}) {
                     if (pnb != 0 && pnb >= tiles) continue;

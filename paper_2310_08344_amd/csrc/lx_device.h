@@ -145,14 +145,17 @@ hipError_t launch_power_norm(const double* x, long n, int nb, double* partials, 
 hipError_t launch_power_sweep(int op, const Tile& t, const PowerArgs& a, int k, hipStream_t s);
 hipError_t launch_power_final(int nb, const double* partials, LoopCtl* ctl, hipStream_t s);
 // Power iteration with kPowerBlockDepth sweeps per launch (block.hip; the
-// five-point diffusion-advection operator, nx even, tiles of 128 x 16 with
-// a.tiles_x/a.tiles_y in that layout): launch b makes nlev (1..depth)
+// diffusion-advection operators, nx even, 128-column tiles of
+// power_block_rows(op) rows with a.tiles_x/a.tiles_y in that layout): launch b makes nlev (1..depth)
 // levels from `in`; the start vector's norm partials at partials[nb + i]
 // (launch_power_norm), its own at partials[2 nb + (b & 1) nb depth + ...];
 // partials needs 2 nb (1 + depth) doubles.  Then the final ratio into
 // ctl->rho.
 constexpr int kPowerBlockDepth = 4;
-hipError_t launch_power_block(const PowerArgs& a, const double* in, double* out, int b, int nlev, hipStream_t s);
+// op: kOpDiffAdv (tiles of 128 x 16) or kOpDiffAdv3 (128 x 8, power_block_rows)
+int power_block_rows(int op);
+hipError_t launch_power_block(int op, const PowerArgs& a, const double* in, double* out, int b, int nlev,
+                              hipStream_t s);
 hipError_t launch_power_block_final(const PowerArgs& a, int b, int nlev, hipStream_t s);
 hipError_t launch_fill_splitmix(double* x, long n, unsigned long long seed, hipStream_t s);
 hipError_t launch_to_fp32(const double* x, float* y, long n, hipStream_t s);

@@ -3,7 +3,7 @@
 
 namespace lx {
 
-constexpr int kMaxPoints = 1002;   // LX_MAX_ITERS + 2: the two-iteration launches read d_{max_iters+1}
+constexpr int kMaxPoints = 1008;   // LX_MAX_ITERS + 8: windows of D iterations read up to d_{max_iters+D}
 
 // phi_l(z) for real z (Sec. 1 recursion; Taylor series near 0).
 double phi_scalar(int l, double z);

@@ -181,3 +181,17 @@ def test_blocked_power_iteration_matches_oracle(ctx, nx, ny, iters):
     assert ctx.stats()["depth"] == 4 and ctx.stats()["n_launch"] == (iters + 3) // 4
     rho_o, _ = power_iteration(_A(prm), x0, iters)
     assert abs(rho - rho_o) <= 1e-12 * rho_o
+
+
+@pytest.mark.parametrize("depth", [3, 4])
+def test_windows_with_the_largest_budget(ctx, depth):
+    """max_iters = LX_MAX_ITERS: the window past the budget reads Leja
+    points and coefficients up to d_{max_iters + depth}."""
+    prm, h = diffadv_setup(64, 64)
+    c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
+    v = np.random.default_rng(12).standard_normal((64, 64))
+    say("window largest budget", depth)
+    r, o = _solve(ctx, depth, 16, 0, _op(prm), v, [0, 3], h, c, g, rtol=1e-10, max_iters=B.LX_MAX_ITERS)
+    assert r.status == B.LX_OK and r.stats["depth"] == depth
+    spec = [(0, 1.0, 1.0), (3, 1.0, 1.0)]
+    oracle_parity(o, r.iters, lambda f: leja_phi(_A(prm), v, spec, h, c, g, 1e-10, 0.0, 300, f), PARITY)

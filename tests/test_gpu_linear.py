@@ -69,7 +69,7 @@ def test_up3_spectrum_matches_oracle(ctx, nx, ny, vx, vy):
 
 # (depth, th, nb): one iteration per launch; two on 8- and 16-row tiles,
 # one workgroup per tile and fewer workgroups than tiles
-SHAPES = [(1, 0, 0), (2, 8, 0), (2, 16, 0), (2, 16, 8), (2, 8, 24)]
+SHAPES = [(1, 0, 0), (2, 8, 0), (2, 16, 0), (2, 16, 8), (2, 8, 24), (3, 8, 0), (3, 16, 8), (4, 8, 0), (4, 16, 0)]
 
 
 @pytest.mark.parametrize("depth,th,nb", SHAPES)
@@ -82,13 +82,13 @@ def test_up3_phi_matches_oracle(ctx, depth, th, nb, vx, vy):
     v = np.random.default_rng(11).standard_normal((136, 200))
     say("up3 phi", depth, th, nb, vx, vy)
     r, o = _solve(ctx, depth, th, nb, op, v, [0, 1, 3], h, c, g, rtol=1e-9, max_iters=300)
-    assert r.status == B.LX_OK and r.stats["depth"] == depth
+    assert r.status == B.LX_OK and r.stats["depth"] == depth   # depth 4 runs 8-row tiles when 16 are asked
     spec = [(0, 1.0, 1.0), (1, 1.0, 1.0), (3, 1.0, 1.0)]
     oracle_parity(o, r.iters, lambda f: leja_phi(A, v, spec, h, c, g, 1e-9, 0.0, 300, f), PARITY)
 
 
-@pytest.mark.parametrize("nx,ny", [(4, 4), (6, 5), (130, 7), (97, 75), (256, 40)])
-@pytest.mark.parametrize("depth", [2, 1])
+@pytest.mark.parametrize("nx,ny", [(4, 4), (6, 5), (130, 7), (97, 75), (256, 40), (8, 8), (12, 9)])
+@pytest.mark.parametrize("depth", [4, 3, 2, 1])
 def test_up3_small_and_odd_grids(ctx, nx, ny, depth):
     """Grids narrower than a tile and than the 4-cell halo reach, odd sides
     (odd nx runs one iteration per launch whatever is asked)."""
@@ -98,7 +98,9 @@ def test_up3_small_and_odd_grids(ctx, nx, ny, depth):
     say("up3 small grid", nx, ny, depth)
     r, o = _solve(ctx, depth, 16, 0, op, v, [0, 2], h, c, g, rtol=1e-9, max_iters=300)
     assert r.status == B.LX_OK
-    assert r.stats["depth"] == (depth if nx % 2 == 0 else 1)
+    # odd nx: one iteration per launch; windows need sides of 2 depth cells
+    want = 1 if nx % 2 else (depth if depth <= 2 or min(nx, ny) >= 2 * depth else 2)
+    assert r.stats["depth"] == want
     spec = [(0, 1.0, 1.0), (2, 1.0, 1.0)]
     oracle_parity(o, r.iters, lambda f: leja_phi(A, v, spec, h, c, g, 1e-9, 0.0, 300, f), PARITY)
 
@@ -116,6 +118,17 @@ def test_up3_depths_agree_and_tile_rows_capped(ctx):
     assert r2.stats["depth"] == 2 and r1.stats["depth"] == 1
     if r2.iters == r1.iters:
         assert max(rel(a, b) for a, b in zip(o2, o1)) <= 1e-13
+
+
+@pytest.mark.parametrize("iters", [1, 6, 20])
+def test_up3_blocked_power_iteration(ctx, iters):
+    prm, op, A, _ = _setup(136, 72, vx=-40.0, vy=90.0)
+    x0 = np.random.default_rng(iters).standard_normal((72, 136))
+    say("up3 blocked power", iters)
+    rho, c, g = ctx.spectrum(op, x0=dev(x0), iters=iters)
+    assert ctx.stats()["depth"] == 4
+    rho_o, _ = power_iteration(A, x0, iters)
+    assert abs(rho - rho_o) <= 1e-12 * rho_o
 
 
 def test_up3_fp32_sweeps_within_tolerance(ctx):
