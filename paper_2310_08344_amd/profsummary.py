@@ -11,9 +11,9 @@ csv -o run` and `rocprofv3 --pmc FETCH_SIZE|WRITE_SIZE --output-format csv
   copy kernel of known size in the same run (`lx_bandwidth_probe`, 2^26 FP64
   elements: 512 MiB read and 512 MiB written).
 
-    python -m paper_2310_08344_amd.profsummary stats DIR [--kernel leja_sweep] [--exit-us 20]
+    python -m paper_2310_08344_amd.profsummary stats DIR [--kernel leja_sweep] [--exit-us 20] [--max-us T]
     python -m paper_2310_08344_amd.profsummary traffic FETCH_DIR WRITE_DIR --points N
-        [--kernel leja_sweep] [--algorithmic BYTES] [--json OUT]
+        [--kernel leja_sweep] [--algorithmic BYTES] [--max-bpp B] [--json OUT]
 """
 from __future__ import annotations
 
@@ -69,9 +69,9 @@ def trace(d: str, kernel: str):
     return out
 
 
-def split_launches(d: str, kernel: str, exit_us: float):
+def split_launches(d: str, kernel: str, exit_us: float, max_us: float = float("inf")):
     t = trace(d, kernel)
-    work = [x / 1e3 for _, x in t if x / 1e3 >= exit_us]
+    work = [x / 1e3 for _, x in t if exit_us <= x / 1e3 < max_us]
     idle = [x / 1e3 for _, x in t if x / 1e3 < exit_us]
     return work, idle
 
@@ -93,7 +93,8 @@ def _values(c, kernel):
     return [v for _, (n, v) in sorted(c.items()) if kernel in n]
 
 
-def traffic(fetch_dir: str, write_dir: str, kernel: str, points: int, exit_bytes_per_point: float = 1.0):
+def traffic(fetch_dir: str, write_dir: str, kernel: str, points: int, exit_bytes_per_point: float = 1.0,
+            max_bytes_per_point: float = float("inf")):
     f = _counter(fetch_dir, "FETCH_SIZE")
     w = _counter(write_dir, "WRITE_SIZE")
     cf, cw = _values(f, "copy_kernel"), _values(w, "copy_kernel")
@@ -106,7 +107,7 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str, points: int, exit_bytes
     if len(kf) != len(kw):
         raise SystemExit(f"{kernel}: {len(kf)} FETCH dispatches but {len(kw)} WRITE dispatches")
     # working launches: those that moved at least exit_bytes_per_point bytes per point
-    pairs = [(a, b) for a, b in zip(kf, kw) if a + b >= exit_bytes_per_point * points]
+    pairs = [(a, b) for a, b in zip(kf, kw) if exit_bytes_per_point * points <= a + b < max_bytes_per_point * points]
     return {
         "counter_scale": {"FETCH_SIZE": round(scale_f, 4), "WRITE_SIZE": round(scale_w, 4)},
         "working_launches": len(pairs),
@@ -123,12 +124,16 @@ def main(argv=None) -> int:
     s.add_argument("dir")
     s.add_argument("--kernel", default="leja_sweep")
     s.add_argument("--exit-us", type=float, default=20.0)
+    s.add_argument("--max-us", type=float, default=float("inf"),
+                   help="count only working launches shorter than this (separates grid sizes)")
     t = sub.add_parser("traffic")
     t.add_argument("fetch_dir")
     t.add_argument("write_dir")
     t.add_argument("--points", type=int, required=True)
     t.add_argument("--kernel", default="leja_sweep")
     t.add_argument("--algorithmic", type=float, default=None, help="algorithmic bytes per working launch")
+    t.add_argument("--max-bpp", type=float, default=float("inf"),
+                   help="count only launches below this many bytes per point (separates grid sizes)")
     t.add_argument("--json", default=None)
     a = ap.parse_args(argv)
     if a.cmd == "stats":
@@ -137,13 +142,14 @@ def main(argv=None) -> int:
         for r in kernel_stats(a.dir):
             print(f"| `{r['kernel']}` | {r['calls']} | {r['avg_us']:.2f} | {r['min_us']:.2f} | "
                   f"{r['max_us']:.2f} | {r['share']:.1f}% |")
-        work, idle = split_launches(a.dir, a.kernel, a.exit_us)
+        work, idle = split_launches(a.dir, a.kernel, a.exit_us, a.max_us)
         if work:
-            print(f"\n{a.kernel}: {len(work)} working launches, average {st.mean(work):.2f} us, "
+            band = f" below {a.max_us:g} us" if a.max_us != float("inf") else ""
+            print(f"\n{a.kernel}: {len(work)} working launches{band}, average {st.mean(work):.2f} us, "
                   f"median {st.median(work):.2f} us; {len(idle)} early-exit launches"
                   + (f", average {st.mean(idle):.2f} us" if idle else ""))
     else:
-        r = traffic(a.fetch_dir, a.write_dir, a.kernel, a.points)
+        r = traffic(a.fetch_dir, a.write_dir, a.kernel, a.points, max_bytes_per_point=a.max_bpp)
         r["kernel"] = a.kernel
         r["sweep_source_sha256"] = sweep_source_hash()
         if a.algorithmic and r["hbm_bytes_per_launch"]:
