@@ -100,6 +100,13 @@ __global__ __launch_bounds__(kBlockThreads) void power_sweep(PowerArgs a, const 
     if (flat_tid() == 0) a.partials[static_cast<long>(k & 1) * a.nb + blockIdx.x] = v[0];
 }
 
+// h (A u + S), tiled like the power sweep (the sums of squares are unused)
+template <int OP, int RY, int V>
+__global__ __launch_bounds__(kBlockThreads) void rhs_sweep(PowerArgs a, const double h) {
+    double acc = 0.0;
+    for_each_tile(a.tiles_x * a.tiles_y, a.nb, [&](int t) { power_tile<OP, RY, V>(a, h, acc, t); });
+}
+
 // partial sums of |x|^2 of the start vector into partials[1][*]
 __global__ __launch_bounds__(kBlockThreads) void power_norm_kernel(const double* __restrict__ x, long n,
                                                                    double* __restrict__ partials) {
@@ -187,26 +194,6 @@ __global__ void burgers_remainder_kernel(const double* __restrict__ u, const dou
         const double Ja = nu * lapa - ((u[ce] * ae - u[cw] * aw) / (2.0 * dx) + (u[cn] * an - u[cs] * as) / (2.0 * dy));
         const double Fu = burgers_F_at(u, i, j, nx, ny, nu, dx, dy);
         out[t] = h * (Fw - Fu - Ja);
-    }
-}
-
-// out = h (A u + S), S optional: the vector whose phi_1 action advances the
-// linear problem with a source (Sec. 3, Problem II).  st is the stencil of
-// A with the radius-2 neighbours (zero for the five-point operator).
-__global__ void linear_rhs_kernel(const double* __restrict__ u, const double* __restrict__ S,
-                                  double* __restrict__ out, int nx, int ny, double cE, double cW, double cN,
-                                  double cS, double cC, double cE2, double cW2, double cN2, double cS2, double h) {
-    const long n = static_cast<long>(nx) * ny;
-    for (long t = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x; t < n;
-         t += static_cast<long>(gridDim.x) * blockDim.x) {
-        const int i = static_cast<int>(t % nx), j = static_cast<int>(t / nx);
-        const long r = static_cast<long>(j) * nx;
-        const long rs = static_cast<long>(wrap(j - 1, ny)) * nx, rn = static_cast<long>(wrap(j + 1, ny)) * nx;
-        const long rs2 = static_cast<long>(wrap(j - 2, ny)) * nx, rn2 = static_cast<long>(wrap(j + 2, ny)) * nx;
-        const int iw = wrap(i - 1, nx), ie = wrap(i + 1, nx), iw2 = wrap(i - 2, nx), ie2 = wrap(i + 2, nx);
-        const double Au = stencil_d3(cW, cE, cS, cN, cC, cW2, cE2, cS2, cN2, u[r + iw], u[r + ie], u[rs + i],
-                                     u[rn + i], u[r + i], u[r + iw2], u[r + ie2], u[rs2 + i], u[rn2 + i]);
-        out[t] = h * ((S != nullptr) ? Au + S[t] : Au);
     }
 }
 
@@ -323,6 +310,24 @@ hipError_t launch_power_r(const Tile& t, const PowerArgs& a, int k, hipStream_t 
     }
 }
 
+template <int OP, int RY>
+hipError_t launch_rhs_v(const Tile& t, const PowerArgs& a, double h, hipStream_t s) {
+    if (t.vec == 2) hipLaunchKernelGGL((rhs_sweep<OP, RY, 2>), dim3(a.nb), dim3(t.tx, t.ty), 0, s, a, h);
+    else hipLaunchKernelGGL((rhs_sweep<OP, RY, 1>), dim3(a.nb), dim3(t.tx, t.ty), 0, s, a, h);
+    return hipGetLastError();
+}
+
+template <int OP>
+hipError_t launch_rhs_r(const Tile& t, const PowerArgs& a, double h, hipStream_t s) {
+    switch (t.ry) {
+        case 1: return launch_rhs_v<OP, 1>(t, a, h, s);
+        case 2: return launch_rhs_v<OP, 2>(t, a, h, s);
+        case 4: return launch_rhs_v<OP, 4>(t, a, h, s);
+        case 8: return launch_rhs_v<OP, 8>(t, a, h, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 int flat_blocks(long n) {
     long b = (n + kBlockThreads - 1) / kBlockThreads;
     if (b > 4096) b = 4096;
@@ -346,6 +351,13 @@ hipError_t launch_power_sweep(int op, const Tile& t, const PowerArgs& a, int k, 
     if (op == kOpDiffAdv) return launch_power_r<kOpDiffAdv>(t, a, k, s);
     if (op == kOpBurgersJ) return launch_power_r<kOpBurgersJ>(t, a, k, s);
     if (op == kOpDiffAdv3) return launch_power_r<kOpDiffAdv3>(t, a, k, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_rhs_sweep(int op, const Tile& t, const PowerArgs& a, double h, hipStream_t s) {
+    if (t.tx * t.ty != kBlockThreads || a.nb < 1) return hipErrorInvalidValue;
+    if (op == kOpDiffAdv) return launch_rhs_r<kOpDiffAdv>(t, a, h, s);
+    if (op == kOpDiffAdv3) return launch_rhs_r<kOpDiffAdv3>(t, a, h, s);
     return hipErrorInvalidValue;
 }
 
@@ -397,14 +409,6 @@ hipError_t launch_burgers_remainder(const double* u, const double* a, double* ou
                                     double dx, double dy, double h, hipStream_t s) {
     hipLaunchKernelGGL(burgers_remainder_kernel, dim3(flat_blocks(static_cast<long>(nx) * ny)),
                        dim3(kBlockThreads), 0, s, u, a, out, nx, ny, nu, dx, dy, h);
-    return hipGetLastError();
-}
-
-hipError_t launch_linear_rhs(int op, const double* u, const double* S, double* out, int nx, int ny,
-                             const double (&st)[9], double h, hipStream_t s) {
-    if ((op != kOpDiffAdv && op != kOpDiffAdv3) || nx < 3 || ny < 3) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(linear_rhs_kernel, dim3(flat_blocks(static_cast<long>(nx) * ny)), dim3(kBlockThreads), 0, s,
-                       u, S, out, nx, ny, st[0], st[1], st[2], st[3], st[4], st[5], st[6], st[7], st[8], h);
     return hipGetLastError();
 }
 

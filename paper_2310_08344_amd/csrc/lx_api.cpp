@@ -1081,9 +1081,30 @@ lx_status lx_linear_step(lx_ctx* ctx, const lx_operator* op, const double* d_u, 
         // Problem II: u + phi_1(h A) h (A u + S)
         if (ctx->ws[0] == nullptr && hipMalloc(&ctx->ws[0], sizeof(double) * ctx->n_max) != hipSuccess)
             return fail(ctx, LX_ENOMEM, "linear-step workspace allocation failed");
+        // h (A u + S) with the power sweep's tiles and shape
         double k9[9];
         diffadv_stencil9(*op, 0.0, 1.0, k9);
-        LX_HIP(ctx, lx::launch_linear_rhs(opcode_of(op->kind), d_u, d_src, ctx->ws[0], nx, ny, k9, h, ctx->stream));
+        const bool vec2 = aligned16(d_u) && aligned16(d_src) && aligned16(ctx->ws[0]);
+        const Tile t = pick_tile(ctx, *op, 1, vec2);
+        PowerArgs a{};
+        a.nx = nx;
+        a.ny = ny;
+        a.tiles_x = (nx + t.cols() - 1) / t.cols();
+        a.tiles_y = (ny + t.rows() - 1) / t.rows();
+        a.nb = grid_size(t, a.tiles_x * a.tiles_y);
+        a.cE = k9[0];
+        a.cW = k9[1];
+        a.cN = k9[2];
+        a.cS = k9[3];
+        a.cC = k9[4];
+        a.cE2 = k9[5];
+        a.cW2 = k9[6];
+        a.cN2 = k9[7];
+        a.cS2 = k9[8];
+        a.in = d_u;
+        a.out = ctx->ws[0];
+        a.add = d_src;
+        LX_HIP(ctx, lx::launch_rhs_sweep(opcode_of(op->kind), t, a, h, ctx->stream));
         q.l[0] = 1;
         q.v = ctx->ws[0];
         s = run_leja_sub(ctx, q);

@@ -93,6 +93,7 @@ struct PowerArgs {
     const double* in;
     double* out;
     const double* u;
+    const double* add;             // rhs_sweep: the source S (else NULL)
     double* partials;              // [2][nb]
     LoopCtl* ctl;
 };
@@ -167,11 +168,9 @@ hipError_t launch_burgers_hF(const double* u, double* out, int nx, int ny, doubl
 // h [N(u + a) - N(u)], N(w) = F(w) - J(u) w
 hipError_t launch_burgers_remainder(const double* u, const double* a, double* out, int nx, int ny,
                                     double nu, double dx, double dy, double h, hipStream_t s);
-// out = h (A u + S) for the linear operators (S may be NULL); st holds the
-// stencil of A as {cE, cW, cN, cS, cC, cE2, cW2, cN2, cS2} (the last four 0
-// for kOpDiffAdv)
-hipError_t launch_linear_rhs(int op, const double* u, const double* S, double* out, int nx, int ny,
-                             const double (&st)[9], double h, hipStream_t s);
+// out = h (A u + S) with a tiled sweep (PowerArgs: stencil of A, in = u,
+// out, add = S or NULL; the shape of lx_spectrum's power sweeps)
+hipError_t launch_rhs_sweep(int op, const Tile& t, const PowerArgs& a, double h, hipStream_t s);
 // out = b * base + sum_i a[i] * x[i] (base may be NULL; at most 8 terms)
 struct LinComb {
     const double* x[8];

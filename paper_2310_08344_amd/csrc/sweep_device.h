@@ -496,8 +496,16 @@ __device__ __forceinline__ void power_tile(const PowerArgs& a, const double s, d
                 o[0] = stencil_bu(a.kx, a.ky, a.gx, a.gy, kc, left, right, up[0], dn[0], cen[0], ul, ur, uup[0], udn[0]);
             }
         }
+        if (a.add != nullptr) {
+            // s (A in + add): the right-hand side h (A u + S) of a linear step
+            double sv[V];
+            ldv<V>(a.add + rw * nx + c0, sv);
 #pragma unroll
-        for (int i = 0; i < V; ++i) o[i] *= s;
+            for (int i = 0; i < V; ++i) o[i] = s * (o[i] + sv[i]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < V; ++i) o[i] *= s;
+        }
         if (ok) {
             stv<V>(out + rw * nx + c0, o);
 #pragma unroll
