@@ -394,17 +394,22 @@ lx_status lx_phi_leja_learned(lx_ctx* ctx, lx_predictor* p, int n, const lx_inst
  * grid, output count K and precision on the context's stream (about
  * `sweeps` timed iterations per candidate, after two warm-up launches, on
  * scratch vectors the call allocates and frees): the one-sweep shapes
- * (tx, ty, ry, vec, workgroups) and, for FP64 with even nx, the
- * two-iteration shapes (tile rows th, workgroups).  It keeps the fastest
- * one-sweep shape (used by lx_spectrum and by depth-1 loops), the fastest
- * two-iteration shape, and the depth with the lower time per iteration:
- * later calls with the same (kind, nx, ny, K, prec) use them.  When the
+ * (tx, ty, ry, vec, workgroups) and, for FP64 with even nx, the shapes of
+ * two iterations per launch and (diffusion-advection operators) of windows
+ * of three and four (tile rows th, workgroups).  It keeps the fastest
+ * one-sweep shape (used by the one-sweep power iteration, the right-hand
+ * side of lx_linear_step and depth-1 loops) and the fastest multi-iteration
+ * shape with its depth, and of the two the one with the lower time per
+ * iteration: later calls with the same (kind, nx, ny, K, prec) use them
+ * (the window kernel needs a second buffer per output, which this call
+ * allocates and keeps in the context).  When the
  * environment variable LX_TUNE_CACHE names a file, the winners are
  * appended to it as one JSON object per line, and lx_create loads the
  * file's entries.
  * report: host buffer of report_len chars, or NULL; receives one line per
  * candidate: "depth tx ty rows vec workgroups microseconds_per_iteration",
- * rows being ry for depth 1 and th for depth 2 (whose workgroups are 64 x 4).
+ * rows being ry for depth 1 and th for depths 2..4 (whose workgroups are
+ * 64 x 4).
  * Errors: LX_EINVAL (op invalid, K out of range, sweeps outside 1..200),
  * LX_ENOMEM. */
 lx_status lx_tune(lx_ctx* ctx, const lx_operator* op, int K, int sweeps, char* report, size_t report_len);
