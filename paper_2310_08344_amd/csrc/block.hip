@@ -637,10 +637,10 @@ __global__ __launch_bounds__(kBlockThreads) void power_block_final(PowerArgs a, 
     }
 }
 
-// at most 64 KB of static LDS per workgroup
+// gfx950 gives a workgroup up to 160 KB of LDS; keep two workgroups per CU
 template <int OP, int TH, int D>
 constexpr bool block_fits() {
-    return sizeof(BlockLds<OP, TH, D>) <= 63 * 1024;
+    return sizeof(BlockLds<OP, TH, D>) <= 78 * 1024;
 }
 
 template <int OP, int K, int D>

@@ -271,8 +271,6 @@ void choose_depth(const lx_ctx* ctx, const lx_operator& op, int K, bool vec2_ok,
     // a radius-2 stencil stages 8 edge cells per row, and three or four
     // iterations per launch hold two levels in LDS: tiles of at most 16 rows
     if ((op.kind == LX_OP_DIFFADV2D_UP3 || t.depth >= 3) && t.th > 16) t.th = 16;
-    // the radius-2 window of four holds 8-row tiles in 64 KB of LDS
-    if (op.kind == LX_OP_DIFFADV2D_UP3 && t.depth == 4) t.th = 8;
 }
 
 lx_status ensure_blk_ws(lx_ctx* ctx, int K) {
@@ -1404,7 +1402,6 @@ lx_status lx_tune(lx_ctx* ctx, const lx_operator* op, int K, int sweeps, char* r
             for (int th : {8, 16, 32}) {
                 // radius 2, and two LDS levels of windows: at most 16 rows
                 if (th > 16 && (op->kind == LX_OP_DIFFADV2D_UP3 || depth >= 3)) continue;
-                if (th > 8 && op->kind == LX_OP_DIFFADV2D_UP3 && depth == 4) continue;   // 64 KB of LDS
                 const int tiles = tiles_x * ((ny + th - 1) / th);
                 for (int pnb : {0, 2048, 1536, 1024, 768, 512, 256}) {
                     if (pnb != 0 && pnb >= tiles) continue;
