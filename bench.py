@@ -334,7 +334,8 @@ def main() -> int:
             "traffic": traffic["bytes_per_launch"] if traffic else None,
             "kernel": ({2: "leja_pair (diffusion-advection, K=3, FP64, two iterations per launch)",
                         3: "leja_block (diffusion-advection, K=3, FP64, windows of three iterations)",
-                        4: "leja_block (diffusion-advection, K=3, FP64, windows of four iterations)"}.get(
+                        4: "leja_block (diffusion-advection, K=3, FP64, windows of four iterations)",
+                        6: "leja_block (diffusion-advection, K=3, FP64, windows of six iterations)"}.get(
                            depth, "leja_sweep (diffusion-advection, K=3, FP64)")),
             "launches": launches, "avg_launch_us": round(sweep_ms * 1e3 / launches, 2),
             "cache_note": "the outputs stream with nontemporal hints and the basis vector (8 of the 64 bytes per point "

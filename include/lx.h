@@ -396,7 +396,7 @@ lx_status lx_phi_leja_learned(lx_ctx* ctx, lx_predictor* p, int n, const lx_inst
  * scratch vectors the call allocates and frees): the one-sweep shapes
  * (tx, ty, ry, vec, workgroups) and, for FP64 with even nx, the shapes of
  * two iterations per launch and (diffusion-advection operators) of windows
- * of three and four (tile rows th, workgroups).  It keeps the fastest
+ * of three, four and six (tile rows th, workgroups).  It keeps the fastest
  * one-sweep shape (used by the one-sweep power iteration, the right-hand
  * side of lx_linear_step and depth-1 loops) and the fastest multi-iteration
  * shape with its depth, and of the two the one with the lower time per
@@ -426,17 +426,18 @@ lx_status lx_set_tile(lx_ctx* ctx, int tx, int ty, int ry, int vec, int nb);
  * depth 1 runs one fused sweep per launch (the shape of lx_set_tile);
  * depth 2 runs two iterations per launch on LDS-resident tiles of 128
  * columns by th (8, 16 or 32) rows with nb workgroups (0 = automatic),
- * reading the basis once per two iterations; depths 3 and 4 run windows of
- * that many iterations (th 8 or 16; larger th is taken as 16) whose terms
+ * reading the basis once per two iterations; depths 3, 4 and 6 run windows
+ * of that many iterations (th 8 or 16; larger th is taken as 16) whose terms
  * are added speculatively, and re-execute a window in which an output
  * stopped (they also use one more buffer per output, allocated on first
  * use); depth 0 restores the automatic choice (the tuned entry, else 2).
- * Depths 2..4 apply to FP64 sweeps on grids with even nx and 16-byte aligned
- * vectors, depths 3 and 4 to LX_OP_DIFFADV2D only (others use 2); other
- * calls use depth 1.  Results agree with depth 1 to rounding (the outputs
+ * Depths 2..6 apply to FP64 sweeps on grids with even nx and 16-byte aligned
+ * vectors; 3 and 4 to the diffusion-advection operators and 6 to
+ * LX_OP_DIFFADV2D (others fall back to 4, then 2), each with sides of at
+ * least depth times the stencil radius; other calls use depth 1.  Results agree with depth 1 to rounding (the outputs
  * take the same terms in the same order; only the order of the norm
  * reductions differs).
- * Errors: LX_EINVAL (depth outside 0..4, th not 0, 8, 16 or 32, nb < 0). */
+ * Errors: LX_EINVAL (depth not 0..4 or 6, th not 0, 8, 16 or 32, nb < 0). */
 lx_status lx_set_depth(lx_ctx* ctx, int depth, int th, int nb);
 
 /* Practical HBM bandwidth of plain streaming HIP kernels, the calibration

@@ -706,6 +706,7 @@ hipError_t launch_leja_block(int op, int K, int th, int depth, const SweepArgs& 
     if (op == kOpDiffAdv) {
         if (depth == 3) return launch_block_k<kOpDiffAdv, 3>(K, th, a, L, s);
         if (depth == 4) return launch_block_k<kOpDiffAdv, 4>(K, th, a, L, s);
+        if (depth == 6) return launch_block_k<kOpDiffAdv, 6>(K, th, a, L, s);
     } else {
         if (depth == 3) return launch_block_k<kOpDiffAdv3, 3>(K, th, a, L, s);
         if (depth == 4) return launch_block_k<kOpDiffAdv3, 4>(K, th, a, L, s);

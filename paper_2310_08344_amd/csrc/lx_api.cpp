@@ -217,7 +217,7 @@ void load_tune_cache(lx_ctx* ctx) {
                               "\"pnb\": %d",
                         &kind, &nx, &ny, &K, &prec, &t.tx, &t.ty, &t.ry, &t.vec, &t.nb, &t.depth, &t.th,
                         &t.pnb) == 13 &&
-            valid_tile(t) && t.depth >= 1 && t.depth <= 4 && (t.th == 8 || t.th == 16 || t.th == 32) &&
+            valid_tile(t) && t.depth >= 1 && t.depth <= 6 && t.depth != 5 && (t.th == 8 || t.th == 16 || t.th == 32) &&
             t.pnb >= 0) {
             ctx->tuned[std::make_tuple(kind, nx, ny, K, prec)] = t;
         }
@@ -258,6 +258,7 @@ void choose_depth(const lx_ctx* ctx, const lx_operator& op, int K, bool vec2_ok,
     // wrap allows only on sides of at least that many cells
     const int halo = depth * (op.kind == LX_OP_DIFFADV2D_UP3 ? 2 : 1);
     if (depth >= 3 && (!is_diffadv(op.kind) || op.nx < halo || op.ny < halo)) depth = 2;
+    if (depth == 6 && op.kind != LX_OP_DIFFADV2D) depth = 4;   // six: the five-point operator only
     t.depth = (depth >= 2 && pair_ok) ? depth : 1;
     if (it != ctx->tuned.end() && it->second.depth >= 2 && it->second.depth == t.depth) {
         t.th = it->second.th;
@@ -1254,8 +1255,9 @@ lx_status lx_exprb_step(lx_ctx* ctx, const lx_operator* op, int scheme, const do
 
 lx_status lx_set_depth(lx_ctx* ctx, int depth, int th, int nb) {
     if (ctx == nullptr) return LX_EINVAL;
-    if (depth < 0 || depth > 4 || !(th == 0 || th == 8 || th == 16 || th == 32) || nb < 0)
-        return fail(ctx, LX_EINVAL, "depth %d, th %d, nb %d: need depth 0..4, th 0/8/16/32, nb >= 0", depth, th, nb);
+    if (depth < 0 || depth == 5 || depth > 6 || !(th == 0 || th == 8 || th == 16 || th == 32) || nb < 0)
+        return fail(ctx, LX_EINVAL, "depth %d, th %d, nb %d: need depth 0..4 or 6, th 0/8/16/32, nb >= 0", depth, th,
+                    nb);
     ctx->depth_forced = depth;
     ctx->pair_th = th;
     ctx->pair_nb = nb;
@@ -1392,7 +1394,8 @@ lx_status lx_tune(lx_ctx* ctx, const lx_operator* op, int K, int sweeps, char* r
     double best_pair_us = 1e300;
     if (op->prec == LX_FP64 && nx % 2 == 0) {
         const int tiles_x = (nx + 127) / 128;
-        for (int depth : {2, 3, 4}) {
+        for (int depth : {2, 3, 4, 6}) {
+            if (depth == 6 && op->kind != LX_OP_DIFFADV2D) continue;
             const int halo = depth * (op->kind == LX_OP_DIFFADV2D_UP3 ? 2 : 1);
             if (depth >= 3 && (!is_diffadv(op->kind) || nx < halo || ny < halo)) continue;
             if (depth >= 3) {

@@ -50,7 +50,8 @@ def _solve(ctx, depth, th, nb, op, v, ls, h, c, g, **kw):
     return r, [host(o) for o in outs]
 
 
-@pytest.mark.parametrize("depth,th,nb", [(3, 8, 0), (3, 16, 0), (4, 8, 0), (4, 16, 0), (4, 16, 8), (3, 8, 24)])
+@pytest.mark.parametrize("depth,th,nb", [(3, 8, 0), (3, 16, 0), (4, 8, 0), (4, 16, 0), (4, 16, 8), (3, 8, 24),
+                                         (6, 8, 0), (6, 16, 16)])
 def test_windows_match_oracle_and_one_iteration(ctx, depth, th, nb):
     """Ragged tiles both ways (200 = 128 + 72 columns, 136 rows); phi_0,
     phi_1 and phi_3 stop in different windows."""
@@ -80,8 +81,8 @@ def test_windows_match_oracle_and_one_iteration(ctx, depth, th, nb):
     assert rb.stats["n_apply"] == depth * windows + sum(redo.values())
 
 
-@pytest.mark.parametrize("depth", [3, 4])
-@pytest.mark.parametrize("nx,ny", [(6, 5), (4, 3), (130, 7), (256, 40)])
+@pytest.mark.parametrize("depth", [3, 4, 6])
+@pytest.mark.parametrize("nx,ny", [(6, 5), (4, 3), (130, 7), (256, 40), (8, 6)])
 def test_windows_small_and_odd_grids(ctx, depth, nx, ny):
     """Grids narrower than a tile and than the halo (indices wrap several
     times), an odd number of rows, a single partial tile row; four outputs."""
@@ -96,8 +97,8 @@ def test_windows_small_and_odd_grids(ctx, depth, nx, ny):
     oracle_parity(o, r.iters, lambda f: leja_phi(_A(prm), v, spec, h, c, g, 1e-9, 0.0, 300, f), PARITY)
 
 
-@pytest.mark.parametrize("depth", [3, 4])
-@pytest.mark.parametrize("max_iters", [1, 2, 3, 4, 5, 7, 9])
+@pytest.mark.parametrize("depth", [3, 4, 6])
+@pytest.mark.parametrize("max_iters", [1, 2, 3, 4, 5, 6, 7, 9, 13])
 def test_windows_at_max_iters(ctx, depth, max_iters):
     """The budget ends at every position inside a window: LX_ENOTCONV with
     exactly max_iters terms."""
@@ -112,7 +113,7 @@ def test_windows_at_max_iters(ctx, depth, max_iters):
     assert max(rel(a, b) for a, b in zip(o, ref.p)) <= PARITY
 
 
-@pytest.mark.parametrize("depth", [3, 4])
+@pytest.mark.parametrize("depth", [3, 4, 6])
 def test_windows_edge_inputs(ctx, depth):
     prm, h = diffadv_setup(64, 64)
     c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
@@ -125,7 +126,7 @@ def test_windows_edge_inputs(ctx, depth):
     assert r.status == B.LX_ENONFINITE
 
 
-@pytest.mark.parametrize("depth", [3, 4])
+@pytest.mark.parametrize("depth", [3, 4, 6])
 def test_windows_1024_squared_workload(ctx, depth):
     p, v = W.config2(n=1024)
     op = B.make_operator(p)
@@ -183,7 +184,7 @@ def test_blocked_power_iteration_matches_oracle(ctx, nx, ny, iters):
     assert abs(rho - rho_o) <= 1e-12 * rho_o
 
 
-@pytest.mark.parametrize("depth", [3, 4])
+@pytest.mark.parametrize("depth", [3, 4, 6])
 def test_windows_with_the_largest_budget(ctx, depth):
     """max_iters = LX_MAX_ITERS: the window past the budget reads Leja
     points and coefficients up to d_{max_iters + depth}."""
