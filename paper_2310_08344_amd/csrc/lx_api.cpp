@@ -413,7 +413,11 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
     }
     auto coeffs_for = [&](int launches) { return per * launches + 1; };   // d_0 .. d_{per*launches}
     int launched = 0, chunk_id = 0, last_slot = -1;
-    int chunk = kFirstChunk / per;
+    // launches per chunk: about kFirstChunk and kChunk iterations, but at
+    // least three and two launches, so that the queue never runs dry while
+    // the host looks at the state of the chunk before
+    const int first_chunk = std::max(3, kFirstChunk / per), next_chunk = std::max(2, kChunk / per);
+    int chunk = first_chunk;
     while (launched <= last) {
         const int n = std::min(chunk, last + 1 - launched);
         s = ensure_coeffs(coeffs_for(launched + n));
@@ -433,14 +437,14 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
         last_slot = slot;
         if (chunk_id >= 1) {
             // the next chunk's coefficients are prepared while the GPU works
-            s = ensure_coeffs(coeffs_for(std::min(launched + kChunk / per, last)));
+            s = ensure_coeffs(coeffs_for(std::min(launched + next_chunk, last)));
             if (s != LX_OK) return s;
             const int prev = slot ^ 1;
             LX_HIP(ctx, hipEventSynchronize(ctx->poll_ev[prev]));
             if (ctx->h_poll[prev].done) break;
         }
         ++chunk_id;
-        chunk = kChunk / per;
+        chunk = next_chunk;
     }
     LX_HIP(ctx, hipEventSynchronize(ctx->poll_ev[last_slot]));
     const SweepState& fin = ctx->h_poll[last_slot];
