@@ -328,6 +328,14 @@ def main() -> int:
     last = recs[-1][1]
     per_launch = leja_bytes / launches
     depth = last["depth"]
+    # the bytes the same iterations move one per launch (y in and out, and
+    # each output still iterating in and out; the first sweep only writes p)
+    n_pts = float(p.n) ** 2
+    one_iter_bytes = 0.0
+    for _, r in recs:
+        its = r["iters"][:3]
+        for m in range(max(its)):
+            one_iter_bytes += n_pts * (16.0 + sum((8.0 if m == 0 else 16.0) for i in its if m < i))
     traffic = committed_traffic(per_launch)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -338,9 +346,11 @@ def main() -> int:
                         6: "leja_block (diffusion-advection, K=3, FP64, windows of six iterations)"}.get(
                            depth, "leja_sweep (diffusion-advection, K=3, FP64)")),
             "launches": launches, "avg_launch_us": round(sweep_ms * 1e3 / launches, 2),
-            "cache_note": "the outputs stream with nontemporal hints and the basis vector (8 of the 64 bytes per point "
-                          "and launch) is mostly read back from the 256 MB Infinity Cache; the L2 traffic counters "
-                          "count it as memory traffic",
+            "iterations_per_launch": depth,
+            "one_iteration_equivalent_gbs": round(one_iter_bytes / (sweep_ms * 1e-3) / 1e9, 1),
+            "cache_note": "the outputs stream with nontemporal hints and the basis vector a launch reads (8 of the "
+                          "64 bytes per point of a window) is mostly served by the 256 MB Infinity Cache; the L2 "
+                          "traffic counters count it as memory traffic",
             "bytes_per_launch": per_launch}
     if traffic:
         roof["traffic_ratio_to_algorithmic"] = traffic["ratio_to_algorithmic"]
