@@ -53,6 +53,18 @@ struct BlockLds {
     static constexpr int P = kPairTW + 2 * CO;   // row pitch in doubles
     double a[ROWS][P];                           // levels 0, 2, ...: LDS row r = tile row r - H,
     double b[ROWS][P];                           // levels 1, 3, ...: LDS column c = tile column c - CO
+    static constexpr bool kHasU = false;
+    __device__ const double (*uu() const)[P] { return nullptr; }
+};
+// the Burgers Jacobian also reads the state u on the level-0 cells
+template <int TH, int D>
+struct BlockLds<kOpBurgersJ, TH, D> {
+    static constexpr int R = 1, H = D, CO = (H + 1) & ~1, ROWS = TH + 2 * H, P = kPairTW + 2 * CO;
+    double a[ROWS][P];
+    double b[ROWS][P];
+    double u[ROWS][P];
+    static constexpr bool kHasU = true;
+    __device__ const double (*uu() const)[P] { return u; }
 };
 
 // y_m of one tile as this thread stages it, loaded a tile ahead
@@ -103,11 +115,14 @@ __device__ __forceinline__ BlockY<TH, D, R> load_block_y(const TileArgs<K>& a, c
 }
 
 // the shifted operator at the column pair j, j+1 of LDS row r of `src`
+// (u: the Burgers state laid out as src, else NULL)
 template <int OP, int P>
 __device__ __forceinline__ void level_pair(const Sten& st, const double shift, const double (*src)[P], const int r,
-                                           const int j, double (&o)[2]) {
+                                           const int j, double (&o)[2], const double (*u)[P] = nullptr) {
     if constexpr (radius<OP>() == 2) {
         shifted_pair3(st, shift, src[r - 2], src[r - 1], src[r], src[r + 1], src[r + 2], j, o);
+    } else if constexpr (OP == kOpBurgersJ) {
+        shifted_pair<OP>(st, shift, src[r - 1], src[r], src[r + 1], u[r - 1], u[r], u[r + 1], j, o);
     } else {
         shifted_pair<OP>(st, shift, src[r - 1], src[r], src[r + 1], nullptr, nullptr, nullptr, j, o);
     }
@@ -115,9 +130,11 @@ __device__ __forceinline__ void level_pair(const Sten& st, const double shift, c
 
 template <int OP, int P>
 __device__ __forceinline__ double level_one(const Sten& st, const double shift, const double (*src)[P], const int r,
-                                            const int j) {
+                                            const int j, const double (*u)[P] = nullptr) {
     if constexpr (radius<OP>() == 2) {
         return shifted_one3(st, shift, src[r - 2], src[r - 1], src[r], src[r + 1], src[r + 2], j);
+    } else if constexpr (OP == kOpBurgersJ) {
+        return shifted_one<OP>(st, shift, src[r - 1], src[r], src[r + 1], u[r - 1], u[r], u[r + 1], j);
     } else {
         return shifted_one<OP>(st, shift, src[r - 1], src[r], src[r + 1], nullptr, nullptr, nullptr, j);
     }
@@ -152,6 +169,19 @@ __device__ __forceinline__ void block_tile(const TileArgs<K>& a, BlockLds<OP, TH
         for (int i = 0; i < RW; ++i) {
             const int grow = y0 + w + i * kPairWaves;
             if (gcol < nx && grow < ny) pv[k][i] = ld_stream(pin[k] + static_cast<long>(grow) * nx + gcol);
+        }
+    }
+    // ---- the Burgers state on the level-0 cells (the same every launch: L2) ----
+    if constexpr (L::kHasU) {
+        const double* __restrict__ uu = a.u;
+        const int gc = wrap(gcol, nx);
+        for (int r = w; r < ROWS; r += kPairWaves)
+            *reinterpret_cast<double2*>(&S.u[r][j0]) =
+                *reinterpret_cast<const double2*>(uu + wrap(y0 - H + r, ny) * static_cast<long>(nx) + gc);
+        for (int e = tid; e < Y::E; e += kBlockThreads) {
+            const int row = e / (2 * H), qq = e % (2 * H);
+            const int tc = (qq < H) ? qq - H : kPairTW + (qq - H);
+            S.u[row][CO + tc] = uu[wrap(y0 - H + row, ny) * static_cast<long>(nx) + wrap(x0 + tc, nx)];
         }
     }
     // ---- level 0: y_m on rows -H..TH+H-1, columns -H..127+H ----
@@ -204,7 +234,7 @@ __device__ __forceinline__ void block_tile(const TileArgs<K>& a, BlockLds<OP, TH
             const int r = r_lo + w + i * kPairWaves;
             if (r < r_hi) {
                 double o[2];
-                level_pair<OP, P>(a.st, shift, src, r, j0, o);
+                level_pair<OP, P>(a.st, shift, src, r, j0, o, S.uu());
                 double2 t;
                 t.x = o[0];
                 t.y = o[1];
@@ -217,7 +247,7 @@ __device__ __forceinline__ void block_tile(const TileArgs<K>& a, BlockLds<OP, TH
         for (int e = tid; e < ne; e += kBlockThreads) {
             const int r = r_lo + e / (2 * side), qq = e % (2 * side);
             const int tc = (qq < side) ? qq - side : kPairTW + (qq - side);
-            dst[r][CO + tc] = level_one<OP, P>(a.st, shift, src, r, CO + tc);
+            dst[r][CO + tc] = level_one<OP, P>(a.st, shift, src, r, CO + tc, S.uu());
         }
         __syncthreads();
 #pragma unroll
@@ -247,7 +277,7 @@ __device__ __forceinline__ void block_tile(const TileArgs<K>& a, BlockLds<OP, TH
             const int r = H + w + i * kPairWaves;
             const int grow = y0 + w + i * kPairWaves;
             double o[2];
-            level_pair<OP, P>(a.st, shift, src, r, j0, o);
+            level_pair<OP, P>(a.st, shift, src, r, j0, o, S.uu());
             if (gcol < nx && grow < ny) {
                 const long idx = static_cast<long>(grow) * nx + gcol;
                 if (store_y) {
@@ -369,7 +399,7 @@ __global__ __launch_bounds__(kBlockThreads) void leja_block(SweepArgs a, const i
             for (int k = 0; k < kKMax; ++k) st.nt[k] = (k < K && st.active[k]) ? D : 0;
             st.n_work = 1;
             st.n_levels = D;
-            double b = 16.0;
+            double b = 16.0 + (OP == kOpBurgersJ ? 8.0 : 0.0);
             for (int k = 0; k < K; ++k) b += st.nt[k] ? 8.0 : 0.0;
             st.bytes_pp = b;
             s_cur = st;
@@ -386,7 +416,7 @@ __global__ __launch_bounds__(kBlockThreads) void leja_block(SweepArgs a, const i
                 // first window only writes it)
                 const bool rd = st.blk_mode == 1;
                 st.n_work += 1;
-                double b = rd ? 8.0 : 16.0;
+                double b = (rd ? 8.0 : 16.0) + (OP == kOpBurgersJ ? 8.0 : 0.0);   // y (and u)
                 int lev = rd ? 0 : D;
                 for (int k = 0; k < K; ++k) {
                     const bool w_k = rd ? st.nt[k] < 0 : st.nt[k] != 0;
@@ -702,11 +732,15 @@ hipError_t launch_leja_block(int op, int K, int th, int depth, const SweepArgs& 
     if (a.tiles_x != (a.nx + kPairTW - 1) / kPairTW || a.tiles_y != (a.ny + th - 1) / th)
         return hipErrorInvalidValue;
     const int H = depth * (op == kOpDiffAdv3 ? 2 : 1);
-    if ((op != kOpDiffAdv && op != kOpDiffAdv3) || a.nx < H || a.ny < H) return hipErrorInvalidValue;   // halo reach
+    if (a.nx < H || a.ny < H) return hipErrorInvalidValue;   // halo reach
     if (op == kOpDiffAdv) {
         if (depth == 3) return launch_block_k<kOpDiffAdv, 3>(K, th, a, L, s);
         if (depth == 4) return launch_block_k<kOpDiffAdv, 4>(K, th, a, L, s);
         if (depth == 6) return launch_block_k<kOpDiffAdv, 6>(K, th, a, L, s);
+    } else if (op == kOpBurgersJ) {
+        if (a.u == nullptr) return hipErrorInvalidValue;
+        if (depth == 3) return launch_block_k<kOpBurgersJ, 3>(K, th, a, L, s);
+        if (depth == 4) return launch_block_k<kOpBurgersJ, 4>(K, th, a, L, s);
     } else {
         if (depth == 3) return launch_block_k<kOpDiffAdv3, 3>(K, th, a, L, s);
         if (depth == 4) return launch_block_k<kOpDiffAdv3, 4>(K, th, a, L, s);

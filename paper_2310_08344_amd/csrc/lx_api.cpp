@@ -246,8 +246,8 @@ struct LejaCall {
 
 // Iterations per launch for this call: forced by lx_set_depth, else the
 // tuned entry's, else two.  Two or more need FP64 sweeps and 16-byte pairs;
-// three and four (speculative windows) the five-point diffusion-advection
-// operator, else two are used.
+// windows of three or more need sides of depth x radius cells (else two),
+// and six the five-point diffusion-advection operator (else four).
 void choose_depth(const lx_ctx* ctx, const lx_operator& op, int K, bool vec2_ok, Tile& t) {
     const bool pair_ok = op.prec == LX_FP64 && vec2_ok && op.nx % 2 == 0;
     auto it = ctx->tuned.find(std::make_tuple(op.kind, op.nx, op.ny, K, op.prec));
@@ -257,7 +257,7 @@ void choose_depth(const lx_ctx* ctx, const lx_operator& op, int K, bool vec2_ok,
     // windows stage a halo of depth * radius cells, which the periodic index
     // wrap allows only on sides of at least that many cells
     const int halo = depth * (op.kind == LX_OP_DIFFADV2D_UP3 ? 2 : 1);
-    if (depth >= 3 && (!is_diffadv(op.kind) || op.nx < halo || op.ny < halo)) depth = 2;
+    if (depth >= 3 && (op.nx < halo || op.ny < halo)) depth = 2;
     if (depth == 6 && op.kind != LX_OP_DIFFADV2D) depth = 4;   // six: the five-point operator only
     t.depth = (depth >= 2 && pair_ok) ? depth : 1;
     if (it != ctx->tuned.end() && it->second.depth >= 2 && it->second.depth == t.depth) {
@@ -1401,7 +1401,7 @@ lx_status lx_tune(lx_ctx* ctx, const lx_operator* op, int K, int sweeps, char* r
         for (int depth : {2, 3, 4, 6}) {
             if (depth == 6 && op->kind != LX_OP_DIFFADV2D) continue;
             const int halo = depth * (op->kind == LX_OP_DIFFADV2D_UP3 ? 2 : 1);
-            if (depth >= 3 && (!is_diffadv(op->kind) || nx < halo || ny < halo)) continue;
+            if (depth >= 3 && (nx < halo || ny < halo)) continue;
             if (depth >= 3) {
                 s = ensure_blk_ws(ctx, K);
                 if (s != LX_OK) return cleanup(s);

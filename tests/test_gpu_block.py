@@ -143,6 +143,55 @@ def test_windows_1024_squared_workload(ctx, depth):
         assert rel(ob, ex) <= 1e-7
 
 
+@pytest.mark.parametrize("depth,th", [(3, 16), (4, 8), (4, 16), (6, 16)])
+def test_burgers_jacobian_windows(ctx, depth, th):
+    """The Burgers state staged beside y_m in every window; six falls back
+    to four for this operator."""
+    n, ny = 130, 90
+    ub = W.fourier_modes(n, seed=5)[:ny, :]
+    nu = 2e-3
+    op_b = B.make_operator(kind=B.LX_OP_BURGERS2D, nx=n, ny=ny, dx=1 / n, dy=1 / ny, nu=nu)
+    vb = np.random.default_rng(2).standard_normal((ny, n))
+    hb = 5.0 * W.burgers_cfl_step(nu, float(np.max(np.abs(ub))), 1 / n, 1 / ny)
+    rho = 2.0 / W.burgers_cfl_step(nu, float(np.max(np.abs(ub))), 1 / n, 1 / ny)
+    cb, gb = -1.05 * rho / 2.0, 1.05 * rho / 4.0
+    say("burgers window", depth, th)
+    outs = [dev(np.zeros((ny, n))) for _ in range(2)]
+    ctx.set_depth(depth, th, 0)
+    try:
+        r = ctx.phi_leja(op_b, dev(vb), outs, [1, 2], hb, cb, gb, u=dev(ub), rtol=1e-8, max_iters=200)
+    finally:
+        ctx.set_depth(0)
+    assert r.status == B.LX_OK and r.stats["depth"] == min(depth, 4)
+    Ab = lambda w: burgers_J(ub, w, nu, 1 / n, 1 / ny)
+    oracle_parity([host(o) for o in outs], r.iters,
+                  lambda f: leja_phi(Ab, vb, [(1, 1.0, 1.0), (2, 1.0, 1.0)], hb, cb, gb, 1e-8, 0.0, 200, f), PARITY)
+
+
+@pytest.mark.parametrize("scheme", ["exprb42", "exprb32"])
+def test_integrator_steps_with_windows(ctx, scheme):
+    from oracle.phi_action import exprb32_step, exprb42_step
+    n = 128
+    nu = 2e-3
+    u0 = W.fourier_modes(n, seed=3)
+    umax = float(np.max(np.abs(u0)))
+    h = 2.0 * W.burgers_cfl_step(nu, umax, 1 / n, 1 / n)
+    op = B.make_operator(kind=B.LX_OP_BURGERS2D, n=n, nu=nu)
+    say("integrator windows", scheme)
+    rho, c, g = ctx.spectrum(op, u=dev(u0), x0=dev(W.start_vector(n)), iters=20)
+    out = dev(np.zeros((n, n)))
+    ctx.set_depth(4)
+    try:
+        code = {"exprb42": B.LX_EXPRB42, "exprb32": B.LX_EXPRB32}[scheme]
+        r = ctx.exprb_step(op, dev(u0), out, h, c, g, rtol=1e-10, max_iters=300, scheme=code)
+    finally:
+        ctx.set_depth(0)
+    assert r.status == B.LX_OK and r.stats["depth"] == 4
+    step = {"exprb42": exprb42_step, "exprb32": exprb32_step}[scheme]
+    ref = step(u0, nu, 1 / n, 1 / n, h, c, g, 1e-10, 0.0, 300)
+    assert rel(host(out), ref.u_next) <= 1e-9
+
+
 def test_windows_repeat_bitwise_and_other_operators_fall_back(ctx):
     prm, h = diffadv_setup(192, 160)
     c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
@@ -151,19 +200,19 @@ def test_windows_repeat_bitwise_and_other_operators_fall_back(ctx):
     r1, o1 = _solve(ctx, 4, 16, 0, _op(prm), v, [1, 2, 3], h, c, g, rtol=1e-8, max_iters=200)
     r2, o2 = _solve(ctx, 4, 16, 0, _op(prm), v, [1, 2, 3], h, c, g, rtol=1e-8, max_iters=200)
     assert r1.iters == r2.iters and all(np.array_equal(a, b) for a, b in zip(o1, o2))
-    # the Burgers Jacobian runs two iterations per launch when four are asked
+    # the Burgers Jacobian runs windows of four when six are asked
     n = 64
     ub = W.fourier_modes(n, seed=5)
     opb = B.make_operator(kind=B.LX_OP_BURGERS2D, n=n, nu=2e-2)
     hb = 2.0 * W.burgers_cfl_step(2e-2, float(np.max(np.abs(ub))), 1 / n, 1 / n)
     rho = 2.0 / W.burgers_cfl_step(2e-2, float(np.max(np.abs(ub))), 1 / n, 1 / n)
     out = dev(np.zeros((n, n)))
-    ctx.set_depth(4)
+    ctx.set_depth(6)
     try:
         rb = ctx.phi_leja(opb, dev(ub), [out], [1], hb, -1.05 * rho / 2, 1.05 * rho / 4, u=dev(ub), rtol=1e-8)
     finally:
         ctx.set_depth(0)
-    assert rb.status == B.LX_OK and rb.stats["depth"] == 2
+    assert rb.status == B.LX_OK and rb.stats["depth"] == 4
     ref = leja_phi(lambda w: burgers_J(ub, w, 2e-2, 1 / n, 1 / n), ub, [(1, 1.0, 1.0)], hb, -1.05 * rho / 2,
                    1.05 * rho / 4, 1e-8, 0.0, 500)
     assert rel(host(out), ref.p[0]) <= 1e-9
