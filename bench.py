@@ -21,6 +21,8 @@ Prints one JSON line on stdout:
                 per-instance path (both with power iteration)
   learned_1024  the learned + batched form against plain batched and plain
                 per-instance solves on 1024 instances at 256^2
+  exprb42_2048  one EXPRB42 step of the 2048^2 Burgers workload, FP64 and
+                FP32 sweeps
   paper_problems_8192
                 the paper's linear test problems (Sec. 3, Problems I and II:
                 nu = 10, third-order upwind gradient, tolerance 1e-12) at
@@ -247,6 +249,55 @@ def bench_paper_problems(lib, n: int = 8192, axpby_gbs=None, tune: bool = True, 
     return res
 
 
+def bench_exprb42(lib, n: int = 2048, repeats: int = 5) -> dict:
+    """One EXPRB42 step of the 2048^2 Burgers workload (nu = 1e-3, four
+    Fourier modes, h = 10 x CFL of the Jacobian, tolerance 1e-8), power
+    iteration included: FP64 sweeps (windows after tuning) and FP32 sweeps;
+    the FP32 update's relative difference from the FP64 one."""
+    import torch
+
+    from paper_2310_08344_amd import binding as B
+    from paper_2310_08344_amd import workloads as W
+
+    p, u0_h = W.config3(n=n)
+    dev = torch.device("cuda:0")
+    u0 = torch.as_tensor(u0_h).to(dev)
+    x0 = torch.as_tensor(W.start_vector(n)).to(dev)
+    out64, out32 = torch.empty_like(u0), torch.empty_like(u0)
+    ctx = lib.context(n_max=n * n, k_max=2)
+    res = {"workload": f"periodic viscous Burgers {n}^2, nu = 1e-3, u0 = 4 seeded Fourier modes, one EXPRB42 step "
+                       "h = 10 x CFL, tolerance 1e-8, 20 power sweeps", "grid": n}
+    try:
+        op = B.make_operator(p)
+        op32 = B.make_operator(p)
+        op32.prec = B.LX_FP32_SWEEP
+        for K in (2, 1):
+            ctx.tune(op, K=K, sweeps=8)
+
+        def step(o, out):
+            _, c, g = ctx.spectrum(o if o.prec == B.LX_FP64 else op, u=u0, x0=x0, iters=20)
+            r = ctx.exprb_step(o, u0, out, p.h, c, g, rtol=1e-8, max_iters=300)
+            if r.status != B.LX_OK:
+                raise RuntimeError(f"exprb_step status {r.status}: {ctx.last_error()}")
+            return r
+
+        for name, o, out in (("fp64", op, out64), ("fp32_sweeps", op32, out32)):
+            r = step(o, out)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(repeats):
+                r = step(o, out)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / repeats
+            res[name] = {"ms_per_step": round(dt * 1e3, 3), "iters_phi1_phi3": list(r.iters),
+                         "depth": r.stats["depth"], "fp32_sweeps": r.stats["n_fp32"]}
+        du64 = out64 - u0
+        res["fp32_update_rel_diff_vs_fp64"] = float(torch.linalg.norm(out32 - out64) / torch.linalg.norm(du64))
+    finally:
+        ctx.close()
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -383,6 +434,9 @@ def main() -> int:
         out["batched_256"] = bench_batched(lib)
         log("learned + batched on 1024 instances at 256^2")
         out["learned_1024"] = bench_learned(lib)
+    if not args.no_batched:
+        log("EXPRB42 step on the 2048^2 Burgers workload")
+        out["exprb42_2048"] = bench_exprb42(lib)
     if not args.no_paper:
         log("paper-shaped problems I and II at 8192^2")
         out["paper_problems_8192"] = bench_paper_problems(lib, axpby_gbs=extra.get("practical_axpby_gbs"),
