@@ -23,7 +23,7 @@ namespace {
 using namespace dev;
 
 constexpr int kCoefThreads = 64;
-constexpr int kMaxCoef = 1002;   // coefficients per instance: max_iters + 2 (two-iteration launches)
+constexpr int kMaxCoef = 1008;   // coefficients per instance: up to max_iters + 1 + the window depth
 
 struct Who {
     int i;   // instance

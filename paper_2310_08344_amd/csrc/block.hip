@@ -382,15 +382,19 @@ __device__ __forceinline__ SweepState block_decide(const SweepArgs& a, const Loo
     return nx;
 }
 
+// One launch L of the window loop as workgroup `wg` of the a.nb that serve
+// this grid: the decision, then the window, its re-execution or nothing.
+// Workgroup 0 records the state; when the loop has ended it publishes
+// slot[2] and, if `done` is given, counts the grid as finished.  `banded`
+// selects the XCD-banded tile order (whole-device grids), else each
+// workgroup takes a contiguous run of tiles (a batch instance).
 template <int OP, int K, int TH, int D>
-__global__ __launch_bounds__(kBlockThreads) void leja_block(SweepArgs a, const int L) {
+__device__ __forceinline__ void block_launch(const SweepArgs& a, const int L, const int wg, const bool banded,
+                                             BlockLds<OP, TH, D>& S, unsigned* done) {
     LoopCtl* __restrict__ ctl = a.ctl;
-    if (loop_ended(ctl)) return;
     constexpr int NV = D * (1 + K);
-    __shared__ BlockLds<OP, TH, D> S;
     __shared__ SweepState s_cur;
     const int tid = flat_tid();
-    const int wg = static_cast<int>(blockIdx.x);
     if (L == 0) {
         if (tid == 0) {
             SweepState st = ctl->slot[0];
@@ -429,7 +433,10 @@ __global__ __launch_bounds__(kBlockThreads) void leja_block(SweepArgs a, const i
             s_cur = st;
             if (wg == 0) {
                 ctl->slot[L & 1] = st;
-                if (st.done) ctl->slot[2] = st;   // this launch does no work
+                if (st.done) {
+                    ctl->slot[2] = st;   // this launch does no work
+                    if (done != nullptr) atomicAdd(done, 1u);
+                }
             }
         }
     }
@@ -464,17 +471,22 @@ __global__ __launch_bounds__(kBlockThreads) void leja_block(SweepArgs a, const i
     }
     const int T = a.tiles_x * a.tiles_y;
     const TileArgs<K> ta = tile_args<OP, K>(a);
-    // this workgroup's tiles: a band of its XCD, as in the two-iteration kernel
+    // this workgroup's tiles: a band of its XCD, as in the two-iteration
+    // kernel, or a contiguous run (batch instances)
     int first, step, end;
-    if (a.nb >= 8 && (a.nb & 7) == 0) {
+    if (banded && a.nb >= 8 && (a.nb & 7) == 0) {
         const int x = wg & 7, nbx = a.nb >> 3;
         first = static_cast<int>((static_cast<long>(x) * T) >> 3) + (wg >> 3);
         step = nbx;
         end = static_cast<int>((static_cast<long>(x + 1) * T) >> 3);
-    } else {
+    } else if (banded) {
         first = wg;
         step = a.nb;
         end = T;
+    } else {
+        first = static_cast<int>((static_cast<long>(wg) * T) / a.nb);
+        step = 1;
+        end = static_cast<int>((static_cast<long>(wg + 1) * T) / a.nb);
     }
     BlockY<TH, D, radius<OP>()> ty;
     if (first < end) ty = load_block_y<K, TH, D, radius<OP>()>(ta, yin, first);
@@ -494,6 +506,73 @@ __global__ __launch_bounds__(kBlockThreads) void leja_block(SweepArgs a, const i
         double* __restrict__ Pp = a.partials + static_cast<long>(L & 1) * a.nb * NV + static_cast<long>(wg) * NV;
 #pragma unroll
         for (int q = 0; q < NV; ++q) Pp[q] = v[q];
+    }
+}
+
+template <int OP, int K, int TH, int D>
+__global__ __launch_bounds__(kBlockThreads) void leja_block(SweepArgs a, const int L) {
+    if (loop_ended(a.ctl)) return;
+    __shared__ BlockLds<OP, TH, D> S;
+    block_launch<OP, K, TH, D>(a, L, static_cast<int>(blockIdx.x), true, S, nullptr);
+}
+
+// Batched windows: every workgroup serves the instance block_inst[blockIdx.x],
+// one output per instance; LDS is sized by the launch for the largest
+// layout in the batch (the Burgers one when the batch holds one).
+template <int TH, int D>
+__global__ __launch_bounds__(kBlockThreads) void batch_block_kernel(const BatchInst* insts, LoopCtl* ctls,
+                                                                    const int* block_inst, double* partials,
+                                                                    const double* coef, const int ld,
+                                                                    const double* xi, unsigned* done, const int L) {
+    extern __shared__ double lds_dyn[];
+    // the instance's arguments live in LDS (a per-lane copy would be indexed
+    // dynamically and spill to scratch)
+    __shared__ SweepArgs a;
+    const int i = block_inst[blockIdx.x];
+    const BatchInst& I = insts[i];
+    LoopCtl* __restrict__ ctl = ctls + i;
+    if (loop_ended(ctl)) return;
+    if (flat_tid() == 0) {
+        a = SweepArgs{};
+        a.nx = I.nx;
+        a.ny = I.ny;
+        a.tiles_x = I.tiles_x;
+        a.tiles_y = I.tiles_y;
+        a.nb = I.nb;
+        a.ld = ld;
+        if (I.kind == kOpDiffAdv) {
+            a.aE = I.st[0];
+            a.aW = I.st[1];
+            a.aN = I.st[2];
+            a.aS = I.st[3];
+            a.aC = I.st[4];
+        } else {
+            a.kx = I.st[0];
+            a.ky = I.st[1];
+            a.gx = I.st[2];
+            a.gy = I.st[3];
+            a.kC = I.st[4];
+        }
+        a.inv_sqrtN = 1.0 / sqrt(static_cast<double>(I.nx) * I.ny);
+        a.v = I.v;
+        a.ybuf[0] = I.y[0];
+        a.ybuf[1] = I.y[1];
+        a.u = I.u;
+        a.p[0] = I.out;
+        a.p2[0] = I.out2;
+        a.coef = coef + static_cast<long>(i) * ld;
+        a.xi = xi;
+        a.partials = partials + I.part_off;
+        a.ctl = ctl;
+    }
+    __syncthreads();
+    const int wg = static_cast<int>(blockIdx.x) - I.wg_begin;
+    if (I.kind == kOpDiffAdv) {
+        block_launch<kOpDiffAdv, 1, TH, D>(a, L, wg, false, *reinterpret_cast<BlockLds<kOpDiffAdv, TH, D>*>(lds_dyn),
+                                           done);
+    } else {
+        block_launch<kOpBurgersJ, 1, TH, D>(a, L, wg, false,
+                                            *reinterpret_cast<BlockLds<kOpBurgersJ, TH, D>*>(lds_dyn), done);
     }
 }
 
@@ -724,6 +803,31 @@ hipError_t launch_power_block(int op, const PowerArgs& a, const double* in, doub
 
 hipError_t launch_power_block_final(const PowerArgs& a, int b, int nlev, hipStream_t s) {
     hipLaunchKernelGGL((power_block_final<kPowerBlockDepth>), dim3(1), dim3(kBlockThreads), 0, s, a, b, nlev);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_block(const BatchInst* insts, LoopCtl* ctls, const int* block_inst, int nblocks, bool burgers,
+                              int th, double* partials, const double* coef, int ld, const double* xi, unsigned* done,
+                              int L, hipStream_t s) {
+    constexpr int D = kBatchBlockDepth;
+    if (nblocks < 1) return hipErrorInvalidValue;
+    const dim3 block(64, kPairWaves), grid(nblocks);
+    switch (th) {
+        case 8: {
+            const size_t lds = burgers ? sizeof(BlockLds<kOpBurgersJ, 8, D>) : sizeof(BlockLds<kOpDiffAdv, 8, D>);
+            hipLaunchKernelGGL((batch_block_kernel<8, D>), grid, block, lds, s, insts, ctls, block_inst, partials, coef,
+                               ld, xi, done, L);
+            break;
+        }
+        case 16: {
+            if (burgers) return hipErrorInvalidValue;   // 78 KB: batches with Burgers take 8-row tiles
+            const size_t lds = sizeof(BlockLds<kOpDiffAdv, 16, D>);
+            hipLaunchKernelGGL((batch_block_kernel<16, D>), grid, block, lds, s, insts, ctls, block_inst, partials,
+                               coef, ld, xi, done, L);
+            break;
+        }
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

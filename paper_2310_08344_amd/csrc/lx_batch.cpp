@@ -107,18 +107,26 @@ extern "C" lx_status lx_phi_leja_batched(lx_ctx* ctx, int n, const lx_instance* 
         return lx_internal_fail(ctx, LX_EINVAL, "max_iters %d outside 1..%d", opt.max_iters, LX_MAX_ITERS);
 
     // ---- layout ----
-    // two iterations per launch when every instance allows 16-byte pairs
+    // two iterations per launch when every instance allows 16-byte pairs;
+    // windows of kBatchBlockDepth when, moreover, every side reaches the
+    // window's halo and lx_set_depth does not ask for one or two
+    constexpr int BD = lx::kBatchBlockDepth;
     bool pair = ctx->depth_forced != 1;
+    bool blk = ctx->depth_forced != 1 && ctx->depth_forced != 2;
     bool any_burgers = false;
     for (int i = 0; i < n; ++i) {
         const lx_instance& q = inst[i];
         any_burgers = any_burgers || q.op.kind == LX_OP_BURGERS2D;
         pair = pair && q.op.nx % 2 == 0 && aligned16(q.d_v) && aligned16(q.d_out) &&
                (q.d_u == nullptr || aligned16(q.d_u)) && (q.d_x0 == nullptr || aligned16(q.d_x0));
+        blk = blk && q.op.nx >= BD && q.op.ny >= BD;
     }
+    blk = blk && pair;
+    if (blk) pair = false;
     // tile rows: 16 (40 KB of LDS, 4 workgroups per CU) unless the Burgers
     // state needs room too, then 8 (36 KB)
-    const int th = (ctx->pair_th == 8 || ctx->pair_th == 16) ? ctx->pair_th : (any_burgers ? 8 : 16);
+    int th = (ctx->pair_th == 8 || ctx->pair_th == 16) ? ctx->pair_th : (any_burgers ? 8 : 16);
+    if (blk && any_burgers) th = 8;   // the Burgers window layout takes 8-row tiles in a batch
     std::vector<BatchInst> hi(static_cast<size_t>(n));
     std::vector<int> budget(static_cast<size_t>(n));
     int total_blocks = 0, max_budget = 1;
@@ -151,7 +159,7 @@ extern "C" lx_status lx_phi_leja_batched(lx_ctx* ctx, int n, const lx_instance* 
         b.vec = (al && b.nx % 2 == 0) ? 2 : 1;
         b.l = q.l;
         long tile_points;
-        if (pair) {
+        if (pair || blk) {
             b.tiles_x = (b.nx + 127) / 128;
             b.tiles_y = (b.ny + th - 1) / th;
             tile_points = 128L * th;
@@ -168,7 +176,7 @@ extern "C" lx_status lx_phi_leja_batched(lx_ctx* ctx, int n, const lx_instance* 
         b.wg_begin = total_blocks;
         total_blocks += b.nb;
         b.part_off = part_total;
-        part_total += (pair ? 8L : 4L) * b.nb;   // [2][nb][NV] partial sums
+        part_total += (blk ? 4L * BD : (pair ? 8L : 4L)) * b.nb;   // [2][nb][NV] partial sums
         b.has_x0 = q.d_x0 != nullptr;
         b.dx = q.op.dx;
         b.dy = q.op.dy;
@@ -186,12 +194,12 @@ extern "C" lx_status lx_phi_leja_batched(lx_ctx* ctx, int n, const lx_instance* 
         b.v = q.d_v;
         b.out = q.d_out;
         b.x0 = q.d_x0;
-        basis_total += 2 * static_cast<size_t>(b.nx) * b.ny;
+        basis_total += (blk ? 3 : 2) * static_cast<size_t>(b.nx) * b.ny;   // windows: a second output buffer
         budget[static_cast<size_t>(i)] = q.budget > 0 ? q.budget : opt.max_iters;
         max_budget = std::max(max_budget, budget[static_cast<size_t>(i)]);
     }
     if (total_blocks > (1 << 30)) return lx_internal_fail(ctx, LX_EINVAL, "batch too large");
-    const int ld = max_budget + (pair ? 2 : 1);   // Newton coefficients per instance
+    const int ld = max_budget + (blk ? BD + 1 : (pair ? 2 : 1));   // Newton coefficients per instance
 
     // ---- workspaces ----
     lx_batch_ws& W = ctx->batch;
@@ -222,6 +230,11 @@ extern "C" lx_status lx_phi_leja_batched(lx_ctx* ctx, int n, const lx_instance* 
         b.y[0] = W.d_basis + boff;
         b.y[1] = W.d_basis + boff + N;
         boff += 2 * N;
+        b.out2 = nullptr;
+        if (blk) {
+            b.out2 = W.d_basis + boff;
+            boff += N;
+        }
         h_inst[i] = b;
         for (int k = 0; k < b.nb; ++k) W.h_block_inst[b.wg_begin + k] = i;
         LoopCtl& c = h_ctl[i];
@@ -260,15 +273,21 @@ extern "C" lx_status lx_phi_leja_batched(lx_ctx* ctx, int n, const lx_instance* 
     LXB_HIP(ctx, lx::launch_batch_coeffs(d_inst, n, ctx->xi, W.d_coef, ld, st));
     if (timing) LXB_HIP(ctx, hipEventRecord(ctx->tev[1], st));
 
-    // ---- batched sweeps (one or two iterations per launch) ----
-    const int last = pair ? (max_budget + 1) / 2 + 1 : max_budget;   // last launch index
-    const int per = pair ? 2 : 1;
+    // ---- batched sweeps (one or two iterations, or a window, per launch) ----
+    // windows: at most ceil(budget / depth) windows, one re-execution (one
+    // output) and one publishing launch per instance
+    const int last = blk ? (max_budget + BD - 1) / BD + 2 : (pair ? (max_budget + 1) / 2 + 1 : max_budget);
+    const int per = blk ? BD : (pair ? 2 : 1);
     int launched = 0, chunk_id = 0, last_slot = 0;
-    int chunk = kFirstChunk / per;
+    const int first_chunk = std::max(3, kFirstChunk / per), next_chunk = std::max(2, kChunk / per);
+    int chunk = first_chunk;
     while (launched <= last) {
         const int cnt = std::min(chunk, last + 1 - launched);
         for (int i = 0; i < cnt; ++i) {
-            if (pair) {
+            if (blk) {
+                LXB_HIP(ctx, lx::launch_batch_block(d_inst, d_ctl, W.d_block_inst, total_blocks, any_burgers, th,
+                                                    W.d_partials, W.d_coef, ld, ctx->xi, W.d_done, launched + i, st));
+            } else if (pair) {
                 LXB_HIP(ctx, lx::launch_batch_pair(d_inst, d_ctl, W.d_block_inst, total_blocks, any_burgers, th,
                                                    W.d_partials, W.d_coef, ld, ctx->xi, W.d_done, launched + i, st));
             } else {
@@ -287,7 +306,7 @@ extern "C" lx_status lx_phi_leja_batched(lx_ctx* ctx, int n, const lx_instance* 
             if (W.h_done[prev] >= static_cast<unsigned>(n)) break;
         }
         ++chunk_id;
-        chunk = kChunk / per;
+        chunk = next_chunk;
     }
     if (timing) LXB_HIP(ctx, hipEventRecord(ctx->tev[2], st));
     LXB_HIP(ctx, hipEventSynchronize(ctx->poll_ev[last_slot]));
@@ -316,7 +335,11 @@ extern "C" lx_status lx_phi_leja_batched(lx_ctx* ctx, int n, const lx_instance* 
         else if (r.status == LX_ENOTCONV && worst == LX_OK) worst = LX_ENOTCONV;
         const double N = static_cast<double>(b.nx) * b.ny;
         const double ub = b.kind == lx::kOpBurgersJ ? 8.0 : 0.0;
-        if (pair) {
+        if (blk) {
+            // counted on the device by the launches that did work
+            bytes += N * f.bytes_pp;
+            max_iter = std::max(max_iter, f.n_levels);
+        } else if (pair) {
             // launches 0..F-1 ran both sweeps (launch 0 writes p without
             // reading it), an even final test added a flush of the deferred term
             const int F = (f.iter + 1) / 2;

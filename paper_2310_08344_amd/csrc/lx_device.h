@@ -122,6 +122,7 @@ struct BatchInst {
     const double* u;
     const double* v;
     double* out;
+    double* out2;            // second output buffer (windows), else NULL
     const double* x0;
     double* y[2];            // basis (and power iteration) buffers
 };
@@ -197,6 +198,13 @@ hipError_t launch_batch_coeffs(const BatchInst* insts, int n_inst, const double*
 hipError_t launch_batch_pair(const BatchInst* insts, LoopCtl* ctls, const int* block_inst, int nblocks, bool burgers,
                              int th, double* partials, const double* coef, int ld, const double* xi, unsigned* done,
                              int L, hipStream_t s);
+// Batched windows of kBatchBlockDepth iterations (block.hip; one output per
+// instance, nx even and sides >= depth, 16-byte aligned vectors, out2 set);
+// th 8 or 16 (8 when the batch holds a Burgers instance).
+constexpr int kBatchBlockDepth = 4;
+hipError_t launch_batch_block(const BatchInst* insts, LoopCtl* ctls, const int* block_inst, int nblocks, bool burgers,
+                              int th, double* partials, const double* coef, int ld, const double* xi, unsigned* done,
+                              int L, hipStream_t s);
 hipError_t launch_batch_sweep(const BatchInst* insts, LoopCtl* ctls, const int* block_inst, int nblocks,
                               double* partials, const double* coef, int ld, const double* xi, unsigned* done,
                               int m, hipStream_t s);

@@ -154,16 +154,17 @@ def test_batch_equals_single_instance_path(ctx):
         assert rel(o, host(out)) <= 1e-12
 
 
-@pytest.mark.parametrize("th", [8, 16])
-def test_two_iteration_batch_matches_oracle(ctx, th):
+@pytest.mark.parametrize("depth,th", [(2, 8), (2, 16), (0, 8), (0, 16)])
+def test_two_iteration_batch_matches_oracle(ctx, depth, th):
     """Even sides (ragged against the 128-column tiles), both operators in
-    one launch, against the oracle instance by instance."""
+    one launch, against the oracle instance by instance; two iterations per
+    launch, and the default windows of four (8-row tiles with Burgers)."""
     inst = _mixed_batch(5, EVEN)
-    say("two-iteration batch", th)
-    ctx.set_depth(0, th, 0)
+    say("multi-iteration batch", depth, th)
+    ctx.set_depth(depth, th, 0)
     try:
         st, res, outs = _run(ctx, inst, rtol=1e-8, max_iters=200)
-        assert ctx.stats()["depth"] == 2
+        assert ctx.stats()["depth"] == (depth or 4)
     finally:
         ctx.set_depth(0)
     assert st == B.LX_OK
@@ -174,14 +175,23 @@ def test_two_iteration_batch_matches_oracle(ctx, th):
                                               1e-8, 0.0, 200, f), PARITY)
 
 
-def test_two_iteration_batch_budgets_and_power_iteration(ctx):
-    """Odd and even budgets end on either test of a launch; the batched
-    power iteration feeds the two-iteration loop."""
+@pytest.mark.parametrize("depth", [2, 0])
+def test_two_iteration_batch_budgets_and_power_iteration(ctx, depth):
+    """Budgets end at every position of a launch (two iterations) or window
+    (four, the default); the batched power iteration feeds the loop."""
+    ctx.set_depth(depth)
+    try:
+        _budgets_and_power(ctx, depth or 4)
+    finally:
+        ctx.set_depth(0)
+
+
+def _budgets_and_power(ctx, depth):
     inst = _mixed_batch(6, EVEN)[:6]
-    budgets = [3, 0, 2, 0, 1, 4]
-    say("two-iteration budgets")
+    budgets = [3, 0, 2, 0, 1, 4] if depth == 2 else [3, 5, 2, 7, 1, 4]
+    say("multi-iteration budgets", depth)
     st, res, outs = _run(ctx, inst, budgets=budgets, rtol=1e-10, max_iters=200)
-    assert ctx.stats()["depth"] == 2 and st == B.LX_ENOTCONV
+    assert ctx.stats()["depth"] == depth and st == B.LX_ENOTCONV
     for q, b, r, o in zip(inst, budgets, res, outs):
         if b == 0:
             assert r["status"] == B.LX_OK
@@ -191,7 +201,7 @@ def test_two_iteration_batch_budgets_and_power_iteration(ctx):
         assert rel(o, ref.p[0]) <= PARITY
     inst = _mixed_batch(7, EVEN)
     st, res, outs = _run(ctx, inst, power_iters=20, rtol=1e-8, max_iters=250)
-    assert ctx.stats()["depth"] == 2 and st == B.LX_OK
+    assert ctx.stats()["depth"] == depth and st == B.LX_OK
     for i, (q, r, o) in enumerate(zip(inst, res, outs)):
         x0 = splitmix_vector(i, q["nx"] * q["ny"]).reshape(q["ny"], q["nx"])
         rho_o, _ = power_iteration(q["A"], x0, 20)
@@ -202,9 +212,15 @@ def test_two_iteration_batch_budgets_and_power_iteration(ctx):
                                                         1e-8, 0.0, 250, f), PARITY)
 
 
-def test_two_iteration_batch_equals_one_iteration_batch(ctx):
+@pytest.mark.parametrize("depth", [2, 0])
+def test_two_iteration_batch_equals_one_iteration_batch(ctx, depth):
     inst = _mixed_batch(8, EVEN)
-    st2, res2, outs2 = _run(ctx, inst, rtol=1e-9, max_iters=200)
+    ctx.set_depth(depth)
+    try:
+        st2, res2, outs2 = _run(ctx, inst, rtol=1e-9, max_iters=200)
+        assert ctx.stats()["depth"] == (depth or 4)
+    finally:
+        ctx.set_depth(0)
     ctx.set_depth(1)
     try:
         st1, res1, outs1 = _run(ctx, inst, rtol=1e-9, max_iters=200)
