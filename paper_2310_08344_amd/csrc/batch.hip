@@ -117,13 +117,16 @@ __global__ __launch_bounds__(kBlockThreads) void batch_power_sweep_kernel(const 
     __syncthreads();
     double acc = 0.0;
     const int T = I.ptiles_x * I.ptiles_y;
+    // each thread marches down kBatchPowerRows rows, so a row of the input
+    // is loaded once per tile instead of three times
+    constexpr int RY = kBatchPowerRows;
     for_tile_band(T, I.nb, w.j, [&](int t) {
         if (I.kind == kOpDiffAdv) {
-            if (I.vec == 2) power_tile<kOpDiffAdv, 1, 2>(a, s, acc, t);
-            else power_tile<kOpDiffAdv, 1, 1>(a, s, acc, t);
+            if (I.vec == 2) power_tile<kOpDiffAdv, RY, 2>(a, s, acc, t);
+            else power_tile<kOpDiffAdv, RY, 1>(a, s, acc, t);
         } else {
-            if (I.vec == 2) power_tile<kOpBurgersJ, 1, 2>(a, s, acc, t);
-            else power_tile<kOpBurgersJ, 1, 1>(a, s, acc, t);
+            if (I.vec == 2) power_tile<kOpBurgersJ, RY, 2>(a, s, acc, t);
+            else power_tile<kOpBurgersJ, RY, 1>(a, s, acc, t);
         }
     });
     double v[1] = {acc};

@@ -169,7 +169,7 @@ extern "C" lx_status lx_phi_leja_batched(lx_ctx* ctx, int n, const lx_instance* 
             tile_points = static_cast<long>(lx::kBatchTx) * b.vec * lx::kBatchTy;
         }
         b.ptiles_x = (b.nx + lx::kBatchTx * b.vec - 1) / (lx::kBatchTx * b.vec);
-        b.ptiles_y = (b.ny + lx::kBatchTy - 1) / lx::kBatchTy;
+        b.ptiles_y = (b.ny + lx::kBatchTy * lx::kBatchPowerRows - 1) / (lx::kBatchTy * lx::kBatchPowerRows);
         const int T = b.tiles_x * b.tiles_y;
         const int tpw = static_cast<int>(std::max(1L, kPointsPerWorkgroup / tile_points));
         b.nb = std::min(std::max((T + tpw - 1) / tpw, 1), kMaxWorkgroupsPerInstance);

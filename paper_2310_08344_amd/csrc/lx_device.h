@@ -111,7 +111,7 @@ struct BatchInst {
     int vec;                 // columns per lane (2 when nx is even and rows are 16-byte aligned)
     int l;                   // phi order
     int tiles_x, tiles_y;    // tiles of the Leja kernel in use (one- or two-iteration layout)
-    int ptiles_x, ptiles_y;  // tiles of the power-iteration sweeps (kBatchTx * vec x kBatchTy)
+    int ptiles_x, ptiles_y;  // tiles of the power-iteration sweeps (kBatchTx * vec x kBatchTy * kBatchPowerRows)
     int wg_begin, nb;        // workgroups [wg_begin, wg_begin + nb) of each launch
     int has_x0;              // x0 given; else a splitmix64 vector in y[1]
     long part_off;           // offset of its partial sums: [2][nb][2]
@@ -128,6 +128,7 @@ struct BatchInst {
 };
 
 constexpr int kBatchTx = 32, kBatchTy = 8;   // workgroup shape of the batched sweeps
+constexpr int kBatchPowerRows = 4;           // rows each thread of a batched power sweep marches over
 
 // Kernel launchers (kernels.hip).  Each returns the hipError_t of the launch.
 // Sweep m of the Leja loop (m = max_iters only takes the last decision).
