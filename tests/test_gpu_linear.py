@@ -146,7 +146,8 @@ def test_up3_fp32_sweeps_within_tolerance(ctx):
 
 
 @pytest.mark.parametrize("source", [False, True])
-@pytest.mark.parametrize("n,cfl,depth", [(128, 10.0, 2), (128, 100.0, 2), (250, 10.0, 2), (250, 10.0, 1), (75, 1.0, 2)])
+@pytest.mark.parametrize("n,cfl,depth", [(128, 10.0, 2), (128, 100.0, 2), (250, 10.0, 2), (250, 10.0, 1), (75, 1.0, 2),
+                                         (128, 100.0, 4), (250, 10.0, 3)])
 def test_linear_step_matches_oracle(ctx, n, cfl, depth, source):
     """Problems I and II on [-1, 1)^2 (nu = 10, the paper's initial data and
     source), tolerance 1e-12: the step against the oracle's step, with the

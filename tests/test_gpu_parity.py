@@ -201,7 +201,7 @@ STEPS = {"ros_euler": (B.LX_ROS_EULER, ros_euler_step), "exprb32": (B.LX_EXPRB32
          "exprb42": (B.LX_EXPRB42, exprb42_step)}
 
 
-@pytest.mark.parametrize("depth", [2, 1])
+@pytest.mark.parametrize("depth", [4, 2, 1])
 @pytest.mark.parametrize("scheme", sorted(STEPS))
 @pytest.mark.parametrize("n", [128, 250])
 def test_integrator_steps_match_oracle(ctx, scheme, n, depth):

@@ -44,7 +44,7 @@ def ctx4(lx):
     c.close()
 
 
-@pytest.mark.parametrize("depth", [2, 1])
+@pytest.mark.parametrize("depth", [4, 3, 2, 1])
 @pytest.mark.parametrize("substeps", [8, 0])
 def test_substeps_match_oracle_and_exact(ctx4, depth, substeps):
     n = 64
