@@ -1,4 +1,4 @@
-// D Leja iterations per launch (D = 3 or 4) on LDS-resident tiles (gfx950),
+// D Leja iterations per launch (D = 3, 4 or 6) on LDS-resident tiles (gfx950),
 // FP64, with speculative windows.
 //
 // Launch w of the plain loop advances the Newton recurrence (Sec. 2.1,
@@ -114,8 +114,40 @@ __device__ __forceinline__ BlockY<TH, D, R> load_block_y(const TileArgs<K>& a, c
     return r;
 }
 
+// v of lane l - 1 (kFromBelow: DPP wave_shr:1) or of lane l + 1 (wave_shl:1);
+// the lane with no such neighbour keeps `old`.  Every lane of the wavefront
+// must be active.
+template <bool kFromBelow>
+__device__ __forceinline__ double lane_neighbour(const double v, const double old) {
+    constexpr int ctrl = kFromBelow ? 0x138 : 0x130;
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), ctrl, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), ctrl, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Row `ce` around the column pair j, j+1 of this lane, where the 64 lanes of
+// the wavefront hold the pairs of 128 consecutive columns (j = j_0 + 2 lane):
+// c = {ce[j], ce[j+1]}, l = {ce[j-2], ce[j-1]}, r = {ce[j+2], ce[j+3]}.  The
+// side columns come from the neighbouring lanes' pairs; only lanes 0 and 63
+// read theirs, the halo beyond the wavefront's columns, from LDS.
+__device__ __forceinline__ void row_pair(const double* ce, const int j, double2& c, double2& l, double2& r) {
+    const int lane = flat_tid() & 63;
+    c = *reinterpret_cast<const double2*>(ce + j);
+    double2 e = double2{0.0, 0.0};
+    if (lane == 0 || lane == 63) e = *reinterpret_cast<const double2*>(ce + (lane == 0 ? j - 2 : j + 2));
+    l.x = lane_neighbour<true>(c.x, e.x);
+    l.y = lane_neighbour<true>(c.y, e.y);
+    r.x = lane_neighbour<false>(c.x, e.x);
+    r.y = lane_neighbour<false>(c.y, e.y);
+}
+
 // the shifted operator at the column pair j, j+1 of LDS row r of `src`
-// (u: the Burgers state laid out as src, else NULL)
+// (u: the Burgers state laid out as src, else NULL).  The five-point
+// diffusion-advection operator takes a wavefront's row of 128 columns at once
+// (row_pair): every lane of the wavefront calls this with j = j_0 + 2 lane;
+// the stencil and its operand order are those of shifted_pair.  (The
+// radius-2 operator reads its four side columns from LDS: exchanging them
+// between lanes measured slower.)
 template <int OP, int P>
 __device__ __forceinline__ void level_pair(const Sten& st, const double shift, const double (*src)[P], const int r,
                                            const int j, double (&o)[2], const double (*u)[P] = nullptr) {
@@ -124,7 +156,12 @@ __device__ __forceinline__ void level_pair(const Sten& st, const double shift, c
     } else if constexpr (OP == kOpBurgersJ) {
         shifted_pair<OP>(st, shift, src[r - 1], src[r], src[r + 1], u[r - 1], u[r], u[r + 1], j, o);
     } else {
-        shifted_pair<OP>(st, shift, src[r - 1], src[r], src[r + 1], nullptr, nullptr, nullptr, j, o);
+        double2 c, l, rr;
+        row_pair(src[r], j, c, l, rr);
+        const double2 s = *reinterpret_cast<const double2*>(src[r - 1] + j);
+        const double2 n = *reinterpret_cast<const double2*>(src[r + 1] + j);
+        o[0] = shifted_at<OP>(st, shift, l.y, c.y, s.x, n.x, c.x, 0, 0, 0, 0);
+        o[1] = shifted_at<OP>(st, shift, c.x, rr.x, s.y, n.y, c.y, 0, 0, 0, 0);
     }
 }
 
