@@ -332,11 +332,15 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
             double* hc = ctx->h_coef + static_cast<size_t>(k) * NC;
             for (int j = have; j < upto; ++j) hc[j] = ctx->series[k].next();
         }
-        for (int k = 0; k < K; ++k) {
-            const size_t off = static_cast<size_t>(k) * NC + have;
-            LX_HIP(ctx, hipMemcpyAsync(ctx->coef + off, ctx->h_coef + off, sizeof(double) * (upto - have),
-                                       hipMemcpyHostToDevice, ctx->stream));
-        }
+        // one copy for all outputs (each copy is a launch on the stream): the
+        // span from d_have of output 0 to d_{upto-1} of output K-1 also
+        // carries the coefficients already on the device (the same values)
+        // and slots past upto that no launch reads before a later copy
+        // brings their final values
+        const size_t off = static_cast<size_t>(have);
+        const size_t len = static_cast<size_t>(K - 1) * NC + upto - have;
+        LX_HIP(ctx, hipMemcpyAsync(ctx->coef + off, ctx->h_coef + off, sizeof(double) * len, hipMemcpyHostToDevice,
+                                   ctx->stream));
         have = upto;
         plan_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - ta).count();
         return LX_OK;
@@ -415,8 +419,12 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
     int launched = 0, chunk_id = 0, last_slot = -1;
     // launches per chunk: about kFirstChunk and kChunk iterations, but at
     // least three and two launches, so that the queue never runs dry while
-    // the host looks at the state of the chunk before
-    const int first_chunk = std::max(3, kFirstChunk / per), next_chunk = std::max(2, kChunk / per);
+    // the host looks at the state of the chunk before.  A window is long
+    // enough on its own to hide the host's work on the next chunk's
+    // coefficients, so windows start with one launch: the GPU waits only for
+    // d_0..d_D, not for the first three windows' coefficients (the first
+    // look still comes after three launches).
+    const int first_chunk = blk ? 1 : std::max(3, kFirstChunk / per), next_chunk = std::max(2, kChunk / per);
     int chunk = first_chunk;
     while (launched <= last) {
         const int n = std::min(chunk, last + 1 - launched);
