@@ -821,6 +821,20 @@ hipError_t launch_block_k(int K, int th, const SweepArgs& a, int L, hipStream_t 
 
 int power_block_rows(int op) { return op == kOpDiffAdv3 ? 8 : 16; }
 
+int power_block_resident(int op) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    const hipError_t e =
+        op == kOpDiffAdv3
+            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                  &per_cu, reinterpret_cast<const void*>(power_block<kOpDiffAdv3, 8, kPowerBlockDepth>), kBlockThreads, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                  &per_cu, reinterpret_cast<const void*>(power_block<kOpDiffAdv, 16, kPowerBlockDepth>), kBlockThreads, 0);
+    return e == hipSuccess ? per_cu * cus : 0;
+}
+
 hipError_t launch_power_block(int op, const PowerArgs& a, const double* in, double* out, int b, int nlev,
                               hipStream_t s) {
     constexpr int D = kPowerBlockDepth;

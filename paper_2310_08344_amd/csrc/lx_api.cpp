@@ -888,7 +888,11 @@ lx_status lx_spectrum(lx_ctx* ctx, const lx_operator* op, const double* d_u, con
         a.ny = ny;
         a.tiles_x = (nx + 127) / 128;
         a.tiles_y = (ny + prow - 1) / prow;
-        a.nb = pair_grid(1024, a.tiles_x * a.tiles_y);
+        // one resident round of workgroups: a grid larger than what fits at
+        // once leaves a partial second round (1024 workgroups of 52 KB of LDS
+        // on 256 CUs that hold three each)
+        const int resident = lx::power_block_resident(pcode);
+        a.nb = pair_grid(resident > 0 ? resident : 1024, a.tiles_x * a.tiles_y);
         double pk[9];
         diffadv_stencil9(*op, 0.0, 1.0, pk);
         a.cE = pk[0];

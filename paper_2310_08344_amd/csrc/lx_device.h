@@ -157,6 +157,9 @@ hipError_t launch_power_final(int nb, const double* partials, LoopCtl* ctl, hipS
 constexpr int kPowerBlockDepth = 4;
 // op: kOpDiffAdv (tiles of 128 x 16) or kOpDiffAdv3 (128 x 8, power_block_rows)
 int power_block_rows(int op);
+// workgroups of power_block that are resident at once on the current device
+// (0 if the runtime cannot tell)
+int power_block_resident(int op);
 hipError_t launch_power_block(int op, const PowerArgs& a, const double* in, double* out, int b, int nlev,
                               hipStream_t s);
 hipError_t launch_power_block_final(const PowerArgs& a, int b, int nlev, hipStream_t s);
