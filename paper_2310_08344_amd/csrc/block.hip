@@ -637,6 +637,19 @@ __device__ __forceinline__ void power_block_tile(const TileArgs<1>& ta, const St
     const int tid = flat_tid(), lane = tid & 63, w = tid >> 6;
     const int j0 = CO + 2 * lane;
     const int gcol = x0 + 2 * lane;
+    // the Burgers state on the level-0 cells (the same every launch: L2)
+    if constexpr (L::kHasU) {
+        const double* __restrict__ uu = ta.u;
+        const int gc = wrap(gcol, nx);
+        for (int r = w; r < ROWS; r += kPairWaves)
+            *reinterpret_cast<double2*>(&S.u[r][j0]) =
+                *reinterpret_cast<const double2*>(uu + wrap(y0 - H + r, ny) * static_cast<long>(nx) + gc);
+        for (int e = tid; e < Y::E; e += kBlockThreads) {
+            const int row = e / (2 * H), qq = e % (2 * H);
+            const int tc = (qq < H) ? qq - H : kPairTW + (qq - H);
+            S.u[row][CO + tc] = uu[wrap(y0 - H + row, ny) * static_cast<long>(nx) + wrap(x0 + tc, nx)];
+        }
+    }
 #pragma unroll
     for (int i = 0; i < Y::RM; ++i) {
         const int r = w + i * kPairWaves;
@@ -669,7 +682,7 @@ __device__ __forceinline__ void power_block_tile(const TileArgs<1>& ta, const St
             const int r = r_lo + w + i * kPairWaves;
             if (r < r_hi) {
                 double o[2];
-                level_pair<OP, P>(st, 0.0, src, r, j0, o);
+                level_pair<OP, P>(st, 0.0, src, r, j0, o, S.uu());
                 double2 t;
                 t.x = o[0];
                 t.y = o[1];
@@ -681,7 +694,7 @@ __device__ __forceinline__ void power_block_tile(const TileArgs<1>& ta, const St
         for (int e = tid; e < ne; e += kBlockThreads) {
             const int r = r_lo + e / (2 * side), qq = e % (2 * side);
             const int tc = (qq < side) ? qq - side : kPairTW + (qq - side);
-            dst[r][CO + tc] = level_one<OP, P>(st, 0.0, src, r, CO + tc);
+            dst[r][CO + tc] = level_one<OP, P>(st, 0.0, src, r, CO + tc, S.uu());
         }
         __syncthreads();
 #pragma unroll
@@ -699,7 +712,7 @@ __device__ __forceinline__ void power_block_tile(const TileArgs<1>& ta, const St
         for (int i = 0; i < RW; ++i) {
             const int grow = y0 + w + i * kPairWaves;
             double o[2];
-            level_pair<OP, P>(st, 0.0, src, H + w + i * kPairWaves, j0, o);
+            level_pair<OP, P>(st, 0.0, src, H + w + i * kPairWaves, j0, o, S.uu());
             if (gcol < nx && grow < ny) {
                 double2 t;
                 t.x = o[0];
@@ -737,7 +750,11 @@ __global__ __launch_bounds__(kBlockThreads) void power_block(PowerArgs a, const 
     ta.nx = a.nx;
     ta.ny = a.ny;
     ta.tiles_x = a.tiles_x;
-    const Sten st{a.cW, a.cE, a.cS, a.cN, a.cC, a.cW2, a.cE2, a.cS2, a.cN2};
+    ta.u = a.u;
+    // the plain operator (no shift): the Burgers centre as the one-sweep
+    // power iteration forms it
+    const Sten st = OP == kOpBurgersJ ? Sten{a.kx, a.ky, a.gx, a.gy, -2.0 * a.kx - 2.0 * a.ky, 0.0, 0.0, 0.0, 0.0}
+                                      : Sten{a.cW, a.cE, a.cS, a.cN, a.cC, a.cW2, a.cE2, a.cS2, a.cN2};
     double sy[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) sy[j] = 0.0;
@@ -819,34 +836,36 @@ hipError_t launch_block_k(int K, int th, const SweepArgs& a, int L, hipStream_t 
 
 }  // namespace
 
-int power_block_rows(int op) { return op == kOpDiffAdv3 ? 8 : 16; }
+int power_block_rows(int op) { return op == kOpDiffAdv ? 16 : 8; }
 
 int power_block_resident(int op) {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
-    const hipError_t e =
-        op == kOpDiffAdv3
-            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                  &per_cu, reinterpret_cast<const void*>(power_block<kOpDiffAdv3, 8, kPowerBlockDepth>), kBlockThreads, 0)
-            : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                  &per_cu, reinterpret_cast<const void*>(power_block<kOpDiffAdv, 16, kPowerBlockDepth>), kBlockThreads, 0);
+    const void* k = op == kOpDiffAdv3   ? reinterpret_cast<const void*>(power_block<kOpDiffAdv3, 8, kPowerBlockDepth>)
+                    : op == kOpBurgersJ ? reinterpret_cast<const void*>(power_block<kOpBurgersJ, 8, kPowerBlockDepth>)
+                                        : reinterpret_cast<const void*>(power_block<kOpDiffAdv, 16, kPowerBlockDepth>);
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kBlockThreads, 0);
     return e == hipSuccess ? per_cu * cus : 0;
 }
 
 hipError_t launch_power_block(int op, const PowerArgs& a, const double* in, double* out, int b, int nlev,
                               hipStream_t s) {
     constexpr int D = kPowerBlockDepth;
-    if (op != kOpDiffAdv && op != kOpDiffAdv3) return hipErrorInvalidValue;
+    if (op != kOpDiffAdv && op != kOpDiffAdv3 && op != kOpBurgersJ) return hipErrorInvalidValue;
+    if (op == kOpBurgersJ && a.u == nullptr) return hipErrorInvalidValue;
     const int TH = power_block_rows(op), H = D * (op == kOpDiffAdv3 ? 2 : 1);
     if (a.nb < 1 || a.nx % 2 != 0 || a.nx < H || a.ny < H || nlev < 1 || nlev > D) return hipErrorInvalidValue;
     if (a.tiles_x != (a.nx + kPairTW - 1) / kPairTW || a.tiles_y != (a.ny + TH - 1) / TH) return hipErrorInvalidValue;
     if (op == kOpDiffAdv) {
         hipLaunchKernelGGL((power_block<kOpDiffAdv, 16, D>), dim3(a.nb), dim3(64, kPairWaves), 0, s, a, in, out, b,
                            nlev);
-    } else {
+    } else if (op == kOpDiffAdv3) {
         hipLaunchKernelGGL((power_block<kOpDiffAdv3, 8, D>), dim3(a.nb), dim3(64, kPairWaves), 0, s, a, in, out, b,
+                           nlev);
+    } else {
+        hipLaunchKernelGGL((power_block<kOpBurgersJ, 8, D>), dim3(a.nb), dim3(64, kPairWaves), 0, s, a, in, out, b,
                            nlev);
     }
     return hipGetLastError();

@@ -875,13 +875,13 @@ lx_status lx_spectrum(lx_ctx* ctx, const lx_operator* op, const double* d_u, con
         x0 = ctx->ybuf[1];
     }
     const bool vec2 = aligned16(x0) && (d_u == nullptr || aligned16(d_u));
-    // the diffusion-advection operators take kPowerBlockDepth sweeps per
-    // launch on LDS tiles (the basis read and written once per launch); the
-    // Burgers Jacobian one sweep per launch
+    // kPowerBlockDepth sweeps per launch on LDS tiles (the basis read and
+    // written once per launch, the Burgers state once per launch); odd or
+    // narrow grids and unaligned vectors one sweep per launch
     constexpr int PD = lx::kPowerBlockDepth;
     const int pcode = opcode_of(op->kind);
     const int ph = PD * (op->kind == LX_OP_DIFFADV2D_UP3 ? 2 : 1);   // halo of a power launch
-    if (is_diffadv(op->kind) && vec2 && nx % 2 == 0 && nx >= ph && ny >= ph) {
+    if (vec2 && nx % 2 == 0 && nx >= ph && ny >= ph) {
         const int prow = lx::power_block_rows(pcode);
         PowerArgs a{};
         a.nx = nx;
@@ -893,17 +893,27 @@ lx_status lx_spectrum(lx_ctx* ctx, const lx_operator* op, const double* d_u, con
         // on 256 CUs that hold three each)
         const int resident = lx::power_block_resident(pcode);
         a.nb = pair_grid(resident > 0 ? resident : 1024, a.tiles_x * a.tiles_y);
-        double pk[9];
-        diffadv_stencil9(*op, 0.0, 1.0, pk);
-        a.cE = pk[0];
-        a.cW = pk[1];
-        a.cN = pk[2];
-        a.cS = pk[3];
-        a.cC = pk[4];
-        a.cE2 = pk[5];
-        a.cW2 = pk[6];
-        a.cN2 = pk[7];
-        a.cS2 = pk[8];
+        if (is_diffadv(op->kind)) {
+            double pk[9];
+            diffadv_stencil9(*op, 0.0, 1.0, pk);
+            a.cE = pk[0];
+            a.cW = pk[1];
+            a.cN = pk[2];
+            a.cS = pk[3];
+            a.cC = pk[4];
+            a.cE2 = pk[5];
+            a.cW2 = pk[6];
+            a.cN2 = pk[7];
+            a.cS2 = pk[8];
+        } else {
+            double pk[5];
+            lx::stencil_coeffs(1, op->dx, op->dy, op->D, op->vx, op->vy, op->nu, 0.0, 1.0, pk);
+            a.kx = pk[0];
+            a.ky = pk[1];
+            a.gx = pk[2];
+            a.gy = pk[3];
+            a.u = d_u;
+        }
         s = ensure_partials(ctx, 2 * static_cast<size_t>(a.nb) * (1 + PD));
         if (s != LX_OK) return s;
         a.partials = ctx->partials;
@@ -931,7 +941,7 @@ lx_status lx_spectrum(lx_ctx* ctx, const lx_operator* op, const double* d_u, con
         S.n_launch = nblk;
         S.depth = PD;
         S.rho_hat = rho;
-        S.bytes = 16.0 * static_cast<double>(N) * nblk;
+        S.bytes = (op->kind == LX_OP_BURGERS2D ? 24.0 : 16.0) * static_cast<double>(N) * nblk;   // + u per launch
         if (ctx->timing) {
             S.loop_ms = elapsed(ctx->tev[0], ctx->tev[nblk]);
             S.sweep_ms = S.loop_ms;
@@ -999,6 +1009,8 @@ lx_status lx_spectrum(lx_ctx* ctx, const lx_operator* op, const double* d_u, con
     const double rho = ctx->h_ctl->rho;
     lx_stats& S = ctx->stats;
     S.n_apply = iters;
+    S.n_launch = iters;
+    S.depth = 1;
     S.rho_hat = rho;
     S.bytes = (16.0 + (op->kind == LX_OP_BURGERS2D ? 8.0 : 0.0)) * static_cast<double>(N) * iters;
     if (ctx->timing) {

@@ -233,6 +233,28 @@ def test_blocked_power_iteration_matches_oracle(ctx, nx, ny, iters):
     assert abs(rho - rho_o) <= 1e-12 * rho_o
 
 
+@pytest.mark.parametrize("nx,ny,iters", [(128, 128, 20), (200, 136, 7), (64, 40, 5), (6, 5, 3), (130, 20, 1),
+                                         (97, 64, 6)])
+def test_blocked_power_iteration_burgers_jacobian(ctx, nx, ny, iters):
+    """The Burgers Jacobian at a seeded state: four sweeps per launch with u
+    staged beside the basis (even nx of at least four cells), one sweep per
+    launch for odd nx; rho_hat as the oracle's normalised iteration."""
+    rng = np.random.default_rng(nx * 31 + ny + iters)
+    u = rng.standard_normal((ny, nx))
+    x0 = rng.standard_normal((ny, nx))
+    nu, dx, dy = 2e-2, 1.0 / nx, 1.0 / ny
+    op = B.make_operator(kind=B.LX_OP_BURGERS2D, nx=nx, ny=ny, dx=dx, dy=dy, nu=nu)
+    say("blocked power burgers", nx, ny, iters)
+    rho, _, _ = ctx.spectrum(op, u=dev(u), x0=dev(x0), iters=iters)
+    st = ctx.stats()
+    if nx % 2 == 0:
+        assert st["depth"] == 4 and st["n_launch"] == (iters + 3) // 4
+    else:
+        assert st["depth"] == 1 and st["n_launch"] == iters
+    rho_o, _ = power_iteration(lambda w: burgers_J(u, w, nu, dx, dy), x0, iters)
+    assert abs(rho - rho_o) <= 1e-12 * rho_o
+
+
 @pytest.mark.parametrize("depth", [3, 4, 6])
 def test_windows_with_the_largest_budget(ctx, depth):
     """max_iters = LX_MAX_ITERS: the window past the budget reads Leja
