@@ -137,25 +137,26 @@ hipError_t launch_leja_sweep(int op, int K, bool fp32_capable, const Tile& t, co
 // Launch L of the two-iterations-per-launch loop (pair.hip): sweeps 2L and
 // 2L+1 on tiles of 128 x th points (th in {8, 16, 32}); FP64, nx even.
 hipError_t launch_leja_pair(int op, int K, int th, const SweepArgs& a, int L, hipStream_t s);
-// Launch L of the loop with `depth` (3 or 4) iterations per launch
+// Launch L of the loop with `depth` (3, 4 or 6) iterations per launch
 // (block.hip): speculative windows re-executed when an output stops inside
-// one; tiles of 128 x th points (th in {8, 16}); FP64, nx even; the
-// five-point diffusion-advection operator.
+// one; tiles of 128 x th points (th in {8, 16}); FP64, nx even, sides of at
+// least depth x radius cells; every operator at depths 3 and 4 (Burgers
+// needs a.u), the five-point diffusion-advection operator also at 6.
 hipError_t launch_leja_block(int op, int K, int th, int depth, const SweepArgs& a, int L, hipStream_t s);
 // Power iteration: norm of the start vector into partials[1], then sweeps
 // k = 0..iters-1, then the final norm into ctl->rho.
 hipError_t launch_power_norm(const double* x, long n, int nb, double* partials, hipStream_t s);
 hipError_t launch_power_sweep(int op, const Tile& t, const PowerArgs& a, int k, hipStream_t s);
 hipError_t launch_power_final(int nb, const double* partials, LoopCtl* ctl, hipStream_t s);
-// Power iteration with kPowerBlockDepth sweeps per launch (block.hip; the
-// diffusion-advection operators, nx even, 128-column tiles of
+// Power iteration with kPowerBlockDepth sweeps per launch (block.hip; every
+// operator (Burgers needs a.u), nx even, 128-column tiles of
 // power_block_rows(op) rows with a.tiles_x/a.tiles_y in that layout): launch b makes nlev (1..depth)
 // levels from `in`; the start vector's norm partials at partials[nb + i]
 // (launch_power_norm), its own at partials[2 nb + (b & 1) nb depth + ...];
 // partials needs 2 nb (1 + depth) doubles.  Then the final ratio into
 // ctl->rho.
 constexpr int kPowerBlockDepth = 4;
-// op: kOpDiffAdv (tiles of 128 x 16) or kOpDiffAdv3 (128 x 8, power_block_rows)
+// op: kOpDiffAdv (tiles of 128 x 16), kOpDiffAdv3 or kOpBurgersJ (128 x 8)
 int power_block_rows(int op);
 // workgroups of power_block that are resident at once on the current device
 // (0 if the runtime cannot tell)
