@@ -128,7 +128,8 @@ typedef struct {
     double first_sweep_ms;  /* duration of sweep 0 (timing on)                */
     double bytes;           /* algorithmic HBM bytes of the working sweeps    */
     int n_launch;           /* Leja-loop launches that did work               */
-    int depth;              /* Leja iterations per launch (1 or 2)            */
+    int depth;              /* Leja iterations per launch: 1, 2, 3, 4, 6 or 8
+                               (lx_spectrum: power sweeps per launch)        */
     double step_err;        /* lx_exprb_step with LX_EXPRB32: embedded error  */
     int substeps;           /* substeps taken (lx_leja_opts.substeps)         */
 } lx_stats;
@@ -408,8 +409,9 @@ lx_status lx_phi_leja_learned(lx_ctx* ctx, lx_predictor* p, int n, const lx_inst
  * file's entries.
  * report: host buffer of report_len chars, or NULL; receives one line per
  * candidate: "depth tx ty rows vec workgroups microseconds_per_iteration",
- * rows being ry for depth 1 and th for depths 2..4 (whose workgroups are
- * 64 x 4).
+ * rows being ry for depth 1, th for LDS-tile depths 2..6 (whose workgroups
+ * are 64 x 4) and the number of bands for register-marching windows, which
+ * report depth as 100 + D.
  * Errors: LX_EINVAL (op invalid, K out of range, sweeps outside 1..200),
  * LX_ENOMEM. */
 lx_status lx_tune(lx_ctx* ctx, const lx_operator* op, int K, int sweeps, char* report, size_t report_len);
@@ -426,19 +428,38 @@ lx_status lx_set_tile(lx_ctx* ctx, int tx, int ty, int ry, int vec, int nb);
  * depth 1 runs one fused sweep per launch (the shape of lx_set_tile);
  * depth 2 runs two iterations per launch on LDS-resident tiles of 128
  * columns by th (8, 16 or 32) rows with nb workgroups (0 = automatic),
- * reading the basis once per two iterations; depths 3, 4 and 6 run windows
- * of that many iterations (th 8 or 16; larger th is taken as 16) whose terms
- * are added speculatively, and re-execute a window in which an output
- * stopped (they also use one more buffer per output, allocated on first
- * use); depth 0 restores the automatic choice (the tuned entry, else 2).
- * Depths 2..6 apply to FP64 sweeps on grids with even nx and 16-byte aligned
- * vectors; 3 and 4 to the diffusion-advection operators and 6 to
- * LX_OP_DIFFADV2D (others fall back to 4, then 2), each with sides of at
- * least depth times the stencil radius; other calls use depth 1.  Results agree with depth 1 to rounding (the outputs
- * take the same terms in the same order; only the order of the norm
- * reductions differs).
- * Errors: LX_EINVAL (depth not 0..4 or 6, th not 0, 8, 16 or 32, nb < 0). */
+ * reading the basis once per two iterations; depths 3, 4, 6 and 8 run
+ * windows of that many iterations whose terms are added speculatively, and
+ * re-execute a window in which an output stopped (they also use one more
+ * buffer per output, allocated on first use).  Windows run either on LDS
+ * tiles (th 8 or 16; larger th is taken as 16; depths 3, 4, 6) or by
+ * register marching (lx_set_window_kernel; depths 4, 6, 8); depth 0
+ * restores the automatic choice (the tuned entry, else 2).
+ * Depths 2..8 apply to FP64 sweeps on grids with even nx and 16-byte aligned
+ * vectors; on LDS tiles 3 and 4 to the diffusion-advection operators and
+ * the Burgers Jacobian, 6 to LX_OP_DIFFADV2D (others fall back to 4, then
+ * 2), each with sides of at least depth times the stencil radius; register
+ * marching to LX_OP_DIFFADV2D only (depth 4 for K <= 4, 6 for K <= 3, 8 for
+ * K = 1; depth 8 otherwise falls back to 6); other calls use depth 1.
+ * Results agree with depth 1 to rounding (the outputs take the same terms
+ * in the same order; only the order of the norm reductions differs).
+ * Errors: LX_EINVAL (depth not 0..4, 6 or 8, th not 0, 8, 16 or 32, nb < 0). */
 lx_status lx_set_depth(lx_ctx* ctx, int depth, int th, int nb);
+
+/* Which kernel later windows (depth >= 3) and power iterations run on:
+ * kind 0 = automatic (windows as the tuned entry says, else LDS tiles;
+ * power iteration by register marching where it applies), 1 = LDS tiles
+ * for both (leja_block, power_block), 2 = register marching where it
+ * applies (leja_stream, power_stream: LX_OP_DIFFADV2D, FP64, even nx,
+ * sides >= depth, 16-byte aligned vectors; windows at depths 4, 6 and 8).
+ * Register marching gives every wavefront a strip of 128 columns (its
+ * output columns and depth columns on each side) and a band of rows, which
+ * it walks from top to bottom forming all levels of the window in
+ * registers.  bands: bands of rows (0 = one resident round of wavefronts);
+ * nb: workgroups of four wavefronts (0 = automatic).  Results are the same
+ * as with LDS tiles up to the order of the norm reductions.
+ * Errors: LX_EINVAL (kind not 0..2, bands < 0, nb < 0). */
+lx_status lx_set_window_kernel(lx_ctx* ctx, int kind, int bands, int nb);
 
 /* Practical HBM bandwidth of plain streaming HIP kernels, the calibration
  * of Sec. 3: kind 0 copies y = x (16 bytes per element), kind 1 computes

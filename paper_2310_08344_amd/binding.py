@@ -146,6 +146,8 @@ def _signatures(lib: C.CDLL) -> None:
     lib.lx_set_tile.restype = _I
     lib.lx_set_depth.argtypes = [_P, _I, _I, _I]
     lib.lx_set_depth.restype = _I
+    lib.lx_set_window_kernel.argtypes = [_P, _I, _I, _I]
+    lib.lx_set_window_kernel.restype = _I
     lib.lx_bandwidth_probe.argtypes = [_P, _I, C.c_size_t, _I, C.POINTER(_D)]
     lib.lx_bandwidth_probe.restype = _I
     lib.lx_leja_points.argtypes = [_I, C.POINTER(_D)]
@@ -158,7 +160,7 @@ def _signatures(lib: C.CDLL) -> None:
 
 EXPORTED = ["lx_create", "lx_destroy", "lx_set_stream", "lx_set_timing", "lx_last_error",
             "lx_status_string", "lx_get_stats", "lx_spectrum", "lx_phi_leja", "lx_exprb_step", "lx_linear_step",
-            "lx_phi_leja_batched", "lx_tune", "lx_set_tile", "lx_set_depth", "lx_bandwidth_probe",
+            "lx_phi_leja_batched", "lx_tune", "lx_set_tile", "lx_set_depth", "lx_set_window_kernel", "lx_bandwidth_probe",
             "lx_predictor_create", "lx_predictor_destroy", "lx_predictor_state_size", "lx_predictor_set_scaling",
             "lx_predictor_get_state", "lx_predictor_set_state", "lx_predictor_save", "lx_predictor_load",
             "lx_predictor_gradient", "lx_predictor_train", "lx_predictor_infer", "lx_instance_features",
@@ -286,8 +288,13 @@ class Context:
         self._check(self.lib.c.lx_set_tile(self._h, int(tx), int(ty), int(ry), int(vec), int(nb)))
 
     def set_depth(self, depth=0, th=0, nb=0) -> None:
-        """Leja iterations per launch (lx_set_depth): 0 automatic, 1 or 2."""
+        """Leja iterations per launch (lx_set_depth): 0 automatic, 1, 2, 3, 4, 6 or 8."""
         self._check(self.lib.c.lx_set_depth(self._h, int(depth), int(th), int(nb)))
+
+    def set_window_kernel(self, kind=0, bands=0, nb=0) -> None:
+        """Kernel of windows and power iteration (lx_set_window_kernel): 0
+        automatic, 1 LDS tiles, 2 register marching."""
+        self._check(self.lib.c.lx_set_window_kernel(self._h, int(kind), int(bands), int(nb)))
 
     def bandwidth_probe(self, kind: int, n: int, reps: int = 20) -> float:
         """GB/s of the copy (kind 0) or z = ax + by (kind 1) probe."""

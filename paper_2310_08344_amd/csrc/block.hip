@@ -38,6 +38,7 @@
 #include "lx_device.h"
 #include "sweep_device.h"
 #include "tile_device.h"
+#include "window_device.h"
 
 namespace lx {
 namespace {
@@ -112,17 +113,6 @@ __device__ __forceinline__ BlockY<TH, D, R> load_block_y(const TileArgs<K>& a, c
         }
     }
     return r;
-}
-
-// v of lane l - 1 (kFromBelow: DPP wave_shr:1) or of lane l + 1 (wave_shl:1);
-// the lane with no such neighbour keeps `old`.  Every lane of the wavefront
-// must be active.
-template <bool kFromBelow>
-__device__ __forceinline__ double lane_neighbour(const double v, const double old) {
-    constexpr int ctrl = kFromBelow ? 0x138 : 0x130;
-    const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), ctrl, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), ctrl, 0xf, 0xf, false);
-    return __hiloint2double(hi, lo);
 }
 
 // Row `ce` around the column pair j, j+1 of this lane, where the 64 lanes of
@@ -349,76 +339,6 @@ __device__ __forceinline__ void block_tile(const TileArgs<K>& a, BlockLds<OP, TH
     __syncthreads();   // the next tile overwrites LDS
 }
 
-// The state entering a launch from the state of the previous launch and its
-// partial sums tot[(j-1)(1+K) + q], q = 0: |y_{m+j}|^2, q = 1+k: |p_k|^2
-// after term m+j (j = 1..D).
-template <int K, int D>
-__device__ __forceinline__ SweepState block_decide(const SweepArgs& a, const LoopCtl& ctl, const SweepState& prev,
-                                                   const double (&tot)[D * (1 + K)]) {
-    SweepState nx = prev;
-    if (prev.blk_mode == 1) {
-        // the window was re-executed with its stops: the outputs that took all
-        // D terms go on from y_{m+D}
-        nx.blk_mode = 0;
-        nx.iter = prev.iter + D;
-        bool any = false;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            nx.active[k] = (prev.active[k] && prev.nt[k] == D) ? 1 : 0;
-            nx.nt[k] = nx.active[k] ? D : 0;
-            any = any || nx.active[k];
-        }
-        if (!any) nx.done = 1;
-        return nx;
-    }
-    const int m = prev.iter;
-    bool stopped = false, nonfinite = false, notconv = false;
-    int nt[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) nt[k] = prev.active[k] ? D : 0;
-    for (int j = 1; j <= D; ++j) {
-        const double ynorm = sqrt(tot[(j - 1) * (1 + K)]) * a.inv_sqrtN;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            if (nt[k] != D) continue;   // inactive, or stopped earlier in this window
-            const double pn = sqrt(tot[(j - 1) * (1 + K) + 1 + k]) * a.inv_sqrtN;
-            const double e = fabs(a.coef[k * a.ld + m + j]) * ynorm;
-            const double thr = ctl.rtol * pn + ctl.atol;
-            nx.err[k] = e;
-            nx.pnorm[k] = pn;
-            nx.ynorm = ynorm;
-            if (!isfinite(pn) || !isfinite(e)) {
-                nonfinite = true;
-            } else if (e <= thr) {
-                nt[k] = -j;   // stopped after term m+j (also when j = D)
-                nx.iters[k] = m + j;
-                stopped = true;
-            } else if (m + j >= ctl.max_iters) {
-                nt[k] = -j;
-                nx.iters[k] = m + j;
-                stopped = true;
-                notconv = true;
-            }
-        }
-    }
-    if (nonfinite) {
-        nx.status = 4;   // LX_ENONFINITE
-        nx.done = 1;
-        return nx;
-    }
-    if (stopped) {
-        // re-execute the window with the stops: nt[k] = -j for an output
-        // that stopped after term m+j, D for one that goes on, 0 otherwise
-        nx.blk_mode = 1;
-#pragma unroll
-        for (int k = 0; k < K; ++k) nx.nt[k] = nt[k];
-        if (notconv) nx.status = 3;   // LX_ENOTCONV
-    } else {
-        nx.iter = m + D;
-    }
-    return nx;
-}
-
 // One launch L of the window loop as workgroup `wg` of the a.nb that serve
 // this grid: the decision, then the window, its re-execution or nothing.
 // Workgroup 0 records the state; when the loop has ended it publishes
@@ -428,77 +348,8 @@ __device__ __forceinline__ SweepState block_decide(const SweepArgs& a, const Loo
 template <int OP, int K, int TH, int D>
 __device__ __forceinline__ void block_launch(const SweepArgs& a, const int L, const int wg, const bool banded,
                                              BlockLds<OP, TH, D>& S, unsigned* done) {
-    LoopCtl* __restrict__ ctl = a.ctl;
-    constexpr int NV = D * (1 + K);
-    __shared__ SweepState s_cur;
-    const int tid = flat_tid();
-    if (L == 0) {
-        if (tid == 0) {
-            SweepState st = ctl->slot[0];
-            st.blk_mode = 0;
-            st.iter = 0;
-            for (int k = 0; k < kKMax; ++k) st.nt[k] = (k < K && st.active[k]) ? D : 0;
-            st.n_work = 1;
-            st.n_levels = D;
-            double b = 16.0 + (OP == kOpBurgersJ ? 8.0 : 0.0);
-            for (int k = 0; k < K; ++k) b += st.nt[k] ? 8.0 : 0.0;
-            st.bytes_pp = b;
-            s_cur = st;
-            if (wg == 0) ctl->slot[0] = st;
-        }
-    } else {
-        double tot[NV];
-        sum_partials<NV>(a.partials + static_cast<long>((L - 1) & 1) * a.nb * NV, a.nb, tot);
-        if (tid == 0) {
-            SweepState st = block_decide<K, D>(a, *ctl, ctl->slot[(L - 1) & 1], tot);
-            if (!st.done) {
-                // algorithmic bytes per point: y in (and out, unless a
-                // re-execution), and per output written p (in and out; the
-                // first window only writes it)
-                const bool rd = st.blk_mode == 1;
-                st.n_work += 1;
-                double b = (rd ? 8.0 : 16.0) + (OP == kOpBurgersJ ? 8.0 : 0.0);   // y (and u)
-                int lev = rd ? 0 : D;
-                for (int k = 0; k < K; ++k) {
-                    const bool w_k = rd ? st.nt[k] < 0 : st.nt[k] != 0;
-                    if (w_k) b += st.iter == 0 ? 8.0 : 16.0;
-                    if (rd && -st.nt[k] > lev) lev = -st.nt[k];
-                }
-                st.bytes_pp += b;
-                st.n_levels += lev;
-            }
-            s_cur = st;
-            if (wg == 0) {
-                ctl->slot[L & 1] = st;
-                if (st.done) {
-                    ctl->slot[2] = st;   // this launch does no work
-                    if (done != nullptr) atomicAdd(done, 1u);
-                }
-            }
-        }
-    }
-    __syncthreads();
-    if (s_cur.done) return;
-    const int m = s_cur.iter;
-    const int win = m / D;
-    const bool redo = s_cur.blk_mode == 1;
-    // terms each output takes in this launch.  A re-execution recomputes
-    // only the outputs that stopped (their final buffer is p); the others,
-    // and y_{m+D}, the window already wrote exactly.
-    int nt[K], jmax = redo ? 0 : D;
-    const double* pin[K];
-    double* pout[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int q = s_cur.nt[k];
-        nt[k] = redo ? (q < 0 ? -q : 0) : q;
-        if (nt[k] > jmax) jmax = nt[k];
-        pin[k] = (win & 1) ? a.p2[k] : a.p[k];
-        pout[k] = redo ? a.p[k] : ((win & 1) ? a.p[k] : a.p2[k]);
-    }
-    const double* __restrict__ yin = (win == 0) ? a.v : static_cast<const double*>(a.ybuf[(win - 1) & 1]);
-    double* __restrict__ yout = static_cast<double*>(a.ybuf[win & 1]);
-
+    WindowPlan<K> w;
+    if (!window_enter<OP, K, D>(a, L, wg, done, w)) return;
     double sy[D], sp[K][D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
@@ -526,24 +377,13 @@ __device__ __forceinline__ void block_launch(const SweepArgs& a, const int L, co
         end = static_cast<int>((static_cast<long>(wg + 1) * T) / a.nb);
     }
     BlockY<TH, D, radius<OP>()> ty;
-    if (first < end) ty = load_block_y<K, TH, D, radius<OP>()>(ta, yin, first);
+    if (first < end) ty = load_block_y<K, TH, D, radius<OP>()>(ta, w.yin, first);
     for (int t = first; t < end; t += step) {
         const int next = (t + step < end) ? t + step : t;
-        block_tile<OP, K, TH, D>(ta, S, yin, yout, pin, pout, m, win == 0, nt, jmax, !redo, sy, sp, t, ty, next);
+        block_tile<OP, K, TH, D>(ta, S, w.yin, w.yout, w.pin, w.pout, w.m, w.win == 0, w.nt, w.jmax, !w.redo, sy,
+                                 sp, t, ty, next);
     }
-    double v[NV];
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-        v[j * (1 + K)] = sy[j];
-#pragma unroll
-        for (int k = 0; k < K; ++k) v[j * (1 + K) + 1 + k] = sp[k][j];
-    }
-    block_sum<NV>(v);
-    if (tid == 0) {
-        double* __restrict__ Pp = a.partials + static_cast<long>(L & 1) * a.nb * NV + static_cast<long>(wg) * NV;
-#pragma unroll
-        for (int q = 0; q < NV; ++q) Pp[q] = v[q];
-    }
+    window_exit<K, D>(a, L, wg, sy, sp);
 }
 
 template <int OP, int K, int TH, int D>

@@ -214,11 +214,12 @@ void load_tune_cache(lx_ctx* ctx) {
         Tile t;
         if (std::sscanf(line, "{\"kind\": %d, \"nx\": %d, \"ny\": %d, \"K\": %d, \"prec\": %d, \"tx\": %d, "
                               "\"ty\": %d, \"ry\": %d, \"vec\": %d, \"nb\": %d, \"depth\": %d, \"th\": %d, "
-                              "\"pnb\": %d",
-                        &kind, &nx, &ny, &K, &prec, &t.tx, &t.ty, &t.ry, &t.vec, &t.nb, &t.depth, &t.th,
-                        &t.pnb) == 13 &&
-            valid_tile(t) && t.depth >= 1 && t.depth <= 6 && t.depth != 5 && (t.th == 8 || t.th == 16 || t.th == 32) &&
-            t.pnb >= 0) {
+                              "\"pnb\": %d, \"stream\": %d, \"bands\": %d, \"snb\": %d",
+                        &kind, &nx, &ny, &K, &prec, &t.tx, &t.ty, &t.ry, &t.vec, &t.nb, &t.depth, &t.th, &t.pnb,
+                        &t.stream, &t.bands, &t.snb) == 16 &&
+            valid_tile(t) && t.depth >= 1 && t.depth <= 8 && t.depth != 5 && t.depth != 7 &&
+            (t.th == 8 || t.th == 16 || t.th == 32) && t.pnb >= 0 && (t.stream == 0 || t.stream == 1) &&
+            t.bands >= 0 && t.snb >= 0) {
             ctx->tuned[std::make_tuple(kind, nx, ny, K, prec)] = t;
         }
     }
@@ -244,6 +245,12 @@ struct LejaCall {
     lx_leja_opts o;
 };
 
+// Whether a call may run its windows by register marching at this depth.
+bool stream_ok(const lx_operator& op, int K, int depth) {
+    return op.kind == LX_OP_DIFFADV2D && op.prec == LX_FP64 && op.nx % 2 == 0 && lx::stream_has(K, depth) &&
+           op.nx >= depth && op.ny >= depth;
+}
+
 // Iterations per launch for this call: forced by lx_set_depth, else the
 // tuned entry's, else two.  Two or more need FP64 sweeps and 16-byte pairs;
 // windows of three or more need sides of depth x radius cells (else two),
@@ -256,11 +263,24 @@ void choose_depth(const lx_ctx* ctx, const lx_operator& op, int K, bool vec2_ok,
     else if (it != ctx->tuned.end()) depth = it->second.depth;
     // windows stage a halo of depth * radius cells, which the periodic index
     // wrap allows only on sides of at least that many cells
+    // windows by register marching: forced by lx_set_window_kernel, else the
+    // tuned entry's choice; eight iterations only that way
+    const bool tuned_stream = it != ctx->tuned.end() && it->second.stream && it->second.depth == depth;
+    t.stream = 0;
+    if (pair_ok && depth >= 3 && (ctx->win_kind == 2 || (ctx->win_kind == 0 && tuned_stream)) &&
+        stream_ok(op, K, depth)) {
+        t.stream = 1;
+        t.depth = depth;
+        t.bands = ctx->win_bands != 0 ? ctx->win_bands : (tuned_stream ? it->second.bands : 0);
+        t.snb = ctx->win_nb != 0 ? ctx->win_nb : (tuned_stream ? it->second.snb : 0);
+        return;
+    }
+    if (depth == 8) depth = 6;
     const int halo = depth * (op.kind == LX_OP_DIFFADV2D_UP3 ? 2 : 1);
     if (depth >= 3 && (op.nx < halo || op.ny < halo)) depth = 2;
     if (depth == 6 && op.kind != LX_OP_DIFFADV2D) depth = 4;   // six: the five-point operator only
     t.depth = (depth >= 2 && pair_ok) ? depth : 1;
-    if (it != ctx->tuned.end() && it->second.depth >= 2 && it->second.depth == t.depth) {
+    if (it != ctx->tuned.end() && it->second.depth >= 2 && it->second.depth == t.depth && !it->second.stream) {
         t.th = it->second.th;
         t.pnb = it->second.pnb;
     } else {
@@ -292,8 +312,38 @@ int pair_grid(int pnb, int tiles) {
     return std::max(nb, 1);
 }
 
+// Grid of a register-marching launch (leja_stream, power_stream): strips of
+// 128 - 2D output columns by bands of rows, one item per wavefront.  By
+// default the bands make one resident round of wavefronts (no partial
+// second round), with bands of at least 4D rows so that the D rows staged
+// above and below a band stay a small share of it; workgroups are a multiple
+// of 8 when that stays within one round (each XCD then takes a contiguous
+// run of bands).
+struct StreamGrid {
+    int strips, bands, nb;
+};
+
+StreamGrid stream_grid(int nx, int ny, int K, int D, int bands, int nb, bool power) {
+    StreamGrid g;
+    g.strips = lx::stream_strips(nx, D);
+    const int resident = lx::stream_resident(K, D, power ? 1 : 0);
+    const int waves = (resident > 0 ? resident : 512) * (lx::kBlockThreads / 64);
+    int by = bands;
+    if (by <= 0) by = std::max(1, std::min(waves / g.strips, ny / (4 * D)));
+    g.bands = std::max(1, std::min(by, ny));
+    const int items = g.strips * g.bands;
+    int wgs = nb > 0 ? nb : (items + 3) / 4;
+    if (nb <= 0 && resident > 0) wgs = std::min(wgs, resident);
+    if (nb <= 0 && wgs >= 8) {
+        const int up = (wgs + 7) & ~7;
+        if (resident <= 0 || up <= resident) wgs = up;
+    }
+    g.nb = std::max(wgs, 1);
+    return g;
+}
+
 // The device-resident Newton-Leja loop (Sec. 2.1, Eq. (2); stop rule of
-// Sec. 2.2), one or two iterations per launch.  Fills ctx->stats.
+// Sec. 2.2), one or more iterations per launch.  Fills ctx->stats.
 lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
     const lx_operator& op = *q.op;
     const int nx = op.nx, ny = op.ny;
@@ -366,7 +416,12 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
     SweepArgs a{};
     a.nx = nx;
     a.ny = ny;
-    if (pair || blk) {
+    if (t.stream) {
+        const StreamGrid g = stream_grid(nx, ny, K, D, t.bands, t.snb, false);
+        a.tiles_x = g.strips;
+        a.tiles_y = g.bands;
+        a.nb = g.nb;
+    } else if (pair || blk) {
         a.tiles_x = (nx + 127) / 128;
         a.tiles_y = (ny + t.th - 1) / t.th;
         a.nb = pair_grid(t.pnb, a.tiles_x * a.tiles_y);
@@ -432,7 +487,8 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
         if (s != LX_OK) return s;
         for (int i = 0; i < n; ++i) {
             const int L = launched + i;
-            if (blk) LX_HIP(ctx, lx::launch_leja_block(opcode, K, t.th, D, a, L, ctx->stream));
+            if (t.stream) LX_HIP(ctx, lx::launch_leja_stream(K, D, a, L, ctx->stream));
+            else if (blk) LX_HIP(ctx, lx::launch_leja_block(opcode, K, t.th, D, a, L, ctx->stream));
             else if (pair) LX_HIP(ctx, lx::launch_leja_pair(opcode, K, t.th, a, L, ctx->stream));
             else LX_HIP(ctx, lx::launch_leja_sweep(opcode, K, fp32, t, a, L, ctx->stream));
             if (ctx->timing && L < last) LX_HIP(ctx, hipEventRecord(ctx->tev[L + 1], ctx->stream));
@@ -728,6 +784,77 @@ lx_status run_leja_sub(lx_ctx* ctx, const LejaCall& q) {
     return worst;
 }
 
+// Power iteration by register marching (power_stream): up to
+// kPowerStreamDepth sweeps per launch, normalised at launch boundaries.  The
+// unnormalised levels grow at most like the Gershgorin bound g of A (the
+// start of a launch has norm 1), so a launch makes at most 140 / log10(g)
+// levels: their squares stay below 1e280.
+lx_status spectrum_stream(lx_ctx* ctx, const lx_operator& op, const double* x0, int iters, double safety,
+                          double* rho_hat, double* c, double* gamma) {
+    constexpr int DP = lx::kPowerStreamDepth;
+    const int nx = op.nx, ny = op.ny;
+    const long N = static_cast<long>(nx) * ny;
+    double pk[9];
+    diffadv_stencil9(op, 0.0, 1.0, pk);
+    const double g = std::fabs(pk[0]) + std::fabs(pk[1]) + std::fabs(pk[2]) + std::fabs(pk[3]) + std::fabs(pk[4]);
+    const int cap = g > 10.0 ? static_cast<int>(140.0 / std::log10(g)) : DP;
+    const int per = std::max(1, std::min(DP, cap));
+    const StreamGrid sg = stream_grid(nx, ny, 1, DP, 0, 0, true);
+    PowerArgs a{};
+    a.nx = nx;
+    a.ny = ny;
+    a.tiles_x = sg.strips;
+    a.tiles_y = sg.bands;
+    a.nb = sg.nb;
+    a.cE = pk[0];
+    a.cW = pk[1];
+    a.cN = pk[2];
+    a.cS = pk[3];
+    a.cC = pk[4];
+    lx_status s = ensure_partials(ctx, 2 * static_cast<size_t>(a.nb) * (1 + DP));
+    if (s != LX_OK) return s;
+    a.partials = ctx->partials;
+    a.ctl = ctx->ctl;
+    const int nblk = (iters + per - 1) / per;
+    LX_HIP(ctx, lx::launch_power_norm(x0, N, a.nb, ctx->partials, ctx->stream));
+    if (ctx->timing) {
+        s = ensure_timing_events(ctx, static_cast<size_t>(nblk) + 1);
+        if (s != LX_OK) return s;
+        LX_HIP(ctx, hipEventRecord(ctx->tev[0], ctx->stream));
+    }
+    int nlev = per, prev = per;
+    for (int b = 0; b < nblk; ++b) {
+        nlev = (b == nblk - 1) ? iters - per * (nblk - 1) : per;
+        const double* in = (b == 0) ? x0 : ctx->ybuf[(b - 1) & 1];
+        LX_HIP(ctx, lx::launch_power_stream(a, in, ctx->ybuf[b & 1], b, nlev, prev, ctx->stream));
+        if (ctx->timing) LX_HIP(ctx, hipEventRecord(ctx->tev[b + 1], ctx->stream));
+        prev = nlev;
+    }
+    LX_HIP(ctx, lx::launch_power_stream_final(a, nblk - 1, nlev, ctx->stream));
+    LX_HIP(ctx, hipMemcpyAsync(ctx->h_ctl, ctx->ctl, sizeof(LoopCtl), hipMemcpyDeviceToHost, ctx->stream));
+    LX_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    const double rho = ctx->h_ctl->rho;
+    lx_stats& S = ctx->stats;
+    S.n_apply = iters;
+    S.n_launch = nblk;
+    S.depth = per;
+    S.rho_hat = rho;
+    S.bytes = 16.0 * static_cast<double>(N) * nblk;
+    if (ctx->timing) {
+        S.loop_ms = elapsed(ctx->tev[0], ctx->tev[nblk]);
+        S.sweep_ms = S.loop_ms;
+        S.first_sweep_ms = elapsed(ctx->tev[0], ctx->tev[1]);
+    }
+    if (!std::isfinite(rho) || !(rho > 0.0))
+        return fail(ctx, LX_ENONFINITE, "power iteration produced a zero or non-finite norm");
+    const double lam = -safety * rho;
+    if (rho_hat) *rho_hat = rho;
+    if (c) *c = lam / 2.0;
+    if (gamma) *gamma = -lam / 4.0;
+    S.status = LX_OK;
+    return LX_OK;
+}
+
 }  // namespace
 
 lx_status lx_internal_fail(lx_ctx* ctx, lx_status s, const char* fmt, ...) {
@@ -878,6 +1005,9 @@ lx_status lx_spectrum(lx_ctx* ctx, const lx_operator* op, const double* d_u, con
     // kPowerBlockDepth sweeps per launch on LDS tiles (the basis read and
     // written once per launch, the Burgers state once per launch); odd or
     // narrow grids and unaligned vectors one sweep per launch
+    if (ctx->win_kind != 1 && op->kind == LX_OP_DIFFADV2D && vec2 && nx % 2 == 0 && nx >= lx::kPowerStreamDepth &&
+        ny >= lx::kPowerStreamDepth)
+        return spectrum_stream(ctx, *op, x0, iters, safety, rho_hat, c, gamma);
     constexpr int PD = lx::kPowerBlockDepth;
     const int pcode = opcode_of(op->kind);
     const int ph = PD * (op->kind == LX_OP_DIFFADV2D_UP3 ? 2 : 1);   // halo of a power launch
@@ -1283,12 +1413,23 @@ lx_status lx_exprb_step(lx_ctx* ctx, const lx_operator* op, int scheme, const do
 
 lx_status lx_set_depth(lx_ctx* ctx, int depth, int th, int nb) {
     if (ctx == nullptr) return LX_EINVAL;
-    if (depth < 0 || depth == 5 || depth > 6 || !(th == 0 || th == 8 || th == 16 || th == 32) || nb < 0)
-        return fail(ctx, LX_EINVAL, "depth %d, th %d, nb %d: need depth 0..4 or 6, th 0/8/16/32, nb >= 0", depth, th,
-                    nb);
+    if (depth < 0 || depth == 5 || depth == 7 || depth > 8 || !(th == 0 || th == 8 || th == 16 || th == 32) || nb < 0)
+        return fail(ctx, LX_EINVAL, "depth %d, th %d, nb %d: need depth 0..4, 6 or 8, th 0/8/16/32, nb >= 0", depth,
+                    th, nb);
     ctx->depth_forced = depth;
     ctx->pair_th = th;
     ctx->pair_nb = nb;
+    return LX_OK;
+}
+
+lx_status lx_set_window_kernel(lx_ctx* ctx, int kind, int bands, int nb) {
+    if (ctx == nullptr) return LX_EINVAL;
+    if (kind < 0 || kind > 2 || bands < 0 || nb < 0)
+        return fail(ctx, LX_EINVAL, "window kernel %d, bands %d, nb %d: need kind 0..2, bands >= 0, nb >= 0", kind,
+                    bands, nb);
+    ctx->win_kind = kind;
+    ctx->win_bands = bands;
+    ctx->win_nb = nb;
     return LX_OK;
 }
 
@@ -1485,11 +1626,75 @@ lx_status lx_tune(lx_ctx* ctx, const lx_operator* op, int K, int sweeps, char* r
                         best.th = th;
                         best.pnb = pnb;
                         best.depth = depth;
+                        best.stream = 0;
                     }
                 }
             }
         }
-        if (!(best_pair_us < best_us)) best.depth = 1;
+        // windows by register marching (the five-point diffusion-advection
+        // operator): depth x bands (one resident round, two rounds, and
+        // bands of 64 and 128 rows)
+        for (int depth : {4, 6, 8}) {
+            if (!stream_ok(*op, K, depth)) continue;
+            s = ensure_blk_ws(ctx, K);
+            if (s != LX_OK) return cleanup(s);
+            const StreamGrid g0 = stream_grid(nx, ny, K, depth, 0, 0, false);
+            int prev_bands = -1;
+            for (int bands : {g0.bands, 2 * g0.bands, ny / 64, ny / 128}) {
+                if (bands < 1 || bands > ny || bands == prev_bands) continue;
+                prev_bands = bands;
+                const StreamGrid g = stream_grid(nx, ny, K, depth, bands, 0, false);
+                SweepArgs a{};
+                a.nx = nx;
+                a.ny = ny;
+                a.tiles_x = g.strips;
+                a.tiles_y = g.bands;
+                a.nb = g.nb;
+                a.ld = ld;
+                set_stencil(a, *op, -2.0, 1.0);
+                a.inv_sqrtN = 1.0 / std::sqrt(static_cast<double>(N));
+                a.v = ctx->ybuf[0];
+                a.ybuf[0] = ctx->ybuf[0];
+                a.ybuf[1] = ctx->ybuf[1];
+                for (int k = 0; k < K; ++k) {
+                    a.p[k] = scratch + static_cast<size_t>(k) * N;
+                    a.p2[k] = ctx->blk_ws[k];
+                }
+                a.coef = ctx->coef;
+                a.xi = ctx->xi;
+                s = ensure_partials(ctx, 2 * static_cast<size_t>(depth) * a.nb * (1 + K));
+                if (s != LX_OK) return cleanup(s);
+                a.partials = ctx->partials;
+                a.ctl = ctx->ctl;
+                if (hipMemcpyAsync(ctx->ctl, &init, sizeof(LoopCtl), hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
+                    return cleanup(fail(ctx, LX_EDEVICE, "state upload failed"));
+                const int n = std::max(1, sweeps / depth);
+                hipError_t e = hipSuccess;
+                for (int L = 0; L < 2 && e == hipSuccess; ++L) e = lx::launch_leja_stream(K, depth, a, L, ctx->stream);
+                if (e == hipSuccess) e = hipEventRecord(ctx->tev[0], ctx->stream);
+                for (int L = 2; L < n + 2 && e == hipSuccess; ++L)
+                    e = lx::launch_leja_stream(K, depth, a, L, ctx->stream);
+                if (e == hipSuccess) e = hipEventRecord(ctx->tev[1], ctx->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(ctx->tev[1]);
+                if (e != hipSuccess)
+                    return cleanup(fail(ctx, LX_EDEVICE, "tuning launch failed: %s", hipGetErrorString(e)));
+                const double us = elapsed(ctx->tev[0], ctx->tev[1]) * 1e3 / (static_cast<double>(depth) * n);
+                char line[112];
+                std::snprintf(line, sizeof(line), "%d 64 1 %d 2 %d %.3f\n", 100 + depth, g.bands, a.nb, us);
+                rep += line;
+                if (us < best_pair_us) {
+                    best_pair_us = us;
+                    best.depth = depth;
+                    best.stream = 1;
+                    best.bands = bands == g0.bands ? 0 : bands;
+                    best.snb = 0;
+                }
+            }
+        }
+        if (!(best_pair_us < best_us)) {
+            best.depth = 1;
+            best.stream = 0;
+        }
     }
     const double best_iter_us = std::min(best_us, best_pair_us);
     ctx->tuned[std::make_tuple(op->kind, nx, ny, K, op->prec)] = best;
@@ -1503,9 +1708,9 @@ lx_status lx_tune(lx_ctx* ctx, const lx_operator* op, int K, int sweeps, char* r
             std::fprintf(f,
                          "{\"kind\": %d, \"nx\": %d, \"ny\": %d, \"K\": %d, \"prec\": %d, \"tx\": %d, "
                          "\"ty\": %d, \"ry\": %d, \"vec\": %d, \"nb\": %d, \"depth\": %d, \"th\": %d, "
-                         "\"pnb\": %d, \"us\": %.3f}\n",
+                         "\"pnb\": %d, \"stream\": %d, \"bands\": %d, \"snb\": %d, \"us\": %.3f}\n",
                          op->kind, nx, ny, K, op->prec, best.tx, best.ty, best.ry, best.vec, best.nb, best.depth,
-                         best.th, best.pnb, best_iter_us);
+                         best.th, best.pnb, best.stream, best.bands, best.snb, best_iter_us);
             std::fclose(f);
         }
     }

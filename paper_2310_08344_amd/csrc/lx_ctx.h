@@ -61,6 +61,8 @@ struct lx_ctx {
     lx::Tile forced{0, 0, 0, 0, 0};         // tx == 0: not forced
     int depth_forced = 0;                   // lx_set_depth: 0 automatic, 1 or 2 iterations per launch
     int pair_th = 0, pair_nb = 0;           // lx_set_depth: forced leja_pair shape (0: automatic)
+    int win_kind = 0;                       // lx_set_window_kernel: 0 automatic, 1 LDS tiles, 2 register march
+    int win_bands = 0, win_nb = 0;          // lx_set_window_kernel: forced bands / workgroups (0: automatic)
     std::map<std::tuple<int, int, int, int, int>, lx::Tile> tuned;
     lx_batch_ws batch;
     std::vector<lx_predictor*> predictors;  // live predictors; lx_destroy frees them

@@ -50,9 +50,12 @@ struct LoopCtl {
 // workgroups (0 = one per tile) loop over the tiles.
 struct Tile {
     int tx = 64, ty = 4, ry = 4, vec = 2, nb = 0;
-    int depth = 1;           // Leja iterations per launch: 1 (leja_sweep) or 2 (leja_pair)
-    int th = 16;             // tile rows of leja_pair (its tiles are 128 columns wide)
-    int pnb = 1024;          // workgroups of leja_pair
+    int depth = 1;           // Leja iterations per launch: 1 (leja_sweep), 2 (leja_pair), 3+ (windows)
+    int th = 16;             // tile rows of leja_pair and leja_block (their tiles are 128 columns wide)
+    int pnb = 1024;          // workgroups of leja_pair and leja_block
+    int stream = 0;          // windows by register streaming (leja_stream) instead of LDS tiles
+    int bands = 0;           // leja_stream: bands of rows (0: one resident round of wavefronts)
+    int snb = 0;             // leja_stream: workgroups (0: as many as hold the items, up to one round)
     int cols() const { return tx * vec; }
     int rows() const { return ty * ry; }
 };
@@ -164,6 +167,31 @@ int power_block_resident(int op);
 hipError_t launch_power_block(int op, const PowerArgs& a, const double* in, double* out, int b, int nlev,
                               hipStream_t s);
 hipError_t launch_power_block_final(const PowerArgs& a, int b, int nlev, hipStream_t s);
+// Windows by register streaming (stream.hip; the five-point
+// diffusion-advection operator, FP64, nx even, sides >= depth, 16-byte
+// aligned vectors): depth 4 or 6 (8 for K <= 2); a.tiles_x =
+// stream_strips(nx, depth) strips of 128 - 2 depth output columns by
+// a.tiles_y (1..ny) bands of rows, a.nb workgroups of four wavefronts that
+// each take items (strip, band) in turn; partials as launch_leja_block.
+int stream_strips(int nx, int depth);
+// whether leja_stream is built for K outputs at this depth (4: K <= 4;
+// 6: K <= 3; 8: K = 1)
+bool stream_has(int K, int depth);
+hipError_t launch_leja_stream(int K, int depth, const SweepArgs& a, int L, hipStream_t s);
+// workgroups of leja_stream<K, depth> (power = 0) or of power_stream
+// (power = 1) resident at once on the current device (0 if unknown)
+int stream_resident(int K, int depth, int power);
+// Power iteration by register streaming, up to kPowerStreamDepth sweeps per
+// launch (the five-point diffusion-advection operator; nx even, sides >=
+// kPowerStreamDepth, a.tiles_x = stream_strips(nx, kPowerStreamDepth),
+// a.tiles_y bands); partials need 2 nb (1 + kPowerStreamDepth) doubles, laid
+// out as for launch_power_block with kPowerStreamDepth in place of its depth.
+constexpr int kPowerStreamDepth = 10;
+// Launch b makes nlev levels, scaled by the norm of the prev levels of
+// launch b - 1 (of the start vector for b = 0).
+hipError_t launch_power_stream(const PowerArgs& a, const double* in, double* out, int b, int nlev, int prev,
+                               hipStream_t s);
+hipError_t launch_power_stream_final(const PowerArgs& a, int b, int nlev, hipStream_t s);
 hipError_t launch_fill_splitmix(double* x, long n, unsigned long long seed, hipStream_t s);
 hipError_t launch_to_fp32(const double* x, float* y, long n, hipStream_t s);
 // kind 0: z = x (copy); kind 1: z = 1.5 x - 0.5 y.  n even.

@@ -1,0 +1,227 @@
+// The window loop's control, shared by its two kernels: leja_block (LDS
+// tiles, block.hip) and leja_stream (register streaming, stream.hip).
+//
+// Launch w of the plain loop advances the Newton recurrence (Sec. 2.1,
+// Eq. (2)) from y_m (m = wD) through y_{m+1} .. y_{m+D}.  The stop rule
+// (Sec. 2.2) for term m+j needs norms of y_{m+j} and of p_{m+j} over the
+// whole grid, which exist only after the launch; a window therefore adds all
+// D terms speculatively to every output still iterating and records, for
+// every j, the sums of squares of y_{m+j} and of each output as it stands
+// after term m+j.  The next launch applies the stop rule at m+1, .., m+D in
+// turn and, if an output stopped inside the window, re-executes the window
+// for the stopped outputs only, with exactly the terms they take.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lx_device.h"
+#include "sweep_device.h"
+#include "tile_device.h"
+
+namespace lx {
+namespace dev {
+
+// v of lane l - 1 (kFromBelow: DPP wave_shr:1) or of lane l + 1 (wave_shl:1);
+// the lane with no such neighbour keeps `old`.  Every lane of the wavefront
+// must be active.
+template <bool kFromBelow>
+__device__ __forceinline__ double lane_neighbour(const double v, const double old) {
+    constexpr int ctrl = kFromBelow ? 0x138 : 0x130;
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), ctrl, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), ctrl, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// The state entering a launch from the state of the previous launch and its
+// partial sums tot[(j-1)(1+K) + q], q = 0: |y_{m+j}|^2, q = 1+k: |p_k|^2
+// after term m+j (j = 1..D).
+template <int K, int D>
+__device__ __forceinline__ SweepState block_decide(const SweepArgs& a, const LoopCtl& ctl, const SweepState& prev,
+                                                   const double (&tot)[D * (1 + K)]) {
+    SweepState nx = prev;
+    if (prev.blk_mode == 1) {
+        // the window was re-executed with its stops: the outputs that took all
+        // D terms go on from y_{m+D}
+        nx.blk_mode = 0;
+        nx.iter = prev.iter + D;
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            nx.active[k] = (prev.active[k] && prev.nt[k] == D) ? 1 : 0;
+            nx.nt[k] = nx.active[k] ? D : 0;
+            any = any || nx.active[k];
+        }
+        if (!any) nx.done = 1;
+        return nx;
+    }
+    const int m = prev.iter;
+    bool stopped = false, nonfinite = false, notconv = false;
+    int nt[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) nt[k] = prev.active[k] ? D : 0;
+    for (int j = 1; j <= D; ++j) {
+        const double ynorm = sqrt(tot[(j - 1) * (1 + K)]) * a.inv_sqrtN;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (nt[k] != D) continue;   // inactive, or stopped earlier in this window
+            const double pn = sqrt(tot[(j - 1) * (1 + K) + 1 + k]) * a.inv_sqrtN;
+            const double e = fabs(a.coef[k * a.ld + m + j]) * ynorm;
+            const double thr = ctl.rtol * pn + ctl.atol;
+            nx.err[k] = e;
+            nx.pnorm[k] = pn;
+            nx.ynorm = ynorm;
+            if (!isfinite(pn) || !isfinite(e)) {
+                nonfinite = true;
+            } else if (e <= thr) {
+                nt[k] = -j;   // stopped after term m+j (also when j = D)
+                nx.iters[k] = m + j;
+                stopped = true;
+            } else if (m + j >= ctl.max_iters) {
+                nt[k] = -j;
+                nx.iters[k] = m + j;
+                stopped = true;
+                notconv = true;
+            }
+        }
+    }
+    if (nonfinite) {
+        nx.status = 4;   // LX_ENONFINITE
+        nx.done = 1;
+        return nx;
+    }
+    if (stopped) {
+        // re-execute the window with the stops: nt[k] = -j for an output
+        // that stopped after term m+j, D for one that goes on, 0 otherwise
+        nx.blk_mode = 1;
+#pragma unroll
+        for (int k = 0; k < K; ++k) nx.nt[k] = nt[k];
+        if (notconv) nx.status = 3;   // LX_ENOTCONV
+    } else {
+        nx.iter = m + D;
+    }
+    return nx;
+}
+
+// What launch L of a window loop does, decided at its entry.
+template <int K>
+struct WindowPlan {
+    int m;                  // the window's first term index
+    int win;                // window number, m / D
+    bool redo;              // re-execution of a window in which an output stopped
+    int nt[K];              // terms each output takes in this launch
+    int jmax;               // levels this launch forms
+    const double* pin[K];   // outputs as the window finds them
+    double* pout[K];        // and where it leaves them
+    const double* yin;      // y_m
+    double* yout;           // y_{m+D}
+};
+
+// Entry of launch L of the window loop as workgroup `wg` of the a.nb that
+// serve this grid: the decision from the previous launch's partial sums.
+// Workgroup 0 records the state; when the loop has ended it publishes
+// slot[2] and, if `done` is given, counts the grid as finished.  Returns
+// false when this launch has nothing to do (the same in every thread).
+//
+// Buffers: window w reads y_m from v (w = 0) or ybuf[(w-1) & 1] and writes
+// y_{m+D} to ybuf[w & 1]; it reads the outputs from p (w even) or p2 (w odd)
+// and writes them to the other; a re-execution writes stopped outputs to p,
+// the caller's buffer, so every final result lands there.
+template <int OP, int K, int D>
+__device__ __forceinline__ bool window_enter(const SweepArgs& a, const int L, const int wg, unsigned* done,
+                                             WindowPlan<K>& w) {
+    LoopCtl* __restrict__ ctl = a.ctl;
+    constexpr int NV = D * (1 + K);
+    __shared__ SweepState s_cur;
+    const int tid = flat_tid();
+    if (L == 0) {
+        if (tid == 0) {
+            SweepState st = ctl->slot[0];
+            st.blk_mode = 0;
+            st.iter = 0;
+            for (int k = 0; k < kKMax; ++k) st.nt[k] = (k < K && st.active[k]) ? D : 0;
+            st.n_work = 1;
+            st.n_levels = D;
+            double b = 16.0 + (OP == kOpBurgersJ ? 8.0 : 0.0);
+            for (int k = 0; k < K; ++k) b += st.nt[k] ? 8.0 : 0.0;
+            st.bytes_pp = b;
+            s_cur = st;
+            if (wg == 0) ctl->slot[0] = st;
+        }
+    } else {
+        double tot[NV];
+        sum_partials<NV>(a.partials + static_cast<long>((L - 1) & 1) * a.nb * NV, a.nb, tot);
+        if (tid == 0) {
+            SweepState st = block_decide<K, D>(a, *ctl, ctl->slot[(L - 1) & 1], tot);
+            if (!st.done) {
+                // algorithmic bytes per point: y in (and out, unless a
+                // re-execution), and per output written p (in and out; the
+                // first window only writes it)
+                const bool rd = st.blk_mode == 1;
+                st.n_work += 1;
+                double b = (rd ? 8.0 : 16.0) + (OP == kOpBurgersJ ? 8.0 : 0.0);   // y (and u)
+                int lev = rd ? 0 : D;
+                for (int k = 0; k < K; ++k) {
+                    const bool w_k = rd ? st.nt[k] < 0 : st.nt[k] != 0;
+                    if (w_k) b += st.iter == 0 ? 8.0 : 16.0;
+                    if (rd && -st.nt[k] > lev) lev = -st.nt[k];
+                }
+                st.bytes_pp += b;
+                st.n_levels += lev;
+            }
+            s_cur = st;
+            if (wg == 0) {
+                ctl->slot[L & 1] = st;
+                if (st.done) {
+                    ctl->slot[2] = st;   // this launch does no work
+                    if (done != nullptr) atomicAdd(done, 1u);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (s_cur.done) return false;
+    // every field below is the same in all threads of the grid
+    w.m = __builtin_amdgcn_readfirstlane(s_cur.iter);
+    w.win = w.m / D;
+    w.redo = __builtin_amdgcn_readfirstlane(s_cur.blk_mode) == 1;
+    // terms each output takes in this launch.  A re-execution recomputes
+    // only the outputs that stopped (their final buffer is p); the others,
+    // and y_{m+D}, the window already wrote exactly.
+    w.jmax = w.redo ? 0 : D;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int q = __builtin_amdgcn_readfirstlane(s_cur.nt[k]);
+        w.nt[k] = w.redo ? (q < 0 ? -q : 0) : q;
+        if (w.nt[k] > w.jmax) w.jmax = w.nt[k];
+        w.pin[k] = (w.win & 1) ? a.p2[k] : a.p[k];
+        w.pout[k] = w.redo ? a.p[k] : ((w.win & 1) ? a.p[k] : a.p2[k]);
+    }
+    w.yin = (w.win == 0) ? a.v : static_cast<const double*>(a.ybuf[(w.win - 1) & 1]);
+    w.yout = static_cast<double*>(a.ybuf[w.win & 1]);
+    return true;
+}
+
+// Exit of a window launch: the workgroup's sums of squares of every level
+// (sy[j-1]: y_{m+j}) and of every output after each term (sp[k][j-1]), in a
+// fixed order, into this workgroup's record of partials[L & 1].
+template <int K, int D>
+__device__ __forceinline__ void window_exit(const SweepArgs& a, const int L, const int wg, const double (&sy)[D],
+                                            const double (&sp)[K][D]) {
+    constexpr int NV = D * (1 + K);
+    double v[NV];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        v[j * (1 + K)] = sy[j];
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[j * (1 + K) + 1 + k] = sp[k][j];
+    }
+    block_sum<NV>(v);
+    if (flat_tid() == 0) {
+        double* __restrict__ Pp = a.partials + static_cast<long>(L & 1) * a.nb * NV + static_cast<long>(wg) * NV;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) Pp[q] = v[q];
+    }
+}
+
+}  // namespace dev
+}  // namespace lx

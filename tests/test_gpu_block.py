@@ -227,8 +227,13 @@ def test_blocked_power_iteration_matches_oracle(ctx, nx, ny, iters):
     prm, _ = diffadv_setup(nx, ny, D=0.7, vx=-30.0, vy=45.0)
     x0 = np.random.default_rng(nx + 7 * ny + iters).standard_normal((ny, nx))
     say("blocked power", nx, ny, iters)
-    rho, c, g = ctx.spectrum(_op(prm), x0=dev(x0), iters=iters)
-    assert ctx.stats()["depth"] == 4 and ctx.stats()["n_launch"] == (iters + 3) // 4
+    ctx.set_window_kernel(1)   # LDS tiles (register marching is the default where it applies)
+    try:
+        rho, c, g = ctx.spectrum(_op(prm), x0=dev(x0), iters=iters)
+        st = ctx.stats()
+    finally:
+        ctx.set_window_kernel(0)
+    assert st["depth"] == 4 and st["n_launch"] == (iters + 3) // 4
     rho_o, _ = power_iteration(_A(prm), x0, iters)
     assert abs(rho - rho_o) <= 1e-12 * rho_o
 

@@ -1,0 +1,181 @@
+"""GPU parity of the register-marching kernels (`leja_stream` windows of
+four, six and eight Leja iterations per launch, `power_stream` power
+iteration) against the CPU oracle, the exact Fourier solution and the
+LDS-tile window kernel, through the C ABI.
+
+Each output must take exactly the terms of the one-iteration loop: the
+oracle comparison at 1e-10 (a borderline stop decision flipped by the order
+of the norm reductions is rerun at the GPU's count and reported), bitwise
+equality with the LDS-tile windows when the counts agree (both form every
+level with the same operand order), stops at every position inside a window,
+forced band and workgroup counts (items per wavefront > 1, idle wavefronts),
+ragged and tiny grids.
+"""
+import numpy as np
+import pytest
+
+from oracle.exact import phi_fft
+from oracle.operators import diffadv_apply
+from oracle.phi_action import leja_phi, power_iteration
+from paper_2310_08344_amd import binding as B
+from paper_2310_08344_amd import workloads as W
+from tests.gpu_helpers import closed_form_shift, dev, diffadv_setup, host, oracle_parity, rel, say
+
+pytestmark = pytest.mark.gpu
+
+PARITY = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ctx(lx):
+    c = lx.context(n_max=1024 * 1024, k_max=4)
+    yield c
+    c.close()
+
+
+def _op(prm):
+    return B.make_operator(kind=B.LX_OP_DIFFADV2D, nx=prm["nx"], ny=prm["ny"], dx=prm["dx"], dy=prm["dy"],
+                           D=prm["D"], vx=prm["vx"], vy=prm["vy"])
+
+
+def _A(prm):
+    return lambda y: diffadv_apply(y, prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
+
+
+def _solve(ctx, depth, kind, bands, nb, op, v, ls, h, c, g, **kw):
+    outs = [dev(np.zeros(v.shape)) for _ in ls]
+    ctx.set_depth(depth, 0, 0)
+    ctx.set_window_kernel(kind, bands, nb)
+    try:
+        r = ctx.phi_leja(op, dev(v), outs, ls, h, c, g, **kw)
+    finally:
+        ctx.set_depth(0)
+        ctx.set_window_kernel(0)
+    return r, [host(o) for o in outs]
+
+
+CASES = [(4, [0, 1, 3, 2]), (6, [0, 1, 3]), (6, [2]), (8, [1]), (4, [1])]
+
+
+@pytest.mark.parametrize("depth,ls", CASES)
+@pytest.mark.parametrize("bands,nb", [(0, 0), (3, 0), (7, 2), (136, 1)])
+def test_stream_windows_match_oracle_and_tiles(ctx, depth, ls, bands, nb):
+    """Ragged strips both ways (200 columns, 136 rows); outputs stop in
+    different windows; several items per wavefront when bands and
+    workgroups are forced."""
+    prm, h = diffadv_setup(200, 136)
+    c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
+    v = np.random.default_rng(31).standard_normal((136, 200))
+    say("stream window", depth, ls, bands, nb)
+    rs, os_ = _solve(ctx, depth, 2, bands, nb, _op(prm), v, ls, h, c, g, rtol=1e-8, max_iters=200)
+    assert rs.status == B.LX_OK and rs.stats["depth"] == depth
+    spec = [(l, 1.0, 1.0) for l in ls]
+    oracle_parity(os_, rs.iters, lambda f: leja_phi(_A(prm), v, spec, h, c, g, 1e-8, 0.0, 200, f), PARITY)
+    its = rs.iters
+    windows = (max(its) + depth - 1) // depth
+    stops = len({(i - 1) // depth for i in its})
+    assert rs.stats["n_launch"] == windows + stops
+    if depth <= 6 and len(ls) <= (3 if depth == 6 else 4):
+        # the LDS-tile windows of the same depth take the same terms in the
+        # same order with the same stencil bits
+        rt, ot = _solve(ctx, depth, 1, 0, 0, _op(prm), v, ls, h, c, g, rtol=1e-8, max_iters=200)
+        if rt.iters == rs.iters:
+            assert all(np.array_equal(a, b) for a, b in zip(os_, ot))
+
+
+@pytest.mark.parametrize("depth", [4, 6, 8])
+@pytest.mark.parametrize("nx,ny", [(8, 8), (10, 12), (64, 9), (130, 20), (256, 40), (14, 200)])
+def test_stream_small_and_odd_grids(ctx, depth, nx, ny):
+    """Strips wider than the grid (columns wrap several times), an odd
+    number of rows, a single band; sides shorter than the window fall back."""
+    prm, h = diffadv_setup(nx, ny, cfl=20.0)
+    c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
+    v = np.random.default_rng(nx * 100 + ny).standard_normal((ny, nx))
+    ls = [0, 2] if depth == 4 else [1]
+    say("stream small grid", depth, nx, ny)
+    r, o = _solve(ctx, depth, 2, 0, 0, _op(prm), v, ls, h, c, g, rtol=1e-9, max_iters=300)
+    assert r.status == B.LX_OK
+    if min(nx, ny) >= depth:
+        assert r.stats["depth"] == depth
+    spec = [(l, 1.0, 1.0) for l in ls]
+    oracle_parity(o, r.iters, lambda f: leja_phi(_A(prm), v, spec, h, c, g, 1e-9, 0.0, 300, f), PARITY)
+
+
+@pytest.mark.parametrize("depth", [4, 6, 8])
+@pytest.mark.parametrize("max_iters", [1, 2, 3, 4, 5, 6, 7, 8, 9, 13])
+def test_stream_windows_at_max_iters(ctx, depth, max_iters):
+    """The budget ends at every position inside a window: LX_ENOTCONV with
+    exactly max_iters terms (the re-execution takes fewer than D terms)."""
+    prm, h = diffadv_setup(96, 64)
+    c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
+    v = np.random.default_rng(4).standard_normal((64, 96))
+    ls = [0, 2] if depth <= 6 else [2]
+    say("stream notconv", depth, max_iters)
+    r, o = _solve(ctx, depth, 2, 0, 0, _op(prm), v, ls, h, c, g, rtol=1e-12, max_iters=max_iters,
+                  raise_on_error=False)
+    assert r.status == B.LX_ENOTCONV and r.iters == [max_iters] * len(ls)
+    ref = leja_phi(_A(prm), v, [(l, 1.0, 1.0) for l in ls], h, c, g, 1e-12, 0.0, max_iters)
+    assert max(rel(a, b) for a, b in zip(o, ref.p)) <= PARITY
+
+
+@pytest.mark.parametrize("depth", [4, 6, 8])
+def test_stream_edge_inputs(ctx, depth):
+    prm, h = diffadv_setup(64, 64)
+    c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
+    say("stream zero / nan", depth)
+    r, o = _solve(ctx, depth, 2, 0, 0, _op(prm), np.zeros((64, 64)), [1], h, c, g, rtol=1e-8)
+    assert r.status == B.LX_OK and r.iters == [1] and not np.any(o[0])
+    v = np.ones((64, 64))
+    v[10, 11] = np.nan
+    r, o = _solve(ctx, depth, 2, 0, 0, _op(prm), v, [0], h, c, g, raise_on_error=False)
+    assert r.status == B.LX_ENONFINITE
+
+
+@pytest.mark.parametrize("depth,ls", [(6, [1, 2, 3]), (4, [1, 2, 3]), (8, [1])])
+def test_stream_1024_squared_workload(ctx, depth, ls):
+    """The 1024^2 phi_1..phi_3 workload: oracle parity and the exact Fourier
+    solution within 10 x tol."""
+    p, v = W.config2(n=1024)
+    op = B.make_operator(p)
+    x0 = W.start_vector(p.n)
+    say("1024^2 stream windows", depth, ls)
+    rho, c, g = ctx.spectrum(op, x0=dev(x0), iters=20)
+    r, o = _solve(ctx, depth, 2, 0, 0, op, v, ls, p.h, c, g, rtol=1e-8, max_iters=200)
+    assert r.status == B.LX_OK and r.stats["depth"] == depth
+    A = _A(dict(D=p.D, vx=p.vx, vy=p.vy, dx=p.dx, dy=p.dy))
+    spec = [(l, 1.0, 1.0) for l in ls]
+    oracle_parity(o, r.iters, lambda f: leja_phi(A, v, spec, p.h, c, g, 1e-8, 0.0, 200, f), PARITY)
+    for l, ob in zip(ls, o):
+        ex = phi_fft(v, l, p.h, p.D, p.vx, p.vy, p.dx, p.dy)
+        assert rel(ob, ex) <= 1e-7
+
+
+def test_stream_repeat_bitwise(ctx):
+    prm, h = diffadv_setup(192, 160)
+    c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
+    v = np.random.default_rng(3).standard_normal((160, 192))
+    say("stream determinism")
+    r1, o1 = _solve(ctx, 6, 2, 0, 0, _op(prm), v, [1, 2, 3], h, c, g, rtol=1e-8, max_iters=200)
+    r2, o2 = _solve(ctx, 6, 2, 0, 0, _op(prm), v, [1, 2, 3], h, c, g, rtol=1e-8, max_iters=200)
+    assert r1.iters == r2.iters and all(np.array_equal(a, b) for a, b in zip(o1, o2))
+
+
+@pytest.mark.parametrize("nx,ny", [(200, 136), (64, 64), (10, 10), (130, 20), (1024, 1024)])
+@pytest.mark.parametrize("iters", [1, 2, 5, 10, 11, 20, 23])
+def test_stream_power_iteration_matches_oracle(ctx, nx, ny, iters):
+    """Up to ten power sweeps per launch by register marching (the last
+    launch takes the rest), the norms deferred to the launch boundary:
+    rho_hat as the oracle's normalised iteration."""
+    prm, _ = diffadv_setup(nx, ny, D=0.7, vx=-30.0, vy=45.0)
+    x0 = np.random.default_rng(nx + 7 * ny + iters).standard_normal((ny, nx))
+    say("stream power", nx, ny, iters)
+    ctx.set_window_kernel(2)
+    try:
+        rho, c, g = ctx.spectrum(_op(prm), x0=dev(x0), iters=iters)
+        st = ctx.stats()
+    finally:
+        ctx.set_window_kernel(0)
+    per = st["depth"]
+    assert 1 <= per <= 10 and st["n_launch"] == (iters + per - 1) // per
+    rho_o, _ = power_iteration(_A(prm), x0, iters)
+    assert abs(rho - rho_o) <= 1e-12 * rho_o
