@@ -225,34 +225,48 @@ def linear_step(apply_A, u, S, h, c, gamma, rtol, atol, max_iters=500) -> "StepR
 @dataclass
 class StepResult:
     u_next: np.ndarray
-    iters: list        # [pass 1 (both phi_1 outputs), pass 2 (phi_3)]
+    iters: list        # iterations of every phi action of the step, in the
+                       # order the step takes them (see each step function)
     status: str
     stages: dict
 
 
-def ros_euler_step(u, nu, dx, dy, h, c, gamma, rtol, atol, max_iters=500) -> StepResult:
+def _forced(force_iters, i):
+    """Iteration count forced on the i-th phi action of a step, or None.
+
+    A step's actions each have their own stop rule (Sec. 2.2); a borderline
+    decision may go the other way in a run whose norms add in another order,
+    and the comparison is then made with the oracle forced to that run's
+    counts, action by action."""
+    return None if force_iters is None else int(force_iters[i])
+
+
+def ros_euler_step(u, nu, dx, dy, h, c, gamma, rtol, atol, max_iters=500, force_iters=None) -> StepResult:
     """One exponential Rosenbrock-Euler step (Sec. 2.3): the phi_1 action of
-    the Jacobian at u on h F(u), added to u."""
+    the Jacobian at u on h F(u), added to u.  iters: [phi_1 action];
+    ``force_iters`` (the same layout) fixes the counts instead."""
     u = np.asarray(u, dtype=np.float64)
     J = lambda w: burgers_J(u, w, nu, dx, dy)
     hF = h * burgers_F(u, nu, dx, dy)
-    r = leja_phi(J, hF, [(1, 1.0, 1.0)], h, c, gamma, rtol, atol, max_iters)
-    return StepResult(u_next=u + r.p[0], iters=[r.iters[0], 0], status=r.status, stages={"phi1": r.p[0]})
+    r = leja_phi(J, hF, [(1, 1.0, 1.0)], h, c, gamma, rtol, atol, max_iters, _forced(force_iters, 0))
+    return StepResult(u_next=u + r.p[0], iters=[r.iters[0]], status=r.status, stages={"phi1": r.p[0]})
 
 
-def exprb32_step(u, nu, dx, dy, h, c, gamma, rtol, atol, max_iters=500) -> StepResult:
+def exprb32_step(u, nu, dx, dy, h, c, gamma, rtol, atol, max_iters=500, force_iters=None) -> StepResult:
     """One EXPRB32 step (Sec. 2.3): the Rosenbrock-Euler stage a, then the
     third-order correction 2 phi_3(hJ) h [N(a) - N(u)] with N(w) = F(w) - J w;
-    stages["error"] is the rms norm of the correction (the embedded estimate)."""
+    stages["error"] is the rms norm of the correction (the embedded estimate)
+    and stages["a"] the embedded second-order solution.  iters: [phi_1,
+    phi_3 action]; ``force_iters`` (the same layout) fixes the counts."""
     u = np.asarray(u, dtype=np.float64)
     J = lambda w: burgers_J(u, w, nu, dx, dy)
     F = lambda w: burgers_F(w, nu, dx, dy)
     hF = h * F(u)
-    r1 = leja_phi(J, hF, [(1, 1.0, 1.0)], h, c, gamma, rtol, atol, max_iters)
+    r1 = leja_phi(J, hF, [(1, 1.0, 1.0)], h, c, gamma, rtol, atol, max_iters, _forced(force_iters, 0))
     a = u + r1.p[0]
     Nl = lambda w: F(w) - J(w)
     R = h * (Nl(a) - Nl(u))
-    r2 = leja_phi(J, R, [(3, 1.0, 2.0)], h, c, gamma, rtol, atol, max_iters)
+    r2 = leja_phi(J, R, [(3, 1.0, 2.0)], h, c, gamma, rtol, atol, max_iters, _forced(force_iters, 1))
     corr = r2.p[0]
     status = r1.status if r1.status != "ok" else r2.status
     return StepResult(u_next=a + corr, iters=[r1.iters[0], r2.iters[0]], status=status,
@@ -260,20 +274,24 @@ def exprb32_step(u, nu, dx, dy, h, c, gamma, rtol, atol, max_iters=500) -> StepR
                               "error": float(np.linalg.norm(corr) / math.sqrt(corr.size))})
 
 
-def exprb42_step(u, nu, dx, dy, h, c, gamma, rtol, atol, max_iters=500) -> StepResult:
+def exprb42_step(u, nu, dx, dy, h, c, gamma, rtol, atol, max_iters=500, force_iters=None) -> StepResult:
     """One EXPRB42 step of u_t = F(u) (Burgers), Jacobian and remainder as in
-    Sec. 2.3; the phi actions use Newton-Leja interpolation."""
+    Sec. 2.3; the phi actions use Newton-Leja interpolation.  iters: [the
+    (3/4) phi_1((3/4) h J) output and the phi_1(h J) output of the first
+    pass (one basis, each with its own stop), the phi_3 action];
+    ``force_iters`` (the same layout) fixes the counts."""
     u = np.asarray(u, dtype=np.float64)
     J = lambda w: burgers_J(u, w, nu, dx, dy)
     F = lambda w: burgers_F(w, nu, dx, dy)
     hF = h * F(u)
-    r1 = leja_phi(J, hF, [(1, 0.75, 0.75), (1, 1.0, 1.0)], h, c, gamma, rtol, atol, max_iters)
+    f1 = None if force_iters is None else [_forced(force_iters, 0), _forced(force_iters, 1)]
+    r1 = leja_phi(J, hF, [(1, 0.75, 0.75), (1, 1.0, 1.0)], h, c, gamma, rtol, atol, max_iters, f1)
     a = r1.p[0]                       # (3/4) h phi_1((3/4) h J) F(u)
     U2 = u + a
     Nl = lambda w: F(w) - J(w)
     R = h * (Nl(U2) - Nl(u))
-    r2 = leja_phi(J, R, [(3, 1.0, 32.0 / 9.0)], h, c, gamma, rtol, atol, max_iters)
+    r2 = leja_phi(J, R, [(3, 1.0, 32.0 / 9.0)], h, c, gamma, rtol, atol, max_iters, _forced(force_iters, 2))
     u_next = u + r1.p[1] + r2.p[0]
     status = r1.status if r1.status != "ok" else r2.status
-    return StepResult(u_next=u_next, iters=[max(r1.iters), r2.iters[0]], status=status,
+    return StepResult(u_next=u_next, iters=[r1.iters[0], r1.iters[1], r2.iters[0]], status=status,
                       stages={"a": a, "phi1": r1.p[1], "R": R, "phi3": r2.p[0]})

@@ -78,3 +78,64 @@ def test_training_fits_a_linear_target():
     assert loss < 0.02 * l0
     Y, _ = forward(th, X)
     assert Y.shape == (512, 2)
+
+
+def test_adam_constant_gradient_gives_unbiased_moments_at_every_step():
+    """With the same gradient g at every step, the bias-corrected moments
+    equal g and g^2 exactly for every t (Kingma and Ba 2015, Sec. 3), so
+    every step moves by lr * g / (|g| + eps): a wrong decay rate or a
+    missing or misplaced bias correction in either moment breaks this at
+    t >= 2."""
+    rng = np.random.default_rng(11)
+    g = rng.standard_normal(N_PARAMS) * np.exp(rng.uniform(-3, 3, N_PARAMS))
+    th = _params(12)
+    m = np.zeros(N_PARAMS)
+    v = np.zeros(N_PARAMS)
+    lr = 2e-3
+    for t in range(1, 40):
+        new, m, v = adam_step(th, g, m, v, t, lr, beta1=0.8, beta2=0.99)
+        assert np.allclose(th - new, lr * g / (np.abs(g) + 1e-8), rtol=1e-10, atol=0.0), t
+        th = new
+
+
+def test_adam_moments_are_normalised_exponential_averages():
+    """After gradients g_1..g_t, the bias-corrected first moment is the
+    average of the g_i weighted by beta1^(t-i) and the second the average of
+    the g_i^2 weighted by beta2^(t-i) (the weights sum to
+    (1 - beta^t) / (1 - beta), which the correction divides out).  Checked
+    with exact rational weights on changing gradients for t = 1..6."""
+    from fractions import Fraction as Fr
+
+    b1, b2, lr = Fr(9, 10), Fr(999, 1000), 1e-2
+    gs = [Fr(3, 2), Fr(-1, 2), Fr(1, 4), Fr(2), Fr(-3), Fr(1, 8)]
+    th = np.array([0.5])
+    m = np.zeros(1)
+    v = np.zeros(1)
+    for t in range(1, len(gs) + 1):
+        new, m, v = adam_step(th, np.array([float(gs[t - 1])]), m, v, t, lr, beta1=float(b1), beta2=float(b2),
+                              eps=0.0)
+        w1 = [b1 ** (t - i) for i in range(1, t + 1)]
+        w2 = [b2 ** (t - i) for i in range(1, t + 1)]
+        mhat = sum(w * g for w, g in zip(w1, gs)) / sum(w1)
+        vhat = sum(w * g * g for w, g in zip(w2, gs)) / sum(w2)
+        expect = lr * float(mhat) / float(vhat) ** 0.5
+        assert abs((th - new)[0] - expect) <= 1e-12 * abs(expect), (t, (th - new)[0], expect)
+        th = new
+
+
+def test_adam_step_is_invariant_to_gradient_scale():
+    """With eps = 0 the update does not change when every gradient is
+    multiplied by the same positive constant (the second moment is of g^2
+    and enters through its square root)."""
+    rng = np.random.default_rng(13)
+    gs = rng.standard_normal((5, N_PARAMS))
+    runs = []
+    for s in (1.0, 1e-3, 37.0):
+        th = _params(14)
+        m = np.zeros(N_PARAMS)
+        v = np.zeros(N_PARAMS)
+        for t in range(1, 6):
+            th, m, v = adam_step(th, s * gs[t - 1], m, v, t, 1e-3, eps=0.0)
+        runs.append(th)
+    assert np.allclose(runs[0], runs[1], rtol=1e-12, atol=1e-15)
+    assert np.allclose(runs[0], runs[2], rtol=1e-12, atol=1e-15)
