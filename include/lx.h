@@ -234,17 +234,29 @@ typedef enum {
     LX_EXPRB42 = 42
 } lx_scheme;
 
-/* One step u -> d_u_out of u_t = F(u) for LX_OP_BURGERS2D.  c and gamma
- * describe the spectrum of J(d_u) (lx_spectrum with d_u).  iters: host [2]
- * or NULL, iterations of the first (phi_1) pass and of the phi_3 pass (0 for
- * LX_ROS_EULER).  d_u_out must differ from d_u.  Three workspace vectors of
- * the context's n_max are allocated on the first call.  Errors as
- * lx_phi_leja; LX_EINVAL for another operator or scheme, or LX_EXPRB42 on a
- * context with k_max < 2. */
+/* One step u -> d_u_out of u_t = F(u) for LX_OP_BURGERS2D (Sec. 2.3: the
+ * integrator entry point of the exponential Rosenbrock listings).  c and
+ * gamma describe the spectrum of J(d_u) (lx_spectrum with d_u).
+ *   d_u, d_u_out  device, nx*ny, caller-owned; d_u_out must differ from d_u.
+ *   d_u_low       device, nx*ny, or NULL.  LX_EXPRB32 only (the one scheme
+ *                 with an embedded method): receives the embedded
+ *                 second-order solution a = u + h phi_1(h J) F(u).  Must
+ *                 differ from d_u and d_u_out; LX_EINVAL for another scheme.
+ *   err           host, or NULL: LX_EXPRB32's embedded error estimate, the
+ *                 rms norm (l2 / sqrt(N)) of u+ - a (the EXPRB32 listing's
+ *                 `error`); 0 for the other schemes, which have none.
+ *   iters         host [3], or NULL: iterations of every phi action of the
+ *                 step in the order taken, each with its own stop rule:
+ *                 LX_ROS_EULER {phi_1, 0, 0}; LX_EXPRB32 {phi_1, phi_3, 0};
+ *                 LX_EXPRB42 {(3/4) phi_1((3/4) h J), phi_1(h J), phi_3}
+ *                 (the first two from one Newton basis).
+ * Three workspace vectors of the context's n_max are allocated on the first
+ * call.  Errors as lx_phi_leja; LX_EINVAL for another operator or scheme,
+ * or LX_EXPRB42 on a context with k_max < 2. */
 lx_status lx_exprb_step(lx_ctx* ctx, const lx_operator* op, int scheme,
-                        const double* d_u, double* d_u_out, double h,
-                        double c, double gamma, const lx_leja_opts* o,
-                        int* iters);
+                        const double* d_u, double* d_u_out, double* d_u_low,
+                        double* err, double h, double c, double gamma,
+                        const lx_leja_opts* o, int* iters);
 
 /* One step of the linear problem u_t = A u + S (Sec. 3, Problems I and
  * II) for LX_OP_DIFFADV2D or LX_OP_DIFFADV2D_UP3:

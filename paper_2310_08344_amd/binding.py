@@ -102,7 +102,7 @@ def _signatures(lib: C.CDLL) -> None:
                                 C.POINTER(_D), C.POINTER(_D), C.POINTER(_P), _D, _D, _D,
                                 C.POINTER(LejaOpts), C.POINTER(_I), C.POINTER(_D)]
     lib.lx_phi_leja.restype = _I
-    lib.lx_exprb_step.argtypes = [_P, C.POINTER(Operator), _I, _P, _P, _D, _D, _D,
+    lib.lx_exprb_step.argtypes = [_P, C.POINTER(Operator), _I, _P, _P, _P, C.POINTER(_D), _D, _D, _D,
                                   C.POINTER(LejaOpts), C.POINTER(_I)]
     lib.lx_exprb_step.restype = _I
     lib.lx_linear_step.argtypes = [_P, C.POINTER(Operator), _P, _P, _P, _D, _D, _D, C.POINTER(LejaOpts),
@@ -398,15 +398,22 @@ class Context:
         return Predictor(self, seed)
 
     def exprb_step(self, op: Operator, u, u_out, h, c, gamma, rtol=1e-8, atol=0.0, max_iters=500,
-                   fp32_switch=1e4, scheme=LX_EXPRB42, raise_on_error=True, substeps=0) -> PhiResult:
+                   fp32_switch=1e4, scheme=LX_EXPRB42, raise_on_error=True, substeps=0, u_low=None) -> PhiResult:
+        """lx_exprb_step.  iters: the step's phi actions in the order taken
+        (Ros-Euler [phi_1]; EXPRB32 [phi_1, phi_3]; EXPRB42 [(3/4) phi_1,
+        phi_1, phi_3]); err: [the embedded estimate] (EXPRB32; 0 otherwise);
+        u_low receives EXPRB32's embedded second-order solution."""
         opts = LejaOpts(float(rtol), float(atol), int(max_iters), float(fp32_switch), int(substeps))
-        it = (_I * 2)()
-        st = self.lib.c.lx_exprb_step(self._h, C.byref(op), int(scheme), _ptr(u), _ptr(u_out), float(h),
+        it = (_I * 3)()
+        e = _D(0.0)
+        st = self.lib.c.lx_exprb_step(self._h, C.byref(op), int(scheme), _ptr(u), _ptr(u_out),
+                                      _ptr(u_low) if u_low is not None else None, C.byref(e), float(h),
                                       float(c), float(gamma), C.byref(opts), it)
         if raise_on_error:
             self._check(st, allow=(LX_OK, LX_ENOTCONV))
         s = self.stats()
-        return PhiResult(st, list(it), s["err"][:2], s)
+        n = {LX_ROS_EULER: 1, LX_EXPRB32: 2}.get(int(scheme), 3)
+        return PhiResult(st, list(it)[:n], [e.value], s)
 
 
     def linear_step(self, op: Operator, u, u_out, h, c, gamma, source=None, rtol=1e-12, atol=0.0,

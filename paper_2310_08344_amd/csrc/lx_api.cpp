@@ -1276,7 +1276,8 @@ lx_status lx_linear_step(lx_ctx* ctx, const lx_operator* op, const double* d_u, 
 }
 
 lx_status lx_exprb_step(lx_ctx* ctx, const lx_operator* op, int scheme, const double* d_u, double* d_u_out,
-                        double h, double c, double gamma, const lx_leja_opts* o, int* iters) {
+                        double* d_u_low, double* err, double h, double c, double gamma, const lx_leja_opts* o,
+                        int* iters) {
     if (ctx == nullptr) return LX_EINVAL;
     ctx->stats = lx_stats{};
     lx_status s = check_op(ctx, op);
@@ -1286,6 +1287,10 @@ lx_status lx_exprb_step(lx_ctx* ctx, const lx_operator* op, int scheme, const do
         return fail(ctx, LX_EINVAL, "unknown scheme %d", scheme);
     if (d_u == nullptr || d_u_out == nullptr || d_u == d_u_out)
         return fail(ctx, LX_EINVAL, "d_u and d_u_out must be distinct, non-NULL");
+    if (d_u_low != nullptr && scheme != LX_EXPRB32)
+        return fail(ctx, LX_EINVAL, "d_u_low: only LX_EXPRB32 has an embedded lower-order solution");
+    if (d_u_low != nullptr && (d_u_low == d_u || d_u_low == d_u_out))
+        return fail(ctx, LX_EINVAL, "d_u_low must differ from d_u and d_u_out");
     if (scheme == LX_EXPRB42 && ctx->k_max < 2) return fail(ctx, LX_EINVAL, "EXPRB42 needs a context with k_max >= 2");
     s = check_shift(ctx, h, c, gamma);
     if (s != LX_OK) return s;
@@ -1329,7 +1334,7 @@ lx_status lx_exprb_step(lx_ctx* ctx, const lx_operator* op, int scheme, const do
     };
     LX_HIP(ctx, lx::launch_burgers_hF(d_u, hF, nx, ny, op->nu, op->dx, op->dy, h, ctx->stream));
     lx_stats acc{};
-    int it1 = 0, it2 = 0;
+    int it[3] = {0, 0, 0};   // every phi action of the step, in the order taken
     double e1 = 0.0, e2 = 0.0, step_err = 0.0;
     if (scheme == LX_ROS_EULER) {
         // u+ = u + phi_1(h J) h F(u)
@@ -1339,21 +1344,22 @@ lx_status lx_exprb_step(lx_ctx* ctx, const lx_operator* op, int scheme, const do
         s = pass(1, l, one, one, out, hF);
         if (s != LX_OK) return s;
         acc = ctx->stats;
-        it1 = acc.iters[0];
+        it[0] = acc.iters[0];
         e1 = acc.err[0];
         LX_HIP(ctx, lx::launch_combine(d_u, d_u_out, nullptr, d_u_out, N, ctx->stream));
     } else if (scheme == LX_EXPRB32) {
         // a = u + phi_1(h J) h F(u);  u+ = a + 2 phi_3(h J) h [N(a) - N(u)];
         // the embedded estimate is the rms norm of the correction
+        // (the embedded second-order solution a goes to d_u_low when given)
         double* p1 = ctx->ws[1];
-        double* a = ctx->ws[2];
+        double* a = d_u_low != nullptr ? d_u_low : ctx->ws[2];
         const int l1[1] = {1}, l3[1] = {3};
         const double one[1] = {1.0}, two[1] = {2.0};
         double* out1[1] = {p1};
         s = pass(1, l1, one, one, out1, hF);
         if (s != LX_OK) return s;
         acc = ctx->stats;
-        it1 = acc.iters[0];
+        it[0] = acc.iters[0];
         e1 = acc.err[0];
         LX_HIP(ctx, lx::launch_combine(d_u, p1, nullptr, a, N, ctx->stream));
         LX_HIP(ctx, lx::launch_burgers_remainder(d_u, p1, hF, nx, ny, op->nu, op->dx, op->dy, h, ctx->stream));
@@ -1361,7 +1367,7 @@ lx_status lx_exprb_step(lx_ctx* ctx, const lx_operator* op, int scheme, const do
         s = pass(1, l3, one, two, out2, hF);
         const lx_stats t = ctx->stats;
         merge(acc, t);
-        it2 = t.iters[0];
+        it[1] = t.iters[0];
         e2 = t.err[0];
         step_err = t.pnorm[0];
         if (s != LX_OK) {
@@ -1381,14 +1387,15 @@ lx_status lx_exprb_step(lx_ctx* ctx, const lx_operator* op, int scheme, const do
         s = pass(2, l1, alpha1, sigma1, out1, hF);
         if (s != LX_OK) return s;
         acc = ctx->stats;
-        it1 = std::max(acc.iters[0], acc.iters[1]);
+        it[0] = acc.iters[0];
+        it[1] = acc.iters[1];
         e1 = std::max(acc.err[0], acc.err[1]);
         LX_HIP(ctx, lx::launch_burgers_remainder(d_u, a, hF, nx, ny, op->nu, op->dx, op->dy, h, ctx->stream));
         double* out2[1] = {d_u_out};
         s = pass(1, l3, one, s3, out2, hF);
         const lx_stats t = ctx->stats;
         merge(acc, t);
-        it2 = t.iters[0];
+        it[2] = t.iters[0];
         e2 = t.err[0];
         if (s != LX_OK) {
             ctx->stats = acc;
@@ -1397,12 +1404,11 @@ lx_status lx_exprb_step(lx_ctx* ctx, const lx_operator* op, int scheme, const do
         LX_HIP(ctx, lx::launch_combine(d_u, p1, d_u_out, d_u_out, N, ctx->stream));
     }
     if (iters) {
-        iters[0] = it1;
-        iters[1] = it2;
+        for (int i = 0; i < 3; ++i) iters[i] = it[i];
     }
-    acc.iters[0] = it1;
-    acc.iters[1] = it2;
-    acc.iters[2] = acc.iters[3] = 0;
+    if (err) *err = step_err;
+    for (int i = 0; i < 3; ++i) acc.iters[i] = it[i];
+    acc.iters[3] = 0;
     acc.err[0] = e1;
     acc.err[1] = e2;
     acc.step_err = step_err;

@@ -58,3 +58,21 @@ def oracle_parity(gpu_outs, gpu_iters, run_oracle, tol):
     for e in errs:
         assert e <= tol, (errs, tol)
     return ref, errs, flipped
+
+
+def oracle_step_parity(gpu_out, gpu_iters, run_step, tol):
+    """Compares an integrator step with the oracle's.  Every phi action of
+    the step has its own stop rule; when a borderline decision went the
+    other way in one of them (counts differ by one), the oracle step is
+    rerun forced to the GPU's counts, action by action, and compared at the
+    same tolerance.  Returns (oracle step, relative error, flipped)."""
+    ref = run_step(None)
+    flipped = list(ref.iters) != list(gpu_iters)
+    if flipped:
+        assert all(abs(a - b) <= 1 for a, b in zip(ref.iters, gpu_iters)), (ref.iters, gpu_iters)
+        say("stop decision differs by one sweep; comparing at the GPU's counts", ref.iters, gpu_iters)
+        ref = run_step(list(gpu_iters))
+    assert ref.status == "ok", ref.status
+    err = rel(gpu_out, ref.u_next)
+    assert err <= tol, (err, tol)
+    return ref, err, flipped

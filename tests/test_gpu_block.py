@@ -17,7 +17,7 @@ from oracle.operators import burgers_J, diffadv_apply
 from oracle.phi_action import leja_phi, power_iteration
 from paper_2310_08344_amd import binding as B
 from paper_2310_08344_amd import workloads as W
-from tests.gpu_helpers import closed_form_shift, dev, diffadv_setup, host, oracle_parity, rel, say
+from tests.gpu_helpers import closed_form_shift, dev, diffadv_setup, host, oracle_parity, oracle_step_parity, rel, say
 
 pytestmark = pytest.mark.gpu
 
@@ -188,8 +188,8 @@ def test_integrator_steps_with_windows(ctx, scheme):
         ctx.set_depth(0)
     assert r.status == B.LX_OK and r.stats["depth"] == 4
     step = {"exprb42": exprb42_step, "exprb32": exprb32_step}[scheme]
-    ref = step(u0, nu, 1 / n, 1 / n, h, c, g, 1e-10, 0.0, 300)
-    assert rel(host(out), ref.u_next) <= 1e-9
+    oracle_step_parity(host(out), r.iters,
+                       lambda f: step(u0, nu, 1 / n, 1 / n, h, c, g, 1e-10, 0.0, 300, force_iters=f), PARITY)
 
 
 def test_windows_repeat_bitwise_and_other_operators_fall_back(ctx):

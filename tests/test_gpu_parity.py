@@ -16,7 +16,7 @@ from oracle.operators import burgers_J, diffadv_apply
 from oracle.phi_action import exprb32_step, exprb42_step, leja_phi, power_iteration, ros_euler_step
 from paper_2310_08344_amd import binding as B
 from paper_2310_08344_amd import workloads as W
-from tests.gpu_helpers import (closed_form_shift, dev, diffadv_setup, host, oracle_parity,
+from tests.gpu_helpers import (closed_form_shift, oracle_step_parity, dev, diffadv_setup, host, oracle_parity,
                                rel, say)
 
 pytestmark = pytest.mark.gpu
@@ -187,14 +187,9 @@ def test_exprb42_step_matches_oracle(ctx, n):
     out = dev(np.zeros_like(u0))
     r = ctx.exprb_step(op, dev(u0), out, p.h, c, g, rtol=1e-8, max_iters=200)
     assert r.status == B.LX_OK
-    ref = exprb42_step(u0, p.nu, p.dx, p.dy, p.h, c, g, 1e-8, 0.0, 200)
-    assert ref.status == "ok"
-    if list(ref.iters) == list(r.iters):
-        assert rel(host(out), ref.u_next) <= PARITY
-    else:
-        say("stop decision differs", ref.iters, r.iters)
-        # the step's update differs by at most tolerance-sized terms
-        assert rel(host(out) - u0, ref.u_next - u0) <= 1e-7
+    assert len(r.iters) == 3
+    oracle_step_parity(host(out), r.iters,
+                       lambda f: exprb42_step(u0, p.nu, p.dx, p.dy, p.h, c, g, 1e-8, 0.0, 200, force_iters=f), PARITY)
 
 
 STEPS = {"ros_euler": (B.LX_ROS_EULER, ros_euler_step), "exprb32": (B.LX_EXPRB32, exprb32_step),
@@ -223,16 +218,42 @@ def test_integrator_steps_match_oracle(ctx, scheme, n, depth):
     finally:
         ctx.set_depth(0)
     assert r.status == B.LX_OK and r.stats["depth"] == depth
-    ref = oracle_step(u0, nu, 1 / n, 1 / n, h, c, g, 1e-8, 0.0, 200)
-    assert ref.status == "ok"
-    if list(ref.iters) == list(r.iters):
-        assert rel(host(out), ref.u_next) <= PARITY
-        if scheme == "exprb32":
-            assert abs(r.stats["step_err"] - ref.stages["error"]) <= 1e-9 * ref.stages["error"]
+    ref, _, _ = oracle_step_parity(
+        host(out), r.iters, lambda f: oracle_step(u0, nu, 1 / n, 1 / n, h, c, g, 1e-8, 0.0, 200, force_iters=f),
+        PARITY)
+    if scheme == "exprb32":
+        # the embedded estimate, through the out-parameter and the stats
+        assert abs(r.err[0] - ref.stages["error"]) <= 1e-9 * ref.stages["error"]
+        assert r.stats["step_err"] == r.err[0]
     else:
-        say("stop decision differs", ref.iters, r.iters)
-        assert max(abs(a - b) for a, b in zip(ref.iters, r.iters)) <= 1
-        assert rel(host(out) - u0, ref.u_next - u0) <= 1e-7
+        assert r.err[0] == 0.0
+
+
+@pytest.mark.parametrize("n", [96, 130])
+def test_exprb32_embedded_solution_out_parameter(ctx, n):
+    """d_u_low receives the embedded second-order solution a = u + h phi_1(hJ)F(u)
+    and err its distance from u+ (rms), both against the oracle's step; the
+    other schemes reject d_u_low."""
+    u0 = W.fourier_modes(n, seed=5)
+    nu = float(np.max(np.abs(u0))) / n / 2.0
+    h = 10.0 * W.burgers_cfl_step(nu, float(np.max(np.abs(u0))), 1 / n, 1 / n)
+    op = B.make_operator(kind=B.LX_OP_BURGERS2D, n=n, nu=nu)
+    say("exprb32 embedded", n)
+    rho, c, g = ctx.spectrum(op, u=dev(u0), x0=dev(W.start_vector(n)), iters=20)
+    out, low = dev(np.zeros_like(u0)), dev(np.zeros_like(u0))
+    r = ctx.exprb_step(op, dev(u0), out, h, c, g, rtol=1e-8, max_iters=200, scheme=B.LX_EXPRB32, u_low=low)
+    assert r.status == B.LX_OK
+    ref, _, _ = oracle_step_parity(
+        host(out), r.iters, lambda f: exprb32_step(u0, nu, 1 / n, 1 / n, h, c, g, 1e-8, 0.0, 200, force_iters=f),
+        PARITY)
+    assert rel(host(low), ref.stages["a"]) <= PARITY
+    assert abs(r.err[0] - ref.stages["error"]) <= 1e-9 * ref.stages["error"]
+    assert abs(r.err[0] - float(np.linalg.norm(host(out) - host(low))) / n) <= 1e-9 * r.err[0]
+    for code in (B.LX_EXPRB42, B.LX_ROS_EULER):
+        assert ctx.exprb_step(op, dev(u0), out, h, c, g, scheme=code, u_low=low,
+                              raise_on_error=False).status == B.LX_EINVAL
+    assert ctx.exprb_step(op, dev(u0), out, h, c, g, scheme=B.LX_EXPRB32, u_low=out,
+                          raise_on_error=False).status == B.LX_EINVAL
 
 
 # ---------------------------------------------------------------------------
@@ -490,13 +511,8 @@ def test_two_iteration_exprb42_matches_one_iteration(ctx):
             ctx.set_depth(0)
         assert r.status == B.LX_OK and r.stats["depth"] == depth
         outs[depth] = (host(o), r.iters)
-    ref = exprb42_step(u0, nu, 1 / n, 1 / n, h, c, g, 1e-8, 0.0, 300)
-    assert ref.status == "ok"
-    if list(ref.iters) == list(outs[2][1]):
-        assert rel(outs[2][0], ref.u_next) <= PARITY
-    else:
-        say("stop decision differs", ref.iters, outs[2][1])
-        assert rel(outs[2][0] - u0, ref.u_next - u0) <= 1e-7
+    oracle_step_parity(outs[2][0], outs[2][1],
+                       lambda f: exprb42_step(u0, nu, 1 / n, 1 / n, h, c, g, 1e-8, 0.0, 300, force_iters=f), PARITY)
     if outs[2][1] == outs[1][1]:
         assert rel(outs[2][0] - u0, outs[1][0] - u0) <= 1e-12
 
