@@ -29,8 +29,10 @@ Prints one JSON line on stdout:
                 8192^2 for h = 1, 10, 100 x CFL to the paper's final times,
                 with the algorithmic bandwidth over the whole time loop as a
                 fraction of the practical peak measured in the same run
-  cpu_baseline  the CPU oracle on a bounded sample (the same solve on a
-                2048^2 grid of the same family, scaled by the point ratio 4)
+  cpu_baseline  the CPU oracle on a bounded sample of the same 4096^2 solve
+                (a few power sweeps, the full planner, the Leja loop forced
+                to a few iterations with three outputs and with one), scaled
+                to the GPU run's iteration counts; one thread and all cores
 
 Usage: python bench.py [--steps K] [--warmup W] [--no-tune] [--no-batched] [--no-paper] [--no-cpu-baseline]
 """
@@ -41,6 +43,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -69,31 +73,127 @@ def committed_traffic(launch_bytes: float):
             round(t["hbm_bytes_per_launch"] / launch_bytes, 4) if launch_bytes else None}
 
 
-def cpu_baseline(sample_n: int = 2048) -> dict:
-    """The oracle as it stands, on one thread, on the sample workload."""
+def cpu_baseline(n: int, gpu_iters, power_iters: int = 20, power_sample: int = 4, leja_sample: int = 8) -> dict:
+    """The oracle as it stands, timed on this host at the benchmarked grid
+    (n^2, the same seeded v and operator), once on one thread and once with
+    every visible core allowed to its thread pools.
+
+    Bounded sample: power_sample power sweeps, the planner for the full
+    run's 301 coefficients per output, and two runs of the Leja loop forced
+    to leja_sample iterations, one with all three outputs taking terms and
+    one with only phi_1 (phi_2 and phi_3 stop after their first term).  Per
+    iteration the loop then costs a + b k with k outputs taking terms; the
+    full solve is power_iters sweeps + the planner + the sum over the GPU
+    run's iterations of a + b k(m) (k(m) from its per-output counts)."""
     from threadpoolctl import threadpool_limits
 
+    from oracle.leja import leja_points, newton_coeffs
     from oracle.operators import make_apply
     from oracle.phi_action import leja_phi, power_iteration, shift_scale
     from paper_2310_08344_amd import workloads as W
 
-    p, v = W.config2(n=sample_n, seed=2)
+    p, v = W.config2(n=n)
     x0 = W.start_vector(p.n)
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        A = make_apply(p)
-        rho, _ = power_iteration(A, x0, 20)
-        c, g = shift_scale(rho)
-        r = leja_phi(A, v, [(1, 1.0, 1.0), (2, 1.0, 1.0), (3, 1.0, 1.0)], p.h, c, g, 1e-8, 0.0, 300)
-        t = time.perf_counter() - t0
-    scale = (4096 * 4096) / float(p.N)
-    return {"value": 3.0 / (t * scale), "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"phi_1..phi_3 solve incl. power iteration at {sample_n}^2 "
-                      f"({t:.1f} s on 1 thread, sweeps {r.iters}), time scaled by the point ratio "
-                      f"{scale:.0f} to 4096^2"}
+    A = make_apply(p)
+    outs = [(1, 1.0, 1.0), (2, 1.0, 1.0), (3, 1.0, 1.0)]
+    max_iters = 300
+    cores = len(os.sched_getaffinity(0))
+    leja_points(max_iters + 1)   # the Leja table, built once (as the library does per context)
+
+    def sample(threads):
+        with threadpool_limits(limits=threads):
+            t0 = time.perf_counter()
+            rho, _ = power_iteration(A, x0, power_sample)
+            t_pw = (time.perf_counter() - t0) / power_sample
+            c, g = shift_scale(rho)
+            t0 = time.perf_counter()
+            for (l, a, sg) in outs:
+                newton_coeffs(l, p.h, c, g, max_iters + 1, alpha=a, sigma=sg)
+            t_plan = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            leja_phi(A, v, outs, p.h, c, g, 1e-8, 0.0, max_iters, force_iters=[leja_sample] * 3)
+            t3 = time.perf_counter() - t0 - t_plan
+            t0 = time.perf_counter()
+            leja_phi(A, v, outs, p.h, c, g, 1e-8, 0.0, max_iters, force_iters=[leja_sample, 1, 1])
+            t1 = time.perf_counter() - t0 - t_plan
+        b = max(0.0, (t3 - t1) / (2.0 * (leja_sample - 1)))
+        a = max(0.0, t3 / leja_sample - 3.0 * b)
+        loop = sum(a + b * sum(1 for it in gpu_iters if m < it) for m in range(max(gpu_iters)))
+        total = power_iters * t_pw + t_plan + loop
+        return {"seconds_per_solve_set": round(total, 3), "power_sweep_s": round(t_pw, 4),
+                "planner_s": round(t_plan, 3), "iteration_s_base_per_output": [round(a, 4), round(b, 4)]}
+
+    one = sample(1)
+    allc = sample(cores)
+    return {"value": round(3.0 / one["seconds_per_solve_set"], 4), "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": (f"the oracle on this workload at {n}^2 (same operator and seeded v): {power_sample} power "
+                       f"sweeps, the planner for 301 coefficients per output, and the Leja loop forced to "
+                       f"{leja_sample} iterations with three outputs and with one; scaled to {power_iters} power "
+                       f"sweeps and the GPU run's iteration counts {list(gpu_iters)} (no grid scaling)"),
+            "one_thread": one,
+            "all_cores": dict(allc, threads_allowed=cores,
+                              value=round(3.0 / allc["seconds_per_solve_set"], 4),
+                              note="numpy runs the oracle's elementwise stencil arithmetic on one thread; only "
+                                   "library calls (norms) may use the wider pool")}
 
 
-def bench_batched(lib, repeats: int = 3) -> dict:
+def bench_small_configs(lib, repeats: int = 20, warmups: int = 3) -> dict:
+    """The two other single-instance workloads, time to solution (power
+    iteration 20 sweeps + planner + Leja loop), median of `repeats` after
+    `warmups`: exp(hA)u on the 64^2 Gaussian workload at rtol 1e-10 (1 solve
+    per step) and phi_1..phi_3 of a seeded N(0,1) v on 1024^2 at rtol 1e-8
+    (3 solves per step; launch shapes tuned first).  Both working sets fit
+    in the 256 MB Infinity Cache, so `effective_gbs` (algorithmic bytes of
+    the power and Leja launches over the step's time) is not an HBM rate."""
+    import torch
+
+    from paper_2310_08344_amd import binding as B
+    from paper_2310_08344_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    res = {}
+    for name, (p, v_h), ls, rtol in (("c1_64_exp", W.config1(), [0], 1e-10),
+                                     ("c2_1024_phi123", W.config2(n=1024), [1, 2, 3], 1e-8)):
+        ctx = lib.context(n_max=p.N, k_max=len(ls))
+        try:
+            op = B.make_operator(p)
+            if len(ls) > 1:
+                ctx.tune(op, K=len(ls), sweeps=8)
+            v = torch.as_tensor(v_h).to(dev)
+            x0 = torch.as_tensor(W.start_vector(p.n)).to(dev)
+            outs = [torch.empty_like(v) for _ in ls]
+            stats = []
+
+            def step():
+                _, c, g = ctx.spectrum(op, x0=x0, iters=20)
+                sp = ctx.stats()
+                r = ctx.phi_leja(op, v, outs, ls, p.h, c, g, rtol=rtol, max_iters=300)
+                if r.status != B.LX_OK:
+                    raise RuntimeError(f"phi_leja status {r.status}: {ctx.last_error()}")
+                stats.append((sp["bytes"], r.stats["bytes"], r.iters))
+
+            for _ in range(warmups):
+                step()
+            ts = []
+            for _ in range(repeats):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                step()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            t = float(np.median(ts))
+            pb, lb, its = stats[-1]
+            res[name] = {"grid": p.n, "rtol": rtol, "outputs": len(ls), "solves_per_s": round(len(ls) / t, 1),
+                         "ms_per_step": round(t * 1e3, 4), "sweeps": list(its)[:len(ls)],
+                         "effective_gbs": round((pb + lb) / t / 1e9, 1),
+                         "timing": f"median of {repeats} after {warmups} warm-ups, wall time of the whole step"}
+            log(name, res[name])
+        finally:
+            ctx.close()
+    return res
+
+
+def bench_batched(lib, repeats: int = 10, warmups: int = 3) -> dict:
     """256 uneven diffusion-advection instances (sides 64..512), exp action
     at rtol 1e-8 with 20 power-iteration sweeps each: one batched call
     against the plain path (lx_spectrum + lx_phi_leja per instance)."""
@@ -121,19 +221,22 @@ def bench_batched(lib, repeats: int = 3) -> dict:
             raise RuntimeError(f"batched status {st}")
         return res
 
-    plain()
-    res = batched()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(repeats):
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
+
+    for _ in range(warmups):
         plain()
-    torch.cuda.synchronize()
-    t_plain = (time.perf_counter() - t0) / repeats
-    t0 = time.perf_counter()
+        res = batched()
+    tp, tb = [], []
     for _ in range(repeats):
-        batched()
-    torch.cuda.synchronize()
-    t_batch = (time.perf_counter() - t0) / repeats
+        tp.append(timed(plain)[1])
+        res, t = timed(batched)
+        tb.append(t)
+    t_plain, t_batch = float(np.median(tp)), float(np.median(tb))
     ctx.close()
     iters = sorted(r["iters"] for r in res)
     return {"workload": "256 diffusion-advection instances, sides uniform in {64,128,256,512}, D ~ LogU(0.1,10), "
@@ -143,6 +246,8 @@ def bench_batched(lib, repeats: int = 3) -> dict:
             "plain_solves_per_s": round(len(items) / t_plain, 1),
             "batched_ms": round(t_batch * 1e3, 3), "plain_ms": round(t_plain * 1e3, 3),
             "speedup_batched_vs_plain": round(t_plain / t_batch, 2),
+            "timing": f"median of {repeats} after {warmups} warm-ups, each path timed whole (power iteration, "
+                      "planner and Leja loop)",
             "sweeps_min_median_max": [iters[0], iters[len(iters) // 2], iters[-1]]}
 
 
@@ -391,7 +496,9 @@ def main() -> int:
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic["bytes_per_launch"] if traffic else None,
-            "kernel": ({2: "leja_pair (diffusion-advection, K=3, FP64, two iterations per launch)",
+            "kernel": (f"leja_stream (diffusion-advection, K=3, FP64, register-marching windows of {depth} "
+                       "iterations)" if last["marching"] else
+                       {2: "leja_pair (diffusion-advection, K=3, FP64, two iterations per launch)",
                         3: "leja_block (diffusion-advection, K=3, FP64, windows of three iterations)",
                         4: "leja_block (diffusion-advection, K=3, FP64, windows of four iterations)",
                         6: "leja_block (diffusion-advection, K=3, FP64, windows of six iterations)"}.get(
@@ -429,6 +536,8 @@ def main() -> int:
     }
     out.update({k: v for k, v in extra.items() if v is not None})
     ctx.close()
+    log("64^2 exp and 1024^2 phi_1..phi_3 workloads")
+    out["small_configs"] = bench_small_configs(lib)
     if not args.no_batched:
         log("batched 256-instance comparison")
         out["batched_256"] = bench_batched(lib)
@@ -446,7 +555,7 @@ def main() -> int:
                                                            tune=not args.no_tune, runs=PAPER_RUNS_16384)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(p.n, last["iters"][:3])
     print(json.dumps(out), flush=True)
     return 0
 

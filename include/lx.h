@@ -132,6 +132,8 @@ typedef struct {
                                (lx_spectrum: power sweeps per launch)        */
     double step_err;        /* lx_exprb_step with LX_EXPRB32: embedded error  */
     int substeps;           /* substeps taken (lx_leja_opts.substeps)         */
+    int marching;           /* 1: the windows (lx_spectrum: the power sweeps)
+                               ran by register marching, 0 otherwise         */
 } lx_stats;
 
 /* ---- context ---------------------------------------------------------- */

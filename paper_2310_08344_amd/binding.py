@@ -49,7 +49,7 @@ class Stats(C.Structure):
                 ("pnorm", C.c_double * LX_K_MAX), ("rho_hat", C.c_double),
                 ("plan_ms", C.c_double), ("loop_ms", C.c_double), ("sweep_ms", C.c_double),
                 ("first_sweep_ms", C.c_double), ("bytes", C.c_double), ("n_launch", C.c_int),
-                ("depth", C.c_int), ("step_err", C.c_double), ("substeps", C.c_int)]
+                ("depth", C.c_int), ("step_err", C.c_double), ("substeps", C.c_int), ("marching", C.c_int)]
 
     def as_dict(self) -> dict:
         return {"status": self.status, "n_apply": self.n_apply, "n_fp32": self.n_fp32,
@@ -57,7 +57,7 @@ class Stats(C.Structure):
                 "rho_hat": self.rho_hat, "plan_ms": self.plan_ms, "loop_ms": self.loop_ms,
                 "sweep_ms": self.sweep_ms, "first_sweep_ms": self.first_sweep_ms,
                 "bytes": self.bytes, "n_launch": self.n_launch, "depth": self.depth,
-                "step_err": self.step_err, "substeps": self.substeps}
+                "step_err": self.step_err, "substeps": self.substeps, "marching": self.marching}
 
 
 class Instance(C.Structure):

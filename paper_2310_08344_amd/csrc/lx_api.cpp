@@ -573,6 +573,7 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
         }
     }
     S.depth = per;
+    S.marching = t.stream ? 1 : 0;
     S.bytes = bytes;
     S.plan_ms = plan_ms;
     if (ctx->timing && S.n_launch > 0) {
@@ -680,6 +681,7 @@ lx_status run_leja_sub(lx_ctx* ctx, const LejaCall& q) {
         acc.sweep_ms += t.sweep_ms;
         acc.bytes += t.bytes;
         acc.depth = t.depth;
+        acc.marching = t.marching;
         if (st == LX_ENOTCONV) {
             worst = LX_ENOTCONV;
             return LX_OK;
@@ -838,6 +840,7 @@ lx_status spectrum_stream(lx_ctx* ctx, const lx_operator& op, const double* x0, 
     S.n_apply = iters;
     S.n_launch = nblk;
     S.depth = per;
+    S.marching = 1;
     S.rho_hat = rho;
     S.bytes = 16.0 * static_cast<double>(N) * nblk;
     if (ctx->timing) {
@@ -1331,6 +1334,7 @@ lx_status lx_exprb_step(lx_ctx* ctx, const lx_operator* op, int scheme, const do
         acc.sweep_ms += t.sweep_ms;
         acc.bytes += t.bytes;
         acc.depth = t.depth;
+        acc.marching = t.marching;
     };
     LX_HIP(ctx, lx::launch_burgers_hF(d_u, hF, nx, ny, op->nu, op->dx, op->dy, h, ctx->stream));
     lx_stats acc{};

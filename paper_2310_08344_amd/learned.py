@@ -225,7 +225,7 @@ def solve_plain_single(ctx, args):
     return res
 
 
-def evaluate(ctx, predictor, margins, count=1024, seed0=SEED_EVALUATION, size=256, repeats=3, pool=None):
+def evaluate(ctx, predictor, margins, count=1024, seed0=SEED_EVALUATION, size=256, repeats=10, warmups=3, pool=None):
     """Time-to-solution of the learned + batched path against the plain
     batched path and the plain single-instance path on `count` instances
     (half diffusion-advection, half Burgers) at size^2, inputs resident on
@@ -249,29 +249,38 @@ def evaluate(ctx, predictor, margins, count=1024, seed0=SEED_EVALUATION, size=25
 
     # descriptors are built once per instance set, for both paths
     pb, lb = ctx.prepare(pargs), ctx.prepare(args)
-    solve_plain(ctx, pb)                          # warm-up
-    solve_learned(ctx, predictor, lb, *margins)
-    t_plain = t_learn = 1e300
+    for _ in range(warmups):
+        solve_plain(ctx, pb)
+        solve_learned(ctx, predictor, lb, *margins)
+    tp, tl = [], []
     for _ in range(repeats):
         res_p, t = timed(lambda: solve_plain(ctx, pb))
-        t_plain = min(t_plain, t)
+        tp.append(t)
         (res_l, fb), t = timed(lambda: solve_learned(ctx, predictor, lb, *margins))
-        t_learn = min(t_learn, t)
+        tl.append(t)
+    t_plain, t_learn = float(np.median(tp)), float(np.median(tl))
     res_s, t_single = timed(lambda: solve_plain_single(ctx, sargs))
     ok_p = [r["status"] == B.LX_OK for r in res_p]
-    diffs = []
-    for a, o, okp in zip(args, outs_plain, ok_p):
+    diffs, idx = [], []
+    for i, (a, o, okp) in enumerate(zip(args, outs_plain, ok_p)):
         if okp:
             d = torch.linalg.vector_norm(a["out"] - o) / torch.clamp(torch.linalg.vector_norm(o), min=1e-300)
             diffs.append(float(d))
+            idx.append(i)
+    order = np.argsort(diffs)[::-1][:3] if diffs else []
+    largest = [{"index": int(idx[j]), "seed": int(seed0 + idx[j]), "kind": items[idx[j]][0].kind,
+                "l": int(items[idx[j]][0].meta["l"]), "rel_diff": diffs[j],
+                "sweeps_learned_plain": [int(res_l[idx[j]]["iters"]), int(res_p[idx[j]]["iters"])],
+                "fallback": bool(res_l[idx[j]]["fallback"])} for j in order]
     sweeps_p = sum(r["iters"] for r in res_p) + POWER_ITERS * count
     sweeps_l = sum(r["iters"] for r in res_l) + POWER_ITERS * len(fb)
     kinds = np.array([0 if p.kind == W.DIFFADV else 1 for p, _, _ in items])
     fb_kinds = kinds[fb] if fb else np.array([], dtype=int)
     return {
         "instances": count, "grid": size, "rtol": RTOL,
-        "timing": f"best of {repeats} (plain and learned batched); inputs resident on the GPU and instance "
-                  "descriptors prepared once for either path",
+        "timing": f"median of {repeats} after {warmups} warm-ups (plain and learned batched, alternating); one "
+                  "run of the per-instance path; inputs resident on the GPU and instance descriptors prepared "
+                  "once for either path",
         "plain_batched_ms": round(t_plain * 1e3, 3), "learned_batched_ms": round(t_learn * 1e3, 3),
         "plain_single_ms": round(t_single * 1e3, 3),
         "speedup_learned_vs_plain_batched": round(t_plain / t_learn, 3),
@@ -284,6 +293,7 @@ def evaluate(ctx, predictor, margins, count=1024, seed0=SEED_EVALUATION, size=25
         "sweeps_plain_incl_power": int(sweeps_p), "sweeps_learned_incl_fallback_power": int(sweeps_l),
         "max_rel_diff_learned_vs_plain": max(diffs) if diffs else None,
         "median_rel_diff_learned_vs_plain": float(np.median(diffs)) if diffs else None,
+        "largest_rel_diffs": largest,
     }
 
 

@@ -97,3 +97,67 @@ def test_committed_predictor_saves_sweeps(ctx):
     assert sweeps_l < sweeps_p
     for a, o in zip(args, plain_out):
         assert rel(host(a["out"]), host(o)) <= 1e-6
+
+
+def _oracle_apply(prm, u):
+    from oracle.operators import make_apply
+    return make_apply(prm, u)
+
+
+def _exact(prm, u, v, l, A):
+    """phi_l(hA)v without the library: the Fourier solution for
+    diffusion-advection; for the Burgers Jacobian (not diagonalised by the
+    FFT) the oracle's own Leja loop at rtol 1e-13 with the closed-form
+    Gershgorin interval, which lies outside every eigenvalue."""
+    from oracle.exact import phi_fft
+    from oracle.phi_action import leja_phi, shift_scale
+    from paper_2310_08344_amd import workloads as W
+    if prm.kind == W.DIFFADV:
+        return phi_fft(v, l, prm.h, prm.D, prm.vx, prm.vy, prm.dx, prm.dy)
+    umax = float(np.max(np.abs(u)))
+    rho = 2.0 / W.burgers_cfl_step(prm.nu, umax, prm.dx, prm.dy)
+    c, g = shift_scale(rho)
+    r = leja_phi(A, v, [(l, 1.0, 1.0)], prm.h, c, g, 1e-13, 0.0, 600)
+    assert r.status == "ok"
+    return r.p[0]
+
+
+@pytest.mark.skipif(not os.path.exists(L.PREDICTOR_FILE), reason="no committed predictor")
+@pytest.mark.parametrize("size,seed0", [(64, 720000), (128, 730000)])
+def test_learned_solves_match_oracle_and_exact_solution(ctx, size, seed0):
+    """Every instance of a learned batch (the committed predictor; half
+    diffusion-advection, half Burgers), accepted or fallen back, against
+    (1) the oracle's Leja loop run with the shift and scale the GPU used and
+    its own stop rule at the same tolerance, at 1e-10 (a flipped borderline
+    stop is compared at the GPU's count); (2) the exact phi_l(hA)v at ten
+    times the tolerance (the reading for several correct results); and the
+    plain batched method's solve of the same instance against the same
+    exact solution."""
+    import torch
+
+    from oracle.phi_action import leja_phi
+    from tests.gpu_helpers import oracle_parity
+    p, margins, meta = L.load_predictor(ctx)
+    items = _items(12, seed0, sizes=(size,))
+    args, keep = L._instance_args(items, "cuda:0")
+    plain_out = [torch.empty_like(a["out"]) for a in args]
+    say("learned vs oracle and exact", size, seed0)
+    res_l, fb = L.solve_learned(ctx, p, args, *margins)
+    res_p = L.solve_plain(ctx, [dict(a, out=o) for a, o in zip(args, plain_out)])
+    worst = [0.0, 0.0, 0.0]
+    for i, ((prm, u, v), a, rl, rp, op_) in enumerate(zip(items, args, res_l, res_p, plain_out)):
+        assert rl["status"] == B.LX_OK and rp["status"] == B.LX_OK, (i, rl, rp)
+        l = prm.meta["l"]
+        A = _oracle_apply(prm, u)
+        got = host(a["out"])
+        mi = rl["iters"] + 8
+        _, errs, flipped = oracle_parity(
+            [got], [rl["iters"]],
+            lambda f: leja_phi(A, v, [(l, 1.0, 1.0)], prm.h, rl["c"], rl["gamma"], L.RTOL, 0.0, mi, f), 1e-10)
+        ex = _exact(prm, u, v, l, A)
+        e_l, e_p = rel(got, ex), rel(host(op_), ex)
+        say(f"instance {i} ({prm.kind}, l={l}, fallback={rl['fallback']}): oracle {errs[0]:.2e}, "
+            f"exact learned {e_l:.2e} plain {e_p:.2e}, sweeps learned {rl['iters']} plain {rp['iters']}")
+        worst = [max(worst[0], errs[0]), max(worst[1], e_l), max(worst[2], e_p)]
+        assert e_l <= 10 * L.RTOL and e_p <= 10 * L.RTOL, (i, e_l, e_p)
+    say("worst: oracle parity", worst[0], "exact learned", worst[1], "exact plain", worst[2])

@@ -71,6 +71,24 @@ def test_leja_matches_dense_expm_burgers_jacobian(l, alpha):
     assert _rel(res.p[0].ravel(), ref) <= 1e-9
 
 
+@pytest.mark.parametrize("index", [1, 13, 21])
+def test_tight_leja_on_learned_burgers_instances_matches_dense_expm(index):
+    """The reference the learned-path tests use for Burgers instances (the
+    Jacobian is not diagonalised by the FFT): the oracle's loop at rtol 1e-13
+    on the closed-form Gershgorin interval, checked here against the dense
+    augmented exponential on 24^2 instances of the learned distribution
+    (phi_2; cell Peclet numbers 0.3 to 3.4; h from 3.3 to 6.4 x CFL)."""
+    prm, u, v = W.learned_instance(index, 720000, (24,))
+    A = make_apply(prm, u)
+    l = prm.meta["l"]
+    rho = 2.0 / W.burgers_cfl_step(prm.nu, float(np.max(np.abs(u))), prm.dx, prm.dy)
+    c, g = shift_scale(rho)
+    r = leja_phi(A, v, [(l, 1.0, 1.0)], prm.h, c, g, 1e-13, 0.0, 400)
+    assert r.status == "ok"
+    ex = phi_dense(dense_matrix(A, 24, 24), v, l, prm.h).reshape(24, 24)
+    assert _rel(r.p[0], ex) <= 1e-12
+
+
 def test_leja_matches_fft_on_64_squared_exp_workload():
     p, u0 = W.config1()
     A_apply = make_apply(p)
