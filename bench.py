@@ -228,6 +228,11 @@ def bench_batched(lib, repeats: int = 10, warmups: int = 3) -> dict:
         torch.cuda.synchronize()
         return r, time.perf_counter() - t0
 
+    # the batch's launch shape from the autotuner (this batch class: 256
+    # diffusion-advection instances with sides 64..512)
+    tuned = ctx.tune_batched(args, power_iters=20, rtol=1e-8, max_iters=300, repeats=3)
+    best = min(tuned, key=lambda r: r[3])
+    log("batch tuner:", " ".join(f"{d}/{th}/{ppw}:{ms:.2f}" for d, th, ppw, ms in tuned))
     for _ in range(warmups):
         plain()
         res = batched()
@@ -237,6 +242,7 @@ def bench_batched(lib, repeats: int = 10, warmups: int = 3) -> dict:
         res, t = timed(batched)
         tb.append(t)
     t_plain, t_batch = float(np.median(tp)), float(np.median(tb))
+    st = ctx.stats()
     ctx.close()
     iters = sorted(r["iters"] for r in res)
     return {"workload": "256 diffusion-advection instances, sides uniform in {64,128,256,512}, D ~ LogU(0.1,10), "
@@ -248,6 +254,15 @@ def bench_batched(lib, repeats: int = 10, warmups: int = 3) -> dict:
             "speedup_batched_vs_plain": round(t_plain / t_batch, 2),
             "timing": f"median of {repeats} after {warmups} warm-ups, each path timed whole (power iteration, "
                       "planner and Leja loop)",
+            "tuned_shape": {"iterations_per_launch": best[0], "tile_rows": best[1], "points_per_workgroup": best[2],
+                            "tuner_median_ms": best[3], "candidates": len(tuned)},
+            "captured_graph_replayed": bool(st["batch_graph"]),
+            "roofline": {"bound": "hbm", "achieved": round(st["bytes"] / t_batch / 1e9, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(st["bytes"] / t_batch / 1e9 / HBM_PEAK_GBS, 4),
+                         "bytes_per_call": st["bytes"],
+                         "note": "algorithmic bytes of the whole batched call (power sweeps 16 B/pt each, windows "
+                                 "as the single-instance kernel) over its median wall time, planner and host "
+                                 "polling included; the per-kernel rates are in the committed profiles"},
             "sweeps_min_median_max": [iters[0], iters[len(iters) // 2], iters[-1]]}
 
 

@@ -134,6 +134,8 @@ typedef struct {
     int substeps;           /* substeps taken (lx_leja_opts.substeps)         */
     int marching;           /* 1: the windows (lx_spectrum: the power sweeps)
                                ran by register marching, 0 otherwise         */
+    int batch_graph;        /* lx_phi_leja_batched: 1 when the call replayed a
+                               captured pipeline (lx_set_batch_graphs)       */
 } lx_stats;
 
 /* ---- context ---------------------------------------------------------- */
@@ -306,9 +308,20 @@ typedef struct {
     int fallback;           /* lx_phi_leja_learned: solved again by the plain method */
 } lx_instance_result;
 
-/* Computes every instance of a batch with one launch per sweep for the whole
- * batch: all instances advance together, each with its own stop decision
- * and budget, and finished instances cost nothing more.  With
+/* Computes every instance of a batch with one launch per window of
+ * iterations (or per one or two iterations) for the whole batch: all
+ * instances advance together, each with its own stop decision and budget
+ * (Sec. 2.2), and finished instances cost nothing more.  Launch shape: the
+ * one lx_tune_batched or lx_set_batch_shape chose for the batch's class,
+ * else windows of four when every side allows them (8-row tiles with a
+ * Burgers instance, 16 otherwise; 16384 points per workgroup), else two
+ * iterations per launch, else one.  The device pipeline (power iteration,
+ * coefficients, windows) of a layout is captured in a hipGraph after its
+ * first call and replayed by later calls with the same layout (the same
+ * instance count, sizes, shape and workspaces), with as many window
+ * launches as the last call needed; a replay that needs more goes on with
+ * launches from the host, one look at the device per chunk
+ * (lx_set_batch_graphs; not with timing on).  With
  * power_iters > 0, each instance's spectral bound first comes from
  * power_iters power-iteration sweeps, and c, gamma follow from safety as in
  * lx_spectrum (Listing 7); otherwise the instances' c and gamma are used.
@@ -321,6 +334,31 @@ typedef struct {
  * (naming the instance), LX_ENOMEM when workspaces cannot grow. */
 lx_status lx_phi_leja_batched(lx_ctx* ctx, int n, const lx_instance* inst, int power_iters, double safety,
                               const lx_leja_opts* o, lx_instance_result* res);
+
+/* The autotuner of batch launch shapes (not in the paper).  Runs the batch
+ * itself (every instance's d_out is written) 1 + repeats times under each
+ * candidate: windows of four, two and one iterations per launch x tile rows
+ * 8, 16 (windows with a Burgers instance: 8) x 4096, 8192, 16384, 32768
+ * points per workgroup; keeps the shape with the lowest median wall time
+ * for the batch's class (whether any instance is a Burgers Jacobian, and
+ * the set of distinct grid sides) in the context, appended to the file
+ * LX_TUNE_CACHE names when set.  report: host text, or NULL: one line per
+ * candidate, "depth th points_per_workgroup median_ms".  repeats: 1..50.
+ * Errors as lx_phi_leja_batched (the shape is then not kept). */
+lx_status lx_tune_batched(lx_ctx* ctx, int n, const lx_instance* inst, int power_iters, double safety,
+                          const lx_leja_opts* o, int repeats, char* report, size_t report_len);
+
+/* Sets the launch shape of the class of this batch (see lx_tune_batched):
+ * depth 0 (the default rule), 1, 2 or 4; th 0 (default), 8 or 16; ppw 0
+ * (default) or the points per workgroup, at most 2^22.  All three 0
+ * forgets the class's shape.  Sides too short for windows, odd sides or
+ * unaligned vectors still take fewer iterations per launch; windows with a
+ * Burgers instance still take 8-row tiles.  Errors: LX_EINVAL. */
+lx_status lx_set_batch_shape(lx_ctx* ctx, int n, const lx_instance* inst, int depth, int th, int ppw);
+
+/* Capture and replay of batch pipelines (lx_phi_leja_batched): on = 1 (the
+ * default) or 0, which also frees the captured graphs. */
+lx_status lx_set_batch_graphs(lx_ctx* ctx, int on);
 
 /* ---- learned spectral bound and sweep budget ------------------------- */
 

@@ -49,7 +49,8 @@ class Stats(C.Structure):
                 ("pnorm", C.c_double * LX_K_MAX), ("rho_hat", C.c_double),
                 ("plan_ms", C.c_double), ("loop_ms", C.c_double), ("sweep_ms", C.c_double),
                 ("first_sweep_ms", C.c_double), ("bytes", C.c_double), ("n_launch", C.c_int),
-                ("depth", C.c_int), ("step_err", C.c_double), ("substeps", C.c_int), ("marching", C.c_int)]
+                ("depth", C.c_int), ("step_err", C.c_double), ("substeps", C.c_int), ("marching", C.c_int),
+                ("batch_graph", C.c_int)]
 
     def as_dict(self) -> dict:
         return {"status": self.status, "n_apply": self.n_apply, "n_fp32": self.n_fp32,
@@ -57,7 +58,8 @@ class Stats(C.Structure):
                 "rho_hat": self.rho_hat, "plan_ms": self.plan_ms, "loop_ms": self.loop_ms,
                 "sweep_ms": self.sweep_ms, "first_sweep_ms": self.first_sweep_ms,
                 "bytes": self.bytes, "n_launch": self.n_launch, "depth": self.depth,
-                "step_err": self.step_err, "substeps": self.substeps, "marching": self.marching}
+                "step_err": self.step_err, "substeps": self.substeps, "marching": self.marching,
+                "batch_graph": self.batch_graph}
 
 
 class Instance(C.Structure):
@@ -111,6 +113,13 @@ def _signatures(lib: C.CDLL) -> None:
     lib.lx_phi_leja_batched.argtypes = [_P, _I, C.POINTER(Instance), _I, _D, C.POINTER(LejaOpts),
                                         C.POINTER(InstanceResult)]
     lib.lx_phi_leja_batched.restype = _I
+    lib.lx_tune_batched.argtypes = [_P, _I, C.POINTER(Instance), _I, _D, C.POINTER(LejaOpts), _I, C.c_char_p,
+                                    C.c_size_t]
+    lib.lx_tune_batched.restype = _I
+    lib.lx_set_batch_shape.argtypes = [_P, _I, C.POINTER(Instance), _I, _I, _I]
+    lib.lx_set_batch_shape.restype = _I
+    lib.lx_set_batch_graphs.argtypes = [_P, _I]
+    lib.lx_set_batch_graphs.restype = _I
     lib.lx_predictor_create.argtypes = [_P, C.c_ulonglong, C.POINTER(_P)]
     lib.lx_predictor_create.restype = _I
     lib.lx_predictor_destroy.argtypes = [_P]
@@ -160,7 +169,7 @@ def _signatures(lib: C.CDLL) -> None:
 
 EXPORTED = ["lx_create", "lx_destroy", "lx_set_stream", "lx_set_timing", "lx_last_error",
             "lx_status_string", "lx_get_stats", "lx_spectrum", "lx_phi_leja", "lx_exprb_step", "lx_linear_step",
-            "lx_phi_leja_batched", "lx_tune", "lx_set_tile", "lx_set_depth", "lx_set_window_kernel", "lx_bandwidth_probe",
+            "lx_phi_leja_batched", "lx_tune_batched", "lx_set_batch_shape", "lx_set_batch_graphs", "lx_tune", "lx_set_tile", "lx_set_depth", "lx_set_window_kernel", "lx_bandwidth_probe",
             "lx_predictor_create", "lx_predictor_destroy", "lx_predictor_state_size", "lx_predictor_set_scaling",
             "lx_predictor_get_state", "lx_predictor_set_state", "lx_predictor_save", "lx_predictor_load",
             "lx_predictor_gradient", "lx_predictor_train", "lx_predictor_infer", "lx_instance_features",
@@ -368,6 +377,32 @@ class Context:
         if raise_on_error:
             self._check(st, allow=(LX_OK, LX_ENOTCONV))
         return st, [r.as_dict() for r in res]
+
+    def tune_batched(self, instances, power_iters=0, safety=1.05, rtol=1e-8, atol=0.0, max_iters=500,
+                     repeats=3) -> list:
+        """lx_tune_batched: runs the batch under every candidate shape and keeps
+        the fastest for its class.  Returns [(depth, th, points_per_workgroup,
+        median_ms), ...]."""
+        n = len(instances)
+        arr = self._instances(instances)
+        opts = LejaOpts(float(rtol), float(atol), int(max_iters), 1e4)
+        buf = C.create_string_buffer(4096)
+        self._check(self.lib.c.lx_tune_batched(self._h, n, arr, int(power_iters), float(safety), C.byref(opts),
+                                               int(repeats), buf, C.c_size_t(4096)))
+        rows = []
+        for line in buf.value.decode().splitlines():
+            d, th, ppw, ms = line.split()
+            rows.append((int(d), int(th), int(ppw), float(ms)))
+        return rows
+
+    def set_batch_shape(self, instances, depth=0, th=0, ppw=0) -> None:
+        """lx_set_batch_shape for the class of this batch (all 0: forget it)."""
+        self._check(self.lib.c.lx_set_batch_shape(self._h, len(instances), self._instances(instances), int(depth),
+                                                  int(th), int(ppw)))
+
+    def set_batch_graphs(self, on: bool) -> None:
+        """lx_set_batch_graphs: capture and replay of batch pipelines."""
+        self._check(self.lib.c.lx_set_batch_graphs(self._h, 1 if on else 0))
 
     def phi_leja_learned(self, instances, predictor, margin_log_rho, margin_log_sweeps, power_iters=20, safety=1.05,
                          rtol=1e-8, atol=0.0, max_iters=500, raise_on_error=True):

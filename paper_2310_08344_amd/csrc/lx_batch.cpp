@@ -8,9 +8,14 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <iterator>
+#include <string>
 #include <vector>
 
 #include "lx.h"
@@ -24,10 +29,11 @@ using lx::LoopCtl;
 
 namespace {
 
-constexpr long kPointsPerWorkgroup = 16384;   // an instance's share of a launch, per workgroup
+constexpr long kPointsPerWorkgroup = 16384;   // an instance's share of a launch, per workgroup (default)
 constexpr int kMaxWorkgroupsPerInstance = 1024;
 constexpr int kFirstChunk = 16;
 constexpr int kChunk = 8;
+constexpr size_t kBatchGraphs = 4;            // captured pipelines kept per context
 
 #define LXB_HIP(ctx, call)                                                                              \
     do {                                                                                                \
@@ -68,11 +74,38 @@ lx_status grow_pinned(lx_ctx* ctx, T** p, size_t* cap, size_t need) {
     return LX_OK;
 }
 
+// The class of a batch for the tuned launch shapes: whether any instance
+// is a Burgers Jacobian, then its distinct grid sides.
+std::vector<int> batch_class(int n, const lx_instance* inst) {
+    bool burgers = false;
+    std::vector<std::pair<int, int>> sides;
+    for (int i = 0; i < n; ++i) {
+        burgers = burgers || inst[i].op.kind == LX_OP_BURGERS2D;
+        sides.emplace_back(inst[i].op.nx, inst[i].op.ny);
+    }
+    std::sort(sides.begin(), sides.end());
+    sides.erase(std::unique(sides.begin(), sides.end()), sides.end());
+    std::vector<int> key{burgers ? 1 : 0};
+    for (const auto& q : sides) {
+        key.push_back(q.first);
+        key.push_back(q.second);
+    }
+    return key;
+}
+
+void drop_graphs(lx_batch_ws& W) {
+    for (auto& g : W.graphs)
+        if (g.exec != nullptr) (void)hipGraphExecDestroy(g.exec);
+    W.graphs.clear();
+}
+
 }  // namespace
 
 // frees the batch workspaces (called by lx_destroy)
 void lx_internal_free_batch(lx_ctx* ctx) {
     lx_batch_ws& b = ctx->batch;
+    drop_graphs(b);
+    if (b.cap_stream != nullptr) (void)hipStreamDestroy(b.cap_stream);
     (void)hipFree(b.d_inst);
     (void)hipFree(b.d_ctl);
     (void)hipFree(b.d_block_inst);
@@ -87,6 +120,18 @@ void lx_internal_free_batch(lx_ctx* ctx) {
     (void)hipFree(b.d_feat);
     (void)hipHostFree(b.h_feat);
     b = lx_batch_ws{};
+}
+
+extern "C" lx_status lx_set_batch_graphs(lx_ctx* ctx, int on) {
+    if (ctx == nullptr) return LX_EINVAL;
+    if (on != 0 && on != 1) return lx_internal_fail(ctx, LX_EINVAL, "lx_set_batch_graphs: on must be 0 or 1");
+    ctx->batch.use_graphs = on;
+    if (!on) {
+        if (hipStreamSynchronize(ctx->stream) != hipSuccess)
+            return lx_internal_fail(ctx, LX_EDEVICE, "stream synchronisation failed");
+        drop_graphs(ctx->batch);
+    }
+    return LX_OK;
 }
 
 extern "C" lx_status lx_phi_leja_batched(lx_ctx* ctx, int n, const lx_instance* inst, int power_iters,
@@ -111,8 +156,16 @@ extern "C" lx_status lx_phi_leja_batched(lx_ctx* ctx, int n, const lx_instance* 
     // windows of kBatchBlockDepth when, moreover, every side reaches the
     // window's halo and lx_set_depth does not ask for one or two
     constexpr int BD = lx::kBatchBlockDepth;
-    bool pair = ctx->depth_forced != 1;
-    bool blk = ctx->depth_forced != 1 && ctx->depth_forced != 2;
+    // the tuned shape of this batch class (lx_tune_batched), unless
+    // lx_set_depth forces the iterations per launch
+    lx::BatchShape ts{};
+    if (ctx->depth_forced == 0) {
+        auto it = ctx->batch.tuned.find(batch_class(n, inst));
+        if (it != ctx->batch.tuned.end()) ts = it->second;
+    }
+    const int want_depth = ctx->depth_forced != 0 ? ctx->depth_forced : ts.depth;
+    bool pair = want_depth != 1;
+    bool blk = want_depth != 1 && want_depth != 2;
     bool any_burgers = false;
     for (int i = 0; i < n; ++i) {
         const lx_instance& q = inst[i];
@@ -125,8 +178,11 @@ extern "C" lx_status lx_phi_leja_batched(lx_ctx* ctx, int n, const lx_instance* 
     if (blk) pair = false;
     // tile rows: 16 (40 KB of LDS, 4 workgroups per CU) unless the Burgers
     // state needs room too, then 8 (36 KB)
-    int th = (ctx->pair_th == 8 || ctx->pair_th == 16) ? ctx->pair_th : (any_burgers ? 8 : 16);
+    int th = (ctx->pair_th == 8 || ctx->pair_th == 16) ? ctx->pair_th
+             : (ts.th == 8 || ts.th == 16)               ? ts.th
+                                                          : (any_burgers ? 8 : 16);
     if (blk && any_burgers) th = 8;   // the Burgers window layout takes 8-row tiles in a batch
+    const long ppw = ts.ppw > 0 ? ts.ppw : kPointsPerWorkgroup;
     std::vector<BatchInst> hi(static_cast<size_t>(n));
     std::vector<int> budget(static_cast<size_t>(n));
     int total_blocks = 0, max_budget = 1;
@@ -171,7 +227,7 @@ extern "C" lx_status lx_phi_leja_batched(lx_ctx* ctx, int n, const lx_instance* 
         b.ptiles_x = (b.nx + lx::kBatchTx * b.vec - 1) / (lx::kBatchTx * b.vec);
         b.ptiles_y = (b.ny + lx::kBatchTy * lx::kBatchPowerRows - 1) / (lx::kBatchTy * lx::kBatchPowerRows);
         const int T = b.tiles_x * b.tiles_y;
-        const int tpw = static_cast<int>(std::max(1L, kPointsPerWorkgroup / tile_points));
+        const int tpw = static_cast<int>(std::max(1L, ppw / tile_points));
         b.nb = std::min(std::max((T + tpw - 1) / tpw, 1), kMaxWorkgroupsPerInstance);
         b.wg_begin = total_blocks;
         total_blocks += b.nb;
@@ -205,6 +261,7 @@ extern "C" lx_status lx_phi_leja_batched(lx_ctx* ctx, int n, const lx_instance* 
     lx_batch_ws& W = ctx->batch;
     lx_status s = LX_OK;
     const size_t nn = static_cast<size_t>(n), nblk = static_cast<size_t>(total_blocks);
+    const void* addr_before[] = {W.d_inst, W.d_ctl, W.d_block_inst, W.d_coef, W.d_partials, W.d_basis, W.d_done};
     if ((s = grow_device(ctx, reinterpret_cast<BatchInst**>(&W.d_inst), &W.cap_d_inst, nn)) != LX_OK ||
         (s = grow_device(ctx, reinterpret_cast<LoopCtl**>(&W.d_ctl), &W.cap_d_ctl, nn)) != LX_OK ||
         (s = grow_pinned(ctx, reinterpret_cast<BatchInst**>(&W.h_inst), &W.cap_h_inst, nn)) != LX_OK ||
@@ -219,6 +276,12 @@ extern "C" lx_status lx_phi_leja_batched(lx_ctx* ctx, int n, const lx_instance* 
         return s;
     s = lx_internal_ensure_xi(ctx, ld);
     if (s != LX_OK) return s;
+    {
+        // a captured pipeline holds the workspace addresses: drop every one
+        // once a workspace has moved
+        const void* addr_after[] = {W.d_inst, W.d_ctl, W.d_block_inst, W.d_coef, W.d_partials, W.d_basis, W.d_done};
+        if (!std::equal(std::begin(addr_before), std::end(addr_before), std::begin(addr_after))) drop_graphs(W);
+    }
 
     // ---- descriptors ----
     BatchInst* h_inst = static_cast<BatchInst*>(W.h_inst);
@@ -259,42 +322,88 @@ extern "C" lx_status lx_phi_leja_batched(lx_ctx* ctx, int n, const lx_instance* 
     if (timing) {
         s = lx_internal_ensure_timing_events(ctx, 4);
         if (s != LX_OK) return s;
-        LXB_HIP(ctx, hipEventRecord(ctx->tev[0], st));
     }
-    // ---- spectral bounds (Listing 7) ----
-    if (power_iters > 0) {
-        LXB_HIP(ctx, lx::launch_batch_fill_x0(d_inst, W.d_block_inst, total_blocks, st));
-        LXB_HIP(ctx, lx::launch_batch_power_norm(d_inst, W.d_block_inst, total_blocks, W.d_partials, st));
-        for (int k = 0; k < power_iters; ++k)
-            LXB_HIP(ctx, lx::launch_batch_power_sweep(d_inst, W.d_block_inst, total_blocks, W.d_partials, k, st));
-        LXB_HIP(ctx, lx::launch_batch_power_final(d_inst, n, W.d_partials, power_iters - 1, safety, st));
+    const int last = blk ? (max_budget + BD - 1) / BD + 2 : (pair ? (max_budget + 1) / 2 + 1 : max_budget);
+    const int per = blk ? BD : (pair ? 2 : 1);
+    // the device pipeline: spectral bounds (Listing 7), Newton coefficients,
+    // then window (or one- or two-iteration) launches first .. first+count-1
+    auto enqueue_head = [&](hipStream_t q) -> hipError_t {
+        hipError_t e = hipSuccess;
+        if (power_iters > 0) {
+            e = lx::launch_batch_fill_x0(d_inst, W.d_block_inst, total_blocks, q);
+            if (e == hipSuccess) e = lx::launch_batch_power_norm(d_inst, W.d_block_inst, total_blocks, W.d_partials, q);
+            for (int k = 0; k < power_iters && e == hipSuccess; ++k)
+                e = lx::launch_batch_power_sweep(d_inst, W.d_block_inst, total_blocks, W.d_partials, k, q);
+            if (e == hipSuccess)
+                e = lx::launch_batch_power_final(d_inst, n, W.d_partials, power_iters - 1, safety, q);
+        }
+        if (e == hipSuccess) e = lx::launch_batch_coeffs(d_inst, n, ctx->xi, W.d_coef, ld, q);
+        return e;
+    };
+    auto enqueue_loop = [&](hipStream_t q, int first, int count) -> hipError_t {
+        hipError_t e = hipSuccess;
+        for (int L = first; L < first + count && e == hipSuccess; ++L) {
+            if (blk) {
+                e = lx::launch_batch_block(d_inst, d_ctl, W.d_block_inst, total_blocks, any_burgers, th, W.d_partials,
+                                           W.d_coef, ld, ctx->xi, W.d_done, L, q);
+            } else if (pair) {
+                e = lx::launch_batch_pair(d_inst, d_ctl, W.d_block_inst, total_blocks, any_burgers, th, W.d_partials,
+                                          W.d_coef, ld, ctx->xi, W.d_done, L, q);
+            } else {
+                e = lx::launch_batch_sweep(d_inst, d_ctl, W.d_block_inst, total_blocks, W.d_partials, W.d_coef, ld,
+                                           ctx->xi, W.d_done, L, q);
+            }
+        }
+        return e;
+    };
+    // what a captured pipeline bakes in: sizes, launch shape and addresses
+    std::vector<long long> key{n, total_blocks, blk ? 1 : 0, pair ? 1 : 0, th, any_burgers ? 1 : 0, power_iters,
+                               ld, static_cast<long long>(ppw)};
+    {
+        long long sb;
+        std::memcpy(&sb, &safety, sizeof(sb));
+        key.push_back(sb);
+        for (const void* a : {static_cast<const void*>(d_inst), static_cast<const void*>(d_ctl),
+                              static_cast<const void*>(W.d_block_inst), static_cast<const void*>(W.d_partials),
+                              static_cast<const void*>(W.d_coef), static_cast<const void*>(W.d_done),
+                              static_cast<const void*>(ctx->xi)})
+            key.push_back(static_cast<long long>(reinterpret_cast<uintptr_t>(a)));
     }
-    // ---- Newton coefficients on the device ----
-    LXB_HIP(ctx, lx::launch_batch_coeffs(d_inst, n, ctx->xi, W.d_coef, ld, st));
-    if (timing) LXB_HIP(ctx, hipEventRecord(ctx->tev[1], st));
+    ++W.calls;
+    lx_batch_graph* graph = nullptr;
+    if (W.use_graphs && !timing) {
+        for (auto& g : W.graphs)
+            if (g.key == key) graph = &g;
+    }
+
+    int launched = 0, chunk_id = 0, last_slot = 0;
+    bool finished = false;
+    const bool replayed = graph != nullptr;
+    if (graph != nullptr) {
+        // one captured pipeline, then one look at the finished count; a batch
+        // that needs more launches than were captured goes on chunk by chunk
+        graph->last_use = W.calls;
+        LXB_HIP(ctx, hipGraphLaunch(graph->exec, st));
+        launched = graph->launches;
+        LXB_HIP(ctx, hipMemcpyAsync(&W.h_done[0], W.d_done, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+        LXB_HIP(ctx, hipEventRecord(ctx->poll_ev[0], st));
+        LXB_HIP(ctx, hipEventSynchronize(ctx->poll_ev[0]));
+        finished = W.h_done[0] >= static_cast<unsigned>(n) || launched > last;
+        chunk_id = 1;
+    } else {
+        if (timing) LXB_HIP(ctx, hipEventRecord(ctx->tev[0], st));
+        LXB_HIP(ctx, enqueue_head(st));
+        if (timing) LXB_HIP(ctx, hipEventRecord(ctx->tev[1], st));
+    }
 
     // ---- batched sweeps (one or two iterations, or a window, per launch) ----
     // windows: at most ceil(budget / depth) windows, one re-execution (one
     // output) and one publishing launch per instance
-    const int last = blk ? (max_budget + BD - 1) / BD + 2 : (pair ? (max_budget + 1) / 2 + 1 : max_budget);
-    const int per = blk ? BD : (pair ? 2 : 1);
-    int launched = 0, chunk_id = 0, last_slot = 0;
     const int first_chunk = std::max(3, kFirstChunk / per), next_chunk = std::max(2, kChunk / per);
-    int chunk = first_chunk;
-    while (launched <= last) {
+    int chunk = graph != nullptr ? next_chunk : first_chunk;
+    while (!finished && launched <= last) {
         const int cnt = std::min(chunk, last + 1 - launched);
-        for (int i = 0; i < cnt; ++i) {
-            if (blk) {
-                LXB_HIP(ctx, lx::launch_batch_block(d_inst, d_ctl, W.d_block_inst, total_blocks, any_burgers, th,
-                                                    W.d_partials, W.d_coef, ld, ctx->xi, W.d_done, launched + i, st));
-            } else if (pair) {
-                LXB_HIP(ctx, lx::launch_batch_pair(d_inst, d_ctl, W.d_block_inst, total_blocks, any_burgers, th,
-                                                   W.d_partials, W.d_coef, ld, ctx->xi, W.d_done, launched + i, st));
-            } else {
-                LXB_HIP(ctx, lx::launch_batch_sweep(d_inst, d_ctl, W.d_block_inst, total_blocks, W.d_partials,
-                                                    W.d_coef, ld, ctx->xi, W.d_done, launched + i, st));
-            }
-        }
+        LXB_HIP(ctx, enqueue_loop(st, launched, cnt));
         launched += cnt;
         const int slot = chunk_id & 1;
         LXB_HIP(ctx, hipMemcpyAsync(&W.h_done[slot], W.d_done, sizeof(unsigned), hipMemcpyDeviceToHost, st));
@@ -363,6 +472,137 @@ extern "C" lx_status lx_phi_leja_batched(lx_ctx* ctx, int n, const lx_instance* 
         S.sweep_ms = lx_internal_elapsed(ctx->tev[0], ctx->tev[2]);
     }
     S.status = worst;
+
+    // ---- capture the windows pipeline for later calls with this layout ----
+    // as many window launches as this call needed (every instance's working
+    // launches and the one that publishes it); a replay that needed more
+    // than it holds is captured again.
+    if (blk && W.use_graphs && !timing) {
+        int needed = 1;
+        for (int i = 0; i < n; ++i) needed = std::max(needed, h_ctl[i].slot[2].n_work + 1);
+        needed = std::min(needed, last + 1);
+        if (graph != nullptr && needed > graph->launches) {
+            (void)hipGraphExecDestroy(graph->exec);
+            W.graphs.erase(W.graphs.begin() + (graph - W.graphs.data()));
+            graph = nullptr;
+        }
+        if (graph == nullptr) {
+            // a failed capture leaves the layout uncaptured; the call's results stand
+            if (W.cap_stream == nullptr && hipStreamCreateWithFlags(&W.cap_stream, hipStreamNonBlocking) != hipSuccess)
+                W.cap_stream = nullptr;
+            hipGraph_t g = nullptr;
+            if (W.cap_stream != nullptr &&
+                hipStreamBeginCapture(W.cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+                hipError_t e = enqueue_head(W.cap_stream);
+                if (e == hipSuccess) e = enqueue_loop(W.cap_stream, 0, needed);
+                const hipError_t e2 = hipStreamEndCapture(W.cap_stream, &g);
+                hipGraphExec_t ex = nullptr;
+                if (e == hipSuccess && e2 == hipSuccess && g != nullptr &&
+                    hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess) {
+                    if (W.graphs.size() >= kBatchGraphs) {
+                        auto lru = std::min_element(W.graphs.begin(), W.graphs.end(),
+                                                    [](const lx_batch_graph& a, const lx_batch_graph& b) {
+                                                        return a.last_use < b.last_use;
+                                                    });
+                        (void)hipGraphExecDestroy(lru->exec);
+                        W.graphs.erase(lru);
+                    }
+                    W.graphs.push_back(lx_batch_graph{key, ex, needed, W.calls});
+                }
+                if (g != nullptr) (void)hipGraphDestroy(g);
+                (void)hipGetLastError();
+            }
+        }
+    }
+    S.batch_graph = replayed ? 1 : 0;
     if (worst != LX_OK) ctx->err = "at least one instance did not converge or became non-finite; see its result";
     return worst;
+}
+
+// Times the batch itself under every candidate launch shape and keeps the
+// fastest for its class (lx.h).
+extern "C" lx_status lx_tune_batched(lx_ctx* ctx, int n, const lx_instance* inst, int power_iters, double safety,
+                                     const lx_leja_opts* o, int repeats, char* report, size_t report_len) {
+    if (ctx == nullptr) return LX_EINVAL;
+    if (n < 1 || n > 65536 || inst == nullptr) return lx_internal_fail(ctx, LX_EINVAL, "tune: batch of %d instances", n);
+    if (repeats < 1 || repeats > 50) return lx_internal_fail(ctx, LX_EINVAL, "tune: repeats %d outside 1..50", repeats);
+    bool burgers = false, even = true;
+    int min_side = 1 << 30;
+    for (int i = 0; i < n; ++i) {
+        burgers = burgers || inst[i].op.kind == LX_OP_BURGERS2D;
+        even = even && inst[i].op.nx % 2 == 0;
+        min_side = std::min(min_side, std::min(inst[i].op.nx, inst[i].op.ny));
+    }
+    std::vector<lx::BatchShape> cands;
+    for (int depth : {lx::kBatchBlockDepth, 2, 1}) {
+        if (depth >= 2 && !even) continue;
+        if (depth == lx::kBatchBlockDepth && min_side < depth) continue;
+        for (int th : {8, 16}) {
+            if (depth == 1 && th == 16) continue;                              // th is not used by one sweep
+            if (th == 16 && burgers && depth == lx::kBatchBlockDepth) continue;  // windows with Burgers: 8 rows
+            for (int ppw : {4096, 8192, 16384, 32768}) cands.push_back(lx::BatchShape{depth, th, ppw});
+        }
+    }
+    const std::vector<int> cls = batch_class(n, inst);
+    const int saved_depth = ctx->depth_forced, saved_th = ctx->pair_th;
+    ctx->depth_forced = 0;
+    ctx->pair_th = 0;
+    std::vector<lx_instance_result> res(static_cast<size_t>(n));
+    std::string rep;
+    double best_ms = 1e300;
+    lx::BatchShape best{};
+    lx_status status = LX_OK;
+    for (const lx::BatchShape& c : cands) {
+        ctx->batch.tuned[cls] = c;
+        std::vector<double> ms;
+        for (int r = 0; r <= repeats && status == LX_OK; ++r) {
+            const auto t0 = std::chrono::steady_clock::now();
+            const lx_status s = lx_phi_leja_batched(ctx, n, inst, power_iters, safety, o, res.data());
+            const double t = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (s != LX_OK && s != LX_ENOTCONV) status = s;
+            if (r > 0) ms.push_back(t);   // the first call is a warm-up (and captures the pipeline)
+        }
+        if (status != LX_OK) break;
+        std::sort(ms.begin(), ms.end());
+        const double med = ms[ms.size() / 2];
+        char line[96];
+        std::snprintf(line, sizeof(line), "%d %d %d %.4f\n", c.depth, c.th, c.ppw, med);
+        rep += line;
+        if (med < best_ms) {
+            best_ms = med;
+            best = c;
+        }
+    }
+    ctx->depth_forced = saved_depth;
+    ctx->pair_th = saved_th;
+    if (status != LX_OK) {
+        ctx->batch.tuned.erase(cls);
+        return status;
+    }
+    ctx->batch.tuned[cls] = best;
+    if (report != nullptr && report_len > 0) std::snprintf(report, report_len, "%s", rep.c_str());
+    const char* path = std::getenv("LX_TUNE_CACHE");
+    if (path != nullptr && *path != 0) {
+        FILE* f = std::fopen(path, "a");
+        if (f != nullptr) {
+            std::fprintf(f, "{\"batch_class\": [");
+            for (size_t i = 0; i < cls.size(); ++i) std::fprintf(f, "%s%d", i ? ", " : "", cls[i]);
+            std::fprintf(f, "], \"depth\": %d, \"th\": %d, \"ppw\": %d, \"ms\": %.4f}\n", best.depth, best.th, best.ppw,
+                         best_ms);
+            std::fclose(f);
+        }
+    }
+    return LX_OK;
+}
+
+extern "C" lx_status lx_set_batch_shape(lx_ctx* ctx, int n, const lx_instance* inst, int depth, int th, int ppw) {
+    if (ctx == nullptr) return LX_EINVAL;
+    if (n < 1 || inst == nullptr) return lx_internal_fail(ctx, LX_EINVAL, "batch shape: no instances");
+    if (!(depth == 0 || depth == 1 || depth == 2 || depth == lx::kBatchBlockDepth) ||
+        !(th == 0 || th == 8 || th == 16) || ppw < 0 || ppw > (1 << 22))
+        return lx_internal_fail(ctx, LX_EINVAL, "batch shape: depth %d, th %d, ppw %d", depth, th, ppw);
+    const std::vector<int> cls = batch_class(n, inst);
+    if (depth == 0 && th == 0 && ppw == 0) ctx->batch.tuned.erase(cls);
+    else ctx->batch.tuned[cls] = lx::BatchShape{depth, th, ppw};
+    return LX_OK;
 }

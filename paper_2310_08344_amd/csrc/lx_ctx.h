@@ -12,6 +12,17 @@
 #include "lx_device.h"
 #include "planner.h"
 
+// A batch's device pipeline captured as a hipGraph: power iteration, the
+// Newton coefficients and the first `launches` window launches, for one
+// layout (key: sizes, launch shape and the workspace addresses the launches
+// take).  Replayed by later calls with the same layout.
+struct lx_batch_graph {
+    std::vector<long long> key;
+    hipGraphExec_t exec = nullptr;
+    int launches = 0;
+    unsigned long long last_use = 0;
+};
+
 // Workspaces of a batch of instances, grown on demand and kept.
 struct lx_batch_ws {
     void* d_inst = nullptr;      // lx::BatchInst[n]
@@ -29,6 +40,13 @@ struct lx_batch_ws {
     void* h_feat = nullptr;
     size_t cap_d_inst = 0, cap_d_ctl = 0, cap_d_blk = 0, cap_coef = 0, cap_partials = 0, cap_basis = 0,
            cap_done = 0, cap_h_inst = 0, cap_h_ctl = 0, cap_h_blk = 0, cap_h_done = 0, cap_feat = 0;
+    std::vector<lx_batch_graph> graphs;    // at most kBatchGraphs, least recently used replaced
+    hipStream_t cap_stream = nullptr;      // private stream the graphs are captured on
+    unsigned long long calls = 0;
+    int use_graphs = 1;                    // lx_set_batch_graphs
+    // tuned launch shapes per batch class (lx_tune_batched); key: any Burgers
+    // instance, then the distinct sides
+    std::map<std::vector<int>, lx::BatchShape> tuned;
 };
 
 struct lx_ctx {

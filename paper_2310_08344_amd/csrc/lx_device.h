@@ -60,6 +60,14 @@ struct Tile {
     int rows() const { return ty * ry; }
 };
 
+// Launch shape of a batch, chosen by lx_tune_batched per batch class: Leja
+// iterations per launch (1, 2 or kBatchBlockDepth), tile rows of the two-
+// iteration and window kernels, and the points each workgroup of an
+// instance serves.  Zero fields take the default rule.
+struct BatchShape {
+    int depth = 0, th = 0, ppw = 0;
+};
+
 struct SweepArgs {
     int nx, ny;
     int tiles_x, tiles_y;

@@ -247,8 +247,12 @@ def evaluate(ctx, predictor, margins, count=1024, seed0=SEED_EVALUATION, size=25
         torch.cuda.synchronize()
         return r, time.perf_counter() - t0
 
-    # descriptors are built once per instance set, for both paths
+    # descriptors are built once per instance set, for both paths; the
+    # batch launch shape of this instance class comes from the autotuner
+    # (timed on the plain batched path; the learned path shares the class)
     pb, lb = ctx.prepare(pargs), ctx.prepare(args)
+    tuned = ctx.tune_batched(pb, power_iters=POWER_ITERS, safety=SAFETY, rtol=RTOL, max_iters=MAX_ITERS, repeats=3)
+    best = min(tuned, key=lambda r: r[3])
     for _ in range(warmups):
         solve_plain(ctx, pb)
         solve_learned(ctx, predictor, lb, *margins)
@@ -294,6 +298,7 @@ def evaluate(ctx, predictor, margins, count=1024, seed0=SEED_EVALUATION, size=25
         "max_rel_diff_learned_vs_plain": max(diffs) if diffs else None,
         "median_rel_diff_learned_vs_plain": float(np.median(diffs)) if diffs else None,
         "largest_rel_diffs": largest,
+        "tuned_shape": {"iterations_per_launch": best[0], "tile_rows": best[1], "points_per_workgroup": best[2]},
     }
 
 

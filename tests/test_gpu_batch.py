@@ -274,3 +274,80 @@ def test_full_256_instance_workload(lx):
         oracle_parity([host(outs[i])], [res[i]["iters"]],
                       lambda f, A=A, u0=u0, p=p, c=c, g=g: leja_phi(A, u0, [(0, 1.0, 1.0)], p.h, c, g, 1e-8, 0.0,
                                                                     300, f), PARITY)
+
+
+def test_batch_graph_replays_match_eager_runs(ctx):
+    """The captured pipeline (power iteration, coefficients, windows) replays
+    bitwise what the eager launches compute.  With capture on, the first
+    call of a layout runs eagerly and captures; later calls replay.  The
+    tighter tolerance needs more windows than the looser call captured: its
+    first call replays those and goes on eagerly (and captures again).
+    Every replay is checked against the eager result, with the program's
+    own eager work and synchronisations between the calls."""
+    import torch
+    inst = _mixed_batch(9, EVEN)
+    say("batch graph replays")
+    kws = [dict(power_iters=20, rtol=1e-6, max_iters=200), dict(power_iters=20, rtol=1e-10, max_iters=200),
+           dict(power_iters=0, rtol=1e-8, max_iters=200)]
+    ctx.set_batch_graphs(False)
+    eager = [_run(ctx, inst, **kw) for kw in kws]
+    ctx.set_batch_graphs(True)
+    expect_replayed = [[0, 1, 1, 1], [1, 1, 1, 1], [0, 1, 1, 1]]
+    for kw, (st0, res0, outs0), flags in zip(kws, eager, expect_replayed):
+        assert st0 == B.LX_OK
+        for k in range(4):
+            st, res, outs = _run(ctx, inst, **kw)
+            assert ctx.stats()["batch_graph"] == flags[k], (kw, k)
+            assert st == st0 and [r["iters"] for r in res] == [r["iters"] for r in res0]
+            assert all(np.array_equal(a, b) for a, b in zip(outs, outs0)), (kw, k)
+            # the program's own eager work between replays
+            q = inst[0]
+            o = dev(np.zeros((q["ny"], q["nx"])))
+            ctx.phi_leja(q["op"], dev(q["v"]), [o], [q["l"]], q["h"], q["c"], q["gamma"], rtol=1e-8,
+                         max_iters=200, **({"u": dev(q["u"])} if q["u"] is not None else {}))
+            torch.cuda.synchronize()
+    # the eager result itself against the oracle (power iteration off)
+    st0, res0, outs0 = eager[2]
+    for q, r, o in zip(inst, res0, outs0):
+        oracle_parity([o], [r["iters"]],
+                      lambda f, q=q: leja_phi(q["A"], q["v"], [(q["l"], 1.0, 1.0)], q["h"], q["c"], q["gamma"],
+                                              1e-8, 0.0, 200, f), PARITY)
+
+
+@pytest.mark.parametrize("depth,th,ppw", [(4, 8, 4096), (4, 16, 32768), (2, 16, 8192), (1, 0, 4096)])
+def test_batch_shapes_match_oracle(ctx, depth, th, ppw):
+    """Every launch shape the batch tuner may pick (iterations per launch,
+    tile rows, points per workgroup: several workgroups per instance)."""
+    inst = _mixed_batch(10, [(256, 256, "da"), (96, 40, "da"), (130, 66, "da"), (512, 128, "da"), (64, 64, "da")])
+    args_probe = [dict(op=q["op"], v=dev(q["v"]), out=dev(np.zeros((q["ny"], q["nx"]))), h=q["h"]) for q in inst]
+    ctx.set_batch_shape(args_probe, depth, th, ppw)
+    say("batch shape", depth, th, ppw)
+    try:
+        st, res, outs = _run(ctx, inst, rtol=1e-8, max_iters=200)
+        assert ctx.stats()["depth"] == depth
+    finally:
+        ctx.set_batch_shape(args_probe)
+    assert st == B.LX_OK
+    for q, r, o in zip(inst, res, outs):
+        oracle_parity([o], [r["iters"]],
+                      lambda f, q=q: leja_phi(q["A"], q["v"], [(q["l"], 1.0, 1.0)], q["h"], q["c"], q["gamma"],
+                                              1e-8, 0.0, 200, f), PARITY)
+
+
+def test_batch_tuner_keeps_the_fastest_shape(ctx):
+    inst = _mixed_batch(11, EVEN)
+    args = [dict(op=q["op"], v=dev(q["v"]), out=dev(np.zeros((q["ny"], q["nx"]))), l=q["l"], h=q["h"], c=q["c"],
+                 gamma=q["gamma"], **({"u": dev(q["u"])} if q["u"] is not None else {})) for q in inst]
+    say("batch tuner")
+    rows = ctx.tune_batched(args, rtol=1e-8, max_iters=200, repeats=1)
+    # Burgers instances present: windows take 8-row tiles only
+    assert {(r[0], r[1]) for r in rows} == {(4, 8), (2, 8), (2, 16), (1, 8)}
+    assert all(r[3] > 0 for r in rows)
+    best = min(rows, key=lambda r: r[3])
+    st, res, outs = _run(ctx, inst, rtol=1e-8, max_iters=200)
+    assert st == B.LX_OK and ctx.stats()["depth"] == best[0]
+    ctx.set_batch_shape(args)
+    for q, r, o in zip(inst, res, outs):
+        oracle_parity([o], [r["iters"]],
+                      lambda f, q=q: leja_phi(q["A"], q["v"], [(q["l"], 1.0, 1.0)], q["h"], q["c"], q["gamma"],
+                                              1e-8, 0.0, 200, f), PARITY)
