@@ -51,18 +51,22 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "leja_block_phi123_4096_traffic.json")
+# HBM traffic of the dominant kernel from rocprofv3 counters, per kernel family
+TRAFFIC_FILES = {"leja_stream": os.path.join(ROOT, "profiles", "leja_stream_phi123_4096_traffic.json"),
+                 "leja_block": os.path.join(ROOT, "profiles", "leja_block_phi123_4096_traffic.json")}
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def committed_traffic(launch_bytes: float):
+def committed_traffic(launch_bytes: float, family: str):
     """HBM bytes per launch of the sweep from the committed counter summary,
     if it was taken on the current kernel source."""
+    if family not in TRAFFIC_FILES:
+        return None
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC_FILES[family]) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -429,6 +433,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper-shaped 8192^2 problems")
+    ap.add_argument("--no-small", action="store_true", help="skip the 64^2 and 1024^2 workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the phi-action path is single-GPU (--gpus {args.gpus} "
@@ -507,7 +512,8 @@ def main() -> int:
         its = r["iters"][:3]
         for m in range(max(its)):
             one_iter_bytes += n_pts * (16.0 + sum((8.0 if m == 0 else 16.0) for i in its if m < i))
-    traffic = committed_traffic(per_launch)
+    traffic = committed_traffic(per_launch, "leja_stream" if last["marching"] else
+                                ("leja_block" if depth >= 3 else "other"))
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic["bytes_per_launch"] if traffic else None,
@@ -551,8 +557,9 @@ def main() -> int:
     }
     out.update({k: v for k, v in extra.items() if v is not None})
     ctx.close()
-    log("64^2 exp and 1024^2 phi_1..phi_3 workloads")
-    out["small_configs"] = bench_small_configs(lib)
+    if not args.no_small:
+        log("64^2 exp and 1024^2 phi_1..phi_3 workloads")
+        out["small_configs"] = bench_small_configs(lib)
     if not args.no_batched:
         log("batched 256-instance comparison")
         out["batched_256"] = bench_batched(lib)

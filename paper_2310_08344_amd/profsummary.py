@@ -28,7 +28,8 @@ import sys
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2310_08344_amd", "csrc")
 # the sources the FP64 Leja kernels (one, two and more iterations per launch) are compiled from
-SWEEP_SOURCES = ("kernels.hip", "pair.hip", "block.hip", "tile_device.h", "sweep_device.h", "lx_device.h")
+SWEEP_SOURCES = ("kernels.hip", "pair.hip", "block.hip", "stream.hip", "tile_device.h", "sweep_device.h",
+                 "window_device.h", "lx_device.h")
 COPY_ELEMS = 1 << 26
 
 
@@ -126,6 +127,7 @@ def main(argv=None) -> int:
     s.add_argument("--exit-us", type=float, default=20.0)
     s.add_argument("--max-us", type=float, default=float("inf"),
                    help="count only working launches shorter than this (separates grid sizes)")
+    s.add_argument("--list", action="store_true", help="also list the working launches' durations in order")
     t = sub.add_parser("traffic")
     t.add_argument("fetch_dir")
     t.add_argument("write_dir")
@@ -148,6 +150,8 @@ def main(argv=None) -> int:
             print(f"\n{a.kernel}: {len(work)} working launches{band}, average {st.mean(work):.2f} us, "
                   f"median {st.median(work):.2f} us; {len(idle)} early-exit launches"
                   + (f", average {st.mean(idle):.2f} us" if idle else ""))
+            if a.list:
+                print("durations (us, in launch order): " + " ".join(f"{x:.1f}" for x in work))
     else:
         r = traffic(a.fetch_dir, a.write_dir, a.kernel, a.points, max_bytes_per_point=a.max_bpp)
         r["kernel"] = a.kernel
