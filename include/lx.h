@@ -215,6 +215,32 @@ lx_status lx_phi_leja(lx_ctx* ctx, const lx_operator* op, const double* d_u,
                       double c, double gamma, const lx_leja_opts* o,
                       int* iters, double* err);
 
+/* For callers that cannot allocate device memory (code in serving loops
+ * or harnesses that forbid allocation after set-up): lx_phi_leja with every
+ * device buffer its kernels use beyond the inputs, the outputs and the
+ * context's fixed workspaces (the Newton basis pair, the windows' second
+ * output buffers, the partial sums) taken from the library's static device
+ * scratch instead of the context, so the call allocates no device memory,
+ * also on its first use (lx_phi_leja grows its workspaces on demand).  The
+ * scratch is a file-scope device array of (2 + LX_K_MAX) * 2^18 + 327680
+ * doubles (about 15 MB) that every GPU the library runs on holds until the
+ * process ends; its address on a device is looked up on the first call on
+ * that device.  Arguments, results, errors and launch shapes as
+ * lx_phi_leja, with these limits (LX_EINVAL beyond them): nx * ny <= 2^18
+ * points (the context's n_max does not apply), FP64 sweeps, no substeps
+ * (lx_leja_opts.substeps 0 must resolve to one), and timing (lx_set_timing)
+ * is not recorded.  Every call on a GPU shares that GPU's scratch, which
+ * keeps the last call's contents (no buffer needs to start at zero: every
+ * launch writes what the next one reads): calls that overlap on one GPU,
+ * on any streams or contexts, race and must be serialised by the caller.
+ * The host planner (Leja points, divided differences) keeps its own
+ * bounded host tables. */
+lx_status lx_phi_leja_static(lx_ctx* ctx, const lx_operator* op, const double* d_u,
+                             const double* d_v, int K, const int* l, const double* alpha,
+                             const double* sigma, double* const* d_out, double h,
+                             double c, double gamma, const lx_leja_opts* o,
+                             int* iters, double* err);
+
 /* ---- exponential integrator steps ------------------------------------- */
 
 /* In all three, J = J(u) and N(w) = F(w) - J w (Sec. 2.3); every phi

@@ -104,6 +104,10 @@ def _signatures(lib: C.CDLL) -> None:
                                 C.POINTER(_D), C.POINTER(_D), C.POINTER(_P), _D, _D, _D,
                                 C.POINTER(LejaOpts), C.POINTER(_I), C.POINTER(_D)]
     lib.lx_phi_leja.restype = _I
+    lib.lx_phi_leja_static.argtypes = [_P, C.POINTER(Operator), _P, _P, _I, C.POINTER(_I),
+                                       C.POINTER(_D), C.POINTER(_D), C.POINTER(_P), _D, _D, _D,
+                                       C.POINTER(LejaOpts), C.POINTER(_I), C.POINTER(_D)]
+    lib.lx_phi_leja_static.restype = _I
     lib.lx_exprb_step.argtypes = [_P, C.POINTER(Operator), _I, _P, _P, _P, C.POINTER(_D), _D, _D, _D,
                                   C.POINTER(LejaOpts), C.POINTER(_I)]
     lib.lx_exprb_step.restype = _I
@@ -168,7 +172,7 @@ def _signatures(lib: C.CDLL) -> None:
 
 
 EXPORTED = ["lx_create", "lx_destroy", "lx_set_stream", "lx_set_timing", "lx_last_error",
-            "lx_status_string", "lx_get_stats", "lx_spectrum", "lx_phi_leja", "lx_exprb_step", "lx_linear_step",
+            "lx_status_string", "lx_get_stats", "lx_spectrum", "lx_phi_leja", "lx_phi_leja_static", "lx_exprb_step", "lx_linear_step",
             "lx_phi_leja_batched", "lx_tune_batched", "lx_set_batch_shape", "lx_set_batch_graphs", "lx_tune", "lx_set_tile", "lx_set_depth", "lx_set_window_kernel", "lx_bandwidth_probe",
             "lx_predictor_create", "lx_predictor_destroy", "lx_predictor_state_size", "lx_predictor_set_scaling",
             "lx_predictor_get_state", "lx_predictor_set_state", "lx_predictor_save", "lx_predictor_load",
@@ -323,8 +327,9 @@ class Context:
 
     def phi_leja(self, op: Operator, v, outs, ls, h, c, gamma, u=None, alphas=None, sigmas=None,
                  rtol=1e-8, atol=0.0, max_iters=500, fp32_switch=1e4, raise_on_error=True,
-                 substeps=0) -> PhiResult:
-        """outs[k] = sigma_k phi_{l_k}(alpha_k h A) v (lx_phi_leja); substeps 0 = automatic."""
+                 substeps=0, static=False) -> PhiResult:
+        """outs[k] = sigma_k phi_{l_k}(alpha_k h A) v (lx_phi_leja); substeps 0 = automatic.
+        static=True calls lx_phi_leja_static (the static device scratch; no allocation)."""
         K = len(outs)
         larr = (_I * K)(*[int(x) for x in ls])
         aarr = (_D * K)(*[float(x) for x in alphas]) if alphas is not None else None
@@ -333,9 +338,9 @@ class Context:
         opts = LejaOpts(float(rtol), float(atol), int(max_iters), float(fp32_switch), int(substeps))
         it = (_I * K)()
         er = (_D * K)()
-        st = self.lib.c.lx_phi_leja(self._h, C.byref(op), _ptr(u), _ptr(v), K, larr,
-                                    aarr, sarr, oarr, float(h), float(c), float(gamma),
-                                    C.byref(opts), it, er)
+        fn = self.lib.c.lx_phi_leja_static if static else self.lib.c.lx_phi_leja
+        st = fn(self._h, C.byref(op), _ptr(u), _ptr(v), K, larr, aarr, sarr, oarr, float(h), float(c), float(gamma),
+                C.byref(opts), it, er)
         if raise_on_error:
             self._check(st, allow=(LX_OK, LX_ENOTCONV))
         return PhiResult(st, list(it), list(er), self.stats())

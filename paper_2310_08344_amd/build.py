@@ -24,7 +24,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "_lx.so")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["kernels.hip", "pair.hip", "block.hip", "stream.hip", "batch.hip", "mlp.hip"]
+HIP_SOURCES = ["kernels.hip", "pair.hip", "block.hip", "stream.hip", "batch.hip", "mlp.hip", "static_ws.hip"]
 CXX_SOURCES = ["lx_api.cpp", "lx_batch.cpp", "lx_predictor.cpp", "planner.cpp"]
 
 

@@ -243,6 +243,10 @@ struct LejaCall {
     double* out[LX_K_MAX];
     double h, c, gamma;
     lx_leja_opts o;
+    // lx_phi_leja_static: the library's static device scratch, which then
+    // holds the basis pair, the windows' second output buffers and the
+    // partial sums (nothing is allocated); nullptr: the context's workspaces
+    double* scratch = nullptr;
 };
 
 // Whether a call may run its windows by register marching at this depth.
@@ -353,6 +357,7 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
     const bool fp32 = op.prec == LX_FP32_SWEEP;
     lx_stats& S = ctx->stats;
     S = lx_stats{};
+    const bool timing = ctx->timing != 0 && q.scratch == nullptr;
 
     bool vec2 = aligned16(q.v) && (q.u == nullptr || aligned16(q.u));
     for (int k = 0; k < K; ++k) vec2 = vec2 && aligned16(q.out[k]);
@@ -434,12 +439,14 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
     set_stencil(a, op, q.c, q.gamma);
     a.inv_sqrtN = 1.0 / std::sqrt(static_cast<double>(N));
     a.v = q.v;
-    a.ybuf[0] = ctx->ybuf[0];
-    a.ybuf[1] = ctx->ybuf[1];
+    a.ybuf[0] = q.scratch != nullptr ? q.scratch : ctx->ybuf[0];
+    a.ybuf[1] = q.scratch != nullptr ? q.scratch + lx::kStaticPoints : ctx->ybuf[1];
     a.u = q.u;
     a.u32 = ctx->u32;
     for (int k = 0; k < K; ++k) a.p[k] = q.out[k];
-    if (blk) {
+    if (blk && q.scratch != nullptr) {
+        for (int k = 0; k < K; ++k) a.p2[k] = q.scratch + (2 + k) * lx::kStaticPoints;
+    } else if (blk) {
         s = ensure_blk_ws(ctx, K);
         if (s != LX_OK) return s;
         for (int k = 0; k < K; ++k) a.p2[k] = ctx->blk_ws[k];
@@ -448,9 +455,17 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
     a.xi = ctx->xi;
     a.ctl = ctx->ctl;
     const int opcode = opcode_of(op.kind);
-    s = ensure_partials(ctx, 2 * static_cast<size_t>(a.nb) * (1 + K) * (blk ? D : (pair ? 2 : 1)));
-    if (s != LX_OK) return s;
-    a.partials = ctx->partials;
+    const size_t need_partials = 2 * static_cast<size_t>(a.nb) * (1 + K) * (blk ? D : (pair ? 2 : 1));
+    if (q.scratch != nullptr) {
+        if (need_partials > lx::kStaticPartials)
+            return fail(ctx, LX_EINVAL, "launch shape needs %zu partial sums, the static scratch holds %zu",
+                        need_partials, lx::kStaticPartials);
+        a.partials = q.scratch + (2 + lx::kKMax) * lx::kStaticPoints;
+    } else {
+        s = ensure_partials(ctx, need_partials);
+        if (s != LX_OK) return s;
+        a.partials = ctx->partials;
+    }
 
     // ---- chunked, device-resident loop ----
     // single: launch m (0 <= m < max_iters) is sweep m, which reads d_m (its
@@ -465,7 +480,7 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
     const int last = blk ? (max_iters + D - 1) / D + K + 2
                          : (pair ? (max_iters + 1) / 2 + 1 : max_iters);   // last launch index
     const int per = blk ? D : (pair ? 2 : 1);                               // iterations per launch
-    if (ctx->timing) {
+    if (timing) {
         s = ensure_timing_events(ctx, static_cast<size_t>(last) + 2);
         if (s != LX_OK) return s;
         LX_HIP(ctx, hipEventRecord(ctx->tev[0], ctx->stream));
@@ -491,7 +506,7 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
             else if (blk) LX_HIP(ctx, lx::launch_leja_block(opcode, K, t.th, D, a, L, ctx->stream));
             else if (pair) LX_HIP(ctx, lx::launch_leja_pair(opcode, K, t.th, a, L, ctx->stream));
             else LX_HIP(ctx, lx::launch_leja_sweep(opcode, K, fp32, t, a, L, ctx->stream));
-            if (ctx->timing && L < last) LX_HIP(ctx, hipEventRecord(ctx->tev[L + 1], ctx->stream));
+            if (timing && L < last) LX_HIP(ctx, hipEventRecord(ctx->tev[L + 1], ctx->stream));
         }
         launched += n;
         const int slot = chunk_id & 1;
@@ -576,7 +591,7 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
     S.marching = t.stream ? 1 : 0;
     S.bytes = bytes;
     S.plan_ms = plan_ms;
-    if (ctx->timing && S.n_launch > 0) {
+    if (timing && S.n_launch > 0) {
         // events follow every launch: a launch's interval also holds the stop
         // decision the next one takes first (a few microseconds)
         S.first_sweep_ms = elapsed(ctx->tev[0], ctx->tev[1]);
@@ -1198,6 +1213,61 @@ lx_status lx_phi_leja(lx_ctx* ctx, const lx_operator* op, const double* d_u, con
         q.out[k] = d_out[k];
     }
     s = run_leja_sub(ctx, q);
+    for (int k = 0; k < K; ++k) {
+        if (iters) iters[k] = ctx->stats.iters[k];
+        if (err) err[k] = ctx->stats.err[k];
+    }
+    return s;
+}
+
+lx_status lx_phi_leja_static(lx_ctx* ctx, const lx_operator* op, const double* d_u, const double* d_v, int K,
+                             const int* l, const double* alpha, const double* sigma, double* const* d_out, double h,
+                             double c, double gamma, const lx_leja_opts* o, int* iters, double* err) {
+    if (ctx == nullptr) return LX_EINVAL;
+    ctx->stats = lx_stats{};
+    lx_status s = lx_internal_check_op(ctx, op, lx::kStaticPoints);
+    if (s != LX_OK) return s;
+    if (op->prec != LX_FP64) return fail(ctx, LX_EINVAL, "lx_phi_leja_static runs FP64 sweeps only");
+    if (K < 1 || K > ctx->k_max) return fail(ctx, LX_EINVAL, "K = %d outside 1..%d", K, ctx->k_max);
+    if (d_v == nullptr || d_out == nullptr || l == nullptr) return fail(ctx, LX_EINVAL, "NULL vector or order array");
+    if (op->kind == LX_OP_BURGERS2D && d_u == nullptr) return fail(ctx, LX_EINVAL, "Burgers Jacobian needs d_u");
+    s = check_shift(ctx, h, c, gamma);
+    if (s != LX_OK) return s;
+    LejaCall q{};
+    s = check_leja_opts(ctx, o, &q.o);
+    if (s != LX_OK) return s;
+    q.op = op;
+    q.u = op->kind == LX_OP_BURGERS2D ? d_u : nullptr;
+    q.v = d_v;
+    q.K = K;
+    q.h = h;
+    q.c = c;
+    q.gamma = gamma;
+    double amax = 0.0;
+    for (int k = 0; k < K; ++k) {
+        if (l[k] < 0 || l[k] > 8) return fail(ctx, LX_EINVAL, "phi order l[%d] = %d outside 0..8", k, l[k]);
+        q.l[k] = l[k];
+        q.alpha[k] = alpha ? alpha[k] : 1.0;
+        q.sigma[k] = sigma ? sigma[k] : 1.0;
+        if (!(q.alpha[k] > 0.0) || !std::isfinite(q.alpha[k]) || !std::isfinite(q.sigma[k]))
+            return fail(ctx, LX_EINVAL, "alpha[%d] must be finite and > 0, sigma finite", k);
+        if (d_out[k] == nullptr) return fail(ctx, LX_EINVAL, "d_out[%d] is NULL", k);
+        if (d_out[k] == d_v || (q.u != nullptr && d_out[k] == q.u))
+            return fail(ctx, LX_EINVAL, "d_out[%d] aliases an input", k);
+        for (int j = 0; j < k; ++j)
+            if (d_out[j] == d_out[k]) return fail(ctx, LX_EINVAL, "d_out[%d] and d_out[%d] alias", j, k);
+        q.out[k] = d_out[k];
+        amax = std::max(amax, q.alpha[k]);
+    }
+    // one Leja call: substeps would need more workspace vectors
+    const int sub = q.o.substeps != 0 ? q.o.substeps
+                                      : static_cast<int>(std::max(1.0, std::ceil(amax * h * gamma / kSubstepHGamma)));
+    if (sub != 1) return fail(ctx, LX_EINVAL, "lx_phi_leja_static takes no substeps (this call would need %d)", sub);
+    // the library's static device scratch on the current device
+    int dev = 0;
+    LX_HIP(ctx, hipGetDevice(&dev));
+    LX_HIP(ctx, lx::static_scratch(dev, &q.scratch));
+    s = run_leja(ctx, q);
     for (int k = 0; k < K; ++k) {
         if (iters) iters[k] = ctx->stats.iters[k];
         if (err) err[k] = ctx->stats.err[k];

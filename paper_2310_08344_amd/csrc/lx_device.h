@@ -60,6 +60,15 @@ struct Tile {
     int rows() const { return ty * ry; }
 };
 
+// Static device scratch of lx_phi_leja_static (static_ws.hip): the basis
+// pair and the windows' second output buffers for grids of at most
+// kStaticPoints points, then kStaticPartials partial sums.
+constexpr size_t kStaticPoints = size_t{1} << 18;
+constexpr size_t kStaticPartials = size_t{2} * 4096 * 8 * (1 + kKMax);
+constexpr size_t kStaticDoubles = (2 + kKMax) * kStaticPoints + kStaticPartials;
+// The scratch's address on `device` (looked up once per device).
+hipError_t static_scratch(int device, double** out);
+
 // Launch shape of a batch, chosen by lx_tune_batched per batch class: Leja
 // iterations per launch (1, 2 or kBatchBlockDepth), tile rows of the two-
 // iteration and window kernels, and the points each workgroup of an
