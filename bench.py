@@ -434,6 +434,10 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper-shaped 8192^2 problems")
     ap.add_argument("--no-small", action="store_true", help="skip the 64^2 and 1024^2 workloads")
+    ap.add_argument("--window-kernel", type=int, default=0, choices=(0, 1, 2),
+                    help="kernel of the windows: 0 tuned, 1 LDS tiles, 2 register marching")
+    ap.add_argument("--depth", type=int, default=0, help="Leja iterations per launch (0: tuned)")
+    ap.add_argument("--tune-sweeps", type=int, default=24, help="Leja iterations each tuning candidate is timed on")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the phi-action path is single-GPU (--gpus {args.gpus} "
@@ -467,9 +471,14 @@ def main() -> int:
         log("calibration copy", extra["practical_copy_gbs"], "axpby", extra["practical_axpby_gbs"], "GB/s")
     if not args.no_tune:
         for K in (3, 2, 1):
-            best = min(ctx.tune(op, K=K, sweeps=8), key=lambda r: r[6])
+            best = min(ctx.tune(op, K=K, sweeps=args.tune_sweeps), key=lambda r: r[6])
             log(f"tuned K={K}: depth {best[0]} tx {best[1]} ty {best[2]} rows {best[3]} vec {best[4]} "
                 f"workgroups {best[5]} {best[6]:.1f} us per iteration")
+
+    if args.window_kernel or args.depth:
+        ctx.set_window_kernel(args.window_kernel)
+        ctx.set_depth(args.depth)
+        log("forced window kernel", args.window_kernel, "depth", args.depth)
 
     def step():
         rho, c, g = ctx.spectrum(op, x0=x0, iters=20)
