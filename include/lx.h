@@ -513,12 +513,15 @@ lx_status lx_set_tile(lx_ctx* ctx, int tx, int ty, int ry, int vec, int nb);
  * tiles (th 8 or 16; larger th is taken as 16; depths 3, 4, 6) or by
  * register marching (lx_set_window_kernel; depths 4, 6, 8); depth 0
  * restores the automatic choice (the tuned entry, else 2).
- * Depths 2..8 apply to FP64 sweeps on grids with even nx and 16-byte aligned
- * vectors; on LDS tiles 3 and 4 to the diffusion-advection operators and
+ * Depths 2..8 apply to grids with even nx and 16-byte aligned vectors; on
+ * LDS tiles (FP64 sweeps) 3 and 4 to the diffusion-advection operators and
  * the Burgers Jacobian, 6 to LX_OP_DIFFADV2D (others fall back to 4, then
  * 2), each with sides of at least depth times the stencil radius; register
- * marching to LX_OP_DIFFADV2D only (depth 4 for K <= 4, 6 for K <= 3, 8 for
- * K = 1; depth 8 otherwise falls back to 6); other calls use depth 1.
+ * marching to LX_OP_DIFFADV2D (FP64: depth 4 for K <= 4, 6 for K <= 3, 8
+ * for K = 1) and LX_OP_BURGERS2D (depth 4 for K <= 2, 6 for K = 1), and to
+ * FP32 sweeps of both for K <= 2 at depth 4 and K = 1 at 6 (windows switch
+ * to FP32 levels on the device); depth 8 otherwise falls back to 6; other
+ * calls use depth 1 (FP32 sweeps: one per launch).
  * Results agree with depth 1 to rounding (the outputs take the same terms
  * in the same order; only the order of the norm reductions differs).
  * Errors: LX_EINVAL (depth not 0..4, 6 or 8, th not 0, 8, 16 or 32, nb < 0). */
@@ -528,8 +531,9 @@ lx_status lx_set_depth(lx_ctx* ctx, int depth, int th, int nb);
  * kind 0 = automatic (windows as the tuned entry says, else LDS tiles;
  * power iteration by register marching where it applies), 1 = LDS tiles
  * for both (leja_block, power_block), 2 = register marching where it
- * applies (leja_stream, power_stream: LX_OP_DIFFADV2D, FP64, even nx,
- * sides >= depth, 16-byte aligned vectors; windows at depths 4, 6 and 8).
+ * applies (leja_stream: the five-point operators, FP64 or FP32 sweeps, at
+ * the depths lx_set_depth lists; power_stream: LX_OP_DIFFADV2D; even nx,
+ * sides >= depth, 16-byte aligned vectors).
  * Register marching gives every wavefront a strip of 128 columns (its
  * output columns and depth columns on each side) and a band of rows, which
  * it walks from top to bottom forming all levels of the window in
