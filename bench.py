@@ -17,8 +17,11 @@ Prints one JSON line on stdout:
                 every sweep of the timed steps; traffic from the committed
                 rocprofv3 counter summary when it was taken on the current
                 kernel source, else null
+  small_configs the 64^2 exp workload (rtol 1e-10) and the 1024^2 phi_1..phi_3
+                workload (rtol 1e-8): solves/s, time to solution
   batched_256   256 uneven instances in one batched call against the plain
-                per-instance path (both with power iteration)
+                per-instance path (both with power iteration), the tuned
+                batch shape, a whole-call roofline
   learned_1024  the learned + batched form against plain batched and plain
                 per-instance solves on 1024 instances at 256^2
   exprb42_2048  one EXPRB42 step of the 2048^2 Burgers workload, FP64 and
@@ -34,7 +37,9 @@ Prints one JSON line on stdout:
                 to a few iterations with three outputs and with one), scaled
                 to the GPU run's iteration counts; one thread and all cores
 
-Usage: python bench.py [--steps K] [--warmup W] [--no-tune] [--no-batched] [--no-paper] [--no-cpu-baseline]
+Usage: python bench.py [--steps K] [--warmup W] [--no-tune] [--no-calibrate] [--no-batched] [--no-learned]
+                       [--no-exprb] [--no-paper] [--no-small] [--no-cpu-baseline] [--window-kernel 0|1|2]
+                       [--depth D] [--tune-sweeps S]
 """
 from __future__ import annotations
 
@@ -396,7 +401,8 @@ def bench_exprb42(lib, n: int = 2048, repeats: int = 5) -> dict:
         op32 = B.make_operator(p)
         op32.prec = B.LX_FP32_SWEEP
         for K in (2, 1):
-            ctx.tune(op, K=K, sweeps=8)
+            ctx.tune(op, K=K, sweeps=24)
+            ctx.tune(op32, K=K, sweeps=24)
 
         def step(o, out):
             _, c, g = ctx.spectrum(o if o.prec == B.LX_FP64 else op, u=u0, x0=x0, iters=20)
@@ -414,7 +420,8 @@ def bench_exprb42(lib, n: int = 2048, repeats: int = 5) -> dict:
             torch.cuda.synchronize()
             dt = (time.perf_counter() - t0) / repeats
             res[name] = {"ms_per_step": round(dt * 1e3, 3), "iters_phi1_phi3": list(r.iters),
-                         "depth": r.stats["depth"], "fp32_sweeps": r.stats["n_fp32"]}
+                         "depth": r.stats["depth"], "register_marching": bool(r.stats["marching"]),
+                         "fp32_levels": r.stats["n_fp32"]}
         du64 = out64 - u0
         res["fp32_update_rel_diff_vs_fp64"] = float(torch.linalg.norm(out32 - out64) / torch.linalg.norm(du64))
     finally:
@@ -434,6 +441,8 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper-shaped 8192^2 problems")
     ap.add_argument("--no-small", action="store_true", help="skip the 64^2 and 1024^2 workloads")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned + batched comparison")
+    ap.add_argument("--no-exprb", action="store_true", help="skip the EXPRB42 Burgers step")
     ap.add_argument("--window-kernel", type=int, default=0, choices=(0, 1, 2),
                     help="kernel of the windows: 0 tuned, 1 LDS tiles, 2 register marching")
     ap.add_argument("--depth", type=int, default=0, help="Leja iterations per launch (0: tuned)")
@@ -572,9 +581,10 @@ def main() -> int:
     if not args.no_batched:
         log("batched 256-instance comparison")
         out["batched_256"] = bench_batched(lib)
+    if not args.no_batched and not args.no_learned:
         log("learned + batched on 1024 instances at 256^2")
         out["learned_1024"] = bench_learned(lib)
-    if not args.no_batched:
+    if not args.no_exprb:
         log("EXPRB42 step on the 2048^2 Burgers workload")
         out["exprb42_2048"] = bench_exprb42(lib)
     if not args.no_paper:

@@ -249,10 +249,12 @@ struct LejaCall {
     double* scratch = nullptr;
 };
 
-// Whether a call may run its windows by register marching at this depth.
+// Whether a call may run its windows by register marching at this depth
+// (the five-point operators, FP64 or FP32 sweeps).
 bool stream_ok(const lx_operator& op, int K, int depth) {
-    return op.kind == LX_OP_DIFFADV2D && op.prec == LX_FP64 && op.nx % 2 == 0 && lx::stream_has(K, depth) &&
-           op.nx >= depth && op.ny >= depth;
+    if (op.kind != LX_OP_DIFFADV2D && op.kind != LX_OP_BURGERS2D) return false;
+    return op.nx % 2 == 0 && op.nx >= depth && op.ny >= depth &&
+           lx::stream_has(opcode_of(op.kind), K, depth, op.prec == LX_FP32_SWEEP);
 }
 
 // Iterations per launch for this call: forced by lx_set_depth, else the
@@ -261,6 +263,8 @@ bool stream_ok(const lx_operator& op, int K, int depth) {
 // and six the five-point diffusion-advection operator (else four).
 void choose_depth(const lx_ctx* ctx, const lx_operator& op, int K, bool vec2_ok, Tile& t) {
     const bool pair_ok = op.prec == LX_FP64 && vec2_ok && op.nx % 2 == 0;
+    // register-marching windows also take FP32 sweeps
+    const bool march_ok = vec2_ok && op.nx % 2 == 0;
     auto it = ctx->tuned.find(std::make_tuple(op.kind, op.nx, op.ny, K, op.prec));
     int depth = 2;
     if (ctx->depth_forced != 0) depth = ctx->depth_forced;
@@ -271,7 +275,7 @@ void choose_depth(const lx_ctx* ctx, const lx_operator& op, int K, bool vec2_ok,
     // tuned entry's choice; eight iterations only that way
     const bool tuned_stream = it != ctx->tuned.end() && it->second.stream && it->second.depth == depth;
     t.stream = 0;
-    if (pair_ok && depth >= 3 && (ctx->win_kind == 2 || (ctx->win_kind == 0 && tuned_stream)) &&
+    if (march_ok && depth >= 3 && (ctx->win_kind == 2 || (ctx->win_kind == 0 && tuned_stream)) &&
         stream_ok(op, K, depth)) {
         t.stream = 1;
         t.depth = depth;
@@ -327,16 +331,18 @@ struct StreamGrid {
     int strips, bands, nb;
 };
 
-StreamGrid stream_grid(int nx, int ny, int K, int D, int bands, int nb, bool power) {
+StreamGrid stream_grid(int op, bool fp32, int nx, int ny, int K, int D, int bands, int nb, bool power) {
     StreamGrid g;
     g.strips = lx::stream_strips(nx, D);
-    const int resident = lx::stream_resident(K, D, power ? 1 : 0);
-    const int waves = (resident > 0 ? resident : 512) * (lx::kBlockThreads / 64);
+    const int resident = lx::stream_resident(op, K, D, fp32, power ? 1 : 0);
+    // wavefronts per item: power sweeps one, windows one per group of outputs
+    const int per_item = power ? 1 : lx::stream_groups(K, D);
+    const int waves = (resident > 0 ? resident : 512) * (lx::kBlockThreads / 64) / per_item;
     int by = bands;
     if (by <= 0) by = std::max(1, std::min(waves / g.strips, ny / (4 * D)));
     g.bands = std::max(1, std::min(by, ny));
     const int items = g.strips * g.bands;
-    int wgs = nb > 0 ? nb : (items + 3) / 4;
+    int wgs = nb > 0 ? nb : (items * per_item + 3) / 4;
     if (nb <= 0 && resident > 0) wgs = std::min(wgs, resident);
     if (nb <= 0 && wgs >= 8) {
         const int up = (wgs + 7) & ~7;
@@ -422,7 +428,7 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
     a.nx = nx;
     a.ny = ny;
     if (t.stream) {
-        const StreamGrid g = stream_grid(nx, ny, K, D, t.bands, t.snb, false);
+        const StreamGrid g = stream_grid(opcode_of(op.kind), fp32, nx, ny, K, D, t.bands, t.snb, false);
         a.tiles_x = g.strips;
         a.tiles_y = g.bands;
         a.nb = g.nb;
@@ -502,7 +508,7 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
         if (s != LX_OK) return s;
         for (int i = 0; i < n; ++i) {
             const int L = launched + i;
-            if (t.stream) LX_HIP(ctx, lx::launch_leja_stream(K, D, a, L, ctx->stream));
+            if (t.stream) LX_HIP(ctx, lx::launch_leja_stream(opcode, K, D, fp32, a, L, ctx->stream));
             else if (blk) LX_HIP(ctx, lx::launch_leja_block(opcode, K, t.th, D, a, L, ctx->stream));
             else if (pair) LX_HIP(ctx, lx::launch_leja_pair(opcode, K, t.th, a, L, ctx->stream));
             else LX_HIP(ctx, lx::launch_leja_sweep(opcode, K, fp32, t, a, L, ctx->stream));
@@ -816,7 +822,7 @@ lx_status spectrum_stream(lx_ctx* ctx, const lx_operator& op, const double* x0, 
     const double g = std::fabs(pk[0]) + std::fabs(pk[1]) + std::fabs(pk[2]) + std::fabs(pk[3]) + std::fabs(pk[4]);
     const int cap = g > 10.0 ? static_cast<int>(140.0 / std::log10(g)) : DP;
     const int per = std::max(1, std::min(DP, cap));
-    const StreamGrid sg = stream_grid(nx, ny, 1, DP, 0, 0, true);
+    const StreamGrid sg = stream_grid(lx::kOpDiffAdv, false, nx, ny, 1, DP, 0, 0, true);
     PowerArgs a{};
     a.nx = nx;
     a.ny = ny;
@@ -1562,11 +1568,15 @@ lx_status lx_tune(lx_ctx* ctx, const lx_operator* op, int K, int sweeps, char* r
     init.max_iters = LX_MAX_ITERS;
     init.rtol = 0.0;
     init.atol = -1.0;
-    init.fp32_switch = -1.0;
+    // FP32 sweeps are timed in FP32 from the first sweep
+    init.fp32_switch = op->prec == LX_FP32_SWEEP ? 0.0 : -1.0;
+    init.slot[0].out32 = op->prec == LX_FP32_SWEEP ? 1 : 0;
     for (int k = 0; k < K; ++k) {
         init.slot[0].active[k] = 1;
         init.slot[0].iters[k] = LX_MAX_ITERS;
     }
+    if (op->prec == LX_FP32_SWEEP && hipMemsetAsync(ctx->u32, 0, sizeof(float) * N, ctx->stream) != hipSuccess)
+        return cleanup(fail(ctx, LX_EDEVICE, "tuning scratch clear failed"));
     s = ensure_timing_events(ctx, 2);
     if (s != LX_OK) return cleanup(s);
 
@@ -1636,14 +1646,15 @@ lx_status lx_tune(lx_ctx* ctx, const lx_operator* op, int K, int sweeps, char* r
             best = t;
         }
     }
-    // several iterations per launch (FP64, even nx): depth x tile rows x
-    // workgroups; depths 3 and 4 (speculative windows) for the five-point
-    // diffusion-advection operator only
+    // several iterations per launch (even nx): in FP64, two iterations and
+    // LDS-tile windows, depth x tile rows x workgroups; register-marching
+    // windows (FP64 or FP32 sweeps), depth x bands
     best.depth = 1;
     double best_pair_us = 1e300;
-    if (op->prec == LX_FP64 && nx % 2 == 0) {
+    if (nx % 2 == 0) {
         const int tiles_x = (nx + 127) / 128;
         for (int depth : {2, 3, 4, 6}) {
+            if (op->prec != LX_FP64) break;
             if (depth == 6 && op->kind != LX_OP_DIFFADV2D) continue;
             const int halo = depth * (op->kind == LX_OP_DIFFADV2D_UP3 ? 2 : 1);
             if (depth >= 3 && (nx < halo || ny < halo)) continue;
@@ -1711,19 +1722,19 @@ lx_status lx_tune(lx_ctx* ctx, const lx_operator* op, int K, int sweeps, char* r
                 }
             }
         }
-        // windows by register marching (the five-point diffusion-advection
-        // operator): depth x bands (one resident round, two rounds, and
-        // bands of 64 and 128 rows)
+        // windows by register marching (the five-point operators; FP32 sweeps
+        // timed in FP32 throughout): depth x bands (one resident round, two
+        // rounds, and bands of 64 and 128 rows)
         for (int depth : {4, 6, 8}) {
             if (!stream_ok(*op, K, depth)) continue;
             s = ensure_blk_ws(ctx, K);
             if (s != LX_OK) return cleanup(s);
-            const StreamGrid g0 = stream_grid(nx, ny, K, depth, 0, 0, false);
+            const StreamGrid g0 = stream_grid(opcode, fp32, nx, ny, K, depth, 0, 0, false);
             int prev_bands = -1;
             for (int bands : {g0.bands, 2 * g0.bands, ny / 64, ny / 128}) {
                 if (bands < 1 || bands > ny || bands == prev_bands) continue;
                 prev_bands = bands;
-                const StreamGrid g = stream_grid(nx, ny, K, depth, bands, 0, false);
+                const StreamGrid g = stream_grid(opcode, fp32, nx, ny, K, depth, bands, 0, false);
                 SweepArgs a{};
                 a.nx = nx;
                 a.ny = ny;
@@ -1736,6 +1747,8 @@ lx_status lx_tune(lx_ctx* ctx, const lx_operator* op, int K, int sweeps, char* r
                 a.v = ctx->ybuf[0];
                 a.ybuf[0] = ctx->ybuf[0];
                 a.ybuf[1] = ctx->ybuf[1];
+                a.u = op->kind == LX_OP_BURGERS2D ? scratch + static_cast<size_t>(K) * N : nullptr;
+                a.u32 = ctx->u32;
                 for (int k = 0; k < K; ++k) {
                     a.p[k] = scratch + static_cast<size_t>(k) * N;
                     a.p2[k] = ctx->blk_ws[k];
@@ -1750,10 +1763,11 @@ lx_status lx_tune(lx_ctx* ctx, const lx_operator* op, int K, int sweeps, char* r
                     return cleanup(fail(ctx, LX_EDEVICE, "state upload failed"));
                 const int n = std::max(1, sweeps / depth);
                 hipError_t e = hipSuccess;
-                for (int L = 0; L < 2 && e == hipSuccess; ++L) e = lx::launch_leja_stream(K, depth, a, L, ctx->stream);
+                for (int L = 0; L < 2 && e == hipSuccess; ++L)
+                    e = lx::launch_leja_stream(opcode, K, depth, fp32, a, L, ctx->stream);
                 if (e == hipSuccess) e = hipEventRecord(ctx->tev[0], ctx->stream);
                 for (int L = 2; L < n + 2 && e == hipSuccess; ++L)
-                    e = lx::launch_leja_stream(K, depth, a, L, ctx->stream);
+                    e = lx::launch_leja_stream(opcode, K, depth, fp32, a, L, ctx->stream);
                 if (e == hipSuccess) e = hipEventRecord(ctx->tev[1], ctx->stream);
                 if (e == hipSuccess) e = hipEventSynchronize(ctx->tev[1]);
                 if (e != hipSuccess)

@@ -185,19 +185,24 @@ hipError_t launch_power_block(int op, const PowerArgs& a, const double* in, doub
                               hipStream_t s);
 hipError_t launch_power_block_final(const PowerArgs& a, int b, int nlev, hipStream_t s);
 // Windows by register streaming (stream.hip; the five-point
-// diffusion-advection operator, FP64, nx even, sides >= depth, 16-byte
-// aligned vectors): depth 4 or 6 (8 for K <= 2); a.tiles_x =
-// stream_strips(nx, depth) strips of 128 - 2 depth output columns by
-// a.tiles_y (1..ny) bands of rows, a.nb workgroups of four wavefronts that
-// each take items (strip, band) in turn; partials as launch_leja_block.
+// diffusion-advection operator or the Burgers Jacobian (a.u, and a.u32 for
+// FP32 sweeps), nx even, sides >= depth, 16-byte aligned vectors); fp32:
+// FP32 sweeps (the device switches windows to FP32 levels, LoopCtl
+// fp32_switch); a.tiles_x = stream_strips(nx, depth) strips of
+// 128 - 2 depth output columns by a.tiles_y (1..ny) bands of rows, a.nb
+// workgroups of four wavefronts that each take items (strip, band) in turn;
+// partials as launch_leja_block.
 int stream_strips(int nx, int depth);
-// whether leja_stream is built for K outputs at this depth (4: K <= 4;
-// 6: K <= 3; 8: K = 1)
-bool stream_has(int K, int depth);
-hipError_t launch_leja_stream(int K, int depth, const SweepArgs& a, int L, hipStream_t s);
-// workgroups of leja_stream<K, depth> (power = 0) or of power_stream
-// (power = 1) resident at once on the current device (0 if unknown)
-int stream_resident(int K, int depth, int power);
+// wavefronts that take each item of a window launch (two groups of outputs
+// for K = 3 at depth 6, else one)
+int stream_groups(int K, int depth);
+// whether leja_stream is built for this operator (kOp*), K outputs, depth
+// and precision mode
+bool stream_has(int op, int K, int depth, bool fp32);
+hipError_t launch_leja_stream(int op, int K, int depth, bool fp32, const SweepArgs& a, int L, hipStream_t s);
+// workgroups of that leja_stream (power = 0) or of power_stream (power = 1)
+// resident at once on the current device (0 if unknown)
+int stream_resident(int op, int K, int depth, bool fp32, int power);
 // Power iteration by register streaming, up to kPowerStreamDepth sweeps per
 // launch (the five-point diffusion-advection operator; nx even, sides >=
 // kPowerStreamDepth, a.tiles_x = stream_strips(nx, kPowerStreamDepth),

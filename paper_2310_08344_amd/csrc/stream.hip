@@ -67,18 +67,50 @@ __device__ __forceinline__ int stream_wave(const int wg, const int nb) {
     return slot * kStreamWaves + wave;
 }
 
-// The five-point operator of shifted_at, split in two so that a level keeps
-// only two rows in registers: stream_partial takes this lane's column pair
-// of row C (the side columns from the neighbouring lanes) and the row S
-// before it, and forms everything but the last term; stream_complete adds
-// the term of the row N after it.  The operand order is stencil_da's:
+template <typename T>
+using P2 = typename Pair<T>::type;
+
+// v of lane l - 1 (kFromBelow) or l + 1 in FP32 (one DPP move; see
+// lane_neighbour for FP64).  Every lane of the wavefront must be active.
+template <bool kFromBelow>
+__device__ __forceinline__ float lane_neighbour32(const float v, const float old) {
+    constexpr int ctrl = kFromBelow ? 0x138 : 0x130;
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), ctrl, 0xf, 0xf, false));
+}
+
+template <bool kFromBelow, typename T>
+__device__ __forceinline__ T nbr(const T v) {
+    if constexpr (sizeof(T) == sizeof(double)) return lane_neighbour<kFromBelow>(v, v);
+    else return lane_neighbour32<kFromBelow>(v, v);
+}
+
+// The stencil's coefficients in the arithmetic of the levels: c0..c3 and
+// the unshifted centre c4 (Sten's order; the shifted centres are per level).
+template <typename T>
+struct StenT {
+    T c0, c1, c2, c3;
+};
+
+template <typename T>
+__device__ __forceinline__ StenT<T> sten_as(const Sten& s) {
+    return StenT<T>{static_cast<T>(s.c0), static_cast<T>(s.c1), static_cast<T>(s.c2), static_cast<T>(s.c3)};
+}
+
+// The five-point diffusion-advection operator of shifted_at, split in two
+// so that a level keeps only two rows in registers: stream_partial takes
+// this lane's column pair of row C (the side columns from the neighbouring
+// lanes) and the row S before it, and forms everything but the last term;
+// stream_complete adds the term of the row N after it.  The operand order is
+// stencil_da's:
 //   fma(cN, N, fma(cS, S, fma(cE, E, fma(cW, W, cC C)))),
-// so every kernel forms the same bits.  All 64 lanes must be active.
-__device__ __forceinline__ double2 stream_partial(const Sten& st, const double cc, const double2 S, const double2 C) {
+// so every kernel forms the same bits (in either precision).  All 64 lanes
+// must be active.
+template <typename T>
+__device__ __forceinline__ P2<T> stream_partial(const StenT<T>& st, const T cc, const P2<T> S, const P2<T> C) {
 #pragma clang fp contract(off)
-    const double w = lane_neighbour<true>(C.y, C.y);    // column j - 1: lane - 1's second column
-    const double e = lane_neighbour<false>(C.x, C.x);   // column j + 2: lane + 1's first column
-    double2 o;
+    const T w = nbr<true>(C.y);    // column j - 1: lane - 1's second column
+    const T e = nbr<false>(C.x);   // column j + 2: lane + 1's first column
+    P2<T> o;
     o.x = fma(st.c2, S.x, fma(st.c1, C.y, fma(st.c0, w, cc * C.x)));
     o.y = fma(st.c2, S.y, fma(st.c1, e, fma(st.c0, C.x, cc * C.y)));
     // formed here, not where the next step uses it: the neighbour values
@@ -88,106 +120,223 @@ __device__ __forceinline__ double2 stream_partial(const Sten& st, const double c
     return o;
 }
 
-__device__ __forceinline__ double2 stream_complete(const Sten& st, const double2 q, const double2 N) {
-    double2 o;
+template <typename T>
+__device__ __forceinline__ P2<T> stream_complete(const StenT<T>& st, const P2<T> q, const P2<T> N) {
+    P2<T> o;
     o.x = fma(st.c3, N.x, q.x);
     o.y = fma(st.c3, N.y, q.y);
     return o;
 }
 
+// The Burgers Jacobian J(u) (stencil_bu, the same operands in the same
+// order as every other kernel) on this lane's column pair of row C, with the
+// rows S before and N after it and the state u on those rows; the side
+// columns of C and of u on C come from the neighbouring lanes.  All 64 lanes
+// must be active.
+template <typename T>
+__device__ __forceinline__ P2<T> stream_burgers(const StenT<T>& k, const T kc, const P2<T> S, const P2<T> C,
+                                                const P2<T> N, const P2<T> uS, const P2<T> uC, const P2<T> uN) {
+    const T w = nbr<true>(C.y), e = nbr<false>(C.x);
+    const T uw = nbr<true>(uC.y), ue = nbr<false>(uC.x);
+    P2<T> o;
+    o.x = stencil_bu<T>(k.c0, k.c1, k.c2, k.c3, kc, w, C.y, S.x, N.x, C.x, uw, uC.y, uS.x, uN.x);
+    o.y = stencil_bu<T>(k.c0, k.c1, k.c2, k.c3, kc, C.x, e, S.y, N.y, C.y, uC.x, ue, uS.y, uN.y);
+    return o;
+}
+
 __device__ __forceinline__ double2 ld_pair(const double* p) { return *reinterpret_cast<const double2*>(p); }
 
-__device__ __forceinline__ double sel(const bool c, const double a, const double b) { return c ? a : b; }
+// A column pair of a stored vector: from FP32 storage (f32, widened
+// exactly) or FP64.
+__device__ __forceinline__ double2 ld_level64(const void* base, const long off, const bool f32) {
+    if (f32) {
+        const float2 f = *reinterpret_cast<const float2*>(static_cast<const float*>(base) + off);
+        return double2{static_cast<double>(f.x), static_cast<double>(f.y)};
+    }
+    return ld_pair(static_cast<const double*>(base) + off);
+}
 
-// One item of a window launch (see the file comment).  dk[k][j] = d_{m+j}
-// of output k, cc[j-1] the centre coefficient of level j.
+// The Burgers state's column pair in T: the FP64 state or its FP32 copy.
+template <typename T>
+__device__ __forceinline__ P2<T> ld_state(const void* base, const long off) {
+    if constexpr (sizeof(T) == sizeof(double)) return ld_pair(static_cast<const double*>(base) + off);
+    else return *reinterpret_cast<const float2*>(static_cast<const float*>(base) + off);
+}
+
+template <typename T>
+__device__ __forceinline__ double2 as_d2(const P2<T> v) {
+    return double2{static_cast<double>(v.x), static_cast<double>(v.y)};
+}
+
+template <typename T>
+__device__ __forceinline__ P2<T> as_t2(const double2 v) {
+    return P2<T>{static_cast<T>(v.x), static_cast<T>(v.y)};
+}
+
+// One item of a window launch (see the file comment), the levels in T (FP64,
+// or FP32 for FP32 sweeps: the basis vectors and the stencil arithmetic;
+// the outputs, the terms d_{m+j} y_{m+j} and the sums of squares stay FP64).
+// dk[k][j] = d_{m+j} of output k, cc[j-1] the centre coefficient of level j.
 //
-// Entering step t, lc[j] holds level j at row t-j-1 and lq[j] level j+1 at
-// row t-j-1 without its last term; the step completes level j+1 there with
-// level j at row t-j, which it has just formed.  Every step forms all D
-// levels: before step 2j, level j is formed on rows whose inputs are not all
-// staged yet, but such rows only feed rows of higher levels that are
-// equally invalid, and no output row is among them (outputs start at row
-// D).  A re-execution forms all D levels as well and takes only the terms
-// its outputs need.  pr[k][i] holds output k at row t-1-i; slots of rows
-// outside the band take no terms and are not stored.  Steps run in pairs,
-// which the roles of lc and lq repeat with, so that they stay in place; an
-// odd count adds one step past the staged rows that stores nothing.
-template <int K, int D>
+// Diffusion-advection: entering step t, lc[j] holds level j at row t-j-1
+// and lq[j] level j+1 at row t-j-1 without its last term; the step
+// completes level j+1 there with level j at row t-j, which it has just
+// formed.  Burgers: lq[j] holds level j at row t-j-2 and lc[j] at row t-j-1,
+// and the step forms level j+1 at row t-j-1 whole once level j at row t-j
+// exists; ur[i] holds u at row t-i (D + 2 rows: level j needs u on rows
+// t-j-1 .. t-j+1).  Every step forms all D levels: before step 2j, level j is
+// formed on rows whose inputs are not all staged yet, but such rows only
+// feed rows of higher levels that are equally invalid, and no output row is
+// among them (outputs start at row D).  A re-execution forms the levels up
+// to the last term an output that stopped inside the window takes, and
+// takes only those terms; outputs that stopped after the window's last term
+// are copied (or kept) instead of recomputed (window_enter).  pr[k][i] holds
+// output k at row t-1-i; slots of rows outside the band take no terms and
+// are not stored.  Steps run in pairs, which the roles of lc and lq repeat
+// with, so that they stay in place; an odd count adds one step past the
+// staged rows that stores nothing.
+template <int OP, int K, int D, typename T>
 __device__ __forceinline__ void stream_window_item(const TileArgs<K>& ta, const WindowPlan<K>& w,
-                                                   const double (&dk)[K][D + 1], const double (&cc)[D],
-                                                   const StreamItem it, const int lane, double (&sy)[D],
-                                                   double (&sp)[K][D]) {
+                                                   const void* __restrict__ ustate, const double (&dk)[K][D + 1],
+                                                   const double (&cc)[D], const StreamItem it, const int lane,
+                                                   double (&sy)[D], double (&sp)[K][D]) {
+    constexpr bool BU = OP == kOpBurgersJ;
     const int nx = ta.nx, ny = ta.ny;
     const int rc = 2 * lane - D;                 // strip column of this lane's pair
     const int gcol = wrap(it.xs + rc, nx);       // even: xs, D and nx are
     const bool ocol = rc >= 0 && rc < it.ws;
     const double mcol = ocol ? 1.0 : 0.0;        // weight of this lane in the sums
-    const int T = it.hb + 2 * D;                 // rows staged: the band and D above and below
+    const int T_ = it.hb + 2 * D;                // rows staged: the band and D above and below
     const int ytop = it.yb - D;
-    const bool first = w.win == 0, store_y = !w.redo;
-    const double* __restrict__ yin = w.yin;
+    const bool first = w.win == 0, store_y = !w.redo && w.yout != nullptr;
+    const bool levels = w.jmax > 0;              // a re-execution that only copies reads no y
+    const bool in32 = sizeof(T) == sizeof(float) && w.in32;   // y_m stored in FP32 (FP32 levels only)
+    const void* __restrict__ yin = w.yin;
+    const StenT<T> st = sten_as<T>(ta.st);
     auto row_off = [&](const int t) { return static_cast<long>(wrap(ytop + t, ny)) * nx + gcol; };
 
-    double2 lc[D], lq[D];
+    P2<T> lc[D], lq[D];
+    P2<T> ur[BU ? D + 2 : 1];
     double2 pr[K][D];
 #pragma unroll
-    for (int j = 0; j < D; ++j) lc[j] = lq[j] = double2{0.0, 0.0};
+    for (int j = 0; j < D; ++j) lc[j] = lq[j] = P2<T>{0, 0};
+#pragma unroll
+    for (int i = 0; i < (BU ? D + 2 : 1); ++i) ur[i] = P2<T>{0, 0};
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
         for (int i = 0; i < D; ++i) pr[k][i] = double2{0.0, 0.0};
-    // level 0 two rows ahead (T >= 2D >= 2)
-    double2 yq0 = ld_pair(yin + row_off(0));
-    double2 yq1 = ld_pair(yin + row_off(1));
+    // Loads run ahead of their use, as far as registers allow without spills
+    // at two wavefronts per SIMD: level 0 three rows ahead with at most eight
+    // output rows in flight (K D) and the five-point operator in FP64, else
+    // two; each output row fetched one step before it enters (used two steps
+    // after its load is issued) with at most twelve, except K = 2, D = 6,
+    // else in the step it enters.  The Burgers state u (in T: the FP32 copy
+    // for FP32 levels) rides with level 0.
+    constexpr int YQ = (K * D <= 8 && !BU && sizeof(T) == sizeof(double)) ? 3 : 2;
+    constexpr bool PFP = K * D <= 12 && !(K == 2 && D == 6);
+    // level 0 is held as stored, exactly (its FP64 value gives p_0 = d_0 y_0)
+    double2 yq0{0.0, 0.0}, yq1{0.0, 0.0}, yq2{0.0, 0.0};
+    P2<T> uq0{0, 0}, uq1{0, 0};
+    if (levels) {
+        yq0 = ld_level64(yin, row_off(0), in32);
+        yq1 = ld_level64(yin, row_off(1), in32);
+        if (YQ == 3) yq2 = ld_level64(yin, row_off(2), in32);
+        if constexpr (BU) {
+            uq0 = ld_state<T>(ustate, row_off(0));
+            uq1 = ld_state<T>(ustate, row_off(1));
+        }
+    }
+    double2 pf[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) pf[k] = double2{0.0, 0.0};   // row 0 is no output row (D >= 1)
 
-    for (int t0 = 0; t0 < T; t0 += 2) {
+    for (int t0 = 0; t0 < T_; t0 += 2) {
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             const int t = t0 + u;
-            double2 cur = yq0;
+            const double2 cur64 = yq0;
+            P2<T> cur = as_t2<T>(cur64);
             yq0 = yq1;
-            yq1 = ld_pair(yin + row_off(t + 2 < T ? t + 2 : T - 1));
-            // an output row enters when level 0 reaches it
+            if (YQ == 3) {
+                yq1 = yq2;
+                if (levels) yq2 = ld_level64(yin, row_off(t + 3 < T_ ? t + 3 : T_ - 1), in32);
+            } else if (levels) {
+                yq1 = ld_level64(yin, row_off(t + 2 < T_ ? t + 2 : T_ - 1), in32);
+            }
+            if constexpr (BU) {
+#pragma unroll
+                for (int i = D + 1; i > 0; --i) ur[i] = ur[i - 1];
+                ur[0] = uq0;   // u at row t
+                uq0 = uq1;
+                if (levels) uq1 = ld_state<T>(ustate, row_off(t + 2 < T_ ? t + 2 : T_ - 1));
+            }
+            // an output row enters when level 0 reaches it; the next one is
+            // fetched now
             double2 pn[K];
-            const bool orow = t >= D && t < D + it.hb;
+            const bool orow0 = t >= D && t < D + it.hb;
+            const bool orow1 = t + 1 >= D && t + 1 < D + it.hb;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                pn[k].x = dk[k][0] * cur.x;   // p_0 = d_0 y_0 (first window)
-                pn[k].y = dk[k][0] * cur.y;
-                if (orow && !first && w.nt[k] > 0 && ocol) pn[k] = ld_stream(w.pin[k] + row_off(t));
+                // the first window starts from p_0 = d_0 y_0 (also when it is
+                // re-executed); a copy reads the window's own result
+                const bool fk = first && !w.copy[k];
+                const bool rd = !fk && (w.nt[k] > 0 || w.copy[k]) && ocol;
+                if constexpr (PFP) {
+                    pn[k] = pf[k];
+                    if (fk) {
+                        pn[k].x = dk[k][0] * cur64.x;
+                        pn[k].y = dk[k][0] * cur64.y;
+                    }
+                    if (orow1 && rd) pf[k] = ld_stream(w.pin[k] + row_off(t + 1));
+                } else {
+                    pn[k].x = dk[k][0] * cur64.x;
+                    pn[k].y = dk[k][0] * cur64.y;
+                    if (orow0 && rd) pn[k] = ld_stream(w.pin[k] + row_off(t));
+                }
             }
 #pragma unroll
             for (int j = 1; j <= D; ++j) {
-                // cur: level j-1 at row t-j+1
-                const double2 y = stream_complete(ta.st, lq[j - 1], cur);   // level j at row t-j
-                lq[j - 1] = stream_partial(ta.st, cc[j - 1], lc[j - 1], cur);
-                lc[j - 1] = cur;
+                // a re-execution forms only the levels its terms need
+                if (j > w.jmax) continue;
+                // cur: level j-1 at row t-j+1; y: level j at row t-j
+                P2<T> y;
+                const T ccj = static_cast<T>(cc[j - 1]);
+                if constexpr (BU) {
+                    y = stream_burgers<T>(st, ccj, lq[j - 1], lc[j - 1], cur, ur[j + 1], ur[j], ur[j - 1]);
+                    lq[j - 1] = lc[j - 1];
+                    lc[j - 1] = cur;
+                } else {
+                    y = stream_complete<T>(st, lq[j - 1], cur);
+                    lq[j - 1] = stream_partial<T>(st, ccj, lc[j - 1], cur);
+                    lc[j - 1] = cur;
+                }
                 cur = y;
+                const double2 y64 = as_d2<T>(y);
                 // masks as factors, not selects: a select of a product
                 // becomes a branch, which splits the step into blocks
                 const int r = t - j;
                 const bool take = r >= D && r < D + it.hb && j <= w.jmax;
                 const double m = take ? mcol : 0.0;
-                sy[j - 1] = fma(m, y.x * y.x + y.y * y.y, sy[j - 1]);
+                sy[j - 1] = fma(m, y64.x * y64.x + y64.y * y64.y, sy[j - 1]);
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     const bool tk = take && w.nt[k] >= j;
                     const double d = tk ? dk[k][j] : 0.0;   // no term: p + 0 y
                     double2& p = pr[k][j - 1];
-                    p.x = fma(d, y.x, p.x);
-                    p.y = fma(d, y.y, p.y);
+                    p.x = fma(d, y64.x, p.x);
+                    p.y = fma(d, y64.y, p.y);
                     sp[k][j - 1] = fma(tk ? mcol : 0.0, p.x * p.x + p.y * p.y, sp[k][j - 1]);
                 }
             }
             // row t-D is complete: y_{m+D} and every output that took terms
             // (an output that stopped after term j < D has not changed since)
-            if (t >= 2 * D && t < T && ocol) {
+            if (t >= 2 * D && t < T_ && ocol) {
                 const long o = row_off(t - D);
-                if (store_y) *reinterpret_cast<double2*>(w.yout + o) = cur;
+                if (store_y) *reinterpret_cast<P2<T>*>(reinterpret_cast<T*>(w.yout) + o) = cur;
 #pragma unroll
                 for (int k = 0; k < K; ++k)
-                    if (w.nt[k] > 0) st_stream(w.pout[k] + o, pr[k][D - 1]);
+                    if (w.nt[k] > 0 || w.copy[k]) st_stream(w.pout[k] + o, pr[k][D - 1]);
             }
 #pragma unroll
             for (int k = 0; k < K; ++k) {
@@ -199,23 +348,119 @@ __device__ __forceinline__ void stream_window_item(const TileArgs<K>& ta, const 
     }
 }
 
-// Launch L of the window loop: a.tiles_x strips by a.tiles_y bands, a.nb
-// workgroups of kStreamWaves wavefronts.
+// A re-execution that forms no level only copies outputs that stopped after
+// the last term of an even window from that window's buffer to the
+// caller's: each lane copies its column pair of the item's band, eight rows
+// in flight per output.
+template <int K>
+__device__ __forceinline__ void stream_copy_item(const WindowPlan<K>& w, const StreamItem it, const int lane,
+                                                 const int nx) {
+    const int c = 2 * lane;
+    if (c >= it.ws) return;
+    const long col = it.xs + c;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (!w.copy[k]) continue;
+        for (int r0 = 0; r0 < it.hb; r0 += 8) {
+            double2 v[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                if (r0 + i < it.hb) v[i] = ld_stream(w.pin[k] + static_cast<long>(it.yb + r0 + i) * nx + col);
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                if (r0 + i < it.hb) st_stream(w.pout[k] + static_cast<long>(it.yb + r0 + i) * nx + col, v[i]);
+        }
+    }
+}
+
+// Wavefront groups of a window launch: with three outputs at depth 6 one
+// wavefront holding every output's rows in flight would need more registers
+// than two wavefronts per SIMD leave, so two wavefronts take each item, one
+// for two outputs and one for the third; the basis vector is read twice
+// (the second read mostly from the caches) and its levels formed twice.
 template <int K, int D>
+constexpr int kStreamGroups = (K == 3 && D == 6) ? 2 : 1;
+template <int K, int D>
+constexpr int kStreamGroupOutputs = (K == 3 && D == 6) ? 2 : K;
+
+// The items of one group (FP64 levels): outputs K0 .. K0+KN-1 of the
+// window; the wavefront's index `wave` (its group is wave & 1) walks the
+// items of its group.  sy: the levels' sums (group 0 only).
+template <int OP, int K, int D, int K0, int KN>
+__device__ __forceinline__ void stream_group(const TileArgs<K>& ta, const WindowPlan<K>& w, const double* u,
+                                             const double (&cc)[D], const SweepArgs& a, const int wave,
+                                             const int lane, double (&sy)[D], double (&sp)[KN][D]) {
+    WindowPlan<KN> g;
+    g.m = w.m;
+    g.win = w.win;
+    g.redo = w.redo;
+    g.win32 = false;
+    g.in32 = false;
+    g.yin = w.yin;
+    g.yout = K0 == 0 ? w.yout : nullptr;
+    g.jmax = w.redo ? 0 : D;
+    double gk[KN][D + 1];
+#pragma unroll
+    for (int k = 0; k < KN; ++k) {
+        g.nt[k] = w.nt[K0 + k];
+        g.copy[k] = w.copy[K0 + k];
+        g.pin[k] = w.pin[K0 + k];
+        g.pout[k] = w.pout[K0 + k];
+        if (g.nt[k] > g.jmax) g.jmax = g.nt[k];
+#pragma unroll
+        for (int j = 0; j <= D; ++j) gk[k][j] = a.coef[(K0 + k) * a.ld + w.m + j];
+    }
+    TileArgs<KN> tg;
+    tg.nx = ta.nx;
+    tg.ny = ta.ny;
+    tg.tiles_x = ta.tiles_x;
+    tg.ld = ta.ld;
+    tg.st = ta.st;
+    tg.u = ta.u;
+    tg.coef = ta.coef;
+    tg.xi = ta.xi;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        sy[j] = 0.0;
+#pragma unroll
+        for (int k = 0; k < KN; ++k) sp[k][j] = 0.0;
+    }
+    // a group with nothing to form in a re-execution (copies are done on
+    // the launch's copy path) skips its items
+    if (g.jmax == 0) return;
+    const int items = a.tiles_x * a.tiles_y, G = a.nb * kStreamWaves;
+    // the wavefronts of one group are every other one: item i of the grid's
+    // strips x bands goes to the wavefronts of index 2i and 2i + 1
+    for (int i = wave >> 1; i < items; i += G >> 1)
+        stream_window_item<OP, KN, D, double>(tg, g, u, gk, cc, stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y),
+                                              lane, sy, sp);
+    // only group 0 stores the basis vector and counts its sums
+    if constexpr (K0 != 0) {
+#pragma unroll
+        for (int j = 0; j < D; ++j) sy[j] = 0.0;
+    }
+}
+
+// Launch L of the window loop: a.tiles_x strips by a.tiles_y bands, a.nb
+// workgroups of kStreamWaves wavefronts.  F32: FP32 sweeps (windows switch
+// to FP32 levels on the device, window_enter; both precisions in one kernel).
+template <int OP, int K, int D, bool F32>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void leja_stream(SweepArgs a,
                                                                                                 const int L) {
     if (loop_ended(a.ctl)) return;
     const int wg = static_cast<int>(blockIdx.x);
     WindowPlan<K> w;
-    if (!window_enter<kOpDiffAdv, K, D>(a, L, wg, nullptr, w)) return;
+    if (!window_enter<OP, K, D, true, F32>(a, L, wg, nullptr, w)) return;
+    // the window's coefficients (groups of wavefronts load their own)
     double dk[K][D + 1], cc[D];
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
-        for (int j = 0; j <= D; ++j) dk[k][j] = a.coef[k * a.ld + w.m + j];
+        for (int j = 0; j <= D; ++j) dk[k][j] = kStreamGroups<K, D> > 1 ? 0.0 : a.coef[k * a.ld + w.m + j];
+    const double centre = OP == kOpBurgersJ ? a.kC : a.aC;
 #pragma unroll
-    for (int j = 0; j < D; ++j) cc[j] = a.aC - a.xi[w.m + j];
-    const TileArgs<K> ta = tile_args<kOpDiffAdv, K>(a);
+    for (int j = 0; j < D; ++j) cc[j] = centre - a.xi[w.m + j];
+    const TileArgs<K> ta = tile_args<OP, K>(a);
     double sy[D], sp[K][D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
@@ -225,8 +470,53 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(2
     }
     const int lane = static_cast<int>(threadIdx.x) & 63;
     const int items = a.tiles_x * a.tiles_y, G = a.nb * kStreamWaves;
-    for (int i = stream_wave(wg, a.nb); i < items; i += G)
-        stream_window_item<K, D>(ta, w, dk, cc, stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y), lane, sy, sp);
+    if (w.jmax == 0) {
+        // a re-execution with copies only, or nothing at all (the sums it
+        // records are not read: the launch after a re-execution goes on
+        // without a stop test)
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < K; ++k) any = any || w.copy[k];
+        if (any)
+            for (int i = stream_wave(wg, a.nb); i < items; i += G)
+                stream_copy_item<K>(w, stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y), lane, a.nx);
+    } else if constexpr (kStreamGroups<K, D> > 1) {
+        // two groups of wavefronts over the same items: even wavefronts take
+        // outputs 0 .. KG-1 and the sums of the levels, odd ones the rest;
+        // each forms every level of its items
+        constexpr int KG = kStreamGroupOutputs<K, D>;
+        double v[D * (1 + K)];
+        const int wave = stream_wave(wg, a.nb);
+        if ((wave & 1) == 0) {
+            double sg[KG][D];
+            stream_group<OP, K, D, 0, KG>(ta, w, a.u, cc, a, wave, lane, sy, sg);
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                v[j * (1 + K)] = sy[j];
+#pragma unroll
+                for (int k = 0; k < K; ++k) v[j * (1 + K) + 1 + k] = k < KG ? sg[k < KG ? k : 0][j] : 0.0;
+            }
+        } else {
+            double sg[K - KG][D], none[D];
+            stream_group<OP, K, D, KG, K - KG>(ta, w, a.u, cc, a, wave, lane, none, sg);
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                v[j * (1 + K)] = 0.0;
+#pragma unroll
+                for (int k = 0; k < K; ++k) v[j * (1 + K) + 1 + k] = k >= KG ? sg[k >= KG ? k - KG : 0][j] : 0.0;
+            }
+        }
+        window_exit_sums<K, D>(a, L, wg, v);
+        return;
+    } else if (F32 && w.win32) {
+        for (int i = stream_wave(wg, a.nb); i < items; i += G)
+            stream_window_item<OP, K, D, float>(ta, w, a.u32, dk, cc, stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y),
+                                                lane, sy, sp);
+    } else {
+        for (int i = stream_wave(wg, a.nb); i < items; i += G)
+            stream_window_item<OP, K, D, double>(ta, w, a.u, dk, cc,
+                                                 stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y), lane, sy, sp);
+    }
     window_exit<K, D>(a, L, wg, sy, sp);
 }
 
@@ -251,6 +541,7 @@ __device__ __forceinline__ void stream_power_item(const Sten& st, const int nx, 
     const int gcol = wrap(it.xs + rc, nx);
     const bool ocol = rc >= 0 && rc < it.ws;
     const int T = it.hb + 2 * DP;
+    const StenT<double> stt = sten_as<double>(st);
     const int ytop = it.yb - DP;
     auto row_off = [&](const int t) { return static_cast<long>(wrap(ytop + t, ny)) * nx + gcol; };
     double2 lc[DP], lq[DP];
@@ -269,8 +560,8 @@ __device__ __forceinline__ void stream_power_item(const Sten& st, const int nx, 
             yq1 = ld_pair(in + row_off(t + 2 < T ? t + 2 : T - 1));
 #pragma unroll
             for (int j = 1; j <= DP; ++j) {
-                const double2 y = stream_complete(st, lq[j - 1], cur);
-                lq[j - 1] = stream_partial(st, st.c4, lc[j - 1], cur);
+                const double2 y = stream_complete<double>(stt, lq[j - 1], cur);
+                lq[j - 1] = stream_partial<double>(stt, st.c4, lc[j - 1], cur);
                 lc[j - 1] = cur;
                 cur = y;
                 const int r = t - j;
@@ -338,61 +629,63 @@ __global__ __launch_bounds__(kBlockThreads) void power_stream_final(PowerArgs a,
     }
 }
 
-template <int K, int D>
-hipError_t launch_stream_kd(const SweepArgs& a, int L, hipStream_t s) {
-    hipLaunchKernelGGL((leja_stream<K, D>), dim3(a.nb), dim3(kBlockThreads), 0, s, a, L);
-    return hipGetLastError();
+// The register-marching window kernels there are: the five-point
+// diffusion-advection operator at depth 4 (K <= 4), 6 (K <= 3) and 8 (K = 1)
+// in FP64, and the Burgers Jacobian at depth 4 (K <= 2) and 6 (K = 1); FP32
+// sweeps for K <= 2 at depths 4 and 6 (K = 1) of both operators.
+#define LX_STREAM_KERNELS(X)                                                                              \
+    X(kOpDiffAdv, 1, 4, false) X(kOpDiffAdv, 2, 4, false) X(kOpDiffAdv, 3, 4, false)                      \
+    X(kOpDiffAdv, 4, 4, false) X(kOpDiffAdv, 1, 6, false) X(kOpDiffAdv, 2, 6, false)                      \
+    X(kOpDiffAdv, 3, 6, false) X(kOpDiffAdv, 1, 8, false) X(kOpBurgersJ, 1, 4, false)                     \
+    X(kOpBurgersJ, 2, 4, false) X(kOpBurgersJ, 1, 6, false) X(kOpDiffAdv, 1, 4, true)                     \
+    X(kOpDiffAdv, 2, 4, true) X(kOpDiffAdv, 1, 6, true) X(kOpBurgersJ, 1, 4, true)                        \
+    X(kOpBurgersJ, 2, 4, true) X(kOpBurgersJ, 1, 6, true)
+
+const void* stream_kernel(int op, int K, int depth, bool f32) {
+#define LX_STREAM_PICK(O, KK, DD, F)                                                    \
+    if (op == (O) && K == (KK) && depth == (DD) && f32 == (F))                          \
+        return reinterpret_cast<const void*>(leja_stream<(O), (KK), (DD), (F)>);
+    LX_STREAM_KERNELS(LX_STREAM_PICK)
+#undef LX_STREAM_PICK
+    return nullptr;
 }
 
 }  // namespace
+
+int stream_groups(int K, int depth) {
+    return K == 3 && depth == 6 ? kStreamGroups<3, 6> : 1;
+}
 
 int stream_strips(int nx, int depth) {
     const int out_pairs = 64 - depth;   // column pairs a strip outputs
     return ((nx / 2) + out_pairs - 1) / out_pairs;
 }
 
-bool stream_has(int K, int depth) {
-    return (depth == 4 && K >= 1 && K <= 4) || (depth == 6 && K >= 1 && K <= 3) || (depth == 8 && K == 1);
-}
+bool stream_has(int op, int K, int depth, bool fp32) { return stream_kernel(op, K, depth, fp32) != nullptr; }
 
-hipError_t launch_leja_stream(int K, int depth, const SweepArgs& a, int L, hipStream_t s) {
-    if (!stream_has(K, depth) || a.nb < 1 || a.nx % 2 != 0 || a.nx < depth || a.ny < depth)
+hipError_t launch_leja_stream(int op, int K, int depth, bool fp32, const SweepArgs& a, int L, hipStream_t s) {
+    if (!stream_has(op, K, depth, fp32) || a.nb < 1 || a.nx % 2 != 0 || a.nx < depth || a.ny < depth)
         return hipErrorInvalidValue;
+    if (op == kOpBurgersJ && (a.u == nullptr || (fp32 && a.u32 == nullptr))) return hipErrorInvalidValue;
     if (a.tiles_x != stream_strips(a.nx, depth) || a.tiles_y < 1 || a.tiles_y > a.ny) return hipErrorInvalidValue;
-    switch (depth * 8 + K) {
-        case 33: return launch_stream_kd<1, 4>(a, L, s);
-        case 34: return launch_stream_kd<2, 4>(a, L, s);
-        case 35: return launch_stream_kd<3, 4>(a, L, s);
-        case 36: return launch_stream_kd<4, 4>(a, L, s);
-        case 49: return launch_stream_kd<1, 6>(a, L, s);
-        case 50: return launch_stream_kd<2, 6>(a, L, s);
-        case 51: return launch_stream_kd<3, 6>(a, L, s);
-        case 65: return launch_stream_kd<1, 8>(a, L, s);
-        default: return hipErrorInvalidValue;
+#define LX_STREAM_LAUNCH(O, KK, DD, F)                                                                         \
+    if (op == (O) && K == (KK) && depth == (DD) && fp32 == (F)) {                                              \
+        hipLaunchKernelGGL((leja_stream<(O), (KK), (DD), (F)>), dim3(a.nb), dim3(kBlockThreads), 0, s, a, L); \
+        return hipGetLastError();                                                                              \
     }
+    LX_STREAM_KERNELS(LX_STREAM_LAUNCH)
+#undef LX_STREAM_LAUNCH
+    return hipErrorInvalidValue;
 }
 
-int stream_resident(int K, int depth, int power) {
+int stream_resident(int op, int K, int depth, bool fp32, int power) {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
-    const void* k = nullptr;
-    if (power) {
-        k = reinterpret_cast<const void*>(power_stream<kPowerStreamDepth>);
-    } else {
-        switch (depth * 8 + K) {
-            case 33: k = reinterpret_cast<const void*>(leja_stream<1, 4>); break;
-            case 34: k = reinterpret_cast<const void*>(leja_stream<2, 4>); break;
-            case 35: k = reinterpret_cast<const void*>(leja_stream<3, 4>); break;
-            case 36: k = reinterpret_cast<const void*>(leja_stream<4, 4>); break;
-            case 49: k = reinterpret_cast<const void*>(leja_stream<1, 6>); break;
-            case 50: k = reinterpret_cast<const void*>(leja_stream<2, 6>); break;
-            case 51: k = reinterpret_cast<const void*>(leja_stream<3, 6>); break;
-            case 65: k = reinterpret_cast<const void*>(leja_stream<1, 8>); break;
-            default: return 0;
-        }
-    }
+    const void* k = power ? reinterpret_cast<const void*>(power_stream<kPowerStreamDepth>)
+                          : stream_kernel(op, K, depth, fp32);
+    if (k == nullptr) return 0;
     const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kBlockThreads, 0);
     return e == hipSuccess ? per_cu * cus : 0;
 }

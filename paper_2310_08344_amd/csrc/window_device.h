@@ -35,7 +35,13 @@ __device__ __forceinline__ double lane_neighbour(const double v, const double ol
 // The state entering a launch from the state of the previous launch and its
 // partial sums tot[(j-1)(1+K) + q], q = 0: |y_{m+j}|^2, q = 1+k: |p_k|^2
 // after term m+j (j = 1..D).
-template <int K, int D>
+//
+// kFp32 (FP32 sweeps): a window forms its levels and writes y_{m+D} in FP32
+// (out32) once, at the last term of the window before it, every output
+// still iterating has |d| ||y|| <= fp32_switch * (rtol ||p|| + atol); from
+// then on every window does.  in32: the window's y_m is stored in FP32.  A
+// re-execution keeps the precision of the window it repeats.
+template <int K, int D, bool kFp32 = false>
 __device__ __forceinline__ SweepState block_decide(const SweepArgs& a, const LoopCtl& ctl, const SweepState& prev,
                                                    const double (&tot)[D * (1 + K)]) {
     SweepState nx = prev;
@@ -44,6 +50,7 @@ __device__ __forceinline__ SweepState block_decide(const SweepArgs& a, const Loo
         // D terms go on from y_{m+D}
         nx.blk_mode = 0;
         nx.iter = prev.iter + D;
+        nx.in32 = prev.out32;
         bool any = false;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -98,6 +105,14 @@ __device__ __forceinline__ SweepState block_decide(const SweepArgs& a, const Loo
         if (notconv) nx.status = 3;   // LX_ENOTCONV
     } else {
         nx.iter = m + D;
+        nx.in32 = prev.out32;
+        if (kFp32 && !prev.out32 && ctl.fp32_switch >= 0.0) {
+            bool small = true;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (nt[k] == D && !(nx.err[k] <= ctl.fp32_switch * (ctl.rtol * nx.pnorm[k] + ctl.atol))) small = false;
+            if (small) nx.out32 = 1;
+        }
     }
     return nx;
 }
@@ -110,6 +125,9 @@ struct WindowPlan {
     bool redo;              // re-execution of a window in which an output stopped
     int nt[K];              // terms each output takes in this launch
     int jmax;               // levels this launch forms
+    bool win32;             // levels formed, and y_{m+D} written, in FP32
+    bool in32;              // y_m is stored in FP32
+    bool copy[K];           // a re-execution copies this output unchanged (pin to pout)
     const double* pin[K];   // outputs as the window finds them
     double* pout[K];        // and where it leaves them
     const double* yin;      // y_m
@@ -122,11 +140,16 @@ struct WindowPlan {
 // slot[2] and, if `done` is given, counts the grid as finished.  Returns
 // false when this launch has nothing to do (the same in every thread).
 //
+// kEndCopy: in a re-execution, an output that stopped after the window's
+// last term (j = D) is not recomputed: the window's own result is exact.
+// An odd window wrote it to the caller's buffer already (nothing to do); an
+// even window's result is copied there (WindowPlan::copy).
+//
 // Buffers: window w reads y_m from v (w = 0) or ybuf[(w-1) & 1] and writes
 // y_{m+D} to ybuf[w & 1]; it reads the outputs from p (w even) or p2 (w odd)
 // and writes them to the other; a re-execution writes stopped outputs to p,
 // the caller's buffer, so every final result lands there.
-template <int OP, int K, int D>
+template <int OP, int K, int D, bool kEndCopy = false, bool kFp32 = false>
 __device__ __forceinline__ bool window_enter(const SweepArgs& a, const int L, const int wg, unsigned* done,
                                              WindowPlan<K>& w) {
     LoopCtl* __restrict__ ctl = a.ctl;
@@ -141,7 +164,11 @@ __device__ __forceinline__ bool window_enter(const SweepArgs& a, const int L, co
             for (int k = 0; k < kKMax; ++k) st.nt[k] = (k < K && st.active[k]) ? D : 0;
             st.n_work = 1;
             st.n_levels = D;
-            double b = 16.0 + (OP == kOpBurgersJ ? 8.0 : 0.0);
+            st.in32 = 0;
+            if (!kFp32) st.out32 = 0;
+            st.n_fp32 = st.out32 ? D : 0;
+            // v in, y_D out, the Burgers state, each output written
+            double b = 8.0 + (st.out32 ? 4.0 : 8.0) + (OP == kOpBurgersJ ? (st.out32 ? 4.0 : 8.0) : 0.0);
             for (int k = 0; k < K; ++k) b += st.nt[k] ? 8.0 : 0.0;
             st.bytes_pp = b;
             s_cur = st;
@@ -151,22 +178,27 @@ __device__ __forceinline__ bool window_enter(const SweepArgs& a, const int L, co
         double tot[NV];
         sum_partials<NV>(a.partials + static_cast<long>((L - 1) & 1) * a.nb * NV, a.nb, tot);
         if (tid == 0) {
-            SweepState st = block_decide<K, D>(a, *ctl, ctl->slot[(L - 1) & 1], tot);
+            SweepState st = block_decide<K, D, kFp32>(a, *ctl, ctl->slot[(L - 1) & 1], tot);
             if (!st.done) {
                 // algorithmic bytes per point: y in (and out, unless a
                 // re-execution), and per output written p (in and out; the
                 // first window only writes it)
                 const bool rd = st.blk_mode == 1;
                 st.n_work += 1;
-                double b = (rd ? 8.0 : 16.0) + (OP == kOpBurgersJ ? 8.0 : 0.0);   // y (and u)
+                double b = 0.0;
                 int lev = rd ? 0 : D;
                 for (int k = 0; k < K; ++k) {
-                    const bool w_k = rd ? st.nt[k] < 0 : st.nt[k] != 0;
-                    if (w_k) b += st.iter == 0 ? 8.0 : 16.0;
-                    if (rd && -st.nt[k] > lev) lev = -st.nt[k];
+                    const bool end = kEndCopy && rd && st.nt[k] == -D;   // exact already: copied or kept
+                    const bool w_k = rd ? (st.nt[k] < 0 && (!end || (st.iter / D) % 2 == 0)) : st.nt[k] != 0;
+                    if (w_k) b += st.iter == 0 && !end ? 8.0 : 16.0;
+                    if (rd && !end && -st.nt[k] > lev) lev = -st.nt[k];
                 }
+                // y in (and out), and u, when levels are formed
+                const double yb = st.in32 ? 4.0 : 8.0, ob = st.out32 ? 4.0 : 8.0;
+                if (!rd || lev > 0) b += yb + (rd ? 0.0 : ob) + (OP == kOpBurgersJ ? ob : 0.0);
                 st.bytes_pp += b;
                 st.n_levels += lev;
+                if (!rd && st.out32) st.n_fp32 += D;
             }
             s_cur = st;
             if (wg == 0) {
@@ -184,6 +216,8 @@ __device__ __forceinline__ bool window_enter(const SweepArgs& a, const int L, co
     w.m = __builtin_amdgcn_readfirstlane(s_cur.iter);
     w.win = w.m / D;
     w.redo = __builtin_amdgcn_readfirstlane(s_cur.blk_mode) == 1;
+    w.win32 = kFp32 && __builtin_amdgcn_readfirstlane(s_cur.out32) != 0;
+    w.in32 = kFp32 && __builtin_amdgcn_readfirstlane(s_cur.in32) != 0;
     // terms each output takes in this launch.  A re-execution recomputes
     // only the outputs that stopped (their final buffer is p); the others,
     // and y_{m+D}, the window already wrote exactly.
@@ -191,15 +225,21 @@ __device__ __forceinline__ bool window_enter(const SweepArgs& a, const int L, co
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int q = __builtin_amdgcn_readfirstlane(s_cur.nt[k]);
-        w.nt[k] = w.redo ? (q < 0 ? -q : 0) : q;
+        const bool end = kEndCopy && w.redo && q == -D;
+        w.nt[k] = (w.redo && !end) ? (q < 0 ? -q : 0) : (w.redo ? 0 : q);
         if (w.nt[k] > w.jmax) w.jmax = w.nt[k];
-        w.pin[k] = (w.win & 1) ? a.p2[k] : a.p[k];
+        // an even window wrote its outputs to p2, an odd one to p
+        w.copy[k] = end && (w.win & 1) == 0;
+        w.pin[k] = end ? a.p2[k] : ((w.win & 1) ? a.p2[k] : a.p[k]);
         w.pout[k] = w.redo ? a.p[k] : ((w.win & 1) ? a.p[k] : a.p2[k]);
     }
     w.yin = (w.win == 0) ? a.v : static_cast<const double*>(a.ybuf[(w.win - 1) & 1]);
     w.yout = static_cast<double*>(a.ybuf[w.win & 1]);
     return true;
 }
+
+template <int K, int D>
+__device__ __forceinline__ void window_exit_sums(const SweepArgs& a, int L, int wg, double (&v)[D * (1 + K)]);
 
 // Exit of a window launch: the workgroup's sums of squares of every level
 // (sy[j-1]: y_{m+j}) and of every output after each term (sp[k][j-1]), in a
@@ -215,6 +255,15 @@ __device__ __forceinline__ void window_exit(const SweepArgs& a, const int L, con
 #pragma unroll
         for (int k = 0; k < K; ++k) v[j * (1 + K) + 1 + k] = sp[k][j];
     }
+    window_exit_sums<K, D>(a, L, wg, v);
+}
+
+// The same from the packed record v[(j-1)(1+K) + q] (q = 0: y_{m+j}, 1+k:
+// output k), this thread's share.
+template <int K, int D>
+__device__ __forceinline__ void window_exit_sums(const SweepArgs& a, const int L, const int wg,
+                                                 double (&v)[D * (1 + K)]) {
+    constexpr int NV = D * (1 + K);
     block_sum<NV>(v);
     if (flat_tid() == 0) {
         double* __restrict__ Pp = a.partials + static_cast<long>(L & 1) * a.nb * NV + static_cast<long>(wg) * NV;

@@ -101,15 +101,16 @@ def test_stream_small_and_odd_grids(ctx, depth, nx, ny):
     oracle_parity(o, r.iters, lambda f: leja_phi(_A(prm), v, spec, h, c, g, 1e-9, 0.0, 300, f), PARITY)
 
 
-@pytest.mark.parametrize("depth", [4, 6, 8])
+@pytest.mark.parametrize("depth,K", [(4, 2), (6, 2), (6, 3), (8, 1)])
 @pytest.mark.parametrize("max_iters", [1, 2, 3, 4, 5, 6, 7, 8, 9, 13])
-def test_stream_windows_at_max_iters(ctx, depth, max_iters):
+def test_stream_windows_at_max_iters(ctx, depth, K, max_iters):
     """The budget ends at every position inside a window: LX_ENOTCONV with
-    exactly max_iters terms (the re-execution takes fewer than D terms)."""
+    exactly max_iters terms (the re-execution takes fewer than D terms; for
+    three outputs at depth 6, two groups of wavefronts per item)."""
     prm, h = diffadv_setup(96, 64)
     c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
     v = np.random.default_rng(4).standard_normal((64, 96))
-    ls = [0, 2] if depth <= 6 else [2]
+    ls = [0, 2, 3][:K] if K > 1 else [2]
     say("stream notconv", depth, max_iters)
     r, o = _solve(ctx, depth, 2, 0, 0, _op(prm), v, ls, h, c, g, rtol=1e-12, max_iters=max_iters,
                   raise_on_error=False)
@@ -179,3 +180,128 @@ def test_stream_power_iteration_matches_oracle(ctx, nx, ny, iters):
     assert 1 <= per <= 10 and st["n_launch"] == (iters + per - 1) // per
     rho_o, _ = power_iteration(_A(prm), x0, iters)
     assert abs(rho - rho_o) <= 1e-12 * rho_o
+
+
+# ---------------------------------------------------------------------------
+# the Burgers Jacobian, and FP32 sweeps, by register marching
+# ---------------------------------------------------------------------------
+
+def _burgers_case(nx, ny, seed, pe=2.0, cfl=5.0):
+    from oracle.operators import burgers_J
+    u = W.fourier_modes(max(nx, ny), seed=seed)[:ny, :nx] + 0.2
+    umax = float(np.max(np.abs(u)))
+    dx, dy = 1.0 / nx, 1.0 / ny
+    nu = umax * max(dx, dy) / pe
+    h = cfl * W.burgers_cfl_step(nu, umax, dx, dy)
+    rho = 2.0 / W.burgers_cfl_step(nu, umax, dx, dy)
+    c, g = -1.05 * rho / 2.0, 1.05 * rho / 4.0
+    op = B.make_operator(kind=B.LX_OP_BURGERS2D, nx=nx, ny=ny, dx=dx, dy=dy, nu=nu)
+    A = lambda w: burgers_J(u, w, nu, dx, dy)
+    v = np.random.default_rng(seed + 100).standard_normal((ny, nx))
+    return op, A, u, v, h, c, g
+
+
+def _solve_u(ctx, depth, kind, op, u, v, ls, h, c, g, **kw):
+    outs = [dev(np.zeros(v.shape)) for _ in ls]
+    ctx.set_depth(depth, 0, 0)
+    ctx.set_window_kernel(kind)
+    try:
+        r = ctx.phi_leja(op, dev(v), outs, ls, h, c, g, u=dev(u), **kw)
+    finally:
+        ctx.set_depth(0)
+        ctx.set_window_kernel(0)
+    return r, [host(o) for o in outs]
+
+
+@pytest.mark.parametrize("depth,ls", [(4, [1]), (4, [0, 3]), (6, [2])])
+@pytest.mark.parametrize("nx,ny", [(200, 136), (128, 128), (10, 12), (66, 34)])
+def test_stream_burgers_windows_match_oracle_and_tiles(ctx, depth, ls, nx, ny):
+    """The Burgers Jacobian by register marching (the state u staged row by
+    row beside level 0): the oracle at 1e-10, and bitwise the LDS-tile
+    windows of four (the same stencil operands in the same order) when the
+    iteration counts agree."""
+    op, A, u, v, h, c, g = _burgers_case(nx, ny, nx + ny)
+    say("stream burgers", depth, ls, nx, ny)
+    r, o = _solve_u(ctx, depth, 2, op, u, v, ls, h, c, g, rtol=1e-9, max_iters=300)
+    assert r.status == B.LX_OK and r.stats["depth"] == depth and r.stats["marching"] == 1
+    spec = [(l, 1.0, 1.0) for l in ls]
+    oracle_parity(o, r.iters, lambda f: leja_phi(A, v, spec, h, c, g, 1e-9, 0.0, 300, f), PARITY)
+    if depth == 4:
+        rt, ot = _solve_u(ctx, 4, 1, op, u, v, ls, h, c, g, rtol=1e-9, max_iters=300)
+        assert rt.stats["marching"] == 0
+        if rt.iters == r.iters:
+            assert all(np.array_equal(a, b) for a, b in zip(o, ot))
+
+
+@pytest.mark.parametrize("max_iters", [1, 3, 4, 5, 8, 9])
+def test_stream_burgers_windows_at_max_iters(ctx, max_iters):
+    op, A, u, v, h, c, g = _burgers_case(96, 64, 5)
+    say("stream burgers notconv", max_iters)
+    r, o = _solve_u(ctx, 4, 2, op, u, v, [1, 2], h, c, g, rtol=1e-13, max_iters=max_iters, raise_on_error=False)
+    assert r.status == B.LX_ENOTCONV and r.iters == [max_iters] * 2
+    ref = leja_phi(A, v, [(1, 1.0, 1.0), (2, 1.0, 1.0)], h, c, g, 1e-13, 0.0, max_iters)
+    assert max(rel(a, b) for a, b in zip(o, ref.p)) <= PARITY
+
+
+@pytest.mark.parametrize("kind", ["diffadv", "burgers"])
+@pytest.mark.parametrize("depth,ls", [(4, [1, 2]), (4, [0]), (6, [3])])
+@pytest.mark.parametrize("switch", [1e4, 0.0])
+def test_stream_fp32_windows_against_fp64_oracle(ctx, kind, depth, ls, switch):
+    """FP32 sweeps in windows: the basis vectors and stencil arithmetic in
+    FP32 once every term is small (fp32_switch times the tolerance; 0: from
+    the first window), the outputs, terms, norms and coefficients in FP64.
+    Error against the FP64 oracle within the tolerance with the default
+    switch (reported for a switch of 0)."""
+    if kind == "diffadv":
+        prm, h = diffadv_setup(256, 192)
+        c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
+        op = _op(prm)
+        op.prec = B.LX_FP32_SWEEP
+        A, u = _A(prm), None
+        v = np.random.default_rng(21).standard_normal((192, 256))
+    else:
+        op, A, u, v, h, c, g = _burgers_case(256, 192, 9)
+        op.prec = B.LX_FP32_SWEEP
+    say("stream fp32", kind, depth, ls, switch)
+    outs = [dev(np.zeros(v.shape)) for _ in ls]
+    ctx.set_depth(depth, 0, 0)
+    ctx.set_window_kernel(2)
+    try:
+        r = ctx.phi_leja(op, dev(v), outs, ls, h, c, g, u=dev(u) if u is not None else None, rtol=1e-8,
+                         max_iters=300, fp32_switch=switch)
+    finally:
+        ctx.set_depth(0)
+        ctx.set_window_kernel(0)
+    assert r.status == B.LX_OK and r.stats["marching"] == 1 and r.stats["depth"] == depth
+    assert r.stats["n_fp32"] > 0 and r.stats["n_fp32"] % depth == 0
+    ref = leja_phi(A, v, [(l, 1.0, 1.0) for l in ls], h, c, g, 1e-8, 0.0, 300)
+    errs = [rel(host(o), q) for o, q in zip(outs, ref.p)]
+    say("fp32 window errors vs fp64 oracle", errs, "iterations", r.iters, "oracle", ref.iters, "fp32 levels",
+        r.stats["n_fp32"])
+    assert max(errs) <= (1e-8 if switch > 0 else 1e-5)
+
+
+def test_stream_fp32_exprb42_step_against_fp64_oracle(ctx):
+    """One EXPRB42 step of a Burgers problem with FP32 sweeps in register-
+    marching windows (both passes) against the FP64 oracle's step."""
+    from oracle.phi_action import exprb42_step
+    n = 192
+    p, u0 = W.config3(n=n)
+    op = B.make_operator(p)
+    op32 = B.make_operator(p)
+    op32.prec = B.LX_FP32_SWEEP
+    rho, c, g = ctx.spectrum(op, u=dev(u0), x0=dev(W.start_vector(n)), iters=20)
+    out = dev(np.zeros_like(u0))
+    say("stream fp32 exprb42", n)
+    ctx.set_depth(4)
+    ctx.set_window_kernel(2)
+    try:
+        r = ctx.exprb_step(op32, dev(u0), out, p.h, c, g, rtol=1e-8, max_iters=200)
+    finally:
+        ctx.set_depth(0)
+        ctx.set_window_kernel(0)
+    assert r.status == B.LX_OK and r.stats["marching"] == 1 and r.stats["n_fp32"] > 0
+    ref = exprb42_step(u0, p.nu, p.dx, p.dy, p.h, c, g, 1e-8, 0.0, 200)
+    err = rel(host(out) - u0, ref.u_next - u0)
+    say("fp32 exprb42 update error", err)
+    assert err <= 1e-7
