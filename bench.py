@@ -202,7 +202,7 @@ def bench_small_configs(lib, repeats: int = 20, warmups: int = 3) -> dict:
     return res
 
 
-def bench_batched(lib, repeats: int = 10, warmups: int = 3) -> dict:
+def bench_batched(lib, repeats: int = 10, warmups: int = 3, tune: bool = True) -> dict:
     """256 uneven diffusion-advection instances (sides 64..512), exp action
     at rtol 1e-8 with 20 power-iteration sweeps each: one batched call
     against the plain path (lx_spectrum + lx_phi_leja per instance)."""
@@ -239,8 +239,9 @@ def bench_batched(lib, repeats: int = 10, warmups: int = 3) -> dict:
 
     # the batch's launch shape from the autotuner (this batch class: 256
     # diffusion-advection instances with sides 64..512)
-    tuned = ctx.tune_batched(args, power_iters=20, rtol=1e-8, max_iters=300, repeats=3)
-    best = min(tuned, key=lambda r: r[3])
+    # (without tuning: the shape LX_TUNE_CACHE holds for this class, else the default rule)
+    tuned = ctx.tune_batched(args, power_iters=20, rtol=1e-8, max_iters=300, repeats=3) if tune else []
+    best = min(tuned, key=lambda r: r[3]) if tuned else (0, 0, 0, None)
     log("batch tuner:", " ".join(f"{d}/{th}/{ppw}:{ms:.2f}" for d, th, ppw, ms in tuned))
     for _ in range(warmups):
         plain()
@@ -275,7 +276,7 @@ def bench_batched(lib, repeats: int = 10, warmups: int = 3) -> dict:
             "sweeps_min_median_max": [iters[0], iters[len(iters) // 2], iters[-1]]}
 
 
-def bench_learned(lib, count: int = 1024) -> dict:
+def bench_learned(lib, count: int = 1024, tune: bool = True) -> dict:
     """The learned + batched form against the plain batched and plain
     single-instance paths on 1024 instances at 256^2 (half
     diffusion-advection, half Burgers), with the committed predictor."""
@@ -283,7 +284,7 @@ def bench_learned(lib, count: int = 1024) -> dict:
 
     ctx = lib.context(n_max=1 << 16, k_max=1)
     p, margins, meta = L.load_predictor(ctx)
-    res = L.evaluate(ctx, p, margins, count=count)
+    res = L.evaluate(ctx, p, margins, count=count, tune=tune)
     ctx.close()
     res["predictor"] = {"records": meta.get("records"), "val_rmse_log_rho": meta.get("val_rmse_log_rho"),
                         "val_rmse_log_sweeps": meta.get("val_rmse_log_sweeps"),
@@ -378,7 +379,7 @@ def bench_paper_problems(lib, n: int = 8192, axpby_gbs=None, tune: bool = True, 
     return res
 
 
-def bench_exprb42(lib, n: int = 2048, repeats: int = 5) -> dict:
+def bench_exprb42(lib, n: int = 2048, repeats: int = 5, tune: bool = True) -> dict:
     """One EXPRB42 step of the 2048^2 Burgers workload (nu = 1e-3, four
     Fourier modes, h = 10 x CFL of the Jacobian, tolerance 1e-8), power
     iteration included: FP64 sweeps (windows after tuning) and FP32 sweeps;
@@ -400,7 +401,7 @@ def bench_exprb42(lib, n: int = 2048, repeats: int = 5) -> dict:
         op = B.make_operator(p)
         op32 = B.make_operator(p)
         op32.prec = B.LX_FP32_SWEEP
-        for K in (2, 1):
+        for K in (2, 1) if tune else ():
             ctx.tune(op, K=K, sweeps=24)
             ctx.tune(op32, K=K, sweeps=24)
 
@@ -580,13 +581,13 @@ def main() -> int:
         out["small_configs"] = bench_small_configs(lib)
     if not args.no_batched:
         log("batched 256-instance comparison")
-        out["batched_256"] = bench_batched(lib)
+        out["batched_256"] = bench_batched(lib, tune=not args.no_tune)
     if not args.no_batched and not args.no_learned:
         log("learned + batched on 1024 instances at 256^2")
-        out["learned_1024"] = bench_learned(lib)
+        out["learned_1024"] = bench_learned(lib, tune=not args.no_tune)
     if not args.no_exprb:
         log("EXPRB42 step on the 2048^2 Burgers workload")
-        out["exprb42_2048"] = bench_exprb42(lib)
+        out["exprb42_2048"] = bench_exprb42(lib, tune=not args.no_tune)
     if not args.no_paper:
         log("paper-shaped problems I and II at 8192^2")
         out["paper_problems_8192"] = bench_paper_problems(lib, axpby_gbs=extra.get("practical_axpby_gbs"),

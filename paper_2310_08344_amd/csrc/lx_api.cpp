@@ -221,7 +221,27 @@ void load_tune_cache(lx_ctx* ctx) {
             (t.th == 8 || t.th == 16 || t.th == 32) && t.pnb >= 0 && (t.stream == 0 || t.stream == 1) &&
             t.bands >= 0 && t.snb >= 0) {
             ctx->tuned[std::make_tuple(kind, nx, ny, K, prec)] = t;
+            continue;
         }
+        // a batch class's shape (lx_tune_batched): {"batch_class": [b, nx, ny, ...], "depth": d, "th": t, "ppw": p
+        const char* q = std::strstr(line, "{\"batch_class\": [");
+        if (q != line) continue;
+        q += std::strlen("{\"batch_class\": [");
+        std::vector<int> cls;
+        char* end = nullptr;
+        for (;;) {
+            const long v = std::strtol(q, &end, 10);
+            if (end == q) break;
+            cls.push_back(static_cast<int>(v));
+            q = end;
+            while (*q == ',' || *q == ' ') ++q;
+        }
+        lx::BatchShape b;
+        if (*q == ']' && cls.size() >= 3 && cls.size() % 2 == 1 &&
+            std::sscanf(q, "], \"depth\": %d, \"th\": %d, \"ppw\": %d", &b.depth, &b.th, &b.ppw) == 3 &&
+            (b.depth == 1 || b.depth == 2 || b.depth == lx::kBatchBlockDepth) && (b.th == 8 || b.th == 16) &&
+            b.ppw > 0 && b.ppw <= (1 << 22))
+            ctx->batch.tuned[cls] = b;
     }
     std::fclose(f);
 }

@@ -251,8 +251,12 @@ __device__ __forceinline__ void stream_window_item(const TileArgs<K>& ta, const 
 #pragma unroll
     for (int k = 0; k < K; ++k) pf[k] = double2{0.0, 0.0};   // row 0 is no output row (D >= 1)
 
+    // steps in pairs, unrolled (the roles of lc and lq repeat with them and
+    // stay in place) except at depth 6, where the unrolled pair needs more
+    // registers than two wavefronts per SIMD leave
+    constexpr int kPair = D == 6 ? 1 : 2;
     for (int t0 = 0; t0 < T_; t0 += 2) {
-#pragma unroll
+#pragma unroll kPair
         for (int u = 0; u < 2; ++u) {
             const int t = t0 + u;
             const double2 cur64 = yq0;

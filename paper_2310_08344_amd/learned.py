@@ -225,7 +225,8 @@ def solve_plain_single(ctx, args):
     return res
 
 
-def evaluate(ctx, predictor, margins, count=1024, seed0=SEED_EVALUATION, size=256, repeats=10, warmups=3, pool=None):
+def evaluate(ctx, predictor, margins, count=1024, seed0=SEED_EVALUATION, size=256, repeats=10, warmups=3, pool=None,
+             tune=True):
     """Time-to-solution of the learned + batched path against the plain
     batched path and the plain single-instance path on `count` instances
     (half diffusion-advection, half Burgers) at size^2, inputs resident on
@@ -251,8 +252,9 @@ def evaluate(ctx, predictor, margins, count=1024, seed0=SEED_EVALUATION, size=25
     # batch launch shape of this instance class comes from the autotuner
     # (timed on the plain batched path; the learned path shares the class)
     pb, lb = ctx.prepare(pargs), ctx.prepare(args)
-    tuned = ctx.tune_batched(pb, power_iters=POWER_ITERS, safety=SAFETY, rtol=RTOL, max_iters=MAX_ITERS, repeats=3)
-    best = min(tuned, key=lambda r: r[3])
+    tuned = (ctx.tune_batched(pb, power_iters=POWER_ITERS, safety=SAFETY, rtol=RTOL, max_iters=MAX_ITERS, repeats=3)
+             if tune else [])
+    best = min(tuned, key=lambda r: r[3]) if tuned else (0, 0, 0, None)
     for _ in range(warmups):
         solve_plain(ctx, pb)
         solve_learned(ctx, predictor, lb, *margins)
