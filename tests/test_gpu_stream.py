@@ -91,7 +91,8 @@ def test_stream_small_and_odd_grids(ctx, depth, nx, ny):
     prm, h = diffadv_setup(nx, ny, cfl=20.0)
     c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
     v = np.random.default_rng(nx * 100 + ny).standard_normal((ny, nx))
-    ls = [0, 2] if depth == 4 else [1]
+    # three outputs at depth 6: two groups of wavefronts per item
+    ls = {4: [0, 2], 6: [0, 1, 3], 8: [1]}[depth]
     say("stream small grid", depth, nx, ny)
     r, o = _solve(ctx, depth, 2, 0, 0, _op(prm), v, ls, h, c, g, rtol=1e-9, max_iters=300)
     assert r.status == B.LX_OK
