@@ -57,8 +57,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 # HBM traffic of the dominant kernel from rocprofv3 counters, per kernel family
-TRAFFIC_FILES = {"leja_stream": os.path.join(ROOT, "profiles", "leja_stream_phi123_4096_traffic.json"),
-                 "leja_block": os.path.join(ROOT, "profiles", "leja_block_phi123_4096_traffic.json")}
+TRAFFIC_FILES = {"leja_stream": os.path.join(ROOT, "profiles", "leja_stream_phi123_4096_traffic.json")}
 
 
 def log(*a):
