@@ -273,7 +273,9 @@ struct LejaCall {
 // (the five-point operators, FP64 or FP32 sweeps).
 bool stream_ok(const lx_operator& op, int K, int depth) {
     if (op.kind != LX_OP_DIFFADV2D && op.kind != LX_OP_BURGERS2D) return false;
+    // vectors of at most 2^30 bytes (the kernel's buffer offsets)
     return op.nx % 2 == 0 && op.nx >= depth && op.ny >= depth &&
+           static_cast<long>(op.nx) * op.ny * 8 <= (1L << 30) &&
            lx::stream_has(opcode_of(op.kind), K, depth, op.prec == LX_FP32_SWEEP);
 }
 
@@ -355,14 +357,12 @@ StreamGrid stream_grid(int op, bool fp32, int nx, int ny, int K, int D, int band
     StreamGrid g;
     g.strips = lx::stream_strips(nx, D);
     const int resident = lx::stream_resident(op, K, D, fp32, power ? 1 : 0);
-    // wavefronts per item: power sweeps one, windows one per group of outputs
-    const int per_item = power ? 1 : lx::stream_groups(K, D);
-    const int waves = (resident > 0 ? resident : 512) * (lx::kBlockThreads / 64) / per_item;
+    const int waves = (resident > 0 ? resident : 512) * (lx::kBlockThreads / 64);
     int by = bands;
     if (by <= 0) by = std::max(1, std::min(waves / g.strips, ny / (4 * D)));
     g.bands = std::max(1, std::min(by, ny));
     const int items = g.strips * g.bands;
-    int wgs = nb > 0 ? nb : (items * per_item + 3) / 4;
+    int wgs = nb > 0 ? nb : (items + 3) / 4;
     if (nb <= 0 && resident > 0) wgs = std::min(wgs, resident);
     if (nb <= 0 && wgs >= 8) {
         const int up = (wgs + 7) & ~7;

@@ -193,9 +193,6 @@ hipError_t launch_power_block_final(const PowerArgs& a, int b, int nlev, hipStre
 // workgroups of four wavefronts that each take items (strip, band) in turn;
 // partials as launch_leja_block.
 int stream_strips(int nx, int depth);
-// wavefronts that take each item of a window launch (two groups of outputs
-// for K = 3 at depth 6, else one)
-int stream_groups(int K, int depth);
 // whether leja_stream is built for this operator (kOp*), K outputs, depth
 // and precision mode
 bool stream_has(int op, int K, int depth, bool fp32);

@@ -1,6 +1,7 @@
 // Windows of D Leja iterations per launch by register streaming (gfx950),
-// FP64, for the five-point diffusion-advection operator; and power
-// iteration with many sweeps per launch in the same way.
+// for the five-point diffusion-advection operator and the Burgers Jacobian,
+// FP64 or FP32 levels; and power iteration with many sweeps per launch in
+// the same way.
 //
 // The window semantics are those of leja_block (window_device.h): every
 // output takes the one-iteration loop's terms in the same order, and the
@@ -9,24 +10,31 @@
 //
 // Every wavefront works alone on an item: a strip of 128 columns (64 lanes,
 // a column pair each) and a band of rows, marched from top to bottom with no
-// LDS and no barrier.  Its 128 columns are the item's output columns and D
-// columns on each side; level j (the basis vector y_{m+j}) is valid on the
-// strip minus j columns on each side, so after D levels the output columns
-// remain.  Rows are staged from D above the band to D below it.  At step t
-// the wavefront loads row t of y_m (level 0) and then forms level j at row
-// t - j for j = 1..D from the two rows of level j-1 it kept in registers and
-// the row of level j-1 it just formed (the Newton recurrence of Sec. 2.1,
+// barrier.  Its 128 columns are the item's output columns and D columns on
+// each side; level j (the basis vector y_{m+j}) is valid on the strip minus
+// j columns on each side, so after D levels the output columns remain.
+// Rows are staged from D above the band to D below it.  At step t the
+// wavefront takes row t of y_m (level 0) and then forms level j at row t - j
+// for j = 1..D from the two rows of level j-1 it kept in registers and the
+// row of level j-1 it just formed (the Newton recurrence of Sec. 2.1,
 // Eq. (2)).  The side neighbours of a column pair come from the neighbouring
-// lanes (DPP wavefront shifts).  An output row enters the registers when
-// level 0 reaches it, takes term j when level j does, and leaves after its
-// last term: D + 1 rows of every output are in flight.  Nothing is formed
-// twice along y (the LDS-tile kernel forms up to 1.7 points per output point
-// at D = 6 on 8-row tiles); along x the strip's side columns are formed by
-// two wavefronts (128 columns per 128 - 2D outputs).
+// lanes (DPP wavefront shifts).  Nothing is formed twice along y (the
+// LDS-tile kernel forms up to 1.7 points per output point at D = 6 on 8-row
+// tiles); along x the strip's side columns are formed by two wavefronts
+// (128 columns per 128 - 2D outputs).
+//
+// The outputs: for the diffusion-advection operator at depths up to six
+// (ring windows, below) every level also goes into a small ring in LDS and
+// the outputs of row t - D take all their terms at step t; otherwise
+// (Burgers, depth eight) an output row enters the registers when level 0
+// reaches it, takes term j when level j does, and leaves after its last
+// term, D + 1 rows of every output in flight.
 //
 // Each wavefront's items are a contiguous run of bands of one XCD, so the
 // side columns a neighbouring strip also loads come from that XCD's L2.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "lx_device.h"
 #include "sweep_device.h"
@@ -170,6 +178,11 @@ __device__ __forceinline__ double2 as_d2(const P2<T> v) {
 
 template <typename T>
 __device__ __forceinline__ P2<T> as_t2(const double2 v) {
+    return P2<T>{static_cast<T>(v.x), static_cast<T>(v.y)};
+}
+
+template <typename T>
+__device__ __forceinline__ P2<T> as_t2(const float2 v) {
     return P2<T>{static_cast<T>(v.x), static_cast<T>(v.y)};
 }
 
@@ -377,72 +390,286 @@ __device__ __forceinline__ void stream_copy_item(const WindowPlan<K>& w, const S
     }
 }
 
-// Wavefront groups of a window launch: with three outputs at depth 6 one
-// wavefront holding every output's rows in flight would need more registers
-// than two wavefronts per SIMD leave, so two wavefronts take each item, one
-// for two outputs and one for the third; the basis vector is read twice
-// (the second read mostly from the caches) and its levels formed twice.
-template <int K, int D>
-constexpr int kStreamGroups = (K == 3 && D == 6) ? 2 : 1;
-template <int K, int D>
-constexpr int kStreamGroupOutputs = (K == 3 && D == 6) ? 2 : K;
+// ---------------------------------------------------------------------------
+// Ring windows (the five-point diffusion-advection operator, D <= 6).
+//
+// The same levels as stream_window_item, formed the same way, but the
+// outputs are completed D steps later: level j of row t - j, formed at step
+// t, also goes into a ring in LDS, and at step t the outputs of row t - D
+// take their terms 1 .. D in order from the rings (level D is the one just
+// formed).  An output row is then one row of registers for one step, not
+// D rows for D steps, so three outputs at depth six fit one wavefront, and
+// every row loaded for a later step sits in a register of its own that is
+// read once and then loaded again: nothing loaded is moved, so no step waits
+// for the loads it has just issued.  Loads and stores go through buffer
+// resources and every step issues the same ones; rows and lanes that must
+// not be touched get offsets past the end of the buffer (the hardware reads
+// zeros and writes nothing), so the wait for a load counts exactly the
+// memory operations issued after it.  Results, sums of squares and the
+// order of every operation are those of stream_window_item.
+//
+// Ring of level j (1 <= j < D): Ring<D>::size(j) >= D - j slots of one row
+// (64 lanes x a column pair), a power of two: row r in slot r mod size.  At
+// step t the slot of row t - D is read before row t - j is written (the
+// only rows alive are t - D .. t - j - 1).  The step loop is unrolled by a
+// multiple of every ring size, so every slot is a fixed LDS offset.
+// ---------------------------------------------------------------------------
 
-// The items of one group (FP64 levels): outputs K0 .. K0+KN-1 of the
-// window; the wavefront's index `wave` (its group is wave & 1) walks the
-// items of its group.  sy: the levels' sums (group 0 only).
-template <int OP, int K, int D, int K0, int KN>
-__device__ __forceinline__ void stream_group(const TileArgs<K>& ta, const WindowPlan<K>& w, const double* u,
-                                             const double (&cc)[D], const SweepArgs& a, const int wave,
-                                             const int lane, double (&sy)[D], double (&sp)[KN][D]) {
-    WindowPlan<KN> g;
-    g.m = w.m;
-    g.win = w.win;
-    g.redo = w.redo;
-    g.win32 = false;
-    g.in32 = false;
-    g.yin = w.yin;
-    g.yout = K0 == 0 ? w.yout : nullptr;
-    g.jmax = w.redo ? 0 : D;
-    double gk[KN][D + 1];
-#pragma unroll
-    for (int k = 0; k < KN; ++k) {
-        g.nt[k] = w.nt[K0 + k];
-        g.copy[k] = w.copy[K0 + k];
-        g.pin[k] = w.pin[K0 + k];
-        g.pout[k] = w.pout[K0 + k];
-        if (g.nt[k] > g.jmax) g.jmax = g.nt[k];
-#pragma unroll
-        for (int j = 0; j <= D; ++j) gk[k][j] = a.coef[(K0 + k) * a.ld + w.m + j];
+template <int D>
+struct Ring {
+    static constexpr int size(const int j) {
+        int s = 1;
+        while (s < D - j) s *= 2;
+        return s;
     }
-    TileArgs<KN> tg;
-    tg.nx = ta.nx;
-    tg.ny = ta.ny;
-    tg.tiles_x = ta.tiles_x;
-    tg.ld = ta.ld;
-    tg.st = ta.st;
-    tg.u = ta.u;
-    tg.coef = ta.coef;
-    tg.xi = ta.xi;
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-        sy[j] = 0.0;
-#pragma unroll
-        for (int k = 0; k < KN; ++k) sp[k][j] = 0.0;
+    static constexpr int base(const int j) {
+        int b = 0;
+        for (int i = 1; i < j; ++i) b += size(i);
+        return b;
     }
-    // a group with nothing to form in a re-execution (copies are done on
-    // the launch's copy path) skips its items
-    if (g.jmax == 0) return;
+    static constexpr int slots = base(D);              // rows per wavefront
+    static constexpr int unroll = size(1) < 4 ? 4 : size(1);
+    static constexpr int ahead_y = 4;                   // level 0 loaded this many steps ahead
+    static constexpr int ahead_p = 2;                   // output rows loaded this many steps ahead
+    static_assert(unroll % ahead_y == 0 && unroll % ahead_p == 0 && unroll % 2 == 0, "ring unroll");
+};
+
+template <int OP, int D>
+constexpr bool kRingWindows = OP == kOpDiffAdv && D >= 3 && D <= 6;
+
+// Buffer resources (raw, byte offsets).  An offset at or past the size
+// reads zeros and writes nothing; kFar is past every buffer a ring window
+// takes (vectors of at most kFar bytes), and a lane offset plus a row
+// offset, each at most kFar, stays below 2^32.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+constexpr unsigned kFar = 1u << 30;
+constexpr int kRsrcWord3 = 0x00020000;   // gfx9 resource word 3: 32-bit elements, no swizzle
+constexpr int kNontemporal = 2;
+
+__device__ __forceinline__ Rsrc make_rsrc(const void* p, const unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, static_cast<int>(bytes), kRsrcWord3);
+}
+
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+
+template <typename S, int kAux = 0>
+__device__ __forceinline__ S buf_ld(const Rsrc r, const unsigned voff, const unsigned soff) {
+    if constexpr (sizeof(S) == 16) {
+        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, static_cast<int>(voff), static_cast<int>(soff), kAux);
+        S o;
+        o.x = __hiloint2double(static_cast<int>(v.y), static_cast<int>(v.x));
+        o.y = __hiloint2double(static_cast<int>(v.w), static_cast<int>(v.z));
+        return o;
+    } else {
+        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, static_cast<int>(voff), static_cast<int>(soff), kAux);
+        S o;
+        o.x = __uint_as_float(v.x);
+        o.y = __uint_as_float(v.y);
+        return o;
+    }
+}
+
+template <typename S, int kAux = 0>
+__device__ __forceinline__ void buf_st(const S d, const Rsrc r, const unsigned voff) {
+    if constexpr (sizeof(S) == 16) {
+        u32x4 v;
+        v.x = static_cast<unsigned>(__double2loint(d.x));
+        v.y = static_cast<unsigned>(__double2hiint(d.x));
+        v.z = static_cast<unsigned>(__double2loint(d.y));
+        v.w = static_cast<unsigned>(__double2hiint(d.y));
+        __builtin_amdgcn_raw_buffer_store_b128(v, r, static_cast<int>(voff), 0, kAux);
+    } else {
+        u32x2 v;
+        v.x = __float_as_uint(d.x);
+        v.y = __float_as_uint(d.y);
+        __builtin_amdgcn_raw_buffer_store_b64(v, r, static_cast<int>(voff), 0, kAux);
+    }
+}
+
+// What a ring window launch does, the same for every item: the buffers
+// (sized 0 where nothing is read or written), the coefficients with the
+// terms each output takes (dk[k][j] = d_{m+j}, 0 past its last term) and
+// the levels' centres.
+template <int K, int D>
+struct RingWin {
+    int nx, ny;
+    Sten st;
+    double cc[D];
+    double dk[K][D + 1];  // [k][0] unused
+    Rsrc yin, yout;      // y_m (level 0), y_{m+D}
+    Rsrc base[K];        // the rows each output starts from: p, or y_m in the first window
+    Rsrc pout[K];
+    double s0[K];        // first window: d_m for an output that starts from d_m y_m, else 1
+};
+
+// One item of a ring window.  kFirst: the first window (outputs that start
+// from d_m y_m); kIn32: y_m stored in FP32 (FP32 levels only).  ring: this
+// wavefront's Ring<D>::slots rows, lane-major.
+template <int K, int D, typename T, bool kFirst, bool kIn32>
+__device__ __forceinline__ void ring_window_item(const RingWin<K, D>& rw, const StreamItem it, const int lane,
+                                                 P2<T>* __restrict__ ring, double (&sy)[D], double (&sp)[K][D]) {
+    using R = Ring<D>;
+    using Y0 = typename std::conditional<kIn32, float2, double2>::type;   // level 0 as stored
+    constexpr int Y = R::ahead_y, P = R::ahead_p, U = R::unroll;
+    const int nx = rw.nx, ny = rw.ny;
+    const int rc = 2 * lane - D;                 // strip column of this lane's pair
+    const int gcol = wrap(it.xs + rc, nx);
+    const bool ocol = rc >= 0 && rc < it.ws;
+    const double mcol = ocol ? 1.0 : 0.0;
+    const int T_ = it.hb + 2 * D;
+    const StenT<T> st = sten_as<T>(rw.st);
+    T cc[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) cc[j] = static_cast<T>(rw.cc[j]);
+    // lane parts of the offsets; the row parts are uniform
+    const unsigned ycol = static_cast<unsigned>(gcol) * sizeof(Y0) / 2;
+    const unsigned ocol8 = ocol ? static_cast<unsigned>(gcol) * 8u : kFar;
+    const unsigned ocolT = ocol ? static_cast<unsigned>(gcol) * sizeof(T) : kFar;
+    const unsigned row8 = static_cast<unsigned>(nx) * 8u, rowT = static_cast<unsigned>(nx) * sizeof(T);
+    const unsigned rowY = static_cast<unsigned>(nx) * sizeof(Y0) / 2;
+    const unsigned allY = rowY * static_cast<unsigned>(ny);
+
+    P2<T> lc[D], lq[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) lc[j] = lq[j] = P2<T>{0, 0};
+    // level 0, rows t .. t + Y - 1 (staged row t is y_m's row yb - D + t)
+    Y0 yq[Y];
+    unsigned yoff = static_cast<unsigned>(wrap(it.yb - D, ny)) * rowY;
+#pragma unroll
+    for (int i = 0; i < Y; ++i) {
+        yq[i] = buf_ld<Y0>(rw.yin, ycol, yoff);
+        yoff += rowY;
+        if (yoff >= allY) yoff -= allY;
+    }
+    // the rows the outputs start from, rows t - D .. t - D + P - 1 (none
+    // before step 2D is an output row)
+    double2 bq[K][P];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int i = 0; i < P; ++i) bq[k][i] = double2{0.0, 0.0};
+
+    // step t, as sub-step u = t mod U of an unrolled block
+    auto step = [&](const int u, const int t) __attribute__((always_inline)) {
+        // level 0 at row t, and the load of row t + Y in its place
+        P2<T> cur = as_t2<T>(yq[u % Y]);
+        yq[u % Y] = buf_ld<Y0>(rw.yin, ycol, yoff);
+        yoff += rowY;
+        if (yoff >= allY) yoff -= allY;
+        // output row t - D (band row t - 2D) starts from its loaded row;
+        // row t - D + P is loaded in its place
+        const int os = t - 2 * D, ol = os + P;
+        const bool vs = os >= 0 && os < it.hb, vl = ol >= 0 && ol < it.hb;
+        const unsigned so = vs ? static_cast<unsigned>(it.yb + os) * row8 : kFar;
+        const unsigned lo = vl ? static_cast<unsigned>(it.yb + ol) * row8 : kFar;
+        double2 p[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            p[k] = bq[k][u % P];
+            if constexpr (kFirst) {
+                p[k].x = rw.s0[k] * p[k].x;
+                p[k].y = rw.s0[k] * p[k].y;
+            }
+            bq[k][u % P] = buf_ld<double2, kNontemporal>(rw.base[k], ocol8 + lo, 0);
+        }
+        const double mo = vs ? mcol : 0.0;
+#pragma unroll
+        for (int j = 1; j <= D; ++j) {
+            // cur: level j-1 at row t-j+1; y: level j at row t-j
+            const P2<T> y = stream_complete<T>(st, lq[j - 1], cur);
+            lq[j - 1] = stream_partial<T>(st, cc[j - 1], lc[j - 1], cur);
+            lc[j - 1] = cur;
+            cur = y;
+            // level j at row t - D
+            P2<T> yr = y;
+            if (j < D) {
+                P2<T>* slot_r = ring + (R::base(j) + ((u - D) & (R::size(j) - 1))) * 64;
+                P2<T>* slot_w = ring + (R::base(j) + ((u - j) & (R::size(j) - 1))) * 64;
+                yr = slot_r[lane];
+                slot_w[lane] = y;
+            }
+            const double2 y64 = as_d2<T>(yr);
+            sy[j - 1] = fma(mo, y64.x * y64.x + y64.y * y64.y, sy[j - 1]);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                p[k].x = fma(rw.dk[k][j], y64.x, p[k].x);
+                p[k].y = fma(rw.dk[k][j], y64.y, p[k].y);
+                sp[k][j - 1] = fma(mo, p[k].x * p[k].x + p[k].y * p[k].y, sp[k][j - 1]);
+            }
+        }
+        // row t - D is complete: y_{m+D} and every output
+        buf_st<P2<T>>(cur, rw.yout, ocolT + (vs ? static_cast<unsigned>(it.yb + os) * rowT : kFar));
+#pragma unroll
+        for (int k = 0; k < K; ++k) buf_st<double2, kNontemporal>(p[k], rw.pout[k], ocol8 + so);
+    };
+    // whole blocks of U steps as straight-line code (no branch between the
+    // steps, so the waits for loads count exactly), then the last steps
+    int t0 = 0;
+    for (; t0 + U <= T_; t0 += U) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) step(u, t0 + u);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        if (t0 + u >= T_) break;
+        step(u, t0 + u);
+    }
+}
+
+// The items of a ring window launch (this wavefront's share), with the
+// launch's buffers and coefficients set up once.
+template <int K, int D, bool F32>
+__device__ __forceinline__ void ring_windows(const SweepArgs& a, const WindowPlan<K>& w, const int wg, const int lane,
+                                             double2* __restrict__ ring_mem, double (&sy)[D], double (&sp)[K][D]) {
+    RingWin<K, D> rw;
+    rw.nx = a.nx;
+    rw.ny = a.ny;
+    rw.st = Sten{a.aW, a.aE, a.aS, a.aN, a.aC, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < D; ++j) rw.cc[j] = a.aC - a.xi[w.m + j];
+    const unsigned n = static_cast<unsigned>(a.nx) * static_cast<unsigned>(a.ny);
+    const bool win32 = F32 && w.win32, in32 = F32 && w.in32, first = w.win == 0;
+    rw.yin = make_rsrc(w.yin, n * (in32 ? 4u : 8u));
+    rw.yout = make_rsrc(w.yout, (!w.redo && w.yout != nullptr) ? n * (win32 ? 4u : 8u) : 0u);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        // the first window starts from p_0 = d_m y_m (also when it is
+        // re-executed); a copy reads the window's own result
+        const bool fk = first && !w.copy[k];
+        const bool wr = w.nt[k] > 0 || w.copy[k];
+        rw.s0[k] = fk ? a.coef[k * a.ld + w.m] : 1.0;
+        rw.base[k] = make_rsrc(fk ? static_cast<const void*>(w.yin) : static_cast<const void*>(w.pin[k]),
+                               (fk || wr) ? n * 8u : 0u);
+        rw.pout[k] = make_rsrc(w.pout[k], wr ? n * 8u : 0u);
+#pragma unroll
+        for (int j = 1; j <= D; ++j) rw.dk[k][j] = j <= w.nt[k] ? a.coef[k * a.ld + w.m + j] : 0.0;
+    }
+    // this wavefront's rings, cleared once so that rows no output takes
+    // (before step 2D of the first item) hold finite values
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+    double2* ring = ring_mem + wave * Ring<D>::slots * 64;
+#pragma unroll
+    for (int i = 0; i < Ring<D>::slots; ++i) ring[i * 64 + lane] = double2{0.0, 0.0};
     const int items = a.tiles_x * a.tiles_y, G = a.nb * kStreamWaves;
-    // the wavefronts of one group are every other one: item i of the grid's
-    // strips x bands goes to the wavefronts of index 2i and 2i + 1
-    for (int i = wave >> 1; i < items; i += G >> 1)
-        stream_window_item<OP, KN, D, double>(tg, g, u, gk, cc, stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y),
-                                              lane, sy, sp);
-    // only group 0 stores the basis vector and counts its sums
-    if constexpr (K0 != 0) {
-#pragma unroll
-        for (int j = 0; j < D; ++j) sy[j] = 0.0;
+#define LX_RING_ITEMS(T, FIRST, IN32)                                                                          \
+    for (int i = stream_wave(wg, a.nb); i < items; i += G)                                                    \
+        ring_window_item<K, D, T, FIRST, IN32>(rw, stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y), lane,    \
+                                              reinterpret_cast<P2<T>*>(ring), sy, sp);
+    if (win32) {
+        if (first) {
+            LX_RING_ITEMS(float, true, false)
+        } else if (in32) {
+            LX_RING_ITEMS(float, false, true)
+        } else {
+            LX_RING_ITEMS(float, false, false)
+        }
+    } else if (first) {
+        LX_RING_ITEMS(double, true, false)
+    } else {
+        LX_RING_ITEMS(double, false, false)
     }
+#undef LX_RING_ITEMS
 }
 
 // Launch L of the window loop: a.tiles_x strips by a.tiles_y bands, a.nb
@@ -455,16 +682,6 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(2
     const int wg = static_cast<int>(blockIdx.x);
     WindowPlan<K> w;
     if (!window_enter<OP, K, D, true, F32>(a, L, wg, nullptr, w)) return;
-    // the window's coefficients (groups of wavefronts load their own)
-    double dk[K][D + 1], cc[D];
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-#pragma unroll
-        for (int j = 0; j <= D; ++j) dk[k][j] = kStreamGroups<K, D> > 1 ? 0.0 : a.coef[k * a.ld + w.m + j];
-    const double centre = OP == kOpBurgersJ ? a.kC : a.aC;
-#pragma unroll
-    for (int j = 0; j < D; ++j) cc[j] = centre - a.xi[w.m + j];
-    const TileArgs<K> ta = tile_args<OP, K>(a);
     double sy[D], sp[K][D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
@@ -484,42 +701,29 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(2
         if (any)
             for (int i = stream_wave(wg, a.nb); i < items; i += G)
                 stream_copy_item<K>(w, stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y), lane, a.nx);
-    } else if constexpr (kStreamGroups<K, D> > 1) {
-        // two groups of wavefronts over the same items: even wavefronts take
-        // outputs 0 .. KG-1 and the sums of the levels, odd ones the rest;
-        // each forms every level of its items
-        constexpr int KG = kStreamGroupOutputs<K, D>;
-        double v[D * (1 + K)];
-        const int wave = stream_wave(wg, a.nb);
-        if ((wave & 1) == 0) {
-            double sg[KG][D];
-            stream_group<OP, K, D, 0, KG>(ta, w, a.u, cc, a, wave, lane, sy, sg);
-#pragma unroll
-            for (int j = 0; j < D; ++j) {
-                v[j * (1 + K)] = sy[j];
-#pragma unroll
-                for (int k = 0; k < K; ++k) v[j * (1 + K) + 1 + k] = k < KG ? sg[k < KG ? k : 0][j] : 0.0;
-            }
-        } else {
-            double sg[K - KG][D], none[D];
-            stream_group<OP, K, D, KG, K - KG>(ta, w, a.u, cc, a, wave, lane, none, sg);
-#pragma unroll
-            for (int j = 0; j < D; ++j) {
-                v[j * (1 + K)] = 0.0;
-#pragma unroll
-                for (int k = 0; k < K; ++k) v[j * (1 + K) + 1 + k] = k >= KG ? sg[k >= KG ? k - KG : 0][j] : 0.0;
-            }
-        }
-        window_exit_sums<K, D>(a, L, wg, v);
-        return;
-    } else if (F32 && w.win32) {
-        for (int i = stream_wave(wg, a.nb); i < items; i += G)
-            stream_window_item<OP, K, D, float>(ta, w, a.u32, dk, cc, stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y),
-                                                lane, sy, sp);
+    } else if constexpr (kRingWindows<OP, D>) {
+        __shared__ double2 ring_mem[kStreamWaves * Ring<D>::slots * 64];
+        ring_windows<K, D, F32>(a, w, wg, lane, ring_mem, sy, sp);
     } else {
-        for (int i = stream_wave(wg, a.nb); i < items; i += G)
-            stream_window_item<OP, K, D, double>(ta, w, a.u, dk, cc,
-                                                 stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y), lane, sy, sp);
+        // the window's coefficients
+        double dk[K][D + 1], cc[D];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int j = 0; j <= D; ++j) dk[k][j] = a.coef[k * a.ld + w.m + j];
+        const double centre = OP == kOpBurgersJ ? a.kC : a.aC;
+#pragma unroll
+        for (int j = 0; j < D; ++j) cc[j] = centre - a.xi[w.m + j];
+        const TileArgs<K> ta = tile_args<OP, K>(a);
+        if (F32 && w.win32) {
+            for (int i = stream_wave(wg, a.nb); i < items; i += G)
+                stream_window_item<OP, K, D, float>(ta, w, a.u32, dk, cc,
+                                                    stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y), lane, sy, sp);
+        } else {
+            for (int i = stream_wave(wg, a.nb); i < items; i += G)
+                stream_window_item<OP, K, D, double>(ta, w, a.u, dk, cc,
+                                                     stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y), lane, sy, sp);
+        }
     }
     window_exit<K, D>(a, L, wg, sy, sp);
 }
@@ -656,10 +860,6 @@ const void* stream_kernel(int op, int K, int depth, bool f32) {
 
 }  // namespace
 
-int stream_groups(int K, int depth) {
-    return K == 3 && depth == 6 ? kStreamGroups<3, 6> : 1;
-}
-
 int stream_strips(int nx, int depth) {
     const int out_pairs = 64 - depth;   // column pairs a strip outputs
     return ((nx / 2) + out_pairs - 1) / out_pairs;
@@ -672,6 +872,7 @@ hipError_t launch_leja_stream(int op, int K, int depth, bool fp32, const SweepAr
         return hipErrorInvalidValue;
     if (op == kOpBurgersJ && (a.u == nullptr || (fp32 && a.u32 == nullptr))) return hipErrorInvalidValue;
     if (a.tiles_x != stream_strips(a.nx, depth) || a.tiles_y < 1 || a.tiles_y > a.ny) return hipErrorInvalidValue;
+    if (static_cast<long>(a.nx) * a.ny * 8 > static_cast<long>(kFar)) return hipErrorInvalidValue;
 #define LX_STREAM_LAUNCH(O, KK, DD, F)                                                                         \
     if (op == (O) && K == (KK) && depth == (DD) && fp32 == (F)) {                                              \
         hipLaunchKernelGGL((leja_stream<(O), (KK), (DD), (F)>), dim3(a.nb), dim3(kBlockThreads), 0, s, a, L); \
