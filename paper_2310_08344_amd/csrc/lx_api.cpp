@@ -1050,7 +1050,7 @@ lx_status lx_spectrum(lx_ctx* ctx, const lx_operator* op, const double* d_u, con
     // written once per launch, the Burgers state once per launch); odd or
     // narrow grids and unaligned vectors one sweep per launch
     if (ctx->win_kind != 1 && op->kind == LX_OP_DIFFADV2D && vec2 && nx % 2 == 0 && nx >= lx::kPowerStreamDepth &&
-        ny >= lx::kPowerStreamDepth)
+        ny >= lx::kPowerStreamDepth && N * 8 <= (1L << 30))
         return spectrum_stream(ctx, *op, x0, iters, safety, rho_hat, c, gamma);
     constexpr int PD = lx::kPowerBlockDepth;
     const int pcode = opcode_of(op->kind);

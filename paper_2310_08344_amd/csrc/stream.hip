@@ -78,18 +78,25 @@ __device__ __forceinline__ int stream_wave(const int wg, const int nb) {
 template <typename T>
 using P2 = typename Pair<T>::type;
 
-// v of lane l - 1 (kFromBelow) or l + 1 in FP32 (one DPP move; see
-// lane_neighbour for FP64).  Every lane of the wavefront must be active.
+// v of lane l - 1 (kFromBelow: DPP wave_shr:1) or of lane l + 1
+// (wave_shl:1), one DPP move per 32 bits; lane 0 (lane 63) has no such
+// neighbour and reads 0.  Those lanes hold the outermost halo columns of a
+// strip, which no output column depends on (level j is valid j columns in
+// from the strip's edges).  Every lane of the wavefront must be active.
 template <bool kFromBelow>
-__device__ __forceinline__ float lane_neighbour32(const float v, const float old) {
-    constexpr int ctrl = kFromBelow ? 0x138 : 0x130;
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), ctrl, 0xf, 0xf, false));
+__device__ __forceinline__ int lane_move(const int v) {
+    return __builtin_amdgcn_mov_dpp(v, kFromBelow ? 0x138 : 0x130, 0xf, 0xf, true);
 }
 
 template <bool kFromBelow, typename T>
 __device__ __forceinline__ T nbr(const T v) {
-    if constexpr (sizeof(T) == sizeof(double)) return lane_neighbour<kFromBelow>(v, v);
-    else return lane_neighbour32<kFromBelow>(v, v);
+    if constexpr (sizeof(T) == sizeof(double)) {
+        const int lo = lane_move<kFromBelow>(__double2loint(v));
+        const int hi = lane_move<kFromBelow>(__double2hiint(v));
+        return __hiloint2double(hi, lo);
+    } else {
+        return __int_as_float(lane_move<kFromBelow>(__float_as_int(v)));
+    }
 }
 
 // The stencil's coefficients in the arithmetic of the levels: c0..c3 and
@@ -504,9 +511,11 @@ struct RingWin {
 };
 
 // One item of a ring window.  kFirst: the first window (outputs that start
-// from d_m y_m); kIn32: y_m stored in FP32 (FP32 levels only).  ring: this
-// wavefront's Ring<D>::slots rows, lane-major.
-template <int K, int D, typename T, bool kFirst, bool kIn32>
+// from d_m y_m); kIn32: y_m stored in FP32 (FP32 levels only); J: the
+// levels formed, D in a window, fewer in a re-execution whose outputs take
+// no term past J (it writes no y).  ring: this wavefront's Ring<D>::slots
+// rows, lane-major.
+template <int K, int D, typename T, bool kFirst, bool kIn32, int J = D>
 __device__ __forceinline__ void ring_window_item(const RingWin<K, D>& rw, const StreamItem it, const int lane,
                                                  P2<T>* __restrict__ ring, double (&sy)[D], double (&sp)[K][D]) {
     using R = Ring<D>;
@@ -575,7 +584,7 @@ __device__ __forceinline__ void ring_window_item(const RingWin<K, D>& rw, const 
         }
         const double mo = vs ? mcol : 0.0;
 #pragma unroll
-        for (int j = 1; j <= D; ++j) {
+        for (int j = 1; j <= J; ++j) {
             // cur: level j-1 at row t-j+1; y: level j at row t-j
             const P2<T> y = stream_complete<T>(st, lq[j - 1], cur);
             lq[j - 1] = stream_partial<T>(st, cc[j - 1], lc[j - 1], cur);
@@ -604,16 +613,38 @@ __device__ __forceinline__ void ring_window_item(const RingWin<K, D>& rw, const 
         for (int k = 0; k < K; ++k) buf_st<double2, kNontemporal>(p[k], rw.pout[k], ocol8 + so);
     };
     // whole blocks of U steps as straight-line code (no branch between the
-    // steps, so the waits for loads count exactly), then the last steps
-    int t0 = 0;
-    for (; t0 + U <= T_; t0 += U) {
+    // steps, so the waits for loads count exactly); the few steps past the
+    // staged rows load rows that exist, store nothing and add nothing
+    for (int t0 = 0; t0 < T_; t0 += U) {
 #pragma unroll
         for (int u = 0; u < U; ++u) step(u, t0 + u);
     }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        if (t0 + u >= T_) break;
-        step(u, t0 + u);
+}
+
+// This wavefront's items of a ring window launch.
+template <int K, int D, typename T, bool kFirst, bool kIn32, int J = D>
+__device__ __forceinline__ void ring_items(const RingWin<K, D>& rw, const SweepArgs& a, const int wg, const int lane,
+                                           double2* __restrict__ ring, double (&sy)[D], double (&sp)[K][D]) {
+    const int items = a.tiles_x * a.tiles_y, G = a.nb * kStreamWaves;
+    for (int i = stream_wave(wg, a.nb); i < items; i += G)
+        ring_window_item<K, D, T, kFirst, kIn32, J>(rw, stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y), lane,
+                                                   reinterpret_cast<P2<T>*>(ring), sy, sp);
+}
+
+// A re-execution (FP64 levels, not the first window) forms only the levels
+// its outputs' terms need: J = jmax.
+template <int K, int D, int J>
+__device__ __forceinline__ void ring_redo(const int jmax, const RingWin<K, D>& rw, const SweepArgs& a, const int wg,
+                                          const int lane, double2* __restrict__ ring, double (&sy)[D],
+                                          double (&sp)[K][D]) {
+    if constexpr (J < D) {
+        if (jmax == J) {
+            ring_items<K, D, double, false, false, J>(rw, a, wg, lane, ring, sy, sp);
+            return;
+        }
+        ring_redo<K, D, J + 1>(jmax, rw, a, wg, lane, ring, sy, sp);
+    } else {
+        ring_items<K, D, double, false, false, D>(rw, a, wg, lane, ring, sy, sp);
     }
 }
 
@@ -651,25 +682,17 @@ __device__ __forceinline__ void ring_windows(const SweepArgs& a, const WindowPla
     double2* ring = ring_mem + wave * Ring<D>::slots * 64;
 #pragma unroll
     for (int i = 0; i < Ring<D>::slots; ++i) ring[i * 64 + lane] = double2{0.0, 0.0};
-    const int items = a.tiles_x * a.tiles_y, G = a.nb * kStreamWaves;
-#define LX_RING_ITEMS(T, FIRST, IN32)                                                                          \
-    for (int i = stream_wave(wg, a.nb); i < items; i += G)                                                    \
-        ring_window_item<K, D, T, FIRST, IN32>(rw, stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y), lane,    \
-                                              reinterpret_cast<P2<T>*>(ring), sy, sp);
     if (win32) {
-        if (first) {
-            LX_RING_ITEMS(float, true, false)
-        } else if (in32) {
-            LX_RING_ITEMS(float, false, true)
-        } else {
-            LX_RING_ITEMS(float, false, false)
-        }
+        if (first) ring_items<K, D, float, true, false>(rw, a, wg, lane, ring, sy, sp);
+        else if (in32) ring_items<K, D, float, false, true>(rw, a, wg, lane, ring, sy, sp);
+        else ring_items<K, D, float, false, false>(rw, a, wg, lane, ring, sy, sp);
     } else if (first) {
-        LX_RING_ITEMS(double, true, false)
+        ring_items<K, D, double, true, false>(rw, a, wg, lane, ring, sy, sp);
+    } else if (w.redo) {
+        ring_redo<K, D, 1>(w.jmax, rw, a, wg, lane, ring, sy, sp);
     } else {
-        LX_RING_ITEMS(double, false, false)
+        ring_items<K, D, double, false, false>(rw, a, wg, lane, ring, sy, sp);
     }
-#undef LX_RING_ITEMS
 }
 
 // Launch L of the window loop: a.tiles_x strips by a.tiles_y bands, a.nb
@@ -740,8 +763,65 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(2
 // launch b's at partials[2 nb + (b & 1) nb DP + i DP + j].
 // ---------------------------------------------------------------------------
 
+// One item of a power launch that makes DP levels: level 0 (row t of `in`,
+// scaled by s) is loaded four steps ahead through a buffer resource and
+// every step issues the same memory operations (rows and lanes outside the
+// item's output get offsets past the end), so no step waits for the load
+// it has just issued.  Steps run in whole blocks of U; the few past the
+// staged rows store nothing and add nothing.
 template <int DP>
-__device__ __forceinline__ void stream_power_item(const Sten& st, const int nx, const int ny,
+__device__ __forceinline__ void stream_power_item(const StenT<double>& st, const double centre, const int nx,
+                                                  const int ny, const Rsrc in, const Rsrc out, const double s,
+                                                  const StreamItem it, const int lane, double (&sy)[DP]) {
+    constexpr int Y = 4, U = 4;   // U: a multiple of Y and of 2 (the roles of lc and lq)
+    const int rc = 2 * lane - DP;
+    const int gcol = wrap(it.xs + rc, nx);
+    const bool ocol = rc >= 0 && rc < it.ws;
+    const double mcol = ocol ? 1.0 : 0.0;
+    const int T = it.hb + 2 * DP;
+    const unsigned col8 = static_cast<unsigned>(gcol) * 8u, ocol8 = ocol ? col8 : kFar;
+    const unsigned row8 = static_cast<unsigned>(nx) * 8u, all8 = row8 * static_cast<unsigned>(ny);
+    double2 lc[DP], lq[DP];
+#pragma unroll
+    for (int j = 0; j < DP; ++j) lc[j] = lq[j] = double2{0.0, 0.0};
+    double2 yq[Y];
+    unsigned yoff = static_cast<unsigned>(wrap(it.yb - DP, ny)) * row8;
+#pragma unroll
+    for (int i = 0; i < Y; ++i) {
+        yq[i] = buf_ld<double2>(in, col8, yoff);
+        yoff += row8;
+        if (yoff >= all8) yoff -= all8;
+    }
+    for (int t0 = 0; t0 < T; t0 += U) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = t0 + u;
+            double2 cur;
+            cur.x = s * yq[u % Y].x;
+            cur.y = s * yq[u % Y].y;
+            yq[u % Y] = buf_ld<double2>(in, col8, yoff);
+            yoff += row8;
+            if (yoff >= all8) yoff -= all8;
+#pragma unroll
+            for (int j = 1; j <= DP; ++j) {
+                const double2 y = stream_complete<double>(st, lq[j - 1], cur);
+                lq[j - 1] = stream_partial<double>(st, centre, lc[j - 1], cur);
+                lc[j - 1] = cur;
+                cur = y;
+                // level j at row t - j, band row t - j - DP
+                const int r = t - j - DP;
+                const bool vr = r >= 0 && r < it.hb;
+                sy[j - 1] = fma(vr ? mcol : 0.0, y.x * y.x + y.y * y.y, sy[j - 1]);
+                if (j == DP) buf_st<double2>(y, out, ocol8 + (vr ? static_cast<unsigned>(it.yb + r) * row8 : kFar));
+            }
+        }
+    }
+}
+
+// Any number of levels nlev <= DP (the last launch of a power iteration
+// whose sweeps are not a multiple of DP).
+template <int DP>
+__device__ __forceinline__ void stream_power_item_any(const Sten& st, const int nx, const int ny,
                                                   const double* __restrict__ in, double* __restrict__ out,
                                                   const double s, const int nlev, const StreamItem it, const int lane,
                                                   double (&sy)[DP]) {
@@ -782,10 +862,11 @@ __device__ __forceinline__ void stream_power_item(const Sten& st, const int nx, 
     }
 }
 
+
 // Launch b makes nlev levels from `in`, scaled by the norm of the last level
 // of launch b - 1 (which made prev levels) or of the start vector.
 template <int DP>
-__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3, 3))) void power_stream(
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void power_stream(
     PowerArgs a, const double* in, double* out, const int b, const int nlev, const int prev) {
     const int wg = static_cast<int>(blockIdx.x);
     double scale;
@@ -804,15 +885,24 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(3
     }
     const int nl = __builtin_amdgcn_readfirstlane(nlev);
     // the plain operator (no shift)
-    const Sten st{a.cW, a.cE, a.cS, a.cN, a.cC, 0.0, 0.0, 0.0, 0.0};
+    const StenT<double> st{a.cW, a.cE, a.cS, a.cN};
     double sy[DP];
 #pragma unroll
     for (int j = 0; j < DP; ++j) sy[j] = 0.0;
     const int lane = static_cast<int>(threadIdx.x) & 63;
     const int items = a.tiles_x * a.tiles_y, G = a.nb * kStreamWaves;
-    for (int i = stream_wave(wg, a.nb); i < items; i += G)
-        stream_power_item<DP>(st, a.nx, a.ny, in, out, scale, nl, stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y),
-                              lane, sy);
+    if (nl == DP) {
+        const unsigned bytes = static_cast<unsigned>(a.nx) * static_cast<unsigned>(a.ny) * 8u;
+        const Rsrc rin = make_rsrc(in, bytes), rout = make_rsrc(out, bytes);
+        for (int i = stream_wave(wg, a.nb); i < items; i += G)
+            stream_power_item<DP>(st, a.cC, a.nx, a.ny, rin, rout, scale,
+                                  stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y), lane, sy);
+    } else {
+        const Sten sa{a.cW, a.cE, a.cS, a.cN, a.cC, 0.0, 0.0, 0.0, 0.0};
+        for (int i = stream_wave(wg, a.nb); i < items; i += G)
+            stream_power_item_any<DP>(sa, a.nx, a.ny, in, out, scale, nl,
+                                      stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y), lane, sy);
+    }
     block_sum<DP>(sy);
     if (flat_tid() == 0) {
         double* __restrict__ Pp = a.partials + 2L * a.nb + static_cast<long>(b & 1) * a.nb * DP + static_cast<long>(wg) * DP;
@@ -901,6 +991,7 @@ hipError_t launch_power_stream(const PowerArgs& a, const double* in, double* out
     if (a.nb < 1 || a.nx % 2 != 0 || a.nx < DP || a.ny < DP || nlev < 1 || nlev > DP || prev < 1 || prev > DP)
         return hipErrorInvalidValue;
     if (a.tiles_x != stream_strips(a.nx, DP) || a.tiles_y < 1 || a.tiles_y > a.ny) return hipErrorInvalidValue;
+    if (static_cast<long>(a.nx) * a.ny * 8 > static_cast<long>(kFar)) return hipErrorInvalidValue;
     hipLaunchKernelGGL((power_stream<DP>), dim3(a.nb), dim3(kBlockThreads), 0, s, a, in, out, b, nlev, prev);
     return hipGetLastError();
 }
