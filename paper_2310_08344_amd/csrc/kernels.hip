@@ -48,7 +48,7 @@ __global__ __launch_bounds__(kBlockThreads) void leja_sweep(SweepArgs a, const i
             s_cur = nxt;
             if (blockIdx.x == 0) {
                 ctl->slot[m & 1] = nxt;
-                if (nxt.done) ctl->slot[2] = nxt;
+                if (nxt.done) publish_final(ctl, a.pub, nxt);
             }
         }
     }

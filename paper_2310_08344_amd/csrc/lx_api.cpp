@@ -5,7 +5,9 @@
 // that read them, while the GPU works), the initial loop state, then sweeps
 // enqueued in chunks.  The sweeps decide by themselves when to stop (a
 // converged loop turns later sweeps into no-ops); the host only looks at the
-// state once per chunk, one chunk behind, to stop enqueuing.
+// state once per chunk, one chunk behind, to stop enqueuing: the launch that
+// ends the loop writes the final state into pinned host memory, so looking
+// costs an event wait and no copy.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -480,6 +482,10 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
     a.coef = ctx->coef;
     a.xi = ctx->xi;
     a.ctl = ctx->ctl;
+    // the launch that ends the loop writes its final state here (pinned)
+    volatile SweepState* pub = ctx->h_poll;
+    pub->done = 0;
+    a.pub = ctx->h_poll;
     const int opcode = opcode_of(op.kind);
     const size_t need_partials = 2 * static_cast<size_t>(a.nb) * (1 + K) * (blk ? D : (pair ? 2 : 1));
     if (q.scratch != nullptr) {
@@ -536,23 +542,21 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
         }
         launched += n;
         const int slot = chunk_id & 1;
-        LX_HIP(ctx, hipMemcpyAsync(&ctx->h_poll[slot], &ctx->ctl->slot[2], sizeof(SweepState),
-                                   hipMemcpyDeviceToHost, ctx->stream));
         LX_HIP(ctx, hipEventRecord(ctx->poll_ev[slot], ctx->stream));
         last_slot = slot;
         if (chunk_id >= 1) {
             // the next chunk's coefficients are prepared while the GPU works
             s = ensure_coeffs(coeffs_for(std::min(launched + next_chunk, last)));
             if (s != LX_OK) return s;
-            const int prev = slot ^ 1;
-            LX_HIP(ctx, hipEventSynchronize(ctx->poll_ev[prev]));
-            if (ctx->h_poll[prev].done) break;
+            // the chunk before has run: has a launch published the final state?
+            LX_HIP(ctx, hipEventSynchronize(ctx->poll_ev[slot ^ 1]));
+            if (pub->done) break;
         }
         ++chunk_id;
         chunk = next_chunk;
     }
     LX_HIP(ctx, hipEventSynchronize(ctx->poll_ev[last_slot]));
-    const SweepState& fin = ctx->h_poll[last_slot];
+    const SweepState fin = *const_cast<const SweepState*>(ctx->h_poll);
     if (!fin.done) return fail(ctx, LX_EDEVICE, "the device loop did not record a final state");
 
     S.n_fp32 = fin.n_fp32;

@@ -101,6 +101,7 @@ struct SweepArgs {
     const double* xi;        // Leja points
     double* partials;        // [2][nb][1+K]
     LoopCtl* ctl;
+    SweepState* pub;         // host-visible copy of the final state (pinned host memory), or NULL
 };
 
 struct PowerArgs {

@@ -300,7 +300,7 @@ __device__ __forceinline__ void pair_launch(const SweepArgs& a, const int L, con
                 // the previous launch flushed the last deferred term
                 s_mode = 2;
                 if (pub) {
-                    ctl->slot[2] = prev;
+                    publish_final(ctl, a.pub, prev);
                     if (done != nullptr) atomicAdd(done, 1u);
                 }
             } else {
@@ -317,7 +317,7 @@ __device__ __forceinline__ void pair_launch(const SweepArgs& a, const int L, con
                     s_mode = 2;
                     if (pub) {
                         ctl->slot[L & 1] = s1;
-                        ctl->slot[2] = s1;
+                        publish_final(ctl, a.pub, s1);
                         if (done != nullptr) atomicAdd(done, 1u);
                     }
                 } else {

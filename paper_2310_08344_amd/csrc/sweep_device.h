@@ -145,6 +145,17 @@ __device__ __forceinline__ void block_sum(double (&v)[NV]) {
 // workgroup: workgroup 0 of the same launch may publish the flag while this
 // workgroup starts, and all its wavefronts must take the same branch since
 // they meet at barriers later.
+// The final state of a loop, into slot[2] and, when the caller gave one,
+// into its host-visible copy (pinned host memory, written through to
+// system scope), which the host reads after the launch without a copy.
+__device__ __forceinline__ void publish_final(LoopCtl* ctl, SweepState* pub, const SweepState& st) {
+    ctl->slot[2] = st;
+    if (pub != nullptr) {
+        *pub = st;
+        __threadfence_system();
+    }
+}
+
 __device__ __forceinline__ bool loop_ended(const LoopCtl* ctl) {
     __shared__ int s_end;
     if (flat_tid() == 0) s_end = ctl->slot[2].done;

@@ -204,7 +204,7 @@ __device__ __forceinline__ bool window_enter(const SweepArgs& a, const int L, co
             if (wg == 0) {
                 ctl->slot[L & 1] = st;
                 if (st.done) {
-                    ctl->slot[2] = st;   // this launch does no work
+                    publish_final(ctl, a.pub, st);   // this launch does no work
                     if (done != nullptr) atomicAdd(done, 1u);
                 }
             }
