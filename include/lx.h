@@ -533,11 +533,13 @@ lx_status lx_set_depth(lx_ctx* ctx, int depth, int th, int nb);
  * for both (leja_block, power_block), 2 = register marching where it
  * applies (leja_stream: the five-point operators, FP64 or FP32 sweeps, at
  * the depths lx_set_depth lists; power_stream: LX_OP_DIFFADV2D; even nx,
- * sides >= depth, 16-byte aligned vectors).
+ * sides >= depth, 16-byte aligned vectors of at most 2^30 bytes).
  * Register marching gives every wavefront a strip of 128 columns (its
  * output columns and depth columns on each side) and a band of rows, which
  * it walks from top to bottom forming all levels of the window in
- * registers.  bands: bands of rows (0 = one resident round of wavefronts);
+ * registers; for LX_OP_DIFFADV2D at depths 4 and 6 every level also passes
+ * through a small ring in LDS, from which each output row takes its terms
+ * depth rows later.  bands: bands of rows (0 = one resident round of wavefronts);
  * nb: workgroups of four wavefronts (0 = automatic).  Results are the same
  * as with LDS tiles up to the order of the norm reductions.
  * Errors: LX_EINVAL (kind not 0..2, bands < 0, nb < 0). */
