@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kBlockThreads) void batch_fill_x0_kernel(BatchInst*
     const BatchInst& I = insts[w.i];
     if (I.has_x0) return;
     const long n = static_cast<long>(I.nx) * I.ny;
-    double* __restrict__ x = I.y[1];
+    double* __restrict__ x = gptr(I.y[1]);
     for (long t = static_cast<long>(w.j) * kBlockThreads + flat_tid(); t < n;
          t += static_cast<long>(I.nb) * kBlockThreads) {
         x[t] = splitmix_unit(static_cast<unsigned long long>(w.i), t);
@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kBlockThreads) void batch_power_norm_kernel(const B
                                                                          double* partials) {
     const Who w = who(insts, block_inst);
     const BatchInst& I = insts[w.i];
-    const double* __restrict__ x = I.has_x0 ? I.x0 : I.y[1];
+    const double* __restrict__ x = gptr(I.has_x0 ? I.x0 : I.y[1]);
     const long n = static_cast<long>(I.nx) * I.ny;
     double acc = 0.0;
     for (long t = static_cast<long>(w.j) * kBlockThreads + flat_tid(); t < n;
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(kBlockThreads) void batch_sweep_kernel(const BatchI
         if (tid == 0) s_cur = ctl->slot[0];
     } else {
         double tot[2];
-        sum_partials<2>(a.partials + static_cast<long>((m - 1) & 1) * I.nb * 2, I.nb, tot);
+        sum_partials<2>(gptr(a.partials) + static_cast<long>((m - 1) & 1) * I.nb * 2, I.nb, tot);
         if (tid == 0) {
             const SweepState nxt = decide<1, false>(a, *ctl, ctl->slot[(m - 1) & 1], m, tot);
             s_cur = nxt;
@@ -279,7 +279,7 @@ __global__ __launch_bounds__(kBlockThreads) void batch_sweep_kernel(const BatchI
     double v[2] = {sy, sp[0]};
     block_sum<2>(v);
     if (tid == 0) {
-        double* __restrict__ Pw = a.partials + static_cast<long>(m & 1) * I.nb * 2 + w.j * 2;
+        double* __restrict__ Pw = gptr(a.partials) + static_cast<long>(m & 1) * I.nb * 2 + w.j * 2;
         Pw[0] = v[0];
         Pw[1] = v[1];
     }

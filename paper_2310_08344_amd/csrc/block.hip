@@ -240,7 +240,7 @@ __device__ __forceinline__ void block_tile(const TileArgs<K>& a, BlockLds<OP, TH
             const double2 c0 = *reinterpret_cast<const double2*>(&S.a[H + w + i * kPairWaves][j0]);
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                const double d0 = a.coef[k * a.ld];
+                const double d0 = gptr(a.coef)[k * a.ld];
                 pv[k][i].x = d0 * c0.x;
                 pv[k][i].y = d0 * c0.y;
             }
@@ -254,7 +254,7 @@ __device__ __forceinline__ void block_tile(const TileArgs<K>& a, BlockLds<OP, TH
         if (j > jmax) break;
         const double (*src)[P] = ((j - 1) & 1) ? S.b : S.a;
         double (*dst)[P] = (j & 1) ? S.b : S.a;
-        const double shift = a.xi[m + j - 1];
+        const double shift = gptr(a.xi)[m + j - 1];
         const int r_lo = j * R, r_hi = ROWS - j * R;    // level j on LDS rows [r_lo, r_hi)
 #pragma unroll
         for (int i = 0; i < (ROWS + kPairWaves - 1) / kPairWaves; ++i) {
@@ -286,7 +286,7 @@ __device__ __forceinline__ void block_tile(const TileArgs<K>& a, BlockLds<OP, TH
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     if (nt[k] < j) continue;
-                    const double dj = a.coef[k * a.ld + m + j];
+                    const double dj = gptr(a.coef)[k * a.ld + m + j];
                     pv[k][i].x = fma(dj, y.x, pv[k][i].x);
                     pv[k][i].y = fma(dj, y.y, pv[k][i].y);
                     sp[k][j - 1] += pv[k][i].x * pv[k][i].x + pv[k][i].y * pv[k][i].y;
@@ -298,7 +298,7 @@ __device__ __forceinline__ void block_tile(const TileArgs<K>& a, BlockLds<OP, TH
     // ---- level D on the tile: y_{m+D} and the last term ----
     if (jmax >= D) {
         const double (*src)[P] = ((D - 1) & 1) ? S.b : S.a;
-        const double shift = a.xi[m + D - 1];
+        const double shift = gptr(a.xi)[m + D - 1];
 #pragma unroll
         for (int i = 0; i < RW; ++i) {
             const int r = H + w + i * kPairWaves;
@@ -317,7 +317,7 @@ __device__ __forceinline__ void block_tile(const TileArgs<K>& a, BlockLds<OP, TH
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     if (nt[k] < D) continue;
-                    const double dD = a.coef[k * a.ld + m + D];
+                    const double dD = gptr(a.coef)[k * a.ld + m + D];
                     pv[k][i].x = fma(dD, o[0], pv[k][i].x);
                     pv[k][i].y = fma(dD, o[1], pv[k][i].y);
                     sp[k][D - 1] += pv[k][i].x * pv[k][i].x + pv[k][i].y * pv[k][i].y;
@@ -388,7 +388,7 @@ __device__ __forceinline__ void block_launch(const SweepArgs& a, const int L, co
 
 template <int OP, int K, int TH, int D>
 __global__ __launch_bounds__(kBlockThreads) void leja_block(SweepArgs a, const int L) {
-    if (loop_ended(a.ctl)) return;
+    if (loop_ended(gptr(a.ctl))) return;
     __shared__ BlockLds<OP, TH, D> S;
     block_launch<OP, K, TH, D>(a, L, static_cast<int>(blockIdx.x), true, S, nullptr);
 }

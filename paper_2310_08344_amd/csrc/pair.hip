@@ -275,7 +275,7 @@ __device__ __forceinline__ void pair_tile(const TileArgs<K>& a, PairLds<OP, TH>&
 template <int OP, int K, int TH>
 __device__ __forceinline__ void pair_launch(const SweepArgs& a, const int L, const int wg, const bool banded,
                                             PairLds<OP, TH>& S, unsigned* done) {
-    LoopCtl* __restrict__ ctl = a.ctl;
+    LoopCtl* __restrict__ ctl = gptr(a.ctl);
     constexpr int NV = 2 * (1 + K);
     __shared__ int s_mode;   // 0: both terms, 1: deferred term only, 2: nothing
     __shared__ int s_add0[K], s_add1[K];
@@ -292,7 +292,7 @@ __device__ __forceinline__ void pair_launch(const SweepArgs& a, const int L, con
         }
     } else {
         double tot[NV];
-        sum_partials<NV>(a.partials + static_cast<long>((L - 1) & 1) * a.nb * NV, a.nb, tot);
+        sum_partials<NV>(gptr(a.partials) + static_cast<long>((L - 1) & 1) * a.nb * NV, a.nb, tot);
         if (tid == 0) {
             const SweepState prev = ctl->slot[(L - 1) & 1];
             const bool pub = wg == 0;
@@ -342,7 +342,7 @@ __device__ __forceinline__ void pair_launch(const SweepArgs& a, const int L, con
         add0[k] = s_add0[k];
         add1[k] = s_add1[k];
     }
-    const double* __restrict__ yin = (L == 0) ? a.v : static_cast<const double*>(a.ybuf[(L - 1) & 1]);
+    const double* __restrict__ yin = gptr((L == 0) ? a.v : static_cast<const double*>(a.ybuf[(L - 1) & 1]));
 
     if (mode == 1) {
         // p_k += d_m y_m for the outputs that passed the stop rule at term m
@@ -352,17 +352,17 @@ __device__ __forceinline__ void pair_launch(const SweepArgs& a, const int L, con
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 if (!add0[k]) continue;
-                const double dm = a.coef[k * a.ld + m];
-                double2 p = reinterpret_cast<const double2*>(a.p[k])[i];
+                const double dm = gptr(a.coef)[k * a.ld + m];
+                double2 p = reinterpret_cast<const double2*>(gptr(a.p[k]))[i];
                 p.x = fma(dm, y.x, p.x);
                 p.y = fma(dm, y.y, p.y);
-                reinterpret_cast<double2*>(a.p[k])[i] = p;
+                reinterpret_cast<double2*>(gptr(a.p[k]))[i] = p;
             }
         }
         return;
     }
 
-    double* __restrict__ yout = static_cast<double*>(a.ybuf[L & 1]);
+    double* __restrict__ yout = gptr(static_cast<double*>(a.ybuf[L & 1]));
     double sy1 = 0.0, sy2 = 0.0, sp1[K], sp2[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -406,7 +406,7 @@ __device__ __forceinline__ void pair_launch(const SweepArgs& a, const int L, con
     }
     block_sum<NV>(v);
     if (tid == 0) {
-        double* __restrict__ P = a.partials + static_cast<long>(L & 1) * a.nb * NV + static_cast<long>(wg) * NV;
+        double* __restrict__ P = gptr(a.partials) + static_cast<long>(L & 1) * a.nb * NV + static_cast<long>(wg) * NV;
 #pragma unroll
         for (int q = 0; q < NV; ++q) P[q] = v[q];
     }
@@ -414,7 +414,7 @@ __device__ __forceinline__ void pair_launch(const SweepArgs& a, const int L, con
 
 template <int OP, int K, int TH>
 __global__ __launch_bounds__(kBlockThreads) void leja_pair(SweepArgs a, const int L) {
-    if (loop_ended(a.ctl)) return;
+    if (loop_ended(gptr(a.ctl))) return;
     __shared__ PairLds<OP, TH> S;
     pair_launch<OP, K, TH>(a, L, static_cast<int>(blockIdx.x), true, S, nullptr);
 }

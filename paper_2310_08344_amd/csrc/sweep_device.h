@@ -10,6 +10,17 @@ namespace lx {
 namespace dev {
 
 
+// A device pointer marked as global memory.  Pointers read from memory
+// (the batched kernels keep their arguments in LDS) are generic to the
+// compiler, which then accesses through them with flat instructions: these
+// count on both the vector-memory and the LDS counters, so every wait for
+// an LDS read also waits for the global loads in flight.
+template <typename T>
+__device__ __forceinline__ T* gptr(T* p) {
+    using G = __attribute__((address_space(1))) T*;
+    return (T*)((G)(reinterpret_cast<unsigned long long>(p)));
+}
+
 __device__ __forceinline__ int wrap(int r, int n) {
     if (r < 0) r += n;
     else if (r >= n) r -= n;
@@ -242,23 +253,23 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const int m, cons
 
     const TI* __restrict__ yin;
     if constexpr (sizeof(TI) == sizeof(double)) {
-        yin = (m == 0) ? reinterpret_cast<const TI*>(a.v) : static_cast<const TI*>(a.ybuf[(m - 1) & 1]);
+        yin = gptr((m == 0) ? reinterpret_cast<const TI*>(a.v) : static_cast<const TI*>(a.ybuf[(m - 1) & 1]));
     } else {
-        yin = static_cast<const TI*>(a.ybuf[(m - 1) & 1]);
+        yin = gptr(static_cast<const TI*>(a.ybuf[(m - 1) & 1]));
     }
-    TO* __restrict__ yout = static_cast<TO*>(a.ybuf[m & 1]);
+    TO* __restrict__ yout = gptr(static_cast<TO*>(a.ybuf[m & 1]));
 
     double* __restrict__ pk[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) pk[k] = a.p[k];
-    const double* __restrict__ uu = a.u;
-    const float* __restrict__ uu32 = a.u32;
-    const double xim = a.xi[m];
+    for (int k = 0; k < K; ++k) pk[k] = gptr(a.p[k]);
+    const double* __restrict__ uu = gptr(a.u);
+    const float* __restrict__ uu32 = gptr(a.u32);
+    const double xim = gptr(a.xi)[m];
     double dn1[K], d0[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        dn1[k] = a.coef[k * a.ld + m + 1];
-        d0[k] = a.coef[k * a.ld];
+        dn1[k] = gptr(a.coef)[k * a.ld + m + 1];
+        d0[k] = gptr(a.coef)[k * a.ld];
     }
 
     AT up[V], cen[V], dn[V];
@@ -406,7 +417,7 @@ __device__ __forceinline__ SweepState decide(const SweepArgs& a, const LoopCtl& 
     for (int k = 0; k < K; ++k) {
         if (!prev.active[k]) continue;
         const double pn = sqrt(tot[1 + k]) * a.inv_sqrtN;
-        const double e = fabs(a.coef[k * a.ld + m]) * ynorm;
+        const double e = fabs(gptr(a.coef)[k * a.ld + m]) * ynorm;
         const double thr = rtol * pn + atol;
         nx.err[k] = e;
         nx.pnorm[k] = pn;

@@ -75,12 +75,12 @@ __device__ __forceinline__ TileArgs<K> tile_args(const SweepArgs& a) {
     } else {
         t.st = Sten{a.kx, a.ky, a.gx, a.gy, a.kC, 0.0, 0.0, 0.0, 0.0};
     }
-    t.u = a.u;
-    t.coef = a.coef;
-    t.xi = a.xi;
+    t.u = gptr(a.u);
+    t.coef = gptr(a.coef);
+    t.xi = gptr(a.xi);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        t.p[k] = a.p[k];
+        t.p[k] = gptr(a.p[k]);
     }
     return t;
 }

@@ -72,7 +72,7 @@ __device__ __forceinline__ SweepState block_decide(const SweepArgs& a, const Loo
         for (int k = 0; k < K; ++k) {
             if (nt[k] != D) continue;   // inactive, or stopped earlier in this window
             const double pn = sqrt(tot[(j - 1) * (1 + K) + 1 + k]) * a.inv_sqrtN;
-            const double e = fabs(a.coef[k * a.ld + m + j]) * ynorm;
+            const double e = fabs(gptr(a.coef)[k * a.ld + m + j]) * ynorm;
             const double thr = ctl.rtol * pn + ctl.atol;
             nx.err[k] = e;
             nx.pnorm[k] = pn;
@@ -152,7 +152,7 @@ struct WindowPlan {
 template <int OP, int K, int D, bool kEndCopy = false, bool kFp32 = false>
 __device__ __forceinline__ bool window_enter(const SweepArgs& a, const int L, const int wg, unsigned* done,
                                              WindowPlan<K>& w) {
-    LoopCtl* __restrict__ ctl = a.ctl;
+    LoopCtl* __restrict__ ctl = gptr(a.ctl);
     constexpr int NV = D * (1 + K);
     __shared__ SweepState s_cur;
     const int tid = flat_tid();
@@ -176,7 +176,7 @@ __device__ __forceinline__ bool window_enter(const SweepArgs& a, const int L, co
         }
     } else {
         double tot[NV];
-        sum_partials<NV>(a.partials + static_cast<long>((L - 1) & 1) * a.nb * NV, a.nb, tot);
+        sum_partials<NV>(gptr(a.partials) + static_cast<long>((L - 1) & 1) * a.nb * NV, a.nb, tot);
         if (tid == 0) {
             SweepState st = block_decide<K, D, kFp32>(a, *ctl, ctl->slot[(L - 1) & 1], tot);
             if (!st.done) {
@@ -230,11 +230,11 @@ __device__ __forceinline__ bool window_enter(const SweepArgs& a, const int L, co
         if (w.nt[k] > w.jmax) w.jmax = w.nt[k];
         // an even window wrote its outputs to p2, an odd one to p
         w.copy[k] = end && (w.win & 1) == 0;
-        w.pin[k] = end ? a.p2[k] : ((w.win & 1) ? a.p2[k] : a.p[k]);
-        w.pout[k] = w.redo ? a.p[k] : ((w.win & 1) ? a.p[k] : a.p2[k]);
+        w.pin[k] = gptr(end ? a.p2[k] : ((w.win & 1) ? a.p2[k] : a.p[k]));
+        w.pout[k] = gptr(w.redo ? a.p[k] : ((w.win & 1) ? a.p[k] : a.p2[k]));
     }
-    w.yin = (w.win == 0) ? a.v : static_cast<const double*>(a.ybuf[(w.win - 1) & 1]);
-    w.yout = static_cast<double*>(a.ybuf[w.win & 1]);
+    w.yin = gptr((w.win == 0) ? a.v : static_cast<const double*>(a.ybuf[(w.win - 1) & 1]));
+    w.yout = gptr(static_cast<double*>(a.ybuf[w.win & 1]));
     return true;
 }
 
@@ -266,7 +266,7 @@ __device__ __forceinline__ void window_exit_sums(const SweepArgs& a, const int L
     constexpr int NV = D * (1 + K);
     block_sum<NV>(v);
     if (flat_tid() == 0) {
-        double* __restrict__ Pp = a.partials + static_cast<long>(L & 1) * a.nb * NV + static_cast<long>(wg) * NV;
+        double* __restrict__ Pp = gptr(a.partials) + static_cast<long>(L & 1) * a.nb * NV + static_cast<long>(wg) * NV;
 #pragma unroll
         for (int q = 0; q < NV; ++q) Pp[q] = v[q];
     }
