@@ -345,12 +345,12 @@ int pair_grid(int pnb, int tiles) {
 }
 
 // Grid of a register-marching launch (leja_stream, power_stream): strips of
-// 128 - 2D output columns by bands of rows, one item per wavefront.  By
-// default the bands make one resident round of wavefronts (no partial
-// second round), with bands of at least 4D rows so that the D rows staged
-// above and below a band stay a small share of it; workgroups are a multiple
-// of 8 when that stays within one round (each XCD then takes a contiguous
-// run of bands).
+// at most 128 - 2D output columns (stream_strips) by bands of rows, one item
+// per wavefront.  By default the bands make one resident round of wavefronts
+// (no partial second round), with bands of at least 4D rows so that the D
+// rows staged above and below a band stay a small share of it; workgroups
+// are a multiple of 8 when that stays within one round (each XCD then takes
+// a contiguous run of bands).
 struct StreamGrid {
     int strips, bands, nb;
 };

@@ -189,8 +189,9 @@ hipError_t launch_power_block_final(const PowerArgs& a, int b, int nlev, hipStre
 // diffusion-advection operator or the Burgers Jacobian (a.u, and a.u32 for
 // FP32 sweeps), nx even, sides >= depth, 16-byte aligned vectors); fp32:
 // FP32 sweeps (the device switches windows to FP32 levels, LoopCtl
-// fp32_switch); a.tiles_x = stream_strips(nx, depth) strips of
-// 128 - 2 depth output columns by a.tiles_y (1..ny) bands of rows, a.nb
+// fp32_switch); a.tiles_x = stream_strips(nx, depth) strips of at most
+// 128 - 2 depth output columns (edges on 128-byte lines where that costs at
+// most four of them) by a.tiles_y (1..ny) bands of rows, a.nb
 // workgroups of four wavefronts that each take items (strip, band) in turn;
 // partials as launch_leja_block.
 int stream_strips(int nx, int depth);

@@ -21,7 +21,7 @@
 // lanes (DPP wavefront shifts).  Nothing is formed twice along y (the
 // LDS-tile kernel forms up to 1.7 points per output point at D = 6 on 8-row
 // tiles); along x the strip's side columns are formed by two wavefronts
-// (128 columns per 128 - 2D outputs).
+// (128 columns per at most 128 - 2D outputs).
 //
 // The outputs: for the diffusion-advection operator at depths up to six
 // (ring windows, below) every level also goes into a small ring in LDS and
@@ -49,18 +49,28 @@ using namespace dev;
 constexpr int kStreamWaves = kBlockThreads / 64;   // wavefronts per workgroup, each on its own items
 
 // Columns [xs, xs + ws) and rows [yb, yb + hb) of item i: items are numbered
-// band-major over sx strips and by bands; strip widths are even.
+// band-major over sx strips and by bands; strip edges are multiples of
+// strip_unit columns.
 struct StreamItem {
     int xs, ws, yb, hb;
 };
 
+// Strip edges fall on 128-byte lines (16 FP64 columns) where that costs at
+// most four of a strip's 128 - 2 depth output columns, else on column pairs.
+// An output row segment that ends inside a line shares that line with the
+// neighbouring strip, and the nontemporal output loads then fetch it twice
+// (the shared line does not stay in L2 between the two wavefronts' loads).
+__host__ __device__ constexpr int strip_unit(const int nx, const int depth) {
+    return (nx % 16 == 0 && (128 - 2 * depth) % 16 <= 4) ? 16 : 2;
+}
+
 __device__ __forceinline__ StreamItem stream_geom(const int i, const int nx, const int ny, const int sx,
-                                                  const int by) {
+                                                  const int by, const int unit) {
     const int b = i / sx, s = i - b * sx;
-    const long half = nx >> 1;
+    const long units = nx / unit;
     StreamItem it;
-    it.xs = 2 * static_cast<int>((s * half) / sx);
-    it.ws = 2 * static_cast<int>(((s + 1) * half) / sx) - it.xs;
+    it.xs = unit * static_cast<int>((s * units) / sx);
+    it.ws = unit * static_cast<int>(((s + 1) * units) / sx) - it.xs;
     it.yb = static_cast<int>((static_cast<long>(b) * ny) / by);
     it.hb = static_cast<int>((static_cast<long>(b + 1) * ny) / by) - it.yb;
     return it;
@@ -627,8 +637,9 @@ __device__ __forceinline__ void ring_items(const RingWin<K, D>& rw, const SweepA
                                            double2* __restrict__ ring, double (&sy)[D], double (&sp)[K][D]) {
     const int items = a.tiles_x * a.tiles_y, G = a.nb * kStreamWaves;
     for (int i = stream_wave(wg, a.nb); i < items; i += G)
-        ring_window_item<K, D, T, kFirst, kIn32, J>(rw, stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y), lane,
-                                                   reinterpret_cast<P2<T>*>(ring), sy, sp);
+        ring_window_item<K, D, T, kFirst, kIn32, J>(
+            rw, stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y, strip_unit(a.nx, D)), lane,
+            reinterpret_cast<P2<T>*>(ring), sy, sp);
 }
 
 // A re-execution (FP64 levels, not the first window) forms only the levels
@@ -723,7 +734,8 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(2
         for (int k = 0; k < K; ++k) any = any || w.copy[k];
         if (any)
             for (int i = stream_wave(wg, a.nb); i < items; i += G)
-                stream_copy_item<K>(w, stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y), lane, a.nx);
+                stream_copy_item<K>(w, stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y, strip_unit(a.nx, D)), lane,
+                                    a.nx);
     } else if constexpr (kRingWindows<OP, D>) {
         __shared__ double2 ring_mem[kStreamWaves * Ring<D>::slots * 64];
         ring_windows<K, D, F32>(a, w, wg, lane, ring_mem, sy, sp);
@@ -738,14 +750,17 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(2
 #pragma unroll
         for (int j = 0; j < D; ++j) cc[j] = centre - a.xi[w.m + j];
         const TileArgs<K> ta = tile_args<OP, K>(a);
+        const int unit = strip_unit(a.nx, D);
         if (F32 && w.win32) {
             for (int i = stream_wave(wg, a.nb); i < items; i += G)
                 stream_window_item<OP, K, D, float>(ta, w, a.u32, dk, cc,
-                                                    stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y), lane, sy, sp);
+                                                    stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y, unit), lane, sy,
+                                                    sp);
         } else {
             for (int i = stream_wave(wg, a.nb); i < items; i += G)
                 stream_window_item<OP, K, D, double>(ta, w, a.u, dk, cc,
-                                                     stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y), lane, sy, sp);
+                                                     stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y, unit), lane, sy,
+                                                     sp);
         }
     }
     window_exit<K, D>(a, L, wg, sy, sp);
@@ -891,17 +906,18 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(2
     for (int j = 0; j < DP; ++j) sy[j] = 0.0;
     const int lane = static_cast<int>(threadIdx.x) & 63;
     const int items = a.tiles_x * a.tiles_y, G = a.nb * kStreamWaves;
+    const int unit = strip_unit(a.nx, DP);
     if (nl == DP) {
         const unsigned bytes = static_cast<unsigned>(a.nx) * static_cast<unsigned>(a.ny) * 8u;
         const Rsrc rin = make_rsrc(in, bytes), rout = make_rsrc(out, bytes);
         for (int i = stream_wave(wg, a.nb); i < items; i += G)
             stream_power_item<DP>(st, a.cC, a.nx, a.ny, rin, rout, scale,
-                                  stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y), lane, sy);
+                                  stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y, unit), lane, sy);
     } else {
         const Sten sa{a.cW, a.cE, a.cS, a.cN, a.cC, 0.0, 0.0, 0.0, 0.0};
         for (int i = stream_wave(wg, a.nb); i < items; i += G)
             stream_power_item_any<DP>(sa, a.nx, a.ny, in, out, scale, nl,
-                                      stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y), lane, sy);
+                                      stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y, unit), lane, sy);
     }
     block_sum<DP>(sy);
     if (flat_tid() == 0) {
@@ -951,8 +967,9 @@ const void* stream_kernel(int op, int K, int depth, bool f32) {
 }  // namespace
 
 int stream_strips(int nx, int depth) {
-    const int out_pairs = 64 - depth;   // column pairs a strip outputs
-    return ((nx / 2) + out_pairs - 1) / out_pairs;
+    const int unit = strip_unit(nx, depth);
+    const int out_units = (128 - 2 * depth) / unit;   // column units a strip outputs
+    return ((nx / unit) + out_units - 1) / out_units;
 }
 
 bool stream_has(int op, int K, int depth, bool fp32) { return stream_kernel(op, K, depth, fp32) != nullptr; }
