@@ -27,7 +27,10 @@
  *   only its context workspaces, allocated once by lx_create (Sec. 2.3,
  *   Listing 10: allocate once per object, free in the destructor).
  *   All device work is enqueued on the stream given to lx_create; every call
- *   that returns host values waits for that stream once, at its end.
+ *   that returns host values waits for that stream once, at its end, except
+ *   that a Leja loop returns as soon as it has read its final state: the few
+ *   launches it enqueued past the end then still run on the stream (they
+ *   read the loop state and return; every output is final on return).
  *   A context is not thread-safe: one host thread at a time per context.
  *   Every call returns an lx_status; on an error other than LX_ENOTCONV the
  *   outputs are unspecified and lx_last_error() holds a message.
@@ -152,7 +155,8 @@ lx_status lx_create(lx_ctx** ctx, size_t n_max, int k_max, void* stream);
  * NULL is a no-op. */
 void lx_destroy(lx_ctx* ctx);
 
-/* Changes the stream later calls enqueue on. */
+/* Changes the stream later calls enqueue on, after waiting for the one
+ * before.  Errors: LX_EDEVICE (that wait failed). */
 lx_status lx_set_stream(lx_ctx* ctx, void* stream);
 
 /* on != 0: record HIP events around every sweep so that lx_stats carries

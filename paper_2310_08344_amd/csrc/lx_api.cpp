@@ -11,6 +11,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -407,13 +408,23 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
         ctx->series[k].reset(q.l[k], q.alpha[k], q.sigma[k], q.h, q.c, q.gamma, ctx->h_xi);
     int have = 0;          // coefficients d_0..d_{have-1} computed and enqueued for upload
     double plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    auto ensure_coeffs = [&](int upto) -> lx_status {
+    // the launch that ends the loop writes its final state here (pinned)
+    volatile SweepState* pub = ctx->h_poll;
+    pub->done = 0;
+    // stop_on_done: a look ahead, abandoned (nothing uploaded, *ended set)
+    // once the loop has published its final state; the series then no longer
+    // match `have`, and the caller ends the loop
+    auto ensure_coeffs = [&](int upto, bool* ended = nullptr) -> lx_status {
         upto = std::min(upto, NC);
         if (upto <= have) return LX_OK;
         const auto ta = std::chrono::steady_clock::now();
-        for (int k = 0; k < K; ++k) {
-            double* hc = ctx->h_coef + static_cast<size_t>(k) * NC;
-            for (int j = have; j < upto; ++j) hc[j] = ctx->series[k].next();
+        for (int j = have; j < upto; ++j) {
+            if (ended != nullptr && pub->done) {
+                *ended = true;
+                plan_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - ta).count();
+                return LX_OK;
+            }
+            for (int k = 0; k < K; ++k) ctx->h_coef[static_cast<size_t>(k) * NC + j] = ctx->series[k].next();
         }
         // one copy for all outputs (each copy is a launch on the stream): the
         // span from d_have of output 0 to d_{upto-1} of output K-1 also
@@ -482,9 +493,6 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
     a.coef = ctx->coef;
     a.xi = ctx->xi;
     a.ctl = ctx->ctl;
-    // the launch that ends the loop writes its final state here (pinned)
-    volatile SweepState* pub = ctx->h_poll;
-    pub->done = 0;
     a.pub = ctx->h_poll;
     const int opcode = opcode_of(op.kind);
     const size_t need_partials = 2 * static_cast<size_t>(a.nb) * (1 + K) * (blk ? D : (pair ? 2 : 1));
@@ -528,6 +536,7 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
     // look still comes after three launches).
     const int first_chunk = blk ? 1 : std::max(3, kFirstChunk / per), next_chunk = std::max(2, kChunk / per);
     int chunk = first_chunk;
+    bool seen_done = false;   // a look at the state found the final one
     while (launched <= last) {
         const int n = std::min(chunk, last + 1 - launched);
         s = ensure_coeffs(coeffs_for(launched + n));
@@ -545,17 +554,29 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
         LX_HIP(ctx, hipEventRecord(ctx->poll_ev[slot], ctx->stream));
         last_slot = slot;
         if (chunk_id >= 1) {
-            // the next chunk's coefficients are prepared while the GPU works
-            s = ensure_coeffs(coeffs_for(std::min(launched + next_chunk, last)));
+            // the next chunk's coefficients are prepared while the GPU works,
+            // unless the final state appears meanwhile (the host then returns
+            // at once instead of finishing them first)
+            s = ensure_coeffs(coeffs_for(std::min(launched + next_chunk, last)), &seen_done);
             if (s != LX_OK) return s;
             // the chunk before has run: has a launch published the final state?
-            LX_HIP(ctx, hipEventSynchronize(ctx->poll_ev[slot ^ 1]));
-            if (pub->done) break;
+            if (!seen_done && !pub->done) LX_HIP(ctx, hipEventSynchronize(ctx->poll_ev[slot ^ 1]));
+            if (seen_done || pub->done) {
+                seen_done = true;
+                break;
+            }
         }
         ++chunk_id;
         chunk = next_chunk;
     }
-    LX_HIP(ctx, hipEventSynchronize(ctx->poll_ev[last_slot]));
+    // Once the final state is published, every launch that writes an output
+    // has finished (they precede the publishing launch on the stream); the
+    // launches still queued only read the loop state and return, so the call
+    // does not wait for them.
+    if (!seen_done) LX_HIP(ctx, hipEventSynchronize(ctx->poll_ev[last_slot]));
+    // the device writes `done` after the rest of the state (both at system
+    // scope): what follows a read of done = 1 sees the whole state
+    std::atomic_thread_fence(std::memory_order_acquire);
     const SweepState fin = *const_cast<const SweepState*>(ctx->h_poll);
     if (!fin.done) return fail(ctx, LX_EDEVICE, "the device loop did not record a final state");
 
@@ -623,7 +644,9 @@ lx_status run_leja(lx_ctx* ctx, const LejaCall& q) {
     S.plan_ms = plan_ms;
     if (timing && S.n_launch > 0) {
         // events follow every launch: a launch's interval also holds the stop
-        // decision the next one takes first (a few microseconds)
+        // decision the next one takes first (a few microseconds); the last
+        // working launch's event precedes the final state on the stream
+        LX_HIP(ctx, hipEventSynchronize(ctx->tev[S.n_launch]));
         S.first_sweep_ms = elapsed(ctx->tev[0], ctx->tev[1]);
         S.loop_ms = elapsed(ctx->tev[0], ctx->tev[S.n_launch]);
         S.sweep_ms = S.loop_ms;
@@ -835,7 +858,8 @@ lx_status run_leja_sub(lx_ctx* ctx, const LejaCall& q) {
 // kPowerStreamDepth sweeps per launch, normalised at launch boundaries.  The
 // unnormalised levels grow at most like the Gershgorin bound g of A (the
 // start of a launch has norm 1), so a launch makes at most 140 / log10(g)
-// levels: their squares stay below 1e280.
+// levels: their squares stay below 1e280 (below 1e300 for a first launch
+// that takes x0 unscaled with ||x0||^2 <= 1e20).
 lx_status spectrum_stream(lx_ctx* ctx, const lx_operator& op, const double* x0, int iters, double safety,
                           double* rho_hat, double* c, double* gamma) {
     constexpr int DP = lx::kPowerStreamDepth;
@@ -863,23 +887,37 @@ lx_status spectrum_stream(lx_ctx* ctx, const lx_operator& op, const double* x0, 
     a.partials = ctx->partials;
     a.ctl = ctx->ctl;
     const int nblk = (iters + per - 1) / per;
-    LX_HIP(ctx, lx::launch_power_norm(x0, N, a.nb, ctx->partials, ctx->stream));
     if (ctx->timing) {
         s = ensure_timing_events(ctx, static_cast<size_t>(nblk) + 1);
         if (s != LX_OK) return s;
-        LX_HIP(ctx, hipEventRecord(ctx->tev[0], ctx->stream));
     }
-    int nlev = per, prev = per;
-    for (int b = 0; b < nblk; ++b) {
-        nlev = (b == nblk - 1) ? iters - per * (nblk - 1) : per;
-        const double* in = (b == 0) ? x0 : ctx->ybuf[(b - 1) & 1];
-        LX_HIP(ctx, lx::launch_power_stream(a, in, ctx->ybuf[b & 1], b, nlev, prev, ctx->stream));
-        if (ctx->timing) LX_HIP(ctx, hipEventRecord(ctx->tev[b + 1], ctx->stream));
-        prev = nlev;
+    // raw: the first launch takes x0 unscaled and measures its norm itself
+    // (when it makes a full DP levels); a NaN estimate from it means that
+    // ||x0|| lay outside the range where that is safe, and the iteration
+    // runs again with x0 scaled first
+    auto run = [&](const bool raw) -> lx_status {
+        if (!raw) LX_HIP(ctx, lx::launch_power_norm(x0, N, a.nb, ctx->partials, ctx->stream));
+        if (ctx->timing) LX_HIP(ctx, hipEventRecord(ctx->tev[0], ctx->stream));
+        int nlev = per, prev = per;
+        for (int b = 0; b < nblk; ++b) {
+            nlev = (b == nblk - 1) ? iters - per * (nblk - 1) : per;
+            const double* in = (b == 0) ? x0 : ctx->ybuf[(b - 1) & 1];
+            LX_HIP(ctx, lx::launch_power_stream(a, in, ctx->ybuf[b & 1], b, nlev, prev, raw, ctx->stream));
+            if (ctx->timing) LX_HIP(ctx, hipEventRecord(ctx->tev[b + 1], ctx->stream));
+            prev = nlev;
+        }
+        LX_HIP(ctx, lx::launch_power_stream_final(a, nblk - 1, nlev, raw, ctx->stream));
+        LX_HIP(ctx, hipMemcpyAsync(ctx->h_ctl, ctx->ctl, sizeof(LoopCtl), hipMemcpyDeviceToHost, ctx->stream));
+        LX_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        return LX_OK;
+    };
+    const bool raw = per == DP && iters >= DP;
+    s = run(raw);
+    if (s != LX_OK) return s;
+    if (raw && !std::isfinite(ctx->h_ctl->rho)) {
+        s = run(false);
+        if (s != LX_OK) return s;
     }
-    LX_HIP(ctx, lx::launch_power_stream_final(a, nblk - 1, nlev, ctx->stream));
-    LX_HIP(ctx, hipMemcpyAsync(ctx->h_ctl, ctx->ctl, sizeof(LoopCtl), hipMemcpyDeviceToHost, ctx->stream));
-    LX_HIP(ctx, hipStreamSynchronize(ctx->stream));
     const double rho = ctx->h_ctl->rho;
     lx_stats& S = ctx->stats;
     S.n_apply = iters;
@@ -1022,6 +1060,9 @@ lx_status lx_create(lx_ctx** out, size_t n_max, int k_max, void* stream) {
 
 lx_status lx_set_stream(lx_ctx* ctx, void* stream) {
     if (ctx == nullptr) return LX_EINVAL;
+    // launches a Leja loop left queued read the loop state, which the next
+    // call resets: they finish before work goes to another stream
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return fail(ctx, LX_EDEVICE, "stream synchronisation failed");
     ctx->stream = static_cast<hipStream_t>(stream);
     return LX_OK;
 }

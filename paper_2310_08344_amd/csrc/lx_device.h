@@ -209,10 +209,14 @@ int stream_resident(int op, int K, int depth, bool fp32, int power);
 // out as for launch_power_block with kPowerStreamDepth in place of its depth.
 constexpr int kPowerStreamDepth = 10;
 // Launch b makes nlev levels, scaled by the norm of the prev levels of
-// launch b - 1 (of the start vector for b = 0).
+// launch b - 1 (of the start vector for b = 0, from launch_power_norm).
+// raw0: launch 0 takes the start vector unscaled (nlev = kPowerStreamDepth)
+// and records its norm in place of launch_power_norm; the final launch then
+// gives a NaN estimate unless ||x||^2 lay in [1e-200, 1e20] (the host then
+// repeats the iteration with the norm first).
 hipError_t launch_power_stream(const PowerArgs& a, const double* in, double* out, int b, int nlev, int prev,
-                               hipStream_t s);
-hipError_t launch_power_stream_final(const PowerArgs& a, int b, int nlev, hipStream_t s);
+                               bool raw0, hipStream_t s);
+hipError_t launch_power_stream_final(const PowerArgs& a, int b, int nlev, bool raw0, hipStream_t s);
 hipError_t launch_fill_splitmix(double* x, long n, unsigned long long seed, hipStream_t s);
 hipError_t launch_to_fp32(const double* x, float* y, long n, hipStream_t s);
 // kind 0: z = x (copy); kind 1: z = 1.5 x - 0.5 y.  n even.

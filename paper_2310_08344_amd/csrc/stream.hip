@@ -773,9 +773,15 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(2
 // The directions are those of the normalised iteration x_{k+1} = A x_k /
 // ||A x_k||, and rho_hat = ||level nlev|| / ||level nlev-1|| of the last
 // launch (level 0 has norm 1).  The host bounds nlev so that the unnormalised
-// levels (at most rho^j) stay far from overflow.
-// Partial sums: the start vector's (power_norm_kernel) at partials[nb + i],
-// launch b's at partials[2 nb + (b & 1) nb DP + i DP + j].
+// levels (at most rho^j) stay far from overflow.  With raw0 the first launch
+// takes the start vector x as it is (levels A^j x, the same directions) and
+// records ||x||^2 itself, which saves a pass over x; the final launch then
+// reports a NaN estimate unless ||x||^2 lay in [1e-200, 1e20], where the
+// unscaled levels keep the margin of the scaled ones, and the host repeats
+// the iteration with x scaled first.
+// Partial sums: the start vector's (power_norm_kernel, or launch 0 with
+// raw0) at partials[nb + i], launch b's at partials[2 nb + (b & 1) nb DP +
+// i DP + j].
 // ---------------------------------------------------------------------------
 
 // One item of a power launch that makes DP levels: level 0 (row t of `in`,
@@ -783,11 +789,13 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(2
 // every step issues the same memory operations (rows and lanes outside the
 // item's output get offsets past the end), so no step waits for the load
 // it has just issued.  Steps run in whole blocks of U; the few past the
-// staged rows store nothing and add nothing.
-template <int DP>
+// staged rows store nothing and add nothing.  kLevel0: also the sum of
+// squares of level 0 on the item's output points, into sy0.
+template <int DP, bool kLevel0>
 __device__ __forceinline__ void stream_power_item(const StenT<double>& st, const double centre, const int nx,
                                                   const int ny, const Rsrc in, const Rsrc out, const double s,
-                                                  const StreamItem it, const int lane, double (&sy)[DP]) {
+                                                  const StreamItem it, const int lane, double (&sy)[DP],
+                                                  double& sy0) {
     constexpr int Y = 4, U = 4;   // U: a multiple of Y and of 2 (the roles of lc and lq)
     const int rc = 2 * lane - DP;
     const int gcol = wrap(it.xs + rc, nx);
@@ -817,6 +825,10 @@ __device__ __forceinline__ void stream_power_item(const StenT<double>& st, const
             yq[u % Y] = buf_ld<double2>(in, col8, yoff);
             yoff += row8;
             if (yoff >= all8) yoff -= all8;
+            if constexpr (kLevel0) {
+                const int r0 = t - DP;
+                sy0 = fma(r0 >= 0 && r0 < it.hb ? mcol : 0.0, cur.x * cur.x + cur.y * cur.y, sy0);
+            }
 #pragma unroll
             for (int j = 1; j <= DP; ++j) {
                 const double2 y = stream_complete<double>(st, lq[j - 1], cur);
@@ -879,16 +891,20 @@ __device__ __forceinline__ void stream_power_item_any(const Sten& st, const int 
 
 
 // Launch b makes nlev levels from `in`, scaled by the norm of the last level
-// of launch b - 1 (which made prev levels) or of the start vector.
+// of launch b - 1 (which made prev levels) or of the start vector (b = 0:
+// unscaled with raw0, which needs nlev = DP).
 template <int DP>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void power_stream(
-    PowerArgs a, const double* in, double* out, const int b, const int nlev, const int prev) {
+    PowerArgs a, const double* in, double* out, const int b, const int nlev, const int prev, const int raw0) {
     const int wg = static_cast<int>(blockIdx.x);
-    double scale;
+    const bool lev0 = b == 0 && raw0 != 0;
+    double scale = 1.0;
     if (b == 0) {
-        double tot[1];
-        sum_partials<1>(a.partials + a.nb, a.nb, tot);
-        scale = 1.0 / sqrt(tot[0]);
+        if (!lev0) {
+            double tot[1];
+            sum_partials<1>(a.partials + a.nb, a.nb, tot);
+            scale = 1.0 / sqrt(tot[0]);
+        }
     } else {
         double tot[DP];
         sum_partials<DP>(a.partials + 2L * a.nb + static_cast<long>((b - 1) & 1) * a.nb * DP, a.nb, tot);
@@ -907,12 +923,19 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(2
     const int lane = static_cast<int>(threadIdx.x) & 63;
     const int items = a.tiles_x * a.tiles_y, G = a.nb * kStreamWaves;
     const int unit = strip_unit(a.nx, DP);
+    double sy0 = 0.0;
     if (nl == DP) {
         const unsigned bytes = static_cast<unsigned>(a.nx) * static_cast<unsigned>(a.ny) * 8u;
         const Rsrc rin = make_rsrc(in, bytes), rout = make_rsrc(out, bytes);
-        for (int i = stream_wave(wg, a.nb); i < items; i += G)
-            stream_power_item<DP>(st, a.cC, a.nx, a.ny, rin, rout, scale,
-                                  stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y, unit), lane, sy);
+        if (lev0) {
+            for (int i = stream_wave(wg, a.nb); i < items; i += G)
+                stream_power_item<DP, true>(st, a.cC, a.nx, a.ny, rin, rout, scale,
+                                            stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y, unit), lane, sy, sy0);
+        } else {
+            for (int i = stream_wave(wg, a.nb); i < items; i += G)
+                stream_power_item<DP, false>(st, a.cC, a.nx, a.ny, rin, rout, scale,
+                                             stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y, unit), lane, sy, sy0);
+        }
     } else {
         const Sten sa{a.cW, a.cE, a.cS, a.cN, a.cC, 0.0, 0.0, 0.0, 0.0};
         for (int i = stream_wave(wg, a.nb); i < items; i += G)
@@ -920,18 +943,28 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(2
                                       stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y, unit), lane, sy);
     }
     block_sum<DP>(sy);
+    if (lev0) {
+        double s0[1] = {sy0};
+        block_sum<1>(s0);
+        sy0 = s0[0];
+    }
     if (flat_tid() == 0) {
         double* __restrict__ Pp = a.partials + 2L * a.nb + static_cast<long>(b & 1) * a.nb * DP + static_cast<long>(wg) * DP;
 #pragma unroll
         for (int j = 0; j < DP; ++j) Pp[j] = sy[j];
+        if (lev0) a.partials[a.nb + wg] = sy0;
     }
 }
 
-// rho_hat = ||level nlev|| / ||level nlev-1|| of the last launch b
+// rho_hat = ||level nlev|| / ||level nlev-1|| of the last launch b; NaN
+// after an unscaled first launch (raw0) whose ||x||^2 left [1e-200, 1e20]
 template <int DP>
-__global__ __launch_bounds__(kBlockThreads) void power_stream_final(PowerArgs a, const int b, const int nlev) {
+__global__ __launch_bounds__(kBlockThreads) void power_stream_final(PowerArgs a, const int b, const int nlev,
+                                                                    const int raw0) {
     double tot[DP];
     sum_partials<DP>(a.partials + 2L * a.nb + static_cast<long>(b & 1) * a.nb * DP, a.nb, tot);
+    double x2[1] = {1.0};
+    if (raw0) sum_partials<1>(a.partials + a.nb, a.nb, x2);
     if (flat_tid() == 0) {
         double last = 0.0, prev = 1.0;
 #pragma unroll
@@ -939,7 +972,8 @@ __global__ __launch_bounds__(kBlockThreads) void power_stream_final(PowerArgs a,
             if (j == nlev - 1) last = tot[j];
             if (j == nlev - 2) prev = tot[j];
         }
-        a.ctl->rho = sqrt(last / prev);
+        const bool safe = x2[0] >= 1e-200 && x2[0] <= 1e20;
+        a.ctl->rho = safe ? sqrt(last / prev) : __builtin_nan("");
     }
 }
 
@@ -1003,18 +1037,21 @@ int stream_resident(int op, int K, int depth, bool fp32, int power) {
 }
 
 hipError_t launch_power_stream(const PowerArgs& a, const double* in, double* out, int b, int nlev, int prev,
-                               hipStream_t s) {
+                               bool raw0, hipStream_t s) {
     constexpr int DP = kPowerStreamDepth;
     if (a.nb < 1 || a.nx % 2 != 0 || a.nx < DP || a.ny < DP || nlev < 1 || nlev > DP || prev < 1 || prev > DP)
         return hipErrorInvalidValue;
+    if (raw0 && b == 0 && nlev != DP) return hipErrorInvalidValue;
     if (a.tiles_x != stream_strips(a.nx, DP) || a.tiles_y < 1 || a.tiles_y > a.ny) return hipErrorInvalidValue;
     if (static_cast<long>(a.nx) * a.ny * 8 > static_cast<long>(kFar)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((power_stream<DP>), dim3(a.nb), dim3(kBlockThreads), 0, s, a, in, out, b, nlev, prev);
+    hipLaunchKernelGGL((power_stream<DP>), dim3(a.nb), dim3(kBlockThreads), 0, s, a, in, out, b, nlev, prev,
+                       raw0 ? 1 : 0);
     return hipGetLastError();
 }
 
-hipError_t launch_power_stream_final(const PowerArgs& a, int b, int nlev, hipStream_t s) {
-    hipLaunchKernelGGL((power_stream_final<kPowerStreamDepth>), dim3(1), dim3(kBlockThreads), 0, s, a, b, nlev);
+hipError_t launch_power_stream_final(const PowerArgs& a, int b, int nlev, bool raw0, hipStream_t s) {
+    hipLaunchKernelGGL((power_stream_final<kPowerStreamDepth>), dim3(1), dim3(kBlockThreads), 0, s, a, b, nlev,
+                       raw0 ? 1 : 0);
     return hipGetLastError();
 }
 

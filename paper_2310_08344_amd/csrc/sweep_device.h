@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
+
 #include "lx_device.h"
 
 namespace lx {
@@ -158,16 +160,22 @@ __device__ __forceinline__ void block_sum(double (&v)[NV]) {
 // they meet at barriers later.
 // The final state of a loop, into slot[2] and, when the caller gave one,
 // into its host-visible copy (pinned host memory, written through to
-// system scope), which the host reads after the launch without a copy.  The
-// copy goes word by word from slot[2], so that the state needs no private
-// memory.
+// system scope), which the host may read as soon as it sees done = 1, while
+// the launch still runs: the word holding `done` goes last, after a
+// system-scope fence.  The copy goes word by word from slot[2], so that the
+// state needs no private memory.
 __device__ __forceinline__ void publish_final(LoopCtl* ctl, SweepState* pub, const SweepState& st) {
     ctl->slot[2] = st;
     if (pub != nullptr) {
         static_assert(sizeof(SweepState) % sizeof(unsigned long long) == 0, "SweepState in 8-byte words");
+        constexpr int kWords = static_cast<int>(sizeof(SweepState) / sizeof(unsigned long long));
+        constexpr int kDone = static_cast<int>(offsetof(SweepState, done) / sizeof(unsigned long long));
         const unsigned long long* src = reinterpret_cast<const unsigned long long*>(&ctl->slot[2]);
         unsigned long long* dst = reinterpret_cast<unsigned long long*>(pub);
-        for (int i = 0; i < static_cast<int>(sizeof(SweepState) / sizeof(unsigned long long)); ++i) dst[i] = src[i];
+        for (int i = 0; i < kWords; ++i)
+            if (i != kDone) dst[i] = src[i];
+        __threadfence_system();
+        dst[kDone] = src[kDone];
         __threadfence_system();
     }
 }

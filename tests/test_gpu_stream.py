@@ -183,6 +183,26 @@ def test_stream_power_iteration_matches_oracle(ctx, nx, ny, iters):
     assert abs(rho - rho_o) <= 1e-12 * rho_o
 
 
+@pytest.mark.parametrize("scale", [1e-110, 1e-90, 1.0, 1e5, 1e15])
+def test_stream_power_iteration_start_vector_scale(ctx, scale):
+    """The first launch takes the start vector unscaled and measures its
+    norm itself when ||x0||^2 lies in [1e-200, 1e20]; outside that range
+    (here 1e-110 and 1e15 on 200 x 136 N(0,1) values) the iteration runs
+    again with x0 scaled first.  Either way rho_hat is the normalised
+    iteration's, which does not depend on the scale of x0."""
+    nx, ny, iters = 200, 136, 20
+    prm, _ = diffadv_setup(nx, ny, D=0.7, vx=-30.0, vy=45.0)
+    x0 = np.random.default_rng(17).standard_normal((ny, nx))
+    say("stream power, start vector scaled by", scale)
+    ctx.set_window_kernel(2)
+    try:
+        rho, _, _ = ctx.spectrum(_op(prm), x0=dev(scale * x0), iters=iters)
+    finally:
+        ctx.set_window_kernel(0)
+    rho_o, _ = power_iteration(_A(prm), x0, iters)
+    assert np.isfinite(rho) and abs(rho - rho_o) <= 1e-12 * rho_o
+
+
 # ---------------------------------------------------------------------------
 # the Burgers Jacobian, and FP32 sweeps, by register marching
 # ---------------------------------------------------------------------------
