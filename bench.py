@@ -64,9 +64,9 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def committed_traffic(launch_bytes: float, family: str):
+def committed_traffic(launch_bytes: float, family: str, depth: int):
     """HBM bytes per launch of the sweep from the committed counter summary,
-    if it was taken on the current kernel source."""
+    if it was taken on the current kernel source at the same depth."""
     if family not in TRAFFIC_FILES:
         return None
     try:
@@ -75,7 +75,7 @@ def committed_traffic(launch_bytes: float, family: str):
     except (OSError, ValueError):
         return None
     from paper_2310_08344_amd.profsummary import sweep_source_hash
-    if t.get("sweep_source_sha256") != sweep_source_hash():
+    if t.get("sweep_source_sha256") != sweep_source_hash() or t.get("depth") != depth:
         return None
     return {"bytes_per_launch": t["hbm_bytes_per_launch"], "ratio_to_algorithmic":
             round(t["hbm_bytes_per_launch"] / launch_bytes, 4) if launch_bytes else None}
@@ -531,12 +531,12 @@ def main() -> int:
         for m in range(max(its)):
             one_iter_bytes += n_pts * (16.0 + sum((8.0 if m == 0 else 16.0) for i in its if m < i))
     traffic = committed_traffic(per_launch, "leja_stream" if last["marching"] else
-                                ("leja_block" if depth >= 3 else "other"))
+                                ("leja_block" if depth >= 3 else "other"), depth)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic["bytes_per_launch"] if traffic else None,
-            "kernel": (f"leja_stream (diffusion-advection, K=3, FP64, register-marching windows of {depth} "
-                       "iterations)" if last["marching"] else
+            "kernel": (f"{'leja_stream_deep' if depth >= 7 else 'leja_stream'} (diffusion-advection, K=3, FP64, "
+                       f"register-marching windows of {depth} iterations)" if last["marching"] else
                        {2: "leja_pair (diffusion-advection, K=3, FP64, two iterations per launch)",
                         3: "leja_block (diffusion-advection, K=3, FP64, windows of three iterations)",
                         4: "leja_block (diffusion-advection, K=3, FP64, windows of four iterations)",

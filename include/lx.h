@@ -521,8 +521,8 @@ lx_status lx_set_tile(lx_ctx* ctx, int tx, int ty, int ry, int vec, int nb);
  * LDS tiles (FP64 sweeps) 3 and 4 to the diffusion-advection operators and
  * the Burgers Jacobian, 6 to LX_OP_DIFFADV2D (others fall back to 4, then
  * 2), each with sides of at least depth times the stencil radius; register
- * marching to LX_OP_DIFFADV2D (FP64: depth 4 for K <= 4, 6 for K <= 3, 8
- * for K = 1) and LX_OP_BURGERS2D (depth 4 for K <= 2, 6 for K = 1), and to
+ * marching to LX_OP_DIFFADV2D (FP64: depth 4 for K <= 4, 6 and 8 for
+ * K <= 3) and LX_OP_BURGERS2D (depth 4 for K <= 2, 6 for K = 1), and to
  * FP32 sweeps of both for K <= 2 at depth 4 and K = 1 at 6 (windows switch
  * to FP32 levels on the device); depth 8 otherwise falls back to 6; other
  * calls use depth 1 (FP32 sweeps: one per launch).

@@ -23,12 +23,14 @@
 // tiles); along x the strip's side columns are formed by two wavefronts
 // (128 columns per at most 128 - 2D outputs).
 //
-// The outputs: for the diffusion-advection operator at depths up to six
-// (ring windows, below) every level also goes into a small ring in LDS and
-// the outputs of row t - D take all their terms at step t; otherwise
-// (Burgers, depth eight) an output row enters the registers when level 0
-// reaches it, takes term j when level j does, and leaves after its last
-// term, D + 1 rows of every output in flight.
+// The outputs: for the diffusion-advection operator (ring windows, below)
+// every level also goes into a small ring in LDS and the outputs of row
+// t - D take all their terms at step t; otherwise (the Burgers Jacobian) an
+// output row enters the registers when level 0 reaches it, takes term j
+// when level j does, and leaves after its last term, D + 1 rows of every
+// output in flight.  Rings of depth 7 or 8 (28 KB or 35 KB per wavefront)
+// leave room in LDS for one wavefront per SIMD: those windows have a kernel
+// of their own, allowed the registers of a single wavefront.
 //
 // Each wavefront's items are a contiguous run of bands of one XCD, so the
 // side columns a neighbouring strip also loads come from that XCD's L2.
@@ -452,7 +454,11 @@ struct Ring {
 };
 
 template <int OP, int D>
-constexpr bool kRingWindows = OP == kOpDiffAdv && D >= 3 && D <= 6;
+constexpr bool kRingWindows = OP == kOpDiffAdv && D >= 3 && D <= 8;
+
+// ring windows whose rings leave room for one wavefront per SIMD
+template <int OP, int D>
+constexpr bool kDeepRing = kRingWindows<OP, D> && D >= 7;
 
 // Buffer resources (raw, byte offsets).  An offset at or past the size
 // reads zeros and writes nothing; kFar is past every buffer a ring window
@@ -710,8 +716,7 @@ __device__ __forceinline__ void ring_windows(const SweepArgs& a, const WindowPla
 // workgroups of kStreamWaves wavefronts.  F32: FP32 sweeps (windows switch
 // to FP32 levels on the device, window_enter; both precisions in one kernel).
 template <int OP, int K, int D, bool F32>
-__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void leja_stream(SweepArgs a,
-                                                                                                const int L) {
+__device__ __forceinline__ void leja_stream_body(const SweepArgs& a, const int L) {
     if (loop_ended(a.ctl)) return;
     const int wg = static_cast<int>(blockIdx.x);
     WindowPlan<K> w;
@@ -764,6 +769,19 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(2
         }
     }
     window_exit<K, D>(a, L, wg, sy, sp);
+}
+
+template <int OP, int K, int D, bool F32>
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void leja_stream(SweepArgs a,
+                                                                                                const int L) {
+    leja_stream_body<OP, K, D, F32>(a, L);
+}
+
+// The same at one wavefront per SIMD (kDeepRing), with its registers.
+template <int OP, int K, int D, bool F32>
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void leja_stream_deep(
+    SweepArgs a, const int L) {
+    leja_stream_body<OP, K, D, F32>(a, L);
 }
 
 // ---------------------------------------------------------------------------
@@ -978,21 +996,36 @@ __global__ __launch_bounds__(kBlockThreads) void power_stream_final(PowerArgs a,
 }
 
 // The register-marching window kernels there are: the five-point
-// diffusion-advection operator at depth 4 (K <= 4), 6 (K <= 3) and 8 (K = 1)
+// diffusion-advection operator at depth 4 (K <= 4), 6 (K <= 3) and 8 (K <= 3)
 // in FP64, and the Burgers Jacobian at depth 4 (K <= 2) and 6 (K = 1); FP32
 // sweeps for K <= 2 at depths 4 and 6 (K = 1) of both operators.
 #define LX_STREAM_KERNELS(X)                                                                              \
     X(kOpDiffAdv, 1, 4, false) X(kOpDiffAdv, 2, 4, false) X(kOpDiffAdv, 3, 4, false)                      \
     X(kOpDiffAdv, 4, 4, false) X(kOpDiffAdv, 1, 6, false) X(kOpDiffAdv, 2, 6, false)                      \
-    X(kOpDiffAdv, 3, 6, false) X(kOpDiffAdv, 1, 8, false) X(kOpBurgersJ, 1, 4, false)                     \
-    X(kOpBurgersJ, 2, 4, false) X(kOpBurgersJ, 1, 6, false) X(kOpDiffAdv, 1, 4, true)                     \
-    X(kOpDiffAdv, 2, 4, true) X(kOpDiffAdv, 1, 6, true) X(kOpBurgersJ, 1, 4, true)                        \
-    X(kOpBurgersJ, 2, 4, true) X(kOpBurgersJ, 1, 6, true)
+    X(kOpDiffAdv, 3, 6, false) X(kOpDiffAdv, 1, 8, false) X(kOpDiffAdv, 2, 8, false)                      \
+    X(kOpDiffAdv, 3, 8, false) X(kOpBurgersJ, 1, 4, false) X(kOpBurgersJ, 2, 4, false)                    \
+    X(kOpBurgersJ, 1, 6, false) X(kOpDiffAdv, 1, 4, true) X(kOpDiffAdv, 2, 4, true)                       \
+    X(kOpDiffAdv, 1, 6, true) X(kOpBurgersJ, 1, 4, true) X(kOpBurgersJ, 2, 4, true)                       \
+    X(kOpBurgersJ, 1, 6, true)
+
+// the kernel of a (operator, K, depth, precision) combination, and its launch
+template <int OP, int K, int D, bool F32>
+const void* stream_fn() {
+    if constexpr (kDeepRing<OP, D>) return reinterpret_cast<const void*>(leja_stream_deep<OP, K, D, F32>);
+    else return reinterpret_cast<const void*>(leja_stream<OP, K, D, F32>);
+}
+
+template <int OP, int K, int D, bool F32>
+void stream_launch(const SweepArgs& a, const int L, hipStream_t s) {
+    if constexpr (kDeepRing<OP, D>)
+        hipLaunchKernelGGL((leja_stream_deep<OP, K, D, F32>), dim3(a.nb), dim3(kBlockThreads), 0, s, a, L);
+    else
+        hipLaunchKernelGGL((leja_stream<OP, K, D, F32>), dim3(a.nb), dim3(kBlockThreads), 0, s, a, L);
+}
 
 const void* stream_kernel(int op, int K, int depth, bool f32) {
 #define LX_STREAM_PICK(O, KK, DD, F)                                                    \
-    if (op == (O) && K == (KK) && depth == (DD) && f32 == (F))                          \
-        return reinterpret_cast<const void*>(leja_stream<(O), (KK), (DD), (F)>);
+    if (op == (O) && K == (KK) && depth == (DD) && f32 == (F)) return stream_fn<(O), (KK), (DD), (F)>();
     LX_STREAM_KERNELS(LX_STREAM_PICK)
 #undef LX_STREAM_PICK
     return nullptr;
@@ -1016,7 +1049,7 @@ hipError_t launch_leja_stream(int op, int K, int depth, bool fp32, const SweepAr
     if (static_cast<long>(a.nx) * a.ny * 8 > static_cast<long>(kFar)) return hipErrorInvalidValue;
 #define LX_STREAM_LAUNCH(O, KK, DD, F)                                                                         \
     if (op == (O) && K == (KK) && depth == (DD) && fp32 == (F)) {                                              \
-        hipLaunchKernelGGL((leja_stream<(O), (KK), (DD), (F)>), dim3(a.nb), dim3(kBlockThreads), 0, s, a, L); \
+        stream_launch<(O), (KK), (DD), (F)>(a, L, s);                                                          \
         return hipGetLastError();                                                                              \
     }
     LX_STREAM_KERNELS(LX_STREAM_LAUNCH)

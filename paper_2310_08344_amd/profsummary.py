@@ -136,6 +136,7 @@ def main(argv=None) -> int:
     t.add_argument("--algorithmic", type=float, default=None, help="algorithmic bytes per working launch")
     t.add_argument("--max-bpp", type=float, default=float("inf"),
                    help="count only launches below this many bytes per point (separates grid sizes)")
+    t.add_argument("--depth", type=int, default=None, help="iterations per launch of the profiled kernel")
     t.add_argument("--json", default=None)
     a = ap.parse_args(argv)
     if a.cmd == "stats":
@@ -155,6 +156,8 @@ def main(argv=None) -> int:
     else:
         r = traffic(a.fetch_dir, a.write_dir, a.kernel, a.points, max_bytes_per_point=a.max_bpp)
         r["kernel"] = a.kernel
+        if a.depth is not None:
+            r["depth"] = a.depth
         r["sweep_source_sha256"] = sweep_source_hash()
         if a.algorithmic and r["hbm_bytes_per_launch"]:
             r["algorithmic_bytes_per_launch"] = a.algorithmic

@@ -524,8 +524,8 @@ def test_tune_then_solve(ctx):
     rows = ctx.tune(_op(prm), K=2, sweeps=3)
     assert len(rows) >= 4 and all(r[5] > 0 for r in rows)
     # one iteration per launch, two, windows of three, four and six on LDS
-    # tiles, and register-marching windows of four and six (100 + D; eight for K = 1 only)
-    assert {r[0] for r in rows} == {1, 2, 3, 4, 6, 104, 106}
+    # tiles, and register-marching windows of four, six and eight (100 + D)
+    assert {r[0] for r in rows} == {1, 2, 3, 4, 6, 104, 106, 108}
     v = np.random.default_rng(41).standard_normal((256, 384))
     outs = [dev(np.zeros((256, 384))) for _ in range(2)]
     r = ctx.phi_leja(_op(prm), dev(v), outs, [1, 2], h, c, g, rtol=1e-8, max_iters=200)

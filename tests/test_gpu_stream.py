@@ -54,7 +54,7 @@ def _solve(ctx, depth, kind, bands, nb, op, v, ls, h, c, g, **kw):
     return r, [host(o) for o in outs]
 
 
-CASES = [(4, [0, 1, 3, 2]), (6, [0, 1, 3]), (6, [2]), (8, [1]), (4, [1])]
+CASES = [(4, [0, 1, 3, 2]), (6, [0, 1, 3]), (6, [2]), (8, [1]), (8, [0, 1, 3]), (8, [2, 3]), (4, [1])]
 
 
 @pytest.mark.parametrize("depth,ls", CASES)
@@ -91,8 +91,7 @@ def test_stream_small_and_odd_grids(ctx, depth, nx, ny):
     prm, h = diffadv_setup(nx, ny, cfl=20.0)
     c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
     v = np.random.default_rng(nx * 100 + ny).standard_normal((ny, nx))
-    # three outputs at depth 6: two groups of wavefronts per item
-    ls = {4: [0, 2], 6: [0, 1, 3], 8: [1]}[depth]
+    ls = {4: [0, 2], 6: [0, 1, 3], 8: [0, 1, 3]}[depth]
     say("stream small grid", depth, nx, ny)
     r, o = _solve(ctx, depth, 2, 0, 0, _op(prm), v, ls, h, c, g, rtol=1e-9, max_iters=300)
     assert r.status == B.LX_OK
@@ -102,12 +101,11 @@ def test_stream_small_and_odd_grids(ctx, depth, nx, ny):
     oracle_parity(o, r.iters, lambda f: leja_phi(_A(prm), v, spec, h, c, g, 1e-9, 0.0, 300, f), PARITY)
 
 
-@pytest.mark.parametrize("depth,K", [(4, 2), (6, 2), (6, 3), (8, 1)])
+@pytest.mark.parametrize("depth,K", [(4, 2), (6, 2), (6, 3), (8, 1), (8, 2), (8, 3)])
 @pytest.mark.parametrize("max_iters", [1, 2, 3, 4, 5, 6, 7, 8, 9, 13])
 def test_stream_windows_at_max_iters(ctx, depth, K, max_iters):
     """The budget ends at every position inside a window: LX_ENOTCONV with
-    exactly max_iters terms (the re-execution takes fewer than D terms; for
-    three outputs at depth 6, two groups of wavefronts per item)."""
+    exactly max_iters terms (the re-execution takes fewer than D terms)."""
     prm, h = diffadv_setup(96, 64)
     c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
     v = np.random.default_rng(4).standard_normal((64, 96))
@@ -133,7 +131,7 @@ def test_stream_edge_inputs(ctx, depth):
     assert r.status == B.LX_ENONFINITE
 
 
-@pytest.mark.parametrize("depth,ls", [(6, [1, 2, 3]), (4, [1, 2, 3]), (8, [1])])
+@pytest.mark.parametrize("depth,ls", [(6, [1, 2, 3]), (4, [1, 2, 3]), (8, [1]), (8, [1, 2, 3])])
 def test_stream_1024_squared_workload(ctx, depth, ls):
     """The 1024^2 phi_1..phi_3 workload: oracle parity and the exact Fourier
     solution within 10 x tol."""
