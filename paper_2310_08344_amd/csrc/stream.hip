@@ -529,9 +529,10 @@ struct RingWin {
 // One item of a ring window.  kFirst: the first window (outputs that start
 // from d_m y_m); kIn32: y_m stored in FP32 (FP32 levels only); J: the
 // levels formed, D in a window, fewer in a re-execution whose outputs take
-// no term past J (it writes no y).  ring: this wavefront's Ring<D>::slots
-// rows, lane-major.
-template <int K, int D, typename T, bool kFirst, bool kIn32, int J = D>
+// no term past J (it writes no y); kShared: every output starts from the
+// rows of base[0] (a first window without copies: y_m), loaded once per
+// step.  ring: this wavefront's Ring<D>::slots rows, lane-major.
+template <int K, int D, typename T, bool kFirst, bool kIn32, int J = D, bool kShared = false>
 __device__ __forceinline__ void ring_window_item(const RingWin<K, D>& rw, const StreamItem it, const int lane,
                                                  P2<T>* __restrict__ ring, double (&sy)[D], double (&sp)[K][D]) {
     using R = Ring<D>;
@@ -569,9 +570,10 @@ __device__ __forceinline__ void ring_window_item(const RingWin<K, D>& rw, const 
     }
     // the rows the outputs start from, rows t - D .. t - D + P - 1 (none
     // before step 2D is an output row)
-    double2 bq[K][P];
+    constexpr int KB = kShared ? 1 : K;
+    double2 bq[KB][P];
 #pragma unroll
-    for (int k = 0; k < K; ++k)
+    for (int k = 0; k < KB; ++k)
 #pragma unroll
         for (int i = 0; i < P; ++i) bq[k][i] = double2{0.0, 0.0};
 
@@ -588,15 +590,20 @@ __device__ __forceinline__ void ring_window_item(const RingWin<K, D>& rw, const 
         const bool vs = os >= 0 && os < it.hb, vl = ol >= 0 && ol < it.hb;
         const unsigned so = vs ? static_cast<unsigned>(it.yb + os) * row8 : kFar;
         const unsigned lo = vl ? static_cast<unsigned>(it.yb + ol) * row8 : kFar;
+        double2 b[KB];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            b[k] = bq[k][u % P];
+            bq[k][u % P] = buf_ld<double2, kNontemporal>(rw.base[k], ocol8 + lo, 0);
+        }
         double2 p[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            p[k] = bq[k][u % P];
+            p[k] = b[kShared ? 0 : k];
             if constexpr (kFirst) {
                 p[k].x = rw.s0[k] * p[k].x;
                 p[k].y = rw.s0[k] * p[k].y;
             }
-            bq[k][u % P] = buf_ld<double2, kNontemporal>(rw.base[k], ocol8 + lo, 0);
         }
         const double mo = vs ? mcol : 0.0;
 #pragma unroll
@@ -638,12 +645,12 @@ __device__ __forceinline__ void ring_window_item(const RingWin<K, D>& rw, const 
 }
 
 // This wavefront's items of a ring window launch.
-template <int K, int D, typename T, bool kFirst, bool kIn32, int J = D>
+template <int K, int D, typename T, bool kFirst, bool kIn32, int J = D, bool kShared = false>
 __device__ __forceinline__ void ring_items(const RingWin<K, D>& rw, const SweepArgs& a, const int wg, const int lane,
                                            double2* __restrict__ ring, double (&sy)[D], double (&sp)[K][D]) {
     const int items = a.tiles_x * a.tiles_y, G = a.nb * kStreamWaves;
     for (int i = stream_wave(wg, a.nb); i < items; i += G)
-        ring_window_item<K, D, T, kFirst, kIn32, J>(
+        ring_window_item<K, D, T, kFirst, kIn32, J, kShared>(
             rw, stream_geom(i, a.nx, a.ny, a.tiles_x, a.tiles_y, strip_unit(a.nx, D)), lane,
             reinterpret_cast<P2<T>*>(ring), sy, sp);
 }
@@ -667,7 +674,9 @@ __device__ __forceinline__ void ring_redo(const int jmax, const RingWin<K, D>& r
 
 // The items of a ring window launch (this wavefront's share), with the
 // launch's buffers and coefficients set up once.
-template <int K, int D, bool F32>
+// kLaunch0: launch 0, always the first window, neither re-executed nor
+// copying, whose outputs all start from y_m: only that form is compiled.
+template <int K, int D, bool F32, bool kLaunch0>
 __device__ __forceinline__ void ring_windows(const SweepArgs& a, const WindowPlan<K>& w, const int wg, const int lane,
                                              double2* __restrict__ ring_mem, double (&sy)[D], double (&sp)[K][D]) {
     RingWin<K, D> rw;
@@ -704,18 +713,18 @@ __device__ __forceinline__ void ring_windows(const SweepArgs& a, const WindowPla
         else if (in32) ring_items<K, D, float, false, true>(rw, a, wg, lane, ring, sy, sp);
         else ring_items<K, D, float, false, false>(rw, a, wg, lane, ring, sy, sp);
     } else if (first) {
-        ring_items<K, D, double, true, false>(rw, a, wg, lane, ring, sy, sp);
-    } else if (w.redo) {
-        ring_redo<K, D, 1>(w.jmax, rw, a, wg, lane, ring, sy, sp);
-    } else {
-        ring_items<K, D, double, false, false>(rw, a, wg, lane, ring, sy, sp);
+        if constexpr (kLaunch0) ring_items<K, D, double, true, false, D, true>(rw, a, wg, lane, ring, sy, sp);
+        else ring_items<K, D, double, true, false>(rw, a, wg, lane, ring, sy, sp);
+    } else if constexpr (!kLaunch0) {
+        if (w.redo) ring_redo<K, D, 1>(w.jmax, rw, a, wg, lane, ring, sy, sp);
+        else ring_items<K, D, double, false, false>(rw, a, wg, lane, ring, sy, sp);
     }
 }
 
 // Launch L of the window loop: a.tiles_x strips by a.tiles_y bands, a.nb
 // workgroups of kStreamWaves wavefronts.  F32: FP32 sweeps (windows switch
 // to FP32 levels on the device, window_enter; both precisions in one kernel).
-template <int OP, int K, int D, bool F32>
+template <int OP, int K, int D, bool F32, bool kLaunch0 = false>
 __device__ __forceinline__ void leja_stream_body(const SweepArgs& a, const int L) {
     if (loop_ended(a.ctl)) return;
     const int wg = static_cast<int>(blockIdx.x);
@@ -743,7 +752,7 @@ __device__ __forceinline__ void leja_stream_body(const SweepArgs& a, const int L
                                     a.nx);
     } else if constexpr (kRingWindows<OP, D>) {
         __shared__ double2 ring_mem[kStreamWaves * Ring<D>::slots * 64];
-        ring_windows<K, D, F32>(a, w, wg, lane, ring_mem, sy, sp);
+        ring_windows<K, D, F32, kLaunch0>(a, w, wg, lane, ring_mem, sy, sp);
     } else {
         // the window's coefficients
         double dk[K][D + 1], cc[D];
@@ -777,11 +786,22 @@ __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(2
     leja_stream_body<OP, K, D, F32>(a, L);
 }
 
-// The same at one wavefront per SIMD (kDeepRing), with its registers.
+// The same at one wavefront per SIMD (kDeepRing), with its registers; launch
+// 0 (the first window) has a kernel of its own, since the registers of a
+// kernel are allocated over all its forms and the first window's form,
+// compiled beside the others, cost the full windows 12 % (and, in its
+// general form with a start row per output, took half as long again as a
+// full window itself).
 template <int OP, int K, int D, bool F32>
 __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void leja_stream_deep(
     SweepArgs a, const int L) {
     leja_stream_body<OP, K, D, F32>(a, L);
+}
+
+template <int OP, int K, int D, bool F32>
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void leja_stream_deep_first(
+    SweepArgs a) {
+    leja_stream_body<OP, K, D, F32, true>(a, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1017,9 +1037,10 @@ const void* stream_fn() {
 
 template <int OP, int K, int D, bool F32>
 void stream_launch(const SweepArgs& a, const int L, hipStream_t s) {
-    if constexpr (kDeepRing<OP, D>)
-        hipLaunchKernelGGL((leja_stream_deep<OP, K, D, F32>), dim3(a.nb), dim3(kBlockThreads), 0, s, a, L);
-    else
+    if constexpr (kDeepRing<OP, D>) {
+        if (L == 0) hipLaunchKernelGGL((leja_stream_deep_first<OP, K, D, F32>), dim3(a.nb), dim3(kBlockThreads), 0, s, a);
+        else hipLaunchKernelGGL((leja_stream_deep<OP, K, D, F32>), dim3(a.nb), dim3(kBlockThreads), 0, s, a, L);
+    } else
         hipLaunchKernelGGL((leja_stream<OP, K, D, F32>), dim3(a.nb), dim3(kBlockThreads), 0, s, a, L);
 }
 
