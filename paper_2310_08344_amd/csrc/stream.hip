@@ -716,8 +716,49 @@ __device__ __forceinline__ void ring_windows(const SweepArgs& a, const WindowPla
         if constexpr (kLaunch0) ring_items<K, D, double, true, false, D, true>(rw, a, wg, lane, ring, sy, sp);
         else ring_items<K, D, double, true, false>(rw, a, wg, lane, ring, sy, sp);
     } else if constexpr (!kLaunch0) {
-        if (w.redo) ring_redo<K, D, 1>(w.jmax, rw, a, wg, lane, ring, sy, sp);
-        else ring_items<K, D, double, false, false>(rw, a, wg, lane, ring, sy, sp);
+        // a window in which one output still takes terms runs the
+        // one-output form (the others' work is all masked: loads of nothing,
+        // products by 0); its sums go to that output's place, the others'
+        // stay 0, and every operation on that output is the same
+        int nact = 0, kact = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (w.nt[k] > 0) {
+                ++nact;
+                kact = k;
+            }
+        if (w.redo) {
+            ring_redo<K, D, 1>(w.jmax, rw, a, wg, lane, ring, sy, sp);
+        } else if (K > 1 && nact == 1) {
+            RingWin<1, D> r1;
+            r1.nx = rw.nx;
+            r1.ny = rw.ny;
+            r1.st = rw.st;
+#pragma unroll
+            for (int j = 0; j < D; ++j) r1.cc[j] = rw.cc[j];
+            r1.yin = rw.yin;
+            r1.yout = rw.yout;
+            r1.s0[0] = 1.0;
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (k == kact) {
+                    r1.base[0] = rw.base[k];
+                    r1.pout[0] = rw.pout[k];
+#pragma unroll
+                    for (int j = 1; j <= D; ++j) r1.dk[0][j] = rw.dk[k][j];
+                }
+            double s1[1][D];
+#pragma unroll
+            for (int j = 0; j < D; ++j) s1[0][j] = 0.0;
+            ring_items<1, D, double, false, false>(r1, a, wg, lane, ring, sy, s1);
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int j = 0; j < D; ++j)
+                    if (k == kact) sp[k][j] += s1[0][j];
+        } else {
+            ring_items<K, D, double, false, false>(rw, a, wg, lane, ring, sy, sp);
+        }
     }
 }
 
