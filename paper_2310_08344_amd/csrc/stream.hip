@@ -716,10 +716,11 @@ __device__ __forceinline__ void ring_windows(const SweepArgs& a, const WindowPla
         if constexpr (kLaunch0) ring_items<K, D, double, true, false, D, true>(rw, a, wg, lane, ring, sy, sp);
         else ring_items<K, D, double, true, false>(rw, a, wg, lane, ring, sy, sp);
     } else if constexpr (!kLaunch0) {
-        // a window in which one output still takes terms runs the
-        // one-output form (the others' work is all masked: loads of nothing,
-        // products by 0); its sums go to that output's place, the others'
-        // stay 0, and every operation on that output is the same
+        // a window in which one output still takes terms, or a re-execution
+        // that recomputes one output and copies none, runs the one-output
+        // form (the others' work is all masked: loads of nothing, products
+        // by 0); its sums go to that output's place, the others' stay 0, and
+        // every operation on that output is the same
         int nact = 0, kact = 0;
 #pragma unroll
         for (int k = 0; k < K; ++k)
@@ -727,7 +728,10 @@ __device__ __forceinline__ void ring_windows(const SweepArgs& a, const WindowPla
                 ++nact;
                 kact = k;
             }
-        if (w.redo) {
+        bool copies = false;
+#pragma unroll
+        for (int k = 0; k < K; ++k) copies = copies || w.copy[k];
+        if (w.redo && !(K > 1 && nact == 1 && !copies)) {
             ring_redo<K, D, 1>(w.jmax, rw, a, wg, lane, ring, sy, sp);
         } else if (K > 1 && nact == 1) {
             RingWin<1, D> r1;
@@ -750,7 +754,8 @@ __device__ __forceinline__ void ring_windows(const SweepArgs& a, const WindowPla
             double s1[1][D];
 #pragma unroll
             for (int j = 0; j < D; ++j) s1[0][j] = 0.0;
-            ring_items<1, D, double, false, false>(r1, a, wg, lane, ring, sy, s1);
+            if (w.redo) ring_redo<1, D, 1>(w.jmax, r1, a, wg, lane, ring, sy, s1);
+            else ring_items<1, D, double, false, false>(r1, a, wg, lane, ring, sy, s1);
 #pragma unroll
             for (int k = 0; k < K; ++k)
 #pragma unroll
