@@ -541,7 +541,7 @@ lx_status lx_set_depth(lx_ctx* ctx, int depth, int th, int nb);
  * Register marching gives every wavefront a strip of 128 columns (its
  * output columns and depth columns on each side) and a band of rows, which
  * it walks from top to bottom forming all levels of the window in
- * registers; for LX_OP_DIFFADV2D at depths 4 and 6 every level also passes
+ * registers; for LX_OP_DIFFADV2D at depths 4, 6 and 8 every level also passes
  * through a small ring in LDS, from which each output row takes its terms
  * depth rows later.  bands: bands of rows (0 = one resident round of wavefronts);
  * nb: workgroups of four wavefronts (0 = automatic).  Results are the same
