@@ -83,6 +83,26 @@ def test_stream_windows_match_oracle_and_tiles(ctx, depth, ls, bands, nb):
             assert all(np.array_equal(a, b) for a, b in zip(os_, ot))
 
 
+@pytest.mark.parametrize("ls", [[0, 1, 3], [1, 2, 3], [2, 3]])
+def test_stream_depth8_matches_depth4_bitwise(ctx, ls):
+    """Every depth takes each output's terms in the same order with the
+    same operations, so windows of eight (the first-window kernel, the
+    one-output forms of the last windows and re-executions) and of four
+    give the same bits whenever the iteration counts agree; outputs stop in
+    different windows here."""
+    prm, h = diffadv_setup(200, 136)
+    c, g = closed_form_shift(prm["D"], prm["vx"], prm["vy"], prm["dx"], prm["dy"])
+    v = np.random.default_rng(77).standard_normal((136, 200))
+    say("stream depth 8 vs 4", ls)
+    r8, o8 = _solve(ctx, 8, 2, 0, 0, _op(prm), v, ls, h, c, g, rtol=1e-8, max_iters=200)
+    r4, o4 = _solve(ctx, 4, 2, 0, 0, _op(prm), v, ls, h, c, g, rtol=1e-8, max_iters=200)
+    assert r8.status == B.LX_OK and r8.stats["depth"] == 8 and r4.stats["depth"] == 4
+    spec = [(l, 1.0, 1.0) for l in ls]
+    oracle_parity(o8, r8.iters, lambda f: leja_phi(_A(prm), v, spec, h, c, g, 1e-8, 0.0, 200, f), PARITY)
+    if r8.iters == r4.iters:
+        assert all(np.array_equal(a, b) for a, b in zip(o8, o4))
+
+
 @pytest.mark.parametrize("depth", [4, 6, 8])
 @pytest.mark.parametrize("nx,ny", [(8, 8), (10, 12), (64, 9), (130, 20), (256, 40), (14, 200)])
 def test_stream_small_and_odd_grids(ctx, depth, nx, ny):
